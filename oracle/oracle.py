@@ -1,0 +1,334 @@
+"""ctypes wrapper of the FP64 CPU oracle (sem_oracle.c).
+
+TEST INFRASTRUCTURE ONLY -- see the package docstring.  Builds
+``liboracle.so`` with gcc/OpenMP on demand (``build_oracle``).
+"""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sem_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+class _StepStats(C.Structure):
+    _fields_ = [("t", C.c_double), ("ke", C.c_double), ("enst", C.c_double), ("maxdiv", C.c_double),
+                ("vit", C.c_int * 3), ("pit", C.c_int), ("vres", C.c_double * 3), ("pres", C.c_double)]
+
+
+def build_oracle(force=False):
+    """Compile liboracle.so (gcc -O2 -fopenmp).  Always recompiles when force."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build_oracle()
+    L = C.CDLL(_LIB)
+    vp = C.c_void_p
+    L.orc_gll.argtypes = [C.c_int, _dp, _dp]
+    L.orc_deriv.argtypes = [C.c_int, _dp, _dp]
+    L.orc_mesh_new.restype = vp
+    L.orc_mesh_new.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, C.c_double, _dp]
+    L.orc_mesh_free.argtypes = [vp]
+    for f in ("orc_mesh_np", "orc_mesh_nglob"):
+        getattr(L, f).restype = C.c_long
+        getattr(L, f).argtypes = [vp]
+    for f in ("orc_mesh_lx", "orc_mesh_E"):
+        getattr(L, f).restype = C.c_int
+        getattr(L, f).argtypes = [vp]
+    L.orc_mesh_vol.restype = C.c_double
+    L.orc_mesh_vol.argtypes = [vp]
+    L.orc_mesh_get.argtypes = [vp, C.c_int, _dp]
+    L.orc_mesh_tables.argtypes = [vp, _dp, _dp, _dp]
+    L.orc_from_lattice.argtypes = [vp, _dp, _dp]
+    L.orc_dssum.argtypes = [vp, _dp]
+    L.orc_glsc.restype = C.c_double
+    L.orc_glsc.argtypes = [vp, _dp, _dp]
+    L.orc_sum.restype = C.c_double
+    L.orc_sum.argtypes = [vp, _dp]
+    L.orc_ax.argtypes = [vp, _dp, _dp, C.c_double, C.c_double]
+    L.orc_diag.argtypes = [vp, C.c_double, C.c_double, _dp]
+    L.orc_grad.argtypes = [vp, _dp, _dp, _dp, _dp]
+    L.orc_opgrad.argtypes = [vp, _dp, _dp, _dp, _dp]
+    L.orc_wdiv.argtypes = [vp, _dp, _dp, _dp, _dp]
+    L.orc_conv.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_curl_div.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_diagnostics.argtypes = [vp, _dp, _dp, _dp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double)]
+    L.orc_pcg.restype = C.c_int
+    L.orc_pcg.argtypes = [vp, C.c_double, C.c_double, _dp, _dp, C.c_double, C.c_int,
+                          C.POINTER(C.c_double), vp]
+    L.orc_gmres.restype = C.c_int
+    L.orc_gmres.argtypes = [vp, C.c_double, C.c_double, _dp, _dp, C.c_double, C.c_int, C.c_int,
+                            C.POINTER(C.c_double), vp]
+    L.orc_remove_mean_unique.argtypes = [vp, _dp]
+    L.orc_remove_mean_mass.argtypes = [vp, _dp]
+    L.orc_poisson.restype = C.c_int
+    L.orc_poisson.argtypes = [vp, _dp, _dp, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_double)]
+    L.orc_fluid_new.restype = vp
+    L.orc_fluid_new.argtypes = [vp, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double,
+                                C.c_int, C.c_int, C.c_int, C.c_int]
+    L.orc_fluid_free.argtypes = [vp]
+    L.orc_fluid_get.argtypes = [vp, C.c_int, _dp]
+    L.orc_fluid_set.argtypes = [vp, C.c_int, _dp]
+    L.orc_fluid_set_clock.argtypes = [vp, C.c_double, C.c_int]
+    L.orc_fluid_time.restype = C.c_double
+    L.orc_fluid_time.argtypes = [vp]
+    L.orc_fluid_stepno.restype = C.c_int
+    L.orc_fluid_stepno.argtypes = [vp]
+    L.orc_fluid_step.argtypes = [vp, C.POINTER(_StepStats)]
+    L.orc_num_threads.restype = C.c_int
+    _lib = L
+    return L
+
+
+def num_threads():
+    return _load().orc_num_threads()
+
+
+def gll(N):
+    """GLL nodes and weights of order N."""
+    L = _load()
+    xi = np.zeros(N + 1)
+    w = np.zeros(N + 1)
+    if L.orc_gll(N, xi, w) != 0:
+        raise ValueError("unsupported order %d" % N)
+    return xi, w
+
+
+def deriv_matrix(N):
+    """GLL derivative matrix D[i, j] = l_j'(xi_i)."""
+    L = _load()
+    xi, _ = gll(N)
+    D = np.zeros((N + 1) * (N + 1))
+    L.orc_deriv(N, xi, D)
+    return D.reshape(N + 1, N + 1)
+
+
+def _c(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleMesh:
+    """Periodic box mesh of nel[0]*nel[1]*nel[2] hexahedra of order N with
+    its geometric factors; fields are flat arrays of E*lx^3 local values."""
+
+    def __init__(self, nel, N, lo=(-np.pi,) * 3, hi=(np.pi,) * 3, amp=0.0, phase=None):
+        self.L = _load()
+        ph = np.zeros(9) if phase is None else _c(phase)
+        self.h = self.L.orc_mesh_new(int(nel[0]), int(nel[1]), int(nel[2]), int(N),
+                                     _c(lo), _c(hi), float(amp), ph)
+        if not self.h:
+            raise ValueError("invalid mesh (element count, order or non-positive Jacobian)")
+        self.nel = tuple(int(v) for v in nel)
+        self.N = int(N)
+        self.lx = self.N + 1
+        self.E = self.L.orc_mesh_E(self.h)
+        self.np = self.L.orc_mesh_np(self.h)
+        self.nglob = self.L.orc_mesh_nglob(self.h)
+        self.vol = self.L.orc_mesh_vol(self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.L.orc_mesh_free(self.h)
+            self.h = None
+
+    def _get(self, which, n):
+        out = np.zeros(n * self.np)
+        self.L.orc_mesh_get(self.h, which, out)
+        return out.reshape(n, self.np) if n > 1 else out
+
+    def coords(self):
+        return self._get(0, 3)
+
+    def jac(self):
+        return self._get(1, 1)
+
+    def mass(self):
+        return self._get(2, 1)
+
+    def drdx(self):
+        return self._get(3, 9)
+
+    def G(self):
+        return self._get(4, 6)
+
+    def M(self):
+        return self._get(5, 9)
+
+    def bsum(self):
+        return self._get(6, 1)
+
+    def mult(self):
+        return self._get(7, 1)
+
+    def gid(self):
+        return self._get(8, 1).astype(np.int64)
+
+    def tables(self):
+        xi = np.zeros(self.lx)
+        w = np.zeros(self.lx)
+        D = np.zeros(self.lx * self.lx)
+        self.L.orc_mesh_tables(self.h, xi, w, D)
+        return xi, w, D.reshape(self.lx, self.lx)
+
+    def from_lattice(self, lat):
+        out = np.zeros(self.np)
+        self.L.orc_from_lattice(self.h, _c(lat).ravel(), out)
+        return out
+
+    def dssum(self, u):
+        u = _c(u).copy()
+        self.L.orc_dssum(self.h, u)
+        return u
+
+    def glsc(self, a, b):
+        return self.L.orc_glsc(self.h, _c(a), _c(b))
+
+    def sum(self, a):
+        return self.L.orc_sum(self.h, _c(a))
+
+    def ax(self, u, h1=1.0, h2=0.0):
+        w = np.zeros(self.np)
+        self.L.orc_ax(self.h, _c(u), w, float(h1), float(h2))
+        return w
+
+    def diag(self, h1=1.0, h2=0.0):
+        d = np.zeros(self.np)
+        self.L.orc_diag(self.h, float(h1), float(h2), d)
+        return d
+
+    def grad(self, u):
+        g = [np.zeros(self.np) for _ in range(3)]
+        self.L.orc_grad(self.h, _c(u), *g)
+        return np.stack(g)
+
+    def opgrad(self, p):
+        g = [np.zeros(self.np) for _ in range(3)]
+        self.L.orc_opgrad(self.h, _c(p), *g)
+        return np.stack(g)
+
+    def wdiv(self, v):
+        out = np.zeros(self.np)
+        self.L.orc_wdiv(self.h, _c(v[0]), _c(v[1]), _c(v[2]), out)
+        return out
+
+    def conv(self, u):
+        o = [np.zeros(self.np) for _ in range(3)]
+        self.L.orc_conv(self.h, _c(u[0]), _c(u[1]), _c(u[2]), *o)
+        return np.stack(o)
+
+    def curl_div(self, u):
+        o = [np.zeros(self.np) for _ in range(4)]
+        self.L.orc_curl_div(self.h, _c(u[0]), _c(u[1]), _c(u[2]), *o)
+        return np.stack(o[:3]), o[3]
+
+    def diagnostics(self, u):
+        ke, en, md = C.c_double(), C.c_double(), C.c_double()
+        self.L.orc_diagnostics(self.h, _c(u[0]), _c(u[1]), _c(u[2]), C.byref(ke), C.byref(en), C.byref(md))
+        return ke.value, en.value, md.value
+
+    def pcg(self, b, h1=1.0, h2=0.0, x0=None, tol=1e-8, maxit=500, history=False):
+        x = np.zeros(self.np) if x0 is None else _c(x0).copy()
+        res = C.c_double()
+        hist = np.zeros(maxit + 2) if history else None
+        it = self.L.orc_pcg(self.h, float(h1), float(h2), _c(b), x, float(tol), int(maxit), C.byref(res),
+                            hist.ctypes.data if history else None)
+        if history:
+            return x, it, res.value, hist[:it + 1].copy()
+        return x, it, res.value
+
+    def gmres(self, b, h1=1.0, h2=0.0, x0=None, tol=1e-8, maxit=1000, restart=30, history=False):
+        x = np.zeros(self.np) if x0 is None else _c(x0).copy()
+        res = C.c_double()
+        hist = np.zeros(2 * maxit + 4) if history else None
+        it = self.L.orc_gmres(self.h, float(h1), float(h2), _c(b), x, float(tol), int(maxit), int(restart),
+                              C.byref(res), hist.ctypes.data if history else None)
+        if history:
+            return x, it, res.value, hist
+        return x, it, res.value
+
+    def remove_mean_unique(self, r):
+        r = _c(r).copy()
+        self.L.orc_remove_mean_unique(self.h, r)
+        return r
+
+    def remove_mean_mass(self, x):
+        x = _c(x).copy()
+        self.L.orc_remove_mean_mass(self.h, x)
+        return x
+
+    def poisson(self, rhs, tol=1e-8, maxit=1000, restart=30):
+        p = np.zeros(self.np)
+        res = C.c_double()
+        it = self.L.orc_poisson(self.h, _c(rhs), p, float(tol), int(maxit), int(restart), C.byref(res))
+        return p, it, res.value
+
+
+INIT_TGV3D, INIT_TGV2D, INIT_ZERO = 0, 1, 2
+FIELD_U, FIELD_P, FIELD_ULAG1, FIELD_ULAG2, FIELD_BNLAG1, FIELD_BNLAG2 = 0, 3, 4, 7, 10, 13
+
+
+class OracleFluid:
+    """FP64 TGV stepper on an OracleMesh (keeps a reference to the mesh)."""
+
+    def __init__(self, mesh, nu, dt, torder=3, vtol=1e-8, ptol=1e-8, vmaxit=500, pmaxit=1000,
+                 restart=30, init=INIT_TGV3D):
+        self.mesh = mesh
+        self.L = mesh.L
+        self.h = self.L.orc_fluid_new(mesh.h, float(nu), float(dt), int(torder), float(vtol), float(ptol),
+                                      int(vmaxit), int(pmaxit), int(restart), int(init))
+        if not self.h:
+            raise ValueError("invalid fluid parameters")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.L.orc_fluid_free(self.h)
+            self.h = None
+
+    def get(self, which):
+        out = np.zeros(self.mesh.np)
+        if self.L.orc_fluid_get(self.h, int(which), out) != 0:
+            raise ValueError(which)
+        return out
+
+    def set(self, which, arr):
+        if self.L.orc_fluid_set(self.h, int(which), _c(arr)) != 0:
+            raise ValueError(which)
+
+    def velocity(self):
+        return np.stack([self.get(c) for c in range(3)])
+
+    def pressure(self):
+        return self.get(FIELD_P)
+
+    @property
+    def time(self):
+        return self.L.orc_fluid_time(self.h)
+
+    @property
+    def stepno(self):
+        return self.L.orc_fluid_stepno(self.h)
+
+    def set_clock(self, t, step):
+        self.L.orc_fluid_set_clock(self.h, float(t), int(step))
+
+    def step(self):
+        st = _StepStats()
+        self.L.orc_fluid_step(self.h, C.byref(st))
+        return {"t": st.t, "ke": st.ke, "enst": st.enst, "maxdiv": st.maxdiv,
+                "vit": list(st.vit), "pit": st.pit, "vres": list(st.vres), "pres": st.pres}

@@ -1,0 +1,987 @@
+/*
+ * sem_oracle.c -- plain FP64 CPU oracle of the SEM incompressible
+ * Navier-Stokes step on the Taylor-Green vortex.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the independent reference that the
+ * GPU library is checked against.  It shares no code, header, table or helper
+ * with the HIP path; only tests, the smoke check and the CPU-baseline leg of
+ * the benchmark may load it.
+ *
+ * Everything is double precision, written as plain loops in the order the
+ * mathematics is stated, with OpenMP only over independent elements.  Sums
+ * over the whole mesh are formed as per-element partial sums that are then
+ * added serially in element order, so the result does not depend on the
+ * number of threads.
+ *
+ * Sources (the paper is "Mixed-Precision SEM-Based CFD Simulations on GPUs:
+ * A Taylor-Green Vortex case"):
+ *   - matrix-free SEM on hexahedra with Gauss-Lobatto-Legendre points, the
+ *     P_N-P_N fluid step and its Fig. 3 ordering (explicit RHS, velocity
+ *     solve, u*, pressure residual, pressure solve, correction): Sec. 2,
+ *     Fig. 3, Fig. 5 discussion;
+ *   - CG+Jacobi for velocity, GMRES for pressure, third-order time
+ *     integration: Sec. 1.1 and Sec. 3 (solver settings paragraph);
+ *   - the Taylor-Green initial condition and Re = v0 L / nu: Sec. 3 eqs.;
+ *   - GLL nodes/weights/derivative matrix, geometric factors and the
+ *     sum-factorised operators are textbook SEM (Deville, Fischer & Mund,
+ *     "High-Order Methods for Incompressible Fluid Flow", 2002, ch. 2-4).
+ *   - GMRES(m): Saad & Schultz (1986), right preconditioned, Givens rotations,
+ *     classical Gram-Schmidt applied twice.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAXLX 16
+
+/* ------------------------------------------------------------------ */
+/* Legendre polynomial L_N(x) and its derivative by the three-term     */
+/* recurrence (textbook).                                               */
+/* ------------------------------------------------------------------ */
+static void legendre(int N, double x, double* L, double* dL)
+{
+    double p0 = 1.0, p1 = x, d0 = 0.0, d1 = 1.0;
+    if (N == 0) { *L = 1.0; *dL = 0.0; return; }
+    for (int k = 1; k < N; ++k) {
+        double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0);
+        double d2 = d0 + (2.0 * k + 1.0) * p1;   /* L'_{k+1} = L'_{k-1} + (2k+1) L_k */
+        p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+    }
+    *L = p1; *dL = d1;
+}
+
+/* GLL nodes (endpoints and roots of L'_N) and weights
+ * w_i = 2 / (N (N+1) L_N(xi_i)^2).  Newton on L'_N uses the Legendre ODE for
+ * L''_N.  Returns 0 on success. */
+int orc_gll(int N, double* xi, double* w)
+{
+    if (N < 1 || N + 1 > ORC_MAXLX) return -1;
+    const double pi = 3.14159265358979323846;
+    xi[0] = -1.0; xi[N] = 1.0;
+    for (int i = 1; i < N; ++i) {
+        double x = -cos(pi * i / N);     /* Chebyshev-Gauss-Lobatto start */
+        for (int it = 0; it < 100; ++it) {
+            double L, dL;
+            legendre(N, x, &L, &dL);
+            double d2L = (2.0 * x * dL - N * (N + 1.0) * L) / (1.0 - x * x);
+            double dx = dL / d2L;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        xi[i] = x;
+    }
+    /* enforce the exact symmetry of the node set */
+    for (int i = 0; i <= N / 2; ++i) {
+        double s = 0.5 * (xi[N - i] - xi[i]);
+        xi[i] = -s; xi[N - i] = s;
+    }
+    if (N % 2 == 0) xi[N / 2] = 0.0;
+    for (int i = 0; i <= N; ++i) {
+        double L, dL;
+        legendre(N, xi[i], &L, &dL);
+        w[i] = 2.0 / (N * (N + 1.0) * L * L);
+    }
+    return 0;
+}
+
+/* Derivative matrix of the Lagrange interpolant on the GLL nodes,
+ * D[i*lx+j] = l_j'(xi_i):
+ *   L_N(xi_i) / (L_N(xi_j) (xi_i - xi_j))   for i != j,
+ *   -N(N+1)/4 at (0,0),  +N(N+1)/4 at (N,N),  0 on the rest of the diagonal. */
+void orc_deriv(int N, const double* xi, double* D)
+{
+    int lx = N + 1;
+    double Lv[ORC_MAXLX];
+    for (int i = 0; i < lx; ++i) { double dL; legendre(N, xi[i], &Lv[i], &dL); }
+    for (int i = 0; i < lx; ++i)
+        for (int j = 0; j < lx; ++j) {
+            double v = 0.0;
+            if (i != j) v = Lv[i] / (Lv[j] * (xi[i] - xi[j]));
+            else if (i == 0) v = -N * (N + 1.0) / 4.0;
+            else if (i == N) v = N * (N + 1.0) / 4.0;
+            D[i * lx + j] = v;
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* Mesh: nx*ny*nz hexahedra on the box [lo,hi], periodic in all three  */
+/* directions, optional smooth sinusoidal node perturbation.           */
+/* Field layout: element-major, u[e][k][j][i], i fastest,              */
+/* e = ex + nx (ey + ny ez).                                            */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int nel[3], N, lx, E;
+    long np;                    /* E * lx^3 local points */
+    long nglob;                 /* unique periodic nodes */
+    double lo[3], hi[3], h[3];
+    double amp, phase[9];
+    double xi[ORC_MAXLX], w[ORC_MAXLX], D[ORC_MAXLX * ORC_MAXLX];
+    double *xyz;                /* 3*np coordinates */
+    double *jac, *B;            /* np */
+    double *drdx;               /* 9*np: (a*3+c) -> d r_a / d x_c */
+    double *G;                  /* 6*np: rr rs rt ss st tt */
+    double *M;                  /* 9*np: M_ac = B d r_a / d x_c */
+    long *gid;                  /* np */
+    int *mult;                  /* np */
+    double *Bsum;               /* dssum(B) */
+    double vol;                 /* sum of B */
+} orc_mesh;
+
+#define PT(m, e, i, j, k) ((long)(e) * (m)->lx * (m)->lx * (m)->lx + (i) + (m)->lx * ((j) + (m)->lx * (k)))
+
+static double* dalloc(long n) { return (double*)calloc((size_t)n, sizeof(double)); }
+
+void orc_dssum(const orc_mesh* m, double* u);
+
+/* Perturbed coordinate of the reference position (X,Y,Z) measured from lo:
+ * each coordinate c gets amp*h_c*sin(pi X/hx + ph[3c]) sin(pi Y/hy + ph[3c+1])
+ * sin(pi Z/hz + ph[3c+2]).  A function of global position only, so the mesh
+ * stays conforming; periodic when every element count is even. */
+static void perturb(const orc_mesh* m, const double X[3], double out[3])
+{
+    const double pi = 3.14159265358979323846;
+    for (int c = 0; c < 3; ++c) {
+        double d = 0.0;
+        if (m->amp != 0.0) {
+            d = m->amp * m->h[c];
+            for (int q = 0; q < 3; ++q) d *= sin(pi * X[q] / m->h[q] + m->phase[3 * c + q]);
+        }
+        out[c] = m->lo[c] + X[c] + d;
+    }
+}
+
+orc_mesh* orc_mesh_new(int nx, int ny, int nz, int N, const double* lo, const double* hi,
+                       double amp, const double* phase)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || N < 1 || N + 1 > ORC_MAXLX) return NULL;
+    if (amp != 0.0 && (nx % 2 || ny % 2 || nz % 2)) return NULL;
+    orc_mesh* m = (orc_mesh*)calloc(1, sizeof(orc_mesh));
+    m->nel[0] = nx; m->nel[1] = ny; m->nel[2] = nz;
+    m->N = N; m->lx = N + 1; m->E = nx * ny * nz;
+    int lx = m->lx;
+    m->np = (long)m->E * lx * lx * lx;
+    for (int c = 0; c < 3; ++c) {
+        m->lo[c] = lo[c]; m->hi[c] = hi[c];
+        m->h[c] = (hi[c] - lo[c]) / m->nel[c];
+    }
+    m->amp = amp;
+    for (int q = 0; q < 9; ++q) m->phase[q] = phase ? phase[q] : 0.0;
+    orc_gll(N, m->xi, m->w);
+    orc_deriv(N, m->xi, m->D);
+
+    long np = m->np;
+    m->xyz = dalloc(3 * np);
+    m->jac = dalloc(np); m->B = dalloc(np);
+    m->drdx = dalloc(9 * np); m->G = dalloc(6 * np); m->M = dalloc(9 * np);
+    m->gid = (long*)calloc((size_t)np, sizeof(long));
+    m->mult = (int*)calloc((size_t)np, sizeof(int));
+    m->Bsum = dalloc(np);
+
+    /* coordinates and periodic global numbering */
+    long ngx = (long)nx * N, ngy = (long)ny * N, ngz = (long)nz * N;
+    m->nglob = ngx * ngy * ngz;
+    for (int ez = 0; ez < nz; ++ez)
+    for (int ey = 0; ey < ny; ++ey)
+    for (int ex = 0; ex < nx; ++ex) {
+        int e = ex + nx * (ey + ny * ez);
+        for (int k = 0; k < lx; ++k)
+        for (int j = 0; j < lx; ++j)
+        for (int i = 0; i < lx; ++i) {
+            long p = PT(m, e, i, j, k);
+            double X[3] = { (ex + 0.5 * (1.0 + m->xi[i])) * m->h[0],
+                            (ey + 0.5 * (1.0 + m->xi[j])) * m->h[1],
+                            (ez + 0.5 * (1.0 + m->xi[k])) * m->h[2] };
+            double xo[3];
+            perturb(m, X, xo);
+            m->xyz[p] = xo[0]; m->xyz[np + p] = xo[1]; m->xyz[2 * np + p] = xo[2];
+            long gx = ((long)ex * N + i) % ngx;
+            long gy = ((long)ey * N + j) % ngy;
+            long gz = ((long)ez * N + k) % ngz;
+            m->gid[p] = gx + ngx * (gy + ngy * gz);
+        }
+    }
+    int* cnt = (int*)calloc((size_t)m->nglob, sizeof(int));
+    for (long p = 0; p < np; ++p) cnt[m->gid[p]]++;
+    for (long p = 0; p < np; ++p) m->mult[p] = cnt[m->gid[p]];
+    free(cnt);
+
+    /* geometric factors: dx_c/dr_a = D_a x_c, jac = det, dr/dx = inverse,
+     * B = jac w_i w_j w_k, G_ab = B sum_c dr_a/dx_c dr_b/dx_c, M_ac = B dr_a/dx_c */
+    const double* D = m->D;
+    int bad = 0;
+    #pragma omp parallel for reduction(|:bad)
+    for (int e = 0; e < m->E; ++e)
+        for (int k = 0; k < lx; ++k)
+        for (int j = 0; j < lx; ++j)
+        for (int i = 0; i < lx; ++i) {
+            long p = PT(m, e, i, j, k);
+            double J[3][3];              /* J[c][a] = d x_c / d r_a */
+            for (int c = 0; c < 3; ++c) {
+                const double* X = m->xyz + (long)c * np;
+                double dr = 0, ds = 0, dt = 0;
+                for (int l = 0; l < lx; ++l) {
+                    dr += D[i * lx + l] * X[PT(m, e, l, j, k)];
+                    ds += D[j * lx + l] * X[PT(m, e, i, l, k)];
+                    dt += D[k * lx + l] * X[PT(m, e, i, j, l)];
+                }
+                J[c][0] = dr; J[c][1] = ds; J[c][2] = dt;
+            }
+            double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+                       - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+                       + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+            if (!(det > 0.0)) bad = 1;
+            /* inverse: (dr/dx)[a][c] = cofactor(J)[c][a] / det */
+            double inv[3][3];
+            inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+            inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+            inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+            inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+            inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+            inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+            inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+            inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+            inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+            double Bp = det * m->w[i] * m->w[j] * m->w[k];
+            m->jac[p] = det;
+            m->B[p] = Bp;
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c) {
+                    m->drdx[(long)(a * 3 + c) * np + p] = inv[a][c];
+                    m->M[(long)(a * 3 + c) * np + p] = Bp * inv[a][c];
+                }
+            static const int ga[6] = {0, 0, 0, 1, 1, 2}, gb[6] = {0, 1, 2, 1, 2, 2};
+            for (int q = 0; q < 6; ++q) {
+                double s = 0;
+                for (int c = 0; c < 3; ++c) s += inv[ga[q]][c] * inv[gb[q]][c];
+                m->G[(long)q * np + p] = Bp * s;
+            }
+        }
+    if (bad) {
+        /* non-positive Jacobian: the mesh is invalid */
+        free(m->xyz); free(m->jac); free(m->B); free(m->drdx); free(m->G); free(m->M);
+        free(m->gid); free(m->mult); free(m->Bsum); free(m);
+        return NULL;
+    }
+    memcpy(m->Bsum, m->B, (size_t)np * sizeof(double));
+    orc_dssum(m, m->Bsum);
+    double vol = 0;
+    for (long p = 0; p < np; ++p) vol += m->B[p];
+    m->vol = vol;
+    return m;
+}
+
+void orc_mesh_free(orc_mesh* m)
+{
+    if (!m) return;
+    free(m->xyz); free(m->jac); free(m->B); free(m->drdx); free(m->G); free(m->M);
+    free(m->gid); free(m->mult); free(m->Bsum); free(m);
+}
+
+/* accessors (copy-out into caller arrays) */
+long orc_mesh_np(const orc_mesh* m) { return m->np; }
+long orc_mesh_nglob(const orc_mesh* m) { return m->nglob; }
+int orc_mesh_lx(const orc_mesh* m) { return m->lx; }
+int orc_mesh_E(const orc_mesh* m) { return m->E; }
+double orc_mesh_vol(const orc_mesh* m) { return m->vol; }
+/* which: 0 xyz(3np) 1 jac 2 B 3 drdx(9np) 4 G(6np) 5 M(9np) 6 Bsum 7 mult 8 gid */
+int orc_mesh_get(const orc_mesh* m, int which, double* out)
+{
+    long np = m->np;
+    switch (which) {
+    case 0: memcpy(out, m->xyz, 3 * np * sizeof(double)); break;
+    case 1: memcpy(out, m->jac, np * sizeof(double)); break;
+    case 2: memcpy(out, m->B, np * sizeof(double)); break;
+    case 3: memcpy(out, m->drdx, 9 * np * sizeof(double)); break;
+    case 4: memcpy(out, m->G, 6 * np * sizeof(double)); break;
+    case 5: memcpy(out, m->M, 9 * np * sizeof(double)); break;
+    case 6: memcpy(out, m->Bsum, np * sizeof(double)); break;
+    case 7: for (long p = 0; p < np; ++p) out[p] = m->mult[p]; break;
+    case 8: for (long p = 0; p < np; ++p) out[p] = (double)m->gid[p]; break;
+    default: return -1;
+    }
+    return 0;
+}
+void orc_mesh_tables(const orc_mesh* m, double* xi, double* w, double* D)
+{
+    int lx = m->lx;
+    memcpy(xi, m->xi, lx * sizeof(double));
+    memcpy(w, m->w, lx * sizeof(double));
+    memcpy(D, m->D, lx * lx * sizeof(double));
+}
+
+/* Expand a field given on the periodic lattice of unique nodes
+ * (index gx + ngx (gy + ngy gz)) to the element-local layout. */
+void orc_from_lattice(const orc_mesh* m, const double* lat, double* u)
+{
+    for (long p = 0; p < m->np; ++p) u[p] = lat[m->gid[p]];
+}
+
+/* ------------------------------------------------------------------ */
+/* Direct stiffness summation Q Q^T: every local copy of a unique node */
+/* receives the sum of all its copies.                                  */
+/* ------------------------------------------------------------------ */
+void orc_dssum(const orc_mesh* m, double* u)
+{
+    double* g = dalloc(m->nglob);
+    for (long p = 0; p < m->np; ++p) g[m->gid[p]] += u[p];
+    for (long p = 0; p < m->np; ++p) u[p] = g[m->gid[p]];
+    free(g);
+}
+
+/* Inner product of two assembled (continuous) vectors over unique nodes:
+ * (a,b) = sum_local a b / mult. */
+double orc_glsc(const orc_mesh* m, const double* a, const double* b)
+{
+    int E = m->E;
+    long n3 = (long)m->lx * m->lx * m->lx;
+    double* part = dalloc(E);
+    #pragma omp parallel for
+    for (int e = 0; e < E; ++e) {
+        double s = 0;
+        for (long q = 0; q < n3; ++q) { long p = e * n3 + q; s += a[p] * b[p] / m->mult[p]; }
+        part[e] = s;
+    }
+    double s = 0;
+    for (int e = 0; e < E; ++e) s += part[e];
+    free(part);
+    return s;
+}
+
+/* Sum of all local values (no multiplicity weighting). */
+double orc_sum(const orc_mesh* m, const double* a)
+{
+    int E = m->E;
+    long n3 = (long)m->lx * m->lx * m->lx;
+    double* part = dalloc(E);
+    #pragma omp parallel for
+    for (int e = 0; e < E; ++e) {
+        double s = 0;
+        for (long q = 0; q < n3; ++q) s += a[e * n3 + q];
+        part[e] = s;
+    }
+    double s = 0;
+    for (int e = 0; e < E; ++e) s += part[e];
+    free(part);
+    return s;
+}
+
+/* ------------------------------------------------------------------ */
+/* Element-local operators (sum factorisation).                         */
+/* ------------------------------------------------------------------ */
+
+/* reference derivatives of one element field: ur = D_r u, us = D_s u, ut = D_t u */
+static void ref_grad(const orc_mesh* m, int e, const double* u, double* ur, double* us, double* ut)
+{
+    int lx = m->lx;
+    const double* D = m->D;
+    for (int k = 0; k < lx; ++k)
+    for (int j = 0; j < lx; ++j)
+    for (int i = 0; i < lx; ++i) {
+        double a = 0, b = 0, c = 0;
+        for (int l = 0; l < lx; ++l) {
+            a += D[i * lx + l] * u[PT(m, e, l, j, k)];
+            b += D[j * lx + l] * u[PT(m, e, i, l, k)];
+            c += D[k * lx + l] * u[PT(m, e, i, j, l)];
+        }
+        int q = i + lx * (j + lx * k);
+        ur[q] = a; us[q] = b; ut[q] = c;
+    }
+}
+
+/* transposed reference derivatives: out = D_r^T fr + D_s^T fs + D_t^T ft */
+static void ref_div_t(const orc_mesh* m, const double* fr, const double* fs, const double* ft, double* out)
+{
+    int lx = m->lx;
+    const double* D = m->D;
+    for (int k = 0; k < lx; ++k)
+    for (int j = 0; j < lx; ++j)
+    for (int i = 0; i < lx; ++i) {
+        double s = 0;
+        for (int l = 0; l < lx; ++l) {
+            s += D[l * lx + i] * fr[l + lx * (j + lx * k)];
+            s += D[l * lx + j] * fs[i + lx * (l + lx * k)];
+            s += D[l * lx + k] * ft[i + lx * (j + lx * l)];
+        }
+        out[i + lx * (j + lx * k)] = s;
+    }
+}
+
+/* Local Helmholtz operator w = h1 sum_ab D_a^T (G_ab o D_b u) + h2 B o u
+ * (no assembly; apply orc_dssum for the assembled operator). */
+void orc_ax(const orc_mesh* m, const double* u, double* w, double h1, double h2)
+{
+    int lx = m->lx;
+    long n3 = (long)lx * lx * lx, np = m->np;
+    #pragma omp parallel
+    {
+        double ur[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX], us[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX],
+               ut[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX], o[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX];
+        #pragma omp for
+        for (int e = 0; e < m->E; ++e) {
+            ref_grad(m, e, u, ur, us, ut);
+            for (long q = 0; q < n3; ++q) {
+                long p = e * n3 + q;
+                double grr = m->G[p], grs = m->G[np + p], grt = m->G[2 * np + p];
+                double gss = m->G[3 * np + p], gst = m->G[4 * np + p], gtt = m->G[5 * np + p];
+                double a = ur[q], b = us[q], c = ut[q];
+                ur[q] = grr * a + grs * b + grt * c;
+                us[q] = grs * a + gss * b + gst * c;
+                ut[q] = grt * a + gst * b + gtt * c;
+            }
+            ref_div_t(m, ur, us, ut, o);
+            for (long q = 0; q < n3; ++q) {
+                long p = e * n3 + q;
+                w[p] = h1 * o[q] + h2 * m->B[p] * u[p];
+            }
+        }
+    }
+}
+
+/* Exact diagonal of the local Helmholtz operator, including the G cross
+ * terms that survive at element-boundary nodes (D has a non-zero diagonal
+ * only at the two end nodes). */
+void orc_diag(const orc_mesh* m, double h1, double h2, double* d)
+{
+    int lx = m->lx;
+    long np = m->np;
+    const double* D = m->D;
+    #pragma omp parallel for
+    for (int e = 0; e < m->E; ++e)
+        for (int k = 0; k < lx; ++k)
+        for (int j = 0; j < lx; ++j)
+        for (int i = 0; i < lx; ++i) {
+            long p = PT(m, e, i, j, k);
+            double s = 0;
+            for (int l = 0; l < lx; ++l) {
+                s += D[l * lx + i] * D[l * lx + i] * m->G[0 * np + PT(m, e, l, j, k)];
+                s += D[l * lx + j] * D[l * lx + j] * m->G[3 * np + PT(m, e, i, l, k)];
+                s += D[l * lx + k] * D[l * lx + k] * m->G[5 * np + PT(m, e, i, j, l)];
+            }
+            double dii = D[i * lx + i], djj = D[j * lx + j], dkk = D[k * lx + k];
+            s += 2.0 * dii * djj * m->G[1 * np + p];
+            s += 2.0 * dii * dkk * m->G[2 * np + p];
+            s += 2.0 * djj * dkk * m->G[4 * np + p];
+            d[p] = h1 * s + h2 * m->B[p];
+        }
+}
+
+/* Physical gradient of a scalar: g_c = sum_a (dr_a/dx_c) D_a u. */
+void orc_grad(const orc_mesh* m, const double* u, double* gx, double* gy, double* gz)
+{
+    int lx = m->lx;
+    long n3 = (long)lx * lx * lx, np = m->np;
+    #pragma omp parallel
+    {
+        double ur[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX], us[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX],
+               ut[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX];
+        #pragma omp for
+        for (int e = 0; e < m->E; ++e) {
+            ref_grad(m, e, u, ur, us, ut);
+            for (long q = 0; q < n3; ++q) {
+                long p = e * n3 + q;
+                double g[3];
+                for (int c = 0; c < 3; ++c)
+                    g[c] = m->drdx[(long)(0 * 3 + c) * np + p] * ur[q]
+                         + m->drdx[(long)(1 * 3 + c) * np + p] * us[q]
+                         + m->drdx[(long)(2 * 3 + c) * np + p] * ut[q];
+                gx[p] = g[0]; gy[p] = g[1]; gz[p] = g[2];
+            }
+        }
+    }
+}
+
+/* Mass-weighted gradient (B grad p)_c = sum_a M_ac D_a p. */
+void orc_opgrad(const orc_mesh* m, const double* p_, double* ox, double* oy, double* oz)
+{
+    int lx = m->lx;
+    long n3 = (long)lx * lx * lx, np = m->np;
+    #pragma omp parallel
+    {
+        double ur[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX], us[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX],
+               ut[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX];
+        #pragma omp for
+        for (int e = 0; e < m->E; ++e) {
+            ref_grad(m, e, p_, ur, us, ut);
+            for (long q = 0; q < n3; ++q) {
+                long p = e * n3 + q;
+                double g[3];
+                for (int c = 0; c < 3; ++c)
+                    g[c] = m->M[(long)(0 * 3 + c) * np + p] * ur[q]
+                         + m->M[(long)(1 * 3 + c) * np + p] * us[q]
+                         + m->M[(long)(2 * 3 + c) * np + p] * ut[q];
+                ox[p] = g[0]; oy[p] = g[1]; oz[p] = g[2];
+            }
+        }
+    }
+}
+
+/* Weak divergence of a vector field: out = sum_a D_a^T (sum_c M_ac v_c),
+ * i.e. the integral of grad(test) . v for every test basis function. */
+void orc_wdiv(const orc_mesh* m, const double* vx, const double* vy, const double* vz, double* out)
+{
+    int lx = m->lx;
+    long n3 = (long)lx * lx * lx, np = m->np;
+    #pragma omp parallel
+    {
+        double fr[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX], fs[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX],
+               ft[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX], o[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX];
+        #pragma omp for
+        for (int e = 0; e < m->E; ++e) {
+            for (long q = 0; q < n3; ++q) {
+                long p = e * n3 + q;
+                double v[3] = { vx[p], vy[p], vz[p] };
+                double f[3];
+                for (int a = 0; a < 3; ++a) {
+                    f[a] = 0;
+                    for (int c = 0; c < 3; ++c) f[a] += m->M[(long)(a * 3 + c) * np + p] * v[c];
+                }
+                fr[q] = f[0]; fs[q] = f[1]; ft[q] = f[2];
+            }
+            ref_div_t(m, fr, fs, ft, o);
+            for (long q = 0; q < n3; ++q) out[e * n3 + q] = o[q];
+        }
+    }
+}
+
+/* Convective term in collocation form, mass weighted:
+ * bn_i = -sum_c u_c sum_a M_ac D_a u_i  (= -B (u . grad) u_i). */
+void orc_conv(const orc_mesh* m, const double* ux, const double* uy, const double* uz,
+              double* bx, double* by, double* bz)
+{
+    int lx = m->lx;
+    long n3 = (long)lx * lx * lx, np = m->np;
+    const double* U[3] = { ux, uy, uz };
+    double* O[3] = { bx, by, bz };
+    #pragma omp parallel
+    {
+        double ur[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX], us[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX],
+               ut[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX];
+        #pragma omp for
+        for (int e = 0; e < m->E; ++e) {
+            for (int f = 0; f < 3; ++f) {
+                ref_grad(m, e, U[f], ur, us, ut);
+                for (long q = 0; q < n3; ++q) {
+                    long p = e * n3 + q;
+                    double s = 0;
+                    for (int c = 0; c < 3; ++c) {
+                        double bg = m->M[(long)(0 * 3 + c) * np + p] * ur[q]
+                                  + m->M[(long)(1 * 3 + c) * np + p] * us[q]
+                                  + m->M[(long)(2 * 3 + c) * np + p] * ut[q];
+                        s += U[c][p] * bg;
+                    }
+                    O[f][p] = -s;
+                }
+            }
+        }
+    }
+}
+
+/* Element-local vorticity and divergence (no inter-element averaging). */
+void orc_curl_div(const orc_mesh* m, const double* ux, const double* uy, const double* uz,
+                  double* wx, double* wy, double* wz, double* dv)
+{
+    long np = m->np;
+    double* g = dalloc(9 * np);      /* g[(f*3+c)] = d u_f / d x_c */
+    orc_grad(m, ux, g, g + np, g + 2 * np);
+    orc_grad(m, uy, g + 3 * np, g + 4 * np, g + 5 * np);
+    orc_grad(m, uz, g + 6 * np, g + 7 * np, g + 8 * np);
+    #pragma omp parallel for
+    for (long p = 0; p < np; ++p) {
+        double dudy = g[1 * np + p], dudz = g[2 * np + p];
+        double dvdx = g[3 * np + p], dvdz = g[5 * np + p];
+        double dwdx = g[6 * np + p], dwdy = g[7 * np + p];
+        wx[p] = dwdy - dvdz;
+        wy[p] = dudz - dwdx;
+        wz[p] = dvdx - dudy;
+        dv[p] = g[0 * np + p] + g[4 * np + p] + g[8 * np + p];
+    }
+    free(g);
+}
+
+/* Volume-averaged kinetic energy (1/|V|) int 1/2 |u|^2, enstrophy
+ * (1/|V|) int 1/2 |omega|^2 and the largest pointwise |div u|. */
+void orc_diagnostics(const orc_mesh* m, const double* ux, const double* uy, const double* uz,
+                     double* ke, double* enst, double* maxdiv)
+{
+    long np = m->np;
+    double* wx = dalloc(np); double* wy = dalloc(np); double* wz = dalloc(np); double* dv = dalloc(np);
+    double* a = dalloc(np); double* b = dalloc(np);
+    orc_curl_div(m, ux, uy, uz, wx, wy, wz, dv);
+    double md = 0;
+    for (long p = 0; p < np; ++p) {
+        a[p] = m->B[p] * 0.5 * (ux[p] * ux[p] + uy[p] * uy[p] + uz[p] * uz[p]);
+        b[p] = m->B[p] * 0.5 * (wx[p] * wx[p] + wy[p] * wy[p] + wz[p] * wz[p]);
+        if (fabs(dv[p]) > md) md = fabs(dv[p]);
+    }
+    *ke = orc_sum(m, a) / m->vol;
+    *enst = orc_sum(m, b) / m->vol;
+    *maxdiv = md;
+    free(wx); free(wy); free(wz); free(dv); free(a); free(b);
+}
+
+/* ------------------------------------------------------------------ */
+/* Krylov solvers on the assembled operator  x -> dssum(A_L x).          */
+/* ------------------------------------------------------------------ */
+static void apply_assembled(const orc_mesh* m, const double* x, double* y, double h1, double h2)
+{
+    orc_ax(m, x, y, h1, h2);
+    orc_dssum(m, y);
+}
+
+/* Jacobi-preconditioned CG for (h1 A + h2 B) x = b, assembled.  x holds the
+ * initial guess on entry.  Stops when sqrt((r,r)) <= tol or after maxit
+ * iterations.  Returns the iteration count; *res gets the final residual
+ * norm (recurrence).  Optional hist[maxit+1] receives the residual history. */
+int orc_pcg(const orc_mesh* m, double h1, double h2, const double* b, double* x,
+            double tol, int maxit, double* res, double* hist)
+{
+    long np = m->np;
+    double* r = dalloc(np); double* z = dalloc(np); double* p = dalloc(np);
+    double* w = dalloc(np); double* d = dalloc(np);
+    orc_diag(m, h1, h2, d);
+    orc_dssum(m, d);
+    apply_assembled(m, x, w, h1, h2);
+    for (long i = 0; i < np; ++i) r[i] = b[i] - w[i];
+    double rn = sqrt(orc_glsc(m, r, r));
+    if (hist) hist[0] = rn;
+    int it = 0;
+    if (rn > tol) {
+        for (long i = 0; i < np; ++i) { z[i] = r[i] / d[i]; p[i] = z[i]; }
+        double rho = orc_glsc(m, r, z);
+        while (it < maxit) {
+            apply_assembled(m, p, w, h1, h2);
+            double alpha = rho / orc_glsc(m, p, w);
+            for (long i = 0; i < np; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * w[i]; }
+            ++it;
+            rn = sqrt(orc_glsc(m, r, r));
+            if (hist) hist[it] = rn;
+            if (rn <= tol) break;
+            for (long i = 0; i < np; ++i) z[i] = r[i] / d[i];
+            double rho1 = orc_glsc(m, r, z);
+            double beta = rho1 / rho;
+            rho = rho1;
+            for (long i = 0; i < np; ++i) p[i] = z[i] + beta * p[i];
+        }
+    }
+    if (res) *res = rn;
+    free(r); free(z); free(p); free(w); free(d);
+    return it;
+}
+
+/* Right-Jacobi-preconditioned restarted GMRES(mrst) for the assembled
+ * Helmholtz operator (h1 A + h2 B) x = b.  Arnoldi with classical
+ * Gram-Schmidt applied twice, Givens rotations on the Hessenberg matrix,
+ * absolute stop on the rotated residual |g_{j+1}| <= tol, and the true
+ * residual recomputed at every restart.  x holds the initial guess.
+ * Returns the number of Arnoldi steps; *res = final true residual norm. */
+int orc_gmres(const orc_mesh* m, double h1, double h2, const double* b, double* x,
+              double tol, int maxit, int mrst, double* res, double* hist)
+{
+    long np = m->np;
+    int mm = mrst;
+    double* V = dalloc((long)(mm + 1) * np);
+    double* w = dalloc(np); double* z = dalloc(np); double* d = dalloc(np); double* r = dalloc(np);
+    double* H = dalloc((long)(mm + 1) * mm);    /* H[i*mm + j] */
+    double* cs = dalloc(mm); double* sn = dalloc(mm); double* g = dalloc(mm + 1);
+    double* y = dalloc(mm); double* hc = dalloc(mm + 1); double* h2v = dalloc(mm + 1);
+    orc_diag(m, h1, h2, d);
+    orc_dssum(m, d);
+    int it = 0;
+    double beta = 0;
+    int hpos = 0;
+    for (;;) {
+        apply_assembled(m, x, w, h1, h2);
+        for (long i = 0; i < np; ++i) r[i] = b[i] - w[i];
+        beta = sqrt(orc_glsc(m, r, r));
+        if (hist) hist[hpos++] = beta;
+        if (beta <= tol || it >= maxit) break;
+        for (long i = 0; i < np; ++i) V[i] = r[i] / beta;
+        for (int i = 0; i <= mm; ++i) g[i] = 0;
+        g[0] = beta;
+        int jend = 0;
+        for (int j = 0; j < mm && it < maxit; ++j) {
+            double* vj = V + (long)j * np;
+            for (long i = 0; i < np; ++i) z[i] = vj[i] / d[i];
+            apply_assembled(m, z, w, h1, h2);
+            /* classical Gram-Schmidt, twice */
+            for (int i = 0; i <= j; ++i) hc[i] = 0;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int i = 0; i <= j; ++i) h2v[i] = orc_glsc(m, V + (long)i * np, w);
+                for (int i = 0; i <= j; ++i) {
+                    const double* vi = V + (long)i * np;
+                    double hi = h2v[i];
+                    for (long q = 0; q < np; ++q) w[q] -= hi * vi[q];
+                    hc[i] += hi;
+                }
+            }
+            double hn = sqrt(orc_glsc(m, w, w));
+            for (int i = 0; i <= j; ++i) H[i * mm + j] = hc[i];
+            H[(j + 1) * mm + j] = hn;
+            double* vn = V + (long)(j + 1) * np;
+            if (hn != 0.0) for (long q = 0; q < np; ++q) vn[q] = w[q] / hn;
+            /* apply previous rotations to column j, then form the new one */
+            for (int i = 0; i < j; ++i) {
+                double a = H[i * mm + j], c = H[(i + 1) * mm + j];
+                H[i * mm + j] = cs[i] * a + sn[i] * c;
+                H[(i + 1) * mm + j] = -sn[i] * a + cs[i] * c;
+            }
+            double a = H[j * mm + j], c = H[(j + 1) * mm + j];
+            double den = sqrt(a * a + c * c);
+            cs[j] = a / den; sn[j] = c / den;
+            H[j * mm + j] = den;
+            H[(j + 1) * mm + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            jend = j + 1;
+            if (hist) hist[hpos++] = fabs(g[j + 1]);
+            if (fabs(g[j + 1]) <= tol || hn == 0.0) break;
+        }
+        /* back substitution H(0:jend,0:jend) y = g */
+        for (int i = jend - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int k = i + 1; k < jend; ++k) s -= H[i * mm + k] * y[k];
+            y[i] = s / H[i * mm + i];
+        }
+        /* x += M^{-1} V y */
+        for (long q = 0; q < np; ++q) {
+            double s = 0;
+            for (int i = 0; i < jend; ++i) s += V[(long)i * np + q] * y[i];
+            x[q] += s / d[q];
+        }
+    }
+    if (res) *res = beta;
+    free(V); free(w); free(z); free(d); free(r); free(H); free(cs); free(sn); free(g);
+    free(y); free(hc); free(h2v);
+    return it;
+}
+
+/* Remove the arithmetic mean over unique nodes from an assembled vector. */
+void orc_remove_mean_unique(const orc_mesh* m, double* r)
+{
+    long np = m->np;
+    double* one = dalloc(np);
+    for (long i = 0; i < np; ++i) one[i] = 1.0;
+    double s = orc_glsc(m, r, one) / (double)m->nglob;
+    for (long i = 0; i < np; ++i) r[i] -= s;
+    free(one);
+}
+
+/* Remove the volume (mass-weighted) mean: x -= int x / |V|. */
+void orc_remove_mean_mass(const orc_mesh* m, double* x)
+{
+    long np = m->np;
+    double* a = dalloc(np);
+    for (long i = 0; i < np; ++i) a[i] = m->B[i] * x[i];
+    double s = orc_sum(m, a) / m->vol;
+    for (long i = 0; i < np; ++i) x[i] -= s;
+    free(a);
+}
+
+/* Periodic Poisson solve A p = rhs (rhs assembled): unique-node mean of the
+ * rhs removed, GMRES from zero, mass-weighted mean of p removed. */
+int orc_poisson(const orc_mesh* m, const double* rhs, double* p, double tol, int maxit, int mrst, double* res)
+{
+    long np = m->np;
+    double* b = dalloc(np);
+    memcpy(b, rhs, np * sizeof(double));
+    orc_remove_mean_unique(m, b);
+    for (long i = 0; i < np; ++i) p[i] = 0.0;
+    int it = orc_gmres(m, 1.0, 0.0, b, p, tol, maxit, mrst, res, NULL);
+    orc_remove_mean_mass(m, p);
+    free(b);
+    return it;
+}
+
+/* ------------------------------------------------------------------ */
+/* Fluid step: BDF-k / EXT-k (k ramps 1,2,3) velocity-first incremental */
+/* pressure correction, in the order of the paper's Fig. 3 workflow.     */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    const orc_mesh* m;
+    double nu, dt, vtol, ptol;
+    int torder, vmaxit, pmaxit, mrst;
+    double t;
+    int step;
+    double *u[3], *ul1[3], *ul2[3];     /* u^n, u^{n-1}, u^{n-2} */
+    double *bn1[3], *bn2[3];            /* B N(u^{n-1}), B N(u^{n-2}) */
+    double *p;
+    /* last step statistics */
+    int vit[3], pit;
+    double vres[3], pres;
+} orc_fluid;
+
+typedef struct {
+    double t, ke, enst, maxdiv;
+    int vit[3], pit;
+    double vres[3], pres;
+} orc_step_stats;
+
+/* init: 0 = 3D Taylor-Green, 1 = 2D Taylor-Green extruded in z, 2 = zero */
+orc_fluid* orc_fluid_new(const orc_mesh* m, double nu, double dt, int torder,
+                         double vtol, double ptol, int vmaxit, int pmaxit, int mrst, int init)
+{
+    if (torder < 1 || torder > 3) return NULL;
+    orc_fluid* f = (orc_fluid*)calloc(1, sizeof(orc_fluid));
+    long np = m->np;
+    f->m = m; f->nu = nu; f->dt = dt; f->torder = torder;
+    f->vtol = vtol; f->ptol = ptol; f->vmaxit = vmaxit; f->pmaxit = pmaxit; f->mrst = mrst;
+    for (int c = 0; c < 3; ++c) {
+        f->u[c] = dalloc(np); f->ul1[c] = dalloc(np); f->ul2[c] = dalloc(np);
+        f->bn1[c] = dalloc(np); f->bn2[c] = dalloc(np);
+    }
+    f->p = dalloc(np);
+    const double* X = m->xyz;
+    const double* Y = m->xyz + np;
+    const double* Z = m->xyz + 2 * np;
+    for (long q = 0; q < np; ++q) {
+        double x = X[q], y = Y[q], z = Z[q];
+        if (init == 0) {
+            f->u[0][q] = sin(x) * cos(y) * cos(z);
+            f->u[1][q] = -cos(x) * sin(y) * cos(z);
+            f->u[2][q] = 0.0;
+            f->p[q] = (cos(2 * x) + cos(2 * y)) * (cos(2 * z) + 2.0) / 16.0;
+        } else if (init == 1) {
+            f->u[0][q] = sin(x) * cos(y);
+            f->u[1][q] = -cos(x) * sin(y);
+            f->u[2][q] = 0.0;
+            f->p[q] = (cos(2 * x) + cos(2 * y)) / 4.0;
+        }
+    }
+    /* history starts at the initial condition */
+    for (int c = 0; c < 3; ++c) {
+        memcpy(f->ul1[c], f->u[c], np * sizeof(double));
+        memcpy(f->ul2[c], f->u[c], np * sizeof(double));
+    }
+    orc_conv(m, f->u[0], f->u[1], f->u[2], f->bn1[0], f->bn1[1], f->bn1[2]);
+    for (int c = 0; c < 3; ++c) memcpy(f->bn2[c], f->bn1[c], np * sizeof(double));
+    return f;
+}
+
+void orc_fluid_free(orc_fluid* f)
+{
+    if (!f) return;
+    for (int c = 0; c < 3; ++c) { free(f->u[c]); free(f->ul1[c]); free(f->ul2[c]); free(f->bn1[c]); free(f->bn2[c]); }
+    free(f->p); free(f);
+}
+
+/* field ids: 0..2 u, 3 p, 4..6 u lag1, 7..9 u lag2, 10..12 BN lag1, 13..15 BN lag2 */
+static double* fluid_field(orc_fluid* f, int which)
+{
+    if (which >= 0 && which < 3) return f->u[which];
+    if (which == 3) return f->p;
+    if (which >= 4 && which < 7) return f->ul1[which - 4];
+    if (which >= 7 && which < 10) return f->ul2[which - 7];
+    if (which >= 10 && which < 13) return f->bn1[which - 10];
+    if (which >= 13 && which < 16) return f->bn2[which - 13];
+    return NULL;
+}
+int orc_fluid_get(orc_fluid* f, int which, double* out)
+{
+    double* s = fluid_field(f, which);
+    if (!s) return -1;
+    memcpy(out, s, f->m->np * sizeof(double));
+    return 0;
+}
+int orc_fluid_set(orc_fluid* f, int which, const double* in)
+{
+    double* s = fluid_field(f, which);
+    if (!s) return -1;
+    memcpy(s, in, f->m->np * sizeof(double));
+    return 0;
+}
+void orc_fluid_set_clock(orc_fluid* f, double t, int step) { f->t = t; f->step = step; }
+double orc_fluid_time(const orc_fluid* f) { return f->t; }
+int orc_fluid_stepno(const orc_fluid* f) { return f->step; }
+
+/* BDF-k and EXT-k coefficients for constant dt. */
+static void bdf_ext(int k, double* beta0, double b[3], double a[3])
+{
+    b[0] = b[1] = b[2] = a[0] = a[1] = a[2] = 0.0;
+    if (k == 1) { *beta0 = 1.0; b[0] = 1.0; a[0] = 1.0; }
+    else if (k == 2) { *beta0 = 1.5; b[0] = 2.0; b[1] = -0.5; a[0] = 2.0; a[1] = -1.0; }
+    else { *beta0 = 11.0 / 6.0; b[0] = 3.0; b[1] = -1.5; b[2] = 1.0 / 3.0; a[0] = 3.0; a[1] = -3.0; a[2] = 1.0; }
+}
+
+int orc_fluid_step(orc_fluid* f, orc_step_stats* st)
+{
+    const orc_mesh* m = f->m;
+    long np = m->np;
+    int k = f->step + 1 < f->torder ? f->step + 1 : f->torder;
+    double beta0, b[3], a[3];
+    bdf_ext(k, &beta0, b, a);
+    double dt = f->dt, nu = f->nu;
+    double h1 = nu, h2 = beta0 / dt;
+
+    double *bn[3], *rhs[3], *gp[3], *us[3];
+    for (int c = 0; c < 3; ++c) { bn[c] = dalloc(np); rhs[c] = dalloc(np); gp[c] = dalloc(np); us[c] = dalloc(np); }
+    double* r = dalloc(np); double* du = dalloc(np); double* w = dalloc(np);
+    double* rp = dalloc(np); double* phi = dalloc(np);
+
+    /* (i) explicit RHS: extrapolated convection, BDF history, old pressure gradient */
+    orc_conv(m, f->u[0], f->u[1], f->u[2], bn[0], bn[1], bn[2]);
+    orc_opgrad(m, f->p, gp[0], gp[1], gp[2]);
+    for (int c = 0; c < 3; ++c) {
+        const double* BN[3] = { bn[c], f->bn1[c], f->bn2[c] };
+        const double* UL[3] = { f->u[c], f->ul1[c], f->ul2[c] };
+        for (long q = 0; q < np; ++q) {
+            double s = 0, hsum = 0;
+            for (int j = 0; j < 3; ++j) { s += a[j] * BN[j][q]; hsum += b[j] * UL[j][q]; }
+            rhs[c][q] = s + m->B[q] / dt * hsum - gp[c][q];
+        }
+        orc_dssum(m, rhs[c]);
+    }
+    /* (ii) velocity: H du = rhs - H u^n, u* = u^n + du */
+    for (int c = 0; c < 3; ++c) {
+        apply_assembled(m, f->u[c], w, h1, h2);
+        for (long q = 0; q < np; ++q) { r[q] = rhs[c][q] - w[q]; du[q] = 0.0; }
+        f->vit[c] = orc_pcg(m, h1, h2, r, du, f->vtol, f->vmaxit, &f->vres[c], NULL);
+        for (long q = 0; q < np; ++q) us[c][q] = f->u[c][q] + du[q];
+    }
+    /* (iii) pressure increment: A phi = (beta0/dt) dssum(wdiv(u*)) */
+    orc_wdiv(m, us[0], us[1], us[2], rp);
+    orc_dssum(m, rp);
+    for (long q = 0; q < np; ++q) rp[q] *= beta0 / dt;
+    f->pit = orc_poisson(m, rp, phi, f->ptol, f->pmaxit, f->mrst, &f->pres);
+    /* (iv) correction u^{n+1} = u* - (dt/beta0) dssum(B grad phi) / Bsum, p += phi */
+    orc_opgrad(m, phi, gp[0], gp[1], gp[2]);
+    for (int c = 0; c < 3; ++c) orc_dssum(m, gp[c]);
+    for (int c = 0; c < 3; ++c) {
+        double* t2 = f->ul2[c];          /* recycle the oldest lag as the new state */
+        for (long q = 0; q < np; ++q) t2[q] = us[c][q] - dt / beta0 * gp[c][q] / m->Bsum[q];
+        f->ul2[c] = f->ul1[c];
+        f->ul1[c] = f->u[c];
+        f->u[c] = t2;
+        double* tb = f->bn2[c];
+        f->bn2[c] = f->bn1[c];
+        f->bn1[c] = tb;
+        memcpy(f->bn1[c], bn[c], np * sizeof(double));
+    }
+    for (long q = 0; q < np; ++q) f->p[q] += phi[q];
+    f->t += dt;
+    f->step += 1;
+
+    if (st) {
+        st->t = f->t;
+        orc_diagnostics(m, f->u[0], f->u[1], f->u[2], &st->ke, &st->enst, &st->maxdiv);
+        for (int c = 0; c < 3; ++c) { st->vit[c] = f->vit[c]; st->vres[c] = f->vres[c]; }
+        st->pit = f->pit; st->pres = f->pres;
+    }
+    for (int c = 0; c < 3; ++c) { free(bn[c]); free(rhs[c]); free(gp[c]); free(us[c]); }
+    free(r); free(du); free(w); free(rp); free(phi);
+    return 0;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
