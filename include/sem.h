@@ -1,0 +1,227 @@
+/*
+ * sem.h -- C ABI of libsem, the MI355X (gfx950) hot path of a matrix-free
+ * spectral-element (SEM) incompressible Navier-Stokes step on the
+ * Taylor-Green vortex with per-component precision control.
+ *
+ * Method: "Mixed-Precision SEM-Based CFD Simulations on GPUs: A Taylor-Green
+ * Vortex case".  The step follows the workflow of the paper's Fig. 3
+ * (explicit RHS, velocity CG+Jacobi solve, intermediate velocity u*,
+ * pressure residual, pressure GMRES solve, projection/correction), with the
+ * third-order time integration and solver settings of Sec. 3, the Taylor-
+ * Green initial condition of Sec. 3 (eqs. for u, v, w and Re = v0 L / nu),
+ * and the three-level precision model of Sec. 2 / Fig. 4: a global cap rp,
+ * block-level (SEM, velocity, pressure) compute/accumulate/storage
+ * precisions, and kernel-level overrides of hotspot kernels (Table 2).
+ *
+ * Conventions
+ *  - Every field is element-major, E*lx^3 values, u[e][k][j][i] with i
+ *    fastest, e = ex + nx*(ey + ny*ez), lx = order + 1.  Assembled fields
+ *    hold equal values in every local copy of a shared node.
+ *  - Device pointers are plain device addresses on the device current when
+ *    sem_bind was called.  The caller owns all device memory (the workspace
+ *    passed to sem_bind and every field buffer) and the stream.
+ *  - Calls that take device pointers are stream-ordered and asynchronous on
+ *    the bound stream unless stated otherwise.
+ *  - Return values: 0 (SEM_OK) or a negative sem_status.  No C++ exception
+ *    crosses this interface.  sem_strerror gives a message.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SEM_ABI_VERSION 1
+
+typedef enum {
+    SEM_OK = 0,
+    SEM_EINVAL = -1,     /* invalid argument or unsupported precision combination */
+    SEM_ENOMEM = -2,     /* workspace passed to sem_bind is too small */
+    SEM_EHIP = -3,       /* a HIP runtime call failed (see sem_strerror / sem_last_error) */
+    SEM_ENAN = -4,       /* a non-finite value appeared in a solve */
+    SEM_ENOTCONV = -5,   /* a Krylov solve hit its iteration limit */
+    SEM_ESTATE = -6      /* call not valid in the context's current state (e.g. not bound) */
+} sem_status;
+
+/* Floating-point formats.  SEM_INHERIT in a kernel override means "use the
+ * block default".  Ordering for the cap: FP64 > FP32 > FP16 = BF16. */
+typedef enum { SEM_FP64 = 0, SEM_FP32 = 1, SEM_FP16 = 2, SEM_BF16 = 3, SEM_INHERIT = -1 } sem_prec;
+
+/* Compute, accumulate and storage precision of a block or kernel (Fig. 4). */
+typedef struct { int compute, accumulate, storage; } sem_role;
+
+enum { SEM_BLOCK_SEM = 0, SEM_BLOCK_VEL = 1, SEM_BLOCK_PRES = 2, SEM_NBLOCK = 3 };
+
+/* Hotspot kernels that may override their block (Table 2 rows B-5..B-7 and
+ * the SEM operators of the step). */
+enum {
+    SEM_K_AX_VEL = 0,    /* velocity Helmholtz operator (block VEL) */
+    SEM_K_AX_PRES = 1,   /* pressure Poisson operator (block PRES) */
+    SEM_K_OPGRAD = 2,    /* mass-weighted gradient (block SEM) */
+    SEM_K_CONV = 3,      /* convective term (block SEM) */
+    SEM_K_DIV = 4,       /* weak divergence (block SEM) */
+    SEM_K_COUNT = 5
+};
+
+/* Quantities that stay in FP64 even when rp = FP32 (Sec. 2: reductions may
+ * use a higher precision capped at fp64; Sec. 4 design: accumulation kept in
+ * fp64).  This implementation requires all four whenever rp = FP32. */
+enum {
+    SEM_X_STATE = 1u << 0,   /* BDF/EXT velocity state, history and pressure */
+    SEM_X_GMRES = 1u << 1,   /* GMRES basis, Hessenberg, orthogonalisation dots */
+    SEM_X_RESID = 1u << 2,   /* true-residual checks */
+    SEM_X_REDUCE = 1u << 3,  /* global stage of every reduction */
+    SEM_X_ALL = 0xF
+};
+
+typedef struct {
+    int size;                        /* sizeof(sem_precision) */
+    int rp;                          /* global cap: SEM_FP64 or SEM_FP32 */
+    sem_role block[SEM_NBLOCK];
+    sem_role kernel[SEM_K_COUNT];    /* SEM_INHERIT fields take the block value */
+    unsigned fp64_exceptions;        /* SEM_X_* bits */
+} sem_precision;
+
+/* Periodic box [lo,hi] of nel[0]*nel[1]*nel[2] hexahedra of polynomial
+ * order `order` (2..11), optionally perturbed by the smooth map
+ *   x_c += amp*h_c*prod_q sin(pi (x_q - lo_q)/h_q + phase[3c+q])
+ * (conforming; periodic because every nel must then be even). */
+typedef struct {
+    int size;                        /* sizeof(sem_mesh_desc) */
+    int nel[3];
+    int order;
+    double lo[3], hi[3];
+    double deform_amp;
+    double deform_phase[9];
+} sem_mesh_desc;
+
+enum { SEM_INIT_ZERO = 0, SEM_INIT_TGV3D = 1, SEM_INIT_TGV2D = 2 };
+enum { SEM_MODE_OPERATOR = 0, SEM_MODE_POISSON = 1, SEM_MODE_FLUID = 2 };
+
+typedef struct {
+    int size;                        /* sizeof(sem_flow_desc) */
+    int mode;                        /* SEM_MODE_*: which workspaces sem_bind carves */
+    double nu, dt;                   /* viscosity (1/Re for v0 = L = 1), time step */
+    int torder;                      /* BDF/EXT order 1..3 (ramped 1,2,3 at start) */
+    double vel_tol, pres_tol;        /* absolute tolerances on the unique-node l2 norm */
+    int vel_maxit, pres_maxit;       /* Krylov iteration limits per solve */
+    int gmres_restart;               /* 1..30 */
+    int vel_max_refine;              /* FP64 true-residual refinement cycles (>= 1) */
+    int init;                        /* SEM_INIT_* */
+} sem_flow_desc;
+
+typedef struct sem_ctx sem_ctx;
+
+/* Per-step statistics of one context (filled after the stream is synced by
+ * sem_fluid_step, which synchronises before returning). */
+typedef struct {
+    double t, ke, enst, maxdiv;      /* after the step */
+    int vel_iters[3], pres_iters;
+    double vel_res[3], pres_res;     /* final residual norms */
+    int status;                      /* SEM_OK, SEM_ENAN or SEM_ENOTCONV */
+} sem_step_stats;
+
+typedef struct {
+    int iters;
+    double res;
+    int status;
+} sem_solve_stats;
+
+typedef struct {
+    double t, ke, enst, maxdiv;
+    int step;
+} sem_diag;
+
+/* Validates the descriptors and builds the host tables (GLL nodes and
+ * weights, derivative matrix, shared-node lists).  Host only: no device
+ * allocation and no HIP call.  Errors: SEM_EINVAL (invalid mesh, order,
+ * flow parameters, or a precision above rp outside the SEM_X exceptions, or
+ * a combination this build has no kernel for). */
+int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_precision* prec, sem_ctx** out);
+
+/* Exact device bytes sem_bind needs for this context (geometry in every
+ * precision its policy uses, plus the workspaces of its mode). */
+size_t sem_workspace_bytes(const sem_ctx* ctx);
+
+/* Binds a caller-owned device buffer (>= sem_workspace_bytes, 256-byte
+ * aligned) and stream (a hipStream_t, 0 = null stream) to the context, then
+ * computes the geometric factors, Jacobi diagonals and, in fluid mode, the
+ * initial condition on that stream.  Errors: SEM_ENOMEM, SEM_EHIP,
+ * SEM_ESTATE (already bound). */
+int sem_bind(sem_ctx* ctx, void* dev_buf, size_t bytes, void* hip_stream);
+
+/* Helmholtz operator w = h1 * sum_ab D_a^T G_ab D_b u + h2 * B u on every
+ * element (the paper's ax_helm), u and w device arrays of E*lx^3 values in
+ * buf_prec (FP64, FP32, FP16 or BF16 storage), geometry in geom_prec (must
+ * be one the context holds; SEM_INHERIT = the AX_PRES policy when h2 == 0,
+ * else AX_VEL).  flags & SEM_ASSEMBLE additionally applies dssum to w. */
+#define SEM_ASSEMBLE 1
+int sem_ax(sem_ctx* ctx, const void* u, void* w, double h1, double h2, int buf_prec, int geom_prec, int flags);
+
+/* Direct stiffness summation in place: every local copy of a shared node
+ * receives the sum of all copies (Q Q^T; the paper's gather/scatter). */
+int sem_dssum(sem_ctx* ctx, void* u, int buf_prec);
+
+/* Advances each of n fluid-mode contexts by nsteps time steps in one batch
+ * (same order and precision policy required, n <= 48).  stats has
+ * n*nsteps entries (ctx-major).  Synchronises the stream of ctxs[0], which
+ * all contexts of the batch must share.  A request whose solve fails is
+ * reported in its stats and keeps no influence on the others. */
+int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stats);
+
+/* Periodic Poisson solves A p = rhs for n POISSON- or FLUID-mode contexts of
+ * the same order and policy: rhs[i] (device, fp64, assembled) has its
+ * unique-node mean removed, GMRES runs from zero, and sol[i] (device, fp64)
+ * receives p with its mass-weighted mean removed. */
+int sem_poisson_solve(sem_ctx* const* ctxs, int n, const void* const* rhs, void* const* sol, sem_solve_stats* stats);
+
+/* Field access for checkpoints and tests.  which: SEM_F_*; component fields
+ * use which + c.  src/dst are fp64 arrays of E*lx^3 values, on the host when
+ * is_host != 0 (the call then synchronises), else device pointers. */
+enum {
+    SEM_F_U = 0,          /* +0..2 velocity u^n */
+    SEM_F_P = 3,
+    SEM_F_ULAG1 = 4,      /* +0..2 */
+    SEM_F_ULAG2 = 7,      /* +0..2 */
+    SEM_F_BNLAG1 = 10,    /* +0..2  B N(u^{n-1}) */
+    SEM_F_BNLAG2 = 13,    /* +0..2 */
+    SEM_F_MASS = 16,      /* read-only geometry */
+    SEM_F_BSUM = 17,
+    SEM_F_G = 18,         /* +0..5 */
+    SEM_F_M = 24,         /* +0..8  M_ac, index a*3+c */
+    SEM_F_DIAG_A = 33,    /* assembled stiffness diagonal */
+    SEM_F_COUNT = 34
+};
+int sem_get_field(sem_ctx* ctx, int which, void* dst, int is_host);
+int sem_set_field(sem_ctx* ctx, int which, const void* src, int is_host);
+/* time and step counter (for checkpoint/restart) */
+int sem_set_clock(sem_ctx* ctx, double t, int step);
+
+/* Kinetic energy, enstrophy and max |div u| of the current velocity
+ * (computes them; synchronises). */
+int sem_diagnostics(sem_ctx* ctx, sem_diag* out);
+
+/* Element-local SEM operators on caller arrays (fp64, E*lx^3 each, not
+ * assembled): conv -> 3 outputs, opgrad(p) -> 3 outputs, wdiv(3 inputs) ->
+ * 1 output; the SEM-block precision policy of the context applies. */
+int sem_conv(sem_ctx* ctx, const double* const* u3, double* const* out3);
+int sem_opgrad(sem_ctx* ctx, const double* p, double* const* out3);
+int sem_wdiv(sem_ctx* ctx, const double* const* v3, double* out);
+
+/* Sizes of a bound or unbound context. */
+int sem_sizes(const sem_ctx* ctx, int64_t* np, int64_t* nglob, int* lx, int* nelem);
+
+void sem_destroy(sem_ctx* ctx);
+const char* sem_strerror(int status);
+/* Text of the last error recorded by any call on this thread. */
+const char* sem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEM_H */

@@ -1,0 +1,648 @@
+// Point-wise Krylov and time-step kernels with fused partial reductions, and
+// the one-workgroup-per-request "finalise" kernels that add the partials in a
+// fixed order (fp64 global stage) and run the scalar logic of PCG, GMRES and
+// the BDF/EXT step on the device.  Inner products of assembled vectors weight
+// each local point by 1/multiplicity, i.e. they run over unique nodes.
+#include "k_common.h"
+
+namespace semk {
+
+struct PtRange {
+    long long p0, p1, L3;
+};
+
+__device__ __forceinline__ PtRange pt_range(const ReqDesc* R, int blk)
+{
+    PtRange r;
+    r.L3 = (long long)R->lx * R->lx * R->lx;
+    r.p0 = (long long)blk * R->epb * r.L3;
+    long long e1 = (long long)(blk + 1) * R->epb;
+    if (e1 > R->E) e1 = R->E;
+    r.p1 = e1 * r.L3;
+    return r;
+}
+
+template <typename T> __device__ __forceinline__ const T* fld(const ReqDesc* R, int id) { return (const T*)R->f[id]; }
+template <typename T> __device__ __forceinline__ T* fldw(const ReqDesc* R, int id) { return (T*)R->f[id]; }
+
+template <typename TV> __device__ __forceinline__ int idv_field() { return F_IDV32; }
+template <> __device__ __forceinline__ int idv_field<double>() { return F_IDV64; }
+template <typename TV> __device__ __forceinline__ int idp_field() { return F_IDP32; }
+template <> __device__ __forceinline__ int idp_field<double>() { return F_IDP64; }
+
+__device__ __forceinline__ void put_partial(const ReqDesc* R, int slot, int blk, double v)
+{
+    R->part[(long long)slot * R->nb + blk] = v;
+}
+
+// ------------------------------------------------------------------ generic point-wise ops
+template <typename TV, typename A>
+__global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs a)
+{
+    __shared__ double red[(SEM_VEC_THREADS / 64) * 2];
+    const int g = blockIdx.x;
+    const int ri = find_req(bt.eb, bt.n, g);
+    const ReqDesc* R = bt.r[ri];
+    const int blk = g - bt.eb[ri];
+    const int c = blockIdx.y;
+    if (!gate_ok(R, a.gate < 0 ? -1 : a.gate + (a.ncomp > 1 ? c : 0))) return;
+    const PtRange pr = pt_range(R, blk);
+    const int lx = R->lx;
+    const double* S = R->S;
+    double acc[2] = {0.0, 0.0};
+
+    switch (a.op) {
+    case V_VRESID: {
+        const double* rhs = fld<double>(R, F_RHS + c);
+        const double* w = fld<double>(R, F_W64 + c);
+        double* r = fldw<double>(R, F_R64 + c);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+            const double v = rhs[p] - w[p];
+            r[p] = v;
+            acc[0] += v * v * inv_mult((int)((p - pr.p0) % pr.L3), lx);
+        }
+        double v2[1] = {acc[0]};
+        block_sum<double, 1>(v2, red);
+        if (threadIdx.x == 0) put_partial(R, R_A + c, blk, v2[0]);
+        break;
+    }
+    case V_PCG_INIT: {
+        const double* r64 = fld<double>(R, F_R64 + c);
+        const TV* idv = fld<TV>(R, idv_field<TV>());
+        TV* x = fldw<TV>(R, F_PX + c);
+        TV* r = fldw<TV>(R, F_PR + c);
+        TV* z = fldw<TV>(R, F_PZ + c);
+        TV* pp = fldw<TV>(R, F_PP + c);
+        A s = 0;
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+            const TV rv = (TV)r64[p];
+            const TV zv = rv * idv[p];
+            x[p] = (TV)0; r[p] = rv; z[p] = zv; pp[p] = zv;
+            s += (A)(rv * zv) * (A)inv_mult((int)((p - pr.p0) % pr.L3), lx);
+        }
+        double v2[1] = {(double)s};
+        block_sum<double, 1>(v2, red);
+        if (threadIdx.x == 0) put_partial(R, R_B + c, blk, v2[0]);
+        break;
+    }
+    case V_PCG_UPD: {
+        const TV alpha = (TV)S[S_ALPHA + c];
+        const TV* idv = fld<TV>(R, idv_field<TV>());
+        TV* x = fldw<TV>(R, F_PX + c);
+        TV* r = fldw<TV>(R, F_PR + c);
+        TV* z = fldw<TV>(R, F_PZ + c);
+        const TV* pp = fld<TV>(R, F_PP + c);
+        const TV* w = fld<TV>(R, F_PW + c);
+        A rr = 0, rz = 0;
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+            x[p] += alpha * pp[p];
+            const TV rv = r[p] - alpha * w[p];
+            const TV zv = rv * idv[p];
+            r[p] = rv; z[p] = zv;
+            const A im = (A)inv_mult((int)((p - pr.p0) % pr.L3), lx);
+            rr += (A)(rv * rv) * im;
+            rz += (A)(rv * zv) * im;
+        }
+        double v2[2] = {(double)rr, (double)rz};
+        block_sum<double, 2>(v2, red);
+        if (threadIdx.x == 0) { put_partial(R, R_B + c, blk, v2[0]); put_partial(R, R_C + c, blk, v2[1]); }
+        break;
+    }
+    case V_PCG_P: {
+        const TV beta = (TV)S[S_BETA + c];
+        const TV* z = fld<TV>(R, F_PZ + c);
+        TV* pp = fldw<TV>(R, F_PP + c);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) pp[p] = z[p] + beta * pp[p];
+        break;
+    }
+    case V_US_COPY: {
+        const double* u = fld<double>(R, F_U + c);
+        double* us = fldw<double>(R, F_US + c);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) us[p] = u[p];
+        break;
+    }
+    case V_US_ADD: {
+        const TV* x = fld<TV>(R, F_PX + c);
+        double* us = fldw<double>(R, F_US + c);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) us[p] += (double)x[p];
+        break;
+    }
+    case V_RHS: {
+        const double* B = fld<double>(R, F_B64);
+        const double* bn0 = fld<double>(R, F_BN + c);
+        const double* bn1 = fld<double>(R, F_BNL1 + c);
+        const double* bn2 = fld<double>(R, F_BNL2 + c);
+        const double* u0 = fld<double>(R, F_U + c);
+        const double* u1 = fld<double>(R, F_UL1 + c);
+        const double* u2 = fld<double>(R, F_UL2 + c);
+        const double* gp = fld<double>(R, F_GP + c);
+        double* rhs = fldw<double>(R, F_RHS + c);
+        const double a1 = S[S_EXT], a2 = S[S_EXT + 1], a3 = S[S_EXT + 2];
+        const double b1 = S[S_BDF], b2 = S[S_BDF + 1], b3 = S[S_BDF + 2];
+        const double idt = 1.0 / S[S_DT];
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+            const double ext = a1 * bn0[p] + a2 * bn1[p] + a3 * bn2[p];
+            const double hist = b1 * u0[p] + b2 * u1[p] + b3 * u2[p];
+            rhs[p] = ext + B[p] * idt * hist - gp[p];
+        }
+        break;
+    }
+    case V_IDV: {
+        const double h1 = S[S_H1], h2 = S[S_H2];
+        const double* da = fld<double>(R, F_DA64);
+        const double* ib = fld<double>(R, F_IBSUM64);
+        double* idv = fldw<double>(R, F_IDV64);
+        float* idv32 = fldw<float>(R, F_IDV32);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+            const double v = 1.0 / (h1 * da[p] + h2 / ib[p]);
+            idv[p] = v;
+            if (idv32) idv32[p] = (float)v;
+        }
+        break;
+    }
+    case V_SUM_UNIQUE:
+    case V_SUM_MASS: {
+        const double* f = a.f0 >= 0 ? fld<double>(R, a.f0) : nullptr;
+        const double* B = fld<double>(R, F_B64);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+            const double fv = f ? f[p] : 1.0;
+            if (a.op == V_SUM_UNIQUE) acc[0] += fv * inv_mult((int)((p - pr.p0) % pr.L3), lx);
+            else acc[0] += fv * B[p];
+        }
+        double v2[1] = {acc[0]};
+        block_sum<double, 1>(v2, red);
+        if (threadIdx.x == 0) put_partial(R, R_X3, blk, v2[0]);
+        break;
+    }
+    case V_SUB_MEAN: {
+        double* f = fldw<double>(R, a.f0);
+        const double m = S[S_MEAN];
+        const double sc = a.f1 >= 0 ? S[a.f1] : 1.0;
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) f[p] = sc * (f[p] - m);
+        break;
+    }
+    case V_COPY: {
+        const double* f = fld<double>(R, a.f0 + c);
+        double* o = fldw<double>(R, a.f1 + c);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) o[p] = f[p];
+        break;
+    }
+    case V_ZERO: {
+        double* f = fldw<double>(R, a.f0 + c);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) f[p] = 0.0;
+        break;
+    }
+    case V_GM_PRECOND: {
+        const int J = R->I[I_GJ];
+        const double* v = fld<double>(R, F_V) + (long long)J * R->np;
+        const double* idp = fld<double>(R, F_IDP64);
+        TV* z = fldw<TV>(R, F_GZ);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) z[p] = (TV)(v[p] * idp[p]);
+        break;
+    }
+    case V_GM_NORMALIZE: {
+        const int J = R->I[I_GJ];
+        double* v = fldw<double>(R, F_V) + (long long)J * R->np;
+        const double* w = fld<double>(R, F_GWD);
+        const double sc = S[S_GNSCALE];
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) v[p] = w[p] * sc;
+        break;
+    }
+    case V_GM_RESID: {
+        const double* b = fld<double>(R, F_GB);
+        double* w = fldw<double>(R, F_GWD);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+            const double v = b[p] - w[p];
+            w[p] = v;
+            acc[0] += v * v * inv_mult((int)((p - pr.p0) % pr.L3), lx);
+        }
+        double v2[1] = {acc[0]};
+        block_sum<double, 1>(v2, red);
+        if (threadIdx.x == 0) put_partial(R, R_GN, blk, v2[0]);
+        break;
+    }
+    case V_CORRECT: {
+        const double* us = fld<double>(R, F_US + c);
+        const double* gp = fld<double>(R, F_GP + c);
+        const double* ib = fld<double>(R, F_IBSUM64);
+        double* un = fldw<double>(R, F_UL2 + c);
+        const double f = S[S_DT] / S[S_BETA0];
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) un[p] = us[p] - f * gp[p] * ib[p];
+        if (c == 0) {
+            double* pres = fldw<double>(R, F_P);
+            const double* phi = fld<double>(R, F_GX);
+            for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) pres[p] += phi[p];
+        }
+        break;
+    }
+    case V_AXPY_RAW: {
+        const double* x = (const double*)a.x_raw;
+        double* y = (double*)a.y_raw;
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) y[p] += a.a * x[p];
+        break;
+    }
+    default: break;
+    }
+}
+
+// ------------------------------------------------------------------ GMRES orthogonalisation passes
+// One pass over the points of a block touches every basis vector V_0..V_J
+// once; per-point values live in a register array sized for the largest
+// restart, indexed only with compile-time indices under a J guard.
+template <typename TW, int MODE>
+__global__ void __launch_bounds__(SEM_VEC_THREADS) gm_pass_kernel(Batch bt, int gate)
+{
+    constexpr int NV = SEM_MAXM + 1;
+    __shared__ double red[(SEM_VEC_THREADS / 64) * NV];
+    const int g = blockIdx.x;
+    const int ri = find_req(bt.eb, bt.n, g);
+    const ReqDesc* R = bt.r[ri];
+    const int blk = g - bt.eb[ri];
+    if (!gate_ok(R, gate)) return;
+    const PtRange pr = pt_range(R, blk);
+    const int lx = R->lx;
+    const int J = R->I[I_GJ];
+    const double* V = fld<double>(R, F_V);
+    const long long np = R->np;
+    const double* S = R->S;
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+
+    if (MODE == 0) {  // dots (V_i, GW)
+        const TW* w = fld<TW>(R, F_GW);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+            const double wv = to<double>(w[p]) * inv_mult((int)((p - pr.p0) % pr.L3), lx);
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                if (i <= J) acc[i] += V[i * np + p] * wv;
+        }
+    } else if (MODE == 1) {  // GWD = GW - sum h_i V_i, dots (V_i, GWD)
+        const TW* w = fld<TW>(R, F_GW);
+        double* wd = fldw<double>(R, F_GWD);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+            double vr[NV];
+            double wv = to<double>(w[p]);
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                if (i <= J) { vr[i] = V[i * np + p]; wv -= S[S_GHC + i] * vr[i]; }
+            wd[p] = wv;
+            wv *= inv_mult((int)((p - pr.p0) % pr.L3), lx);
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                if (i <= J) acc[i] += vr[i] * wv;
+        }
+    } else {  // GWD -= sum h2_i V_i, |GWD|^2
+        double* wd = fldw<double>(R, F_GWD);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+            double wv = wd[p];
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                if (i <= J) wv -= S[S_GH2 + i] * V[i * np + p];
+            wd[p] = wv;
+            acc[0] += wv * wv * inv_mult((int)((p - pr.p0) % pr.L3), lx);
+        }
+    }
+
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int nv = MODE == 2 ? 1 : J + 1;
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+        if (i < nv) acc[i] = wave_sum(acc[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) red[wid * NV + i] = acc[i];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+        double s = 0;
+        for (int w = 0; w < nw; ++w) s += red[w * NV + i];
+        put_partial(R, MODE == 2 ? R_GN : R_GM + i, blk, s);
+    }
+}
+
+// x += IDP * sum_{i < jend} y_i V_i  (right preconditioning applied once per cycle)
+__global__ void __launch_bounds__(SEM_VEC_THREADS) gm_xupd_kernel(Batch bt, int gate)
+{
+    constexpr int NV = SEM_MAXM;
+    const int g = blockIdx.x;
+    const int ri = find_req(bt.eb, bt.n, g);
+    const ReqDesc* R = bt.r[ri];
+    const int blk = g - bt.eb[ri];
+    if (!gate_ok(R, gate)) return;
+    const PtRange pr = pt_range(R, blk);
+    const int jend = R->I[I_GJEND];
+    const double* V = fld<double>(R, F_V);
+    const double* idp = fld<double>(R, F_IDP64);
+    double* x = fldw<double>(R, F_GX);
+    const long long np = R->np;
+    const double* y = R->S + S_GY;
+    for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i < jend) s += y[i] * V[i * np + p];
+        x[p] += s * idp[p];
+    }
+}
+
+void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s)
+{
+    dim3 grid(b.eb[b.n], a.ncomp > 0 ? a.ncomp : 1);
+    dim3 blk(SEM_VEC_THREADS);
+    if (grid.x == 0) return;
+    switch (a.op) {
+    case V_GM_DOTS:
+        if (a.tv == P64) hipLaunchKernelGGL((gm_pass_kernel<double, 0>), grid, blk, 0, s, b, a.gate);
+        else hipLaunchKernelGGL((gm_pass_kernel<float, 0>), grid, blk, 0, s, b, a.gate);
+        return;
+    case V_GM_UPD_DOTS:
+        if (a.tv == P64) hipLaunchKernelGGL((gm_pass_kernel<double, 1>), grid, blk, 0, s, b, a.gate);
+        else hipLaunchKernelGGL((gm_pass_kernel<float, 1>), grid, blk, 0, s, b, a.gate);
+        return;
+    case V_GM_UPD_NORM:
+        hipLaunchKernelGGL((gm_pass_kernel<double, 2>), grid, blk, 0, s, b, a.gate);
+        return;
+    case V_GM_XUPD:
+        hipLaunchKernelGGL(gm_xupd_kernel, grid, blk, 0, s, b, a.gate);
+        return;
+    default: break;
+    }
+    if (a.tv == P64) hipLaunchKernelGGL((vec_kernel<double, double>), grid, blk, 0, s, b, a);
+    else if (a.ta == P64) hipLaunchKernelGGL((vec_kernel<float, double>), grid, blk, 0, s, b, a);
+    else hipLaunchKernelGGL((vec_kernel<float, float>), grid, blk, 0, s, b, a);
+}
+
+// ------------------------------------------------------------------ finalise kernels
+// fixed-order sum of the partials of one slot (valid in thread 0)
+__device__ double slot_sum(const ReqDesc* R, int slot, double* red)
+{
+    double s = 0.0;
+    const double* p = R->part + (long long)slot * R->nb;
+    for (int q = threadIdx.x; q < R->nb; q += blockDim.x) s += p[q];
+    double v[1] = {s};
+    block_sum<double, 1>(v, red);
+    return v[0];
+}
+__device__ double slot_max(const ReqDesc* R, int slot, double* red)
+{
+    double s = 0.0;
+    const double* p = R->part + (long long)slot * R->nb;
+    for (int q = threadIdx.x; q < R->nb; q += blockDim.x) s = fmax(s, p[q]);
+    s = wave_max(s);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double m = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+    __syncthreads();
+    return m;
+}
+
+__device__ __forceinline__ bool finite(double v) { return isfinite(v); }
+
+__global__ void __launch_bounds__(256) fin_kernel(Batch bt, FinArgs a)
+{
+    __shared__ double red[8 * 4];
+    __shared__ double sums[SEM_MAXM + 2];
+    const int ri = blockIdx.x;
+    ReqDesc* R = (ReqDesc*)bt.r[ri];
+    double* S = R->S;
+    int* I = R->I;
+    const int t = threadIdx.x;
+    switch (a.op) {
+    case FIN_VINIT: {
+        for (int c = 0; c < 3; ++c) {
+            double s = slot_sum(R, R_A + c, red);
+            if (t == 0) {
+                double rn = sqrt(s);
+                S[S_R0 + c] = rn;
+                S[S_RN + c] = rn;
+                bool act = rn > S[S_VTOL] && I[I_VREF + c] < I[I_VMAXREF];
+                if (!finite(rn)) { I[I_NAN] = 1; act = false; }
+                if (act) I[I_VREF + c] += 1;
+                I[I_VACT + c] = act ? 1 : 0;
+            }
+        }
+        break;
+    }
+    case FIN_PCG_RHO: {
+        for (int c = 0; c < 3; ++c) {
+            double s = slot_sum(R, R_B + c, red);
+            if (t == 0 && I[I_VACT + c]) S[S_RHO + c] = s;
+        }
+        break;
+    }
+    case FIN_PCG_ALPHA: {
+        for (int c = 0; c < 3; ++c) {
+            if (!I[I_VACT + c]) continue;  // uniform per block
+            double s = slot_sum(R, R_A + c, red);
+            if (t == 0) S[S_ALPHA + c] = S[S_RHO + c] / s;
+        }
+        break;
+    }
+    case FIN_PCG_BETA: {
+        for (int c = 0; c < 3; ++c) {
+            if (!I[I_VACT + c]) continue;
+            double rr = slot_sum(R, R_B + c, red);
+            double rz = slot_sum(R, R_C + c, red);
+            if (t == 0) {
+                double rn = sqrt(rr);
+                S[S_RN + c] = rn;
+                I[I_VIT + c] += 1;
+                if (!finite(rn)) { I[I_NAN] = 1; I[I_VACT + c] = 0; }
+                else if (rn <= S[S_VTOL] || I[I_VIT + c] >= I[I_VMAXIT]) I[I_VACT + c] = 0;
+                else { S[S_BETA + c] = rz / S[S_RHO + c]; S[S_RHO + c] = rz; }
+            }
+        }
+        break;
+    }
+    case FIN_MEAN_UNIQUE: {
+        double s = slot_sum(R, R_X3, red);
+        if (t == 0) S[S_MEAN] = s / (double)R->nglob;
+        break;
+    }
+    case FIN_MEAN_MASS: {
+        double s = slot_sum(R, R_X3, red);
+        if (t == 0) S[S_MEAN] = s / S[S_VOL];
+        break;
+    }
+    case FIN_GM_H1:
+    case FIN_GM_H2: {
+        if (!I[I_GARN]) break;
+        const int J = I[I_GJ];
+        for (int i = 0; i <= J; ++i) {
+            double s = slot_sum(R, R_GM + i, red);
+            if (t == 0) S[(a.op == FIN_GM_H1 ? S_GHC : S_GH2) + i] = s;
+        }
+        if (t == 0) I[I_GNORM] = 0;
+        break;
+    }
+    case FIN_GM_COL: {
+        if (!I[I_GARN]) break;
+        double hn2 = slot_sum(R, R_GN, red);
+        if (t == 0) {
+            const int m = I[I_GM];
+            const int J = I[I_GJ];
+            double* H = S + S_GH;
+            double* cs = S + S_GCS;
+            double* sn = S + S_GSN;
+            double* gg = S + S_GG;
+            const double hn = sqrt(hn2);
+            for (int i = 0; i <= J; ++i) H[i * m + J] = S[S_GHC + i] + S[S_GH2 + i];
+            H[(J + 1) * m + J] = hn;
+            for (int i = 0; i < J; ++i) {
+                const double x = H[i * m + J], y = H[(i + 1) * m + J];
+                H[i * m + J] = cs[i] * x + sn[i] * y;
+                H[(i + 1) * m + J] = -sn[i] * x + cs[i] * y;
+            }
+            const double x = H[J * m + J], y = H[(J + 1) * m + J];
+            const double den = sqrt(x * x + y * y);
+            cs[J] = x / den;
+            sn[J] = y / den;
+            H[J * m + J] = den;
+            H[(J + 1) * m + J] = 0.0;
+            gg[J + 1] = -sn[J] * gg[J];
+            gg[J] = cs[J] * gg[J];
+            I[I_GIT] += 1;
+            const bool bad = !finite(gg[J + 1]) || !finite(den);
+            if (bad) I[I_NAN] = 1;
+            if (bad || fabs(gg[J + 1]) <= S[S_PTOL] || hn == 0.0 || J + 1 == m || I[I_GIT] >= I[I_GMAXIT]) {
+                const int jend = bad ? 0 : J + 1;
+                double* yv = S + S_GY;
+                for (int r = jend - 1; r >= 0; --r) {
+                    double s = gg[r];
+                    for (int k = r + 1; k < jend; ++k) s -= H[r * m + k] * yv[k];
+                    yv[r] = s / H[r * m + r];
+                }
+                I[I_GJEND] = jend;
+                I[I_GARN] = 0;
+                I[I_GEND] = 1;
+                I[I_GNORM] = 0;
+            } else {
+                I[I_GJ] = J + 1;
+                S[S_GNSCALE] = 1.0 / hn;
+                I[I_GNORM] = 1;
+            }
+        }
+        break;
+    }
+    case FIN_GM_RESTART: {
+        if (!I[I_GEND]) break;
+        double s = slot_sum(R, R_GN, red);
+        if (t == 0) {
+            const double beta = sqrt(s);
+            S[S_GBETA] = beta;
+            I[I_GEND] = 0;
+            if (!finite(beta)) I[I_NAN] = 1;
+            if (!finite(beta) || beta <= S[S_PTOL] || I[I_GIT] >= I[I_GMAXIT]) {
+                I[I_GACT] = 0; I[I_GARN] = 0; I[I_GNORM] = 0;
+            } else {
+                I[I_GJ] = 0;
+                double* gg = S + S_GG;
+                for (int i = 0; i <= SEM_MAXM; ++i) gg[i] = 0.0;
+                gg[0] = beta;
+                S[S_GNSCALE] = 1.0 / beta;
+                I[I_GARN] = 1; I[I_GNORM] = 1;
+            }
+        }
+        break;
+    }
+    case FIN_GM_START: {
+        // fresh solve from x = 0: the first cycle end computes r = b
+        if (t == 0) {
+            I[I_GJ] = 0; I[I_GJEND] = 0; I[I_GIT] = 0;
+            I[I_GACT] = 1; I[I_GARN] = 0; I[I_GEND] = 1; I[I_GNORM] = 0;
+        }
+        break;
+    }
+    case FIN_DIAG: {
+        double ke = slot_sum(R, R_X0, red);
+        double en = slot_sum(R, R_X1, red);
+        double md = slot_max(R, R_X2, red);
+        if (t == 0) {
+            S[S_KE] = ke / S[S_VOL];
+            S[S_ENST] = en / S[S_VOL];
+            S[S_MAXDIV] = md;
+            if (!finite(ke) || !finite(en)) I[I_NAN] = 1;
+        }
+        break;
+    }
+    case FIN_STEP_BEGIN: {
+        if (t == 0) {
+            const int torder = I[I_TORDER];
+            const int k = I[I_STEP] + 1 < torder ? I[I_STEP] + 1 : torder;
+            I[I_ORDER] = k;
+            double b0, b1 = 0, b2 = 0, b3 = 0, a1 = 0, a2 = 0, a3 = 0;
+            if (k == 1) { b0 = 1.0; b1 = 1.0; a1 = 1.0; }
+            else if (k == 2) { b0 = 1.5; b1 = 2.0; b2 = -0.5; a1 = 2.0; a2 = -1.0; }
+            else { b0 = 11.0 / 6.0; b1 = 3.0; b2 = -1.5; b3 = 1.0 / 3.0; a1 = 3.0; a2 = -3.0; a3 = 1.0; }
+            S[S_BETA0] = b0;
+            S[S_BDF] = b1; S[S_BDF + 1] = b2; S[S_BDF + 2] = b3;
+            S[S_EXT] = a1; S[S_EXT + 1] = a2; S[S_EXT + 2] = a3;
+            S[S_H1] = S[S_NU];
+            S[S_H2] = b0 / S[S_DT];
+            S[S_MEAN + 0] = 0.0;
+            for (int c = 0; c < 3; ++c) { I[I_VIT + c] = 0; I[I_VREF + c] = 0; I[I_VACT + c] = 0; }
+        }
+        break;
+    }
+    case FIN_STEP_END: {
+        if (t == 0) {
+            for (int c = 0; c < 3; ++c) {
+                void* un = R->f[F_UL2 + c];          // holds u^{n+1}
+                R->f[F_UL2 + c] = R->f[F_UL1 + c];
+                R->f[F_UL1 + c] = R->f[F_U + c];
+                R->f[F_U + c] = un;
+                void* bs = R->f[F_BNL2 + c];
+                R->f[F_BNL2 + c] = R->f[F_BNL1 + c];
+                R->f[F_BNL1 + c] = R->f[F_BN + c];
+                R->f[F_BN + c] = bs;
+            }
+            I[I_STEP] += 1;
+            S[S_TIME] += S[S_DT];
+        }
+        break;
+    }
+    case FIN_POLL: {
+        if (t == 0) {
+            int v = 0;
+            for (int c = 0; c < (a.ncomp > 1 ? a.ncomp : 1); ++c) v |= I[a.gate + c];
+            a.host_flags[ri] = v;
+        }
+        break;
+    }
+    case FIN_SUM_RAW: {
+        double s = slot_sum(R, a.f0, red);
+        if (t == 0) S[S_RED + a.gate] = s;
+        break;
+    }
+    case FIN_VOL: {
+        double s = slot_sum(R, R_X3, red);
+        if (t == 0) S[S_VOL] = s;
+        break;
+    }
+    case FIN_STATS: {
+        if (t == 0) {
+            double* o = a.host_stats + (long long)ri * SEM_NSTAT;
+            o[0] = S[S_TIME]; o[1] = S[S_KE]; o[2] = S[S_ENST]; o[3] = S[S_MAXDIV];
+            for (int c = 0; c < 3; ++c) { o[4 + c] = I[I_VIT + c]; o[7 + c] = S[S_RN + c]; }
+            o[10] = I[I_GIT]; o[11] = S[S_GBETA]; o[12] = I[I_NAN]; o[13] = I[I_STEP];
+            o[14] = I[I_VREF] + I[I_VREF + 1] + I[I_VREF + 2]; o[15] = I[I_ORDER];
+        }
+        break;
+    }
+    default: break;
+    }
+    (void)sums;
+}
+
+void launch_fin(const Batch& b, const FinArgs& a, hipStream_t s)
+{
+    if (b.n == 0) return;
+    hipLaunchKernelGGL(fin_kernel, dim3(b.n), dim3(256), 0, s, b, a);
+}
+
+}  // namespace semk

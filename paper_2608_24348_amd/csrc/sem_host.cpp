@@ -1,0 +1,1123 @@
+// Host runtime of libsem: descriptor validation, precision-policy resolution,
+// GLL tables, shared-node lists, workspace layout, and the drivers of the
+// batched Jacobi-PCG, GMRES and fluid step.  All arithmetic of the hot path
+// runs in the HIP kernels; the host only sequences launches and polls small
+// device-written convergence flags.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sem.h"
+#include "sem_internal.h"
+
+using namespace semk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(SEM_EHIP, std::string(#call " failed: ") + hipGetErrorString(e_));     \
+    } while (0)
+
+// ------------------------------------------------------------------ GLL tables
+// Nodes: -1, 1 and the zeros of q(x) = L_{N+1}(x) - L_{N-1}(x) (proportional
+// to (1-x^2) L_N'(x)), found by Newton from Chebyshev-Gauss-Lobatto guesses.
+// Weights 2 / (N (N+1) L_N(x)^2).  Derivative matrix from barycentric weights
+// (off-diagonal (lam_j/lam_i)/(x_i-x_j), diagonal = minus the row sum).
+void legendre_trio(int N, double x, double& lNm1, double& lN, double& lNp1, double& dNm1, double& dNp1)
+{
+    // values and derivatives of L_{N-1}, L_N, L_{N+1} by the Bonnet recurrence
+    double p_prev = 1.0, p = x, d_prev = 0.0, d = 1.0;
+    std::vector<double> P(N + 2), Dv(N + 2);
+    P[0] = 1.0; Dv[0] = 0.0;
+    P[1] = x; Dv[1] = 1.0;
+    for (int n = 1; n <= N; ++n) {
+        double pn = ((2 * n + 1) * x * p - n * p_prev) / (n + 1);
+        double dn = d_prev + (2 * n + 1) * p;
+        p_prev = p; p = pn; d_prev = d; d = dn;
+        P[n + 1] = p; Dv[n + 1] = d;
+    }
+    lNm1 = P[N - 1]; lN = P[N]; lNp1 = P[N + 1];
+    dNm1 = Dv[N - 1]; dNp1 = Dv[N + 1];
+}
+
+void gll_tables(int N, std::vector<double>& x, std::vector<double>& w, std::vector<double>& D)
+{
+    const int n = N + 1;
+    x.assign(n, 0.0); w.assign(n, 0.0); D.assign(n * n, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int j = 0; j <= N; ++j) {
+        double xj = -std::cos(pi * j / N);
+        if (j > 0 && j < N) {
+            for (int it = 0; it < 200; ++it) {
+                double a, b, c, da, dc;
+                legendre_trio(N, xj, a, b, c, da, dc);
+                double q = c - a, dq = dc - da;
+                double dx = q / dq;
+                xj -= dx;
+                if (std::fabs(dx) <= 1e-17) break;
+            }
+        }
+        x[j] = xj;
+    }
+    x[0] = -1.0; x[N] = 1.0;
+    for (int j = 1; j <= N / 2; ++j) {  // symmetric pairs
+        double s = 0.5 * (x[N - j] - x[j]);
+        x[j] = -s; x[N - j] = s;
+    }
+    if (N % 2 == 0) x[N / 2] = 0.0;
+    for (int j = 0; j <= N; ++j) {
+        double a, b, c, da, dc;
+        legendre_trio(N, x[j], a, b, c, da, dc);
+        w[j] = 2.0 / (N * (N + 1.0) * b * b);
+    }
+    std::vector<double> lam(n, 1.0);
+    for (int j = 0; j < n; ++j) {
+        double prod = 1.0;
+        for (int k = 0; k < n; ++k)
+            if (k != j) prod *= (x[j] - x[k]);
+        lam[j] = 1.0 / prod;
+    }
+    for (int i = 0; i < n; ++i) {
+        double rs = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (i == j) continue;
+            double v = (lam[j] / lam[i]) / (x[i] - x[j]);
+            D[i * n + j] = v;
+            rs += v;
+        }
+        D[i * n + i] = -rs;
+    }
+}
+
+int prec_rank(int p)
+{
+    // FP64 > FP32 > FP16 = BF16
+    switch (p) {
+    case SEM_FP64: return 3;
+    case SEM_FP32: return 2;
+    case SEM_FP16: return 1;
+    case SEM_BF16: return 1;
+    default: return -1;
+    }
+}
+
+const char* pname(int p)
+{
+    switch (p) {
+    case SEM_FP64: return "fp64";
+    case SEM_FP32: return "fp32";
+    case SEM_FP16: return "fp16";
+    case SEM_BF16: return "bf16";
+    default: return "?";
+    }
+}
+
+int to_pid(int p)
+{
+    switch (p) {
+    case SEM_FP64: return P64;
+    case SEM_FP32: return P32;
+    case SEM_FP16: return P16;
+    default: return PBF;
+    }
+}
+
+size_t psize(int pid) { return pid == P64 ? 8 : pid == P32 ? 4 : 2; }
+
+struct Resolved {
+    int tv, tva;            // velocity vectors, velocity dot accumulation (PrecId)
+    int axv_g;              // velocity Ax geometry storage
+    int tp;                 // pressure Ax vectors
+    int axp_g;              // pressure Ax geometry storage
+    int opg_m, conv_m, div_m;
+    bool need32, need16;
+    int kind16;             // P16 or PBF
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+struct sem_ctx {
+    sem_mesh_desc mesh;
+    sem_flow_desc flow;
+    sem_precision prec;
+    Resolved rs;
+    int N, lx, E, epb, nb;
+    long long np, nglob;
+    int n2, n4, n8;
+    std::vector<double> D64tab;
+    std::vector<float> D32tab;
+    std::vector<int> idx2, idx4, idx8;
+    double vol;
+    // layout
+    size_t off_desc, off_S, off_I, off_part, off_D64, off_D32, off_i2, off_i4, off_i8;
+    size_t foff[NFIELD];
+    size_t fbytes[NFIELD];
+    size_t bytes;
+    // bound state
+    bool bound = false;
+    char* dev = nullptr;
+    hipStream_t stream = nullptr;
+    ReqDesc* ddesc = nullptr;
+    ReqDesc hdesc;
+    int* hflags = nullptr;  // pinned host flags for polls
+    MeshParams mp;
+};
+
+namespace {
+
+int resolve_policy(const sem_precision* p, Resolved& r)
+{
+    if (!p || p->size != (int)sizeof(sem_precision)) return fail(SEM_EINVAL, "sem_precision: bad size field");
+    if (p->rp != SEM_FP64 && p->rp != SEM_FP32) return fail(SEM_EINVAL, "rp must be SEM_FP64 or SEM_FP32");
+    const int rp = prec_rank(p->rp);
+    if (p->rp == SEM_FP32 && (p->fp64_exceptions & SEM_X_ALL) != SEM_X_ALL)
+        return fail(SEM_EINVAL, "rp = fp32 requires the fp64 exceptions STATE|GMRES|RESID|REDUCE (state, GMRES "
+                                "orthogonalisation, residual checks and the global reduction stage stay fp64)");
+    sem_role blk[SEM_NBLOCK];
+    for (int b = 0; b < SEM_NBLOCK; ++b) {
+        blk[b] = p->block[b];
+        const int v[3] = {blk[b].compute, blk[b].accumulate, blk[b].storage};
+        for (int q = 0; q < 3; ++q)
+            if (prec_rank(v[q]) < 0) return fail(SEM_EINVAL, "block precision must be FP64, FP32, FP16 or BF16");
+    }
+    static const int kblock[SEM_K_COUNT] = {SEM_BLOCK_VEL, SEM_BLOCK_PRES, SEM_BLOCK_SEM, SEM_BLOCK_SEM, SEM_BLOCK_SEM};
+    static const char* kname[SEM_K_COUNT] = {"ax_vel", "ax_pres", "opgrad", "conv", "div"};
+    sem_role kr[SEM_K_COUNT];
+    for (int k = 0; k < SEM_K_COUNT; ++k) {
+        const sem_role& o = p->kernel[k];
+        const sem_role& d = blk[kblock[k]];
+        kr[k].compute = o.compute == SEM_INHERIT ? d.compute : o.compute;
+        kr[k].accumulate = o.accumulate == SEM_INHERIT ? d.accumulate : o.accumulate;
+        kr[k].storage = o.storage == SEM_INHERIT ? d.storage : o.storage;
+        const int v[3] = {kr[k].compute, kr[k].accumulate, kr[k].storage};
+        for (int q = 0; q < 3; ++q) {
+            if (prec_rank(v[q]) < 0) return fail(SEM_EINVAL, std::string(kname[k]) + ": unknown precision");
+            if (prec_rank(v[q]) > rp) return fail(SEM_EINVAL, std::string(kname[k]) + ": precision above rp");
+        }
+    }
+    for (int b = 0; b < SEM_NBLOCK; ++b) {
+        const int v[3] = {blk[b].compute, blk[b].accumulate, blk[b].storage};
+        for (int q = 0; q < 3; ++q)
+            if (prec_rank(v[q]) > rp) return fail(SEM_EINVAL, "block precision above rp");
+    }
+    // vectors of the solver blocks: compute == storage in {fp64, fp32}
+    const sem_role& vb = blk[SEM_BLOCK_VEL];
+    const sem_role& pb = blk[SEM_BLOCK_PRES];
+    if (vb.storage != SEM_FP64 && vb.storage != SEM_FP32)
+        return fail(SEM_EINVAL, "velocity block storage must be fp64 or fp32 (16-bit storage is a kernel override of ax_vel)");
+    if (vb.compute != vb.storage) return fail(SEM_EINVAL, "velocity block: compute must equal storage");
+    if (prec_rank(vb.accumulate) < prec_rank(vb.compute)) return fail(SEM_EINVAL, "velocity block: accumulate below compute");
+    if (pb.storage != SEM_FP64 && pb.storage != SEM_FP32)
+        return fail(SEM_EINVAL, "pressure block storage must be fp64 or fp32 (16-bit storage is a kernel override of ax_pres)");
+    if (pb.compute != pb.storage) return fail(SEM_EINVAL, "pressure block: compute must equal storage");
+    r.tv = to_pid(vb.storage);
+    r.tva = to_pid(vb.accumulate);
+    r.tp = to_pid(pb.storage);
+    // Ax kernels: (vec64, geo64, C64) or (vec32, geo32|16|bf16, C32)
+    auto check_ax = [&](int k, int vec, int& geo) -> int {
+        const sem_role& q = kr[k];
+        if (q.compute == SEM_FP64) {
+            if (vec != P64 || q.storage != SEM_FP64)
+                return fail(SEM_EINVAL, std::string(kname[k]) + ": fp64 compute needs fp64 vectors and geometry");
+        } else if (q.compute == SEM_FP32) {
+            if (vec != P32) return fail(SEM_EINVAL, std::string(kname[k]) + ": fp32 compute needs fp32 block vectors");
+        } else {
+            return fail(SEM_EINVAL, std::string(kname[k]) + ": 16-bit arithmetic is expressed as 16-bit storage with "
+                                    "fp32 compute/accumulate");
+        }
+        if (prec_rank(q.accumulate) < prec_rank(q.compute))
+            return fail(SEM_EINVAL, std::string(kname[k]) + ": accumulate below compute");
+        geo = to_pid(q.storage);
+        return 0;
+    };
+    int rc;
+    if ((rc = check_ax(SEM_K_AX_VEL, r.tv, r.axv_g))) return rc;
+    if ((rc = check_ax(SEM_K_AX_PRES, r.tp, r.axp_g))) return rc;
+    auto check_op = [&](int k, int& m) -> int {
+        const sem_role& q = kr[k];
+        if (q.compute == SEM_FP64) {
+            if (q.storage != SEM_FP64) return fail(SEM_EINVAL, std::string(kname[k]) + ": fp64 compute needs fp64 storage");
+        } else if (q.compute != SEM_FP32) {
+            return fail(SEM_EINVAL, std::string(kname[k]) + ": compute must be fp64 or fp32");
+        } else if (q.storage == SEM_FP64) {
+            return fail(SEM_EINVAL, std::string(kname[k]) + ": fp32 compute reads fp32 or 16-bit metric terms");
+        }
+        m = to_pid(q.storage);
+        return 0;
+    };
+    if ((rc = check_op(SEM_K_OPGRAD, r.opg_m))) return rc;
+    if ((rc = check_op(SEM_K_CONV, r.conv_m))) return rc;
+    if ((rc = check_op(SEM_K_DIV, r.div_m))) return rc;
+    const int all[5] = {r.axv_g, r.axp_g, r.opg_m, r.conv_m, r.div_m};
+    r.need32 = false; r.need16 = false; r.kind16 = 0;
+    for (int v : all) {
+        if (v == P32) r.need32 = true;
+        if (v == P16 || v == PBF) {
+            if (r.need16 && r.kind16 != v) return fail(SEM_EINVAL, "one context holds a single 16-bit format (fp16 or bf16)");
+            r.need16 = true;
+            r.kind16 = v;
+        }
+    }
+    return 0;
+}
+
+// shared-node tuples of the periodic box, grouped by multiplicity, each
+// tuple sorted by local index and emitted once (by its smallest copy)
+void build_tuples(sem_ctx* c)
+{
+    const int nx = c->mesh.nel[0], ny = c->mesh.nel[1], nz = c->mesh.nel[2];
+    const int N = c->N, lx = c->lx;
+    const long long L3 = (long long)lx * lx * lx;
+    c->idx2.clear(); c->idx4.clear(); c->idx8.clear();
+    for (int e = 0; e < c->E; ++e) {
+        const int ex = e % nx, ey = (e / nx) % ny, ez = e / (nx * ny);
+        for (int k = 0; k < lx; ++k)
+            for (int j = 0; j < lx; ++j)
+                for (int i = 0; i < lx; ++i) {
+                    const bool bi = (i == 0 || i == N), bj = (j == 0 || j == N), bk = (k == 0 || k == N);
+                    const int nb = (int)bi + (int)bj + (int)bk;
+                    if (nb == 0) continue;
+                    // candidate (element coordinate, local index) pairs per direction
+                    int ce[3][2], cl[3][2], cn[3];
+                    const int ecoord[3] = {ex, ey, ez}, lcoord[3] = {i, j, k}, nel[3] = {nx, ny, nz};
+                    for (int d = 0; d < 3; ++d) {
+                        const int l = lcoord[d], ec = ecoord[d];
+                        if (l == 0) {
+                            ce[d][0] = ec; cl[d][0] = 0;
+                            ce[d][1] = (ec - 1 + nel[d]) % nel[d]; cl[d][1] = N;
+                            cn[d] = 2;
+                        } else if (l == N) {
+                            ce[d][0] = ec; cl[d][0] = N;
+                            ce[d][1] = (ec + 1) % nel[d]; cl[d][1] = 0;
+                            cn[d] = 2;
+                        } else {
+                            ce[d][0] = ec; cl[d][0] = l; cn[d] = 1;
+                        }
+                    }
+                    int ids[8], m = 0;
+                    for (int a = 0; a < cn[0]; ++a)
+                        for (int b = 0; b < cn[1]; ++b)
+                            for (int q = 0; q < cn[2]; ++q) {
+                                const long long ee = ce[0][a] + (long long)nx * (ce[1][b] + (long long)ny * ce[2][q]);
+                                ids[m++] = (int)(ee * L3 + cl[0][a] + lx * (cl[1][b] + lx * cl[2][q]));
+                            }
+                    std::sort(ids, ids + m);
+                    const int self = (int)(e * L3 + i + lx * (j + lx * k));
+                    if (ids[0] != self) continue;
+                    std::vector<int>& dst = m == 2 ? c->idx2 : m == 4 ? c->idx4 : c->idx8;
+                    dst.insert(dst.end(), ids, ids + m);
+                }
+    }
+    c->n2 = (int)(c->idx2.size() / 2);
+    c->n4 = (int)(c->idx4.size() / 4);
+    c->n8 = (int)(c->idx8.size() / 8);
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+void build_layout(sem_ctx* c)
+{
+    const long long np = c->np;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    c->off_desc = take(sizeof(ReqDesc));
+    c->off_S = take(sizeof(double) * NSCALAR);
+    c->off_I = take(sizeof(int) * NINT);
+    c->off_part = take(sizeof(double) * (size_t)NRED * c->nb);
+    c->off_D64 = take(sizeof(double) * (c->lx * c->lx + 2 * c->lx));
+    c->off_D32 = take(sizeof(float) * (c->lx * c->lx + 2 * c->lx));
+    c->off_i2 = take(sizeof(int) * c->idx2.size());
+    c->off_i4 = take(sizeof(int) * c->idx4.size());
+    c->off_i8 = take(sizeof(int) * c->idx8.size());
+    for (int f = 0; f < NFIELD; ++f) { c->foff[f] = 0; c->fbytes[f] = 0; }
+    auto field = [&](int f, size_t bytes) { c->fbytes[f] = bytes; c->foff[f] = take(bytes); };
+    const size_t d = 8 * (size_t)np;
+    field(F_G64, 6 * d);
+    field(F_B64, d);
+    field(F_M64, 9 * d);
+    field(F_IBSUM64, d);
+    field(F_DA64, d);
+    field(F_IDP64, d);
+    const Resolved& r = c->rs;
+    if (r.need32) {
+        field(F_G32, 6 * 4 * (size_t)np);
+        field(F_B32, 4 * (size_t)np);
+        field(F_M32, 9 * 4 * (size_t)np);
+    }
+    if (r.need16) {
+        field(F_G16, 6 * 2 * (size_t)np);
+        field(F_B16, 2 * (size_t)np);
+        field(F_M16, 9 * 2 * (size_t)np);
+        field(F_GSC, 2 * 4 * (size_t)c->E);
+        field(F_MSC, 4 * (size_t)c->E);
+    }
+    const int mode = c->flow.mode;
+    if (mode >= SEM_MODE_POISSON) {
+        const size_t tp = psize(r.tp);
+        field(F_V, (size_t)(c->flow.gmres_restart + 1) * d);
+        field(F_GZ, tp * np);
+        field(F_GW, tp * np);
+        field(F_GWD, d);
+        field(F_GB, d);
+        field(F_GX, d);
+    }
+    if (mode >= SEM_MODE_FLUID) {
+        field(F_IDV64, d);
+        if (r.tv == P32) field(F_IDV32, 4 * (size_t)np);
+        for (int f = F_U; f <= F_PHI; ++f) field(f, d);
+        const size_t tv = psize(r.tv);
+        for (int f = F_PX; f <= F_PWc; ++f) field(f, tv * np);
+    }
+    c->bytes = off;
+}
+
+semk::Batch make_batch(sem_ctx* const* ctxs, int n)
+{
+    semk::Batch b;
+    memset(&b, 0, sizeof(b));
+    b.n = n;
+    b.eb[0] = 0;
+    b.gs[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        sem_ctx* c = ctxs[i];
+        b.eb[i + 1] = b.eb[i] + c->nb;
+        b.gs[i + 1] = b.gs[i] + c->hdesc.c2 + c->hdesc.c4 + c->hdesc.c8;
+        b.r[i] = c->ddesc;
+    }
+    return b;
+}
+
+int check_hip_last()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SEM_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return 0;
+}
+
+int poll_k()
+{
+    static int k = -1;
+    if (k < 0) {
+        const char* s = getenv("SEM_POLL_K");
+        k = s ? std::max(1, atoi(s)) : 4;
+    }
+    return k;
+}
+
+// ------------------------------------------------------------------ launch helpers
+void ax(const Batch& b, int lx, int src, int dst, int ncomp, int hsel, double h1, double h2, int precond, int pdot,
+        int gate, int tu, int tg, hipStream_t s)
+{
+    AxLaunch a;
+    a.src = src; a.dst = dst; a.ncomp = ncomp; a.hsel = hsel; a.h1 = h1; a.h2 = h2;
+    a.precond = precond; a.pdot = pdot; a.gate = gate; a.tu = tu; a.tg = tg;
+    a.u_raw = nullptr; a.w_raw = nullptr;
+    launch_ax(b, lx, a, s);
+}
+
+void vec(const Batch& b, int op, int ncomp, int tv, int gate, hipStream_t s, int f0 = -1, int f1 = -1, int ta = P64)
+{
+    VecArgs a;
+    a.op = op; a.gate = gate; a.ncomp = ncomp; a.tv = tv; a.ta = ta; a.f0 = f0; a.f1 = f1; a.a = 0.0;
+    a.x_raw = nullptr; a.y_raw = nullptr;
+    launch_vec(b, a, s);
+}
+
+void fin(const Batch& b, int op, hipStream_t s, int gate = -1, int ncomp = 1, int* flags = nullptr, int f0 = 0)
+{
+    FinArgs a;
+    a.op = op; a.gate = gate; a.ncomp = ncomp; a.f0 = f0; a.host_flags = flags;
+    launch_fin(b, a, s);
+}
+
+// poll: returns number of requests whose flag (any component) is set, or <0 on error
+int poll(const Batch& b, int gate, int ncomp, int* hflags, hipStream_t s)
+{
+    fin(b, FIN_POLL, s, gate, ncomp, hflags);
+    int rc = check_hip_last();
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(SEM_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    int cnt = 0;
+    for (int i = 0; i < b.n; ++i) cnt += hflags[i] != 0;
+    return cnt;
+}
+
+// Jacobi-PCG on the assembled velocity Helmholtz operator for the three
+// components of every request: solves H x_c = R64_c in the velocity storage
+// precision; on return US_c += x_c.  With fp32 vectors the residual is
+// recomputed in fp64 from US and further correction solves run until the
+// fp64 residual meets the tolerance (or the refinement limit).
+int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
+{
+    sem_ctx* c0 = ctxs[0];
+    const int lx = c0->lx;
+    const Resolved& r = c0->rs;
+    const int tv = r.tv;
+    int* hf = c0->hflags;
+    // fp64 residual of the current state: R64 = RHS - dssum(H U), norms -> VACT
+    vec(b, V_US_COPY, 3, P64, -1, s);
+    ax(b, lx, F_U, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, s);
+    launch_dssum(b, F_W64, 3, P64, -1, nullptr, s);
+    vec(b, V_VRESID, 3, P64, -1, s);
+    fin(b, FIN_VINIT, s);
+    const int maxref = c0->flow.vel_max_refine;
+    for (int cyc = 0; cyc < maxref; ++cyc) {
+        int act = poll(b, I_VACT, 3, hf, s);
+        if (act < 0) return act;
+        if (act == 0) break;
+        vec(b, V_PCG_INIT, 3, tv, -1, s, -1, -1, r.tva);
+        fin(b, FIN_PCG_RHO, s);
+        const int K = poll_k();
+        int guard = 0;
+        for (;;) {
+            for (int q = 0; q < K; ++q) {
+                ax(b, lx, F_PP, F_PW, 3, S_H1, 0, 0, -1, R_A, I_VACT, tv, r.axv_g, s);
+                launch_dssum(b, F_PW, 3, tv, I_VACT, nullptr, s);
+                fin(b, FIN_PCG_ALPHA, s);
+                vec(b, V_PCG_UPD, 3, tv, I_VACT, s, -1, -1, r.tva);
+                fin(b, FIN_PCG_BETA, s);
+                vec(b, V_PCG_P, 3, tv, I_VACT, s);
+            }
+            guard += K;
+            int a2 = poll(b, I_VACT, 3, hf, s);
+            if (a2 < 0) return a2;
+            if (a2 == 0 || guard > c0->flow.vel_maxit + K) break;
+        }
+        vec(b, V_US_ADD, 3, tv, -1, s);
+        if (tv == P64) break;  // fp64 recurrence residual is the solver's stop criterion
+        ax(b, lx, F_US, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, s);
+        launch_dssum(b, F_W64, 3, P64, -1, nullptr, s);
+        vec(b, V_VRESID, 3, P64, -1, s);
+        fin(b, FIN_VINIT, s);
+    }
+    return check_hip_last();
+}
+
+// One GMRES(m) cycle iteration sequence (Arnoldi step, then cycle end when
+// pending); every kernel is gated so converged requests idle.
+void gmres_iteration(const Batch& b, int lx, const Resolved& r, hipStream_t s)
+{
+    const int tp = r.tp;
+    vec(b, V_GM_PRECOND, 1, tp, I_GARN, s);
+    ax(b, lx, F_GZ, F_GW, 1, -1, 1.0, 0.0, -1, -1, I_GARN, tp, r.axp_g, s);
+    launch_dssum(b, F_GW, 1, tp, I_GARN, nullptr, s);
+    vec(b, V_GM_DOTS, 1, tp, I_GARN, s);
+    fin(b, FIN_GM_H1, s);
+    vec(b, V_GM_UPD_DOTS, 1, tp, I_GARN, s);
+    fin(b, FIN_GM_H2, s);
+    vec(b, V_GM_UPD_NORM, 1, P64, I_GARN, s);
+    fin(b, FIN_GM_COL, s);
+    vec(b, V_GM_NORMALIZE, 1, P64, I_GNORM, s);
+    // cycle end: x update and fp64 true residual, then restart or finish
+    vec(b, V_GM_XUPD, 1, P64, I_GEND, s);
+    ax(b, lx, F_GX, F_GWD, 1, -1, 1.0, 0.0, -1, -1, I_GEND, P64, P64, s);
+    launch_dssum(b, F_GWD, 1, P64, I_GEND, nullptr, s);
+    vec(b, V_GM_RESID, 1, P64, I_GEND, s);
+    fin(b, FIN_GM_RESTART, s);
+    vec(b, V_GM_NORMALIZE, 1, P64, I_GNORM, s);
+}
+
+// GMRES on F_GB -> F_GX (GX zeroed by the caller), then mass-mean removal of GX
+int pressure_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
+{
+    sem_ctx* c0 = ctxs[0];
+    const int lx = c0->lx;
+    int* hf = c0->hflags;
+    fin(b, FIN_GM_START, s);
+    const int K = poll_k();
+    const int m = c0->flow.gmres_restart;
+    const int limit = c0->flow.pres_maxit + c0->flow.pres_maxit / std::max(1, m) + 4;
+    int guard = 0;
+    for (;;) {
+        for (int q = 0; q < K; ++q) gmres_iteration(b, lx, c0->rs, s);
+        guard += K;
+        int act = poll(b, I_GACT, 1, hf, s);
+        if (act < 0) return act;
+        if (act == 0 || guard > limit) break;
+    }
+    vec(b, V_SUM_MASS, 1, P64, -1, s, F_GX);
+    fin(b, FIN_MEAN_MASS, s);
+    vec(b, V_SUB_MEAN, 1, P64, -1, s, F_GX, -1);
+    return check_hip_last();
+}
+
+int bind_check(sem_ctx* c)
+{
+    if (!c) return fail(SEM_EINVAL, "null context");
+    if (!c->bound) return fail(SEM_ESTATE, "context is not bound");
+    return 0;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* sem_strerror(int status)
+{
+    switch (status) {
+    case SEM_OK: return "ok";
+    case SEM_EINVAL: return "invalid argument";
+    case SEM_ENOMEM: return "workspace too small";
+    case SEM_EHIP: return "HIP runtime error";
+    case SEM_ENAN: return "non-finite value in a solve";
+    case SEM_ENOTCONV: return "solver did not converge";
+    case SEM_ESTATE: return "invalid state";
+    default: return "unknown status";
+    }
+}
+
+const char* sem_last_error(void) { return g_err.c_str(); }
+
+int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_precision* prec, sem_ctx** out)
+{
+    if (!mesh || !flow || !prec || !out) return fail(SEM_EINVAL, "null argument");
+    *out = nullptr;
+    if (mesh->size != (int)sizeof(sem_mesh_desc)) return fail(SEM_EINVAL, "sem_mesh_desc: bad size field");
+    if (flow->size != (int)sizeof(sem_flow_desc)) return fail(SEM_EINVAL, "sem_flow_desc: bad size field");
+    if (mesh->order < 2 || mesh->order > 11) return fail(SEM_EINVAL, "order must be in 2..11");
+    long long E = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (mesh->nel[d] < 1) return fail(SEM_EINVAL, "element counts must be >= 1");
+        if (!(mesh->hi[d] > mesh->lo[d])) return fail(SEM_EINVAL, "hi must exceed lo");
+        if (mesh->deform_amp != 0.0 && mesh->nel[d] % 2) return fail(SEM_EINVAL, "a perturbed mesh needs even element counts");
+        E *= mesh->nel[d];
+    }
+    const long long lx = mesh->order + 1;
+    if (E * lx * lx * lx >= (1LL << 31)) return fail(SEM_EINVAL, "more than 2^31 local points");
+    if (!(std::fabs(mesh->deform_amp) < 0.25)) return fail(SEM_EINVAL, "deform_amp must be below 0.25 (positive Jacobian)");
+    if (flow->mode < SEM_MODE_OPERATOR || flow->mode > SEM_MODE_FLUID) return fail(SEM_EINVAL, "bad mode");
+    if (flow->mode >= SEM_MODE_POISSON) {
+        if (flow->gmres_restart < 1 || flow->gmres_restart > SEM_MAXM) return fail(SEM_EINVAL, "gmres_restart must be 1..30");
+        if (!(flow->pres_tol > 0) || flow->pres_maxit < 1) return fail(SEM_EINVAL, "bad pressure tolerance/limit");
+    }
+    if (flow->mode == SEM_MODE_FLUID) {
+        if (!(flow->nu > 0) || !(flow->dt > 0)) return fail(SEM_EINVAL, "nu and dt must be positive");
+        if (flow->torder < 1 || flow->torder > 3) return fail(SEM_EINVAL, "torder must be 1..3");
+        if (!(flow->vel_tol > 0) || flow->vel_maxit < 1 || flow->vel_max_refine < 1)
+            return fail(SEM_EINVAL, "bad velocity tolerance/limits");
+        if (flow->init < SEM_INIT_ZERO || flow->init > SEM_INIT_TGV2D) return fail(SEM_EINVAL, "bad init");
+    }
+    Resolved rs;
+    int rc = resolve_policy(prec, rs);
+    if (rc) return rc;
+
+    sem_ctx* c = new sem_ctx();
+    c->mesh = *mesh;
+    c->flow = *flow;
+    c->prec = *prec;
+    c->rs = rs;
+    c->N = mesh->order;
+    c->lx = (int)lx;
+    c->E = (int)E;
+    c->np = E * lx * lx * lx;
+    c->nglob = E * (long long)mesh->order * mesh->order * mesh->order;
+    c->epb = epb_of(c->lx);
+    c->nb = (int)((E + c->epb - 1) / c->epb);
+    std::vector<double> x, w, D;
+    gll_tables(c->N, x, w, D);
+    c->D64tab.resize(lx * lx + 2 * lx);
+    c->D32tab.resize(lx * lx + 2 * lx);
+    for (int q = 0; q < lx * lx; ++q) c->D64tab[q] = D[q];
+    for (int q = 0; q < lx; ++q) { c->D64tab[lx * lx + q] = w[q]; c->D64tab[lx * lx + lx + q] = x[q]; }
+    for (size_t q = 0; q < c->D64tab.size(); ++q) c->D32tab[q] = (float)c->D64tab[q];
+    build_tuples(c);
+    build_layout(c);
+    MeshParams& mp = c->mp;
+    for (int d = 0; d < 3; ++d) {
+        mp.nel[d] = mesh->nel[d];
+        mp.lo[d] = mesh->lo[d];
+        mp.h[d] = (mesh->hi[d] - mesh->lo[d]) / mesh->nel[d];
+    }
+    mp.N = c->N;
+    mp.amp = mesh->deform_amp;
+    for (int q = 0; q < 9; ++q) mp.phase[q] = mesh->deform_phase[q];
+    *out = c;
+    return 0;
+}
+
+size_t sem_workspace_bytes(const sem_ctx* ctx) { return ctx ? ctx->bytes : 0; }
+
+int sem_sizes(const sem_ctx* c, int64_t* np, int64_t* nglob, int* lx, int* nelem)
+{
+    if (!c) return fail(SEM_EINVAL, "null context");
+    if (np) *np = c->np;
+    if (nglob) *nglob = c->nglob;
+    if (lx) *lx = c->lx;
+    if (nelem) *nelem = c->E;
+    return 0;
+}
+
+int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
+{
+    if (!c || !dev_buf) return fail(SEM_EINVAL, "null argument");
+    if (c->bound) return fail(SEM_ESTATE, "context already bound");
+    if (bytes < c->bytes) return fail(SEM_ENOMEM, "workspace smaller than sem_workspace_bytes");
+    if (((uintptr_t)dev_buf) & 255) return fail(SEM_EINVAL, "workspace must be 256-byte aligned");
+    c->dev = (char*)dev_buf;
+    c->stream = (hipStream_t)hip_stream;
+    hipStream_t s = c->stream;
+    ReqDesc& d = c->hdesc;
+    memset(&d, 0, sizeof(d));
+    d.E = c->E; d.lx = c->lx; d.epb = c->epb; d.nb = c->nb;
+    d.n2 = c->n2; d.n4 = c->n4; d.n8 = c->n8;
+    d.c2 = (c->n2 + SEM_GS_CHUNK - 1) / SEM_GS_CHUNK;
+    d.c4 = (c->n4 + SEM_GS_CHUNK - 1) / SEM_GS_CHUNK;
+    d.c8 = (c->n8 + SEM_GS_CHUNK - 1) / SEM_GS_CHUNK;
+    d.prec16 = c->rs.need16 ? c->rs.kind16 : 0;
+    d.gm_m = c->flow.gmres_restart;
+    d.np = c->np; d.nglob = c->nglob;
+    d.idx2 = (const int*)(c->dev + c->off_i2);
+    d.idx4 = (const int*)(c->dev + c->off_i4);
+    d.idx8 = (const int*)(c->dev + c->off_i8);
+    d.S = (double*)(c->dev + c->off_S);
+    d.I = (int*)(c->dev + c->off_I);
+    d.part = (double*)(c->dev + c->off_part);
+    d.D64 = (const double*)(c->dev + c->off_D64);
+    d.D32 = (const float*)(c->dev + c->off_D32);
+    for (int f = 0; f < NFIELD; ++f) d.f[f] = c->fbytes[f] ? (void*)(c->dev + c->foff[f]) : nullptr;
+    c->ddesc = (ReqDesc*)(c->dev + c->off_desc);
+
+    // scalars and integer state
+    std::vector<double> S(NSCALAR, 0.0);
+    std::vector<int> I(NINT, 0);
+    S[S_NU] = c->flow.nu;
+    S[S_DT] = c->flow.dt;
+    S[S_VTOL] = c->flow.vel_tol;
+    S[S_PTOL] = c->flow.pres_tol;
+    S[S_H1] = 1.0;
+    I[I_TORDER] = c->flow.torder;
+    I[I_VMAXIT] = c->flow.vel_maxit;
+    I[I_VMAXREF] = c->flow.vel_max_refine;
+    I[I_GMAXIT] = c->flow.pres_maxit;
+    I[I_GM] = c->flow.gmres_restart;
+    I[I_ALWAYS] = 1;
+    HIPCHK(hipHostMalloc((void**)&c->hflags, sizeof(int) * SEM_MAXB, hipHostMallocDefault));
+    HIPCHK(hipMemcpyAsync(c->ddesc, &d, sizeof(d), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d.S, S.data(), sizeof(double) * NSCALAR, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d.I, I.data(), sizeof(int) * NINT, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync((void*)d.D64, c->D64tab.data(), sizeof(double) * c->D64tab.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync((void*)d.D32, c->D32tab.data(), sizeof(float) * c->D32tab.size(), hipMemcpyHostToDevice, s));
+    if (!c->idx2.empty()) HIPCHK(hipMemcpyAsync((void*)d.idx2, c->idx2.data(), sizeof(int) * c->idx2.size(), hipMemcpyHostToDevice, s));
+    if (!c->idx4.empty()) HIPCHK(hipMemcpyAsync((void*)d.idx4, c->idx4.data(), sizeof(int) * c->idx4.size(), hipMemcpyHostToDevice, s));
+    if (!c->idx8.empty()) HIPCHK(hipMemcpyAsync((void*)d.idx8, c->idx8.data(), sizeof(int) * c->idx8.size(), hipMemcpyHostToDevice, s));
+    c->bound = true;
+
+    sem_ctx* one[1] = {c};
+    Batch b = make_batch(one, 1);
+    launch_geometry(b, c->lx, c->mp, s);
+    launch_diag_a(b, c->lx, s);
+    launch_dssum(b, F_DA64, 1, P64, -1, nullptr, s);
+    HIPCHK(hipMemcpyAsync(d.f[F_IBSUM64], d.f[F_B64], 8 * (size_t)c->np, hipMemcpyDeviceToDevice, s));
+    launch_dssum(b, F_IBSUM64, 1, P64, -1, nullptr, s);
+    launch_geo_post(b, s);
+    if (c->rs.need32 || c->rs.need16) launch_geo_cast(b, c->lx, c->rs.need32 ? 1 : 0, c->rs.need16 ? c->rs.kind16 : 0, s);
+    // domain volume (sum of B)
+    vec(b, V_SUM_MASS, 1, P64, -1, s, -1);
+    fin(b, FIN_VOL, s);
+    int rc = check_hip_last();
+    if (rc) return rc;
+    if (c->flow.mode == SEM_MODE_FLUID) {
+        launch_init_fields(b, c->lx, c->flow.init, c->mp, s);
+        // history of the convective term starts at the initial field
+        launch_conv(b, c->lx, c->rs.conv_m, s);
+        vec(b, V_COPY, 3, P64, -1, s, F_BN, F_BNL1);
+        vec(b, V_COPY, 3, P64, -1, s, F_BN, F_BNL2);
+        rc = check_hip_last();
+        if (rc) return rc;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    int nanflag = 0;
+    HIPCHK(hipMemcpy(&nanflag, d.I + I_NAN, sizeof(int), hipMemcpyDeviceToHost));
+    if (nanflag) return fail(SEM_EINVAL, "non-positive Jacobian in the mesh");
+    return 0;
+}
+
+void sem_destroy(sem_ctx* c)
+{
+    if (!c) return;
+    if (c->hflags) (void)hipHostFree(c->hflags);
+    delete c;
+}
+
+}  // extern "C"
+
+namespace {
+
+int field_of(const sem_ctx* c, int which, int& fid)
+{
+    if (which >= SEM_F_U && which < SEM_F_U + 3) fid = F_U + (which - SEM_F_U);
+    else if (which == SEM_F_P) fid = F_P;
+    else if (which >= SEM_F_ULAG1 && which < SEM_F_ULAG1 + 3) fid = F_UL1 + (which - SEM_F_ULAG1);
+    else if (which >= SEM_F_ULAG2 && which < SEM_F_ULAG2 + 3) fid = F_UL2 + (which - SEM_F_ULAG2);
+    else if (which >= SEM_F_BNLAG1 && which < SEM_F_BNLAG1 + 3) fid = F_BNL1 + (which - SEM_F_BNLAG1);
+    else if (which >= SEM_F_BNLAG2 && which < SEM_F_BNLAG2 + 3) fid = F_BNL2 + (which - SEM_F_BNLAG2);
+    else if (which == SEM_F_MASS) fid = F_B64;
+    else if (which == SEM_F_BSUM) fid = F_IBSUM64;
+    else if (which >= SEM_F_G && which < SEM_F_G + 6) fid = F_G64;
+    else if (which >= SEM_F_M && which < SEM_F_M + 9) fid = F_M64;
+    else if (which == SEM_F_DIAG_A) fid = F_DA64;
+    else return fail(SEM_EINVAL, "unknown field");
+    if (!c->fbytes[fid]) return fail(SEM_EINVAL, "field not present in this context's mode");
+    return 0;
+}
+
+// current device pointer of a field (state fields rotate on the device)
+int current_ptr(sem_ctx* c, int fid, char** out)
+{
+    void* p = nullptr;
+    HIPCHK(hipMemcpy(&p, &c->ddesc->f[fid], sizeof(void*), hipMemcpyDeviceToHost));
+    *out = (char*)p;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sem_ax(sem_ctx* c, const void* u, void* w, double h1, double h2, int buf_prec, int geom_prec, int flags)
+{
+    int rc = bind_check(c);
+    if (rc) return rc;
+    if (!u || !w) return fail(SEM_EINVAL, "null field pointer");
+    if (buf_prec < SEM_FP64 || buf_prec > SEM_BF16) return fail(SEM_EINVAL, "bad buf_prec");
+    int tg;
+    if (geom_prec == SEM_INHERIT) tg = h2 == 0.0 ? c->rs.axp_g : c->rs.axv_g;
+    else if (geom_prec >= SEM_FP64 && geom_prec <= SEM_BF16) tg = to_pid(geom_prec);
+    else return fail(SEM_EINVAL, "bad geom_prec");
+    const int tu = to_pid(buf_prec);
+    bool held = tg == P64 || (tg == P32 && c->rs.need32) || ((tg == P16 || tg == PBF) && c->rs.need16 && c->rs.kind16 == tg);
+    if (!held) return fail(SEM_EINVAL, std::string("geometry in ") + pname(geom_prec) + " is not held by this context");
+    bool ok = (tu == P64 && tg == P64) || (tu == P32 && tg != P64) || (tu == P16 && tg == P16) || (tu == PBF && tg == PBF);
+    if (!ok) return fail(SEM_EINVAL, "unsupported (vector, geometry) precision pair for Ax");
+    sem_ctx* one[1] = {c};
+    Batch b = make_batch(one, 1);
+    AxLaunch a;
+    a.src = -1; a.dst = -1; a.ncomp = 1; a.hsel = -1; a.h1 = h1; a.h2 = h2;
+    a.precond = -1; a.pdot = -1; a.gate = -1; a.tu = tu; a.tg = tg;
+    a.u_raw = u; a.w_raw = w;
+    launch_ax(b, c->lx, a, c->stream);
+    if (flags & SEM_ASSEMBLE) launch_dssum(b, -1, 1, tu, -1, w, c->stream);
+    return check_hip_last();
+}
+
+int sem_dssum(sem_ctx* c, void* u, int buf_prec)
+{
+    int rc = bind_check(c);
+    if (rc) return rc;
+    if (!u) return fail(SEM_EINVAL, "null field pointer");
+    if (buf_prec < SEM_FP64 || buf_prec > SEM_BF16) return fail(SEM_EINVAL, "bad buf_prec");
+    sem_ctx* one[1] = {c};
+    Batch b = make_batch(one, 1);
+    launch_dssum(b, -1, 1, to_pid(buf_prec), -1, u, c->stream);
+    return check_hip_last();
+}
+
+static int check_batch(sem_ctx* const* ctxs, int n, int min_mode)
+{
+    if (!ctxs || n < 1 || n > SEM_MAXB) return fail(SEM_EINVAL, "batch size must be 1..48");
+    for (int i = 0; i < n; ++i) {
+        int rc = bind_check(ctxs[i]);
+        if (rc) return rc;
+        if (ctxs[i]->flow.mode < min_mode) return fail(SEM_EINVAL, "context mode does not hold the needed workspaces");
+        if (ctxs[i]->lx != ctxs[0]->lx) return fail(SEM_EINVAL, "batched contexts must share the order");
+        if (memcmp(&ctxs[i]->rs, &ctxs[0]->rs, sizeof(Resolved)) != 0)
+            return fail(SEM_EINVAL, "batched contexts must share the precision policy");
+        if (ctxs[i]->stream != ctxs[0]->stream) return fail(SEM_EINVAL, "batched contexts must share the stream");
+        if (ctxs[i]->flow.gmres_restart != ctxs[0]->flow.gmres_restart)
+            return fail(SEM_EINVAL, "batched contexts must share the GMRES restart length");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(SEM_EINVAL, "a context appears twice in a batch");
+    }
+    return 0;
+}
+
+static double* stats_buffer()
+{
+    static double* buf = nullptr;
+    if (!buf) {
+        if (hipHostMalloc((void**)&buf, sizeof(double) * SEM_MAXB * SEM_NSTAT, hipHostMallocDefault) != hipSuccess)
+            buf = nullptr;
+    }
+    return buf;
+}
+
+int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stats)
+{
+    int rc = check_batch(ctxs, n, SEM_MODE_FLUID);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(SEM_EINVAL, "nsteps must be >= 0");
+    sem_ctx* c0 = ctxs[0];
+    const int lx = c0->lx;
+    const Resolved& r = c0->rs;
+    hipStream_t s = c0->stream;
+    Batch b = make_batch(ctxs, n);
+    double* hs = stats_buffer();
+    if (!hs) return fail(SEM_EHIP, "pinned statistics buffer allocation failed");
+    int status = 0;
+    for (int st = 0; st < nsteps; ++st) {
+        fin(b, FIN_STEP_BEGIN, s);
+        vec(b, V_IDV, 1, P64, -1, s);
+        // (i) explicit terms: convection, old pressure gradient, BDF/EXT history
+        launch_conv(b, lx, r.conv_m, s);
+        launch_opgrad(b, lx, r.opg_m, F_P, F_GP, s);
+        vec(b, V_RHS, 3, P64, -1, s);
+        launch_dssum(b, F_RHS, 3, P64, -1, nullptr, s);
+        // (ii) velocity Helmholtz solves -> u*
+        rc = velocity_solve(ctxs, b, s);
+        if (rc) return rc;
+        // (iii) pressure increment: A phi = (beta0/dt) dssum(wdiv(u*)), zero-mean rhs
+        launch_wdiv(b, lx, r.div_m, F_US, F_RP, s);
+        launch_dssum(b, F_RP, 1, P64, -1, nullptr, s);
+        vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_RP);
+        fin(b, FIN_MEAN_UNIQUE, s);
+        vec(b, V_SUB_MEAN, 1, P64, -1, s, F_RP, S_H2);
+        vec(b, V_COPY, 1, P64, -1, s, F_RP, F_GB);
+        vec(b, V_ZERO, 1, P64, -1, s, F_GX);
+        rc = pressure_solve(ctxs, b, s);
+        if (rc) return rc;
+        // (iv) correction and pressure update, lag rotation, diagnostics
+        launch_opgrad(b, lx, r.opg_m, F_GX, F_GP, s);
+        launch_dssum(b, F_GP, 3, P64, -1, nullptr, s);
+        vec(b, V_CORRECT, 3, P64, -1, s);
+        fin(b, FIN_STEP_END, s);
+        launch_diagnostics(b, lx, s);
+        fin(b, FIN_DIAG, s);
+        FinArgs fa;
+        fa.op = FIN_STATS; fa.gate = -1; fa.ncomp = 1; fa.f0 = 0; fa.host_flags = nullptr; fa.host_stats = hs;
+        launch_fin(b, fa, s);
+        rc = check_hip_last();
+        if (rc) return rc;
+        HIPCHK(hipStreamSynchronize(s));
+        for (int i = 0; i < n; ++i) {
+            const double* o = hs + (size_t)i * SEM_NSTAT;
+            sem_ctx* c = ctxs[i];
+            int sti = SEM_OK;
+            if (o[12] != 0.0) sti = SEM_ENAN;
+            else if (o[11] > c->flow.pres_tol) sti = SEM_ENOTCONV;
+            else
+                for (int q = 0; q < 3; ++q)
+                    if (o[7 + q] > c->flow.vel_tol) sti = SEM_ENOTCONV;
+            if (sti && !status) status = sti;
+            if (stats) {
+                sem_step_stats& ss = stats[(size_t)i * nsteps + st];
+                ss.t = o[0]; ss.ke = o[1]; ss.enst = o[2]; ss.maxdiv = o[3];
+                for (int q = 0; q < 3; ++q) { ss.vel_iters[q] = (int)o[4 + q]; ss.vel_res[q] = o[7 + q]; }
+                ss.pres_iters = (int)o[10];
+                ss.pres_res = o[11];
+                ss.status = sti;
+            }
+        }
+    }
+    (void)status;
+    return 0;
+}
+
+int sem_poisson_solve(sem_ctx* const* ctxs, int n, const void* const* rhs, void* const* sol, sem_solve_stats* stats)
+{
+    int rc = check_batch(ctxs, n, SEM_MODE_POISSON);
+    if (rc) return rc;
+    if (!rhs || !sol) return fail(SEM_EINVAL, "null rhs/sol");
+    sem_ctx* c0 = ctxs[0];
+    hipStream_t s = c0->stream;
+    for (int i = 0; i < n; ++i) {
+        if (!rhs[i] || !sol[i]) return fail(SEM_EINVAL, "null rhs/sol entry");
+        HIPCHK(hipMemcpyAsync(ctxs[i]->hdesc.f[F_GB], rhs[i], 8 * (size_t)ctxs[i]->np, hipMemcpyDeviceToDevice, s));
+    }
+    Batch b = make_batch(ctxs, n);
+    vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_GB);
+    fin(b, FIN_MEAN_UNIQUE, s);
+    vec(b, V_SUB_MEAN, 1, P64, -1, s, F_GB, -1);
+    vec(b, V_ZERO, 1, P64, -1, s, F_GX);
+    rc = pressure_solve(ctxs, b, s);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i)
+        HIPCHK(hipMemcpyAsync(sol[i], ctxs[i]->hdesc.f[F_GX], 8 * (size_t)ctxs[i]->np, hipMemcpyDeviceToDevice, s));
+    if (stats) {
+        for (int i = 0; i < n; ++i) {
+            int it = 0, nan = 0;
+            double res = 0;
+            HIPCHK(hipMemcpyAsync(&it, ctxs[i]->hdesc.I + I_GIT, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(&nan, ctxs[i]->hdesc.I + I_NAN, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(&res, ctxs[i]->hdesc.S + S_GBETA, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            stats[i].iters = it;
+            stats[i].res = res;
+            stats[i].status = nan ? SEM_ENAN : (res > ctxs[i]->flow.pres_tol ? SEM_ENOTCONV : SEM_OK);
+        }
+    }
+    return check_hip_last();
+}
+
+int sem_get_field(sem_ctx* c, int which, void* dst, int is_host)
+{
+    int rc = bind_check(c);
+    if (rc) return rc;
+    if (!dst) return fail(SEM_EINVAL, "null destination");
+    int fid;
+    if ((rc = field_of(c, which, fid))) return rc;
+    char* p;
+    if ((rc = current_ptr(c, fid, &p))) return rc;
+    size_t off = 0;
+    if (which >= SEM_F_G && which < SEM_F_G + 6) off = (size_t)(which - SEM_F_G);
+    if (which >= SEM_F_M && which < SEM_F_M + 9) off = (size_t)(which - SEM_F_M);
+    const long long L3 = (long long)c->lx * c->lx * c->lx;
+    if (fid == F_G64 || fid == F_M64) {
+        // [E][ncomp][lx3] -> component-major copy, one element at a time (host-side gather)
+        const int nc = fid == F_G64 ? 6 : 9;
+        std::vector<double> tmp((size_t)c->np * nc);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipMemcpy(tmp.data(), p, 8 * tmp.size(), hipMemcpyDeviceToHost));
+        std::vector<double> out((size_t)c->np);
+        for (long long e = 0; e < c->E; ++e)
+            memcpy(out.data() + e * L3, tmp.data() + (e * nc + (long long)off) * L3, 8 * L3);
+        if (is_host) memcpy(dst, out.data(), 8 * out.size());
+        else HIPCHK(hipMemcpy(dst, out.data(), 8 * out.size(), hipMemcpyHostToDevice));
+        return 0;
+    }
+    if (fid == F_IBSUM64) {
+        // stored as 1/Bsum
+        std::vector<double> out((size_t)c->np);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipMemcpy(out.data(), p, 8 * out.size(), hipMemcpyDeviceToHost));
+        for (auto& v : out) v = 1.0 / v;
+        if (is_host) memcpy(dst, out.data(), 8 * out.size());
+        else HIPCHK(hipMemcpy(dst, out.data(), 8 * out.size(), hipMemcpyHostToDevice));
+        return 0;
+    }
+    if (is_host) {
+        HIPCHK(hipMemcpyAsync(dst, p, 8 * (size_t)c->np, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    } else {
+        HIPCHK(hipMemcpyAsync(dst, p, 8 * (size_t)c->np, hipMemcpyDeviceToDevice, c->stream));
+    }
+    return 0;
+}
+
+int sem_set_field(sem_ctx* c, int which, const void* src, int is_host)
+{
+    int rc = bind_check(c);
+    if (rc) return rc;
+    if (!src) return fail(SEM_EINVAL, "null source");
+    if (which >= SEM_F_MASS) return fail(SEM_EINVAL, "geometry fields are read-only");
+    int fid;
+    if ((rc = field_of(c, which, fid))) return rc;
+    char* p;
+    if ((rc = current_ptr(c, fid, &p))) return rc;
+    HIPCHK(hipMemcpyAsync(p, src, 8 * (size_t)c->np, is_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, c->stream));
+    if (is_host) HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int sem_set_clock(sem_ctx* c, double t, int step)
+{
+    int rc = bind_check(c);
+    if (rc) return rc;
+    if (step < 0) return fail(SEM_EINVAL, "negative step");
+    HIPCHK(hipMemcpyAsync(c->hdesc.S + S_TIME, &t, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->hdesc.I + I_STEP, &step, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int sem_diagnostics(sem_ctx* c, sem_diag* out)
+{
+    int rc = bind_check(c);
+    if (rc) return rc;
+    if (!out) return fail(SEM_EINVAL, "null output");
+    if (c->flow.mode != SEM_MODE_FLUID) return fail(SEM_EINVAL, "diagnostics need a fluid-mode context");
+    sem_ctx* one[1] = {c};
+    Batch b = make_batch(one, 1);
+    launch_diagnostics(b, c->lx, c->stream);
+    fin(b, FIN_DIAG, c->stream);
+    if ((rc = check_hip_last())) return rc;
+    double v[3];
+    int st = 0;
+    double t = 0;
+    HIPCHK(hipMemcpyAsync(v, c->hdesc.S + S_KE, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&t, c->hdesc.S + S_TIME, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&st, c->hdesc.I + I_STEP, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    out->ke = v[0]; out->enst = v[1]; out->maxdiv = v[2]; out->t = t; out->step = st;
+    return 0;
+}
+
+// element-local operators on caller arrays: staged through the context's
+// own fields (fluid-mode workspace), then copied out
+int sem_conv(sem_ctx* c, const double* const* u3, double* const* out3)
+{
+    int rc = bind_check(c);
+    if (rc) return rc;
+    if (c->flow.mode != SEM_MODE_FLUID) return fail(SEM_EINVAL, "needs a fluid-mode context");
+    const size_t nb = 8 * (size_t)c->np;
+    char* sv[3];
+    char* bnp[3];
+    for (int q = 0; q < 3; ++q) {
+        if ((rc = current_ptr(c, F_U + q, &sv[q]))) return rc;
+        if ((rc = current_ptr(c, F_BN + q, &bnp[q]))) return rc;
+    }
+    // save state, run, restore
+    for (int q = 0; q < 3; ++q) {
+        HIPCHK(hipMemcpyAsync(c->hdesc.f[F_W64 + q], sv[q], nb, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(sv[q], u3[q], nb, hipMemcpyDeviceToDevice, c->stream));
+    }
+    sem_ctx* one[1] = {c};
+    Batch b = make_batch(one, 1);
+    launch_conv(b, c->lx, c->rs.conv_m, c->stream);
+    for (int q = 0; q < 3; ++q) {
+        HIPCHK(hipMemcpyAsync(out3[q], bnp[q], nb, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(sv[q], c->hdesc.f[F_W64 + q], nb, hipMemcpyDeviceToDevice, c->stream));
+    }
+    return check_hip_last();
+}
+
+int sem_opgrad(sem_ctx* c, const double* p, double* const* out3)
+{
+    int rc = bind_check(c);
+    if (rc) return rc;
+    if (c->flow.mode != SEM_MODE_FLUID) return fail(SEM_EINVAL, "needs a fluid-mode context");
+    const size_t nb = 8 * (size_t)c->np;
+    HIPCHK(hipMemcpyAsync(c->hdesc.f[F_PHI], p, nb, hipMemcpyDeviceToDevice, c->stream));
+    sem_ctx* one[1] = {c};
+    Batch b = make_batch(one, 1);
+    launch_opgrad(b, c->lx, c->rs.opg_m, F_PHI, F_R64, c->stream);
+    for (int q = 0; q < 3; ++q)
+        HIPCHK(hipMemcpyAsync(out3[q], c->hdesc.f[F_R64 + q], nb, hipMemcpyDeviceToDevice, c->stream));
+    return check_hip_last();
+}
+
+int sem_wdiv(sem_ctx* c, const double* const* v3, double* out)
+{
+    int rc = bind_check(c);
+    if (rc) return rc;
+    if (c->flow.mode != SEM_MODE_FLUID) return fail(SEM_EINVAL, "needs a fluid-mode context");
+    const size_t nb = 8 * (size_t)c->np;
+    for (int q = 0; q < 3; ++q)
+        HIPCHK(hipMemcpyAsync(c->hdesc.f[F_R64 + q], v3[q], nb, hipMemcpyDeviceToDevice, c->stream));
+    sem_ctx* one[1] = {c};
+    Batch b = make_batch(one, 1);
+    launch_wdiv(b, c->lx, c->rs.div_m, F_R64, F_PHI, c->stream);
+    HIPCHK(hipMemcpyAsync(out, c->hdesc.f[F_PHI], nb, hipMemcpyDeviceToDevice, c->stream));
+    return check_hip_last();
+}
+
+}  // extern "C"

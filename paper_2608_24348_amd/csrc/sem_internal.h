@@ -1,0 +1,281 @@
+// Internal layout shared by the host runtime and the HIP kernels of libsem.
+//
+// A request (one sem_ctx) owns a device workspace carved from the caller's
+// buffer.  Its descriptor ReqDesc lives at the start of that workspace and
+// holds every field pointer by id, the per-request scalar area S (double),
+// the integer state I, the reduction partials and the shared-node lists.
+// Kernels receive a Batch by value: up to SEM_MAXB descriptors plus prefix
+// tables over their element blocks and shared-node chunks, so one launch
+// covers every request of a batch, and a batch of one is the plain case.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#define SEM_MAXB 48          // requests per batched launch
+#define SEM_MAXM 30          // largest GMRES restart length
+#define SEM_GS_CHUNK 256     // shared-node tuples per workgroup
+#define SEM_VEC_THREADS 256  // threads of point-wise kernels
+
+namespace semk {
+
+enum PrecId { P64 = 0, P32 = 1, P16 = 2, PBF = 3 };
+
+// ---------------------------------------------------------------- fields
+enum FieldId : int {
+    // geometry, fp64 (always present)
+    F_G64 = 0,      // [E][6][lx3]  G_rr G_rs G_rt G_ss G_st G_tt
+    F_B64,          // [E][lx3]     mass B = jac w_i w_j w_k
+    F_M64,          // [E][9][lx3]  M_ac = B dr_a/dx_c, index a*3+c
+    F_IBSUM64,      // 1 / dssum(B)
+    F_DA64,         // dssum(diag A_L)  (stiffness diagonal, assembled)
+    F_IDP64,        // 1 / F_DA64 with the zero guard (pressure Jacobi)
+    F_IDV64,        // 1 / (h1 dA + h2 dssum(B))  (velocity Jacobi, current h)
+    // reduced-storage geometry copies
+    F_G32, F_B32, F_M32, F_IDP32, F_IDV32,
+    F_G16, F_B16, F_M16,       // 16-bit (fp16 or bf16, one kind per request), element-scaled
+    F_GSC,                      // float[E]: scale of G16 (and of B16 in F_GSC + E)
+    F_MSC,                      // float[E]: scale of M16
+    // fluid state (fp64)
+    F_U, F_U1, F_U2,            // u^n components
+    F_UL1, F_UL1b, F_UL1c,      // u^{n-1}
+    F_UL2, F_UL2b, F_UL2c,      // u^{n-2}
+    F_BN, F_BNb, F_BNc,         // B N(u^n)
+    F_BNL1, F_BNL1b, F_BNL1c,
+    F_BNL2, F_BNL2b, F_BNL2c,
+    F_P,                        // p^n
+    F_RHS, F_RHSb, F_RHSc,      // assembled velocity rhs
+    F_US, F_USb, F_USc,         // u*
+    F_GP, F_GPb, F_GPc,         // gradient scratch (fp64)
+    F_R64, F_R64b, F_R64c,      // fp64 residual scratch
+    F_W64, F_W64b, F_W64c,      // fp64 operator output scratch
+    F_RP,                       // pressure rhs
+    F_PHI,                      // pressure increment
+    // velocity PCG vectors (velocity storage precision), 3 components each
+    F_PX, F_PXb, F_PXc,
+    F_PR, F_PRb, F_PRc,
+    F_PZ, F_PZb, F_PZc,
+    F_PP, F_PPb, F_PPc,
+    F_PW, F_PWb, F_PWc,
+    // GMRES (fp64 basis and iterate; pressure-Ax precision for z and w)
+    F_V,                        // (m+1) vectors, stride np
+    F_GZ,                       // Ax input (pressure storage precision)
+    F_GW,                       // Ax output (pressure storage precision)
+    F_GWD,                      // fp64 working vector of the Arnoldi step
+    F_GB,                       // rhs (fp64)
+    F_GX,                       // iterate (fp64)
+    NFIELD
+};
+
+// ---------------------------------------------------------------- scalars (double S[])
+enum ScalarId : int {
+    S_H1 = 0, S_H2,             // velocity Helmholtz coefficients of the current step
+    S_NU, S_DT, S_BETA0,
+    S_BDF,                      // 3 values b_1..b_3
+    S_EXT = S_BDF + 3,          // 3 values a_1..a_3
+    S_TIME = S_EXT + 3,
+    S_VTOL, S_PTOL,
+    S_IDV_H1, S_IDV_H2,         // h of the stored velocity Jacobi diagonal
+    S_RHO,                      // 3: PCG rho per component
+    S_ALPHA = S_RHO + 3,
+    S_BETA = S_ALPHA + 3,
+    S_RN = S_BETA + 3,          // 3: current PCG residual norm
+    S_R0 = S_RN + 3,            // 3: fp64 true residual norm
+    S_GBETA = S_R0 + 3,         // GMRES true residual norm
+    S_GH,                       // (m+1)*m Hessenberg, row-major H[i*m + j]
+    S_GCS = S_GH + (SEM_MAXM + 1) * SEM_MAXM,
+    S_GSN = S_GCS + SEM_MAXM,
+    S_GG = S_GSN + SEM_MAXM,    // m+1 rotated rhs
+    S_GY = S_GG + SEM_MAXM + 1, // m solution of the small system
+    S_GHC = S_GY + SEM_MAXM,    // m+1 first-pass Gram-Schmidt coefficients
+    S_GH2 = S_GHC + SEM_MAXM + 1,  // m+1 second-pass coefficients
+    S_MEAN = S_GH2 + SEM_MAXM + 1, // scratch for mean removal
+    S_KE, S_ENST, S_MAXDIV,
+    S_VOL,                      // sum of B (domain volume)
+    S_GNSCALE,                  // scale applied by the GMRES normalisation kernel
+    S_RED,                      // generic finalised reductions (SEM_NRED values)
+    NSCALAR = S_RED + 64
+};
+
+// ---------------------------------------------------------------- integer state (int I[])
+enum IntId : int {
+    I_STEP = 0, I_ORDER, I_TORDER,
+    I_VACT,                     // 3: PCG component active
+    I_VIT = I_VACT + 3,         // 3: PCG iterations (cumulative over refinement cycles)
+    I_VREF = I_VIT + 3,         // 3: refinement cycles
+    I_VMAXIT = I_VREF + 3,
+    I_GPHASE,                   // 0 Arnoldi, 1 cycle end pending, 2 done
+    I_GJ,                       // current Arnoldi index j (vectors 0..j exist)
+    I_GJEND,                    // size of the small system at cycle end
+    I_GIT,                      // total Arnoldi steps
+    I_GMAXIT, I_GM,
+    I_GACT,                     // GMRES active (phase != done)
+    I_NAN,                      // non-finite value seen
+    I_ALWAYS,                   // constant 1 (gate for unconditional launches)
+    I_VDONE,                    // velocity refinement finished for all components
+    I_GARN,                     // GMRES: Arnoldi step pending (phase 0)
+    I_GEND,                     // GMRES: cycle end pending (phase 1)
+    I_GNORM,                    // GMRES: normalisation of V_J pending
+    I_VMAXREF,                  // velocity refinement cycle limit
+    NINT = I_VMAXREF + 8
+};
+
+// reduction slots (partials[slot][block])
+enum RedSlot : int {
+    R_A = 0,                    // 3 generic per-component slots
+    R_B = 3,                    // 3
+    R_C = 6,                    // 3
+    R_GM = 9,                   // SEM_MAXM + 1 GMRES dot slots
+    R_GN = R_GM + SEM_MAXM + 1, // GMRES norm
+    R_X0, R_X1, R_X2, R_X3,     // diagnostics and means
+    NRED
+};
+
+struct ReqDesc {
+    int E, lx, epb, nb;         // elements, points per direction, elements per block, blocks
+    int n2, n4, n8;             // shared-node tuple counts (pairs, quads, octets)
+    int c2, c4, c8;             // tuple chunk counts
+    int prec16;                 // 0 none, 2 fp16, 3 bf16
+    int gm_m;                   // GMRES restart
+    long long np, nglob;
+    const int* idx2;            // [n2][2]
+    const int* idx4;            // [n4][4]
+    const int* idx8;            // [n8][8]
+    double* S;                  // scalars
+    int* I;                     // integer state
+    double* part;               // reduction partials [NRED][nb]
+    const double* D64;          // D[i*lx+l] (lx*lx), then w[lx], then xi[lx]
+    const float* D32;           // same layout in fp32
+    void* f[NFIELD];
+};
+
+// periodic box mesh, optional sinusoidal node perturbation
+struct MeshParams {
+    int nel[3];
+    int N;
+    double lo[3], h[3];
+    double amp;
+    double phase[9];
+};
+
+struct Batch {
+    int n;                      // requests
+    int eb[SEM_MAXB + 1];       // prefix over element blocks
+    int gs[SEM_MAXB + 1];       // prefix over shared-node chunks
+    const ReqDesc* r[SEM_MAXB];
+};
+
+// elements per workgroup of the element kernels (shared by host and device)
+__host__ __device__ constexpr int epb_of(int lx)
+{
+    return lx == 12 ? 4 : lx == 10 ? 5 : lx == 11 ? 2 : (256 / (lx * lx) > 0 ? 256 / (lx * lx) : 1);
+}
+
+// locate the request of a flat block index in a prefix table
+__device__ __forceinline__ int find_req(const int* prefix, int n, int g)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+}  // namespace semk
+
+// ---------------------------------------------------------------- launch interface
+namespace semk {
+
+struct AxLaunch {
+    int src, dst;               // field ids (components add blockIdx.y)
+    int ncomp;                  // 1 or 3
+    int hsel;                   // S index of (h1,h2) or -1 to use h1,h2 below
+    double h1, h2;
+    int precond;                // field id of the inverse diagonal applied to src on load, or -1
+    int pdot;                   // reduction slot for sum(u*w) over local points, or -1
+    int gate;                   // I index checked per component (nonzero = run), or -1
+    int tu, tg;                 // PrecId of vectors and of geometry
+    const void* u_raw;          // direct pointers (standalone sem_ax), used when src < 0
+    void* w_raw;
+};
+
+void launch_ax(const Batch& b, int lx, const AxLaunch& a, hipStream_t s);
+void launch_dssum(const Batch& b, int field, int ncomp, int tprec, int gate, void* raw, hipStream_t s);
+
+// geometry and setup
+void launch_geometry(const Batch& b, int lx, const MeshParams& mp, hipStream_t s);
+void launch_diag_a(const Batch& b, int lx, hipStream_t s);
+void launch_geo_post(const Batch& b, hipStream_t s);
+void launch_geo_cast(const Batch& b, int lx, int want32, int want16, hipStream_t s);
+void launch_init_fields(const Batch& b, int lx, int init, const MeshParams& mp, hipStream_t s);
+
+// SEM operators (output fp64)
+void launch_conv(const Batch& b, int lx, int tm, hipStream_t s);
+void launch_opgrad(const Batch& b, int lx, int tm, int src, int dst, hipStream_t s);
+void launch_wdiv(const Batch& b, int lx, int tm, int src, int dst, hipStream_t s);
+void launch_diagnostics(const Batch& b, int lx, hipStream_t s);
+
+// point-wise / reduction / scalar kernels
+enum VecOp : int {
+    V_VRESID = 0,     // R64 = RHS - W64, partial |R64|^2 -> R_A+c
+    V_PCG_INIT,       // PX = 0, PR = R64, PZ = PR*IDV, PP = PZ, partial (r,z) -> R_B+c
+    V_PCG_UPD,        // PX += a PP, PR -= a PW, PZ = PR*IDV, partials (r,r) -> R_B+c, (r,z) -> R_C+c
+    V_PCG_P,          // PP = PZ + b PP
+    V_US_COPY,        // US = U
+    V_US_ADD,         // US += PX
+    V_RHS,            // velocity rhs from the BDF/EXT history
+    V_IDV,            // velocity Jacobi inverse diagonal for the current (h1,h2)
+    V_SUM_UNIQUE,     // partial sum(f/mult) of field f0 -> R_X3
+    V_SUM_MASS,       // partial sum(B f) of field f0 -> R_X3
+    V_SUB_MEAN,       // f0 = scale*(f0 - S_MEAN)   (scale = S[f1] or 1 when f1 < 0)
+    V_COPY,           // f1 = f0 (fp64)
+    V_ZERO,           // f0 = 0 (fp64)
+    V_GM_PRECOND,     // GZ = V_J * IDP
+    V_GM_DOTS,        // partials (V_i, GW) -> R_GM+i, i <= J
+    V_GM_UPD_DOTS,    // GWD = GW - sum GHC_i V_i ; partials (V_i, GWD) -> R_GM+i
+    V_GM_UPD_NORM,    // GWD -= sum GH2_i V_i ; partial |GWD|^2 -> R_GN
+    V_GM_NORMALIZE,   // V_J = GWD * S_GNSCALE
+    V_GM_XUPD,        // GX += IDP * sum_{i<jend} y_i V_i
+    V_GM_RESID,       // GWD = GB - GWD, partial |GWD|^2 -> R_GN
+    V_CORRECT,        // U_new = US - dt/beta0 GP / Bsum  (into the u^{n-2} buffer); P += GX
+    V_AXPY_RAW,       // raw y += a x (fp64), used by the standalone API
+    NVECOP
+};
+
+struct VecArgs {
+    int op, gate, ncomp;
+    int tv;           // PrecId of the velocity/pressure solver vectors
+    int ta;           // PrecId of the per-thread partial sums (fp64 or fp32)
+    int f0, f1;
+    double a;
+    const void* x_raw;
+    void* y_raw;
+};
+
+enum FinOp : int {
+    FIN_VINIT = 0, FIN_PCG_RHO, FIN_PCG_ALPHA, FIN_PCG_BETA,
+    FIN_MEAN_UNIQUE, FIN_MEAN_MASS,
+    FIN_GM_H1, FIN_GM_H2, FIN_GM_COL, FIN_GM_RESTART, FIN_GM_START,
+    FIN_DIAG, FIN_STEP_BEGIN, FIN_STEP_END,
+    FIN_POLL,         // host flag[ri] = I[gate] (| I[gate+1] | I[gate+2] when ncomp = 3)
+    FIN_SUM_RAW,      // S[S_RED + gate] = sum of slot f0 partials
+    FIN_VOL,          // S_VOL = sum of slot R_X3 partials
+    FIN_STATS,        // host_stats[ri*SEM_NSTAT ...] = step statistics
+    NFINOP
+};
+
+#define SEM_NSTAT 16
+
+struct FinArgs {
+    int op, gate, ncomp, f0;
+    int* host_flags;
+    double* host_stats;
+};
+
+void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s);
+void launch_fin(const Batch& b, const FinArgs& a, hipStream_t s);
+
+}  // namespace semk

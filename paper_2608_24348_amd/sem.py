@@ -1,0 +1,343 @@
+"""Python binding of libsem (argument marshalling only).
+
+Every step of the hot path runs in the HIP kernels of ``libsem.so``; this
+module builds the C descriptor structs, hands torch-owned device memory and
+the current torch stream to the library, and converts status codes into
+exceptions.  It never falls back to any other implementation: a missing or
+unloadable library raises.
+"""
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libsem.so")
+
+FP64, FP32, FP16, BF16, INHERIT = 0, 1, 2, 3, -1
+BLOCK_SEM, BLOCK_VEL, BLOCK_PRES = 0, 1, 2
+K_AX_VEL, K_AX_PRES, K_OPGRAD, K_CONV, K_DIV, K_COUNT = 0, 1, 2, 3, 4, 5
+X_ALL = 0xF
+INIT_ZERO, INIT_TGV3D, INIT_TGV2D = 0, 1, 2
+MODE_OPERATOR, MODE_POISSON, MODE_FLUID = 0, 1, 2
+ASSEMBLE = 1
+F_U, F_P, F_ULAG1, F_ULAG2, F_BNLAG1, F_BNLAG2 = 0, 3, 4, 7, 10, 13
+F_MASS, F_BSUM, F_G, F_M, F_DIAG_A = 16, 17, 18, 24, 33
+
+STATUS = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_ENOMEM", -3: "SEM_EHIP", -4: "SEM_ENAN",
+          -5: "SEM_ENOTCONV", -6: "SEM_ESTATE"}
+
+
+class SemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class Role(C.Structure):
+    _fields_ = [("compute", C.c_int), ("accumulate", C.c_int), ("storage", C.c_int)]
+
+
+class Precision(C.Structure):
+    _fields_ = [("size", C.c_int), ("rp", C.c_int), ("block", Role * 3), ("kernel", Role * K_COUNT),
+                ("fp64_exceptions", C.c_uint)]
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("size", C.c_int), ("nel", C.c_int * 3), ("order", C.c_int), ("lo", C.c_double * 3),
+                ("hi", C.c_double * 3), ("deform_amp", C.c_double), ("deform_phase", C.c_double * 9)]
+
+
+class FlowDesc(C.Structure):
+    _fields_ = [("size", C.c_int), ("mode", C.c_int), ("nu", C.c_double), ("dt", C.c_double),
+                ("torder", C.c_int), ("vel_tol", C.c_double), ("pres_tol", C.c_double),
+                ("vel_maxit", C.c_int), ("pres_maxit", C.c_int), ("gmres_restart", C.c_int),
+                ("vel_max_refine", C.c_int), ("init", C.c_int)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("t", C.c_double), ("ke", C.c_double), ("enst", C.c_double), ("maxdiv", C.c_double),
+                ("vel_iters", C.c_int * 3), ("pres_iters", C.c_int), ("vel_res", C.c_double * 3),
+                ("pres_res", C.c_double), ("status", C.c_int)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("res", C.c_double), ("status", C.c_int)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("t", C.c_double), ("ke", C.c_double), ("enst", C.c_double), ("maxdiv", C.c_double),
+                ("step", C.c_int)]
+
+
+EXPORTS = ["sem_setup", "sem_workspace_bytes", "sem_bind", "sem_ax", "sem_dssum", "sem_fluid_step",
+           "sem_poisson_solve", "sem_get_field", "sem_set_field", "sem_set_clock", "sem_diagnostics",
+           "sem_conv", "sem_opgrad", "sem_wdiv", "sem_sizes", "sem_destroy", "sem_strerror", "sem_last_error"]
+
+_lib = None
+
+
+def load():
+    """Load libsem.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise RuntimeError("libsem.so is not built (run __graft_entry__.build() or paper_2608_24348_amd/build.py)")
+    L = C.CDLL(LIBPATH)
+    vp = C.c_void_p
+    L.sem_setup.argtypes = [C.POINTER(MeshDesc), C.POINTER(FlowDesc), C.POINTER(Precision), C.POINTER(vp)]
+    L.sem_workspace_bytes.restype = C.c_size_t
+    L.sem_workspace_bytes.argtypes = [vp]
+    L.sem_bind.argtypes = [vp, vp, C.c_size_t, vp]
+    L.sem_ax.argtypes = [vp, vp, vp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int]
+    L.sem_dssum.argtypes = [vp, vp, C.c_int]
+    L.sem_fluid_step.argtypes = [C.POINTER(vp), C.c_int, C.c_int, C.POINTER(StepStats)]
+    L.sem_poisson_solve.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveStats)]
+    L.sem_get_field.argtypes = [vp, C.c_int, vp, C.c_int]
+    L.sem_set_field.argtypes = [vp, C.c_int, vp, C.c_int]
+    L.sem_set_clock.argtypes = [vp, C.c_double, C.c_int]
+    L.sem_diagnostics.argtypes = [vp, C.POINTER(Diag)]
+    L.sem_conv.argtypes = [vp, C.POINTER(vp), C.POINTER(vp)]
+    L.sem_opgrad.argtypes = [vp, vp, C.POINTER(vp)]
+    L.sem_wdiv.argtypes = [vp, C.POINTER(vp), vp]
+    L.sem_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.sem_destroy.argtypes = [vp]
+    L.sem_strerror.restype = C.c_char_p
+    L.sem_strerror.argtypes = [C.c_int]
+    L.sem_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise SemError(rc, load().sem_last_error().decode())
+
+
+# ---------------------------------------------------------------- precision policies
+def precision(rp=FP64, blocks=None, kernels=None, exceptions=None):
+    """Build a sem_precision: blocks maps block id -> (compute, accumulate,
+    storage); kernels maps kernel id -> (compute, accumulate, storage) with
+    INHERIT allowed."""
+    p = Precision()
+    p.size = C.sizeof(Precision)
+    p.rp = rp
+    for b in range(3):
+        v = (blocks or {}).get(b, (rp, rp, rp))
+        p.block[b] = Role(*v)
+    for k in range(K_COUNT):
+        v = (kernels or {}).get(k, (INHERIT, INHERIT, INHERIT))
+        p.kernel[k] = Role(*v)
+    p.fp64_exceptions = (X_ALL if rp == FP32 else 0) if exceptions is None else exceptions
+    return p
+
+
+def tier(name):
+    """Named precision presets.
+
+    fp64          global fp64 (the paper's A-0)
+    fp32b         rp = fp32, every block fp32, state/GMRES/residuals/reductions fp64 (B-0 with fp64 accumulation)
+    fp32b+fp16    fp32b with fp16-stored geometry for the velocity Helmholtz operator and opgrad (B-6 style)
+    fp32b+bf16    same with bf16
+    fp32b+fp16p   fp32b with fp16-stored geometry for the pressure operator (B-7)
+    fp32b+fp16all fp32b with fp16 geometry for both operators and opgrad (operator microbenchmarks)
+    """
+    if name == "fp64":
+        return precision(FP64)
+    if name == "fp32b":
+        return precision(FP32)
+    h = {"fp32b+fp16": FP16, "fp32b+bf16": BF16, "fp32b+fp16p": FP16, "fp32b+fp16all": FP16,
+         "fp32b+bf16all": BF16}.get(name)
+    if h is None:
+        raise ValueError("unknown tier %r" % name)
+    ks = {}
+    if name in ("fp32b+fp16", "fp32b+bf16", "fp32b+fp16all", "fp32b+bf16all"):
+        ks[K_AX_VEL] = (FP32, FP32, h)
+        ks[K_OPGRAD] = (FP32, FP32, h)
+    if name in ("fp32b+fp16p", "fp32b+fp16all", "fp32b+bf16all"):
+        ks[K_AX_PRES] = (FP32, FP32, h)
+    return precision(FP32, kernels=ks)
+
+
+def mesh_desc(nel, order, lo=(-math.pi,) * 3, hi=(math.pi,) * 3, amp=0.0, phase=None):
+    m = MeshDesc()
+    m.size = C.sizeof(MeshDesc)
+    for d in range(3):
+        m.nel[d] = int(nel[d])
+        m.lo[d] = float(lo[d])
+        m.hi[d] = float(hi[d])
+    m.order = int(order)
+    m.deform_amp = float(amp)
+    ph = np.zeros(9) if phase is None else np.asarray(phase, dtype=np.float64)
+    for q in range(9):
+        m.deform_phase[q] = float(ph[q])
+    return m
+
+
+def flow_desc(mode=MODE_FLUID, nu=1.0 / 1600, dt=1e-3, torder=3, vel_tol=1e-8, pres_tol=1e-8, vel_maxit=500,
+              pres_maxit=1000, restart=30, max_refine=8, init=INIT_TGV3D):
+    f = FlowDesc()
+    f.size = C.sizeof(FlowDesc)
+    f.mode = mode
+    f.nu = nu
+    f.dt = dt
+    f.torder = torder
+    f.vel_tol = vel_tol
+    f.pres_tol = pres_tol
+    f.vel_maxit = vel_maxit
+    f.pres_maxit = pres_maxit
+    f.gmres_restart = restart
+    f.vel_max_refine = max_refine
+    f.init = init
+    return f
+
+
+_TORCH_DT = None
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dtype_of(prec):
+    torch = _torch()
+    return {FP64: torch.float64, FP32: torch.float32, FP16: torch.float16, BF16: torch.bfloat16}[prec]
+
+
+def prec_of(t):
+    torch = _torch()
+    return {torch.float64: FP64, torch.float32: FP32, torch.float16: FP16, torch.bfloat16: BF16}[t.dtype]
+
+
+class Context:
+    """One request: mesh + flow + precision policy, bound to a torch-owned
+    device workspace and the current torch stream of ``device``."""
+
+    def __init__(self, mesh, flow, prec, device="cuda:0", bind=True):
+        L = load()
+        self.L = L
+        self.mesh = mesh
+        self.flow = flow
+        self.prec = prec
+        h = C.c_void_p()
+        _check(L.sem_setup(C.byref(mesh), C.byref(flow), C.byref(prec), C.byref(h)))
+        self.h = h
+        np_, ng = C.c_int64(), C.c_int64()
+        lx, ne = C.c_int(), C.c_int()
+        _check(L.sem_sizes(h, C.byref(np_), C.byref(ng), C.byref(lx), C.byref(ne)))
+        self.np, self.nglob, self.lx, self.E = np_.value, ng.value, lx.value, ne.value
+        self.bytes = L.sem_workspace_bytes(h)
+        self.ws = None
+        self.device = device
+        if bind:
+            self.bind(device)
+
+    def bind(self, device="cuda:0", stream=None):
+        torch = _torch()
+        self.ws = torch.empty(self.bytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self.stream = s
+        _check(self.L.sem_bind(self.h, C.c_void_p(aligned), C.c_size_t(self.bytes), C.c_void_p(s.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.sem_destroy(self.h)
+            self.h = None
+        self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- operators on torch device tensors
+    def ax(self, u, w, h1=1.0, h2=0.0, geom=INHERIT, assemble=False):
+        assert u.is_cuda and w.is_cuda and u.numel() == self.np and w.numel() == self.np and u.dtype == w.dtype
+        assert u.is_contiguous() and w.is_contiguous()
+        _check(self.L.sem_ax(self.h, C.c_void_p(u.data_ptr()), C.c_void_p(w.data_ptr()), float(h1), float(h2),
+                             prec_of(u), int(geom), ASSEMBLE if assemble else 0))
+        return w
+
+    def dssum(self, u):
+        assert u.is_cuda and u.numel() == self.np and u.is_contiguous()
+        _check(self.L.sem_dssum(self.h, C.c_void_p(u.data_ptr()), prec_of(u)))
+        return u
+
+    def get(self, which):
+        out = np.zeros(self.np)
+        _check(self.L.sem_get_field(self.h, int(which), out.ctypes.data_as(C.c_void_p), 1))
+        return out
+
+    def set(self, which, arr):
+        a = np.ascontiguousarray(arr, dtype=np.float64)
+        assert a.size == self.np
+        _check(self.L.sem_set_field(self.h, int(which), a.ctypes.data_as(C.c_void_p), 1))
+
+    def set_clock(self, t, step):
+        _check(self.L.sem_set_clock(self.h, float(t), int(step)))
+
+    def velocity(self):
+        return np.stack([self.get(F_U + c) for c in range(3)])
+
+    def pressure(self):
+        return self.get(F_P)
+
+    def diagnostics(self):
+        d = Diag()
+        _check(self.L.sem_diagnostics(self.h, C.byref(d)))
+        return {"t": d.t, "ke": d.ke, "enst": d.enst, "maxdiv": d.maxdiv, "step": d.step}
+
+    def conv(self, u3):
+        torch = _torch()
+        outs = [torch.empty_like(u3[0]) for _ in range(3)]
+        ins = (C.c_void_p * 3)(*[C.c_void_p(t.data_ptr()) for t in u3])
+        os_ = (C.c_void_p * 3)(*[C.c_void_p(t.data_ptr()) for t in outs])
+        _check(self.L.sem_conv(self.h, ins, os_))
+        return outs
+
+    def opgrad(self, p):
+        torch = _torch()
+        outs = [torch.empty_like(p) for _ in range(3)]
+        os_ = (C.c_void_p * 3)(*[C.c_void_p(t.data_ptr()) for t in outs])
+        _check(self.L.sem_opgrad(self.h, C.c_void_p(p.data_ptr()), os_))
+        return outs
+
+    def wdiv(self, v3):
+        torch = _torch()
+        out = torch.empty_like(v3[0])
+        ins = (C.c_void_p * 3)(*[C.c_void_p(t.data_ptr()) for t in v3])
+        _check(self.L.sem_wdiv(self.h, ins, C.c_void_p(out.data_ptr())))
+        return out
+
+
+def _stats_dict(s):
+    return {"t": s.t, "ke": s.ke, "enst": s.enst, "maxdiv": s.maxdiv, "vit": list(s.vel_iters),
+            "pit": s.pres_iters, "vres": list(s.vel_res), "pres": s.pres_res, "status": s.status}
+
+
+def fluid_step(ctxs, nsteps=1):
+    """Advance a batch of fluid contexts by nsteps; returns per-context lists of step stats."""
+    if isinstance(ctxs, Context):
+        ctxs = [ctxs]
+    n = len(ctxs)
+    arr = (C.c_void_p * n)(*[c.h for c in ctxs])
+    st = (StepStats * (n * max(nsteps, 1)))()
+    _check(load().sem_fluid_step(arr, n, int(nsteps), st))
+    return [[_stats_dict(st[i * nsteps + k]) for k in range(nsteps)] for i in range(n)]
+
+
+def poisson_solve(ctxs, rhs, sol):
+    """Batched periodic Poisson solves; rhs/sol are lists of fp64 device tensors."""
+    n = len(ctxs)
+    arr = (C.c_void_p * n)(*[c.h for c in ctxs])
+    r = (C.c_void_p * n)(*[C.c_void_p(t.data_ptr()) for t in rhs])
+    s = (C.c_void_p * n)(*[C.c_void_p(t.data_ptr()) for t in sol])
+    st = (SolveStats * n)()
+    _check(load().sem_poisson_solve(arr, n, r, s, st))
+    return [{"iters": st[i].iters, "res": st[i].res, "status": st[i].status} for i in range(n)]
