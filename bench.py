@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the SEM Taylor-Green fluid step on one MI355X.
+
+Workload (default): Taylor-Green vortex, Re = 1600, periodic box [-pi, pi]^3,
+32^3 hexahedra of order N = 7 (16.8 M local points), dt = 5e-4, BDF3/EXT3,
+Jacobi-PCG velocity and GMRES(30) pressure to an absolute 1e-8.  One "step"
+is one full fluid time step (convection, RHS, three velocity solves,
+pressure solve, correction, diagnostics).  The reported value is steps/s of
+the fp32-bounded tier; the plain fp64 tier runs the same steps on the same
+GPU for the speedup and for the kinetic-energy / enstrophy error series.
+
+Also reported: Ax GDOF/s of the Helmholtz operator on the same mesh, a
+roofline record for the dominant kernel (HIP-event kernel times measured in
+the timed region, algorithmic bytes per launch), and the FP64 CPU oracle
+timed on the host cores on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "TGV steps/s & Ax GDOF/s, mixed vs fp64 at stated enstrophy error; p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gmres_j_sequence(iters, m):
+    """Arnoldi indices J of every step of a GMRES(m) solve with `iters` steps."""
+    out = []
+    for it in range(iters):
+        out.append(it % m)
+    return out
+
+
+def run_tier(sem, torch, tier, nel, N, nu, dt, warmup, steps, prof_class=None, vtol=1e-6, ptol=1e-4):
+    ctx = sem.Context(sem.mesh_desc(nel, N), sem.flow_desc(nu=nu, dt=dt, restart=30, vel_tol=vtol, pres_tol=ptol),
+                      sem.tier(tier))
+    torch.cuda.synchronize()
+    series = []
+    d0 = ctx.diagnostics()
+    series.append((0.0, d0["ke"], d0["enst"], d0["maxdiv"]))
+    if warmup:
+        for s in sem.fluid_step([ctx], warmup)[0]:
+            series.append((s["t"], s["ke"], s["enst"], s["maxdiv"]))
+            log("  %s warmup step t=%.4f its v=%s p=%d" % (tier, s["t"], s["vit"], s["pit"]))
+    torch.cuda.synchronize()
+    if prof_class:
+        sem.prof_start(prof_class)
+    t0 = time.perf_counter()
+    st = sem.fluid_step([ctx], steps)[0]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sem.prof_stop() if prof_class else None
+    for s in st:
+        series.append((s["t"], s["ke"], s["enst"], s["maxdiv"]))
+        log("  %s step t=%.4f its v=%s p=%d ke=%.12f" % (tier, s["t"], s["vit"], s["pit"], s["ke"]))
+        if s["status"] != 0:
+            raise RuntimeError("%s step failed with status %d" % (tier, s["status"]))
+    return ctx, (t1 - t0), st, series, prof
+
+
+def ax_rate(sem, torch, ctx, dtype, reps=20):
+    """Helmholtz operator GDOF/s on the context's mesh (HIP events, current stream)."""
+    u = torch.randn(ctx.np, dtype=torch.float64, device="cuda:0").to(dtype)
+    w = torch.empty_like(u)
+    for _ in range(3):
+        ctx.ax(u, w, 1.0, 0.0)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.ax(u, w, 1.0, 0.0)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return ctx.np / (ms * 1e-3) / 1e9, ms
+
+
+def cpu_baseline(nel, N, nu, dt, pres_iters_per_step, restart=30):
+    """FP64 oracle on the host cores, on a bounded sample of the same workload.
+
+    Sample: (a) the oracle's first fluid step from the initial condition (all
+    operators, three velocity solves, and a 2-iteration pressure solve), and
+    (b) one full GMRES(restart) cycle of the oracle's pressure solver on the
+    same mesh.  A steady step is (a) plus (p - 2)/restart cycles of (b), with
+    p the mean pressure iteration count of the timed GPU steps (the oracle's
+    counts equal the GPU's by the parity tests); steps/s = 1 / that time.
+    """
+    import numpy as np
+    from oracle import OracleMesh, OracleFluid, num_threads
+    m = OracleMesh(nel, N)
+    f = OracleFluid(m, nu, dt)
+    t0 = time.perf_counter()
+    o = f.step()
+    t_step = time.perf_counter() - t0
+    rhs = m.remove_mean_unique(m.dssum(m.mass() * np.random.default_rng(0).standard_normal(m.np)))
+    t0 = time.perf_counter()
+    _, its, _ = m.gmres(rhs, 1.0, 0.0, tol=1e-30, maxit=restart, restart=restart)
+    t_cycle = time.perf_counter() - t0
+    t_est = t_step + max(pres_iters_per_step - o["pit"], 0.0) / its * t_cycle
+    return {"value": 1.0 / t_est, "unit": "steps/s", "cores": num_threads(), "kind": "oracle",
+            "sample": "oracle first step of the same workload (%.2f s, %d pressure its) + one %d-iteration GMRES "
+                      "cycle on the same mesh (%.2f s); steady step = first step + (%.1f - %d)/%d cycles"
+                      % (t_step, o["pit"], its, t_cycle, pres_iters_per_step, o["pit"], its)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--tier", default="fp32b")
+    ap.add_argument("--nel", type=int, default=32)
+    ap.add_argument("--order", type=int, default=7)
+    ap.add_argument("--dt", type=float, default=5e-4)
+    ap.add_argument("--re", type=float, default=1600.0)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ax", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the element-sharded "
+              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2608_24348_amd import sem
+    from oracle.metrics import e_max, e_peak
+    sem.load()
+    nel = (args.nel,) * 3
+    N = args.order
+    nu = 1.0 / args.re
+    dt = args.dt
+    npts = args.nel ** 3 * (N + 1) ** 3
+
+    log("bench: %s  %d^3 elements N=%d (%d pts)  dt=%g  Re=%g" % (args.tier, args.nel, N, npts, dt, args.re))
+    prof_class = sem.PROF_GM_UPD_DOTS
+    ctx, t_mx, st_mx, ser_mx, prof = run_tier(sem, torch, args.tier, nel, N, nu, dt, args.warmup, args.steps, prof_class)
+    steps_s = args.steps / t_mx
+    out = {"metric": METRIC, "value": steps_s, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * t_mx / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if args.tier != "fp64" else "f64",
+           "data": "synthetic",
+           "config": {"workload": "TGV Re=%g, %d^3 elements, N=%d (%d local pts), dt=%g, tier %s (fp64 state, "
+                                  "GMRES orthogonalisation and residual checks)" % (args.re, args.nel, N, npts, dt, args.tier),
+                      "global_batch": 1, "seq_len": npts, "parallelism": "single-gpu"}}
+    out["iters"] = {"vel": [s["vit"] for s in st_mx], "pres": [s["pit"] for s in st_mx]}
+
+    # roofline of the dominant kernel: the GMRES update+dots pass (reads V_0..V_J and w, writes w')
+    tot_ms, nlaunch = prof
+    tp_bytes = 4 if args.tier != "fp64" else 8
+    alg_bytes = 0.0
+    active = 0
+    for s in st_mx:
+        for J in gmres_j_sequence(s["pit"], 30):
+            alg_bytes += npts * ((J + 1) * 8 + tp_bytes + 8)
+            active += 1
+    per_launch = alg_bytes / max(active, 1)
+    avg_ms = tot_ms / max(nlaunch, 1)
+    # time of all launches (gated no-op launches included) against the bytes of the active ones
+    achieved = alg_bytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+    out["roofline"] = {"kernel": "gm_pass_kernel<float,1> (GMRES CGS2 update + dots)", "bound": "hbm",
+                       "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": None, "launches": nlaunch, "active_launches": active,
+                       "avg_launch_ms": avg_ms, "alg_bytes_per_active_launch": per_launch}
+
+    if not args.no_ax:
+        g32, ms32 = ax_rate(sem, torch, ctx, torch.float32)
+        out["ax_gdofs"] = {"fp32": g32, "fp32_ms": ms32}
+    if not args.no_fp64:
+        ctx64, t64, st64, ser64, _ = run_tier(sem, torch, "fp64", nel, N, nu, dt, args.warmup, args.steps)
+        out["fp64_steps_per_s"] = args.steps / t64
+        out["speedup_vs_fp64"] = steps_s / (args.steps / t64)
+        ke_mx = [r[1] for r in ser_mx]
+        ke64 = [r[1] for r in ser64]
+        en_mx = [r[2] for r in ser_mx]
+        en64 = [r[2] for r in ser64]
+        out["error_vs_fp64_gpu"] = {"e_E_max_pct": e_max(ke_mx, ke64), "e_Omega_max_pct": e_max(en_mx, en64),
+                                    "e_Omega_peak_pct": e_peak(en_mx, en64),
+                                    "max_div_mx": max(r[3] for r in ser_mx), "max_div_fp64": max(r[3] for r in ser64),
+                                    "steps_compared": len(ke64)}
+        out["iters_fp64"] = {"vel": [s["vit"] for s in st64], "pres": [s["pit"] for s in st64]}
+        if not args.no_ax:
+            g64, ms64 = ax_rate(sem, torch, ctx64, torch.float64)
+            out["ax_gdofs"]["fp64"] = g64
+            out["ax_gdofs"]["fp64_ms"] = ms64
+        del ctx64
+    del ctx
+    torch.cuda.synchronize()
+    if not args.no_cpu:
+        log("cpu baseline: oracle sample of the same workload")
+        pbar = sum(s["pit"] for s in st_mx) / len(st_mx)
+        out["cpu_baseline"] = cpu_baseline(nel, N, nu, dt, pbar)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

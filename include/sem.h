@@ -64,7 +64,9 @@ enum {
     SEM_K_AX_PRES = 1,   /* pressure Poisson operator (block PRES) */
     SEM_K_OPGRAD = 2,    /* mass-weighted gradient (block SEM) */
     SEM_K_CONV = 3,      /* convective term (block SEM) */
-    SEM_K_DIV = 4,       /* weak divergence (block SEM) */
+    SEM_K_DIV = 4,       /* weak divergence (block SEM; sem_wdiv).  Inside sem_fluid_step the
+                            weak divergence of u* is the pressure solve's initial residual and
+                            is always formed in fp64 (SEM_X_RESID). */
     SEM_K_COUNT = 5
 };
 
@@ -159,8 +161,11 @@ int sem_bind(sem_ctx* ctx, void* dev_buf, size_t bytes, void* hip_stream);
  * element (the paper's ax_helm), u and w device arrays of E*lx^3 values in
  * buf_prec (FP64, FP32, FP16 or BF16 storage), geometry in geom_prec (must
  * be one the context holds; SEM_INHERIT = the AX_PRES policy when h2 == 0,
- * else AX_VEL).  flags & SEM_ASSEMBLE additionally applies dssum to w. */
+ * else AX_VEL).  Arithmetic is fp64 for fp64 vectors (fp32 with
+ * SEM_AX_FP32_COMPUTE) and fp32 otherwise.  flags & SEM_ASSEMBLE
+ * additionally applies dssum to w. */
 #define SEM_ASSEMBLE 1
+#define SEM_AX_FP32_COMPUTE 2  /* fp64 vectors, fp32 arithmetic (needs fp32 or 16-bit geometry) */
 int sem_ax(sem_ctx* ctx, const void* u, void* w, double h1, double h2, int buf_prec, int geom_prec, int flags);
 
 /* Direct stiffness summation in place: every local copy of a shared node
@@ -212,6 +217,24 @@ int sem_diagnostics(sem_ctx* ctx, sem_diag* out);
 int sem_conv(sem_ctx* ctx, const double* const* u3, double* const* out3);
 int sem_opgrad(sem_ctx* ctx, const double* p, double* const* out3);
 int sem_wdiv(sem_ctx* ctx, const double* const* v3, double* out);
+
+/* Optional HIP-event timing of one kernel class on the stream it is launched
+ * on (for roofline measurements).  sem_prof_start arms recording of every
+ * launch of that class made by any context on this process; sem_prof_stop
+ * synchronises the recorded events and returns the summed kernel time and
+ * the number of launches (inactive, gated launches included).  Not
+ * thread-safe; recording adds one event pair per launch. */
+enum {
+    SEM_PROF_AX_VEL = 1,      /* velocity Helmholtz operator inside PCG */
+    SEM_PROF_AX_PRES = 2,     /* pressure operator inside the Arnoldi step */
+    SEM_PROF_GM_DOTS = 3,     /* GMRES first Gram-Schmidt pass */
+    SEM_PROF_GM_UPD_DOTS = 4, /* GMRES update + second-pass dots */
+    SEM_PROF_GM_UPD_NORM = 5, /* GMRES second update + norm */
+    SEM_PROF_DSSUM_PRES = 6,  /* dssum of the Arnoldi operator output */
+    SEM_PROF_AX_ANY = 7       /* every standalone sem_ax call */
+};
+int sem_prof_start(int kclass);
+int sem_prof_stop(double* total_ms, int64_t* launches);
 
 /* Sizes of a bound or unbound context. */
 int sem_sizes(const sem_ctx* ctx, int64_t* np, int64_t* nglob, int* lx, int* nelem);

@@ -75,6 +75,9 @@ def _load():
     L.orc_gmres.restype = C.c_int
     L.orc_gmres.argtypes = [vp, C.c_double, C.c_double, _dp, _dp, C.c_double, C.c_int, C.c_int,
                             C.POINTER(C.c_double), vp]
+    L.orc_gmres_ex.restype = C.c_int
+    L.orc_gmres_ex.argtypes = [vp, C.c_double, C.c_double, _dp, _dp, C.c_double, C.c_int, C.c_int, C.c_int,
+                               C.POINTER(C.c_double), vp]
     L.orc_remove_mean_unique.argtypes = [vp, _dp]
     L.orc_remove_mean_mass.argtypes = [vp, _dp]
     L.orc_poisson.restype = C.c_int
@@ -252,12 +255,12 @@ class OracleMesh:
             return x, it, res.value, hist[:it + 1].copy()
         return x, it, res.value
 
-    def gmres(self, b, h1=1.0, h2=0.0, x0=None, tol=1e-8, maxit=1000, restart=30, history=False):
+    def gmres(self, b, h1=1.0, h2=0.0, x0=None, tol=1e-8, maxit=1000, restart=30, history=False, deflate=False):
         x = np.zeros(self.np) if x0 is None else _c(x0).copy()
         res = C.c_double()
         hist = np.zeros(2 * maxit + 4) if history else None
-        it = self.L.orc_gmres(self.h, float(h1), float(h2), _c(b), x, float(tol), int(maxit), int(restart),
-                              C.byref(res), hist.ctypes.data if history else None)
+        it = self.L.orc_gmres_ex(self.h, float(h1), float(h2), _c(b), x, float(tol), int(maxit), int(restart),
+                                 int(bool(deflate)), C.byref(res), hist.ctypes.data if history else None)
         if history:
             return x, it, res.value, hist
         return x, it, res.value

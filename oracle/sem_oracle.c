@@ -137,6 +137,7 @@ typedef struct {
 static double* dalloc(long n) { return (double*)calloc((size_t)n, sizeof(double)); }
 
 void orc_dssum(const orc_mesh* m, double* u);
+void orc_remove_mean_unique(const orc_mesh* m, double* r);
 
 /* Perturbed coordinate of the reference position (X,Y,Z) measured from lo:
  * each coordinate c gets amp*h_c*sin(pi X/hx + ph[3c]) sin(pi Y/hy + ph[3c+1])
@@ -678,9 +679,13 @@ int orc_pcg(const orc_mesh* m, double h1, double h2, const double* b, double* x,
  * Gram-Schmidt applied twice, Givens rotations on the Hessenberg matrix,
  * absolute stop on the rotated residual |g_{j+1}| <= tol, and the true
  * residual recomputed at every restart.  x holds the initial guess.
+ * With deflate != 0 (the singular periodic Poisson operator, whose range is
+ * orthogonal to constants) each operator output has its unique-node mean
+ * removed before orthogonalisation: a no-op in exact arithmetic that keeps
+ * rounding errors from feeding the constant null direction into the basis.
  * Returns the number of Arnoldi steps; *res = final true residual norm. */
-int orc_gmres(const orc_mesh* m, double h1, double h2, const double* b, double* x,
-              double tol, int maxit, int mrst, double* res, double* hist)
+int orc_gmres_ex(const orc_mesh* m, double h1, double h2, const double* b, double* x,
+                 double tol, int maxit, int mrst, int deflate, double* res, double* hist)
 {
     long np = m->np;
     int mm = mrst;
@@ -708,6 +713,7 @@ int orc_gmres(const orc_mesh* m, double h1, double h2, const double* b, double* 
             double* vj = V + (long)j * np;
             for (long i = 0; i < np; ++i) z[i] = vj[i] / d[i];
             apply_assembled(m, z, w, h1, h2);
+            if (deflate) orc_remove_mean_unique(m, w);
             /* classical Gram-Schmidt, twice */
             for (int i = 0; i <= j; ++i) hc[i] = 0;
             for (int pass = 0; pass < 2; ++pass) {
@@ -761,6 +767,12 @@ int orc_gmres(const orc_mesh* m, double h1, double h2, const double* b, double* 
     return it;
 }
 
+int orc_gmres(const orc_mesh* m, double h1, double h2, const double* b, double* x,
+              double tol, int maxit, int mrst, double* res, double* hist)
+{
+    return orc_gmres_ex(m, h1, h2, b, x, tol, maxit, mrst, 0, res, hist);
+}
+
 /* Remove the arithmetic mean over unique nodes from an assembled vector. */
 void orc_remove_mean_unique(const orc_mesh* m, double* r)
 {
@@ -792,7 +804,7 @@ int orc_poisson(const orc_mesh* m, const double* rhs, double* p, double tol, int
     memcpy(b, rhs, np * sizeof(double));
     orc_remove_mean_unique(m, b);
     for (long i = 0; i < np; ++i) p[i] = 0.0;
-    int it = orc_gmres(m, 1.0, 0.0, b, p, tol, maxit, mrst, res, NULL);
+    int it = orc_gmres_ex(m, 1.0, 0.0, b, p, tol, maxit, mrst, 1, res, NULL);
     orc_remove_mean_mass(m, p);
     free(b);
     return it;

@@ -70,11 +70,13 @@ ax_kernel(Batch bt, AxLaunch a)
         else sD[q] = (C)R->D32[q];
     }
 
-    const TU* u = a.src >= 0 ? (const TU*)R->f[a.src + comp] : (const TU*)a.u_raw;
+    const TU* u = a.src_vj ? (const TU*)R->f[F_V] + (long long)R->I[I_GJ] * R->np
+                           : a.src >= 0 ? (const TU*)R->f[a.src + comp] : (const TU*)a.u_raw;
     TU* w = a.dst >= 0 ? (TU*)R->f[a.dst + comp] : (TU*)a.w_raw;
     const TG* G = (const TG*)R->f[gfield<TG>()];
     const TG* Bm = (const TG*)R->f[bfield<TG>()];
-    const double* pc = a.precond >= 0 ? (const double*)R->f[a.precond] : nullptr;
+    const double* pc64 = a.precond >= 0 && a.tpc == P64 ? (const double*)R->f[a.precond] : nullptr;
+    const float* pc32 = a.precond >= 0 && a.tpc == P32 ? (const float*)R->f[a.precond] : nullptr;
     C h1, h2;
     if (a.hsel >= 0) { h1 = (C)R->S[a.hsel]; h2 = (C)R->S[a.hsel + 1]; }
     else { h1 = (C)a.h1; h2 = (C)a.h2; }
@@ -86,23 +88,45 @@ ax_kernel(Batch bt, AxLaunch a)
         bsc = (C)sc[R->E + ee];
     }
 
-    C ureg[LX], wacc[LX];
+    // The column's global loads are issued ahead of the k-walk: all of u and
+    // B up front, and the six G_ab either all up front (when they fit in
+    // registers) or one layer ahead, so the walk itself only waits on LDS.
+#ifndef SEM_AX_GALL_BYTES
+#define SEM_AX_GALL_BYTES 384
+#endif
+    constexpr bool GALL = 6 * LX * sizeof(C) <= SEM_AX_GALL_BYTES;
+    constexpr int NG = GALL ? LX : 2;
+    C ureg[LX], wacc[LX], bcol[LX], g6[6][NG];
     const long long ebase = (long long)ee * L3;
+    const long long gbase = (long long)ee * 6 * L3;
+    const bool helm = h2 != (C)0;
 #pragma unroll
     for (int k = 0; k < LX; ++k) {
+        const int p = k * L2 + ij;
         C v = (C)0;
         if (live) {
-            v = to<C>(u[ebase + k * L2 + ij]);
-            if (pc) v *= (C)pc[ebase + k * L2 + ij];
+            v = to<C>(u[ebase + p]);
+            if (pc64) v *= (C)pc64[ebase + p];
+            else if (pc32) v *= (C)pc32[ebase + p];
         }
         ureg[k] = v;
         wacc[k] = (C)0;
+        if (GALL) bcol[k] = (live && helm) ? GeoLoad<TG, C>::ld(Bm + ebase + p, bsc) : (C)0;
+        if (GALL || k == 0) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) g6[q][GALL ? k : 0] = live ? GeoLoad<TG, C>::ld(G + gbase + q * L3 + p, gsc) : (C)0;
+        }
     }
     __syncthreads();
 
-    const long long gbase = (long long)ee * 6 * L3;
 #pragma unroll
     for (int k = 0; k < LX; ++k) {
+        const int kc = GALL ? k : (k & 1);
+        if (!GALL && k + 1 < LX) {
+            const int pn = (k + 1) * L2 + ij;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) g6[q][(k + 1) & 1] = live ? GeoLoad<TG, C>::ld(G + gbase + q * L3 + pn, gsc) : (C)0;
+        }
         if (el < EPB) su[el][ij] = ureg[k];
         __syncthreads();
         C ur = 0, us = 0, ut = 0;
@@ -114,19 +138,9 @@ ax_kernel(Batch bt, AxLaunch a)
                 ut += sD[k * LX + l] * ureg[l];
             }
         }
-        const int p = k * L2 + ij;
-        C grr = 0, grs = 0, grt = 0, gss = 0, gst = 0, gtt = 0;
-        if (live) {
-            grr = GeoLoad<TG, C>::ld(G + gbase + 0 * L3 + p, gsc);
-            grs = GeoLoad<TG, C>::ld(G + gbase + 1 * L3 + p, gsc);
-            grt = GeoLoad<TG, C>::ld(G + gbase + 2 * L3 + p, gsc);
-            gss = GeoLoad<TG, C>::ld(G + gbase + 3 * L3 + p, gsc);
-            gst = GeoLoad<TG, C>::ld(G + gbase + 4 * L3 + p, gsc);
-            gtt = GeoLoad<TG, C>::ld(G + gbase + 5 * L3 + p, gsc);
-        }
-        const C wr = grr * ur + grs * us + grt * ut;
-        const C ws = grs * ur + gss * us + gst * ut;
-        const C wt = grt * ur + gst * us + gtt * ut;
+        const C wr = g6[0][kc] * ur + g6[1][kc] * us + g6[2][kc] * ut;
+        const C ws = g6[1][kc] * ur + g6[3][kc] * us + g6[4][kc] * ut;
+        const C wt = g6[2][kc] * ur + g6[4][kc] * us + g6[5][kc] * ut;
         if (el < EPB) { sr[el][ij] = wr; ss[el][ij] = ws; }
 #pragma unroll
         for (int l = 0; l < LX; ++l) wacc[l] += sD[k * LX + l] * wt;
@@ -147,10 +161,9 @@ ax_kernel(Batch bt, AxLaunch a)
 #pragma unroll
         for (int k = 0; k < LX; ++k) {
             const int p = k * L2 + ij;
-            C hb = (C)0;
-            if (h2 != (C)0) hb = h2 * GeoLoad<TG, C>::ld(Bm + (long long)ee * L3 + p, bsc);
-            C wv = h1 * wacc[k] + hb * ureg[k];
-            TU ws = to<TU>(wv);
+            const C bk = GALL ? bcol[k] : (helm ? GeoLoad<TG, C>::ld(Bm + ebase + p, bsc) : (C)0);
+            const C wv = h1 * wacc[k] + h2 * bk * ureg[k];
+            const TU ws = to<TU>(wv);
             w[ebase + p] = ws;
             if (a.pdot >= 0) dot += (double)ureg[k] * (double)to<C>(ws);
         }
@@ -158,7 +171,10 @@ ax_kernel(Batch bt, AxLaunch a)
     if (a.pdot >= 0) {
         double v[1] = {dot};
         block_sum<double, 1>(v, red);
-        if (t == 0) R->part[(long long)(a.pdot + comp) * R->nb + blk] = v[0];
+        if (t == 0) {
+            R->part[(long long)(a.pdot + comp) * R->pstride + blk] = v[0];
+            if (blk == 0) R->I[I_PCNT + a.pdot + comp] = R->nb;
+        }
     }
 }
 
@@ -169,15 +185,24 @@ static void ax_go(const Batch& b, const AxLaunch& a, hipStream_t s)
     hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
 }
 
+// supported (vector, geometry, arithmetic) instantiations; ax_supported()
+// in the host runtime lists the same set
 template <int LX>
 static void ax_lx(const Batch& b, const AxLaunch& a, hipStream_t s)
 {
-    if (a.tu == P64 && a.tg == P64) ax_go<LX, double, double, double>(b, a, s);
-    else if (a.tu == P32 && a.tg == P32) ax_go<LX, float, float, float>(b, a, s);
-    else if (a.tu == P32 && a.tg == P16) ax_go<LX, float, __half, float>(b, a, s);
-    else if (a.tu == P32 && a.tg == PBF) ax_go<LX, float, __hip_bfloat16, float>(b, a, s);
-    else if (a.tu == P16 && a.tg == P16) ax_go<LX, __half, __half, float>(b, a, s);
-    else if (a.tu == PBF && a.tg == PBF) ax_go<LX, __hip_bfloat16, __hip_bfloat16, float>(b, a, s);
+    const int u = a.tu, g = a.tg, c = a.tc;
+    if (u == P64 && g == P64 && c == P64) ax_go<LX, double, double, double>(b, a, s);
+    else if (u == P64 && g == P32 && c == P64) ax_go<LX, double, float, double>(b, a, s);
+    else if (u == P64 && g == P16 && c == P64) ax_go<LX, double, __half, double>(b, a, s);
+    else if (u == P64 && g == PBF && c == P64) ax_go<LX, double, __hip_bfloat16, double>(b, a, s);
+    else if (u == P64 && g == P32 && c == P32) ax_go<LX, double, float, float>(b, a, s);
+    else if (u == P64 && g == P16 && c == P32) ax_go<LX, double, __half, float>(b, a, s);
+    else if (u == P64 && g == PBF && c == P32) ax_go<LX, double, __hip_bfloat16, float>(b, a, s);
+    else if (u == P32 && g == P32 && c == P32) ax_go<LX, float, float, float>(b, a, s);
+    else if (u == P32 && g == P16 && c == P32) ax_go<LX, float, __half, float>(b, a, s);
+    else if (u == P32 && g == PBF && c == P32) ax_go<LX, float, __hip_bfloat16, float>(b, a, s);
+    else if (u == P16 && g == P16 && c == P32) ax_go<LX, __half, __half, float>(b, a, s);
+    else if (u == PBF && g == PBF && c == P32) ax_go<LX, __hip_bfloat16, __hip_bfloat16, float>(b, a, s);
 }
 
 void launch_ax(const Batch& b, int lx, const AxLaunch& a, hipStream_t s)

@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(256) diag_a_kernel(Batch bt)
     }
 }
 
-// after assembly: 1/Bsum in place, pressure Jacobi 1/dA
+// after assembly: 1/Bsum in place, pressure Jacobi 1/dA (and its fp32 copy)
 __global__ void __launch_bounds__(256) geo_post_kernel(Batch bt)
 {
     const int g = blockIdx.x;
@@ -147,9 +147,12 @@ __global__ void __launch_bounds__(256) geo_post_kernel(Batch bt)
     double* ib = (double*)R->f[F_IBSUM64];
     const double* da = (const double*)R->f[F_DA64];
     double* idp = (double*)R->f[F_IDP64];
+    float* idp32 = (float*)R->f[F_IDP32];
     for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
         ib[p] = 1.0 / ib[p];
-        idp[p] = da[p] > 0.0 ? 1.0 / da[p] : 0.0;
+        const double v = da[p] > 0.0 ? 1.0 / da[p] : 0.0;
+        idp[p] = v;
+        if (idp32) idp32[p] = (float)v;
     }
 }
 

@@ -264,9 +264,10 @@ __global__ void __launch_bounds__(ONthr<LX>::v) diagnostics_kernel(Batch bt)
     if (t == 0) {
         double m = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, mred[w]);
-        R->part[(long long)R_X0 * R->nb + blk] = v[0];
-        R->part[(long long)R_X1 * R->nb + blk] = v[1];
-        R->part[(long long)R_X2 * R->nb + blk] = m;
+        R->part[(long long)R_X0 * R->pstride + blk] = v[0];
+        R->part[(long long)R_X1 * R->pstride + blk] = v[1];
+        R->part[(long long)R_X2 * R->pstride + blk] = m;
+        if (blk == 0) { R->I[I_PCNT + R_X0] = R->nb; R->I[I_PCNT + R_X1] = R->nb; R->I[I_PCNT + R_X2] = R->nb; }
     }
 }
 
@@ -276,38 +277,35 @@ __global__ void __launch_bounds__(ONthr<LX>::v) diagnostics_kernel(Batch bt)
     case 7: CALL(7); break; case 8: CALL(8); break; case 9: CALL(9); break; case 10: CALL(10); break; \
     case 11: CALL(11); break; case 12: CALL(12); break; default: break; }
 
-void launch_conv(const Batch& b, int lx, int tm, hipStream_t s)
+// supported (metric storage, arithmetic) pairs: (fp64, fp64), (fp32, fp32),
+// (fp16, fp32), (bf16, fp32) and (fp32, fp64)
+#define OPS_DISPATCH(KERNEL, L, grid, blk, s, ...)                                                                  \
+    if (tm == P64) hipLaunchKernelGGL((KERNEL<L, double, double>), grid, blk, 0, s, __VA_ARGS__);                 \
+    else if (tm == P32 && tc == P64) hipLaunchKernelGGL((KERNEL<L, float, double>), grid, blk, 0, s, __VA_ARGS__);\
+    else if (tm == P32) hipLaunchKernelGGL((KERNEL<L, float, float>), grid, blk, 0, s, __VA_ARGS__);              \
+    else if (tm == P16) hipLaunchKernelGGL((KERNEL<L, __half, float>), grid, blk, 0, s, __VA_ARGS__);             \
+    else hipLaunchKernelGGL((KERNEL<L, __hip_bfloat16, float>), grid, blk, 0, s, __VA_ARGS__);
+
+void launch_conv(const Batch& b, int lx, int tm, int tc, hipStream_t s)
 {
     dim3 grid(b.eb[b.n]);
-#define GO(L)                                                                                                         \
-    if (tm == P64) hipLaunchKernelGGL((conv_kernel<L, double, double>), grid, dim3(ONthr<L>::v), 0, s, b);           \
-    else if (tm == P32) hipLaunchKernelGGL((conv_kernel<L, float, float>), grid, dim3(ONthr<L>::v), 0, s, b);        \
-    else if (tm == P16) hipLaunchKernelGGL((conv_kernel<L, __half, float>), grid, dim3(ONthr<L>::v), 0, s, b);       \
-    else hipLaunchKernelGGL((conv_kernel<L, __hip_bfloat16, float>), grid, dim3(ONthr<L>::v), 0, s, b);
+#define GO(L) OPS_DISPATCH(conv_kernel, L, grid, dim3(ONthr<L>::v), s, b)
     OPS_LX_SWITCH(lx, GO)
 #undef GO
 }
 
-void launch_opgrad(const Batch& b, int lx, int tm, int src, int dst, hipStream_t s)
+void launch_opgrad(const Batch& b, int lx, int tm, int tc, int src, int dst, hipStream_t s)
 {
     dim3 grid(b.eb[b.n]);
-#define GO(L)                                                                                                                   \
-    if (tm == P64) hipLaunchKernelGGL((opgrad_kernel<L, double, double>), grid, dim3(ONthr<L>::v), 0, s, b, src, dst);         \
-    else if (tm == P32) hipLaunchKernelGGL((opgrad_kernel<L, float, float>), grid, dim3(ONthr<L>::v), 0, s, b, src, dst);      \
-    else if (tm == P16) hipLaunchKernelGGL((opgrad_kernel<L, __half, float>), grid, dim3(ONthr<L>::v), 0, s, b, src, dst);     \
-    else hipLaunchKernelGGL((opgrad_kernel<L, __hip_bfloat16, float>), grid, dim3(ONthr<L>::v), 0, s, b, src, dst);
+#define GO(L) OPS_DISPATCH(opgrad_kernel, L, grid, dim3(ONthr<L>::v), s, b, src, dst)
     OPS_LX_SWITCH(lx, GO)
 #undef GO
 }
 
-void launch_wdiv(const Batch& b, int lx, int tm, int src, int dst, hipStream_t s)
+void launch_wdiv(const Batch& b, int lx, int tm, int tc, int src, int dst, hipStream_t s)
 {
     dim3 grid(b.eb[b.n]);
-#define GO(L)                                                                                                                 \
-    if (tm == P64) hipLaunchKernelGGL((wdiv_kernel<L, double, double>), grid, dim3(ONthr<L>::v), 0, s, b, src, dst);         \
-    else if (tm == P32) hipLaunchKernelGGL((wdiv_kernel<L, float, float>), grid, dim3(ONthr<L>::v), 0, s, b, src, dst);      \
-    else if (tm == P16) hipLaunchKernelGGL((wdiv_kernel<L, __half, float>), grid, dim3(ONthr<L>::v), 0, s, b, src, dst);     \
-    else hipLaunchKernelGGL((wdiv_kernel<L, __hip_bfloat16, float>), grid, dim3(ONthr<L>::v), 0, s, b, src, dst);
+#define GO(L) OPS_DISPATCH(wdiv_kernel, L, grid, dim3(ONthr<L>::v), s, b, src, dst)
     OPS_LX_SWITCH(lx, GO)
 #undef GO
 }

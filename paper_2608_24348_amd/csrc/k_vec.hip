@@ -11,12 +11,13 @@ struct PtRange {
     long long p0, p1, L3;
 };
 
+// points of point-wise block blk (vepb whole elements)
 __device__ __forceinline__ PtRange pt_range(const ReqDesc* R, int blk)
 {
     PtRange r;
     r.L3 = (long long)R->lx * R->lx * R->lx;
-    r.p0 = (long long)blk * R->epb * r.L3;
-    long long e1 = (long long)(blk + 1) * R->epb;
+    r.p0 = (long long)blk * R->vepb * r.L3;
+    long long e1 = (long long)(blk + 1) * R->vepb;
     if (e1 > R->E) e1 = R->E;
     r.p1 = e1 * r.L3;
     return r;
@@ -30,9 +31,11 @@ template <> __device__ __forceinline__ int idv_field<double>() { return F_IDV64;
 template <typename TV> __device__ __forceinline__ int idp_field() { return F_IDP32; }
 template <> __device__ __forceinline__ int idp_field<double>() { return F_IDP64; }
 
+// partial of point-wise block blk; block 0 also records how many partials the slot holds
 __device__ __forceinline__ void put_partial(const ReqDesc* R, int slot, int blk, double v)
 {
-    R->part[(long long)slot * R->nb + blk] = v;
+    R->part[(long long)slot * R->pstride + blk] = v;
+    if (blk == 0) R->I[I_PCNT + slot] = R->nvb;
 }
 
 // ------------------------------------------------------------------ generic point-wise ops
@@ -41,9 +44,9 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
 {
     __shared__ double red[(SEM_VEC_THREADS / 64) * 2];
     const int g = blockIdx.x;
-    const int ri = find_req(bt.eb, bt.n, g);
+    const int ri = find_req(bt.vb, bt.n, g);
     const ReqDesc* R = bt.r[ri];
-    const int blk = g - bt.eb[ri];
+    const int blk = g - bt.vb[ri];
     const int c = blockIdx.y;
     if (!gate_ok(R, a.gate < 0 ? -1 : a.gate + (a.ncomp > 1 ? c : 0))) return;
     const PtRange pr = pt_range(R, blk);
@@ -192,14 +195,6 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) f[p] = 0.0;
         break;
     }
-    case V_GM_PRECOND: {
-        const int J = R->I[I_GJ];
-        const double* v = fld<double>(R, F_V) + (long long)J * R->np;
-        const double* idp = fld<double>(R, F_IDP64);
-        TV* z = fldw<TV>(R, F_GZ);
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) z[p] = (TV)(v[p] * idp[p]);
-        break;
-    }
     case V_GM_NORMALIZE: {
         const int J = R->I[I_GJ];
         double* v = fldw<double>(R, F_V) + (long long)J * R->np;
@@ -247,63 +242,80 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
 
 // ------------------------------------------------------------------ GMRES orthogonalisation passes
 // One pass over the points of a block touches every basis vector V_0..V_J
-// once; per-point values live in a register array sized for the largest
-// restart, indexed only with compile-time indices under a J guard.
-template <typename TW, int MODE>
+// once.  The body is instantiated for every basis size NJ = J+1 (J is read on
+// the device and dispatched with a uniform switch), so each point issues its
+// NJ independent loads back to back before any arithmetic consumes them.
+// The periodic Poisson operator is singular with constant null vectors and a
+// range orthogonal to them, so the first pass also sums the operator output
+// over unique nodes and the second subtracts that mean: a no-op in exact
+// arithmetic that keeps rounding (notably of fp32 operators) from feeding the
+// null direction into the basis.
+template <int NJ, int MODE>
+__device__ __forceinline__ void gm_body(const ReqDesc* R, const PtRange& pr, double (&acc)[SEM_MAXM + 1], double& accm)
+{
+    const double* V = fld<double>(R, F_V);
+    const long long np = R->np;
+    const int lx = R->lx;
+    double h[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) h[i] = MODE == 1 ? R->S[S_GHC + i] : MODE == 2 ? R->S[S_GH2 + i] : 0.0;
+    const double mean = MODE == 1 ? R->S[S_GMEAN] : 0.0;
+    const double* w = fld<double>(R, F_GW);
+    double* wd = fldw<double>(R, F_GWD);
+    for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+        double vr[NJ];
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) vr[i] = V[i * np + p];
+        const double im = inv_mult((int)((p - pr.p0) % pr.L3), lx);
+        if (MODE == 0) {
+            const double wv = w[p] * im;
+            accm += wv;
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) acc[i] += vr[i] * wv;
+        } else if (MODE == 1) {
+            double wv = w[p] - mean;
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) wv -= h[i] * vr[i];
+            wd[p] = wv;
+            wv *= im;
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) acc[i] += vr[i] * wv;
+        } else {
+            double wv = wd[p];
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) wv -= h[i] * vr[i];
+            wd[p] = wv;
+            acc[0] += wv * wv * im;
+        }
+    }
+}
+
+#define SEM_NJ_CASES(F)                                                                                 \
+    F(1) F(2) F(3) F(4) F(5) F(6) F(7) F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) F(16) F(17) F(18) \
+    F(19) F(20) F(21) F(22) F(23) F(24) F(25) F(26) F(27) F(28) F(29) F(30) F(31)
+
+template <int MODE>
 __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_pass_kernel(Batch bt, int gate)
 {
     constexpr int NV = SEM_MAXM + 1;
     __shared__ double red[(SEM_VEC_THREADS / 64) * NV];
     const int g = blockIdx.x;
-    const int ri = find_req(bt.eb, bt.n, g);
+    const int ri = find_req(bt.vb, bt.n, g);
     const ReqDesc* R = bt.r[ri];
-    const int blk = g - bt.eb[ri];
+    const int blk = g - bt.vb[ri];
     if (!gate_ok(R, gate)) return;
     const PtRange pr = pt_range(R, blk);
-    const int lx = R->lx;
     const int J = R->I[I_GJ];
-    const double* V = fld<double>(R, F_V);
-    const long long np = R->np;
-    const double* S = R->S;
     double acc[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-
-    if (MODE == 0) {  // dots (V_i, GW)
-        const TW* w = fld<TW>(R, F_GW);
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
-            const double wv = to<double>(w[p]) * inv_mult((int)((p - pr.p0) % pr.L3), lx);
-#pragma unroll
-            for (int i = 0; i < NV; ++i)
-                if (i <= J) acc[i] += V[i * np + p] * wv;
-        }
-    } else if (MODE == 1) {  // GWD = GW - sum h_i V_i, dots (V_i, GWD)
-        const TW* w = fld<TW>(R, F_GW);
-        double* wd = fldw<double>(R, F_GWD);
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
-            double vr[NV];
-            double wv = to<double>(w[p]);
-#pragma unroll
-            for (int i = 0; i < NV; ++i)
-                if (i <= J) { vr[i] = V[i * np + p]; wv -= S[S_GHC + i] * vr[i]; }
-            wd[p] = wv;
-            wv *= inv_mult((int)((p - pr.p0) % pr.L3), lx);
-#pragma unroll
-            for (int i = 0; i < NV; ++i)
-                if (i <= J) acc[i] += vr[i] * wv;
-        }
-    } else {  // GWD -= sum h2_i V_i, |GWD|^2
-        double* wd = fldw<double>(R, F_GWD);
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
-            double wv = wd[p];
-#pragma unroll
-            for (int i = 0; i < NV; ++i)
-                if (i <= J) wv -= S[S_GH2 + i] * V[i * np + p];
-            wd[p] = wv;
-            acc[0] += wv * wv * inv_mult((int)((p - pr.p0) % pr.L3), lx);
-        }
+    double accm = 0.0;
+    switch (J + 1) {
+#define GM_CASE(n) case n: gm_body<n, MODE>(R, pr, acc, accm); break;
+        SEM_NJ_CASES(GM_CASE)
+#undef GM_CASE
+    default: break;
     }
-
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int nv = MODE == 2 ? 1 : J + 1;
 #pragma unroll
@@ -320,52 +332,71 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_pass_kernel(Batch bt, int 
         for (int w = 0; w < nw; ++w) s += red[w * NV + i];
         put_partial(R, MODE == 2 ? R_GN : R_GM + i, blk, s);
     }
+    if (MODE == 0) {
+        double v1[1] = {accm};
+        block_sum<double, 1>(v1, red);
+        if (threadIdx.x == 0) put_partial(R, R_GMEAN, blk, v1[0]);
+    }
 }
 
-// x += IDP * sum_{i < jend} y_i V_i  (right preconditioning applied once per cycle)
-__global__ void __launch_bounds__(SEM_VEC_THREADS) gm_xupd_kernel(Batch bt, int gate)
+// x += IDP * sum_{i < jend} y_i V_i  (right preconditioning applied once per
+// cycle, with the same stored diagonal the Arnoldi operator used)
+template <int NJ, typename TD>
+__device__ __forceinline__ void xupd_body(const ReqDesc* R, const PtRange& pr)
 {
-    constexpr int NV = SEM_MAXM;
-    const int g = blockIdx.x;
-    const int ri = find_req(bt.eb, bt.n, g);
-    const ReqDesc* R = bt.r[ri];
-    const int blk = g - bt.eb[ri];
-    if (!gate_ok(R, gate)) return;
-    const PtRange pr = pt_range(R, blk);
-    const int jend = R->I[I_GJEND];
     const double* V = fld<double>(R, F_V);
-    const double* idp = fld<double>(R, F_IDP64);
+    const TD* idp = fld<TD>(R, sizeof(TD) == 8 ? F_IDP64 : F_IDP32);
     double* x = fldw<double>(R, F_GX);
     const long long np = R->np;
-    const double* y = R->S + S_GY;
+    double y[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) y[i] = R->S[S_GY + i];
     for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+        double vr[NJ];
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) vr[i] = V[i * np + p];
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < NV; ++i)
-            if (i < jend) s += y[i] * V[i * np + p];
-        x[p] += s * idp[p];
+        for (int i = 0; i < NJ; ++i) s += y[i] * vr[i];
+        x[p] += s * (double)idp[p];
+    }
+}
+
+template <typename TD>
+__global__ void __launch_bounds__(SEM_VEC_THREADS) gm_xupd_kernel(Batch bt, int gate)
+{
+    const int g = blockIdx.x;
+    const int ri = find_req(bt.vb, bt.n, g);
+    const ReqDesc* R = bt.r[ri];
+    const int blk = g - bt.vb[ri];
+    if (!gate_ok(R, gate)) return;
+    const PtRange pr = pt_range(R, blk);
+    switch (R->I[I_GJEND]) {
+#define XU_CASE(n) case n: xupd_body<n, TD>(R, pr); break;
+        SEM_NJ_CASES(XU_CASE)
+#undef XU_CASE
+    default: break;
     }
 }
 
 void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s)
 {
-    dim3 grid(b.eb[b.n], a.ncomp > 0 ? a.ncomp : 1);
+    dim3 grid(b.vb[b.n], a.ncomp > 0 ? a.ncomp : 1);
     dim3 blk(SEM_VEC_THREADS);
     if (grid.x == 0) return;
     switch (a.op) {
     case V_GM_DOTS:
-        if (a.tv == P64) hipLaunchKernelGGL((gm_pass_kernel<double, 0>), grid, blk, 0, s, b, a.gate);
-        else hipLaunchKernelGGL((gm_pass_kernel<float, 0>), grid, blk, 0, s, b, a.gate);
+        hipLaunchKernelGGL(gm_pass_kernel<0>, grid, blk, 0, s, b, a.gate);
         return;
     case V_GM_UPD_DOTS:
-        if (a.tv == P64) hipLaunchKernelGGL((gm_pass_kernel<double, 1>), grid, blk, 0, s, b, a.gate);
-        else hipLaunchKernelGGL((gm_pass_kernel<float, 1>), grid, blk, 0, s, b, a.gate);
+        hipLaunchKernelGGL(gm_pass_kernel<1>, grid, blk, 0, s, b, a.gate);
         return;
     case V_GM_UPD_NORM:
-        hipLaunchKernelGGL((gm_pass_kernel<double, 2>), grid, blk, 0, s, b, a.gate);
+        hipLaunchKernelGGL(gm_pass_kernel<2>, grid, blk, 0, s, b, a.gate);
         return;
     case V_GM_XUPD:
-        hipLaunchKernelGGL(gm_xupd_kernel, grid, blk, 0, s, b, a.gate);
+        if (a.tv == P64) hipLaunchKernelGGL(gm_xupd_kernel<double>, grid, blk, 0, s, b, a.gate);
+        else hipLaunchKernelGGL(gm_xupd_kernel<float>, grid, blk, 0, s, b, a.gate);
         return;
     default: break;
     }
@@ -379,8 +410,9 @@ void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s)
 __device__ double slot_sum(const ReqDesc* R, int slot, double* red)
 {
     double s = 0.0;
-    const double* p = R->part + (long long)slot * R->nb;
-    for (int q = threadIdx.x; q < R->nb; q += blockDim.x) s += p[q];
+    const double* p = R->part + (long long)slot * R->pstride;
+    const int cnt = R->I[I_PCNT + slot];
+    for (int q = threadIdx.x; q < cnt; q += blockDim.x) s += p[q];
     double v[1] = {s};
     block_sum<double, 1>(v, red);
     return v[0];
@@ -388,8 +420,9 @@ __device__ double slot_sum(const ReqDesc* R, int slot, double* red)
 __device__ double slot_max(const ReqDesc* R, int slot, double* red)
 {
     double s = 0.0;
-    const double* p = R->part + (long long)slot * R->nb;
-    for (int q = threadIdx.x; q < R->nb; q += blockDim.x) s = fmax(s, p[q]);
+    const double* p = R->part + (long long)slot * R->pstride;
+    const int cnt = R->I[I_PCNT + slot];
+    for (int q = threadIdx.x; q < cnt; q += blockDim.x) s = fmax(s, p[q]);
     s = wave_max(s);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -401,12 +434,35 @@ __device__ double slot_max(const ReqDesc* R, int slot, double* red)
     return m;
 }
 
+// fixed-order sums of nslots (<= 32) consecutive slots at once: 8 groups of
+// 32 threads, thread (g, s) adds partials g, g+8, ... of slot s; the 8 group
+// sums are then added in group order.  out must hold nslots values.
+__device__ void multi_slot_sum(const ReqDesc* R, int slot0, int nslots, double* out, double* scratch)
+{
+    const int t = threadIdx.x, sl = t & 31, g = t >> 5;
+    double acc = 0.0;
+    if (sl < nslots) {
+        const double* p = R->part + (long long)(slot0 + sl) * R->pstride;
+        const int cnt = R->I[I_PCNT + slot0 + sl];
+        for (int q = g; q < cnt; q += 8) acc += p[q];
+    }
+    scratch[t] = acc;
+    __syncthreads();
+    if (t < nslots) {
+        double v = 0.0;
+        for (int k = 0; k < 8; ++k) v += scratch[k * 32 + t];
+        out[t] = v;
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ bool finite(double v) { return isfinite(v); }
 
 __global__ void __launch_bounds__(256) fin_kernel(Batch bt, FinArgs a)
 {
     __shared__ double red[8 * 4];
     __shared__ double sums[SEM_MAXM + 2];
+    __shared__ double scratch[256];
     const int ri = blockIdx.x;
     ReqDesc* R = (ReqDesc*)bt.r[ri];
     double* S = R->S;
@@ -473,9 +529,11 @@ __global__ void __launch_bounds__(256) fin_kernel(Batch bt, FinArgs a)
     case FIN_GM_H2: {
         if (!I[I_GARN]) break;
         const int J = I[I_GJ];
-        for (int i = 0; i <= J; ++i) {
-            double s = slot_sum(R, R_GM + i, red);
-            if (t == 0) S[(a.op == FIN_GM_H1 ? S_GHC : S_GH2) + i] = s;
+        multi_slot_sum(R, R_GM, J + 1, sums, scratch);
+        if (t <= J) S[(a.op == FIN_GM_H1 ? S_GHC : S_GH2) + t] = sums[t];
+        if (a.op == FIN_GM_H1) {
+            double s = slot_sum(R, R_GMEAN, red);
+            if (t == 0) S[S_GMEAN] = s / (double)R->nglob;
         }
         if (t == 0) I[I_GNORM] = 0;
         break;

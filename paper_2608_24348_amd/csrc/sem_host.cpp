@@ -143,13 +143,29 @@ size_t psize(int pid) { return pid == P64 ? 8 : pid == P32 ? 4 : 2; }
 
 struct Resolved {
     int tv, tva;            // velocity vectors, velocity dot accumulation (PrecId)
-    int axv_g;              // velocity Ax geometry storage
-    int tp;                 // pressure Ax vectors
-    int axp_g;              // pressure Ax geometry storage
-    int opg_m, conv_m, div_m;
+    int axv_g, axv_c;       // velocity Ax geometry storage and arithmetic
+    int tpd;                // pressure Jacobi diagonal storage
+    int axp_g, axp_c;       // pressure Ax geometry storage and arithmetic (vectors are the fp64 GMRES basis)
+    int opg_m, opg_c, conv_m, conv_c, div_m, div_c;  // SEM operators: metric storage and arithmetic
     bool need32, need16;
     int kind16;             // P16 or PBF
 };
+
+// (vector, geometry, arithmetic) instantiations of the Helmholtz kernel
+bool ax_supported(int u, int g, int c)
+{
+    if (u == P64) return (c == P64) || (c == P32 && g != P64);
+    if (u == P32) return c == P32 && g != P64;
+    if (u == P16) return c == P32 && g == P16;
+    if (u == PBF) return c == P32 && g == PBF;
+    return false;
+}
+
+// (metric storage, arithmetic) instantiations of the SEM operator kernels
+bool op_supported(int m, int c)
+{
+    return (m == P64 && c == P64) || (m != P64 && c == P32) || (m == P32 && c == P64);
+}
 
 }  // namespace
 
@@ -159,7 +175,7 @@ struct sem_ctx {
     sem_flow_desc flow;
     sem_precision prec;
     Resolved rs;
-    int N, lx, E, epb, nb;
+    int N, lx, E, epb, nb, vepb, nvb, pstride;
     long long np, nglob;
     int n2, n4, n8;
     std::vector<double> D64tab;
@@ -183,6 +199,10 @@ struct sem_ctx {
 
 namespace {
 
+// Precision policy (the paper's three-level model, Sec. 2 / Fig. 4, Table 2).
+// rp caps the storage role of every block and kernel (the paper's Group B
+// runs fp64 compute on fp32 storage under rp = fp32, so compute and
+// accumulate may exceed rp).  Kernel overrides replace their block's roles.
 int resolve_policy(const sem_precision* p, Resolved& r)
 {
     if (!p || p->size != (int)sizeof(sem_precision)) return fail(SEM_EINVAL, "sem_precision: bad size field");
@@ -190,13 +210,17 @@ int resolve_policy(const sem_precision* p, Resolved& r)
     const int rp = prec_rank(p->rp);
     if (p->rp == SEM_FP32 && (p->fp64_exceptions & SEM_X_ALL) != SEM_X_ALL)
         return fail(SEM_EINVAL, "rp = fp32 requires the fp64 exceptions STATE|GMRES|RESID|REDUCE (state, GMRES "
-                                "orthogonalisation, residual checks and the global reduction stage stay fp64)");
+                                "basis and orthogonalisation, residual checks and the global reduction stage stay fp64)");
+    static const char* bname[SEM_NBLOCK] = {"sem", "velocity", "pressure"};
     sem_role blk[SEM_NBLOCK];
     for (int b = 0; b < SEM_NBLOCK; ++b) {
         blk[b] = p->block[b];
         const int v[3] = {blk[b].compute, blk[b].accumulate, blk[b].storage};
         for (int q = 0; q < 3; ++q)
-            if (prec_rank(v[q]) < 0) return fail(SEM_EINVAL, "block precision must be FP64, FP32, FP16 or BF16");
+            if (prec_rank(v[q]) < 0) return fail(SEM_EINVAL, std::string(bname[b]) + " block: unknown precision");
+        if (prec_rank(blk[b].storage) > rp) return fail(SEM_EINVAL, std::string(bname[b]) + " block: storage above rp");
+        if (prec_rank(blk[b].accumulate) < prec_rank(blk[b].compute))
+            return fail(SEM_EINVAL, std::string(bname[b]) + " block: accumulate below compute");
     }
     static const int kblock[SEM_K_COUNT] = {SEM_BLOCK_VEL, SEM_BLOCK_PRES, SEM_BLOCK_SEM, SEM_BLOCK_SEM, SEM_BLOCK_SEM};
     static const char* kname[SEM_K_COUNT] = {"ax_vel", "ax_pres", "opgrad", "conv", "div"};
@@ -208,66 +232,48 @@ int resolve_policy(const sem_precision* p, Resolved& r)
         kr[k].accumulate = o.accumulate == SEM_INHERIT ? d.accumulate : o.accumulate;
         kr[k].storage = o.storage == SEM_INHERIT ? d.storage : o.storage;
         const int v[3] = {kr[k].compute, kr[k].accumulate, kr[k].storage};
-        for (int q = 0; q < 3; ++q) {
-            if (prec_rank(v[q]) < 0) return fail(SEM_EINVAL, std::string(kname[k]) + ": unknown precision");
-            if (prec_rank(v[q]) > rp) return fail(SEM_EINVAL, std::string(kname[k]) + ": precision above rp");
-        }
-    }
-    for (int b = 0; b < SEM_NBLOCK; ++b) {
-        const int v[3] = {blk[b].compute, blk[b].accumulate, blk[b].storage};
         for (int q = 0; q < 3; ++q)
-            if (prec_rank(v[q]) > rp) return fail(SEM_EINVAL, "block precision above rp");
+            if (prec_rank(v[q]) < 0) return fail(SEM_EINVAL, std::string(kname[k]) + ": unknown precision");
+        if (prec_rank(kr[k].storage) > rp) return fail(SEM_EINVAL, std::string(kname[k]) + ": storage above rp");
+        if (kr[k].compute != SEM_FP64 && kr[k].compute != SEM_FP32)
+            return fail(SEM_EINVAL, std::string(kname[k]) + ": arithmetic must be fp64 or fp32 (16-bit work is "
+                                    "expressed as 16-bit storage)");
+        if (prec_rank(kr[k].accumulate) < prec_rank(kr[k].compute))
+            return fail(SEM_EINVAL, std::string(kname[k]) + ": accumulate below compute");
     }
-    // vectors of the solver blocks: compute == storage in {fp64, fp32}
     const sem_role& vb = blk[SEM_BLOCK_VEL];
     const sem_role& pb = blk[SEM_BLOCK_PRES];
     if (vb.storage != SEM_FP64 && vb.storage != SEM_FP32)
-        return fail(SEM_EINVAL, "velocity block storage must be fp64 or fp32 (16-bit storage is a kernel override of ax_vel)");
+        return fail(SEM_EINVAL, "velocity block storage must be fp64 or fp32 (16-bit storage is an ax_vel override)");
     if (vb.compute != vb.storage) return fail(SEM_EINVAL, "velocity block: compute must equal storage");
-    if (prec_rank(vb.accumulate) < prec_rank(vb.compute)) return fail(SEM_EINVAL, "velocity block: accumulate below compute");
     if (pb.storage != SEM_FP64 && pb.storage != SEM_FP32)
-        return fail(SEM_EINVAL, "pressure block storage must be fp64 or fp32 (16-bit storage is a kernel override of ax_pres)");
-    if (pb.compute != pb.storage) return fail(SEM_EINVAL, "pressure block: compute must equal storage");
+        return fail(SEM_EINVAL, "pressure block storage must be fp64 or fp32 (16-bit storage is an ax_pres override)");
     r.tv = to_pid(vb.storage);
     r.tva = to_pid(vb.accumulate);
-    r.tp = to_pid(pb.storage);
-    // Ax kernels: (vec64, geo64, C64) or (vec32, geo32|16|bf16, C32)
-    auto check_ax = [&](int k, int vec, int& geo) -> int {
-        const sem_role& q = kr[k];
-        if (q.compute == SEM_FP64) {
-            if (vec != P64 || q.storage != SEM_FP64)
-                return fail(SEM_EINVAL, std::string(kname[k]) + ": fp64 compute needs fp64 vectors and geometry");
-        } else if (q.compute == SEM_FP32) {
-            if (vec != P32) return fail(SEM_EINVAL, std::string(kname[k]) + ": fp32 compute needs fp32 block vectors");
-        } else {
-            return fail(SEM_EINVAL, std::string(kname[k]) + ": 16-bit arithmetic is expressed as 16-bit storage with "
-                                    "fp32 compute/accumulate");
-        }
-        if (prec_rank(q.accumulate) < prec_rank(q.compute))
-            return fail(SEM_EINVAL, std::string(kname[k]) + ": accumulate below compute");
-        geo = to_pid(q.storage);
-        return 0;
-    };
-    int rc;
-    if ((rc = check_ax(SEM_K_AX_VEL, r.tv, r.axv_g))) return rc;
-    if ((rc = check_ax(SEM_K_AX_PRES, r.tp, r.axp_g))) return rc;
-    auto check_op = [&](int k, int& m) -> int {
-        const sem_role& q = kr[k];
-        if (q.compute == SEM_FP64) {
-            if (q.storage != SEM_FP64) return fail(SEM_EINVAL, std::string(kname[k]) + ": fp64 compute needs fp64 storage");
-        } else if (q.compute != SEM_FP32) {
-            return fail(SEM_EINVAL, std::string(kname[k]) + ": compute must be fp64 or fp32");
-        } else if (q.storage == SEM_FP64) {
-            return fail(SEM_EINVAL, std::string(kname[k]) + ": fp32 compute reads fp32 or 16-bit metric terms");
-        }
-        m = to_pid(q.storage);
-        return 0;
-    };
-    if ((rc = check_op(SEM_K_OPGRAD, r.opg_m))) return rc;
-    if ((rc = check_op(SEM_K_CONV, r.conv_m))) return rc;
-    if ((rc = check_op(SEM_K_DIV, r.div_m))) return rc;
+    r.tpd = to_pid(pb.storage);
+    r.axv_g = to_pid(kr[SEM_K_AX_VEL].storage);
+    r.axv_c = to_pid(kr[SEM_K_AX_VEL].compute);
+    if (!ax_supported(r.tv, r.axv_g, r.axv_c))
+        return fail(SEM_EINVAL, std::string("ax_vel: no kernel for vectors ") + pname(vb.storage) + ", geometry " +
+                                pname(kr[SEM_K_AX_VEL].storage) + ", arithmetic " + pname(kr[SEM_K_AX_VEL].compute));
+    r.axp_g = to_pid(kr[SEM_K_AX_PRES].storage);
+    r.axp_c = to_pid(kr[SEM_K_AX_PRES].compute);
+    if (!ax_supported(P64, r.axp_g, r.axp_c))
+        return fail(SEM_EINVAL, std::string("ax_pres: no kernel for geometry ") + pname(kr[SEM_K_AX_PRES].storage) +
+                                ", arithmetic " + pname(kr[SEM_K_AX_PRES].compute));
+    int* mm[3] = {&r.opg_m, &r.conv_m, &r.div_m};
+    int* cc[3] = {&r.opg_c, &r.conv_c, &r.div_c};
+    for (int q = 0; q < 3; ++q) {
+        const int k = SEM_K_OPGRAD + q;
+        *mm[q] = to_pid(kr[k].storage);
+        *cc[q] = to_pid(kr[k].compute);
+        if (!op_supported(*mm[q], *cc[q]))
+            return fail(SEM_EINVAL, std::string(kname[k]) + ": no kernel for this storage/arithmetic pair");
+    }
     const int all[5] = {r.axv_g, r.axp_g, r.opg_m, r.conv_m, r.div_m};
-    r.need32 = false; r.need16 = false; r.kind16 = 0;
+    r.need32 = r.tpd == P32;
+    r.need16 = false;
+    r.kind16 = 0;
     for (int v : all) {
         if (v == P32) r.need32 = true;
         if (v == P16 || v == PBF) {
@@ -341,7 +347,7 @@ void build_layout(sem_ctx* c)
     c->off_desc = take(sizeof(ReqDesc));
     c->off_S = take(sizeof(double) * NSCALAR);
     c->off_I = take(sizeof(int) * NINT);
-    c->off_part = take(sizeof(double) * (size_t)NRED * c->nb);
+    c->off_part = take(sizeof(double) * (size_t)NRED * c->pstride);
     c->off_D64 = take(sizeof(double) * (c->lx * c->lx + 2 * c->lx));
     c->off_D32 = take(sizeof(float) * (c->lx * c->lx + 2 * c->lx));
     c->off_i2 = take(sizeof(int) * c->idx2.size());
@@ -361,6 +367,7 @@ void build_layout(sem_ctx* c)
         field(F_G32, 6 * 4 * (size_t)np);
         field(F_B32, 4 * (size_t)np);
         field(F_M32, 9 * 4 * (size_t)np);
+        field(F_IDP32, 4 * (size_t)np);
     }
     if (r.need16) {
         field(F_G16, 6 * 2 * (size_t)np);
@@ -371,10 +378,8 @@ void build_layout(sem_ctx* c)
     }
     const int mode = c->flow.mode;
     if (mode >= SEM_MODE_POISSON) {
-        const size_t tp = psize(r.tp);
         field(F_V, (size_t)(c->flow.gmres_restart + 1) * d);
-        field(F_GZ, tp * np);
-        field(F_GW, tp * np);
+        field(F_GW, d);
         field(F_GWD, d);
         field(F_GB, d);
         field(F_GX, d);
@@ -395,10 +400,12 @@ semk::Batch make_batch(sem_ctx* const* ctxs, int n)
     memset(&b, 0, sizeof(b));
     b.n = n;
     b.eb[0] = 0;
+    b.vb[0] = 0;
     b.gs[0] = 0;
     for (int i = 0; i < n; ++i) {
         sem_ctx* c = ctxs[i];
         b.eb[i + 1] = b.eb[i] + c->nb;
+        b.vb[i + 1] = b.vb[i] + c->nvb;
         b.gs[i + 1] = b.gs[i] + c->hdesc.c2 + c->hdesc.c4 + c->hdesc.c8;
         b.r[i] = c->ddesc;
     }
@@ -422,13 +429,42 @@ int poll_k()
     return k;
 }
 
+// ------------------------------------------------------------------ event profiler
+struct Prof {
+    int kclass = 0;
+    std::vector<hipEvent_t> ev;  // pairs
+    size_t used = 0;             // events used (2 per launch)
+    std::vector<hipStream_t> st;
+};
+Prof g_prof;
+
+void prof_mark(int kclass, hipStream_t s)
+{
+    if (g_prof.kclass != kclass) return;
+    if (g_prof.used == g_prof.ev.size()) {
+        for (int q = 0; q < 256; ++q) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            g_prof.ev.push_back(e);
+        }
+    }
+    (void)hipEventRecord(g_prof.ev[g_prof.used++], s);
+}
+
+struct ProfScope {
+    int k;
+    hipStream_t s;
+    ProfScope(int kclass, hipStream_t st) : k(kclass), s(st) { prof_mark(k, s); }
+    ~ProfScope() { prof_mark(k, s); }
+};
+
 // ------------------------------------------------------------------ launch helpers
 void ax(const Batch& b, int lx, int src, int dst, int ncomp, int hsel, double h1, double h2, int precond, int pdot,
-        int gate, int tu, int tg, hipStream_t s)
+        int gate, int tu, int tg, int tc, hipStream_t s)
 {
     AxLaunch a;
-    a.src = src; a.dst = dst; a.ncomp = ncomp; a.hsel = hsel; a.h1 = h1; a.h2 = h2;
-    a.precond = precond; a.pdot = pdot; a.gate = gate; a.tu = tu; a.tg = tg;
+    a.src = src; a.src_vj = 0; a.dst = dst; a.ncomp = ncomp; a.hsel = hsel; a.h1 = h1; a.h2 = h2;
+    a.precond = precond; a.tpc = P64; a.pdot = pdot; a.gate = gate; a.tu = tu; a.tg = tg; a.tc = tc;
     a.u_raw = nullptr; a.w_raw = nullptr;
     launch_ax(b, lx, a, s);
 }
@@ -475,7 +511,7 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
     int* hf = c0->hflags;
     // fp64 residual of the current state: R64 = RHS - dssum(H U), norms -> VACT
     vec(b, V_US_COPY, 3, P64, -1, s);
-    ax(b, lx, F_U, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, s);
+    ax(b, lx, F_U, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, P64, s);
     launch_dssum(b, F_W64, 3, P64, -1, nullptr, s);
     vec(b, V_VRESID, 3, P64, -1, s);
     fin(b, FIN_VINIT, s);
@@ -490,7 +526,10 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
         int guard = 0;
         for (;;) {
             for (int q = 0; q < K; ++q) {
-                ax(b, lx, F_PP, F_PW, 3, S_H1, 0, 0, -1, R_A, I_VACT, tv, r.axv_g, s);
+                {
+                    ProfScope ps(SEM_PROF_AX_VEL, s);
+                    ax(b, lx, F_PP, F_PW, 3, S_H1, 0, 0, -1, R_A, I_VACT, tv, r.axv_g, r.axv_c, s);
+                }
                 launch_dssum(b, F_PW, 3, tv, I_VACT, nullptr, s);
                 fin(b, FIN_PCG_ALPHA, s);
                 vec(b, V_PCG_UPD, 3, tv, I_VACT, s, -1, -1, r.tva);
@@ -504,7 +543,7 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
         }
         vec(b, V_US_ADD, 3, tv, -1, s);
         if (tv == P64) break;  // fp64 recurrence residual is the solver's stop criterion
-        ax(b, lx, F_US, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, s);
+        ax(b, lx, F_US, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, P64, s);
         launch_dssum(b, F_W64, 3, P64, -1, nullptr, s);
         vec(b, V_VRESID, 3, P64, -1, s);
         fin(b, FIN_VINIT, s);
@@ -516,20 +555,38 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
 // pending); every kernel is gated so converged requests idle.
 void gmres_iteration(const Batch& b, int lx, const Resolved& r, hipStream_t s)
 {
-    const int tp = r.tp;
-    vec(b, V_GM_PRECOND, 1, tp, I_GARN, s);
-    ax(b, lx, F_GZ, F_GW, 1, -1, 1.0, 0.0, -1, -1, I_GARN, tp, r.axp_g, s);
-    launch_dssum(b, F_GW, 1, tp, I_GARN, nullptr, s);
-    vec(b, V_GM_DOTS, 1, tp, I_GARN, s);
+    {
+        // w = A M^{-1} V_J: the Jacobi scaling is applied while loading V_J
+        ProfScope ps(SEM_PROF_AX_PRES, s);
+        AxLaunch a;
+        a.src = -1; a.src_vj = 1; a.dst = F_GW; a.ncomp = 1; a.hsel = -1; a.h1 = 1.0; a.h2 = 0.0;
+        a.precond = r.tpd == P64 ? F_IDP64 : F_IDP32; a.tpc = r.tpd; a.pdot = -1; a.gate = I_GARN;
+        a.tu = P64; a.tg = r.axp_g; a.tc = r.axp_c; a.u_raw = nullptr; a.w_raw = nullptr;
+        launch_ax(b, lx, a, s);
+    }
+    {
+        ProfScope ps(SEM_PROF_DSSUM_PRES, s);
+        launch_dssum(b, F_GW, 1, P64, I_GARN, nullptr, s);
+    }
+    {
+        ProfScope ps(SEM_PROF_GM_DOTS, s);
+        vec(b, V_GM_DOTS, 1, P64, I_GARN, s);
+    }
     fin(b, FIN_GM_H1, s);
-    vec(b, V_GM_UPD_DOTS, 1, tp, I_GARN, s);
+    {
+        ProfScope ps(SEM_PROF_GM_UPD_DOTS, s);
+        vec(b, V_GM_UPD_DOTS, 1, P64, I_GARN, s);
+    }
     fin(b, FIN_GM_H2, s);
-    vec(b, V_GM_UPD_NORM, 1, P64, I_GARN, s);
+    {
+        ProfScope ps(SEM_PROF_GM_UPD_NORM, s);
+        vec(b, V_GM_UPD_NORM, 1, P64, I_GARN, s);
+    }
     fin(b, FIN_GM_COL, s);
     vec(b, V_GM_NORMALIZE, 1, P64, I_GNORM, s);
     // cycle end: x update and fp64 true residual, then restart or finish
-    vec(b, V_GM_XUPD, 1, P64, I_GEND, s);
-    ax(b, lx, F_GX, F_GWD, 1, -1, 1.0, 0.0, -1, -1, I_GEND, P64, P64, s);
+    vec(b, V_GM_XUPD, 1, r.tpd, I_GEND, s);
+    ax(b, lx, F_GX, F_GWD, 1, -1, 1.0, 0.0, -1, -1, I_GEND, P64, P64, P64, s);
     launch_dssum(b, F_GWD, 1, P64, I_GEND, nullptr, s);
     vec(b, V_GM_RESID, 1, P64, I_GEND, s);
     fin(b, FIN_GM_RESTART, s);
@@ -633,6 +690,14 @@ int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_pr
     c->nglob = E * (long long)mesh->order * mesh->order * mesh->order;
     c->epb = epb_of(c->lx);
     c->nb = (int)((E + c->epb - 1) / c->epb);
+    c->vepb = vepb_of(c->lx, c->E);
+    c->nvb = (c->E + c->vepb - 1) / c->vepb;
+    c->pstride = std::max(c->nb, c->nvb);
+    if (c->nb > c->pstride || c->nvb > c->pstride || (long long)c->nb * c->epb < c->E ||
+        (long long)c->nvb * c->vepb < c->E) {
+        delete c;
+        return fail(SEM_EINVAL, "internal block layout inconsistent");
+    }
     std::vector<double> x, w, D;
     gll_tables(c->N, x, w, D);
     c->D64tab.resize(lx * lx + 2 * lx);
@@ -678,7 +743,10 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     hipStream_t s = c->stream;
     ReqDesc& d = c->hdesc;
     memset(&d, 0, sizeof(d));
-    d.E = c->E; d.lx = c->lx; d.epb = c->epb; d.nb = c->nb;
+    d.E = c->E; d.lx = c->lx; d.epb = c->epb; d.nb = c->nb; d.vepb = c->vepb; d.nvb = c->nvb;
+    d.pstride = c->pstride;
+    if (c->nb > c->pstride || c->nvb > c->pstride || (long long)c->nb * c->epb < c->E || (long long)c->nvb * c->vepb < c->E)
+        return fail(SEM_EINVAL, "internal block layout inconsistent");
     d.n2 = c->n2; d.n4 = c->n4; d.n8 = c->n8;
     d.c2 = (c->n2 + SEM_GS_CHUNK - 1) / SEM_GS_CHUNK;
     d.c4 = (c->n4 + SEM_GS_CHUNK - 1) / SEM_GS_CHUNK;
@@ -739,7 +807,7 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     if (c->flow.mode == SEM_MODE_FLUID) {
         launch_init_fields(b, c->lx, c->flow.init, c->mp, s);
         // history of the convective term starts at the initial field
-        launch_conv(b, c->lx, c->rs.conv_m, s);
+        launch_conv(b, c->lx, c->rs.conv_m, c->rs.conv_c, s);
         vec(b, V_COPY, 3, P64, -1, s, F_BN, F_BNL1);
         vec(b, V_COPY, 3, P64, -1, s, F_BN, F_BNL2);
         rc = check_hip_last();
@@ -806,16 +874,19 @@ int sem_ax(sem_ctx* c, const void* u, void* w, double h1, double h2, int buf_pre
     else return fail(SEM_EINVAL, "bad geom_prec");
     const int tu = to_pid(buf_prec);
     bool held = tg == P64 || (tg == P32 && c->rs.need32) || ((tg == P16 || tg == PBF) && c->rs.need16 && c->rs.kind16 == tg);
-    if (!held) return fail(SEM_EINVAL, std::string("geometry in ") + pname(geom_prec) + " is not held by this context");
-    bool ok = (tu == P64 && tg == P64) || (tu == P32 && tg != P64) || (tu == P16 && tg == P16) || (tu == PBF && tg == PBF);
-    if (!ok) return fail(SEM_EINVAL, "unsupported (vector, geometry) precision pair for Ax");
+    if (!held) return fail(SEM_EINVAL, "the requested geometry precision is not held by this context");
+    const int tc = (tu == P64 && !(flags & SEM_AX_FP32_COMPUTE)) ? P64 : P32;
+    if (!ax_supported(tu, tg, tc)) return fail(SEM_EINVAL, "unsupported (vector, geometry, arithmetic) combination for Ax");
     sem_ctx* one[1] = {c};
     Batch b = make_batch(one, 1);
     AxLaunch a;
-    a.src = -1; a.dst = -1; a.ncomp = 1; a.hsel = -1; a.h1 = h1; a.h2 = h2;
-    a.precond = -1; a.pdot = -1; a.gate = -1; a.tu = tu; a.tg = tg;
+    a.src = -1; a.src_vj = 0; a.dst = -1; a.ncomp = 1; a.hsel = -1; a.h1 = h1; a.h2 = h2;
+    a.precond = -1; a.tpc = P64; a.pdot = -1; a.gate = -1; a.tu = tu; a.tg = tg; a.tc = tc;
     a.u_raw = u; a.w_raw = w;
-    launch_ax(b, c->lx, a, c->stream);
+    {
+        ProfScope ps(SEM_PROF_AX_ANY, c->stream);
+        launch_ax(b, c->lx, a, c->stream);
+    }
     if (flags & SEM_ASSEMBLE) launch_dssum(b, -1, 1, tu, -1, w, c->stream);
     return check_hip_last();
 }
@@ -878,15 +949,19 @@ int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stat
         fin(b, FIN_STEP_BEGIN, s);
         vec(b, V_IDV, 1, P64, -1, s);
         // (i) explicit terms: convection, old pressure gradient, BDF/EXT history
-        launch_conv(b, lx, r.conv_m, s);
-        launch_opgrad(b, lx, r.opg_m, F_P, F_GP, s);
+        launch_conv(b, lx, r.conv_m, r.conv_c, s);
+        launch_opgrad(b, lx, r.opg_m, r.opg_c, F_P, F_GP, s);
         vec(b, V_RHS, 3, P64, -1, s);
         launch_dssum(b, F_RHS, 3, P64, -1, nullptr, s);
         // (ii) velocity Helmholtz solves -> u*
         rc = velocity_solve(ctxs, b, s);
         if (rc) return rc;
-        // (iii) pressure increment: A phi = (beta0/dt) dssum(wdiv(u*)), zero-mean rhs
-        launch_wdiv(b, lx, r.div_m, F_US, F_RP, s);
+        // (iii) pressure increment: A phi = (beta0/dt) dssum(wdiv(u*)), zero-mean rhs.
+        // This rhs is the initial residual of the pressure solve (phi = 0): it
+        // is formed in fp64 like every residual check, because the weak
+        // divergence of a nearly divergence-free u* is a small difference of
+        // large element terms whose fp32 rounding would dominate it.
+        launch_wdiv(b, lx, P64, P64, F_US, F_RP, s);
         launch_dssum(b, F_RP, 1, P64, -1, nullptr, s);
         vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_RP);
         fin(b, FIN_MEAN_UNIQUE, s);
@@ -896,7 +971,7 @@ int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stat
         rc = pressure_solve(ctxs, b, s);
         if (rc) return rc;
         // (iv) correction and pressure update, lag rotation, diagnostics
-        launch_opgrad(b, lx, r.opg_m, F_GX, F_GP, s);
+        launch_opgrad(b, lx, r.opg_m, r.opg_c, F_GX, F_GP, s);
         launch_dssum(b, F_GP, 3, P64, -1, nullptr, s);
         vec(b, V_CORRECT, 3, P64, -1, s);
         fin(b, FIN_STEP_END, s);
@@ -966,6 +1041,31 @@ int sem_poisson_solve(sem_ctx* const* ctxs, int n, const void* const* rhs, void*
         }
     }
     return check_hip_last();
+}
+
+int sem_prof_start(int kclass)
+{
+    if (kclass < SEM_PROF_AX_VEL || kclass > SEM_PROF_AX_ANY) return fail(SEM_EINVAL, "unknown profiling class");
+    g_prof.kclass = kclass;
+    g_prof.used = 0;
+    return 0;
+}
+
+int sem_prof_stop(double* total_ms, int64_t* launches)
+{
+    double tot = 0.0;
+    const size_t n = g_prof.used / 2;
+    for (size_t i = 0; i < n; ++i) {
+        HIPCHK(hipEventSynchronize(g_prof.ev[2 * i + 1]));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]));
+        tot += ms;
+    }
+    g_prof.kclass = 0;
+    g_prof.used = 0;
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int64_t)n;
+    return 0;
 }
 
 int sem_get_field(sem_ctx* c, int which, void* dst, int is_host)
@@ -1082,7 +1182,7 @@ int sem_conv(sem_ctx* c, const double* const* u3, double* const* out3)
     }
     sem_ctx* one[1] = {c};
     Batch b = make_batch(one, 1);
-    launch_conv(b, c->lx, c->rs.conv_m, c->stream);
+    launch_conv(b, c->lx, c->rs.conv_m, c->rs.conv_c, c->stream);
     for (int q = 0; q < 3; ++q) {
         HIPCHK(hipMemcpyAsync(out3[q], bnp[q], nb, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(sv[q], c->hdesc.f[F_W64 + q], nb, hipMemcpyDeviceToDevice, c->stream));
@@ -1099,7 +1199,7 @@ int sem_opgrad(sem_ctx* c, const double* p, double* const* out3)
     HIPCHK(hipMemcpyAsync(c->hdesc.f[F_PHI], p, nb, hipMemcpyDeviceToDevice, c->stream));
     sem_ctx* one[1] = {c};
     Batch b = make_batch(one, 1);
-    launch_opgrad(b, c->lx, c->rs.opg_m, F_PHI, F_R64, c->stream);
+    launch_opgrad(b, c->lx, c->rs.opg_m, c->rs.opg_c, F_PHI, F_R64, c->stream);
     for (int q = 0; q < 3; ++q)
         HIPCHK(hipMemcpyAsync(out3[q], c->hdesc.f[F_R64 + q], nb, hipMemcpyDeviceToDevice, c->stream));
     return check_hip_last();
@@ -1115,7 +1215,7 @@ int sem_wdiv(sem_ctx* c, const double* const* v3, double* out)
         HIPCHK(hipMemcpyAsync(c->hdesc.f[F_R64 + q], v3[q], nb, hipMemcpyDeviceToDevice, c->stream));
     sem_ctx* one[1] = {c};
     Batch b = make_batch(one, 1);
-    launch_wdiv(b, c->lx, c->rs.div_m, F_R64, F_PHI, c->stream);
+    launch_wdiv(b, c->lx, c->rs.div_m, c->rs.div_c, F_R64, F_PHI, c->stream);
     HIPCHK(hipMemcpyAsync(out, c->hdesc.f[F_PHI], nb, hipMemcpyDeviceToDevice, c->stream));
     return check_hip_last();
 }

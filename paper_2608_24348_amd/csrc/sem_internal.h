@@ -61,8 +61,7 @@ enum FieldId : int {
     F_PW, F_PWb, F_PWc,
     // GMRES (fp64 basis and iterate; pressure-Ax precision for z and w)
     F_V,                        // (m+1) vectors, stride np
-    F_GZ,                       // Ax input (pressure storage precision)
-    F_GW,                       // Ax output (pressure storage precision)
+    F_GW,                       // operator output of the Arnoldi step (fp64)
     F_GWD,                      // fp64 working vector of the Arnoldi step
     F_GB,                       // rhs (fp64)
     F_GX,                       // iterate (fp64)
@@ -95,8 +94,21 @@ enum ScalarId : int {
     S_KE, S_ENST, S_MAXDIV,
     S_VOL,                      // sum of B (domain volume)
     S_GNSCALE,                  // scale applied by the GMRES normalisation kernel
+    S_GMEAN,                    // unique-node mean of the current Arnoldi operator output
     S_RED,                      // generic finalised reductions (SEM_NRED values)
     NSCALAR = S_RED + 64
+};
+
+// reduction slots (partials[slot][block])
+enum RedSlot : int {
+    R_A = 0,                    // 3 generic per-component slots
+    R_B = 3,                    // 3
+    R_C = 6,                    // 3
+    R_GM = 9,                   // SEM_MAXM + 1 GMRES dot slots
+    R_GN = R_GM + SEM_MAXM + 1, // GMRES norm
+    R_GMEAN,                    // GMRES operator-output unique sum (null-space deflation)
+    R_X0, R_X1, R_X2, R_X3,     // diagnostics and means
+    NRED
 };
 
 // ---------------------------------------------------------------- integer state (int I[])
@@ -119,22 +131,14 @@ enum IntId : int {
     I_GEND,                     // GMRES: cycle end pending (phase 1)
     I_GNORM,                    // GMRES: normalisation of V_J pending
     I_VMAXREF,                  // velocity refinement cycle limit
-    NINT = I_VMAXREF + 8
-};
-
-// reduction slots (partials[slot][block])
-enum RedSlot : int {
-    R_A = 0,                    // 3 generic per-component slots
-    R_B = 3,                    // 3
-    R_C = 6,                    // 3
-    R_GM = 9,                   // SEM_MAXM + 1 GMRES dot slots
-    R_GN = R_GM + SEM_MAXM + 1, // GMRES norm
-    R_X0, R_X1, R_X2, R_X3,     // diagnostics and means
-    NRED
+    I_PCNT,                     // NRED: number of partials the last producer of each slot wrote
+    NINT = I_PCNT + NRED + 8
 };
 
 struct ReqDesc {
     int E, lx, epb, nb;         // elements, points per direction, elements per block, blocks
+    int vepb, nvb;              // elements per point-wise block, point-wise blocks
+    int pstride;                // row stride of the partials: max(nb, nvb)
     int n2, n4, n8;             // shared-node tuple counts (pairs, quads, octets)
     int c2, c4, c8;             // tuple chunk counts
     int prec16;                 // 0 none, 2 fp16, 3 bf16
@@ -145,7 +149,7 @@ struct ReqDesc {
     const int* idx8;            // [n8][8]
     double* S;                  // scalars
     int* I;                     // integer state
-    double* part;               // reduction partials [NRED][nb]
+    double* part;               // reduction partials [NRED][pstride]
     const double* D64;          // D[i*lx+l] (lx*lx), then w[lx], then xi[lx]
     const float* D32;           // same layout in fp32
     void* f[NFIELD];
@@ -163,6 +167,7 @@ struct MeshParams {
 struct Batch {
     int n;                      // requests
     int eb[SEM_MAXB + 1];       // prefix over element blocks
+    int vb[SEM_MAXB + 1];       // prefix over point-wise blocks
     int gs[SEM_MAXB + 1];       // prefix over shared-node chunks
     const ReqDesc* r[SEM_MAXB];
 };
@@ -170,7 +175,19 @@ struct Batch {
 // elements per workgroup of the element kernels (shared by host and device)
 __host__ __device__ constexpr int epb_of(int lx)
 {
-    return lx == 12 ? 4 : lx == 10 ? 5 : lx == 11 ? 2 : (256 / (lx * lx) > 0 ? 256 / (lx * lx) : 1);
+    return lx == 12 ? 2 : lx == 10 ? 5 : lx == 11 ? 2 : (256 / (lx * lx) > 0 ? 256 / (lx * lx) : 1);
+}
+
+// elements per point-wise block: about 1024 blocks per request, at most
+// ~16K points per block (depends only on the request, so a request's
+// reductions are identical alone and in a batch)
+inline int vepb_of(int lx, int E)
+{
+    const int cap = 16384 / (lx * lx * lx) > 0 ? 16384 / (lx * lx * lx) : 1;
+    int v = E / 1024;
+    if (v < 1) v = 1;
+    if (v > cap) v = cap;
+    return v;
 }
 
 // locate the request of a flat block index in a prefix table
@@ -191,13 +208,15 @@ namespace semk {
 
 struct AxLaunch {
     int src, dst;               // field ids (components add blockIdx.y)
+    int src_vj;                 // nonzero: input is GMRES basis vector V_J (J read on the device)
     int ncomp;                  // 1 or 3
     int hsel;                   // S index of (h1,h2) or -1 to use h1,h2 below
     double h1, h2;
     int precond;                // field id of the inverse diagonal applied to src on load, or -1
+    int tpc;                    // PrecId of that diagonal (P64 or P32)
     int pdot;                   // reduction slot for sum(u*w) over local points, or -1
     int gate;                   // I index checked per component (nonzero = run), or -1
-    int tu, tg;                 // PrecId of vectors and of geometry
+    int tu, tg, tc;             // PrecId of vectors, geometry and arithmetic
     const void* u_raw;          // direct pointers (standalone sem_ax), used when src < 0
     void* w_raw;
 };
@@ -213,9 +232,9 @@ void launch_geo_cast(const Batch& b, int lx, int want32, int want16, hipStream_t
 void launch_init_fields(const Batch& b, int lx, int init, const MeshParams& mp, hipStream_t s);
 
 // SEM operators (output fp64)
-void launch_conv(const Batch& b, int lx, int tm, hipStream_t s);
-void launch_opgrad(const Batch& b, int lx, int tm, int src, int dst, hipStream_t s);
-void launch_wdiv(const Batch& b, int lx, int tm, int src, int dst, hipStream_t s);
+void launch_conv(const Batch& b, int lx, int tm, int tc, hipStream_t s);
+void launch_opgrad(const Batch& b, int lx, int tm, int tc, int src, int dst, hipStream_t s);
+void launch_wdiv(const Batch& b, int lx, int tm, int tc, int src, int dst, hipStream_t s);
 void launch_diagnostics(const Batch& b, int lx, hipStream_t s);
 
 // point-wise / reduction / scalar kernels
@@ -233,9 +252,8 @@ enum VecOp : int {
     V_SUB_MEAN,       // f0 = scale*(f0 - S_MEAN)   (scale = S[f1] or 1 when f1 < 0)
     V_COPY,           // f1 = f0 (fp64)
     V_ZERO,           // f0 = 0 (fp64)
-    V_GM_PRECOND,     // GZ = V_J * IDP
-    V_GM_DOTS,        // partials (V_i, GW) -> R_GM+i, i <= J
-    V_GM_UPD_DOTS,    // GWD = GW - sum GHC_i V_i ; partials (V_i, GWD) -> R_GM+i
+    V_GM_DOTS,        // partials (V_i, GW) -> R_GM+i, i <= J, and sum(GW/mult) -> R_GMEAN
+    V_GM_UPD_DOTS,    // GWD = GW - S_GMEAN - sum GHC_i V_i ; partials (V_i, GWD) -> R_GM+i
     V_GM_UPD_NORM,    // GWD -= sum GH2_i V_i ; partial |GWD|^2 -> R_GN
     V_GM_NORMALIZE,   // V_J = GWD * S_GNSCALE
     V_GM_XUPD,        // GX += IDP * sum_{i<jend} y_i V_i

@@ -22,6 +22,7 @@ X_ALL = 0xF
 INIT_ZERO, INIT_TGV3D, INIT_TGV2D = 0, 1, 2
 MODE_OPERATOR, MODE_POISSON, MODE_FLUID = 0, 1, 2
 ASSEMBLE = 1
+AX_FP32_COMPUTE = 2
 F_U, F_P, F_ULAG1, F_ULAG2, F_BNLAG1, F_BNLAG2 = 0, 3, 4, 7, 10, 13
 F_MASS, F_BSUM, F_G, F_M, F_DIAG_A = 16, 17, 18, 24, 33
 
@@ -73,7 +74,9 @@ class Diag(C.Structure):
 
 EXPORTS = ["sem_setup", "sem_workspace_bytes", "sem_bind", "sem_ax", "sem_dssum", "sem_fluid_step",
            "sem_poisson_solve", "sem_get_field", "sem_set_field", "sem_set_clock", "sem_diagnostics",
-           "sem_conv", "sem_opgrad", "sem_wdiv", "sem_sizes", "sem_destroy", "sem_strerror", "sem_last_error"]
+           "sem_conv", "sem_opgrad", "sem_wdiv", "sem_sizes", "sem_destroy", "sem_strerror", "sem_last_error",
+           "sem_prof_start", "sem_prof_stop"]
+PROF_AX_VEL, PROF_AX_PRES, PROF_GM_DOTS, PROF_GM_UPD_DOTS, PROF_GM_UPD_NORM, PROF_DSSUM_PRES, PROF_AX_ANY = range(1, 8)
 
 _lib = None
 
@@ -107,6 +110,8 @@ def load():
     L.sem_strerror.restype = C.c_char_p
     L.sem_strerror.argtypes = [C.c_int]
     L.sem_last_error.restype = C.c_char_p
+    L.sem_prof_start.argtypes = [C.c_int]
+    L.sem_prof_stop.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     _lib = L
     return L
 
@@ -134,31 +139,44 @@ def precision(rp=FP64, blocks=None, kernels=None, exceptions=None):
     return p
 
 
-def tier(name):
-    """Named precision presets.
+TIERS = ("fp64", "fp32b", "fp32b-p32", "fp32b+fp16", "fp32b+bf16", "fp32b+fp16p", "fp32b+fp16all", "fp32b+bf16all")
 
-    fp64          global fp64 (the paper's A-0)
-    fp32b         rp = fp32, every block fp32, state/GMRES/residuals/reductions fp64 (B-0 with fp64 accumulation)
-    fp32b+fp16    fp32b with fp16-stored geometry for the velocity Helmholtz operator and opgrad (B-6 style)
+
+def tier(name):
+    """Named precision presets (the paper's Table 2 configurations on this path).
+
+    fp64          global fp64 (A-0)
+    fp32b         rp = fp32 storage; SEM operators and velocity solver fp32;
+                  pressure operator fp64 arithmetic on fp32-stored geometry and
+                  Jacobi diagonal (B-4 "pressure-only fp64 compute"); BDF/EXT
+                  state, GMRES basis/orthogonalisation, residual checks and the
+                  global reduction stage fp64
+    fp32b-p32     fp32b with fp32 arithmetic in the pressure operator too (B-0
+                  with fp64 accumulation); with Jacobi preconditioning its GMRES
+                  cannot meet an absolute 1e-8 on large meshes
+    fp32b+fp16    fp32b with fp16-stored geometry for the velocity Helmholtz
+                  operator and opgrad (B-6 style)
     fp32b+bf16    same with bf16
     fp32b+fp16p   fp32b with fp16-stored geometry for the pressure operator (B-7)
-    fp32b+fp16all fp32b with fp16 geometry for both operators and opgrad (operator microbenchmarks)
+    fp32b+fp16all / fp32b+bf16all  16-bit geometry for both operators and
+                  opgrad (operator microbenchmarks)
     """
     if name == "fp64":
         return precision(FP64)
-    if name == "fp32b":
-        return precision(FP32)
-    h = {"fp32b+fp16": FP16, "fp32b+bf16": BF16, "fp32b+fp16p": FP16, "fp32b+fp16all": FP16,
-         "fp32b+bf16all": BF16}.get(name)
-    if h is None:
+    h = {"fp32b": None, "fp32b-p32": None, "fp32b+fp16": FP16, "fp32b+bf16": BF16, "fp32b+fp16p": FP16,
+         "fp32b+fp16all": FP16, "fp32b+bf16all": BF16}
+    if name not in h:
         raise ValueError("unknown tier %r" % name)
+    blocks = {BLOCK_SEM: (FP32, FP32, FP32), BLOCK_VEL: (FP32, FP32, FP32), BLOCK_PRES: (FP64, FP64, FP32)}
+    if name == "fp32b-p32":
+        blocks[BLOCK_PRES] = (FP32, FP32, FP32)
     ks = {}
     if name in ("fp32b+fp16", "fp32b+bf16", "fp32b+fp16all", "fp32b+bf16all"):
-        ks[K_AX_VEL] = (FP32, FP32, h)
-        ks[K_OPGRAD] = (FP32, FP32, h)
+        ks[K_AX_VEL] = (FP32, FP32, h[name])
+        ks[K_OPGRAD] = (FP32, FP32, h[name])
     if name in ("fp32b+fp16p", "fp32b+fp16all", "fp32b+bf16all"):
-        ks[K_AX_PRES] = (FP32, FP32, h)
-    return precision(FP32, kernels=ks)
+        ks[K_AX_PRES] = (FP64, FP64, h[name])
+    return precision(FP32, blocks=blocks, kernels=ks)
 
 
 def mesh_desc(nel, order, lo=(-math.pi,) * 3, hi=(math.pi,) * 3, amp=0.0, phase=None):
@@ -257,11 +275,12 @@ class Context:
             pass
 
     # ---- operators on torch device tensors
-    def ax(self, u, w, h1=1.0, h2=0.0, geom=INHERIT, assemble=False):
+    def ax(self, u, w, h1=1.0, h2=0.0, geom=INHERIT, assemble=False, fp32_compute=False):
         assert u.is_cuda and w.is_cuda and u.numel() == self.np and w.numel() == self.np and u.dtype == w.dtype
         assert u.is_contiguous() and w.is_contiguous()
+        flags = (ASSEMBLE if assemble else 0) | (AX_FP32_COMPUTE if fp32_compute else 0)
         _check(self.L.sem_ax(self.h, C.c_void_p(u.data_ptr()), C.c_void_p(w.data_ptr()), float(h1), float(h2),
-                             prec_of(u), int(geom), ASSEMBLE if assemble else 0))
+                             prec_of(u), int(geom), flags))
         return w
 
     def dssum(self, u):
@@ -330,6 +349,18 @@ def fluid_step(ctxs, nsteps=1):
     st = (StepStats * (n * max(nsteps, 1)))()
     _check(load().sem_fluid_step(arr, n, int(nsteps), st))
     return [[_stats_dict(st[i * nsteps + k]) for k in range(nsteps)] for i in range(n)]
+
+
+def prof_start(kclass):
+    """Arm HIP-event timing of one kernel class (see sem.h SEM_PROF_*)."""
+    _check(load().sem_prof_start(int(kclass)))
+
+
+def prof_stop():
+    """Return (total kernel milliseconds, number of launches) since prof_start."""
+    ms, n = C.c_double(), C.c_int64()
+    _check(load().sem_prof_stop(C.byref(ms), C.byref(n)))
+    return ms.value, n.value
 
 
 def poisson_solve(ctxs, rhs, sol):

@@ -108,6 +108,8 @@ def _abs_op_bound(m, u, h1, h2):
 
 @pytest.mark.parametrize("tier,buf,eps_geo,eps_vec", [
     ("fp32b", "float32", 2 ** -24, 2 ** -24),
+    ("fp32b", "float64", 2 ** -24, 0.0),
+    ("fp32b+fp16all", "float64", 2 ** -11, 0.0),
     ("fp32b+fp16all", "float32", 2 ** -11, 2 ** -24),
     ("fp32b+bf16all", "float32", 2 ** -8, 2 ** -24),
     ("fp32b+fp16all", "float16", 2 ** -11, 2 ** -11),
@@ -124,14 +126,12 @@ def test_ax_reduced_precision_within_rounding_bound(sem, tier, buf, eps_geo, eps
     h1, h2 = 1.0, 0.0
     ref = m.ax(u_rounded, h1, h2)
     w = torch.empty(c.np, dtype=dt, device="cuda:0")
-    geom = {"float32": sem.INHERIT}.get(buf, sem.INHERIT)
-    if tier != "fp32b":
-        geom = sem.FP16 if "fp16" in tier else sem.BF16
+    geom = sem.FP32 if tier == "fp32b" else (sem.FP16 if "fp16" in tier else sem.BF16)
     c.ax(ut, w, h1, h2, geom=geom)
     got = w.double().cpu().numpy()
     lx = N + 1
     k = 2 * lx + 8
-    u32 = 2 ** -24
+    u32 = 2 ** -24 if buf != "float64" else 2 ** -53  # fp64 vectors run fp64 arithmetic
     gamma = k * u32 / (1 - k * u32)
     bound = (gamma + 2 * eps_geo + eps_vec) * _abs_op_bound(m, u_rounded, h1, h2)
     err = np.abs(got - ref)
@@ -224,3 +224,24 @@ def test_batched_step_is_bitwise_equal_to_alone(sem):
         assert [s["pit"] for s in mix[i]] == [s["pit"] for s in st]
         assert np.array_equal(c.velocity(), u)
         assert np.array_equal(c.pressure(), p)
+
+
+@pytest.mark.parametrize("tier", ["fp32b", "fp32b+fp16", "fp32b+bf16"])
+def test_mixed_tier_c1_energy_and_enstrophy_error(sem, tier):
+    """Mixed tiers against the FP64 oracle on C1 (8^3, N=7, 10 steps): the error
+    metrics of the paper (Sec. 4.2 equations) stay inside the stated bounds:
+    fp32b e_E,max <= 1e-4 %, e_Omega,max <= 1e-3 %; 16-bit geometry tiers
+    e_E,max <= 1e-2 %, e_Omega,max <= 1e-1 %."""
+    from oracle import e_max
+    nel, N, nu, dt = (8, 8, 8), 7, 1 / 1600, 1e-3
+    c = _ctx(sem, nel, N, tier=tier, nu=nu, dt=dt)
+    m = OracleMesh(nel, N)
+    f = OracleFluid(m, nu, dt, init=INIT_TGV3D)
+    gst = sem.fluid_step([c], 10)[0]
+    ost = [f.step() for _ in range(10)]
+    assert all(s["status"] == 0 for s in gst)
+    eE = e_max([s["ke"] for s in gst], [s["ke"] for s in ost])
+    eO = e_max([s["enst"] for s in gst], [s["enst"] for s in ost])
+    print(tier, "e_E,max %.3e %%  e_Omega,max %.3e %%" % (eE, eO), "pit", [s["pit"] for s in gst])
+    lim = (1e-4, 1e-3) if tier == "fp32b" else (1e-2, 1e-1)
+    assert eE <= lim[0] and eO <= lim[1]

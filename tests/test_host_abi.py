@@ -1,0 +1,98 @@
+"""Host-side checks of libsem that need no GPU: the library loads, exports
+every symbol include/sem.h declares, and sem_setup validates descriptors and
+precision policies and sizes workspaces without touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2608_24348_amd import sem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "sem.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|void|const char\*)\s+(sem_[a-z_0-9]+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = sem.load()
+    names = _declared_symbols()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) <= set(sem.EXPORTS)
+
+
+def test_strerror_and_status_codes():
+    L = sem.load()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.sem_strerror(code).decode()
+
+
+@pytest.mark.parametrize("nel,N", [((1, 1, 1), 2), ((2, 3, 4), 3), ((8, 8, 8), 7), ((4, 4, 4), 11), ((3, 5, 7), 9),
+                                   ((32, 32, 32), 7), ((16, 16, 16), 11), ((24, 24, 24), 5), ((1, 1, 64), 4)])
+@pytest.mark.parametrize("tier", ["fp64", "fp32b", "fp32b+fp16"])
+def test_setup_sizes_and_layout(nel, N, tier):
+    c = sem.Context(sem.mesh_desc(nel, N), sem.flow_desc(), sem.tier(tier), bind=False)
+    E = nel[0] * nel[1] * nel[2]
+    assert c.E == E and c.lx == N + 1
+    assert c.np == E * (N + 1) ** 3
+    assert c.nglob == E * N ** 3
+    # fluid workspace holds at least ~40 fp64 fields per point
+    assert c.bytes >= 40 * 8 * c.np
+    op = sem.Context(sem.mesh_desc(nel, N), sem.flow_desc(mode=sem.MODE_OPERATOR), sem.tier(tier), bind=False)
+    assert op.bytes < c.bytes
+
+
+@pytest.mark.parametrize("bad", [
+    dict(order=1), dict(order=12), dict(nel=(0, 2, 2)),
+    dict(amp=0.1, nel=(3, 2, 2)), dict(amp=0.3),
+])
+def test_setup_rejects_bad_meshes(bad):
+    nel = bad.get("nel", (2, 2, 2))
+    with pytest.raises(sem.SemError) as e:
+        sem.Context(sem.mesh_desc(nel, bad.get("order", 4), amp=bad.get("amp", 0.0)), sem.flow_desc(), sem.tier("fp64"),
+                    bind=False)
+    assert e.value.code == -1
+
+
+def test_policy_rules():
+    md, fd = sem.mesh_desc((2, 2, 2), 4), sem.flow_desc()
+    # rp = fp32 without the fp64 exceptions is rejected
+    with pytest.raises(sem.SemError):
+        sem.Context(md, fd, sem.precision(sem.FP32, exceptions=0), bind=False)
+    # storage above rp is rejected
+    with pytest.raises(sem.SemError):
+        sem.Context(md, fd, sem.precision(sem.FP32, blocks={sem.BLOCK_VEL: (sem.FP64, sem.FP64, sem.FP64)}), bind=False)
+    # fp64 compute on fp32 storage is the paper's Group B pattern and is accepted for the pressure block
+    sem.Context(md, fd, sem.precision(sem.FP32, blocks={sem.BLOCK_PRES: (sem.FP64, sem.FP64, sem.FP32)}), bind=False)
+    # 16-bit arithmetic is not a kernel; 16-bit storage is
+    with pytest.raises(sem.SemError):
+        sem.Context(md, fd, sem.precision(sem.FP32, kernels={sem.K_AX_VEL: (sem.FP16, sem.FP32, sem.FP16)}), bind=False)
+    sem.Context(md, fd, sem.precision(sem.FP32, kernels={sem.K_AX_VEL: (sem.FP32, sem.FP32, sem.FP16)}), bind=False)
+    # two 16-bit formats in one context are rejected
+    with pytest.raises(sem.SemError):
+        sem.Context(md, fd, sem.precision(sem.FP32, kernels={sem.K_AX_VEL: (sem.FP32, sem.FP32, sem.FP16),
+                                                             sem.K_OPGRAD: (sem.FP32, sem.FP32, sem.BF16)}), bind=False)
+    # velocity vectors below fp32 are rejected
+    with pytest.raises(sem.SemError):
+        sem.Context(md, fd, sem.precision(sem.FP32, blocks={sem.BLOCK_VEL: (sem.FP32, sem.FP32, sem.FP16)}), bind=False)
+    for t in sem.TIERS:
+        sem.Context(md, fd, sem.tier(t), bind=False)
+
+
+def test_flow_validation():
+    md = sem.mesh_desc((2, 2, 2), 4)
+    for kw in (dict(nu=0.0), dict(dt=-1.0), dict(torder=4), dict(restart=31), dict(vel_tol=0.0), dict(max_refine=0)):
+        with pytest.raises(sem.SemError):
+            sem.Context(md, sem.flow_desc(**kw), sem.tier("fp64"), bind=False)
+
+
+def test_unbound_context_calls_fail_cleanly():
+    c = sem.Context(sem.mesh_desc((2, 2, 2), 3), sem.flow_desc(), sem.tier("fp64"), bind=False)
+    L = sem.load()
+    assert L.sem_dssum(c.h, C.c_void_p(1), 0) == -6
+    assert L.sem_ax(c.h, C.c_void_p(1), C.c_void_p(1), 1.0, 0.0, 0, -1, 0) == -6
