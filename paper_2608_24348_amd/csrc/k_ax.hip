@@ -10,6 +10,14 @@
 // type C are template parameters; 16-bit geometry carries a per-element scale.
 #include "k_common.h"
 
+#include <type_traits>
+
+// register budget (bytes per thread) under which all six geometric factors of
+// a column are loaded before the k-walk instead of one layer ahead
+#ifndef SEM_AX_GALL_BYTES
+#define SEM_AX_GALL_BYTES 384
+#endif
+
 namespace semk {
 
 template <int LX> struct Epb {
@@ -22,23 +30,25 @@ template <int LX> struct Nthr {
 
 template <typename TG, typename C> struct GeoLoad {
     // geometry value with optional element scale (16-bit storage)
-    static __device__ __forceinline__ C ld(const TG* p, C scale) { return to<C>(*p) * scale; }
+    static __device__ __forceinline__ C ld(const SEM_GLOBAL TG* p, C scale) { return to<C>(ldg(p)) * scale; }
 };
 template <typename C> struct GeoLoad<double, C> {
-    static __device__ __forceinline__ C ld(const double* p, C) { return (C)*p; }
+    static __device__ __forceinline__ C ld(const SEM_GLOBAL double* p, C) { return (C)*p; }
 };
 template <typename C> struct GeoLoad<float, C> {
-    static __device__ __forceinline__ C ld(const float* p, C) { return (C)*p; }
+    static __device__ __forceinline__ C ld(const SEM_GLOBAL float* p, C) { return (C)*p; }
 };
 
-template <typename TG> __device__ __forceinline__ int gfield() { return F_G16; }
-template <> __device__ __forceinline__ int gfield<double>() { return F_G64; }
-template <> __device__ __forceinline__ int gfield<float>() { return F_G32; }
+template <typename TG> __device__ __forceinline__ int gfield_id() { return F_G16; }
+template <> __device__ __forceinline__ int gfield_id<double>() { return F_G64; }
+template <> __device__ __forceinline__ int gfield_id<float>() { return F_G32; }
 template <typename TG> __device__ __forceinline__ int bfield() { return F_B16; }
 template <> __device__ __forceinline__ int bfield<double>() { return F_B64; }
 template <> __device__ __forceinline__ int bfield<float>() { return F_B32; }
 
-template <int LX, typename TU, typename TG, typename C>
+// PC: Jacobi scaling of the input on load (0 none, 1 fp64 diagonal, 2 fp32),
+// a template parameter so the load stays unconditional
+template <int LX, typename TU, typename TG, typename C, int PC>
 __global__ void __launch_bounds__(Nthr<LX>::v)
 ax_kernel(Batch bt, AxLaunch a)
 {
@@ -66,58 +76,80 @@ ax_kernel(Batch bt, AxLaunch a)
     const bool live = el < EPB && e < R->E;
 
     for (int q = t; q < L2; q += blockDim.x) {
-        if constexpr (sizeof(C) == 8) sD[q] = (C)R->D64[q];
-        else sD[q] = (C)R->D32[q];
+        if constexpr (sizeof(C) == 8) sD[q] = (C)gp(R->D64)[q];
+        else sD[q] = (C)gp(R->D32)[q];
     }
 
-    const TU* u = a.src_vj ? (const TU*)R->f[F_V] + (long long)R->I[I_GJ] * R->np
-                           : a.src >= 0 ? (const TU*)R->f[a.src + comp] : (const TU*)a.u_raw;
-    TU* w = a.dst >= 0 ? (TU*)R->f[a.dst + comp] : (TU*)a.w_raw;
-    const TG* G = (const TG*)R->f[gfield<TG>()];
-    const TG* Bm = (const TG*)R->f[bfield<TG>()];
-    const double* pc64 = a.precond >= 0 && a.tpc == P64 ? (const double*)R->f[a.precond] : nullptr;
-    const float* pc32 = a.precond >= 0 && a.tpc == P32 ? (const float*)R->f[a.precond] : nullptr;
+    const SEM_GLOBAL TU* u = a.src_vj ? gfield<TU>(R, F_V) + (long long)gp(R->I)[I_GJ] * R->np
+                                      : a.src >= 0 ? gfield<TU>(R, a.src + comp) : gp((const TU*)a.u_raw);
+    SEM_GLOBAL TU* w = a.dst >= 0 ? gfieldw<TU>(R, a.dst + comp) : gp((TU*)a.w_raw);
+    const SEM_GLOBAL TG* G = gfield<TG>(R, gfield_id<TG>());
+    const SEM_GLOBAL TG* Bm = gfield<TG>(R, bfield<TG>());
+    using TPC = typename std::conditional<PC == 2, float, double>::type;
+    const SEM_GLOBAL TPC* pcv = PC ? gfield<TPC>(R, a.precond) : nullptr;
     C h1, h2;
-    if (a.hsel >= 0) { h1 = (C)R->S[a.hsel]; h2 = (C)R->S[a.hsel + 1]; }
+    if (a.hsel >= 0) { h1 = (C)gp(R->S)[a.hsel]; h2 = (C)gp(R->S)[a.hsel + 1]; }
     else { h1 = (C)a.h1; h2 = (C)a.h2; }
     C gsc = (C)1, bsc = (C)1;
     const int ee = live ? e : 0;
+    const bool helm = h2 != (C)0;
     if (sizeof(TG) == 2) {
-        const float* sc = (const float*)R->f[F_GSC];
+        const SEM_GLOBAL float* sc = gfield<float>(R, F_GSC);
         gsc = (C)sc[ee];
         bsc = (C)sc[R->E + ee];
     }
 
-    // The column's global loads are issued ahead of the k-walk: all of u and
-    // B up front, and the six G_ab either all up front (when they fit in
-    // registers) or one layer ahead, so the walk itself only waits on LDS.
-#ifndef SEM_AX_GALL_BYTES
-#define SEM_AX_GALL_BYTES 384
-#endif
-    constexpr bool GALL = 6 * LX * sizeof(C) <= SEM_AX_GALL_BYTES;
+    // The column's global loads are issued ahead of the k-walk and kept in
+    // their storage type (converted only where they are used): u first, then
+    // the six G_ab one layer ahead (all up front for fp32 arithmetic on
+    // short columns), B at the end.  The thread's D rows/columns live in
+    // registers; only the k-uniform row D[k][.] is read from LDS (broadcast).
+    constexpr bool GALL = sizeof(C) == 4 && 6 * LX * 4 <= SEM_AX_GALL_BYTES;
     constexpr int NG = GALL ? LX : 2;
-    C ureg[LX], wacc[LX], bcol[LX], g6[6][NG];
+    TU uraw[LX];
+    TG graw[6][NG];
+    TG braw[LX];
+    TPC praw[PC ? LX : 1];
+    C ureg[LX], wacc[LX];
     const long long ebase = (long long)ee * L3;
     const long long gbase = (long long)ee * 6 * L3;
-    const bool helm = h2 != (C)0;
+    // Loads are unconditional: threads without an element (block padding or
+    // past the last element) address element 0 (ee == 0), which always
+    // exists, and never store.  Guarding the loads would turn each into a
+    // divergent branch whose join waits for it.
 #pragma unroll
-    for (int k = 0; k < LX; ++k) {
-        const int p = k * L2 + ij;
-        C v = (C)0;
-        if (live) {
-            v = to<C>(u[ebase + p]);
-            if (pc64) v *= (C)pc64[ebase + p];
-            else if (pc32) v *= (C)pc32[ebase + p];
-        }
-        ureg[k] = v;
-        wacc[k] = (C)0;
-        if (GALL) bcol[k] = (live && helm) ? GeoLoad<TG, C>::ld(Bm + ebase + p, bsc) : (C)0;
+    for (int k = 0; k < LX; ++k) uraw[k] = ldg(u + ebase + k * L2 + ij);
+    if constexpr (PC != 0) {
+#pragma unroll
+        for (int k = 0; k < LX; ++k) praw[k] = ldg(pcv + ebase + k * L2 + ij);
+    }
+    if (helm) {
+#pragma unroll
+        for (int k = 0; k < LX; ++k) braw[k] = ldg(Bm + ebase + k * L2 + ij);
+    }
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
         if (GALL || k == 0) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) g6[q][GALL ? k : 0] = live ? GeoLoad<TG, C>::ld(G + gbase + q * L3 + p, gsc) : (C)0;
+            for (int q = 0; q < 6; ++q) graw[q][k] = ldg(G + gbase + q * L3 + k * L2 + ij);
         }
     }
-    __syncthreads();
+    block_sync_lds();  // sD ready
+    C Di[LX], Dj[LX], DTi[LX], DTj[LX];
+#pragma unroll
+    for (int l = 0; l < LX; ++l) {
+        Di[l] = sD[i * LX + l];
+        Dj[l] = sD[j * LX + l];
+        DTi[l] = sD[l * LX + i];
+        DTj[l] = sD[l * LX + j];
+    }
+#pragma unroll
+    for (int k = 0; k < LX; ++k) {
+        C v = to<C>(uraw[k]);
+        if constexpr (PC != 0) v *= (C)praw[k];
+        ureg[k] = v;
+        wacc[k] = (C)0;
+    }
 
 #pragma unroll
     for (int k = 0; k < LX; ++k) {
@@ -125,32 +157,35 @@ ax_kernel(Batch bt, AxLaunch a)
         if (!GALL && k + 1 < LX) {
             const int pn = (k + 1) * L2 + ij;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) g6[q][(k + 1) & 1] = live ? GeoLoad<TG, C>::ld(G + gbase + q * L3 + pn, gsc) : (C)0;
+            for (int q = 0; q < 6; ++q) graw[q][(k + 1) & 1] = ldg(G + gbase + q * L3 + pn);
         }
         if (el < EPB) su[el][ij] = ureg[k];
-        __syncthreads();
+        block_sync_lds();
         C ur = 0, us = 0, ut = 0;
         if (el < EPB) {
 #pragma unroll
             for (int l = 0; l < LX; ++l) {
-                ur += sD[i * LX + l] * su[el][j * LX + l];
-                us += sD[j * LX + l] * su[el][l * LX + i];
+                ur += Di[l] * su[el][j * LX + l];
+                us += Dj[l] * su[el][l * LX + i];
                 ut += sD[k * LX + l] * ureg[l];
             }
         }
-        const C wr = g6[0][kc] * ur + g6[1][kc] * us + g6[2][kc] * ut;
-        const C ws = g6[1][kc] * ur + g6[3][kc] * us + g6[4][kc] * ut;
-        const C wt = g6[2][kc] * ur + g6[4][kc] * us + g6[5][kc] * ut;
+        C g6[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) g6[q] = to<C>(graw[q][kc]) * gsc;
+        const C wr = g6[0] * ur + g6[1] * us + g6[2] * ut;
+        const C ws = g6[1] * ur + g6[3] * us + g6[4] * ut;
+        const C wt = g6[2] * ur + g6[4] * us + g6[5] * ut;
         if (el < EPB) { sr[el][ij] = wr; ss[el][ij] = ws; }
 #pragma unroll
         for (int l = 0; l < LX; ++l) wacc[l] += sD[k * LX + l] * wt;
-        __syncthreads();
+        block_sync_lds();
         if (el < EPB) {
             C acc = 0;
 #pragma unroll
             for (int l = 0; l < LX; ++l) {
-                acc += sD[l * LX + i] * sr[el][j * LX + l];
-                acc += sD[l * LX + j] * ss[el][l * LX + i];
+                acc += DTi[l] * sr[el][j * LX + l];
+                acc += DTj[l] * ss[el][l * LX + i];
             }
             wacc[k] += acc;
         }
@@ -161,10 +196,10 @@ ax_kernel(Batch bt, AxLaunch a)
 #pragma unroll
         for (int k = 0; k < LX; ++k) {
             const int p = k * L2 + ij;
-            const C bk = GALL ? bcol[k] : (helm ? GeoLoad<TG, C>::ld(Bm + ebase + p, bsc) : (C)0);
+            const C bk = helm ? to<C>(braw[k]) * bsc : (C)0;
             const C wv = h1 * wacc[k] + h2 * bk * ureg[k];
             const TU ws = to<TU>(wv);
-            w[ebase + p] = ws;
+            stg(w + ebase + p, ws);
             if (a.pdot >= 0) dot += (double)ureg[k] * (double)to<C>(ws);
         }
     }
@@ -172,8 +207,8 @@ ax_kernel(Batch bt, AxLaunch a)
         double v[1] = {dot};
         block_sum<double, 1>(v, red);
         if (t == 0) {
-            R->part[(long long)(a.pdot + comp) * R->pstride + blk] = v[0];
-            if (blk == 0) R->I[I_PCNT + a.pdot + comp] = R->nb;
+            gp(R->part)[(long long)(a.pdot + comp) * R->pstride + blk] = v[0];
+            if (blk == 0) gp(R->I)[I_PCNT + a.pdot + comp] = R->nb;
         }
     }
 }
@@ -182,7 +217,18 @@ template <int LX, typename TU, typename TG, typename C>
 static void ax_go(const Batch& b, const AxLaunch& a, hipStream_t s)
 {
     dim3 grid(b.eb[b.n], a.ncomp);
-    hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+    if constexpr (sizeof(TU) == 8) {
+        // only the pressure operator (fp64 basis vectors) takes a Jacobi scaling
+        if (a.precond >= 0 && a.tpc == P64) {
+            hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 1>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+            return;
+        }
+        if (a.precond >= 0) {
+            hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 2>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
 }
 
 // supported (vector, geometry, arithmetic) instantiations; ax_supported()

@@ -5,6 +5,53 @@
 
 namespace semk {
 
+// Field pointers are read from the request descriptor in device memory, so
+// the compiler cannot infer their address space and would emit FLAT
+// accesses (which also count against the LDS wait counter and so stall the
+// LDS-heavy contractions on every outstanding HBM load).  Every kernel
+// converts them to global-address-space pointers first.
+#define SEM_GLOBAL __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ SEM_GLOBAL T* gp(T* p) { return (SEM_GLOBAL T*)p; }
+template <typename T> __device__ __forceinline__ const SEM_GLOBAL T* gp(const T* p) { return (const SEM_GLOBAL T*)p; }
+template <typename T> __device__ __forceinline__ const SEM_GLOBAL T* gfield(const ReqDesc* R, int id)
+{
+    return (const SEM_GLOBAL T*)R->f[id];
+}
+template <typename T> __device__ __forceinline__ SEM_GLOBAL T* gfieldw(const ReqDesc* R, int id)
+{
+    return (SEM_GLOBAL T*)R->f[id];
+}
+
+// Workgroup barrier for LDS producer/consumer hand-offs only: waits for this
+// wave's LDS operations (lgkmcnt) but not for its outstanding global loads,
+// so prefetched HBM data stays in flight across the barrier (__syncthreads()
+// would also drain vmcnt).  Global data that other waves must see still goes
+// through __syncthreads().
+__device__ __forceinline__ void block_sync_lds()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// loads and stores through global pointers (16-bit types move as raw bits)
+template <typename T> __device__ __forceinline__ T ldg(const SEM_GLOBAL T* p) { return *p; }
+template <> __device__ __forceinline__ __half ldg<__half>(const SEM_GLOBAL __half* p)
+{
+    return __ushort_as_half(*(const SEM_GLOBAL unsigned short*)p);
+}
+template <> __device__ __forceinline__ __hip_bfloat16 ldg<__hip_bfloat16>(const SEM_GLOBAL __hip_bfloat16* p)
+{
+    return __ushort_as_bfloat16(*(const SEM_GLOBAL unsigned short*)p);
+}
+template <typename T> __device__ __forceinline__ void stg(SEM_GLOBAL T* p, T v) { *p = v; }
+template <> __device__ __forceinline__ void stg<__half>(SEM_GLOBAL __half* p, __half v)
+{
+    *(SEM_GLOBAL unsigned short*)p = __half_as_ushort(v);
+}
+template <> __device__ __forceinline__ void stg<__hip_bfloat16>(SEM_GLOBAL __hip_bfloat16* p, __hip_bfloat16 v)
+{
+    *(SEM_GLOBAL unsigned short*)p = __bfloat16_as_ushort(v);
+}
+
 template <typename T> struct TypeOf;
 template <> struct TypeOf<double> { static constexpr int id = P64; };
 template <> struct TypeOf<float> { static constexpr int id = P32; };
@@ -85,7 +132,7 @@ template <typename A, int NV> __device__ __forceinline__ void block_sum(A (&v)[N
 
 __device__ __forceinline__ bool gate_ok(const ReqDesc* R, int gate)
 {
-    return gate < 0 || R->I[gate] != 0;
+    return gate < 0 || gp(R->I)[gate] != 0;
 }
 
 }  // namespace semk

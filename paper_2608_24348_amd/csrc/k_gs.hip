@@ -11,17 +11,17 @@
 namespace semk {
 
 template <typename T, typename A, int M>
-__device__ __forceinline__ void gs_tuple(T* u, const int* idx)
+__device__ __forceinline__ void gs_tuple(SEM_GLOBAL T* u, const SEM_GLOBAL int* idx)
 {
     int id[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) id[q] = idx[q];
     A s = (A)0;
 #pragma unroll
-    for (int q = 0; q < M; ++q) s += to<A>(u[id[q]]);
+    for (int q = 0; q < M; ++q) s += to<A>(ldg(u + id[q]));
     const T v = to<T>(s);
 #pragma unroll
-    for (int q = 0; q < M; ++q) u[id[q]] = v;
+    for (int q = 0; q < M; ++q) stg(u + id[q], v);
 }
 
 template <typename T, typename A>
@@ -33,23 +33,23 @@ dssum_kernel(Batch bt, int field, int gate, void* raw)
     const ReqDesc* R = bt.r[ri];
     const int comp = blockIdx.y;
     if (!gate_ok(R, gate < 0 ? -1 : gate + comp)) return;
-    T* u = field >= 0 ? (T*)R->f[field + comp] : (T*)raw;
+    SEM_GLOBAL T* u = field >= 0 ? gfieldw<T>(R, field + comp) : gp((T*)raw);
     int c = g - bt.gs[ri];
     const int t = threadIdx.x;
     if (c < R->c2) {
         int tup = c * SEM_GS_CHUNK + t;
-        if (tup < R->n2) gs_tuple<T, A, 2>(u, R->idx2 + 2LL * tup);
+        if (tup < R->n2) gs_tuple<T, A, 2>(u, gp(R->idx2) + 2LL * tup);
         return;
     }
     c -= R->c2;
     if (c < R->c4) {
         int tup = c * SEM_GS_CHUNK + t;
-        if (tup < R->n4) gs_tuple<T, A, 4>(u, R->idx4 + 4LL * tup);
+        if (tup < R->n4) gs_tuple<T, A, 4>(u, gp(R->idx4) + 4LL * tup);
         return;
     }
     c -= R->c4;
     int tup = c * SEM_GS_CHUNK + t;
-    if (tup < R->n8) gs_tuple<T, A, 8>(u, R->idx8 + 8LL * tup);
+    if (tup < R->n8) gs_tuple<T, A, 8>(u, gp(R->idx8) + 8LL * tup);
 }
 
 void launch_dssum(const Batch& b, int field, int ncomp, int tprec, int gate, void* raw, hipStream_t s)

@@ -22,16 +22,16 @@ template <> __device__ __forceinline__ int mfield<double>() { return F_M64; }
 template <> __device__ __forceinline__ int mfield<float>() { return F_M32; }
 
 template <typename TM, typename C>
-__device__ __forceinline__ C ldm(const TM* M, long long off, C sc)
+__device__ __forceinline__ C ldm(const SEM_GLOBAL TM* M, long long off, C sc)
 {
-    if constexpr (sizeof(TM) == 2) return to<C>(M[off]) * sc;
+    if constexpr (sizeof(TM) == 2) return to<C>(ldg(M + off)) * sc;
     else return (C)M[off];
 }
 
 template <typename TM, typename C>
 __device__ __forceinline__ C melem_scale(const ReqDesc* R, int e)
 {
-    if constexpr (sizeof(TM) == 2) return (C)((const float*)R->f[F_MSC])[e];
+    if constexpr (sizeof(TM) == 2) return (C)gfield<float>(R, F_MSC)[e];
     else return (C)1;
 }
 
@@ -57,8 +57,8 @@ template <int LX, typename C>
 __device__ __forceinline__ void load_D(const ReqDesc* R, C* sD)
 {
     for (int q = threadIdx.x; q < LX * LX; q += blockDim.x) {
-        if constexpr (sizeof(C) == 8) sD[q] = (C)R->D64[q];
-        else sD[q] = (C)R->D32[q];
+        if constexpr (sizeof(C) == 8) sD[q] = (C)gp(R->D64)[q];
+        else sD[q] = (C)gp(R->D32)[q];
     }
 }
 
@@ -69,23 +69,23 @@ __global__ void __launch_bounds__(ONthr<LX>::v) conv_kernel(Batch bt)
     __shared__ C sD[L2];
     __shared__ C su[3][EPB][L2];
     load_D<LX, C>(R, sD);
-    const TM* M = (const TM*)R->f[mfield<TM>()];
+    const SEM_GLOBAL TM* M = gfield<TM>(R, mfield<TM>());
     const C msc = melem_scale<TM, C>(R, ee);
     C col[3][LX];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double* u = (const double*)R->f[F_U + c];
+        const SEM_GLOBAL double* u = gfield<double>(R, F_U + c);
 #pragma unroll
-        for (int k = 0; k < LX; ++k) col[c][k] = live ? (C)u[ebase + k * L2 + ij] : (C)0;
+        for (int k = 0; k < LX; ++k) col[c][k] = (C)u[ebase + k * L2 + ij];
     }
-    __syncthreads();
+    block_sync_lds();
 #pragma unroll
     for (int k = 0; k < LX; ++k) {
         if (el < EPB) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) su[c][el][ij] = col[c][k];
         }
-        __syncthreads();
+        block_sync_lds();
         if (live) {
             const int p = k * L2 + ij;
             C m[9];
@@ -103,10 +103,10 @@ __global__ void __launch_bounds__(ONthr<LX>::v) conv_kernel(Batch bt)
                 C s = 0;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) s += col[c][k] * (m[0 * 3 + c] * dr + m[1 * 3 + c] * ds + m[2 * 3 + c] * dt);
-                ((double*)R->f[F_BN + f])[ebase + p] = -(double)s;
+                gfieldw<double>(R, F_BN + f)[ebase + p] = -(double)s;
             }
         }
-        __syncthreads();
+        block_sync_lds();
     }
 }
 
@@ -117,17 +117,17 @@ __global__ void __launch_bounds__(ONthr<LX>::v) opgrad_kernel(Batch bt, int src,
     __shared__ C sD[L2];
     __shared__ C su[EPB][L2];
     load_D<LX, C>(R, sD);
-    const TM* M = (const TM*)R->f[mfield<TM>()];
+    const SEM_GLOBAL TM* M = gfield<TM>(R, mfield<TM>());
     const C msc = melem_scale<TM, C>(R, ee);
-    const double* u = (const double*)R->f[src];
+    const SEM_GLOBAL double* u = gfield<double>(R, src);
     C col[LX];
 #pragma unroll
-    for (int k = 0; k < LX; ++k) col[k] = live ? (C)u[ebase + k * L2 + ij] : (C)0;
-    __syncthreads();
+    for (int k = 0; k < LX; ++k) col[k] = (C)u[ebase + k * L2 + ij];
+    block_sync_lds();
 #pragma unroll
     for (int k = 0; k < LX; ++k) {
         if (el < EPB) su[el][ij] = col[k];
-        __syncthreads();
+        block_sync_lds();
         if (live) {
             const int p = k * L2 + ij;
             C dr = 0, ds = 0, dt = 0;
@@ -142,10 +142,10 @@ __global__ void __launch_bounds__(ONthr<LX>::v) opgrad_kernel(Batch bt, int src,
                 C gc = ldm<TM, C>(M, ((long long)ee * 9 + 0 * 3 + c) * L3 + p, msc) * dr
                      + ldm<TM, C>(M, ((long long)ee * 9 + 1 * 3 + c) * L3 + p, msc) * ds
                      + ldm<TM, C>(M, ((long long)ee * 9 + 2 * 3 + c) * L3 + p, msc) * dt;
-                ((double*)R->f[dst + c])[ebase + p] = (double)gc;
+                gfieldw<double>(R, dst + c)[ebase + p] = (double)gc;
             }
         }
-        __syncthreads();
+        block_sync_lds();
     }
 }
 
@@ -157,12 +157,12 @@ __global__ void __launch_bounds__(ONthr<LX>::v) wdiv_kernel(Batch bt, int src, i
     __shared__ C sr[EPB][L2];
     __shared__ C ss[EPB][L2];
     load_D<LX, C>(R, sD);
-    const TM* M = (const TM*)R->f[mfield<TM>()];
+    const SEM_GLOBAL TM* M = gfield<TM>(R, mfield<TM>());
     const C msc = melem_scale<TM, C>(R, ee);
     C wacc[LX];
 #pragma unroll
     for (int k = 0; k < LX; ++k) wacc[k] = 0;
-    __syncthreads();
+    block_sync_lds();
 #pragma unroll
     for (int k = 0; k < LX; ++k) {
         const int p = k * L2 + ij;
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(ONthr<LX>::v) wdiv_kernel(Batch bt, int src, i
         if (live) {
             C v[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) v[c] = (C)((const double*)R->f[src + c])[ebase + p];
+            for (int c = 0; c < 3; ++c) v[c] = (C)gfield<double>(R, src + c)[ebase + p];
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(ONthr<LX>::v) wdiv_kernel(Batch bt, int src, i
         if (el < EPB) { sr[el][ij] = f[0]; ss[el][ij] = f[1]; }
 #pragma unroll
         for (int l = 0; l < LX; ++l) wacc[l] += sD[k * LX + l] * f[2];
-        __syncthreads();
+        block_sync_lds();
         if (el < EPB) {
             C acc = 0;
 #pragma unroll
@@ -189,14 +189,17 @@ __global__ void __launch_bounds__(ONthr<LX>::v) wdiv_kernel(Batch bt, int src, i
             }
             wacc[k] += acc;
         }
-        __syncthreads();
+        block_sync_lds();
     }
     if (live) {
-        double* out = (double*)R->f[dst];
+        SEM_GLOBAL double* out = gfieldw<double>(R, dst);
 #pragma unroll
         for (int k = 0; k < LX; ++k) out[ebase + k * L2 + ij] = (double)wacc[k];
     }
 }
+
+// (element kernels: the column loads are unconditional -- threads without an
+// element read element 0 -- and the k-walk uses LDS-only barriers)
 
 // kinetic energy and enstrophy integrands (B/2 |u|^2, B/2 |omega|^2) and the
 // largest |div u|, element-local derivatives, fp64; partials R_X0, R_X1 (sum)
@@ -209,24 +212,24 @@ __global__ void __launch_bounds__(ONthr<LX>::v) diagnostics_kernel(Batch bt)
     __shared__ double su[3][EPB][L2];
     __shared__ double red[ONthr<LX>::v / 64 * 2];
     load_D<LX, double>(R, sD);
-    const double* M = (const double*)R->f[F_M64];
-    const double* B = (const double*)R->f[F_B64];
+    const SEM_GLOBAL double* M = gfield<double>(R, F_M64);
+    const SEM_GLOBAL double* B = gfield<double>(R, F_B64);
     double col[3][LX];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double* u = (const double*)R->f[F_U + c];
+        const SEM_GLOBAL double* u = gfield<double>(R, F_U + c);
 #pragma unroll
-        for (int k = 0; k < LX; ++k) col[c][k] = live ? u[ebase + k * L2 + ij] : 0.0;
+        for (int k = 0; k < LX; ++k) col[c][k] = u[ebase + k * L2 + ij];
     }
     double ke = 0, en = 0, md = 0;
-    __syncthreads();
+    block_sync_lds();
 #pragma unroll
     for (int k = 0; k < LX; ++k) {
         if (el < EPB) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) su[c][el][ij] = col[c][k];
         }
-        __syncthreads();
+        block_sync_lds();
         if (live) {
             const int p = k * L2 + ij;
             const double bm = B[ebase + p];
@@ -253,21 +256,22 @@ __global__ void __launch_bounds__(ONthr<LX>::v) diagnostics_kernel(Batch bt)
             en += bm * 0.5 * (wx * wx + wy * wy + wz * wz);
             md = fmax(md, fabs(dv));
         }
-        __syncthreads();
+        block_sync_lds();
     }
     double v[2] = {ke, en};
     block_sum<double, 2>(v, red);
     md = wave_max(md);
     __shared__ double mred[ONthr<LX>::v / 64];
     if ((t & 63) == 0) mred[t >> 6] = md;
-    __syncthreads();
+    block_sync_lds();
     if (t == 0) {
         double m = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, mred[w]);
-        R->part[(long long)R_X0 * R->pstride + blk] = v[0];
-        R->part[(long long)R_X1 * R->pstride + blk] = v[1];
-        R->part[(long long)R_X2 * R->pstride + blk] = m;
-        if (blk == 0) { R->I[I_PCNT + R_X0] = R->nb; R->I[I_PCNT + R_X1] = R->nb; R->I[I_PCNT + R_X2] = R->nb; }
+        SEM_GLOBAL double* part = gp(R->part);
+        part[(long long)R_X0 * R->pstride + blk] = v[0];
+        part[(long long)R_X1 * R->pstride + blk] = v[1];
+        part[(long long)R_X2 * R->pstride + blk] = m;
+        if (blk == 0) { gp(R->I)[I_PCNT + R_X0] = R->nb; gp(R->I)[I_PCNT + R_X1] = R->nb; gp(R->I)[I_PCNT + R_X2] = R->nb; }
     }
 }
 

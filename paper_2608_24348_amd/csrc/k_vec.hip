@@ -23,8 +23,8 @@ __device__ __forceinline__ PtRange pt_range(const ReqDesc* R, int blk)
     return r;
 }
 
-template <typename T> __device__ __forceinline__ const T* fld(const ReqDesc* R, int id) { return (const T*)R->f[id]; }
-template <typename T> __device__ __forceinline__ T* fldw(const ReqDesc* R, int id) { return (T*)R->f[id]; }
+template <typename T> __device__ __forceinline__ const SEM_GLOBAL T* fld(const ReqDesc* R, int id) { return gfield<T>(R, id); }
+template <typename T> __device__ __forceinline__ SEM_GLOBAL T* fldw(const ReqDesc* R, int id) { return gfieldw<T>(R, id); }
 
 template <typename TV> __device__ __forceinline__ int idv_field() { return F_IDV32; }
 template <> __device__ __forceinline__ int idv_field<double>() { return F_IDV64; }
@@ -34,8 +34,8 @@ template <> __device__ __forceinline__ int idp_field<double>() { return F_IDP64;
 // partial of point-wise block blk; block 0 also records how many partials the slot holds
 __device__ __forceinline__ void put_partial(const ReqDesc* R, int slot, int blk, double v)
 {
-    R->part[(long long)slot * R->pstride + blk] = v;
-    if (blk == 0) R->I[I_PCNT + slot] = R->nvb;
+    gp(R->part)[(long long)slot * R->pstride + blk] = v;
+    if (blk == 0) gp(R->I)[I_PCNT + slot] = R->nvb;
 }
 
 // ------------------------------------------------------------------ generic point-wise ops
@@ -51,14 +51,14 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
     if (!gate_ok(R, a.gate < 0 ? -1 : a.gate + (a.ncomp > 1 ? c : 0))) return;
     const PtRange pr = pt_range(R, blk);
     const int lx = R->lx;
-    const double* S = R->S;
+    const SEM_GLOBAL double* S = gp(R->S);
     double acc[2] = {0.0, 0.0};
 
     switch (a.op) {
     case V_VRESID: {
-        const double* rhs = fld<double>(R, F_RHS + c);
-        const double* w = fld<double>(R, F_W64 + c);
-        double* r = fldw<double>(R, F_R64 + c);
+        auto rhs = fld<double>(R, F_RHS + c);
+        auto w = fld<double>(R, F_W64 + c);
+        auto r = fldw<double>(R, F_R64 + c);
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
             const double v = rhs[p] - w[p];
             r[p] = v;
@@ -70,12 +70,12 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         break;
     }
     case V_PCG_INIT: {
-        const double* r64 = fld<double>(R, F_R64 + c);
-        const TV* idv = fld<TV>(R, idv_field<TV>());
-        TV* x = fldw<TV>(R, F_PX + c);
-        TV* r = fldw<TV>(R, F_PR + c);
-        TV* z = fldw<TV>(R, F_PZ + c);
-        TV* pp = fldw<TV>(R, F_PP + c);
+        auto r64 = fld<double>(R, F_R64 + c);
+        auto idv = fld<TV>(R, idv_field<TV>());
+        auto x = fldw<TV>(R, F_PX + c);
+        auto r = fldw<TV>(R, F_PR + c);
+        auto z = fldw<TV>(R, F_PZ + c);
+        auto pp = fldw<TV>(R, F_PP + c);
         A s = 0;
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
             const TV rv = (TV)r64[p];
@@ -90,12 +90,12 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
     }
     case V_PCG_UPD: {
         const TV alpha = (TV)S[S_ALPHA + c];
-        const TV* idv = fld<TV>(R, idv_field<TV>());
-        TV* x = fldw<TV>(R, F_PX + c);
-        TV* r = fldw<TV>(R, F_PR + c);
-        TV* z = fldw<TV>(R, F_PZ + c);
-        const TV* pp = fld<TV>(R, F_PP + c);
-        const TV* w = fld<TV>(R, F_PW + c);
+        auto idv = fld<TV>(R, idv_field<TV>());
+        auto x = fldw<TV>(R, F_PX + c);
+        auto r = fldw<TV>(R, F_PR + c);
+        auto z = fldw<TV>(R, F_PZ + c);
+        auto pp = fld<TV>(R, F_PP + c);
+        auto w = fld<TV>(R, F_PW + c);
         A rr = 0, rz = 0;
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
             x[p] += alpha * pp[p];
@@ -113,33 +113,33 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
     }
     case V_PCG_P: {
         const TV beta = (TV)S[S_BETA + c];
-        const TV* z = fld<TV>(R, F_PZ + c);
-        TV* pp = fldw<TV>(R, F_PP + c);
+        auto z = fld<TV>(R, F_PZ + c);
+        auto pp = fldw<TV>(R, F_PP + c);
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) pp[p] = z[p] + beta * pp[p];
         break;
     }
     case V_US_COPY: {
-        const double* u = fld<double>(R, F_U + c);
-        double* us = fldw<double>(R, F_US + c);
+        auto u = fld<double>(R, F_U + c);
+        auto us = fldw<double>(R, F_US + c);
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) us[p] = u[p];
         break;
     }
     case V_US_ADD: {
-        const TV* x = fld<TV>(R, F_PX + c);
-        double* us = fldw<double>(R, F_US + c);
+        auto x = fld<TV>(R, F_PX + c);
+        auto us = fldw<double>(R, F_US + c);
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) us[p] += (double)x[p];
         break;
     }
     case V_RHS: {
-        const double* B = fld<double>(R, F_B64);
-        const double* bn0 = fld<double>(R, F_BN + c);
-        const double* bn1 = fld<double>(R, F_BNL1 + c);
-        const double* bn2 = fld<double>(R, F_BNL2 + c);
-        const double* u0 = fld<double>(R, F_U + c);
-        const double* u1 = fld<double>(R, F_UL1 + c);
-        const double* u2 = fld<double>(R, F_UL2 + c);
-        const double* gp = fld<double>(R, F_GP + c);
-        double* rhs = fldw<double>(R, F_RHS + c);
+        auto B = fld<double>(R, F_B64);
+        auto bn0 = fld<double>(R, F_BN + c);
+        auto bn1 = fld<double>(R, F_BNL1 + c);
+        auto bn2 = fld<double>(R, F_BNL2 + c);
+        auto u0 = fld<double>(R, F_U + c);
+        auto u1 = fld<double>(R, F_UL1 + c);
+        auto u2 = fld<double>(R, F_UL2 + c);
+        auto gp = fld<double>(R, F_GP + c);
+        auto rhs = fldw<double>(R, F_RHS + c);
         const double a1 = S[S_EXT], a2 = S[S_EXT + 1], a3 = S[S_EXT + 2];
         const double b1 = S[S_BDF], b2 = S[S_BDF + 1], b3 = S[S_BDF + 2];
         const double idt = 1.0 / S[S_DT];
@@ -152,10 +152,10 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
     }
     case V_IDV: {
         const double h1 = S[S_H1], h2 = S[S_H2];
-        const double* da = fld<double>(R, F_DA64);
-        const double* ib = fld<double>(R, F_IBSUM64);
-        double* idv = fldw<double>(R, F_IDV64);
-        float* idv32 = fldw<float>(R, F_IDV32);
+        auto da = fld<double>(R, F_DA64);
+        auto ib = fld<double>(R, F_IBSUM64);
+        auto idv = fldw<double>(R, F_IDV64);
+        auto idv32 = fldw<float>(R, F_IDV32);
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
             const double v = 1.0 / (h1 * da[p] + h2 / ib[p]);
             idv[p] = v;
@@ -165,8 +165,8 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
     }
     case V_SUM_UNIQUE:
     case V_SUM_MASS: {
-        const double* f = a.f0 >= 0 ? fld<double>(R, a.f0) : nullptr;
-        const double* B = fld<double>(R, F_B64);
+        const SEM_GLOBAL double* f = a.f0 >= 0 ? fld<double>(R, a.f0) : nullptr;
+        auto B = fld<double>(R, F_B64);
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
             const double fv = f ? f[p] : 1.0;
             if (a.op == V_SUM_UNIQUE) acc[0] += fv * inv_mult((int)((p - pr.p0) % pr.L3), lx);
@@ -178,34 +178,34 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         break;
     }
     case V_SUB_MEAN: {
-        double* f = fldw<double>(R, a.f0);
+        auto f = fldw<double>(R, a.f0);
         const double m = S[S_MEAN];
         const double sc = a.f1 >= 0 ? S[a.f1] : 1.0;
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) f[p] = sc * (f[p] - m);
         break;
     }
     case V_COPY: {
-        const double* f = fld<double>(R, a.f0 + c);
-        double* o = fldw<double>(R, a.f1 + c);
+        auto f = fld<double>(R, a.f0 + c);
+        auto o = fldw<double>(R, a.f1 + c);
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) o[p] = f[p];
         break;
     }
     case V_ZERO: {
-        double* f = fldw<double>(R, a.f0 + c);
+        auto f = fldw<double>(R, a.f0 + c);
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) f[p] = 0.0;
         break;
     }
     case V_GM_NORMALIZE: {
         const int J = R->I[I_GJ];
-        double* v = fldw<double>(R, F_V) + (long long)J * R->np;
-        const double* w = fld<double>(R, F_GWD);
+        auto v = fldw<double>(R, F_V) + (long long)J * R->np;
+        auto w = fld<double>(R, F_GWD);
         const double sc = S[S_GNSCALE];
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) v[p] = w[p] * sc;
         break;
     }
     case V_GM_RESID: {
-        const double* b = fld<double>(R, F_GB);
-        double* w = fldw<double>(R, F_GWD);
+        auto b = fld<double>(R, F_GB);
+        auto w = fldw<double>(R, F_GWD);
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
             const double v = b[p] - w[p];
             w[p] = v;
@@ -217,15 +217,15 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         break;
     }
     case V_CORRECT: {
-        const double* us = fld<double>(R, F_US + c);
-        const double* gp = fld<double>(R, F_GP + c);
-        const double* ib = fld<double>(R, F_IBSUM64);
-        double* un = fldw<double>(R, F_UL2 + c);
+        auto us = fld<double>(R, F_US + c);
+        auto gp = fld<double>(R, F_GP + c);
+        auto ib = fld<double>(R, F_IBSUM64);
+        auto un = fldw<double>(R, F_UL2 + c);
         const double f = S[S_DT] / S[S_BETA0];
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) un[p] = us[p] - f * gp[p] * ib[p];
         if (c == 0) {
-            double* pres = fldw<double>(R, F_P);
-            const double* phi = fld<double>(R, F_GX);
+            auto pres = fldw<double>(R, F_P);
+            auto phi = fld<double>(R, F_GX);
             for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) pres[p] += phi[p];
         }
         break;
@@ -253,15 +253,15 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
 template <int NJ, int MODE>
 __device__ __forceinline__ void gm_body(const ReqDesc* R, const PtRange& pr, double (&acc)[SEM_MAXM + 1], double& accm)
 {
-    const double* V = fld<double>(R, F_V);
+    auto V = fld<double>(R, F_V);
     const long long np = R->np;
     const int lx = R->lx;
     double h[NJ];
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) h[i] = MODE == 1 ? R->S[S_GHC + i] : MODE == 2 ? R->S[S_GH2 + i] : 0.0;
-    const double mean = MODE == 1 ? R->S[S_GMEAN] : 0.0;
-    const double* w = fld<double>(R, F_GW);
-    double* wd = fldw<double>(R, F_GWD);
+    for (int i = 0; i < NJ; ++i) h[i] = MODE == 1 ? gp(R->S)[S_GHC + i] : MODE == 2 ? gp(R->S)[S_GH2 + i] : 0.0;
+    const double mean = MODE == 1 ? gp(R->S)[S_GMEAN] : 0.0;
+    auto w = fld<double>(R, F_GW);
+    auto wd = fldw<double>(R, F_GWD);
     for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
         double vr[NJ];
 #pragma unroll
@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_pass_kernel(Batch bt, int 
     const int blk = g - bt.vb[ri];
     if (!gate_ok(R, gate)) return;
     const PtRange pr = pt_range(R, blk);
-    const int J = R->I[I_GJ];
+    const int J = gp(R->I)[I_GJ];
     double acc[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
@@ -344,13 +344,13 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_pass_kernel(Batch bt, int 
 template <int NJ, typename TD>
 __device__ __forceinline__ void xupd_body(const ReqDesc* R, const PtRange& pr)
 {
-    const double* V = fld<double>(R, F_V);
-    const TD* idp = fld<TD>(R, sizeof(TD) == 8 ? F_IDP64 : F_IDP32);
-    double* x = fldw<double>(R, F_GX);
+    auto V = fld<double>(R, F_V);
+    auto idp = fld<TD>(R, sizeof(TD) == 8 ? F_IDP64 : F_IDP32);
+    auto x = fldw<double>(R, F_GX);
     const long long np = R->np;
     double y[NJ];
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) y[i] = R->S[S_GY + i];
+    for (int i = 0; i < NJ; ++i) y[i] = gp(R->S)[S_GY + i];
     for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
         double vr[NJ];
 #pragma unroll
@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_xupd_kernel(Batch bt, int 
     const int blk = g - bt.vb[ri];
     if (!gate_ok(R, gate)) return;
     const PtRange pr = pt_range(R, blk);
-    switch (R->I[I_GJEND]) {
+    switch (gp(R->I)[I_GJEND]) {
 #define XU_CASE(n) case n: xupd_body<n, TD>(R, pr); break;
         SEM_NJ_CASES(XU_CASE)
 #undef XU_CASE
@@ -410,8 +410,8 @@ void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s)
 __device__ double slot_sum(const ReqDesc* R, int slot, double* red)
 {
     double s = 0.0;
-    const double* p = R->part + (long long)slot * R->pstride;
-    const int cnt = R->I[I_PCNT + slot];
+    const SEM_GLOBAL double* p = gp(R->part) + (long long)slot * R->pstride;
+    const int cnt = gp(R->I)[I_PCNT + slot];
     for (int q = threadIdx.x; q < cnt; q += blockDim.x) s += p[q];
     double v[1] = {s};
     block_sum<double, 1>(v, red);
@@ -420,8 +420,8 @@ __device__ double slot_sum(const ReqDesc* R, int slot, double* red)
 __device__ double slot_max(const ReqDesc* R, int slot, double* red)
 {
     double s = 0.0;
-    const double* p = R->part + (long long)slot * R->pstride;
-    const int cnt = R->I[I_PCNT + slot];
+    const SEM_GLOBAL double* p = gp(R->part) + (long long)slot * R->pstride;
+    const int cnt = gp(R->I)[I_PCNT + slot];
     for (int q = threadIdx.x; q < cnt; q += blockDim.x) s = fmax(s, p[q]);
     s = wave_max(s);
     __syncthreads();
@@ -442,8 +442,8 @@ __device__ void multi_slot_sum(const ReqDesc* R, int slot0, int nslots, double* 
     const int t = threadIdx.x, sl = t & 31, g = t >> 5;
     double acc = 0.0;
     if (sl < nslots) {
-        const double* p = R->part + (long long)(slot0 + sl) * R->pstride;
-        const int cnt = R->I[I_PCNT + slot0 + sl];
+        const SEM_GLOBAL double* p = gp(R->part) + (long long)(slot0 + sl) * R->pstride;
+        const int cnt = gp(R->I)[I_PCNT + slot0 + sl];
         for (int q = g; q < cnt; q += 8) acc += p[q];
     }
     scratch[t] = acc;
@@ -465,8 +465,8 @@ __global__ void __launch_bounds__(256) fin_kernel(Batch bt, FinArgs a)
     __shared__ double scratch[256];
     const int ri = blockIdx.x;
     ReqDesc* R = (ReqDesc*)bt.r[ri];
-    double* S = R->S;
-    int* I = R->I;
+    SEM_GLOBAL double* S = gp(R->S);
+    SEM_GLOBAL int* I = gp(R->I);
     const int t = threadIdx.x;
     switch (a.op) {
     case FIN_VINIT: {
@@ -544,10 +544,10 @@ __global__ void __launch_bounds__(256) fin_kernel(Batch bt, FinArgs a)
         if (t == 0) {
             const int m = I[I_GM];
             const int J = I[I_GJ];
-            double* H = S + S_GH;
-            double* cs = S + S_GCS;
-            double* sn = S + S_GSN;
-            double* gg = S + S_GG;
+            SEM_GLOBAL double* H = S + S_GH;
+            SEM_GLOBAL double* cs = S + S_GCS;
+            SEM_GLOBAL double* sn = S + S_GSN;
+            SEM_GLOBAL double* gg = S + S_GG;
             const double hn = sqrt(hn2);
             for (int i = 0; i <= J; ++i) H[i * m + J] = S[S_GHC + i] + S[S_GH2 + i];
             H[(J + 1) * m + J] = hn;
@@ -569,7 +569,7 @@ __global__ void __launch_bounds__(256) fin_kernel(Batch bt, FinArgs a)
             if (bad) I[I_NAN] = 1;
             if (bad || fabs(gg[J + 1]) <= S[S_PTOL] || hn == 0.0 || J + 1 == m || I[I_GIT] >= I[I_GMAXIT]) {
                 const int jend = bad ? 0 : J + 1;
-                double* yv = S + S_GY;
+                SEM_GLOBAL double* yv = S + S_GY;
                 for (int r = jend - 1; r >= 0; --r) {
                     double s = gg[r];
                     for (int k = r + 1; k < jend; ++k) s -= H[r * m + k] * yv[k];
@@ -599,7 +599,7 @@ __global__ void __launch_bounds__(256) fin_kernel(Batch bt, FinArgs a)
                 I[I_GACT] = 0; I[I_GARN] = 0; I[I_GNORM] = 0;
             } else {
                 I[I_GJ] = 0;
-                double* gg = S + S_GG;
+                SEM_GLOBAL double* gg = S + S_GG;
                 for (int i = 0; i <= SEM_MAXM; ++i) gg[i] = 0.0;
                 gg[0] = beta;
                 S[S_GNSCALE] = 1.0 / beta;
@@ -684,7 +684,7 @@ __global__ void __launch_bounds__(256) fin_kernel(Batch bt, FinArgs a)
     }
     case FIN_STATS: {
         if (t == 0) {
-            double* o = a.host_stats + (long long)ri * SEM_NSTAT;
+            double* o = a.host_stats + (long long)ri * SEM_NSTAT;  // pinned host memory
             o[0] = S[S_TIME]; o[1] = S[S_KE]; o[2] = S[S_ENST]; o[3] = S[S_MAXDIV];
             for (int c = 0; c < 3; ++c) { o[4 + c] = I[I_VIT + c]; o[7 + c] = S[S_RN + c]; }
             o[10] = I[I_GIT]; o[11] = S[S_GBETA]; o[12] = I[I_NAN]; o[13] = I[I_STEP];
