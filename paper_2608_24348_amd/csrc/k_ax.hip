@@ -48,7 +48,7 @@ template <> __device__ __forceinline__ int bfield<float>() { return F_B32; }
 
 // PC: Jacobi scaling of the input on load (0 none, 1 fp64 diagonal, 2 fp32),
 // a template parameter so the load stays unconditional
-template <int LX, typename TU, typename TG, typename C, int PC>
+template <int LX, typename TU, typename TG, typename C, int PC, typename TW>
 __global__ void __launch_bounds__(Nthr<LX>::v)
 ax_kernel(Batch bt, AxLaunch a)
 {
@@ -82,7 +82,7 @@ ax_kernel(Batch bt, AxLaunch a)
 
     const SEM_GLOBAL TU* u = a.src_vj ? gfield<TU>(R, F_V) + (long long)gp(R->I)[I_GJ] * R->np
                                       : a.src >= 0 ? gfield<TU>(R, a.src + comp) : gp((const TU*)a.u_raw);
-    SEM_GLOBAL TU* w = a.dst >= 0 ? gfieldw<TU>(R, a.dst + comp) : gp((TU*)a.w_raw);
+    SEM_GLOBAL TW* w = a.dst >= 0 ? gfieldw<TW>(R, a.dst + comp) : gp((TW*)a.w_raw);
     const SEM_GLOBAL TG* G = gfield<TG>(R, gfield_id<TG>());
     const SEM_GLOBAL TG* Bm = gfield<TG>(R, bfield<TG>());
     using TPC = typename std::conditional<PC == 2, float, double>::type;
@@ -198,7 +198,7 @@ ax_kernel(Batch bt, AxLaunch a)
             const int p = k * L2 + ij;
             const C bk = helm ? to<C>(braw[k]) * bsc : (C)0;
             const C wv = h1 * wacc[k] + h2 * bk * ureg[k];
-            const TU ws = to<TU>(wv);
+            const TW ws = to<TW>(wv);
             stg(w + ebase + p, ws);
             if (a.pdot >= 0) dot += (double)ureg[k] * (double)to<C>(ws);
         }
@@ -217,18 +217,31 @@ template <int LX, typename TU, typename TG, typename C>
 static void ax_go(const Batch& b, const AxLaunch& a, hipStream_t s)
 {
     dim3 grid(b.eb[b.n], a.ncomp);
-    if constexpr (sizeof(TU) == 8) {
-        // only the pressure operator (fp64 basis vectors) takes a Jacobi scaling
-        if (a.precond >= 0 && a.tpc == P64) {
-            hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 1>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
-            return;
-        }
-        if (a.precond >= 0) {
-            hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 2>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+    if constexpr (sizeof(TU) == 4) {
+        // the Arnoldi operator of an fp32-stored GMRES basis: Jacobi scaling on
+        // load and an fp64 output
+        if (a.out64) {
+            if (a.precond >= 0 && a.tpc == P64)
+                hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 1, double>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+            else if (a.precond >= 0)
+                hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 2, double>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+            else
+                hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0, double>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
             return;
         }
     }
-    hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+    if constexpr (sizeof(TU) == 8) {
+        // the Arnoldi operator of an fp64 GMRES basis (Jacobi scaling on load)
+        if (a.precond >= 0 && a.tpc == P64) {
+            hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 1, TU>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+            return;
+        }
+        if (a.precond >= 0) {
+            hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 2, TU>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0, TU>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
 }
 
 // supported (vector, geometry, arithmetic) instantiations; ax_supported()
@@ -244,6 +257,9 @@ static void ax_lx(const Batch& b, const AxLaunch& a, hipStream_t s)
     else if (u == P64 && g == P32 && c == P32) ax_go<LX, double, float, float>(b, a, s);
     else if (u == P64 && g == P16 && c == P32) ax_go<LX, double, __half, float>(b, a, s);
     else if (u == P64 && g == PBF && c == P32) ax_go<LX, double, __hip_bfloat16, float>(b, a, s);
+    else if (u == P32 && g == P32 && c == P64) ax_go<LX, float, float, double>(b, a, s);
+    else if (u == P32 && g == P16 && c == P64) ax_go<LX, float, __half, double>(b, a, s);
+    else if (u == P32 && g == PBF && c == P64) ax_go<LX, float, __hip_bfloat16, double>(b, a, s);
     else if (u == P32 && g == P32 && c == P32) ax_go<LX, float, float, float>(b, a, s);
     else if (u == P32 && g == P16 && c == P32) ax_go<LX, float, __half, float>(b, a, s);
     else if (u == P32 && g == PBF && c == P32) ax_go<LX, float, __hip_bfloat16, float>(b, a, s);

@@ -127,7 +127,12 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
     case V_US_ADD: {
         auto x = fld<TV>(R, F_PX + c);
         auto us = fldw<double>(R, F_US + c);
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) us[p] += (double)x[p];
+        if (a.f0 == 1) {
+            auto u = fld<double>(R, F_U + c);
+            for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) us[p] = u[p] + (double)x[p];
+        } else {
+            for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) us[p] += (double)x[p];
+        }
         break;
     }
     case V_RHS: {
@@ -195,19 +200,12 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) f[p] = 0.0;
         break;
     }
-    case V_GM_NORMALIZE: {
-        const int J = R->I[I_GJ];
-        auto v = fldw<double>(R, F_V) + (long long)J * R->np;
-        auto w = fld<double>(R, F_GWD);
-        const double sc = S[S_GNSCALE];
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) v[p] = w[p] * sc;
-        break;
-    }
     case V_GM_RESID: {
         auto b = fld<double>(R, F_GB);
         auto w = fldw<double>(R, F_GWD);
+        const bool ax = gp(R->I)[I_GENDAX] != 0;  // iterate nonzero: GWD holds A x
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
-            const double v = b[p] - w[p];
+            const double v = ax ? b[p] - w[p] : b[p];
             w[p] = v;
             acc[0] += v * v * inv_mult((int)((p - pr.p0) % pr.L3), lx);
         }
@@ -250,10 +248,10 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
 // over unique nodes and the second subtracts that mean: a no-op in exact
 // arithmetic that keeps rounding (notably of fp32 operators) from feeding the
 // null direction into the basis.
-template <int NJ, int MODE>
+template <int NJ, int MODE, typename TB>
 __device__ __forceinline__ void gm_body(const ReqDesc* R, const PtRange& pr, double (&acc)[SEM_MAXM + 1], double& accm)
 {
-    auto V = fld<double>(R, F_V);
+    const SEM_GLOBAL TB* V = fld<TB>(R, F_V);
     const long long np = R->np;
     const int lx = R->lx;
     double h[NJ];
@@ -265,7 +263,7 @@ __device__ __forceinline__ void gm_body(const ReqDesc* R, const PtRange& pr, dou
     for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
         double vr[NJ];
 #pragma unroll
-        for (int i = 0; i < NJ; ++i) vr[i] = V[i * np + p];
+        for (int i = 0; i < NJ; ++i) vr[i] = (double)V[i * np + p];
         const double im = inv_mult((int)((p - pr.p0) % pr.L3), lx);
         if (MODE == 0) {
             const double wv = w[p] * im;
@@ -294,7 +292,7 @@ __device__ __forceinline__ void gm_body(const ReqDesc* R, const PtRange& pr, dou
     F(1) F(2) F(3) F(4) F(5) F(6) F(7) F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) F(16) F(17) F(18) \
     F(19) F(20) F(21) F(22) F(23) F(24) F(25) F(26) F(27) F(28) F(29) F(30) F(31)
 
-template <int MODE>
+template <int MODE, typename TB>
 __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_pass_kernel(Batch bt, int gate)
 {
     constexpr int NV = SEM_MAXM + 1;
@@ -311,7 +309,7 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_pass_kernel(Batch bt, int 
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
     double accm = 0.0;
     switch (J + 1) {
-#define GM_CASE(n) case n: gm_body<n, MODE>(R, pr, acc, accm); break;
+#define GM_CASE(n) case n: gm_body<n, MODE, TB>(R, pr, acc, accm); break;
         SEM_NJ_CASES(GM_CASE)
 #undef GM_CASE
     default: break;
@@ -341,10 +339,10 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_pass_kernel(Batch bt, int 
 
 // x += IDP * sum_{i < jend} y_i V_i  (right preconditioning applied once per
 // cycle, with the same stored diagonal the Arnoldi operator used)
-template <int NJ, typename TD>
+template <int NJ, typename TD, typename TB>
 __device__ __forceinline__ void xupd_body(const ReqDesc* R, const PtRange& pr)
 {
-    auto V = fld<double>(R, F_V);
+    const SEM_GLOBAL TB* V = fld<TB>(R, F_V);
     auto idp = fld<TD>(R, sizeof(TD) == 8 ? F_IDP64 : F_IDP32);
     auto x = fldw<double>(R, F_GX);
     const long long np = R->np;
@@ -354,7 +352,7 @@ __device__ __forceinline__ void xupd_body(const ReqDesc* R, const PtRange& pr)
     for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
         double vr[NJ];
 #pragma unroll
-        for (int i = 0; i < NJ; ++i) vr[i] = V[i * np + p];
+        for (int i = 0; i < NJ; ++i) vr[i] = (double)V[i * np + p];
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < NJ; ++i) s += y[i] * vr[i];
@@ -362,7 +360,7 @@ __device__ __forceinline__ void xupd_body(const ReqDesc* R, const PtRange& pr)
     }
 }
 
-template <typename TD>
+template <typename TD, typename TB>
 __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_xupd_kernel(Batch bt, int gate)
 {
     const int g = blockIdx.x;
@@ -372,11 +370,27 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_xupd_kernel(Batch bt, int 
     if (!gate_ok(R, gate)) return;
     const PtRange pr = pt_range(R, blk);
     switch (gp(R->I)[I_GJEND]) {
-#define XU_CASE(n) case n: xupd_body<n, TD>(R, pr); break;
+#define XU_CASE(n) case n: xupd_body<n, TD, TB>(R, pr); break;
         SEM_NJ_CASES(XU_CASE)
 #undef XU_CASE
     default: break;
     }
+}
+
+// V_J = GWD * S_GNSCALE, rounded to the basis storage type
+template <typename TB>
+__global__ void __launch_bounds__(SEM_VEC_THREADS) gm_norm_kernel(Batch bt, int gate)
+{
+    const int g = blockIdx.x;
+    const int ri = find_req(bt.vb, bt.n, g);
+    const ReqDesc* R = bt.r[ri];
+    const int blk = g - bt.vb[ri];
+    if (!gate_ok(R, gate)) return;
+    const PtRange pr = pt_range(R, blk);
+    SEM_GLOBAL TB* v = fldw<TB>(R, F_V) + (long long)gp(R->I)[I_GJ] * R->np;
+    auto w = fld<double>(R, F_GWD);
+    const double sc = gp(R->S)[S_GNSCALE];
+    for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) v[p] = (TB)(w[p] * sc);
 }
 
 void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s)
@@ -386,17 +400,26 @@ void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s)
     if (grid.x == 0) return;
     switch (a.op) {
     case V_GM_DOTS:
-        hipLaunchKernelGGL(gm_pass_kernel<0>, grid, blk, 0, s, b, a.gate);
+        if (a.tb == P64) hipLaunchKernelGGL((gm_pass_kernel<0, double>), grid, blk, 0, s, b, a.gate);
+        else hipLaunchKernelGGL((gm_pass_kernel<0, float>), grid, blk, 0, s, b, a.gate);
         return;
     case V_GM_UPD_DOTS:
-        hipLaunchKernelGGL(gm_pass_kernel<1>, grid, blk, 0, s, b, a.gate);
+        if (a.tb == P64) hipLaunchKernelGGL((gm_pass_kernel<1, double>), grid, blk, 0, s, b, a.gate);
+        else hipLaunchKernelGGL((gm_pass_kernel<1, float>), grid, blk, 0, s, b, a.gate);
         return;
     case V_GM_UPD_NORM:
-        hipLaunchKernelGGL(gm_pass_kernel<2>, grid, blk, 0, s, b, a.gate);
+        if (a.tb == P64) hipLaunchKernelGGL((gm_pass_kernel<2, double>), grid, blk, 0, s, b, a.gate);
+        else hipLaunchKernelGGL((gm_pass_kernel<2, float>), grid, blk, 0, s, b, a.gate);
+        return;
+    case V_GM_NORMALIZE:
+        if (a.tb == P64) hipLaunchKernelGGL(gm_norm_kernel<double>, grid, blk, 0, s, b, a.gate);
+        else hipLaunchKernelGGL(gm_norm_kernel<float>, grid, blk, 0, s, b, a.gate);
         return;
     case V_GM_XUPD:
-        if (a.tv == P64) hipLaunchKernelGGL(gm_xupd_kernel<double>, grid, blk, 0, s, b, a.gate);
-        else hipLaunchKernelGGL(gm_xupd_kernel<float>, grid, blk, 0, s, b, a.gate);
+        if (a.tv == P64 && a.tb == P64) hipLaunchKernelGGL((gm_xupd_kernel<double, double>), grid, blk, 0, s, b, a.gate);
+        else if (a.tv == P64) hipLaunchKernelGGL((gm_xupd_kernel<double, float>), grid, blk, 0, s, b, a.gate);
+        else if (a.tb == P64) hipLaunchKernelGGL((gm_xupd_kernel<float, double>), grid, blk, 0, s, b, a.gate);
+        else hipLaunchKernelGGL((gm_xupd_kernel<float, float>), grid, blk, 0, s, b, a.gate);
         return;
     default: break;
     }
@@ -578,6 +601,7 @@ __global__ void __launch_bounds__(256) fin_kernel(Batch bt, FinArgs a)
                 I[I_GJEND] = jend;
                 I[I_GARN] = 0;
                 I[I_GEND] = 1;
+                I[I_GENDAX] = 1;
                 I[I_GNORM] = 0;
             } else {
                 I[I_GJ] = J + 1;
@@ -594,6 +618,7 @@ __global__ void __launch_bounds__(256) fin_kernel(Batch bt, FinArgs a)
             const double beta = sqrt(s);
             S[S_GBETA] = beta;
             I[I_GEND] = 0;
+            I[I_GENDAX] = 0;
             if (!finite(beta)) I[I_NAN] = 1;
             if (!finite(beta) || beta <= S[S_PTOL] || I[I_GIT] >= I[I_GMAXIT]) {
                 I[I_GACT] = 0; I[I_GARN] = 0; I[I_GNORM] = 0;
@@ -612,7 +637,7 @@ __global__ void __launch_bounds__(256) fin_kernel(Batch bt, FinArgs a)
         // fresh solve from x = 0: the first cycle end computes r = b
         if (t == 0) {
             I[I_GJ] = 0; I[I_GJEND] = 0; I[I_GIT] = 0;
-            I[I_GACT] = 1; I[I_GARN] = 0; I[I_GEND] = 1; I[I_GNORM] = 0;
+            I[I_GACT] = 1; I[I_GARN] = 0; I[I_GEND] = 1; I[I_GENDAX] = 0; I[I_GNORM] = 0;
         }
         break;
     }
@@ -642,6 +667,10 @@ __global__ void __launch_bounds__(256) fin_kernel(Batch bt, FinArgs a)
             S[S_EXT] = a1; S[S_EXT + 1] = a2; S[S_EXT + 2] = a3;
             S[S_H1] = S[S_NU];
             S[S_H2] = b0 / S[S_DT];
+            const bool stale = I[I_STEP] == 0 || S[S_IDV_H1] != S[S_H1] || S[S_IDV_H2] != S[S_H2];
+            I[I_IDVSTALE] = stale ? 1 : 0;
+            S[S_IDV_H1] = S[S_H1];
+            S[S_IDV_H2] = S[S_H2];
             S[S_MEAN + 0] = 0.0;
             for (int c = 0; c < 3; ++c) { I[I_VIT + c] = 0; I[I_VREF + c] = 0; I[I_VACT + c] = 0; }
         }

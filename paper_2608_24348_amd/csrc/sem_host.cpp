@@ -145,6 +145,7 @@ struct Resolved {
     int tv, tva;            // velocity vectors, velocity dot accumulation (PrecId)
     int axv_g, axv_c;       // velocity Ax geometry storage and arithmetic
     int tpd;                // pressure Jacobi diagonal storage
+    int tb;                 // GMRES basis storage (orthogonalisation arithmetic is fp64)
     int axp_g, axp_c;       // pressure Ax geometry storage and arithmetic (vectors are the fp64 GMRES basis)
     int opg_m, opg_c, conv_m, conv_c, div_m, div_c;  // SEM operators: metric storage and arithmetic
     bool need32, need16;
@@ -155,7 +156,7 @@ struct Resolved {
 bool ax_supported(int u, int g, int c)
 {
     if (u == P64) return (c == P64) || (c == P32 && g != P64);
-    if (u == P32) return c == P32 && g != P64;
+    if (u == P32) return g != P64;
     if (u == P16) return c == P32 && g == P16;
     if (u == PBF) return c == P32 && g == PBF;
     return false;
@@ -251,6 +252,7 @@ int resolve_policy(const sem_precision* p, Resolved& r)
     r.tv = to_pid(vb.storage);
     r.tva = to_pid(vb.accumulate);
     r.tpd = to_pid(pb.storage);
+    r.tb = r.tpd;
     r.axv_g = to_pid(kr[SEM_K_AX_VEL].storage);
     r.axv_c = to_pid(kr[SEM_K_AX_VEL].compute);
     if (!ax_supported(r.tv, r.axv_g, r.axv_c))
@@ -258,7 +260,7 @@ int resolve_policy(const sem_precision* p, Resolved& r)
                                 pname(kr[SEM_K_AX_VEL].storage) + ", arithmetic " + pname(kr[SEM_K_AX_VEL].compute));
     r.axp_g = to_pid(kr[SEM_K_AX_PRES].storage);
     r.axp_c = to_pid(kr[SEM_K_AX_PRES].compute);
-    if (!ax_supported(P64, r.axp_g, r.axp_c))
+    if (!ax_supported(r.tb, r.axp_g, r.axp_c))
         return fail(SEM_EINVAL, std::string("ax_pres: no kernel for geometry ") + pname(kr[SEM_K_AX_PRES].storage) +
                                 ", arithmetic " + pname(kr[SEM_K_AX_PRES].compute));
     int* mm[3] = {&r.opg_m, &r.conv_m, &r.div_m};
@@ -378,18 +380,22 @@ void build_layout(sem_ctx* c)
     }
     const int mode = c->flow.mode;
     if (mode >= SEM_MODE_POISSON) {
-        field(F_V, (size_t)(c->flow.gmres_restart + 1) * d);
+        field(F_V, (size_t)(c->flow.gmres_restart + 1) * psize(r.tb) * (size_t)np);
         field(F_GW, d);
         field(F_GWD, d);
         field(F_GB, d);
         field(F_GX, d);
     }
     if (mode >= SEM_MODE_FLUID) {
+        // the pressure solve's rhs is the pressure residual itself
+        c->fbytes[F_GB] = 0;
         field(F_IDV64, d);
         if (r.tv == P32) field(F_IDV32, 4 * (size_t)np);
         for (int f = F_U; f <= F_PHI; ++f) field(f, d);
         const size_t tv = psize(r.tv);
         for (int f = F_PX; f <= F_PWc; ++f) field(f, tv * np);
+        c->foff[F_GB] = c->foff[F_RP];
+        c->fbytes[F_GB] = c->fbytes[F_RP];
     }
     c->bytes = off;
 }
@@ -464,15 +470,16 @@ void ax(const Batch& b, int lx, int src, int dst, int ncomp, int hsel, double h1
 {
     AxLaunch a;
     a.src = src; a.src_vj = 0; a.dst = dst; a.ncomp = ncomp; a.hsel = hsel; a.h1 = h1; a.h2 = h2;
-    a.precond = precond; a.tpc = P64; a.pdot = pdot; a.gate = gate; a.tu = tu; a.tg = tg; a.tc = tc;
+    a.precond = precond; a.tpc = P64; a.pdot = pdot; a.gate = gate; a.tu = tu; a.tg = tg; a.tc = tc; a.out64 = 0;
     a.u_raw = nullptr; a.w_raw = nullptr;
     launch_ax(b, lx, a, s);
 }
 
-void vec(const Batch& b, int op, int ncomp, int tv, int gate, hipStream_t s, int f0 = -1, int f1 = -1, int ta = P64)
+void vec(const Batch& b, int op, int ncomp, int tv, int gate, hipStream_t s, int f0 = -1, int f1 = -1, int ta = P64,
+         int tb = P64)
 {
     VecArgs a;
-    a.op = op; a.gate = gate; a.ncomp = ncomp; a.tv = tv; a.ta = ta; a.f0 = f0; a.f1 = f1; a.a = 0.0;
+    a.op = op; a.gate = gate; a.ncomp = ncomp; a.tv = tv; a.ta = ta; a.tb = tb; a.f0 = f0; a.f1 = f1; a.a = 0.0;
     a.x_raw = nullptr; a.y_raw = nullptr;
     launch_vec(b, a, s);
 }
@@ -510,7 +517,6 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
     const int tv = r.tv;
     int* hf = c0->hflags;
     // fp64 residual of the current state: R64 = RHS - dssum(H U), norms -> VACT
-    vec(b, V_US_COPY, 3, P64, -1, s);
     ax(b, lx, F_U, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, P64, s);
     launch_dssum(b, F_W64, 3, P64, -1, nullptr, s);
     vec(b, V_VRESID, 3, P64, -1, s);
@@ -541,7 +547,7 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
             if (a2 < 0) return a2;
             if (a2 == 0 || guard > c0->flow.vel_maxit + K) break;
         }
-        vec(b, V_US_ADD, 3, tv, -1, s);
+        vec(b, V_US_ADD, 3, tv, -1, s, cyc == 0 ? 1 : 0);
         if (tv == P64) break;  // fp64 recurrence residual is the solver's stop criterion
         ax(b, lx, F_US, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, P64, s);
         launch_dssum(b, F_W64, 3, P64, -1, nullptr, s);
@@ -561,7 +567,8 @@ void gmres_iteration(const Batch& b, int lx, const Resolved& r, hipStream_t s)
         AxLaunch a;
         a.src = -1; a.src_vj = 1; a.dst = F_GW; a.ncomp = 1; a.hsel = -1; a.h1 = 1.0; a.h2 = 0.0;
         a.precond = r.tpd == P64 ? F_IDP64 : F_IDP32; a.tpc = r.tpd; a.pdot = -1; a.gate = I_GARN;
-        a.tu = P64; a.tg = r.axp_g; a.tc = r.axp_c; a.u_raw = nullptr; a.w_raw = nullptr;
+        a.tu = r.tb; a.tg = r.axp_g; a.tc = r.axp_c; a.u_raw = nullptr; a.w_raw = nullptr;
+        a.out64 = 1;
         launch_ax(b, lx, a, s);
     }
     {
@@ -570,27 +577,27 @@ void gmres_iteration(const Batch& b, int lx, const Resolved& r, hipStream_t s)
     }
     {
         ProfScope ps(SEM_PROF_GM_DOTS, s);
-        vec(b, V_GM_DOTS, 1, P64, I_GARN, s);
+        vec(b, V_GM_DOTS, 1, P64, I_GARN, s, -1, -1, P64, r.tb);
     }
     fin(b, FIN_GM_H1, s);
     {
         ProfScope ps(SEM_PROF_GM_UPD_DOTS, s);
-        vec(b, V_GM_UPD_DOTS, 1, P64, I_GARN, s);
+        vec(b, V_GM_UPD_DOTS, 1, P64, I_GARN, s, -1, -1, P64, r.tb);
     }
     fin(b, FIN_GM_H2, s);
     {
         ProfScope ps(SEM_PROF_GM_UPD_NORM, s);
-        vec(b, V_GM_UPD_NORM, 1, P64, I_GARN, s);
+        vec(b, V_GM_UPD_NORM, 1, P64, I_GARN, s, -1, -1, P64, r.tb);
     }
     fin(b, FIN_GM_COL, s);
-    vec(b, V_GM_NORMALIZE, 1, P64, I_GNORM, s);
-    // cycle end: x update and fp64 true residual, then restart or finish
-    vec(b, V_GM_XUPD, 1, r.tpd, I_GEND, s);
-    ax(b, lx, F_GX, F_GWD, 1, -1, 1.0, 0.0, -1, -1, I_GEND, P64, P64, P64, s);
-    launch_dssum(b, F_GWD, 1, P64, I_GEND, nullptr, s);
+    vec(b, V_GM_NORMALIZE, 1, P64, I_GNORM, s, -1, -1, P64, r.tb);
+    // cycle end: x update and fp64 true residual (no operator while x is still zero), then restart or finish
+    vec(b, V_GM_XUPD, 1, r.tpd, I_GEND, s, -1, -1, P64, r.tb);
+    ax(b, lx, F_GX, F_GWD, 1, -1, 1.0, 0.0, -1, -1, I_GENDAX, P64, P64, P64, s);
+    launch_dssum(b, F_GWD, 1, P64, I_GENDAX, nullptr, s);
     vec(b, V_GM_RESID, 1, P64, I_GEND, s);
     fin(b, FIN_GM_RESTART, s);
-    vec(b, V_GM_NORMALIZE, 1, P64, I_GNORM, s);
+    vec(b, V_GM_NORMALIZE, 1, P64, I_GNORM, s, -1, -1, P64, r.tb);
 }
 
 // GMRES on F_GB -> F_GX (GX zeroed by the caller), then mass-mean removal of GX
@@ -881,7 +888,7 @@ int sem_ax(sem_ctx* c, const void* u, void* w, double h1, double h2, int buf_pre
     Batch b = make_batch(one, 1);
     AxLaunch a;
     a.src = -1; a.src_vj = 0; a.dst = -1; a.ncomp = 1; a.hsel = -1; a.h1 = h1; a.h2 = h2;
-    a.precond = -1; a.tpc = P64; a.pdot = -1; a.gate = -1; a.tu = tu; a.tg = tg; a.tc = tc;
+    a.precond = -1; a.tpc = P64; a.pdot = -1; a.gate = -1; a.tu = tu; a.tg = tg; a.tc = tc; a.out64 = 0;
     a.u_raw = u; a.w_raw = w;
     {
         ProfScope ps(SEM_PROF_AX_ANY, c->stream);
@@ -947,7 +954,7 @@ int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stat
     int status = 0;
     for (int st = 0; st < nsteps; ++st) {
         fin(b, FIN_STEP_BEGIN, s);
-        vec(b, V_IDV, 1, P64, -1, s);
+        vec(b, V_IDV, 1, P64, I_IDVSTALE, s);
         // (i) explicit terms: convection, old pressure gradient, BDF/EXT history
         launch_conv(b, lx, r.conv_m, r.conv_c, s);
         launch_opgrad(b, lx, r.opg_m, r.opg_c, F_P, F_GP, s);
@@ -965,8 +972,7 @@ int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stat
         launch_dssum(b, F_RP, 1, P64, -1, nullptr, s);
         vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_RP);
         fin(b, FIN_MEAN_UNIQUE, s);
-        vec(b, V_SUB_MEAN, 1, P64, -1, s, F_RP, S_H2);
-        vec(b, V_COPY, 1, P64, -1, s, F_RP, F_GB);
+        vec(b, V_SUB_MEAN, 1, P64, -1, s, F_RP, S_H2);  // F_GB aliases F_RP
         vec(b, V_ZERO, 1, P64, -1, s, F_GX);
         rc = pressure_solve(ctxs, b, s);
         if (rc) return rc;

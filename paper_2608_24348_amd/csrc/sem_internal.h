@@ -60,7 +60,7 @@ enum FieldId : int {
     F_PP, F_PPb, F_PPc,
     F_PW, F_PWb, F_PWc,
     // GMRES (fp64 basis and iterate; pressure-Ax precision for z and w)
-    F_V,                        // (m+1) vectors, stride np
+    F_V,                        // (m+1) GMRES basis vectors, stride np, basis storage precision
     F_GW,                       // operator output of the Arnoldi step (fp64)
     F_GWD,                      // fp64 working vector of the Arnoldi step
     F_GB,                       // rhs (fp64)
@@ -131,6 +131,8 @@ enum IntId : int {
     I_GEND,                     // GMRES: cycle end pending (phase 1)
     I_GNORM,                    // GMRES: normalisation of V_J pending
     I_VMAXREF,                  // velocity refinement cycle limit
+    I_GENDAX,                   // GMRES: cycle end with a nonzero iterate (true residual needs A x)
+    I_IDVSTALE,                 // velocity Jacobi diagonal must be rebuilt for new (h1,h2)
     I_PCNT,                     // NRED: number of partials the last producer of each slot wrote
     NINT = I_PCNT + NRED + 8
 };
@@ -217,6 +219,7 @@ struct AxLaunch {
     int pdot;                   // reduction slot for sum(u*w) over local points, or -1
     int gate;                   // I index checked per component (nonzero = run), or -1
     int tu, tg, tc;             // PrecId of vectors, geometry and arithmetic
+    int out64;                  // nonzero: the output is fp64 whatever tu is (Arnoldi operator output)
     const void* u_raw;          // direct pointers (standalone sem_ax), used when src < 0
     void* w_raw;
 };
@@ -244,7 +247,7 @@ enum VecOp : int {
     V_PCG_UPD,        // PX += a PP, PR -= a PW, PZ = PR*IDV, partials (r,r) -> R_B+c, (r,z) -> R_C+c
     V_PCG_P,          // PP = PZ + b PP
     V_US_COPY,        // US = U
-    V_US_ADD,         // US += PX
+    V_US_ADD,         // US += PX  (f0 == 1: US = U + PX)
     V_RHS,            // velocity rhs from the BDF/EXT history
     V_IDV,            // velocity Jacobi inverse diagonal for the current (h1,h2)
     V_SUM_UNIQUE,     // partial sum(f/mult) of field f0 -> R_X3
@@ -257,7 +260,7 @@ enum VecOp : int {
     V_GM_UPD_NORM,    // GWD -= sum GH2_i V_i ; partial |GWD|^2 -> R_GN
     V_GM_NORMALIZE,   // V_J = GWD * S_GNSCALE
     V_GM_XUPD,        // GX += IDP * sum_{i<jend} y_i V_i
-    V_GM_RESID,       // GWD = GB - GWD, partial |GWD|^2 -> R_GN
+    V_GM_RESID,       // GWD = GB - GWD (GB alone when I_GENDAX == 0), partial |GWD|^2 -> R_GN
     V_CORRECT,        // U_new = US - dt/beta0 GP / Bsum  (into the u^{n-2} buffer); P += GX
     V_AXPY_RAW,       // raw y += a x (fp64), used by the standalone API
     NVECOP
@@ -267,6 +270,7 @@ struct VecArgs {
     int op, gate, ncomp;
     int tv;           // PrecId of the velocity/pressure solver vectors
     int ta;           // PrecId of the per-thread partial sums (fp64 or fp32)
+    int tb;           // PrecId of the GMRES basis storage
     int f0, f1;
     double a;
     const void* x_raw;
