@@ -185,6 +185,18 @@ int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stat
  * receives p with its mass-weighted mean removed. */
 int sem_poisson_solve(sem_ctx* const* ctxs, int n, const void* const* rhs, void* const* sol, sem_solve_stats* stats);
 
+/* The same solve in steps, for serving loops that change the batch between
+ * iteration chunks (continuous batching): sem_poisson_begin starts the solves
+ * of n contexts (copies and mean-centres rhs[i], zero initial guess);
+ * sem_poisson_advance runs up to max_iters Arnoldi steps on any batch of
+ * begun contexts (same order/policy/stream; finished ones idle) and sets
+ * active[i] (nullable) to whether context i still iterates (synchronises);
+ * sem_poisson_finish removes the mass-weighted mean, copies the solution to
+ * sol (device fp64, nullable) and fills st (nullable). */
+int sem_poisson_begin(sem_ctx* const* ctxs, int n, const void* const* rhs);
+int sem_poisson_advance(sem_ctx* const* ctxs, int n, int max_iters, int* active);
+int sem_poisson_finish(sem_ctx* ctx, void* sol, sem_solve_stats* st);
+
 /* Field access for checkpoints and tests.  which: SEM_F_*; component fields
  * use which + c.  src/dst are fp64 arrays of E*lx^3 values, on the host when
  * is_host != 0 (the call then synchronises), else device pointers. */
@@ -204,6 +216,16 @@ enum {
 };
 int sem_get_field(sem_ctx* ctx, int which, void* dst, int is_host);
 int sem_set_field(sem_ctx* ctx, int which, const void* src, int is_host);
+/* Mass matrix: out = B o f (element-local), plus dssum when flags &
+ * SEM_ASSEMBLE (out then is the assembled load vector of f).  Device fp64
+ * arrays of E*lx^3 values; asynchronous. */
+int sem_mass(sem_ctx* ctx, const double* f, double* out, int flags);
+
+/* Node fields for synthetic inputs: what = 0, 1, 2 writes the x, y or z
+ * coordinate of every local node; what = 3 writes amp sin x sin y sin z (the
+ * manufactured Poisson solution family).  out: device fp64, E*lx^3. */
+int sem_node_field(sem_ctx* ctx, int what, double amp, double* out);
+
 /* time and step counter (for checkpoint/restart) */
 int sem_set_clock(sem_ctx* ctx, double t, int step);
 

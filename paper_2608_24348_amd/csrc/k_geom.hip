@@ -252,6 +252,30 @@ __global__ void __launch_bounds__(256) init_kernel(Batch bt, int init, MeshParam
     }
 }
 
+// node fields for inputs: what = 0,1,2 -> coordinate x_c; 3 -> amp sin x sin y sin z
+template <int LX>
+__global__ void __launch_bounds__(256) node_field_kernel(Batch bt, MeshParams mp, int what, double amp, double* out)
+{
+    constexpr int L3 = LX * LX * LX;
+    __shared__ double sxi[LX];
+    const int g = blockIdx.x;
+    const int ri = find_req(bt.eb, bt.n, g);
+    const ReqDesc* R = bt.r[ri];
+    const int blk = g - bt.eb[ri];
+    for (int q = threadIdx.x; q < LX; q += blockDim.x) sxi[q] = R->D64[LX * LX + LX + q];
+    __syncthreads();
+    for (int el = 0; el < R->epb; ++el) {
+        const int e = blk * R->epb + el;
+        if (e >= R->E) break;
+        for (int q = threadIdx.x; q < L3; q += blockDim.x) {
+            int i = q % LX, j = (q / LX) % LX, k = q / (LX * LX);
+            double X[3];
+            node_xyz(mp, sxi, e, i, j, k, X);
+            out[(long long)e * L3 + q] = what < 3 ? X[what] : amp * sin(X[0]) * sin(X[1]) * sin(X[2]);
+        }
+    }
+}
+
 #define SEM_LX_SWITCH(lx, CALL) \
     switch (lx) { \
     case 3: CALL(3); break; case 4: CALL(4); break; case 5: CALL(5); break; case 6: CALL(6); break; \
@@ -285,6 +309,12 @@ void launch_geo_cast(const Batch& b, int lx, int want32, int want16, hipStream_t
         SEM_LX_SWITCH(lx, GO)
 #undef GO
     }
+}
+void launch_node_field(const Batch& b, int lx, const MeshParams& mp, int what, double amp, double* out, hipStream_t s)
+{
+#define GO(L) hipLaunchKernelGGL(node_field_kernel<L>, dim3(b.eb[b.n]), dim3(256), 0, s, b, mp, what, amp, out)
+    SEM_LX_SWITCH(lx, GO)
+#undef GO
 }
 void launch_init_fields(const Batch& b, int lx, int init, const MeshParams& mp, hipStream_t s)
 {

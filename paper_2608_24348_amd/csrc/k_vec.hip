@@ -228,6 +228,13 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         }
         break;
     }
+    case V_MASS_RAW: {
+        const SEM_GLOBAL double* x = gp((const double*)a.x_raw);
+        SEM_GLOBAL double* y = gp((double*)a.y_raw);
+        auto B = fld<double>(R, F_B64);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) y[p] = B[p] * x[p];
+        break;
+    }
     case V_AXPY_RAW: {
         const double* x = (const double*)a.x_raw;
         double* y = (double*)a.y_raw;

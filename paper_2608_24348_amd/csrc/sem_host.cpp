@@ -7,6 +7,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -170,6 +174,11 @@ bool op_supported(int m, int c)
 
 }  // namespace
 
+// shared-node lists of one periodic box shape (nel, order)
+struct Tuples {
+    std::vector<int> idx2, idx4, idx8;
+};
+
 // ------------------------------------------------------------------ context
 struct sem_ctx {
     sem_mesh_desc mesh;
@@ -181,7 +190,7 @@ struct sem_ctx {
     int n2, n4, n8;
     std::vector<double> D64tab;
     std::vector<float> D32tab;
-    std::vector<int> idx2, idx4, idx8;
+    std::shared_ptr<const struct Tuples> tup;  // shared-node lists (cached per mesh shape)
     double vol;
     // layout
     size_t off_desc, off_S, off_I, off_part, off_D64, off_D32, off_i2, off_i4, off_i8;
@@ -289,12 +298,11 @@ int resolve_policy(const sem_precision* p, Resolved& r)
 
 // shared-node tuples of the periodic box, grouped by multiplicity, each
 // tuple sorted by local index and emitted once (by its smallest copy)
-void build_tuples(sem_ctx* c)
+void build_tuples_into(const sem_ctx* c, Tuples* T)
 {
     const int nx = c->mesh.nel[0], ny = c->mesh.nel[1], nz = c->mesh.nel[2];
     const int N = c->N, lx = c->lx;
     const long long L3 = (long long)lx * lx * lx;
-    c->idx2.clear(); c->idx4.clear(); c->idx8.clear();
     for (int e = 0; e < c->E; ++e) {
         const int ex = e % nx, ey = (e / nx) % ny, ez = e / (nx * ny);
         for (int k = 0; k < lx; ++k)
@@ -330,13 +338,35 @@ void build_tuples(sem_ctx* c)
                     std::sort(ids, ids + m);
                     const int self = (int)(e * L3 + i + lx * (j + lx * k));
                     if (ids[0] != self) continue;
-                    std::vector<int>& dst = m == 2 ? c->idx2 : m == 4 ? c->idx4 : c->idx8;
+                    std::vector<int>& dst = m == 2 ? T->idx2 : m == 4 ? T->idx4 : T->idx8;
                     dst.insert(dst.end(), ids, ids + m);
                 }
     }
-    c->n2 = (int)(c->idx2.size() / 2);
-    c->n4 = (int)(c->idx4.size() / 4);
-    c->n8 = (int)(c->idx8.size() / 8);
+}
+
+// The lists depend only on (nel, order): contexts of the same shape share one
+// immutable copy (serving creates many requests of few shapes).
+void build_tuples(sem_ctx* c)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int>, std::shared_ptr<const Tuples>> cache;
+    const auto key = std::make_tuple(c->mesh.nel[0], c->mesh.nel[1], c->mesh.nel[2], c->N);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) c->tup = it->second;
+    }
+    if (!c->tup) {
+        auto T = std::make_shared<Tuples>();
+        build_tuples_into(c, T.get());
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it == cache.end()) it = cache.emplace(key, std::shared_ptr<const Tuples>(T)).first;
+        c->tup = it->second;
+    }
+    c->n2 = (int)(c->tup->idx2.size() / 2);
+    c->n4 = (int)(c->tup->idx4.size() / 4);
+    c->n8 = (int)(c->tup->idx8.size() / 8);
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -352,9 +382,9 @@ void build_layout(sem_ctx* c)
     c->off_part = take(sizeof(double) * (size_t)NRED * c->pstride);
     c->off_D64 = take(sizeof(double) * (c->lx * c->lx + 2 * c->lx));
     c->off_D32 = take(sizeof(float) * (c->lx * c->lx + 2 * c->lx));
-    c->off_i2 = take(sizeof(int) * c->idx2.size());
-    c->off_i4 = take(sizeof(int) * c->idx4.size());
-    c->off_i8 = take(sizeof(int) * c->idx8.size());
+    c->off_i2 = take(sizeof(int) * c->tup->idx2.size());
+    c->off_i4 = take(sizeof(int) * c->tup->idx4.size());
+    c->off_i8 = take(sizeof(int) * c->tup->idx8.size());
     for (int f = 0; f < NFIELD; ++f) { c->foff[f] = 0; c->fbytes[f] = 0; }
     auto field = [&](int f, size_t bytes) { c->fbytes[f] = bytes; c->foff[f] = take(bytes); };
     const size_t d = 8 * (size_t)np;
@@ -600,27 +630,44 @@ void gmres_iteration(const Batch& b, int lx, const Resolved& r, hipStream_t s)
     vec(b, V_GM_NORMALIZE, 1, P64, I_GNORM, s, -1, -1, P64, r.tb);
 }
 
-// GMRES on F_GB -> F_GX (GX zeroed by the caller), then mass-mean removal of GX
-int pressure_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
+// GMRES on F_GB -> F_GX in three pieces so a serving loop can change the
+// batch between iteration chunks (all solver state is per request, on the
+// device): start (GX zeroed by the caller), advance by up to max_iters Arnoldi
+// steps, finish (mass-mean removal of GX).
+void gmres_start(const Batch& b, hipStream_t s) { fin(b, FIN_GM_START, s); }
+
+// returns the number of requests still iterating, or a negative status
+int gmres_advance(sem_ctx* const* ctxs, const Batch& b, hipStream_t s, int max_iters)
 {
     sem_ctx* c0 = ctxs[0];
-    const int lx = c0->lx;
-    int* hf = c0->hflags;
-    fin(b, FIN_GM_START, s);
     const int K = poll_k();
-    const int m = c0->flow.gmres_restart;
-    const int limit = c0->flow.pres_maxit + c0->flow.pres_maxit / std::max(1, m) + 4;
-    int guard = 0;
-    for (;;) {
-        for (int q = 0; q < K; ++q) gmres_iteration(b, lx, c0->rs, s);
-        guard += K;
-        int act = poll(b, I_GACT, 1, hf, s);
-        if (act < 0) return act;
-        if (act == 0 || guard > limit) break;
+    int done = 0, act = 0;
+    while (done < max_iters) {
+        const int k = std::min(K, max_iters - done);
+        for (int q = 0; q < k; ++q) gmres_iteration(b, c0->lx, c0->rs, s);
+        done += k;
+        act = poll(b, I_GACT, 1, c0->hflags, s);
+        if (act <= 0) return act;
     }
+    return act;
+}
+
+void gmres_finish(const Batch& b, hipStream_t s)
+{
     vec(b, V_SUM_MASS, 1, P64, -1, s, F_GX);
     fin(b, FIN_MEAN_MASS, s);
     vec(b, V_SUB_MEAN, 1, P64, -1, s, F_GX, -1);
+}
+
+int pressure_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
+{
+    sem_ctx* c0 = ctxs[0];
+    const int m = c0->flow.gmres_restart;
+    const int limit = c0->flow.pres_maxit + c0->flow.pres_maxit / std::max(1, m) + 4;
+    gmres_start(b, s);
+    int rc = gmres_advance(ctxs, b, s, limit);
+    if (rc < 0) return rc;
+    gmres_finish(b, s);
     return check_hip_last();
 }
 
@@ -792,9 +839,12 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     HIPCHK(hipMemcpyAsync(d.I, I.data(), sizeof(int) * NINT, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync((void*)d.D64, c->D64tab.data(), sizeof(double) * c->D64tab.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync((void*)d.D32, c->D32tab.data(), sizeof(float) * c->D32tab.size(), hipMemcpyHostToDevice, s));
-    if (!c->idx2.empty()) HIPCHK(hipMemcpyAsync((void*)d.idx2, c->idx2.data(), sizeof(int) * c->idx2.size(), hipMemcpyHostToDevice, s));
-    if (!c->idx4.empty()) HIPCHK(hipMemcpyAsync((void*)d.idx4, c->idx4.data(), sizeof(int) * c->idx4.size(), hipMemcpyHostToDevice, s));
-    if (!c->idx8.empty()) HIPCHK(hipMemcpyAsync((void*)d.idx8, c->idx8.data(), sizeof(int) * c->idx8.size(), hipMemcpyHostToDevice, s));
+    const Tuples& T = *c->tup;
+    if (!T.idx2.empty()) HIPCHK(hipMemcpyAsync((void*)d.idx2, T.idx2.data(), sizeof(int) * T.idx2.size(), hipMemcpyHostToDevice, s));
+    if (!T.idx4.empty()) HIPCHK(hipMemcpyAsync((void*)d.idx4, T.idx4.data(), sizeof(int) * T.idx4.size(), hipMemcpyHostToDevice, s));
+    if (!T.idx8.empty()) HIPCHK(hipMemcpyAsync((void*)d.idx8, T.idx8.data(), sizeof(int) * T.idx8.size(), hipMemcpyHostToDevice, s));
+    // the copies read pageable host memory owned by the cache: finish them before returning
+    HIPCHK(hipStreamSynchronize(s));
     c->bound = true;
 
     sem_ctx* one[1] = {c};
@@ -1049,6 +1099,63 @@ int sem_poisson_solve(sem_ctx* const* ctxs, int n, const void* const* rhs, void*
     return check_hip_last();
 }
 
+int sem_poisson_begin(sem_ctx* const* ctxs, int n, const void* const* rhs)
+{
+    int rc = check_batch(ctxs, n, SEM_MODE_POISSON);
+    if (rc) return rc;
+    if (!rhs) return fail(SEM_EINVAL, "null rhs");
+    sem_ctx* c0 = ctxs[0];
+    hipStream_t s = c0->stream;
+    for (int i = 0; i < n; ++i) {
+        if (!rhs[i]) return fail(SEM_EINVAL, "null rhs entry");
+        HIPCHK(hipMemcpyAsync(ctxs[i]->hdesc.f[F_GB], rhs[i], 8 * (size_t)ctxs[i]->np, hipMemcpyDeviceToDevice, s));
+    }
+    Batch b = make_batch(ctxs, n);
+    vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_GB);
+    fin(b, FIN_MEAN_UNIQUE, s);
+    vec(b, V_SUB_MEAN, 1, P64, -1, s, F_GB, -1);
+    vec(b, V_ZERO, 1, P64, -1, s, F_GX);
+    gmres_start(b, s);
+    return check_hip_last();
+}
+
+int sem_poisson_advance(sem_ctx* const* ctxs, int n, int max_iters, int* active)
+{
+    int rc = check_batch(ctxs, n, SEM_MODE_POISSON);
+    if (rc) return rc;
+    if (max_iters < 1) return fail(SEM_EINVAL, "max_iters must be >= 1");
+    Batch b = make_batch(ctxs, n);
+    rc = gmres_advance(ctxs, b, ctxs[0]->stream, max_iters);
+    if (rc < 0) return rc;
+    if (active)
+        for (int i = 0; i < n; ++i) active[i] = ctxs[0]->hflags[i] != 0;
+    return 0;
+}
+
+int sem_poisson_finish(sem_ctx* c, void* sol, sem_solve_stats* st)
+{
+    int rc = bind_check(c);
+    if (rc) return rc;
+    if (c->flow.mode < SEM_MODE_POISSON) return fail(SEM_EINVAL, "context mode has no solver workspace");
+    sem_ctx* one[1] = {c};
+    Batch b = make_batch(one, 1);
+    hipStream_t s = c->stream;
+    gmres_finish(b, s);
+    if (sol) HIPCHK(hipMemcpyAsync(sol, c->hdesc.f[F_GX], 8 * (size_t)c->np, hipMemcpyDeviceToDevice, s));
+    int it = 0, nan = 0;
+    double res = 0;
+    HIPCHK(hipMemcpyAsync(&it, c->hdesc.I + I_GIT, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&nan, c->hdesc.I + I_NAN, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&res, c->hdesc.S + S_GBETA, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st) {
+        st->iters = it;
+        st->res = res;
+        st->status = nan ? SEM_ENAN : (res > c->flow.pres_tol ? SEM_ENOTCONV : SEM_OK);
+    }
+    return check_hip_last();
+}
+
 int sem_prof_start(int kclass)
 {
     if (kclass < SEM_PROF_AX_VEL || kclass > SEM_PROF_AX_ANY) return fail(SEM_EINVAL, "unknown profiling class");
@@ -1132,6 +1239,33 @@ int sem_set_field(sem_ctx* c, int which, const void* src, int is_host)
     HIPCHK(hipMemcpyAsync(p, src, 8 * (size_t)c->np, is_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, c->stream));
     if (is_host) HIPCHK(hipStreamSynchronize(c->stream));
     return 0;
+}
+
+int sem_mass(sem_ctx* c, const double* f, double* out, int flags)
+{
+    int rc = bind_check(c);
+    if (rc) return rc;
+    if (!f || !out) return fail(SEM_EINVAL, "null field pointer");
+    sem_ctx* one[1] = {c};
+    Batch b = make_batch(one, 1);
+    VecArgs a;
+    memset(&a, 0, sizeof(a));
+    a.op = V_MASS_RAW; a.gate = -1; a.ncomp = 1; a.tv = P64; a.ta = P64; a.tb = P64; a.f0 = -1; a.f1 = -1;
+    a.x_raw = f; a.y_raw = out;
+    launch_vec(b, a, c->stream);
+    if (flags & SEM_ASSEMBLE) launch_dssum(b, -1, 1, P64, -1, out, c->stream);
+    return check_hip_last();
+}
+
+int sem_node_field(sem_ctx* c, int what, double amp, double* out)
+{
+    int rc = bind_check(c);
+    if (rc) return rc;
+    if (!out || what < 0 || what > 3) return fail(SEM_EINVAL, "bad node field request");
+    sem_ctx* one[1] = {c};
+    Batch b = make_batch(one, 1);
+    launch_node_field(b, c->lx, c->mp, what, amp, out, c->stream);
+    return check_hip_last();
 }
 
 int sem_set_clock(sem_ctx* c, double t, int step)

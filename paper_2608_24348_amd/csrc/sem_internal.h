@@ -233,6 +233,7 @@ void launch_diag_a(const Batch& b, int lx, hipStream_t s);
 void launch_geo_post(const Batch& b, hipStream_t s);
 void launch_geo_cast(const Batch& b, int lx, int want32, int want16, hipStream_t s);
 void launch_init_fields(const Batch& b, int lx, int init, const MeshParams& mp, hipStream_t s);
+void launch_node_field(const Batch& b, int lx, const MeshParams& mp, int what, double amp, double* out, hipStream_t s);
 
 // SEM operators (output fp64)
 void launch_conv(const Batch& b, int lx, int tm, int tc, hipStream_t s);
@@ -263,6 +264,7 @@ enum VecOp : int {
     V_GM_RESID,       // GWD = GB - GWD (GB alone when I_GENDAX == 0), partial |GWD|^2 -> R_GN
     V_CORRECT,        // U_new = US - dt/beta0 GP / Bsum  (into the u^{n-2} buffer); P += GX
     V_AXPY_RAW,       // raw y += a x (fp64), used by the standalone API
+    V_MASS_RAW,       // raw y = B x (fp64)
     NVECOP
 };
 

@@ -75,7 +75,8 @@ class Diag(C.Structure):
 EXPORTS = ["sem_setup", "sem_workspace_bytes", "sem_bind", "sem_ax", "sem_dssum", "sem_fluid_step",
            "sem_poisson_solve", "sem_get_field", "sem_set_field", "sem_set_clock", "sem_diagnostics",
            "sem_conv", "sem_opgrad", "sem_wdiv", "sem_sizes", "sem_destroy", "sem_strerror", "sem_last_error",
-           "sem_prof_start", "sem_prof_stop"]
+           "sem_prof_start", "sem_prof_stop", "sem_poisson_begin", "sem_poisson_advance", "sem_poisson_finish",
+           "sem_mass", "sem_node_field"]
 PROF_AX_VEL, PROF_AX_PRES, PROF_GM_DOTS, PROF_GM_UPD_DOTS, PROF_GM_UPD_NORM, PROF_DSSUM_PRES, PROF_AX_ANY = range(1, 8)
 
 _lib = None
@@ -110,6 +111,11 @@ def load():
     L.sem_strerror.restype = C.c_char_p
     L.sem_strerror.argtypes = [C.c_int]
     L.sem_last_error.restype = C.c_char_p
+    L.sem_poisson_begin.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp)]
+    L.sem_poisson_advance.argtypes = [C.POINTER(vp), C.c_int, C.c_int, C.POINTER(C.c_int)]
+    L.sem_poisson_finish.argtypes = [vp, vp, C.POINTER(SolveStats)]
+    L.sem_mass.argtypes = [vp, vp, vp, C.c_int]
+    L.sem_node_field.argtypes = [vp, C.c_int, C.c_double, vp]
     L.sem_prof_start.argtypes = [C.c_int]
     L.sem_prof_stop.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     _lib = L
@@ -312,6 +318,20 @@ class Context:
         _check(self.L.sem_diagnostics(self.h, C.byref(d)))
         return {"t": d.t, "ke": d.ke, "enst": d.enst, "maxdiv": d.maxdiv, "step": d.step}
 
+    def mass(self, f, out=None, assemble=True):
+        """out = B o f (assembled when assemble); fp64 device tensors."""
+        torch = _torch()
+        out = torch.empty_like(f) if out is None else out
+        _check(self.L.sem_mass(self.h, C.c_void_p(f.data_ptr()), C.c_void_p(out.data_ptr()), ASSEMBLE if assemble else 0))
+        return out
+
+    def node_field(self, what, amp=1.0):
+        """Device fp64 tensor of node coordinates (what 0..2) or amp sin x sin y sin z (what 3)."""
+        torch = _torch()
+        out = torch.empty(self.np, dtype=torch.float64, device=self.device)
+        _check(self.L.sem_node_field(self.h, int(what), float(amp), C.c_void_p(out.data_ptr())))
+        return out
+
     def conv(self, u3):
         torch = _torch()
         outs = [torch.empty_like(u3[0]) for _ in range(3)]
@@ -361,6 +381,30 @@ def prof_stop():
     ms, n = C.c_double(), C.c_int64()
     _check(load().sem_prof_stop(C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+def poisson_begin(ctxs, rhs):
+    """Start batched Poisson solves (rhs: fp64 device tensors, assembled)."""
+    n = len(ctxs)
+    arr = (C.c_void_p * n)(*[c.h for c in ctxs])
+    r = (C.c_void_p * n)(*[C.c_void_p(t.data_ptr()) for t in rhs])
+    _check(load().sem_poisson_begin(arr, n, r))
+
+
+def poisson_advance(ctxs, max_iters):
+    """Run up to max_iters Arnoldi steps on a batch of begun solves; returns the still-active flags."""
+    n = len(ctxs)
+    arr = (C.c_void_p * n)(*[c.h for c in ctxs])
+    act = (C.c_int * n)()
+    _check(load().sem_poisson_advance(arr, n, int(max_iters), act))
+    return [bool(a) for a in act]
+
+
+def poisson_finish(ctx, sol=None):
+    """Finish one solve: mean removal, copy to sol (fp64 device tensor or None); returns its stats."""
+    st = SolveStats()
+    _check(load().sem_poisson_finish(ctx.h, C.c_void_p(sol.data_ptr()) if sol is not None else None, C.byref(st)))
+    return {"iters": st.iters, "res": st.res, "status": st.status}
 
 
 def poisson_solve(ctxs, rhs, sol):
