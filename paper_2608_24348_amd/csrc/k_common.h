@@ -79,19 +79,6 @@ template <> __device__ __forceinline__ __half to<__half, double>(double v) { ret
 template <> __device__ __forceinline__ __hip_bfloat16 to<__hip_bfloat16, float>(float v) { return __float2bfloat16(v); }
 template <> __device__ __forceinline__ __hip_bfloat16 to<__hip_bfloat16, double>(double v) { return __float2bfloat16(d2f_round_odd(v)); }
 
-// 1 / multiplicity of local point q (0 <= q < lx^3) of a conforming periodic
-// box mesh: every coordinate on an element face doubles the number of copies.
-__device__ __forceinline__ double inv_mult(int q, int lx)
-{
-    int i = q % lx, t = q / lx, j = t % lx, k = t / lx;
-    int n = lx - 1;
-    double r = 1.0;
-    if (i == 0 || i == n) r *= 0.5;
-    if (j == 0 || j == n) r *= 0.5;
-    if (k == 0 || k == n) r *= 0.5;
-    return r;
-}
-
 // wavefront sum (64 lanes), fixed butterfly order -> deterministic
 template <typename A> __device__ __forceinline__ A wave_sum(A v)
 {

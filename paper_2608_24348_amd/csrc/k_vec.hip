@@ -4,6 +4,7 @@
 // the BDF/EXT step on the device.  Inner products of assembled vectors weight
 // each local point by 1/multiplicity, i.e. they run over unique nodes.
 #include "k_common.h"
+#include "k_fin.h"
 
 namespace semk {
 
@@ -31,6 +32,28 @@ template <> __device__ __forceinline__ int idv_field<double>() { return F_IDV64;
 template <typename TV> __device__ __forceinline__ int idp_field() { return F_IDP32; }
 template <> __device__ __forceinline__ int idp_field<double>() { return F_IDP64; }
 
+// 1/multiplicity of the points a thread visits in a point-wise loop
+// (p = p0 + threadIdx.x, p += blockDim.x over whole elements): the local
+// index q advances by blockDim.x mod lx^3 with one wrap, and the weight comes
+// from the per-request table after D, weights and nodes.
+struct MulWalk {
+    const SEM_GLOBAL double* tab;
+    int q, step, L3;
+    __device__ __forceinline__ MulWalk(const ReqDesc* R, const PtRange& pr)
+    {
+        L3 = (int)pr.L3;
+        tab = gp(R->D64) + R->lx * R->lx + 2 * R->lx;
+        q = (int)threadIdx.x % L3;
+        step = (int)blockDim.x % L3;
+    }
+    __device__ __forceinline__ double im() const { return tab[q]; }
+    __device__ __forceinline__ void next()
+    {
+        q += step;
+        if (q >= L3) q -= L3;
+    }
+};
+
 // partial of point-wise block blk; block 0 also records how many partials the slot holds
 __device__ __forceinline__ void put_partial(const ReqDesc* R, int slot, int blk, double v)
 {
@@ -50,7 +73,6 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
     const int c = blockIdx.y;
     if (!gate_ok(R, a.gate < 0 ? -1 : a.gate + (a.ncomp > 1 ? c : 0))) return;
     const PtRange pr = pt_range(R, blk);
-    const int lx = R->lx;
     const SEM_GLOBAL double* S = gp(R->S);
     double acc[2] = {0.0, 0.0};
 
@@ -59,10 +81,11 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         auto rhs = fld<double>(R, F_RHS + c);
         auto w = fld<double>(R, F_W64 + c);
         auto r = fldw<double>(R, F_R64 + c);
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+        MulWalk mw(R, pr);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x, mw.next()) {
             const double v = rhs[p] - w[p];
             r[p] = v;
-            acc[0] += v * v * inv_mult((int)((p - pr.p0) % pr.L3), lx);
+            acc[0] += v * v * mw.im();
         }
         double v2[1] = {acc[0]};
         block_sum<double, 1>(v2, red);
@@ -77,11 +100,12 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         auto z = fldw<TV>(R, F_PZ + c);
         auto pp = fldw<TV>(R, F_PP + c);
         A s = 0;
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+        MulWalk mw(R, pr);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x, mw.next()) {
             const TV rv = (TV)r64[p];
             const TV zv = rv * idv[p];
             x[p] = (TV)0; r[p] = rv; z[p] = zv; pp[p] = zv;
-            s += (A)(rv * zv) * (A)inv_mult((int)((p - pr.p0) % pr.L3), lx);
+            s += (A)(rv * zv) * (A)mw.im();
         }
         double v2[1] = {(double)s};
         block_sum<double, 1>(v2, red);
@@ -97,12 +121,13 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         auto pp = fld<TV>(R, F_PP + c);
         auto w = fld<TV>(R, F_PW + c);
         A rr = 0, rz = 0;
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+        MulWalk mw(R, pr);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x, mw.next()) {
             x[p] += alpha * pp[p];
             const TV rv = r[p] - alpha * w[p];
             const TV zv = rv * idv[p];
             r[p] = rv; z[p] = zv;
-            const A im = (A)inv_mult((int)((p - pr.p0) % pr.L3), lx);
+            const A im = (A)mw.im();
             rr += (A)(rv * rv) * im;
             rz += (A)(rv * zv) * im;
         }
@@ -172,9 +197,10 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
     case V_SUM_MASS: {
         const SEM_GLOBAL double* f = a.f0 >= 0 ? fld<double>(R, a.f0) : nullptr;
         auto B = fld<double>(R, F_B64);
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+        MulWalk mw(R, pr);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x, mw.next()) {
             const double fv = f ? f[p] : 1.0;
-            if (a.op == V_SUM_UNIQUE) acc[0] += fv * inv_mult((int)((p - pr.p0) % pr.L3), lx);
+            if (a.op == V_SUM_UNIQUE) acc[0] += fv * mw.im();
             else acc[0] += fv * B[p];
         }
         double v2[1] = {acc[0]};
@@ -204,10 +230,11 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         auto b = fld<double>(R, F_GB);
         auto w = fldw<double>(R, F_GWD);
         const bool ax = gp(R->I)[I_GENDAX] != 0;  // iterate nonzero: GWD holds A x
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+        MulWalk mw(R, pr);
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x, mw.next()) {
             const double v = ax ? b[p] - w[p] : b[p];
             w[p] = v;
-            acc[0] += v * v * inv_mult((int)((p - pr.p0) % pr.L3), lx);
+            acc[0] += v * v * mw.im();
         }
         double v2[1] = {acc[0]};
         block_sum<double, 1>(v2, red);
@@ -260,18 +287,18 @@ __device__ __forceinline__ void gm_body(const ReqDesc* R, const PtRange& pr, dou
 {
     const SEM_GLOBAL TB* V = fld<TB>(R, F_V);
     const long long np = R->np;
-    const int lx = R->lx;
     double h[NJ];
 #pragma unroll
     for (int i = 0; i < NJ; ++i) h[i] = MODE == 1 ? gp(R->S)[S_GHC + i] : MODE == 2 ? gp(R->S)[S_GH2 + i] : 0.0;
     const double mean = MODE == 1 ? gp(R->S)[S_GMEAN] : 0.0;
     auto w = fld<double>(R, F_GW);
     auto wd = fldw<double>(R, F_GWD);
-    for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+    MulWalk mw(R, pr);
+    for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x, mw.next()) {
         double vr[NJ];
 #pragma unroll
         for (int i = 0; i < NJ; ++i) vr[i] = (double)V[i * np + p];
-        const double im = inv_mult((int)((p - pr.p0) % pr.L3), lx);
+        const double im = mw.im();
         if (MODE == 0) {
             const double wv = w[p] * im;
             accm += wv;
@@ -435,302 +462,10 @@ void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s)
     else hipLaunchKernelGGL((vec_kernel<float, float>), grid, blk, 0, s, b, a);
 }
 
-// ------------------------------------------------------------------ finalise kernels
-// fixed-order sum of the partials of one slot (valid in thread 0)
-__device__ double slot_sum(const ReqDesc* R, int slot, double* red)
-{
-    double s = 0.0;
-    const SEM_GLOBAL double* p = gp(R->part) + (long long)slot * R->pstride;
-    const int cnt = gp(R->I)[I_PCNT + slot];
-    for (int q = threadIdx.x; q < cnt; q += blockDim.x) s += p[q];
-    double v[1] = {s};
-    block_sum<double, 1>(v, red);
-    return v[0];
-}
-__device__ double slot_max(const ReqDesc* R, int slot, double* red)
-{
-    double s = 0.0;
-    const SEM_GLOBAL double* p = gp(R->part) + (long long)slot * R->pstride;
-    const int cnt = gp(R->I)[I_PCNT + slot];
-    for (int q = threadIdx.x; q < cnt; q += blockDim.x) s = fmax(s, p[q]);
-    s = wave_max(s);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    double m = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
-    __syncthreads();
-    return m;
-}
-
-// fixed-order sums of nslots (<= 32) consecutive slots at once: 8 groups of
-// 32 threads, thread (g, s) adds partials g, g+8, ... of slot s; the 8 group
-// sums are then added in group order.  out must hold nslots values.
-__device__ void multi_slot_sum(const ReqDesc* R, int slot0, int nslots, double* out, double* scratch)
-{
-    const int t = threadIdx.x, sl = t & 31, g = t >> 5;
-    double acc = 0.0;
-    if (sl < nslots) {
-        const SEM_GLOBAL double* p = gp(R->part) + (long long)(slot0 + sl) * R->pstride;
-        const int cnt = gp(R->I)[I_PCNT + slot0 + sl];
-        for (int q = g; q < cnt; q += 8) acc += p[q];
-    }
-    scratch[t] = acc;
-    __syncthreads();
-    if (t < nslots) {
-        double v = 0.0;
-        for (int k = 0; k < 8; ++k) v += scratch[k * 32 + t];
-        out[t] = v;
-    }
-    __syncthreads();
-}
-
-__device__ __forceinline__ bool finite(double v) { return isfinite(v); }
-
+// ------------------------------------------------------------------ finalise kernel
 __global__ void __launch_bounds__(256) fin_kernel(Batch bt, FinArgs a)
 {
-    __shared__ double red[8 * 4];
-    __shared__ double sums[SEM_MAXM + 2];
-    __shared__ double scratch[256];
-    const int ri = blockIdx.x;
-    ReqDesc* R = (ReqDesc*)bt.r[ri];
-    SEM_GLOBAL double* S = gp(R->S);
-    SEM_GLOBAL int* I = gp(R->I);
-    const int t = threadIdx.x;
-    switch (a.op) {
-    case FIN_VINIT: {
-        for (int c = 0; c < 3; ++c) {
-            double s = slot_sum(R, R_A + c, red);
-            if (t == 0) {
-                double rn = sqrt(s);
-                S[S_R0 + c] = rn;
-                S[S_RN + c] = rn;
-                bool act = rn > S[S_VTOL] && I[I_VREF + c] < I[I_VMAXREF];
-                if (!finite(rn)) { I[I_NAN] = 1; act = false; }
-                if (act) I[I_VREF + c] += 1;
-                I[I_VACT + c] = act ? 1 : 0;
-            }
-        }
-        break;
-    }
-    case FIN_PCG_RHO: {
-        for (int c = 0; c < 3; ++c) {
-            double s = slot_sum(R, R_B + c, red);
-            if (t == 0 && I[I_VACT + c]) S[S_RHO + c] = s;
-        }
-        break;
-    }
-    case FIN_PCG_ALPHA: {
-        for (int c = 0; c < 3; ++c) {
-            if (!I[I_VACT + c]) continue;  // uniform per block
-            double s = slot_sum(R, R_A + c, red);
-            if (t == 0) S[S_ALPHA + c] = S[S_RHO + c] / s;
-        }
-        break;
-    }
-    case FIN_PCG_BETA: {
-        for (int c = 0; c < 3; ++c) {
-            if (!I[I_VACT + c]) continue;
-            double rr = slot_sum(R, R_B + c, red);
-            double rz = slot_sum(R, R_C + c, red);
-            if (t == 0) {
-                double rn = sqrt(rr);
-                S[S_RN + c] = rn;
-                I[I_VIT + c] += 1;
-                if (!finite(rn)) { I[I_NAN] = 1; I[I_VACT + c] = 0; }
-                else if (rn <= S[S_VTOL] || I[I_VIT + c] >= I[I_VMAXIT]) I[I_VACT + c] = 0;
-                else { S[S_BETA + c] = rz / S[S_RHO + c]; S[S_RHO + c] = rz; }
-            }
-        }
-        break;
-    }
-    case FIN_MEAN_UNIQUE: {
-        double s = slot_sum(R, R_X3, red);
-        if (t == 0) S[S_MEAN] = s / (double)R->nglob;
-        break;
-    }
-    case FIN_MEAN_MASS: {
-        double s = slot_sum(R, R_X3, red);
-        if (t == 0) S[S_MEAN] = s / S[S_VOL];
-        break;
-    }
-    case FIN_GM_H1:
-    case FIN_GM_H2: {
-        if (!I[I_GARN]) break;
-        const int J = I[I_GJ];
-        multi_slot_sum(R, R_GM, J + 1, sums, scratch);
-        if (t <= J) S[(a.op == FIN_GM_H1 ? S_GHC : S_GH2) + t] = sums[t];
-        if (a.op == FIN_GM_H1) {
-            double s = slot_sum(R, R_GMEAN, red);
-            if (t == 0) S[S_GMEAN] = s / (double)R->nglob;
-        }
-        if (t == 0) I[I_GNORM] = 0;
-        break;
-    }
-    case FIN_GM_COL: {
-        if (!I[I_GARN]) break;
-        double hn2 = slot_sum(R, R_GN, red);
-        if (t == 0) {
-            const int m = I[I_GM];
-            const int J = I[I_GJ];
-            SEM_GLOBAL double* H = S + S_GH;
-            SEM_GLOBAL double* cs = S + S_GCS;
-            SEM_GLOBAL double* sn = S + S_GSN;
-            SEM_GLOBAL double* gg = S + S_GG;
-            const double hn = sqrt(hn2);
-            for (int i = 0; i <= J; ++i) H[i * m + J] = S[S_GHC + i] + S[S_GH2 + i];
-            H[(J + 1) * m + J] = hn;
-            for (int i = 0; i < J; ++i) {
-                const double x = H[i * m + J], y = H[(i + 1) * m + J];
-                H[i * m + J] = cs[i] * x + sn[i] * y;
-                H[(i + 1) * m + J] = -sn[i] * x + cs[i] * y;
-            }
-            const double x = H[J * m + J], y = H[(J + 1) * m + J];
-            const double den = sqrt(x * x + y * y);
-            cs[J] = x / den;
-            sn[J] = y / den;
-            H[J * m + J] = den;
-            H[(J + 1) * m + J] = 0.0;
-            gg[J + 1] = -sn[J] * gg[J];
-            gg[J] = cs[J] * gg[J];
-            I[I_GIT] += 1;
-            const bool bad = !finite(gg[J + 1]) || !finite(den);
-            if (bad) I[I_NAN] = 1;
-            if (bad || fabs(gg[J + 1]) <= S[S_PTOL] || hn == 0.0 || J + 1 == m || I[I_GIT] >= I[I_GMAXIT]) {
-                const int jend = bad ? 0 : J + 1;
-                SEM_GLOBAL double* yv = S + S_GY;
-                for (int r = jend - 1; r >= 0; --r) {
-                    double s = gg[r];
-                    for (int k = r + 1; k < jend; ++k) s -= H[r * m + k] * yv[k];
-                    yv[r] = s / H[r * m + r];
-                }
-                I[I_GJEND] = jend;
-                I[I_GARN] = 0;
-                I[I_GEND] = 1;
-                I[I_GENDAX] = 1;
-                I[I_GNORM] = 0;
-            } else {
-                I[I_GJ] = J + 1;
-                S[S_GNSCALE] = 1.0 / hn;
-                I[I_GNORM] = 1;
-            }
-        }
-        break;
-    }
-    case FIN_GM_RESTART: {
-        if (!I[I_GEND]) break;
-        double s = slot_sum(R, R_GN, red);
-        if (t == 0) {
-            const double beta = sqrt(s);
-            S[S_GBETA] = beta;
-            I[I_GEND] = 0;
-            I[I_GENDAX] = 0;
-            if (!finite(beta)) I[I_NAN] = 1;
-            if (!finite(beta) || beta <= S[S_PTOL] || I[I_GIT] >= I[I_GMAXIT]) {
-                I[I_GACT] = 0; I[I_GARN] = 0; I[I_GNORM] = 0;
-            } else {
-                I[I_GJ] = 0;
-                SEM_GLOBAL double* gg = S + S_GG;
-                for (int i = 0; i <= SEM_MAXM; ++i) gg[i] = 0.0;
-                gg[0] = beta;
-                S[S_GNSCALE] = 1.0 / beta;
-                I[I_GARN] = 1; I[I_GNORM] = 1;
-            }
-        }
-        break;
-    }
-    case FIN_GM_START: {
-        // fresh solve from x = 0: the first cycle end computes r = b
-        if (t == 0) {
-            I[I_GJ] = 0; I[I_GJEND] = 0; I[I_GIT] = 0;
-            I[I_GACT] = 1; I[I_GARN] = 0; I[I_GEND] = 1; I[I_GENDAX] = 0; I[I_GNORM] = 0;
-        }
-        break;
-    }
-    case FIN_DIAG: {
-        double ke = slot_sum(R, R_X0, red);
-        double en = slot_sum(R, R_X1, red);
-        double md = slot_max(R, R_X2, red);
-        if (t == 0) {
-            S[S_KE] = ke / S[S_VOL];
-            S[S_ENST] = en / S[S_VOL];
-            S[S_MAXDIV] = md;
-            if (!finite(ke) || !finite(en)) I[I_NAN] = 1;
-        }
-        break;
-    }
-    case FIN_STEP_BEGIN: {
-        if (t == 0) {
-            const int torder = I[I_TORDER];
-            const int k = I[I_STEP] + 1 < torder ? I[I_STEP] + 1 : torder;
-            I[I_ORDER] = k;
-            double b0, b1 = 0, b2 = 0, b3 = 0, a1 = 0, a2 = 0, a3 = 0;
-            if (k == 1) { b0 = 1.0; b1 = 1.0; a1 = 1.0; }
-            else if (k == 2) { b0 = 1.5; b1 = 2.0; b2 = -0.5; a1 = 2.0; a2 = -1.0; }
-            else { b0 = 11.0 / 6.0; b1 = 3.0; b2 = -1.5; b3 = 1.0 / 3.0; a1 = 3.0; a2 = -3.0; a3 = 1.0; }
-            S[S_BETA0] = b0;
-            S[S_BDF] = b1; S[S_BDF + 1] = b2; S[S_BDF + 2] = b3;
-            S[S_EXT] = a1; S[S_EXT + 1] = a2; S[S_EXT + 2] = a3;
-            S[S_H1] = S[S_NU];
-            S[S_H2] = b0 / S[S_DT];
-            const bool stale = I[I_STEP] == 0 || S[S_IDV_H1] != S[S_H1] || S[S_IDV_H2] != S[S_H2];
-            I[I_IDVSTALE] = stale ? 1 : 0;
-            S[S_IDV_H1] = S[S_H1];
-            S[S_IDV_H2] = S[S_H2];
-            S[S_MEAN + 0] = 0.0;
-            for (int c = 0; c < 3; ++c) { I[I_VIT + c] = 0; I[I_VREF + c] = 0; I[I_VACT + c] = 0; }
-        }
-        break;
-    }
-    case FIN_STEP_END: {
-        if (t == 0) {
-            for (int c = 0; c < 3; ++c) {
-                void* un = R->f[F_UL2 + c];          // holds u^{n+1}
-                R->f[F_UL2 + c] = R->f[F_UL1 + c];
-                R->f[F_UL1 + c] = R->f[F_U + c];
-                R->f[F_U + c] = un;
-                void* bs = R->f[F_BNL2 + c];
-                R->f[F_BNL2 + c] = R->f[F_BNL1 + c];
-                R->f[F_BNL1 + c] = R->f[F_BN + c];
-                R->f[F_BN + c] = bs;
-            }
-            I[I_STEP] += 1;
-            S[S_TIME] += S[S_DT];
-        }
-        break;
-    }
-    case FIN_POLL: {
-        if (t == 0) {
-            int v = 0;
-            for (int c = 0; c < (a.ncomp > 1 ? a.ncomp : 1); ++c) v |= I[a.gate + c];
-            a.host_flags[ri] = v;
-        }
-        break;
-    }
-    case FIN_SUM_RAW: {
-        double s = slot_sum(R, a.f0, red);
-        if (t == 0) S[S_RED + a.gate] = s;
-        break;
-    }
-    case FIN_VOL: {
-        double s = slot_sum(R, R_X3, red);
-        if (t == 0) S[S_VOL] = s;
-        break;
-    }
-    case FIN_STATS: {
-        if (t == 0) {
-            double* o = a.host_stats + (long long)ri * SEM_NSTAT;  // pinned host memory
-            o[0] = S[S_TIME]; o[1] = S[S_KE]; o[2] = S[S_ENST]; o[3] = S[S_MAXDIV];
-            for (int c = 0; c < 3; ++c) { o[4 + c] = I[I_VIT + c]; o[7 + c] = S[S_RN + c]; }
-            o[10] = I[I_GIT]; o[11] = S[S_GBETA]; o[12] = I[I_NAN]; o[13] = I[I_STEP];
-            o[14] = I[I_VREF] + I[I_VREF + 1] + I[I_VREF + 2]; o[15] = I[I_ORDER];
-        }
-        break;
-    }
-    default: break;
-    }
-    (void)sums;
+    fin_body((ReqDesc*)bt.r[blockIdx.x], blockIdx.x, a);
 }
 
 void launch_fin(const Batch& b, const FinArgs& a, hipStream_t s)

@@ -205,6 +205,9 @@ struct sem_ctx {
     ReqDesc hdesc;
     int* hflags = nullptr;  // pinned host flags for polls
     MeshParams mp;
+    // iteration counts of the previous step: where the host first reads the
+    // convergence flags (launches past convergence are gated no-ops)
+    int pred_v = 4, pred_p = 4;
 };
 
 namespace {
@@ -380,8 +383,8 @@ void build_layout(sem_ctx* c)
     c->off_S = take(sizeof(double) * NSCALAR);
     c->off_I = take(sizeof(int) * NINT);
     c->off_part = take(sizeof(double) * (size_t)NRED * c->pstride);
-    c->off_D64 = take(sizeof(double) * (c->lx * c->lx + 2 * c->lx));
-    c->off_D32 = take(sizeof(float) * (c->lx * c->lx + 2 * c->lx));
+    c->off_D64 = take(sizeof(double) * c->D64tab.size());
+    c->off_D32 = take(sizeof(float) * c->D32tab.size());
     c->off_i2 = take(sizeof(int) * c->tup->idx2.size());
     c->off_i4 = take(sizeof(int) * c->tup->idx4.size());
     c->off_i8 = take(sizeof(int) * c->tup->idx8.size());
@@ -455,14 +458,24 @@ int check_hip_last()
     return 0;
 }
 
+// Iterations launched between two reads of the device convergence flags:
+// the first read comes after the batch's iteration count of the previous
+// step (at most 8), later ones every SEM_POLL_K (default 2) iterations.
 int poll_k()
 {
     static int k = -1;
     if (k < 0) {
         const char* s = getenv("SEM_POLL_K");
-        k = s ? std::max(1, atoi(s)) : 4;
+        k = s ? std::max(1, atoi(s)) : 2;
     }
     return k;
+}
+
+int first_chunk(sem_ctx* const* ctxs, int n, bool pressure)
+{
+    int k = 1;
+    for (int i = 0; i < n; ++i) k = std::max(k, pressure ? ctxs[i]->pred_p : ctxs[i]->pred_v);
+    return std::min(k, 8);
 }
 
 // ------------------------------------------------------------------ event profiler
@@ -505,13 +518,19 @@ void ax(const Batch& b, int lx, int src, int dst, int ncomp, int hsel, double h1
     launch_ax(b, lx, a, s);
 }
 
+// fin: FinOp launched right after (the scalar step consuming the partials), or -1
 void vec(const Batch& b, int op, int ncomp, int tv, int gate, hipStream_t s, int f0 = -1, int f1 = -1, int ta = P64,
-         int tb = P64)
+         int tb = P64, int fin_op = -1)
 {
     VecArgs a;
     a.op = op; a.gate = gate; a.ncomp = ncomp; a.tv = tv; a.ta = ta; a.tb = tb; a.f0 = f0; a.f1 = f1; a.a = 0.0;
     a.x_raw = nullptr; a.y_raw = nullptr;
     launch_vec(b, a, s);
+    if (fin_op >= 0) {
+        FinArgs f;
+        f.op = fin_op; f.gate = -1; f.ncomp = 1; f.f0 = 0; f.host_flags = nullptr; f.host_stats = nullptr;
+        launch_fin(b, f, s);
+    }
 }
 
 void fin(const Batch& b, int op, hipStream_t s, int gate = -1, int ncomp = 1, int* flags = nullptr, int f0 = 0)
@@ -549,30 +568,34 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
     // fp64 residual of the current state: R64 = RHS - dssum(H U), norms -> VACT
     ax(b, lx, F_U, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, P64, s);
     launch_dssum(b, F_W64, 3, P64, -1, nullptr, s);
-    vec(b, V_VRESID, 3, P64, -1, s);
-    fin(b, FIN_VINIT, s);
+    vec(b, V_VRESID, 3, P64, -1, s, -1, -1, P64, P64, FIN_VINIT);
     const int maxref = c0->flow.vel_max_refine;
     for (int cyc = 0; cyc < maxref; ++cyc) {
-        int act = poll(b, I_VACT, 3, hf, s);
-        if (act < 0) return act;
-        if (act == 0) break;
-        vec(b, V_PCG_INIT, 3, tv, -1, s, -1, -1, r.tva);
-        fin(b, FIN_PCG_RHO, s);
-        const int K = poll_k();
+        if (cyc > 0) {
+            // the first cycle runs without a read: if the initial residual
+            // already meets the tolerance its launches are gated no-ops
+            int act = poll(b, I_VACT, 3, hf, s);
+            if (act < 0) return act;
+            if (act == 0) break;
+        }
+        vec(b, V_PCG_INIT, 3, tv, -1, s, -1, -1, r.tva, P64, FIN_PCG_RHO);
+        int K = first_chunk(ctxs, b.n, false);
         int guard = 0;
         for (;;) {
             for (int q = 0; q < K; ++q) {
                 {
                     ProfScope ps(SEM_PROF_AX_VEL, s);
+                    // alpha = rho / (p, w): the dot of a continuous p with dssum(w_L)
+                    // equals the plain local sum of p w_L, formed before the dssum
                     ax(b, lx, F_PP, F_PW, 3, S_H1, 0, 0, -1, R_A, I_VACT, tv, r.axv_g, r.axv_c, s);
                 }
                 launch_dssum(b, F_PW, 3, tv, I_VACT, nullptr, s);
                 fin(b, FIN_PCG_ALPHA, s);
-                vec(b, V_PCG_UPD, 3, tv, I_VACT, s, -1, -1, r.tva);
-                fin(b, FIN_PCG_BETA, s);
+                vec(b, V_PCG_UPD, 3, tv, I_VACT, s, -1, -1, r.tva, P64, FIN_PCG_BETA);
                 vec(b, V_PCG_P, 3, tv, I_VACT, s);
             }
             guard += K;
+            K = poll_k();
             int a2 = poll(b, I_VACT, 3, hf, s);
             if (a2 < 0) return a2;
             if (a2 == 0 || guard > c0->flow.vel_maxit + K) break;
@@ -581,14 +604,24 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
         if (tv == P64) break;  // fp64 recurrence residual is the solver's stop criterion
         ax(b, lx, F_US, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, P64, s);
         launch_dssum(b, F_W64, 3, P64, -1, nullptr, s);
-        vec(b, V_VRESID, 3, P64, -1, s);
-        fin(b, FIN_VINIT, s);
+        vec(b, V_VRESID, 3, P64, -1, s, -1, -1, P64, P64, FIN_VINIT);
     }
     return check_hip_last();
 }
 
-// One GMRES(m) cycle iteration sequence (Arnoldi step, then cycle end when
-// pending); every kernel is gated so converged requests idle.
+// Cycle end of GMRES(m), gated on requests whose cycle ended: x update, fp64
+// true residual (no operator while x is still zero), then restart or finish.
+void gmres_cycle_end(const Batch& b, int lx, const Resolved& r, hipStream_t s)
+{
+    vec(b, V_GM_XUPD, 1, r.tpd, I_GEND, s, -1, -1, P64, r.tb);
+    ax(b, lx, F_GX, F_GWD, 1, -1, 1.0, 0.0, -1, -1, I_GENDAX, P64, P64, P64, s);
+    launch_dssum(b, F_GWD, 1, P64, I_GENDAX, nullptr, s);
+    vec(b, V_GM_RESID, 1, P64, I_GEND, s, -1, -1, P64, P64, FIN_GM_RESTART);
+    vec(b, V_GM_NORMALIZE, 1, P64, I_GNORM, s, -1, -1, P64, r.tb);
+}
+
+// One Arnoldi step of GMRES(m), then the cycle end where pending; every
+// kernel is gated so converged requests idle.
 void gmres_iteration(const Batch& b, int lx, const Resolved& r, hipStream_t s)
 {
     {
@@ -607,45 +640,42 @@ void gmres_iteration(const Batch& b, int lx, const Resolved& r, hipStream_t s)
     }
     {
         ProfScope ps(SEM_PROF_GM_DOTS, s);
-        vec(b, V_GM_DOTS, 1, P64, I_GARN, s, -1, -1, P64, r.tb);
+        vec(b, V_GM_DOTS, 1, P64, I_GARN, s, -1, -1, P64, r.tb, FIN_GM_H1);
     }
-    fin(b, FIN_GM_H1, s);
     {
         ProfScope ps(SEM_PROF_GM_UPD_DOTS, s);
-        vec(b, V_GM_UPD_DOTS, 1, P64, I_GARN, s, -1, -1, P64, r.tb);
+        vec(b, V_GM_UPD_DOTS, 1, P64, I_GARN, s, -1, -1, P64, r.tb, FIN_GM_H2);
     }
-    fin(b, FIN_GM_H2, s);
     {
         ProfScope ps(SEM_PROF_GM_UPD_NORM, s);
-        vec(b, V_GM_UPD_NORM, 1, P64, I_GARN, s, -1, -1, P64, r.tb);
+        vec(b, V_GM_UPD_NORM, 1, P64, I_GARN, s, -1, -1, P64, r.tb, FIN_GM_COL);
     }
-    fin(b, FIN_GM_COL, s);
     vec(b, V_GM_NORMALIZE, 1, P64, I_GNORM, s, -1, -1, P64, r.tb);
-    // cycle end: x update and fp64 true residual (no operator while x is still zero), then restart or finish
-    vec(b, V_GM_XUPD, 1, r.tpd, I_GEND, s, -1, -1, P64, r.tb);
-    ax(b, lx, F_GX, F_GWD, 1, -1, 1.0, 0.0, -1, -1, I_GENDAX, P64, P64, P64, s);
-    launch_dssum(b, F_GWD, 1, P64, I_GENDAX, nullptr, s);
-    vec(b, V_GM_RESID, 1, P64, I_GEND, s);
-    fin(b, FIN_GM_RESTART, s);
-    vec(b, V_GM_NORMALIZE, 1, P64, I_GNORM, s, -1, -1, P64, r.tb);
+    gmres_cycle_end(b, lx, r, s);
 }
 
 // GMRES on F_GB -> F_GX in three pieces so a serving loop can change the
 // batch between iteration chunks (all solver state is per request, on the
 // device): start (GX zeroed by the caller), advance by up to max_iters Arnoldi
 // steps, finish (mass-mean removal of GX).
-void gmres_start(const Batch& b, hipStream_t s) { fin(b, FIN_GM_START, s); }
+// Start: the first cycle end runs at once (r = b, beta, V_0 = r / beta).
+void gmres_start(const Batch& b, int lx, const Resolved& r, hipStream_t s)
+{
+    fin(b, FIN_GM_START, s);
+    gmres_cycle_end(b, lx, r, s);
+}
 
 // returns the number of requests still iterating, or a negative status
 int gmres_advance(sem_ctx* const* ctxs, const Batch& b, hipStream_t s, int max_iters)
 {
     sem_ctx* c0 = ctxs[0];
-    const int K = poll_k();
+    int K = first_chunk(ctxs, b.n, true);
     int done = 0, act = 0;
     while (done < max_iters) {
         const int k = std::min(K, max_iters - done);
         for (int q = 0; q < k; ++q) gmres_iteration(b, c0->lx, c0->rs, s);
         done += k;
+        K = poll_k();
         act = poll(b, I_GACT, 1, c0->hflags, s);
         if (act <= 0) return act;
     }
@@ -654,8 +684,7 @@ int gmres_advance(sem_ctx* const* ctxs, const Batch& b, hipStream_t s, int max_i
 
 void gmres_finish(const Batch& b, hipStream_t s)
 {
-    vec(b, V_SUM_MASS, 1, P64, -1, s, F_GX);
-    fin(b, FIN_MEAN_MASS, s);
+    vec(b, V_SUM_MASS, 1, P64, -1, s, F_GX, -1, P64, P64, FIN_MEAN_MASS);
     vec(b, V_SUB_MEAN, 1, P64, -1, s, F_GX, -1);
 }
 
@@ -664,7 +693,7 @@ int pressure_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
     sem_ctx* c0 = ctxs[0];
     const int m = c0->flow.gmres_restart;
     const int limit = c0->flow.pres_maxit + c0->flow.pres_maxit / std::max(1, m) + 4;
-    gmres_start(b, s);
+    gmres_start(b, c0->lx, c0->rs, s);
     int rc = gmres_advance(ctxs, b, s, limit);
     if (rc < 0) return rc;
     gmres_finish(b, s);
@@ -754,11 +783,23 @@ int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_pr
     }
     std::vector<double> x, w, D;
     gll_tables(c->N, x, w, D);
-    c->D64tab.resize(lx * lx + 2 * lx);
+    // fp64 table: D (lx*lx), GLL weights, GLL nodes, then 1/multiplicity of
+    // every local point of a conforming box mesh (lx^3; a face coordinate
+    // doubles the number of copies); fp32 table: D, weights, nodes
+    c->D64tab.resize(lx * lx + 2 * lx + lx * lx * lx);
     c->D32tab.resize(lx * lx + 2 * lx);
     for (int q = 0; q < lx * lx; ++q) c->D64tab[q] = D[q];
     for (int q = 0; q < lx; ++q) { c->D64tab[lx * lx + q] = w[q]; c->D64tab[lx * lx + lx + q] = x[q]; }
-    for (size_t q = 0; q < c->D64tab.size(); ++q) c->D32tab[q] = (float)c->D64tab[q];
+    for (size_t q = 0; q < c->D32tab.size(); ++q) c->D32tab[q] = (float)c->D64tab[q];
+    for (int k = 0; k < lx; ++k)
+        for (int j = 0; j < lx; ++j)
+            for (int i = 0; i < lx; ++i) {
+                double r = 1.0;
+                if (i == 0 || i == lx - 1) r *= 0.5;
+                if (j == 0 || j == lx - 1) r *= 0.5;
+                if (k == 0 || k == lx - 1) r *= 0.5;
+                c->D64tab[lx * lx + 2 * lx + i + lx * (j + lx * k)] = r;
+            }
     build_tuples(c);
     build_layout(c);
     MeshParams& mp = c->mp;
@@ -802,9 +843,10 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     if (c->nb > c->pstride || c->nvb > c->pstride || (long long)c->nb * c->epb < c->E || (long long)c->nvb * c->vepb < c->E)
         return fail(SEM_EINVAL, "internal block layout inconsistent");
     d.n2 = c->n2; d.n4 = c->n4; d.n8 = c->n8;
-    d.c2 = (c->n2 + SEM_GS_CHUNK - 1) / SEM_GS_CHUNK;
-    d.c4 = (c->n4 + SEM_GS_CHUNK - 1) / SEM_GS_CHUNK;
-    d.c8 = (c->n8 + SEM_GS_CHUNK - 1) / SEM_GS_CHUNK;
+    const int ch2 = SEM_GS_THREADS * SEM_GS_TPT2, ch4 = SEM_GS_THREADS * SEM_GS_TPT4, ch8 = SEM_GS_THREADS * SEM_GS_TPT8;
+    d.c2 = (c->n2 + ch2 - 1) / ch2;
+    d.c4 = (c->n4 + ch4 - 1) / ch4;
+    d.c8 = (c->n8 + ch8 - 1) / ch8;
     d.prec16 = c->rs.need16 ? c->rs.kind16 : 0;
     d.gm_m = c->flow.gmres_restart;
     d.np = c->np; d.nglob = c->nglob;
@@ -857,8 +899,7 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     launch_geo_post(b, s);
     if (c->rs.need32 || c->rs.need16) launch_geo_cast(b, c->lx, c->rs.need32 ? 1 : 0, c->rs.need16 ? c->rs.kind16 : 0, s);
     // domain volume (sum of B)
-    vec(b, V_SUM_MASS, 1, P64, -1, s, -1);
-    fin(b, FIN_VOL, s);
+    vec(b, V_SUM_MASS, 1, P64, -1, s, -1, -1, P64, P64, FIN_VOL);
     int rc = check_hip_last();
     if (rc) return rc;
     if (c->flow.mode == SEM_MODE_FLUID) {
@@ -1020,8 +1061,7 @@ int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stat
         // large element terms whose fp32 rounding would dominate it.
         launch_wdiv(b, lx, P64, P64, F_US, F_RP, s);
         launch_dssum(b, F_RP, 1, P64, -1, nullptr, s);
-        vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_RP);
-        fin(b, FIN_MEAN_UNIQUE, s);
+        vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_RP, -1, P64, P64, FIN_MEAN_UNIQUE);
         vec(b, V_SUB_MEAN, 1, P64, -1, s, F_RP, S_H2);  // F_GB aliases F_RP
         vec(b, V_ZERO, 1, P64, -1, s, F_GX);
         rc = pressure_solve(ctxs, b, s);
@@ -1057,6 +1097,8 @@ int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stat
                 ss.pres_res = o[11];
                 ss.status = sti;
             }
+            c->pred_v = std::max(1, (int)std::max(o[4], std::max(o[5], o[6])));
+            c->pred_p = std::max(1, (int)o[10]);
         }
     }
     (void)status;
@@ -1075,8 +1117,7 @@ int sem_poisson_solve(sem_ctx* const* ctxs, int n, const void* const* rhs, void*
         HIPCHK(hipMemcpyAsync(ctxs[i]->hdesc.f[F_GB], rhs[i], 8 * (size_t)ctxs[i]->np, hipMemcpyDeviceToDevice, s));
     }
     Batch b = make_batch(ctxs, n);
-    vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_GB);
-    fin(b, FIN_MEAN_UNIQUE, s);
+    vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_GB, -1, P64, P64, FIN_MEAN_UNIQUE);
     vec(b, V_SUB_MEAN, 1, P64, -1, s, F_GB, -1);
     vec(b, V_ZERO, 1, P64, -1, s, F_GX);
     rc = pressure_solve(ctxs, b, s);
@@ -1111,11 +1152,10 @@ int sem_poisson_begin(sem_ctx* const* ctxs, int n, const void* const* rhs)
         HIPCHK(hipMemcpyAsync(ctxs[i]->hdesc.f[F_GB], rhs[i], 8 * (size_t)ctxs[i]->np, hipMemcpyDeviceToDevice, s));
     }
     Batch b = make_batch(ctxs, n);
-    vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_GB);
-    fin(b, FIN_MEAN_UNIQUE, s);
+    vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_GB, -1, P64, P64, FIN_MEAN_UNIQUE);
     vec(b, V_SUB_MEAN, 1, P64, -1, s, F_GB, -1);
     vec(b, V_ZERO, 1, P64, -1, s, F_GX);
-    gmres_start(b, s);
+    gmres_start(b, c0->lx, c0->rs, s);
     return check_hip_last();
 }
 

@@ -16,7 +16,10 @@
 
 #define SEM_MAXB 48          // requests per batched launch
 #define SEM_MAXM 30          // largest GMRES restart length
-#define SEM_GS_CHUNK 256     // shared-node tuples per workgroup
+#define SEM_GS_THREADS 256   // threads of the gather-scatter kernel
+#define SEM_GS_TPT2 4        // pairs per thread
+#define SEM_GS_TPT4 2        // quads per thread
+#define SEM_GS_TPT8 1        // octets per thread
 #define SEM_VEC_THREADS 256  // threads of point-wise kernels
 
 namespace semk {
