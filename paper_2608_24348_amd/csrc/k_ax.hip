@@ -90,6 +90,8 @@ ax_kernel(Batch bt, AxLaunch a)
     C h1, h2;
     if (a.hsel >= 0) { h1 = (C)gp(R->S)[a.hsel]; h2 = (C)gp(R->S)[a.hsel + 1]; }
     else { h1 = (C)a.h1; h2 = (C)a.h2; }
+    // a stored GMRES basis vector is unnormalised: A (s_J V_J) = s_J A V_J
+    if (a.src_vj) h1 *= (C)gp(R->S)[S_GVS + gp(R->I)[I_GJ]];
     C gsc = (C)1, bsc = (C)1;
     const int ee = live ? e : 0;
     const bool helm = h2 != (C)0;

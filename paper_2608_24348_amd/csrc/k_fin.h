@@ -153,7 +153,8 @@ static __device__ __noinline__ void fin_body(ReqDesc* R, int ri, const FinArgs a
         if (!I[I_GARN]) break;
         const int J = I[I_GJ];
         multi_slot_sum(R, R_GM, J + 1, sums, scratch);
-        if (t <= J) S[(a.op == FIN_GM_H1 ? S_GHC : S_GH2) + t] = sums[t];
+        // dots with the stored vectors, scaled to the normalised basis
+        if (t <= J) S[(a.op == FIN_GM_H1 ? S_GHC : S_GH2) + t] = sums[t] * S[S_GVS + t];
         if (a.op == FIN_GM_H1) {
             double s = slot_sum(R, R_GMEAN, red);
             if (t == 0) S[S_GMEAN] = s / (double)R->nglob;
@@ -205,7 +206,7 @@ static __device__ __noinline__ void fin_body(ReqDesc* R, int ri, const FinArgs a
                 I[I_GNORM] = 0;
             } else {
                 I[I_GJ] = J + 1;
-                S[S_GNSCALE] = 1.0 / hn;
+                S[S_GVS + J + 1] = 1.0 / hn;
                 I[I_GNORM] = 1;
             }
         }
@@ -227,7 +228,7 @@ static __device__ __noinline__ void fin_body(ReqDesc* R, int ri, const FinArgs a
                 SEM_GLOBAL double* gg = S + S_GG;
                 for (int i = 0; i <= SEM_MAXM; ++i) gg[i] = 0.0;
                 gg[0] = beta;
-                S[S_GNSCALE] = 1.0 / beta;
+                S[S_GVS] = 1.0 / beta;
                 I[I_GARN] = 1; I[I_GNORM] = 1;
             }
         }

@@ -227,13 +227,18 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         break;
     }
     case V_GM_RESID: {
+        // r = b - A x (fp64), stored as the next cycle's first basis vector
+        // V_0 (unnormalised; FIN_GM_RESTART records 1/|r|)
         auto b = fld<double>(R, F_GB);
-        auto w = fldw<double>(R, F_GWD);
+        auto w = fld<double>(R, F_GWD);
         const bool ax = gp(R->I)[I_GENDAX] != 0;  // iterate nonzero: GWD holds A x
+        SEM_GLOBAL double* v64 = a.tb == P64 ? fldw<double>(R, F_V) : nullptr;
+        SEM_GLOBAL float* v32 = a.tb == P64 ? nullptr : fldw<float>(R, F_V);
         MulWalk mw(R, pr);
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x, mw.next()) {
             const double v = ax ? b[p] - w[p] : b[p];
-            w[p] = v;
+            if (v64) v64[p] = v;
+            else v32[p] = (float)v;
             acc[0] += v * v * mw.im();
         }
         double v2[1] = {acc[0]};
@@ -289,10 +294,13 @@ __device__ __forceinline__ void gm_body(const ReqDesc* R, const PtRange& pr, dou
     const long long np = R->np;
     double h[NJ];
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) h[i] = MODE == 1 ? gp(R->S)[S_GHC + i] : MODE == 2 ? gp(R->S)[S_GH2 + i] : 0.0;
+    for (int i = 0; i < NJ; ++i)
+        h[i] = (MODE == 1 ? gp(R->S)[S_GHC + i] : MODE == 2 ? gp(R->S)[S_GH2 + i] : 0.0) * gp(R->S)[S_GVS + i];
     const double mean = MODE == 1 ? gp(R->S)[S_GMEAN] : 0.0;
     auto w = fld<double>(R, F_GW);
     auto wd = fldw<double>(R, F_GWD);
+    // the last pass stores the orthogonalised vector as V_{J+1}, unnormalised
+    SEM_GLOBAL TB* vn = fldw<TB>(R, F_V) + (long long)NJ * np;
     MulWalk mw(R, pr);
     for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x, mw.next()) {
         double vr[NJ];
@@ -316,7 +324,7 @@ __device__ __forceinline__ void gm_body(const ReqDesc* R, const PtRange& pr, dou
             double wv = wd[p];
 #pragma unroll
             for (int i = 0; i < NJ; ++i) wv -= h[i] * vr[i];
-            wd[p] = wv;
+            vn[p] = (TB)wv;
             acc[0] += wv * wv * im;
         }
     }
@@ -382,7 +390,7 @@ __device__ __forceinline__ void xupd_body(const ReqDesc* R, const PtRange& pr)
     const long long np = R->np;
     double y[NJ];
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) y[i] = gp(R->S)[S_GY + i];
+    for (int i = 0; i < NJ; ++i) y[i] = gp(R->S)[S_GY + i] * gp(R->S)[S_GVS + i];
     for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
         double vr[NJ];
 #pragma unroll
@@ -411,22 +419,6 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_xupd_kernel(Batch bt, int 
     }
 }
 
-// V_J = GWD * S_GNSCALE, rounded to the basis storage type
-template <typename TB>
-__global__ void __launch_bounds__(SEM_VEC_THREADS) gm_norm_kernel(Batch bt, int gate)
-{
-    const int g = blockIdx.x;
-    const int ri = find_req(bt.vb, bt.n, g);
-    const ReqDesc* R = bt.r[ri];
-    const int blk = g - bt.vb[ri];
-    if (!gate_ok(R, gate)) return;
-    const PtRange pr = pt_range(R, blk);
-    SEM_GLOBAL TB* v = fldw<TB>(R, F_V) + (long long)gp(R->I)[I_GJ] * R->np;
-    auto w = fld<double>(R, F_GWD);
-    const double sc = gp(R->S)[S_GNSCALE];
-    for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) v[p] = (TB)(w[p] * sc);
-}
-
 void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s)
 {
     dim3 grid(b.vb[b.n], a.ncomp > 0 ? a.ncomp : 1);
@@ -444,10 +436,6 @@ void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s)
     case V_GM_UPD_NORM:
         if (a.tb == P64) hipLaunchKernelGGL((gm_pass_kernel<2, double>), grid, blk, 0, s, b, a.gate);
         else hipLaunchKernelGGL((gm_pass_kernel<2, float>), grid, blk, 0, s, b, a.gate);
-        return;
-    case V_GM_NORMALIZE:
-        if (a.tb == P64) hipLaunchKernelGGL(gm_norm_kernel<double>, grid, blk, 0, s, b, a.gate);
-        else hipLaunchKernelGGL(gm_norm_kernel<float>, grid, blk, 0, s, b, a.gate);
         return;
     case V_GM_XUPD:
         if (a.tv == P64 && a.tb == P64) hipLaunchKernelGGL((gm_xupd_kernel<double, double>), grid, blk, 0, s, b, a.gate);

@@ -616,8 +616,7 @@ void gmres_cycle_end(const Batch& b, int lx, const Resolved& r, hipStream_t s)
     vec(b, V_GM_XUPD, 1, r.tpd, I_GEND, s, -1, -1, P64, r.tb);
     ax(b, lx, F_GX, F_GWD, 1, -1, 1.0, 0.0, -1, -1, I_GENDAX, P64, P64, P64, s);
     launch_dssum(b, F_GWD, 1, P64, I_GENDAX, nullptr, s);
-    vec(b, V_GM_RESID, 1, P64, I_GEND, s, -1, -1, P64, P64, FIN_GM_RESTART);
-    vec(b, V_GM_NORMALIZE, 1, P64, I_GNORM, s, -1, -1, P64, r.tb);
+    vec(b, V_GM_RESID, 1, P64, I_GEND, s, -1, -1, P64, r.tb, FIN_GM_RESTART);
 }
 
 // One Arnoldi step of GMRES(m), then the cycle end where pending; every
@@ -650,7 +649,6 @@ void gmres_iteration(const Batch& b, int lx, const Resolved& r, hipStream_t s)
         ProfScope ps(SEM_PROF_GM_UPD_NORM, s);
         vec(b, V_GM_UPD_NORM, 1, P64, I_GARN, s, -1, -1, P64, r.tb, FIN_GM_COL);
     }
-    vec(b, V_GM_NORMALIZE, 1, P64, I_GNORM, s, -1, -1, P64, r.tb);
     gmres_cycle_end(b, lx, r, s);
 }
 

@@ -96,8 +96,8 @@ enum ScalarId : int {
     S_MEAN = S_GH2 + SEM_MAXM + 1, // scratch for mean removal
     S_KE, S_ENST, S_MAXDIV,
     S_VOL,                      // sum of B (domain volume)
-    S_GNSCALE,                  // scale applied by the GMRES normalisation kernel
-    S_GMEAN,                    // unique-node mean of the current Arnoldi operator output
+    S_GVS,                      // m+1: 1/norm of the stored (unnormalised) basis vectors V_i
+    S_GMEAN = S_GVS + SEM_MAXM + 1,  // unique-node mean of the current Arnoldi operator output
     S_RED,                      // generic finalised reductions (SEM_NRED values)
     NSCALAR = S_RED + 64
 };
@@ -132,7 +132,7 @@ enum IntId : int {
     I_VDONE,                    // velocity refinement finished for all components
     I_GARN,                     // GMRES: Arnoldi step pending (phase 0)
     I_GEND,                     // GMRES: cycle end pending (phase 1)
-    I_GNORM,                    // GMRES: normalisation of V_J pending
+    I_GNORM,                    // GMRES: a new basis vector was stored (informational)
     I_VMAXREF,                  // velocity refinement cycle limit
     I_GENDAX,                   // GMRES: cycle end with a nonzero iterate (true residual needs A x)
     I_IDVSTALE,                 // velocity Jacobi diagonal must be rebuilt for new (h1,h2)
@@ -261,10 +261,9 @@ enum VecOp : int {
     V_ZERO,           // f0 = 0 (fp64)
     V_GM_DOTS,        // partials (V_i, GW) -> R_GM+i, i <= J, and sum(GW/mult) -> R_GMEAN
     V_GM_UPD_DOTS,    // GWD = GW - S_GMEAN - sum GHC_i V_i ; partials (V_i, GWD) -> R_GM+i
-    V_GM_UPD_NORM,    // GWD -= sum GH2_i V_i ; partial |GWD|^2 -> R_GN
-    V_GM_NORMALIZE,   // V_J = GWD * S_GNSCALE
+    V_GM_UPD_NORM,    // V_{J+1} = GWD - sum GH2_i V_i (unnormalised); partial |V_{J+1}|^2 -> R_GN
     V_GM_XUPD,        // GX += IDP * sum_{i<jend} y_i V_i
-    V_GM_RESID,       // GWD = GB - GWD (GB alone when I_GENDAX == 0), partial |GWD|^2 -> R_GN
+    V_GM_RESID,       // V_0 = GB - GWD (GB alone when I_GENDAX == 0), partial |V_0|^2 -> R_GN
     V_CORRECT,        // U_new = US - dt/beta0 GP / Bsum  (into the u^{n-2} buffer); P += GX
     V_AXPY_RAW,       // raw y += a x (fp64), used by the standalone API
     V_MASS_RAW,       // raw y = B x (fp64)
