@@ -94,6 +94,22 @@ def _load():
     L.orc_fluid_stepno.restype = C.c_int
     L.orc_fluid_stepno.argtypes = [vp]
     L.orc_fluid_step.argtypes = [vp, C.POINTER(_StepStats)]
+    L.orc_fluid_set_proj.restype = C.c_int
+    L.orc_fluid_set_proj.argtypes = [vp, C.c_int]
+    L.orc_fluid_proj_size.restype = C.c_int
+    L.orc_fluid_proj_size.argtypes = [vp]
+    L.orc_proj_new.restype = vp
+    L.orc_proj_new.argtypes = [vp, C.c_int]
+    L.orc_proj_free.argtypes = [vp]
+    L.orc_proj_size.restype = C.c_int
+    L.orc_proj_size.argtypes = [vp]
+    L.orc_proj_guess.argtypes = [vp, _dp, _dp]
+    L.orc_proj_get.restype = C.c_int
+    L.orc_proj_get.argtypes = [vp, C.c_int, _dp]
+    L.orc_proj_update.restype = C.c_int
+    L.orc_proj_update.argtypes = [vp, _dp, _dp]
+    L.orc_poisson_proj.restype = C.c_int
+    L.orc_poisson_proj.argtypes = [vp, vp, _dp, _dp, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_double)]
     L.orc_num_threads.restype = C.c_int
     _lib = L
     return L
@@ -282,6 +298,47 @@ class OracleMesh:
         return p, it, res.value
 
 
+class OracleProjection:
+    """Pressure projection space (A-orthonormal earlier solutions) on an OracleMesh."""
+
+    def __init__(self, mesh, dim=20):
+        self.mesh = mesh
+        self.L = mesh.L
+        self.h = self.L.orc_proj_new(mesh.h, int(dim))
+        if not self.h:
+            raise ValueError("projection dimension must be >= 1")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.L.orc_proj_free(self.h)
+            self.h = None
+
+    @property
+    def size(self):
+        return self.L.orc_proj_size(self.h)
+
+    def vector(self, i):
+        out = np.zeros(self.mesh.np)
+        if self.L.orc_proj_get(self.h, int(i), out) != 0:
+            raise IndexError(i)
+        return out
+
+    def guess(self, b):
+        x = np.zeros(self.mesh.np)
+        self.L.orc_proj_guess(self.h, _c(b), x)
+        return x
+
+    def update(self, x, xbar):
+        return bool(self.L.orc_proj_update(self.h, _c(x), _c(xbar)))
+
+    def poisson(self, rhs, tol=1e-8, maxit=1000, restart=30):
+        p = np.zeros(self.mesh.np)
+        res = C.c_double()
+        it = self.L.orc_poisson_proj(self.mesh.h, self.h, _c(rhs), p, float(tol), int(maxit), int(restart),
+                                     C.byref(res))
+        return p, it, res.value
+
+
 INIT_TGV3D, INIT_TGV2D, INIT_ZERO = 0, 1, 2
 FIELD_U, FIELD_P, FIELD_ULAG1, FIELD_ULAG2, FIELD_BNLAG1, FIELD_BNLAG2 = 0, 3, 4, 7, 10, 13
 
@@ -290,13 +347,19 @@ class OracleFluid:
     """FP64 TGV stepper on an OracleMesh (keeps a reference to the mesh)."""
 
     def __init__(self, mesh, nu, dt, torder=3, vtol=1e-8, ptol=1e-8, vmaxit=500, pmaxit=1000,
-                 restart=30, init=INIT_TGV3D):
+                 restart=30, init=INIT_TGV3D, proj=0):
         self.mesh = mesh
         self.L = mesh.L
         self.h = self.L.orc_fluid_new(mesh.h, float(nu), float(dt), int(torder), float(vtol), float(ptol),
                                       int(vmaxit), int(pmaxit), int(restart), int(init))
         if not self.h:
             raise ValueError("invalid fluid parameters")
+        if self.L.orc_fluid_set_proj(self.h, int(proj)) != 0:
+            raise ValueError("invalid projection dimension")
+
+    @property
+    def proj_size(self):
+        return self.L.orc_fluid_proj_size(self.h)
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -811,6 +811,112 @@ int orc_poisson(const orc_mesh* m, const double* rhs, double* p, double tol, int
 }
 
 /* ------------------------------------------------------------------ */
+/* Projection of the pressure solve onto earlier solutions (the solver  */
+/* settings of Sec. 3 give the pressure a projection space of dimension */
+/* 20).  Written from the successive-right-hand-side method of Fischer  */
+/* (1998): keep X = [x_1..x_l], orthonormal in the A inner product       */
+/* (x_i^T A x_j = delta_ij, inner products over unique nodes).  For a new*/
+/* rhs b the best approximation of A^-1 b in span X in the A-norm is     */
+/* xbar = sum_i (x_i, b) x_i; the solver starts from xbar.  Afterwards   */
+/* the correction v = x - xbar (or, when the space is full, the whole    */
+/* solution x with the space emptied first) is A-orthogonalised against  */
+/* X, normalised with ||v||_A^2 = (v, A v) - sum_i beta_i^2 (exact for an */
+/* A-orthonormal X), and appended unless it is numerically dependent.    */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    const orc_mesh* m;
+    int L, l;
+    double* X;          /* L * np */
+} orc_proj;
+
+orc_proj* orc_proj_new(const orc_mesh* m, int L)
+{
+    if (L < 1 || L > 64) return NULL;
+    orc_proj* P = (orc_proj*)calloc(1, sizeof(orc_proj));
+    P->m = m; P->L = L; P->l = 0;
+    P->X = dalloc((long)L * m->np);
+    return P;
+}
+
+void orc_proj_free(orc_proj* P)
+{
+    if (!P) return;
+    free(P->X); free(P);
+}
+
+int orc_proj_size(const orc_proj* P) { return P->l; }
+
+int orc_proj_get(const orc_proj* P, int i, double* out)
+{
+    if (i < 0 || i >= P->l) return -1;
+    memcpy(out, P->X + (long)i * P->m->np, P->m->np * sizeof(double));
+    return 0;
+}
+
+/* xbar = sum_i (x_i, b) x_i */
+void orc_proj_guess(const orc_proj* P, const double* b, double* xbar)
+{
+    long np = P->m->np;
+    for (long q = 0; q < np; ++q) xbar[q] = 0.0;
+    for (int i = 0; i < P->l; ++i) {
+        const double* xi = P->X + (long)i * np;
+        double a = orc_glsc(P->m, xi, b);
+        for (long q = 0; q < np; ++q) xbar[q] += a * xi[q];
+    }
+}
+
+/* add the new direction after a solve that started from xbar and ended at
+ * x (the periodic Poisson operator, h1 = 1, h2 = 0).  Returns 1 if added. */
+int orc_proj_update(orc_proj* P, const double* x, const double* xbar)
+{
+    const orc_mesh* m = P->m;
+    long np = m->np;
+    if (P->l == P->L) P->l = 0;                 /* full: restart from x */
+    const int whole = P->l == 0;
+    double* v = dalloc(np); double* w = dalloc(np);
+    double beta[64];
+    for (long q = 0; q < np; ++q) v[q] = whole ? x[q] : x[q] - xbar[q];
+    apply_assembled(m, v, w, 1.0, 0.0);
+    double n2 = orc_glsc(m, v, w);
+    const double n2b = n2;
+    for (int i = 0; i < P->l; ++i) beta[i] = orc_glsc(m, P->X + (long)i * np, w);
+    for (int i = 0; i < P->l; ++i) {
+        const double* xi = P->X + (long)i * np;
+        for (long q = 0; q < np; ++q) v[q] -= beta[i] * xi[q];
+        n2 -= beta[i] * beta[i];
+    }
+    int added = 0;
+    if (n2b > 0.0 && n2 > 1e-12 * n2b) {
+        double s = 1.0 / sqrt(n2);
+        double* xl = P->X + (long)P->l * np;
+        for (long q = 0; q < np; ++q) xl[q] = v[q] * s;
+        P->l += 1;
+        added = 1;
+    }
+    free(v); free(w);
+    return added;
+}
+
+/* Periodic Poisson solve with projection: unique-node mean of the rhs
+ * removed, GMRES from the projected guess, space updated, mass-weighted
+ * mean of p removed. */
+int orc_poisson_proj(const orc_mesh* m, orc_proj* P, const double* rhs, double* p, double tol, int maxit,
+                     int mrst, double* res)
+{
+    long np = m->np;
+    double* b = dalloc(np); double* xbar = dalloc(np);
+    memcpy(b, rhs, np * sizeof(double));
+    orc_remove_mean_unique(m, b);
+    orc_proj_guess(P, b, xbar);
+    memcpy(p, xbar, np * sizeof(double));
+    int it = orc_gmres_ex(m, 1.0, 0.0, b, p, tol, maxit, mrst, 1, res, NULL);
+    orc_proj_update(P, p, xbar);
+    orc_remove_mean_mass(m, p);
+    free(b); free(xbar);
+    return it;
+}
+
+/* ------------------------------------------------------------------ */
 /* Fluid step: BDF-k / EXT-k (k ramps 1,2,3) velocity-first incremental */
 /* pressure correction, in the order of the paper's Fig. 3 workflow.     */
 /* ------------------------------------------------------------------ */
@@ -826,6 +932,7 @@ typedef struct {
     /* last step statistics */
     int vit[3], pit;
     double vres[3], pres;
+    orc_proj* proj;                     /* pressure projection space, or NULL */
 } orc_fluid;
 
 typedef struct {
@@ -875,9 +982,21 @@ orc_fluid* orc_fluid_new(const orc_mesh* m, double nu, double dt, int torder,
     return f;
 }
 
+/* pressure projection space of dimension L (0 switches it off) */
+int orc_fluid_set_proj(orc_fluid* f, int L)
+{
+    if (L < 0 || L > 64) return -1;
+    orc_proj_free(f->proj);
+    f->proj = L > 0 ? orc_proj_new(f->m, L) : NULL;
+    return 0;
+}
+
+int orc_fluid_proj_size(const orc_fluid* f) { return f->proj ? f->proj->l : 0; }
+
 void orc_fluid_free(orc_fluid* f)
 {
     if (!f) return;
+    orc_proj_free(f->proj);
     for (int c = 0; c < 3; ++c) { free(f->u[c]); free(f->ul1[c]); free(f->ul2[c]); free(f->bn1[c]); free(f->bn2[c]); }
     free(f->p); free(f);
 }
@@ -959,7 +1078,8 @@ int orc_fluid_step(orc_fluid* f, orc_step_stats* st)
     orc_wdiv(m, us[0], us[1], us[2], rp);
     orc_dssum(m, rp);
     for (long q = 0; q < np; ++q) rp[q] *= beta0 / dt;
-    f->pit = orc_poisson(m, rp, phi, f->ptol, f->pmaxit, f->mrst, &f->pres);
+    if (f->proj) f->pit = orc_poisson_proj(m, f->proj, rp, phi, f->ptol, f->pmaxit, f->mrst, &f->pres);
+    else f->pit = orc_poisson(m, rp, phi, f->ptol, f->pmaxit, f->mrst, &f->pres);
     /* (iv) correction u^{n+1} = u* - (dt/beta0) dssum(B grad phi) / Bsum, p += phi */
     orc_opgrad(m, phi, gp[0], gp[1], gp[2]);
     for (int c = 0; c < 3; ++c) orc_dssum(m, gp[c]);

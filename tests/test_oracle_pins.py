@@ -11,7 +11,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle import OracleMesh, OracleFluid, gll, deriv_matrix, e_max, e_peak, e_series
+from oracle import OracleMesh, OracleFluid, OracleProjection, gll, deriv_matrix, e_max, e_peak, e_series
 from oracle.oracle import INIT_TGV2D, INIT_TGV3D
 from paper_2608_24348_amd import inputs
 
@@ -325,6 +325,79 @@ def test_gmres_matches_dense_solve_nonsingular_and_singular():
     x0, it0, res0 = m.gmres(y0[uid], 1.0, 0.0, tol=1e-12, maxit=3000, restart=30)
     got = x0 - m.glsc(x0, np.ones(m.np)) / m.nglob
     assert np.abs(got - ref[uid]).max() < 1e-9 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------- pressure projection
+def _unique(loc, uid, n):
+    u = np.zeros(n)
+    u[uid] = loc
+    return u
+
+
+def test_projection_space_is_A_orthonormal_and_guess_is_A_optimal():
+    m = OracleMesh((2, 2, 2), 3, amp=0.1, phase=inputs.deform_phases())
+    A, uid = _assembled_dense(m, 1.0, 0.0)
+    P = OracleProjection(m, dim=3)
+    rng = np.random.default_rng(11)
+    sizes = []
+    for _ in range(5):
+        y = rng.standard_normal(m.nglob)
+        y -= y.mean()
+        p, it, res = P.poisson(y[uid], tol=1e-12, maxit=3000)
+        assert res <= 1e-12
+        # the solution is that of the dense singular system (zero-mean parts)
+        ref, *_ = np.linalg.lstsq(A, y, rcond=None)
+        got = _unique(p, uid, m.nglob)
+        assert np.abs((got - got.mean()) - (ref - ref.mean())).max() < 1e-9 * np.abs(ref).max()
+        sizes.append(P.size)
+    # one direction per solve; a full space restarts from the latest solution
+    assert sizes == [1, 2, 3, 1, 2]
+    X = np.stack([_unique(P.vector(i), uid, m.nglob) for i in range(P.size)])
+    assert np.abs(X @ A @ X.T - np.eye(P.size)).max() < 1e-9
+    # the guess is the A-norm best approximation in span X: its residual is
+    # orthogonal to the space (Galerkin condition), checked with the dense A
+    y = rng.standard_normal(m.nglob)
+    y -= y.mean()
+    xbar = _unique(P.guess(y[uid]), uid, m.nglob)
+    r = y - A @ xbar
+    assert np.abs(X @ r).max() < 1e-10 * np.abs(y).max()
+    # a rhs inside the space is reproduced exactly by the guess
+    b_in = A @ (0.7 * X[0] - 1.3 * X[1])
+    xg = _unique(P.guess(b_in[uid]), uid, m.nglob)
+    assert np.abs(A @ xg - b_in).max() < 1e-9 * np.abs(b_in).max()
+
+
+def test_projection_repeated_rhs_needs_no_iterations():
+    m = OracleMesh((4, 4, 4), 5)
+    X = m.coords()
+    s = np.sin(X[0]) * np.sin(X[1]) * np.sin(X[2])
+    b = m.dssum(m.mass() * 3 * s)
+    P = OracleProjection(m, dim=20)
+    p1, it1, res1 = P.poisson(b, tol=1e-10, maxit=5000)
+    p2, it2, res2 = P.poisson(b, tol=1e-10, maxit=5000)
+    assert it1 > 0 and it2 == 0 and res2 <= 1e-10
+    assert np.abs(p2 - p1).max() < 1e-9
+    # without projection the plain solver gives the same answer
+    p0, it0, _ = m.poisson(b, tol=1e-10, maxit=5000)
+    assert it0 == it1 and np.abs(p0 - p1).max() < 1e-9
+
+
+def test_fluid_with_projection_matches_plain_solver():
+    nu, dt = 1 / 1600, 1e-3
+    m = OracleMesh((4, 4, 4), 5)
+    f0 = OracleFluid(m, nu, dt, init=INIT_TGV3D)
+    f1 = OracleFluid(m, nu, dt, init=INIT_TGV3D, proj=20)
+    it0 = it1 = 0
+    for _ in range(8):
+        a, b = f0.step(), f1.step()
+        it0 += a["pit"]
+        it1 += b["pit"]
+        assert b["pres"] <= 1e-8
+        assert abs(a["ke"] - b["ke"]) <= 1e-10 * a["ke"]
+        assert abs(a["enst"] - b["enst"]) <= 1e-8 * a["enst"]
+    assert f1.proj_size > 0
+    # projection onto earlier increments cuts the pressure iterations
+    assert it1 < it0
 
 
 def test_poisson_spectral_convergence():
