@@ -115,7 +115,12 @@ typedef struct {
     int gmres_restart;               /* 1..30 */
     int vel_max_refine;              /* FP64 true-residual refinement cycles (>= 1) */
     int init;                        /* SEM_INIT_* */
+    int proj_dim;                    /* pressure projection space 0..SEM_MAX_PROJ (0 = off; fluid mode):
+                                        GMRES starts from the A-norm best approximation of the new
+                                        pressure increment in the span of earlier ones (Sec. 3 uses 20) */
 } sem_flow_desc;
+
+#define SEM_MAX_PROJ 20
 
 typedef struct sem_ctx sem_ctx;
 

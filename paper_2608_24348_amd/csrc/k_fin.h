@@ -235,11 +235,49 @@ static __device__ __noinline__ void fin_body(ReqDesc* R, int ri, const FinArgs a
         break;
     }
     case FIN_GM_START: {
-        // fresh solve from x = 0: the first cycle end computes r = b
+        // fresh solve: the first cycle end computes r = b, or r = b - A x0
+        // when the iterate starts from a nonzero projected guess
         if (t == 0) {
+            const int x0 = R->proj_L > 0 && I[I_PRL] > 0;
             I[I_GJ] = 0; I[I_GJEND] = 0; I[I_GIT] = 0;
-            I[I_GACT] = 1; I[I_GARN] = 0; I[I_GEND] = 1; I[I_GENDAX] = 0; I[I_GNORM] = 0;
+            I[I_GACT] = 1; I[I_GARN] = 0; I[I_GEND] = 1; I[I_GENDAX] = x0; I[I_GNORM] = 0;
         }
+        break;
+    }
+    case FIN_PR_ALPHA: {
+        const int l = I[I_PRL];
+        multi_slot_sum(R, R_GM, l, sums, scratch);
+        if (t < l) S[S_PRA + t] = sums[t] * S[S_PRS + t];
+        break;
+    }
+    case FIN_PR_POST: {
+        if (t == 0) {
+            const int full = I[I_PRL] >= R->proj_L;
+            if (full) I[I_PRL] = 0;
+            I[I_PRFULL] = full;
+        }
+        break;
+    }
+    case FIN_PR_BETA: {
+        const int l = I[I_PRL];
+        multi_slot_sum(R, R_GM, l + 1, sums, scratch);
+        if (t == 0) {
+            const double n2b = sums[l];
+            double n2 = n2b;
+            for (int i = 0; i < l; ++i) {
+                const double bi = sums[i] * S[S_PRS + i];
+                S[S_PRB + i] = bi;
+                n2 -= bi * bi;
+            }
+            // a vector whose A-norm mostly lies in the space is dependent: dropped
+            const int add = finite(n2b) && n2b > 0.0 && n2 > 1e-12 * n2b;
+            I[I_PRADD] = add;
+            if (add) S[S_PRS + l] = 1.0 / sqrt(n2);
+        }
+        break;
+    }
+    case FIN_PR_COMMIT: {
+        if (t == 0 && I[I_PRADD]) I[I_PRL] += 1;
         break;
     }
     case FIN_DIAG: {

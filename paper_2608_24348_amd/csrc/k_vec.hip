@@ -267,6 +267,19 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) y[p] = B[p] * x[p];
         break;
     }
+    case V_PR_V: {
+        // the candidate direction: the correction the solver added to the
+        // projected guess, or the whole solution when the space restarts
+        auto gx = fld<double>(R, F_GX);
+        auto xb = fld<double>(R, F_PRXB);
+        auto v = fldw<double>(R, F_GW);
+        if (gp(R->I)[I_PRFULL]) {
+            for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) v[p] = gx[p];
+        } else {
+            for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) v[p] = gx[p] - xb[p];
+        }
+        break;
+    }
     case V_AXPY_RAW: {
         const double* x = (const double*)a.x_raw;
         double* y = (double*)a.y_raw;
@@ -379,6 +392,104 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_pass_kernel(Batch bt, int 
     }
 }
 
+// ------------------------------------------------------------------ pressure projection passes
+// The space holds l stored vectors X_i (unnormalised, scale s_i = 1/||X_i||_A
+// kept in S_PRS), l read on the device; the body is instantiated per l.
+//   MODE 0: partials (X_i, b)                      -> alpha_i = s_i (X_i, b)
+//   MODE 1: GX = PRXB = sum alpha_i s_i X_i         (the projected guess)
+//   MODE 2: partials (X_i, w), (v, w), w = A v      -> beta_i, ||v||_A^2
+//   MODE 3: X_l = v - sum beta_i s_i X_i            (A-orthogonalised new vector)
+template <int NJ, int MODE, typename TB>
+__device__ __forceinline__ void pr_body(const ReqDesc* R, const PtRange& pr, double (&acc)[SEM_MAX_PROJ + 1])
+{
+    const SEM_GLOBAL TB* X = fld<TB>(R, F_PRX);
+    const long long np = R->np;
+    constexpr int NA = NJ > 0 ? NJ : 1;
+    double cf[NA];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i)
+        cf[i] = MODE == 1 ? gp(R->S)[S_PRA + i] * gp(R->S)[S_PRS + i]
+              : MODE == 3 ? gp(R->S)[S_PRB + i] * gp(R->S)[S_PRS + i] : 0.0;
+    auto b = fld<double>(R, F_GB);
+    auto w = fld<double>(R, F_GWD);
+    auto v = fld<double>(R, F_GW);
+    auto gx = fldw<double>(R, F_GX);
+    auto xb = fldw<double>(R, F_PRXB);
+    SEM_GLOBAL TB* xl = fldw<TB>(R, F_PRX) + (long long)NJ * np;
+    MulWalk mw(R, pr);
+    for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x, mw.next()) {
+        double xr[NA];
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) xr[i] = (double)X[i * np + p];
+        if (MODE == 0) {
+            const double bv = b[p] * mw.im();
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) acc[i] += xr[i] * bv;
+        } else if (MODE == 1) {
+            double sum = 0.0;
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) sum += cf[i] * xr[i];
+            gx[p] = sum;
+            xb[p] = sum;
+        } else if (MODE == 2) {
+            const double wv = w[p] * mw.im();
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) acc[i] += xr[i] * wv;
+            acc[NJ] += v[p] * wv;
+        } else {
+            double sum = v[p];
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) sum -= cf[i] * xr[i];
+            xl[p] = (TB)sum;
+        }
+    }
+}
+
+#define SEM_NP_CASES(F)                                                                                 \
+    F(0) F(1) F(2) F(3) F(4) F(5) F(6) F(7) F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) F(16) F(17)   \
+    F(18) F(19) F(20)
+
+template <int MODE, typename TB>
+__global__ void __launch_bounds__(SEM_VEC_THREADS) pr_pass_kernel(Batch bt, int gate)
+{
+    constexpr int NV = SEM_MAX_PROJ + 1;
+    __shared__ double red[(SEM_VEC_THREADS / 64) * NV];
+    const int g = blockIdx.x;
+    const int ri = find_req(bt.vb, bt.n, g);
+    const ReqDesc* R = bt.r[ri];
+    const int blk = g - bt.vb[ri];
+    if (!gate_ok(R, gate)) return;
+    const PtRange pr = pt_range(R, blk);
+    const int l = gp(R->I)[I_PRL];
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    switch (l) {
+#define PR_CASE(n) case n: pr_body<n, MODE, TB>(R, pr, acc); break;
+        SEM_NP_CASES(PR_CASE)
+#undef PR_CASE
+    default: break;
+    }
+    if (MODE == 0 || MODE == 2) {
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        const int nv = MODE == 0 ? l : l + 1;
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) acc[i] = wave_sum(acc[i]);
+        if (lane == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                if (i < nv) red[wid * NV + i] = acc[i];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+            double sum = 0;
+            for (int q = 0; q < nw; ++q) sum += red[q * NV + i];
+            put_partial(R, R_GM + i, blk, sum);
+        }
+    }
+}
+
 // x += IDP * sum_{i < jend} y_i V_i  (right preconditioning applied once per
 // cycle, with the same stored diagonal the Arnoldi operator used)
 template <int NJ, typename TD, typename TB>
@@ -437,6 +548,18 @@ void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s)
         if (a.tb == P64) hipLaunchKernelGGL((gm_pass_kernel<2, double>), grid, blk, 0, s, b, a.gate);
         else hipLaunchKernelGGL((gm_pass_kernel<2, float>), grid, blk, 0, s, b, a.gate);
         return;
+    case V_PR_ADOTS:
+    case V_PR_GUESS:
+    case V_PR_BDOTS:
+    case V_PR_ORTH: {
+        const int mode = a.op == V_PR_ADOTS ? 0 : a.op == V_PR_GUESS ? 1 : a.op == V_PR_BDOTS ? 2 : 3;
+#define PR_GO(M)                                                                                       \
+    if (a.tb == P64) hipLaunchKernelGGL((pr_pass_kernel<M, double>), grid, blk, 0, s, b, a.gate);      \
+    else hipLaunchKernelGGL((pr_pass_kernel<M, float>), grid, blk, 0, s, b, a.gate);
+        if (mode == 0) { PR_GO(0) } else if (mode == 1) { PR_GO(1) } else if (mode == 2) { PR_GO(2) } else { PR_GO(3) }
+#undef PR_GO
+        return;
+    }
     case V_GM_XUPD:
         if (a.tv == P64 && a.tb == P64) hipLaunchKernelGGL((gm_xupd_kernel<double, double>), grid, blk, 0, s, b, a.gate);
         else if (a.tv == P64) hipLaunchKernelGGL((gm_xupd_kernel<double, float>), grid, blk, 0, s, b, a.gate);

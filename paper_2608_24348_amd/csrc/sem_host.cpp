@@ -429,6 +429,10 @@ void build_layout(sem_ctx* c)
         for (int f = F_PX; f <= F_PWc; ++f) field(f, tv * np);
         c->foff[F_GB] = c->foff[F_RP];
         c->fbytes[F_GB] = c->fbytes[F_RP];
+        if (c->flow.proj_dim > 0) {
+            field(F_PRX, (size_t)c->flow.proj_dim * psize(r.tb) * (size_t)np);
+            field(F_PRXB, d);
+        }
     }
     c->bytes = off;
 }
@@ -686,14 +690,40 @@ void gmres_finish(const Batch& b, hipStream_t s)
     vec(b, V_SUB_MEAN, 1, P64, -1, s, F_GX, -1);
 }
 
+// Projection of the pressure increment onto earlier ones (the pressure
+// solver's projection space of Sec. 3): before the solve, the guess
+// GX = sum_i (X_i, b) X_i over the A-orthonormal stored vectors, from which
+// GMRES starts (its first cycle end forms b - A GX in fp64).
+void projection_guess(const Batch& b, const Resolved& r, hipStream_t s)
+{
+    vec(b, V_PR_ADOTS, 1, P64, -1, s, -1, -1, P64, r.tb, FIN_PR_ALPHA);
+    vec(b, V_PR_GUESS, 1, P64, -1, s, -1, -1, P64, r.tb);
+}
+
+// After the solve: the correction GX - guess (the whole GX when the space is
+// full and restarts) is A-orthogonalised against the space with the fp64
+// operator and appended unless dependent.
+void projection_update(const Batch& b, int lx, const Resolved& r, hipStream_t s)
+{
+    fin(b, FIN_PR_POST, s);
+    vec(b, V_PR_V, 1, P64, -1, s);
+    ax(b, lx, F_GW, F_GWD, 1, -1, 1.0, 0.0, -1, -1, -1, P64, P64, P64, s);
+    launch_dssum(b, F_GWD, 1, P64, -1, nullptr, s);
+    vec(b, V_PR_BDOTS, 1, P64, -1, s, -1, -1, P64, r.tb, FIN_PR_BETA);
+    vec(b, V_PR_ORTH, 1, P64, I_PRADD, s, -1, -1, P64, r.tb);
+    fin(b, FIN_PR_COMMIT, s);
+}
+
 int pressure_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
 {
     sem_ctx* c0 = ctxs[0];
     const int m = c0->flow.gmres_restart;
     const int limit = c0->flow.pres_maxit + c0->flow.pres_maxit / std::max(1, m) + 4;
+    const bool proj = c0->flow.mode == SEM_MODE_FLUID && c0->flow.proj_dim > 0;
     gmres_start(b, c0->lx, c0->rs, s);
     int rc = gmres_advance(ctxs, b, s, limit);
     if (rc < 0) return rc;
+    if (proj) projection_update(b, c0->lx, c0->rs, s);
     gmres_finish(b, s);
     return check_hip_last();
 }
@@ -754,6 +784,9 @@ int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_pr
         if (!(flow->vel_tol > 0) || flow->vel_maxit < 1 || flow->vel_max_refine < 1)
             return fail(SEM_EINVAL, "bad velocity tolerance/limits");
         if (flow->init < SEM_INIT_ZERO || flow->init > SEM_INIT_TGV2D) return fail(SEM_EINVAL, "bad init");
+        if (flow->proj_dim < 0 || flow->proj_dim > SEM_MAX_PROJ) return fail(SEM_EINVAL, "proj_dim must be 0..20");
+    } else if (flow->proj_dim != 0) {
+        return fail(SEM_EINVAL, "proj_dim applies to the fluid mode only");
     }
     Resolved rs;
     int rc = resolve_policy(prec, rs);
@@ -847,6 +880,7 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     d.c8 = (c->n8 + ch8 - 1) / ch8;
     d.prec16 = c->rs.need16 ? c->rs.kind16 : 0;
     d.gm_m = c->flow.gmres_restart;
+    d.proj_L = c->flow.mode == SEM_MODE_FLUID ? c->flow.proj_dim : 0;
     d.np = c->np; d.nglob = c->nglob;
     d.idx2 = (const int*)(c->dev + c->off_i2);
     d.idx4 = (const int*)(c->dev + c->off_i4);
@@ -870,6 +904,7 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     I[I_TORDER] = c->flow.torder;
     I[I_VMAXIT] = c->flow.vel_maxit;
     I[I_VMAXREF] = c->flow.vel_max_refine;
+    I[I_PRL] = 0;
     I[I_GMAXIT] = c->flow.pres_maxit;
     I[I_GM] = c->flow.gmres_restart;
     I[I_ALWAYS] = 1;
@@ -1012,6 +1047,8 @@ static int check_batch(sem_ctx* const* ctxs, int n, int min_mode)
         if (ctxs[i]->stream != ctxs[0]->stream) return fail(SEM_EINVAL, "batched contexts must share the stream");
         if (ctxs[i]->flow.gmres_restart != ctxs[0]->flow.gmres_restart)
             return fail(SEM_EINVAL, "batched contexts must share the GMRES restart length");
+        if (ctxs[i]->flow.proj_dim != ctxs[0]->flow.proj_dim)
+            return fail(SEM_EINVAL, "batched contexts must share the projection dimension");
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(SEM_EINVAL, "a context appears twice in a batch");
     }
@@ -1061,7 +1098,8 @@ int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stat
         launch_dssum(b, F_RP, 1, P64, -1, nullptr, s);
         vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_RP, -1, P64, P64, FIN_MEAN_UNIQUE);
         vec(b, V_SUB_MEAN, 1, P64, -1, s, F_RP, S_H2);  // F_GB aliases F_RP
-        vec(b, V_ZERO, 1, P64, -1, s, F_GX);
+        if (c0->flow.proj_dim > 0) projection_guess(b, r, s);
+        else vec(b, V_ZERO, 1, P64, -1, s, F_GX);
         rc = pressure_solve(ctxs, b, s);
         if (rc) return rc;
         // (iv) correction and pressure update, lag rotation, diagnostics

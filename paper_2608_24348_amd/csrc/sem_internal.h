@@ -14,6 +14,8 @@
 #include <hip/hip_bf16.h>
 #include <stdint.h>
 
+#include "sem.h"
+
 #define SEM_MAXB 48          // requests per batched launch
 #define SEM_MAXM 30          // largest GMRES restart length
 #define SEM_GS_THREADS 256   // threads of the gather-scatter kernel
@@ -68,6 +70,9 @@ enum FieldId : int {
     F_GWD,                      // fp64 working vector of the Arnoldi step
     F_GB,                       // rhs (fp64)
     F_GX,                       // iterate (fp64)
+    // pressure projection (fluid mode with proj_dim > 0)
+    F_PRX,                      // proj_dim stored vectors, stride np, basis storage precision, unnormalised
+    F_PRXB,                     // the projected guess of the current step (fp64)
     NFIELD
 };
 
@@ -96,7 +101,10 @@ enum ScalarId : int {
     S_MEAN = S_GH2 + SEM_MAXM + 1, // scratch for mean removal
     S_KE, S_ENST, S_MAXDIV,
     S_VOL,                      // sum of B (domain volume)
-    S_GVS,                      // m+1: 1/norm of the stored (unnormalised) basis vectors V_i
+    S_PRA,                      // SEM_MAX_PROJ: projection coefficients alpha_i of the guess
+    S_PRB = S_PRA + SEM_MAX_PROJ,   // SEM_MAX_PROJ: A-orthogonalisation coefficients beta_i
+    S_PRS = S_PRB + SEM_MAX_PROJ,   // SEM_MAX_PROJ: 1/||X_i||_A of the stored projection vectors
+    S_GVS = S_PRS + SEM_MAX_PROJ,   // m+1: 1/norm of the stored (unnormalised) basis vectors V_i
     S_GMEAN = S_GVS + SEM_MAXM + 1,  // unique-node mean of the current Arnoldi operator output
     S_RED,                      // generic finalised reductions (SEM_NRED values)
     NSCALAR = S_RED + 64
@@ -136,6 +144,9 @@ enum IntId : int {
     I_VMAXREF,                  // velocity refinement cycle limit
     I_GENDAX,                   // GMRES: cycle end with a nonzero iterate (true residual needs A x)
     I_IDVSTALE,                 // velocity Jacobi diagonal must be rebuilt for new (h1,h2)
+    I_PRL,                      // projection: vectors in the space
+    I_PRFULL,                   // projection: the space was full and restarts from the whole solution
+    I_PRADD,                    // projection: the new vector is independent and will be appended
     I_PCNT,                     // NRED: number of partials the last producer of each slot wrote
     NINT = I_PCNT + NRED + 8
 };
@@ -148,6 +159,7 @@ struct ReqDesc {
     int c2, c4, c8;             // tuple chunk counts
     int prec16;                 // 0 none, 2 fp16, 3 bf16
     int gm_m;                   // GMRES restart
+    int proj_L;                 // pressure projection space dimension (0 = off)
     long long np, nglob;
     const int* idx2;            // [n2][2]
     const int* idx4;            // [n4][4]
@@ -267,6 +279,11 @@ enum VecOp : int {
     V_CORRECT,        // U_new = US - dt/beta0 GP / Bsum  (into the u^{n-2} buffer); P += GX
     V_AXPY_RAW,       // raw y += a x (fp64), used by the standalone API
     V_MASS_RAW,       // raw y = B x (fp64)
+    V_PR_ADOTS,       // partials (X_i, GB) -> R_GM+i, i < l
+    V_PR_GUESS,       // GX = PRXB = sum_i alpha_i s_i X_i
+    V_PR_V,           // GW = GX - PRXB (GX alone when the space restarts): the candidate direction
+    V_PR_BDOTS,       // partials (X_i, GWD) -> R_GM+i, i < l, and (GW, GWD) -> R_GM+l
+    V_PR_ORTH,        // X_l = GW - sum_i beta_i s_i X_i
     NVECOP
 };
 
@@ -290,6 +307,10 @@ enum FinOp : int {
     FIN_SUM_RAW,      // S[S_RED + gate] = sum of slot f0 partials
     FIN_VOL,          // S_VOL = sum of slot R_X3 partials
     FIN_STATS,        // host_stats[ri*SEM_NSTAT ...] = step statistics
+    FIN_PR_ALPHA,     // alpha_i = s_i (X_i, GB)
+    FIN_PR_POST,      // a full space restarts (l = 0, I_PRFULL)
+    FIN_PR_BETA,      // beta_i = s_i (X_i, A v); ||v_orth||_A^2 = (v, A v) - sum beta_i^2; I_PRADD, s_l
+    FIN_PR_COMMIT,    // l += I_PRADD
     NFINOP
 };
 

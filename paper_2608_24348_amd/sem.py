@@ -54,7 +54,7 @@ class FlowDesc(C.Structure):
     _fields_ = [("size", C.c_int), ("mode", C.c_int), ("nu", C.c_double), ("dt", C.c_double),
                 ("torder", C.c_int), ("vel_tol", C.c_double), ("pres_tol", C.c_double),
                 ("vel_maxit", C.c_int), ("pres_maxit", C.c_int), ("gmres_restart", C.c_int),
-                ("vel_max_refine", C.c_int), ("init", C.c_int)]
+                ("vel_max_refine", C.c_int), ("init", C.c_int), ("proj_dim", C.c_int)]
 
 
 class StepStats(C.Structure):
@@ -201,7 +201,7 @@ def mesh_desc(nel, order, lo=(-math.pi,) * 3, hi=(math.pi,) * 3, amp=0.0, phase=
 
 
 def flow_desc(mode=MODE_FLUID, nu=1.0 / 1600, dt=1e-3, torder=3, vel_tol=1e-8, pres_tol=1e-8, vel_maxit=500,
-              pres_maxit=1000, restart=30, max_refine=8, init=INIT_TGV3D):
+              pres_maxit=1000, restart=30, max_refine=8, init=INIT_TGV3D, proj=0):
     f = FlowDesc()
     f.size = C.sizeof(FlowDesc)
     f.mode = mode
@@ -215,6 +215,7 @@ def flow_desc(mode=MODE_FLUID, nu=1.0 / 1600, dt=1e-3, torder=3, vel_tol=1e-8, p
     f.gmres_restart = restart
     f.vel_max_refine = max_refine
     f.init = init
+    f.proj_dim = proj
     return f
 
 
