@@ -180,6 +180,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ax", action="store_true")
+    ap.add_argument("--serve", type=int, default=64,
+                    help="requests of the serving leg (seeded TGV/Poisson stream; 0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the element-sharded "
@@ -238,6 +240,17 @@ def main():
         del ctx64
     del ctx
     torch.cuda.synchronize()
+    if args.serve > 0:
+        from paper_2608_24348_amd import serve
+        log("serving: %d requests, burst then Poisson arrivals at 0.7x the burst rate" % args.serve)
+        sv = serve.measure(args.serve, loads=(0.7,), log=log)
+        sat, mid = sv["saturated"], sv["load_0.7"]
+        out["serving"] = {"requests": args.serve, "stream_seed": sv["seed"],
+                          "workload": "TGV (20 steps) and Poisson (tol 1e-8) requests, n 4-24, N 5/7/9, "
+                                      "Re 100-1600, tiers fp64/fp32b, batched by (order, tier, kind)",
+                          "saturated_requests_per_s": sat["requests_per_s"], "saturated_gdof_per_s": sat["gdof_per_s"],
+                          "qps": mid["qps"], "p50_s": mid.get("p50_s"), "p99_s": mid.get("p99_s"),
+                          "gdof_per_s": mid["gdof_per_s"], "ok": mid["ok"]}
     if not args.no_cpu:
         log("cpu baseline: oracle sample of the same workload")
         pbar = sum(s["pit"] for s in st_mx) / len(st_mx)

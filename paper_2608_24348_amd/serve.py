@@ -52,8 +52,8 @@ class Request:
 class Server:
     """Runs a list of request specs (see inputs.request_stream) to completion."""
 
-    def __init__(self, budget_bytes=None, max_batch=16, gmres_chunk=30, device="cuda:0", vel_tol=1e-8,
-                 pres_tol=1e-8, keep_fields=False):
+    def __init__(self, budget_bytes=None, max_batch=16, gmres_chunk=30, device="cuda:0", vel_tol=1e-6,
+                 pres_tol=1e-4, poisson_tol=1e-8, keep_fields=False):
         import torch
         self.torch = torch
         self.device = device
@@ -63,8 +63,9 @@ class Server:
         self.budget = int(budget_bytes)
         self.max_batch = min(int(max_batch), 48)
         self.gmres_chunk = int(gmres_chunk)
-        self.vel_tol = vel_tol
+        self.vel_tol = vel_tol          # TGV requests: the paper's absolute solver tolerances
         self.pres_tol = pres_tol
+        self.poisson_tol = poisson_tol  # Poisson requests
         self.keep_fields = keep_fields
         self.used = 0
 
@@ -72,7 +73,8 @@ class Server:
     def _setup(self, r):
         s = r.spec
         mode = sem.MODE_FLUID if r.kind == "tgv" else sem.MODE_POISSON
-        flow = sem.flow_desc(mode=mode, nu=1.0 / s["Re"], dt=s["dt"], vel_tol=self.vel_tol, pres_tol=self.pres_tol,
+        ptol = self.pres_tol if r.kind == "tgv" else self.poisson_tol
+        flow = sem.flow_desc(mode=mode, nu=1.0 / s["Re"], dt=s["dt"], vel_tol=self.vel_tol, pres_tol=ptol,
                              pres_maxit=3000)
         r.ctx = sem.Context(sem.mesh_desc(s["nel"], s["N"]), flow, sem.tier(s["tier"]), device=self.device,
                             bind=False)
@@ -196,3 +198,41 @@ def summarize(done, makespan):
         out.update({"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                     "mean_s": float(lat.mean()), "max_s": float(lat.max())})
     return out
+
+
+def measure(n_requests=256, seed=24348, loads=(0.4, 0.7, 1.0), max_batch=16, log=None):
+    """Serving measurement: a burst of the whole stream (all requests at t = 0)
+    gives the saturated request rate; the same stream is then replayed with
+    Poisson arrivals at each fraction of that rate."""
+    from . import inputs
+    out = {"requests": n_requests, "seed": seed}
+    burst = inputs.request_stream(n_requests=n_requests, qps=1e12, seed=seed)
+    done, ms = Server(max_batch=max_batch).run(burst, log=log)
+    sat = summarize(done, ms)
+    out["saturated"] = sat
+    for f in loads:
+        qps = f * sat["requests_per_s"]
+        specs = inputs.request_stream(n_requests=n_requests, qps=qps, seed=seed)
+        done, ms = Server(max_batch=max_batch).run(specs, log=log)
+        out["load_%.1f" % f] = dict(summarize(done, ms), qps=qps)
+    return out
+
+
+def main():
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="Serve a seeded stream of TGV and Poisson requests on one GPU")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=24348)
+    ap.add_argument("--loads", default="0.4,0.7,1.0", help="fractions of the saturated request rate")
+    ap.add_argument("--max-batch", type=int, default=16)
+    args = ap.parse_args()
+    sem.load()
+    res = measure(args.requests, args.seed, tuple(float(x) for x in args.loads.split(",")), args.max_batch,
+                  log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
