@@ -43,6 +43,9 @@ def _load():
     L.orc_deriv.argtypes = [C.c_int, _dp, _dp]
     L.orc_mesh_new.restype = vp
     L.orc_mesh_new.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, C.c_double, _dp]
+    L.orc_mesh_subset_new.restype = vp
+    L.orc_mesh_subset_new.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, C.c_double, _dp,
+                                      C.POINTER(C.c_int), C.c_int]
     L.orc_mesh_free.argtypes = [vp]
     for f in ("orc_mesh_np", "orc_mesh_nglob"):
         getattr(L, f).restype = C.c_long
@@ -146,11 +149,19 @@ class OracleMesh:
     """Periodic box mesh of nel[0]*nel[1]*nel[2] hexahedra of order N with
     its geometric factors; fields are flat arrays of E*lx^3 local values."""
 
-    def __init__(self, nel, N, lo=(-np.pi,) * 3, hi=(np.pi,) * 3, amp=0.0, phase=None):
+    def __init__(self, nel, N, lo=(-np.pi,) * 3, hi=(np.pi,) * 3, amp=0.0, phase=None, elements=None):
+        """elements: optional list of element indices of the full box; the mesh
+        then holds only those elements (element-local operators only, no
+        assembly), for element-by-element checks of large meshes."""
         self.L = _load()
         ph = np.zeros(9) if phase is None else _c(phase)
-        self.h = self.L.orc_mesh_new(int(nel[0]), int(nel[1]), int(nel[2]), int(N),
-                                     _c(lo), _c(hi), float(amp), ph)
+        if elements is None:
+            self.h = self.L.orc_mesh_new(int(nel[0]), int(nel[1]), int(nel[2]), int(N),
+                                         _c(lo), _c(hi), float(amp), ph)
+        else:
+            el = np.ascontiguousarray(elements, dtype=np.int32)
+            self.h = self.L.orc_mesh_subset_new(int(nel[0]), int(nel[1]), int(nel[2]), int(N), _c(lo), _c(hi),
+                                                float(amp), ph, el.ctypes.data_as(C.POINTER(C.c_int)), len(el))
         if not self.h:
             raise ValueError("invalid mesh (element count, order or non-positive Jacobian)")
         self.nel = tuple(int(v) for v in nel)

@@ -156,6 +156,66 @@ static void perturb(const orc_mesh* m, const double X[3], double out[3])
     }
 }
 
+/* Geometric factors of every element of m from its coordinates (m->xyz):
+ * dx_c/dr_a = D_a x_c, jac = det, dr/dx = inverse, B = jac w_i w_j w_k,
+ * G_ab = B sum_c dr_a/dx_c dr_b/dx_c, M_ac = B dr_a/dx_c.  Returns nonzero
+ * if some Jacobian is not positive. */
+static int mesh_geometry(orc_mesh* m)
+{
+    const int lx = m->lx;
+    const long np = m->np;
+    const double* D = m->D;
+    int bad = 0;
+    #pragma omp parallel for reduction(|:bad)
+    for (int e = 0; e < m->E; ++e)
+        for (int k = 0; k < lx; ++k)
+        for (int j = 0; j < lx; ++j)
+        for (int i = 0; i < lx; ++i) {
+            long p = PT(m, e, i, j, k);
+            double J[3][3];              /* J[c][a] = d x_c / d r_a */
+            for (int c = 0; c < 3; ++c) {
+                const double* X = m->xyz + (long)c * np;
+                double dr = 0, ds = 0, dt = 0;
+                for (int l = 0; l < lx; ++l) {
+                    dr += D[i * lx + l] * X[PT(m, e, l, j, k)];
+                    ds += D[j * lx + l] * X[PT(m, e, i, l, k)];
+                    dt += D[k * lx + l] * X[PT(m, e, i, j, l)];
+                }
+                J[c][0] = dr; J[c][1] = ds; J[c][2] = dt;
+            }
+            double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+                       - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+                       + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+            if (!(det > 0.0)) bad = 1;
+            /* inverse: (dr/dx)[a][c] = cofactor(J)[c][a] / det */
+            double inv[3][3];
+            inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+            inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+            inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+            inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+            inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+            inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+            inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+            inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+            inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+            double Bp = det * m->w[i] * m->w[j] * m->w[k];
+            m->jac[p] = det;
+            m->B[p] = Bp;
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c) {
+                    m->drdx[(long)(a * 3 + c) * np + p] = inv[a][c];
+                    m->M[(long)(a * 3 + c) * np + p] = Bp * inv[a][c];
+                }
+            static const int ga[6] = {0, 0, 0, 1, 1, 2}, gb[6] = {0, 1, 2, 1, 2, 2};
+            for (int q = 0; q < 6; ++q) {
+                double s = 0;
+                for (int c = 0; c < 3; ++c) s += inv[ga[q]][c] * inv[gb[q]][c];
+                m->G[(long)q * np + p] = Bp * s;
+            }
+        }
+    return bad;
+}
+
 orc_mesh* orc_mesh_new(int nx, int ny, int nz, int N, const double* lo, const double* hi,
                        double amp, const double* phase)
 {
@@ -211,58 +271,7 @@ orc_mesh* orc_mesh_new(int nx, int ny, int nz, int N, const double* lo, const do
     for (long p = 0; p < np; ++p) m->mult[p] = cnt[m->gid[p]];
     free(cnt);
 
-    /* geometric factors: dx_c/dr_a = D_a x_c, jac = det, dr/dx = inverse,
-     * B = jac w_i w_j w_k, G_ab = B sum_c dr_a/dx_c dr_b/dx_c, M_ac = B dr_a/dx_c */
-    const double* D = m->D;
-    int bad = 0;
-    #pragma omp parallel for reduction(|:bad)
-    for (int e = 0; e < m->E; ++e)
-        for (int k = 0; k < lx; ++k)
-        for (int j = 0; j < lx; ++j)
-        for (int i = 0; i < lx; ++i) {
-            long p = PT(m, e, i, j, k);
-            double J[3][3];              /* J[c][a] = d x_c / d r_a */
-            for (int c = 0; c < 3; ++c) {
-                const double* X = m->xyz + (long)c * np;
-                double dr = 0, ds = 0, dt = 0;
-                for (int l = 0; l < lx; ++l) {
-                    dr += D[i * lx + l] * X[PT(m, e, l, j, k)];
-                    ds += D[j * lx + l] * X[PT(m, e, i, l, k)];
-                    dt += D[k * lx + l] * X[PT(m, e, i, j, l)];
-                }
-                J[c][0] = dr; J[c][1] = ds; J[c][2] = dt;
-            }
-            double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
-                       - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
-                       + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-            if (!(det > 0.0)) bad = 1;
-            /* inverse: (dr/dx)[a][c] = cofactor(J)[c][a] / det */
-            double inv[3][3];
-            inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
-            inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
-            inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
-            inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
-            inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
-            inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
-            inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
-            inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
-            inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
-            double Bp = det * m->w[i] * m->w[j] * m->w[k];
-            m->jac[p] = det;
-            m->B[p] = Bp;
-            for (int a = 0; a < 3; ++a)
-                for (int c = 0; c < 3; ++c) {
-                    m->drdx[(long)(a * 3 + c) * np + p] = inv[a][c];
-                    m->M[(long)(a * 3 + c) * np + p] = Bp * inv[a][c];
-                }
-            static const int ga[6] = {0, 0, 0, 1, 1, 2}, gb[6] = {0, 1, 2, 1, 2, 2};
-            for (int q = 0; q < 6; ++q) {
-                double s = 0;
-                for (int c = 0; c < 3; ++c) s += inv[ga[q]][c] * inv[gb[q]][c];
-                m->G[(long)q * np + p] = Bp * s;
-            }
-        }
-    if (bad) {
+    if (mesh_geometry(m)) {
         /* non-positive Jacobian: the mesh is invalid */
         free(m->xyz); free(m->jac); free(m->B); free(m->drdx); free(m->G); free(m->M);
         free(m->gid); free(m->mult); free(m->Bsum); free(m);
@@ -270,6 +279,70 @@ orc_mesh* orc_mesh_new(int nx, int ny, int nz, int N, const double* lo, const do
     }
     memcpy(m->Bsum, m->B, (size_t)np * sizeof(double));
     orc_dssum(m, m->Bsum);
+    double vol = 0;
+    for (long p = 0; p < np; ++p) vol += m->B[p];
+    m->vol = vol;
+    return m;
+}
+
+/* A mesh holding only the listed elements of the nx x ny x nz box (with the
+ * same optional perturbation): coordinates and geometric factors of each
+ * listed element are those it has in the full mesh, so every element-local
+ * operator (Ax, Jacobi diagonal, convection, gradient, weak divergence) of
+ * the subset equals the full mesh's on those elements.  No assembly: every
+ * point is its own unique node (mult 1).  Checks large meshes element by
+ * element. */
+orc_mesh* orc_mesh_subset_new(int nx, int ny, int nz, int N, const double* lo, const double* hi,
+                              double amp, const double* phase, const int* elems, int ne)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || N < 1 || N + 1 > ORC_MAXLX || ne < 1) return NULL;
+    if (amp != 0.0 && (nx % 2 || ny % 2 || nz % 2)) return NULL;
+    for (int q = 0; q < ne; ++q)
+        if (elems[q] < 0 || (long)elems[q] >= (long)nx * ny * nz) return NULL;
+    orc_mesh* m = (orc_mesh*)calloc(1, sizeof(orc_mesh));
+    m->nel[0] = nx; m->nel[1] = ny; m->nel[2] = nz;
+    m->N = N; m->lx = N + 1; m->E = ne;
+    int lx = m->lx;
+    m->np = (long)ne * lx * lx * lx;
+    for (int c = 0; c < 3; ++c) {
+        m->lo[c] = lo[c]; m->hi[c] = hi[c];
+        m->h[c] = (hi[c] - lo[c]) / m->nel[c];
+    }
+    m->amp = amp;
+    for (int q = 0; q < 9; ++q) m->phase[q] = phase ? phase[q] : 0.0;
+    orc_gll(N, m->xi, m->w);
+    orc_deriv(N, m->xi, m->D);
+    long np = m->np;
+    m->xyz = dalloc(3 * np);
+    m->jac = dalloc(np); m->B = dalloc(np);
+    m->drdx = dalloc(9 * np); m->G = dalloc(6 * np); m->M = dalloc(9 * np);
+    m->gid = (long*)calloc((size_t)np, sizeof(long));
+    m->mult = (int*)calloc((size_t)np, sizeof(int));
+    m->Bsum = dalloc(np);
+    m->nglob = np;
+    for (int q = 0; q < ne; ++q) {
+        const int ef = elems[q];
+        const int ex = ef % nx, ey = (ef / nx) % ny, ez = ef / (nx * ny);
+        for (int k = 0; k < lx; ++k)
+        for (int j = 0; j < lx; ++j)
+        for (int i = 0; i < lx; ++i) {
+            long p = PT(m, q, i, j, k);
+            double X[3] = { (ex + 0.5 * (1.0 + m->xi[i])) * m->h[0],
+                            (ey + 0.5 * (1.0 + m->xi[j])) * m->h[1],
+                            (ez + 0.5 * (1.0 + m->xi[k])) * m->h[2] };
+            double xo[3];
+            perturb(m, X, xo);
+            m->xyz[p] = xo[0]; m->xyz[np + p] = xo[1]; m->xyz[2 * np + p] = xo[2];
+            m->gid[p] = p;
+            m->mult[p] = 1;
+        }
+    }
+    if (mesh_geometry(m)) {
+        free(m->xyz); free(m->jac); free(m->B); free(m->drdx); free(m->G); free(m->M);
+        free(m->gid); free(m->mult); free(m->Bsum); free(m);
+        return NULL;
+    }
+    memcpy(m->Bsum, m->B, (size_t)np * sizeof(double));
     double vol = 0;
     for (long p = 0; p < np; ++p) vol += m->B[p];
     m->vol = vol;

@@ -327,6 +327,22 @@ def test_gmres_matches_dense_solve_nonsingular_and_singular():
     assert np.abs(got - ref[uid]).max() < 1e-9 * np.abs(ref).max()
 
 
+def test_element_subset_mesh_reproduces_full_mesh_elements():
+    nel, N = (4, 4, 4), 5
+    ph = inputs.deform_phases()
+    full = OracleMesh(nel, N, amp=0.1, phase=ph)
+    els = [0, 5, 17, 63, 40]
+    sub = OracleMesh(nel, N, amp=0.1, phase=ph, elements=els)
+    n3 = (N + 1) ** 3
+    pick = np.concatenate([np.arange(e * n3, (e + 1) * n3) for e in els])
+    assert np.array_equal(sub.coords(), full.coords()[:, pick])
+    assert np.array_equal(sub.G(), full.G()[:, pick]) and np.array_equal(sub.mass(), full.mass()[pick])
+    u = np.random.default_rng(9).standard_normal(full.np)
+    assert np.array_equal(sub.ax(u[pick], 0.3, 7.0), full.ax(u, 0.3, 7.0)[pick])
+    v = np.random.default_rng(10).standard_normal((3, full.np))
+    assert np.array_equal(sub.conv(v[:, pick]), full.conv(v)[:, pick])
+
+
 # ---------------------------------------------------------------- pressure projection
 def _unique(loc, uid, n):
     u = np.zeros(n)
