@@ -1,0 +1,209 @@
+"""GPU parity at the full sizes of the benchmark workloads.
+
+C3: 64^3 elements, N = 7 (134 M local points), deformed mesh (amplitude 0.1 h,
+phases from seed 2608), u ~ N(0,1) per local point.  The operator is checked
+on sampled elements against the oracle's element-subset mesh (same
+coordinates and geometric factors as the full mesh on those elements), in
+every storage tier; dssum against copy sets derived from the box structure.
+C2: 32^3 elements, N = 7, the benchmark's step configuration (Re 1600,
+dt 5e-4, absolute tolerances 1e-6 / 1e-4), against the full FP64 oracle.
+C4: 16^3 elements, N = 11, the first steps against the oracle, then 400 steps
+of the fp16-geometry tier against the fp64 tier (error metrics of Sec. 4.2).
+"""
+import numpy as np
+import pytest
+
+from oracle import OracleMesh, OracleFluid, e_max, e_peak
+from oracle.oracle import INIT_TGV3D
+from paper_2608_24348_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+C3 = (64, 64, 64)
+
+
+@pytest.fixture(scope="module")
+def sem():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2608_24348_amd import sem as s
+    s.load()
+    return s
+
+
+def _ctx(sem, nel, N, tier, mode, amp=0.0, **kw):
+    ph = inputs.deform_phases() if amp else None
+    return sem.Context(sem.mesh_desc(nel, N, amp=amp, phase=ph), sem.flow_desc(mode=mode, **kw), sem.tier(tier))
+
+
+def _sample_elements(E, n=48, seed=2608):
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([[0, E - 1], rng.choice(E, n, replace=False)])).astype(np.int64)
+
+
+def _gather(t, els, n3):
+    idx = torch.from_numpy(np.concatenate([np.arange(e * n3, (e + 1) * n3) for e in els])).to(t.device)
+    return t.index_select(0, idx).double().cpu().numpy()
+
+
+def _op_bound(m, u, h1, h2):
+    """Conservative per-point bound of (|A| |u|): max|D|-row-sum^2 * 3 * max sum|G| * max|u| + h2 B |u|."""
+    _, _, D = m.tables()
+    gsum = np.abs(m.G()).sum(axis=0)
+    dn = np.abs(D).sum(axis=1).max()
+    return h1 * dn * dn * 3 * gsum.max() * np.abs(u).max() * np.ones(m.np) + h2 * m.mass() * np.abs(u)
+
+
+@pytest.mark.parametrize("tier16", ["fp32b+fp16all", "fp32b+bf16all"])
+def test_c3_ax_sampled_elements_every_tier(sem, tier16):
+    N = 7
+    c = _ctx(sem, C3, N, tier16, sem.MODE_OPERATOR, amp=0.1)
+    els = _sample_elements(c.E)
+    n3 = (N + 1) ** 3
+    m = OracleMesh(C3, N, amp=0.1, phase=inputs.deform_phases(), elements=els)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(0)
+    u64 = torch.randn(c.np, dtype=torch.float64, device="cuda:0", generator=g)
+    k16 = sem.FP16 if "fp16" in tier16 else sem.BF16
+    e16 = 2 ** -11 if "fp16" in tier16 else 2 ** -8
+    t16 = torch.float16 if "fp16" in tier16 else torch.bfloat16
+    cases = [(torch.float64, sem.FP64, 0.0, 0.0), (torch.float32, sem.FP32, 2 ** -24, 2 ** -24),
+             (torch.float64, sem.FP32, 2 ** -24, 0.0), (torch.float32, k16, e16, 2 ** -24), (t16, k16, e16, e16)]
+    if "bf16" in tier16:
+        cases = cases[3:]
+    for h1, h2 in [(1.0, 0.0), (1 / 1600, 11 / 6 / 5e-4)]:
+        for dt, geom, eps_geo, eps_vec in cases:
+            u = u64.to(dt)
+            w = torch.empty_like(u)
+            c.ax(u, w, h1, h2, geom=geom)
+            torch.cuda.synchronize()
+            ul = _gather(u, els, n3)
+            ref = m.ax(ul, h1, h2)
+            got = _gather(w, els, n3)
+            if geom == sem.FP64:
+                assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+                continue
+            lx = N + 1
+            kk = 2 * lx + 8
+            ua = 2 ** -24 if dt != torch.float64 else 2 ** -53
+            gam = kk * ua / (1 - kk * ua)
+            bound = (gam + 2 * eps_geo + eps_vec) * _op_bound(m, ul, h1, h2)
+            err = np.abs(got - ref)
+            assert np.all(err <= bound), (str(dt), geom, (err / bound).max())
+        del u, w
+    del c
+    torch.cuda.empty_cache()
+
+
+def _copies(e, i, j, k, nel, N):
+    """Local indices of all copies of node (e; i, j, k) of the periodic box, from its structure."""
+    nx, ny, nz = nel
+    lx = N + 1
+    ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
+    opts = []
+    for l, ec, n in ((i, ex, nx), (j, ey, ny), (k, ez, nz)):
+        if l == 0:
+            opts.append([(ec, 0), ((ec - 1) % n, N)])
+        elif l == N:
+            opts.append([(ec, N), ((ec + 1) % n, 0)])
+        else:
+            opts.append([(ec, l)])
+    out = []
+    for ax_, ai in opts[0]:
+        for ay, aj in opts[1]:
+            for az, ak in opts[2]:
+                ee = ax_ + nx * (ay + ny * az)
+                out.append(ee * lx ** 3 + ai + lx * (aj + lx * ak))
+    return sorted(out)
+
+
+def test_c3_dssum_sampled_copy_sets_and_multiplicity(sem):
+    N = 7
+    c = _ctx(sem, C3, N, "fp32b", sem.MODE_OPERATOR, amp=0.1)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(1)
+    u = torch.randn(c.np, dtype=torch.float64, device="cuda:0", generator=g)
+    w = u.clone()
+    c.dssum(w)
+    one = torch.ones(c.np, dtype=torch.float64, device="cuda:0")
+    c.dssum(one)
+    # multiplicity histogram of the conforming periodic box
+    E = c.E
+    counts = {v: int((one == v).sum()) for v in (1.0, 2.0, 4.0, 8.0)}
+    assert sum(counts.values()) == c.np
+    assert counts[1.0] == E * (N - 1) ** 3 and counts[2.0] == E * 6 * (N - 1) ** 2
+    assert counts[4.0] == E * 12 * (N - 1) and counts[8.0] == E * 8
+    # sum over local points of dssum(u) = sum of mult * u
+    assert abs(float(w.sum()) - float((one * u).sum())) <= 1e-10 * float(u.abs().sum())
+    # sampled nodes: the sum of the structural copy set, equal in every copy
+    rng = np.random.default_rng(5)
+    for _ in range(64):
+        e = int(rng.integers(0, E))
+        i, j, k = (int(x) for x in rng.choice([0, N, 1, N - 1, 3], 3))
+        cp = _copies(e, i, j, k, C3, N)
+        idx = torch.tensor(cp, device="cuda:0")
+        uv = u.index_select(0, idx).cpu().numpy()
+        wv = w.index_select(0, idx).cpu().numpy()
+        ref = 0.0
+        for x in uv:
+            ref += x
+        assert np.all(wv == wv[0])
+        assert abs(wv[0] - ref) <= 1e-14 * np.abs(uv).sum()
+    del c, u, w, one
+    torch.cuda.empty_cache()
+
+
+def test_c2_bench_configuration_five_steps_match_oracle(sem):
+    """The benchmark's workload and launch path (32^3, N = 7, Re 1600, dt 5e-4,
+    tolerances 1e-6 / 1e-4), fp64 tier, against the full oracle; the fifth
+    step is the first with pressure iterations."""
+    nel, N, nu, dt = (32, 32, 32), 7, 1 / 1600, 5e-4
+    c = _ctx(sem, nel, N, "fp64", sem.MODE_FLUID, nu=nu, dt=dt, vel_tol=1e-6, pres_tol=1e-4)
+    gst = sem.fluid_step([c], 5)[0]
+    m = OracleMesh(nel, N)
+    f = OracleFluid(m, nu, dt, vtol=1e-6, ptol=1e-4, init=INIT_TGV3D)
+    for k in range(5):
+        o = f.step()
+        g = gst[k]
+        print("step", k + 1, "gpu", g["vit"], g["pit"], "oracle", o["vit"], o["pit"])
+        assert g["status"] == 0
+        assert g["vit"] == o["vit"] and g["pit"] == o["pit"]
+        assert abs(g["ke"] - o["ke"]) <= 1e-9 * o["ke"]
+        assert abs(g["enst"] - o["enst"]) <= 1e-9 * o["enst"]
+    assert sum(s["pit"] for s in gst) > 0
+    ug = c.velocity()
+    uo = f.velocity()
+    assert np.linalg.norm(ug - uo) <= 1e-8 * np.linalg.norm(uo)
+
+
+def test_c4_order11_first_steps_match_oracle_and_fp16_tier_400_steps(sem):
+    nel, N, nu, dt = (16, 16, 16), 11, 1 / 1600, 2.5e-4
+    kw = dict(nu=nu, dt=dt, vel_tol=1e-6, pres_tol=1e-4)
+    c64 = _ctx(sem, nel, N, "fp64", sem.MODE_FLUID, **kw)
+    g3 = sem.fluid_step([c64], 3)[0]
+    m = OracleMesh(nel, N)
+    f = OracleFluid(m, nu, dt, vtol=1e-6, ptol=1e-4, init=INIT_TGV3D)
+    for k in range(3):
+        o = f.step()
+        assert g3[k]["vit"] == o["vit"] and g3[k]["pit"] == o["pit"]
+        assert abs(g3[k]["ke"] - o["ke"]) <= 1e-9 * o["ke"]
+        assert abs(g3[k]["enst"] - o["enst"]) <= 1e-9 * o["enst"]
+    del f, m
+    series = {}
+    for tier in ("fp64", "fp32b+fp16", "fp32b+fp16p"):
+        c = _ctx(sem, nel, N, tier, sem.MODE_FLUID, **kw)
+        d0 = c.diagnostics()
+        st = sem.fluid_step([c], 400)[0]
+        assert all(s["status"] == 0 for s in st), tier
+        series[tier] = ([d0["ke"]] + [s["ke"] for s in st], [d0["enst"]] + [s["enst"] for s in st],
+                        [d0["maxdiv"]] + [s["maxdiv"] for s in st])
+        del c
+    ke64, en64, dv64 = series["fp64"]
+    for tier in ("fp32b+fp16", "fp32b+fp16p"):
+        ke, en, dv = series[tier]
+        eE, eO, eP = e_max(ke, ke64), e_max(en, en64), e_peak(en, en64)
+        ddiv = max(abs(a - b) for a, b in zip(dv, dv64))
+        print(tier, "e_E,max %.3e %%  e_Omega,max %.3e %%  e_Omega,peak %.3e %%  max|div| diff %.3e (fp64 max %.3e)"
+              % (eE, eO, eP, ddiv, max(dv64)))
+        assert eE <= 1e-2 and eO <= 1e-1
