@@ -99,27 +99,88 @@ def _bytes_per_point(kind, tier):
         geo = 2 if (mixed and g16) else vec
         return 2 * vec + 7 * geo
     if kind == "ax_pres":
-        # V_J and w (fp64 basis) + Jacobi diagonal + 6 G
+        # V_J (basis) + Jacobi diagonal + 6 G + w (fp64)
         geo = 8 if not mixed else (2 if tier.endswith("16p") else 4)
+        bv = 4 if mixed else 8
         dg = 4 if mixed else 8
-        return 8 + 8 + dg + 6 * geo
+        return bv + dg + 6 * geo + 8
     raise ValueError(kind)
 
 
-def roofline(kind, tier, prof, steps, npts):
+def _basis_bytes(tier):
+    return 8 if tier in ("fp64",) else 4
+
+
+# the roofline kernel classes: kernel name as rocprofv3 reports it, and the
+# algorithmic bytes of one launch as a function of the Arnoldi index J
+PROF_KERNELS = {
+    "gm_upd_dots": ("gm_pass_kernel<1, %s>", "GMRES CGS2 pass 1: w' = w - mean - sum h_i V_i, dots (V_i, w')",
+                    lambda npts, J, bv: npts * (16 + (J + 1) * bv)),
+    "gm_upd_norm": ("gm_pass_kernel<2, %s>", "GMRES CGS2 pass 2: V_{J+1} = w' - sum h2_i V_i, |V_{J+1}|^2",
+                    lambda npts, J, bv: npts * (8 + (J + 2) * bv)),
+}
+
+
+KERNEL_SOURCES = {"ax_resid": ("k_ax.hip", "k_common.h", "sem_internal.h"),
+                  "ax_vel": ("k_ax.hip", "k_common.h", "sem_internal.h"),
+                  "ax_pres": ("k_ax.hip", "k_common.h", "sem_internal.h")}
+
+
+def kernel_sources_sha(kind="gm_upd_dots"):
+    """Hash of the sources that make a kernel class (a stored PMC traffic
+    figure is valid only for the exact kernel it was taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    base = os.path.join(ROOT, "paper_2608_24348_amd", "csrc")
+    for f in KERNEL_SOURCES.get(kind, ("k_vec.hip", "k_common.h", "k_fin.h", "sem_internal.h")):
+        with open(os.path.join(base, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kind, tier, workload):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary of this
+    kernel class and workload, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kind, tier))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("sources_sha256") != kernel_sources_sha(kind) or d.get("workload") != workload:
+        return None
+    return d["hbm_bytes_per_launch"]
+
+
+def roofline(kind, tier, prof, steps, npts, workload):
     """Achieved HBM bandwidth of one kernel class over the timed region:
-    algorithmic bytes of its active launches / summed HIP-event kernel time of
-    all its launches (gated no-op launches after convergence included)."""
+    algorithmic bytes of its launches / summed HIP-event kernel time of all
+    its launches (gated no-op launches after convergence included)."""
     tot_ms, nlaunch = prof
-    if kind == "gm_upd_dots":
-        tp_bytes = 8
+    bv = _basis_bytes(tier)
+    if kind == "ax_resid":
+        # fp64 operator of the true residuals: per step one velocity check
+        # before the solve and one after every cycle with fp32 vectors (3
+        # components, Helmholtz: u, w, 6 G, B = 72 B/point each), and one
+        # Poisson residual (u, w, 6 G = 64 B/point) at the end of every GMRES
+        # cycle that started from a nonzero iterate; other launches are gated
+        # no-ops (converged requests)
+        alg = 0.0
+        active = 0
+        for s in steps:
+            nv = 1 + (s["vcyc"] if tier != "fp64" else 0)
+            ncyc = (s["pit"] + 29) // 30 if s["pit"] > 0 else 0
+            alg += nv * 3 * npts * 72 + ncyc * npts * 64
+            active += nv + ncyc
+        name = "ax_kernel<8, double, double, double, 0, double> -- fp64 operator of the true residuals"
+    elif kind in PROF_KERNELS:
+        kname, what, fbytes = PROF_KERNELS[kind]
         alg = 0.0
         active = 0
         for s in steps:
             for J in gmres_j_sequence(s["pit"], 30):
-                alg += npts * ((J + 1) * 8 + tp_bytes + 8)
+                alg += fbytes(npts, J, bv)
                 active += 1
-        name = "gm_pass_kernel<1> (GMRES CGS2 update + dots)"
+        name = (kname % ("float" if bv == 4 else "double")) + " -- " + what
     elif kind == "ax_vel":
         active = sum(sum(s["vit"]) for s in steps)  # component launches that did work
         alg = active * npts * _bytes_per_point(kind, tier)
@@ -127,12 +188,13 @@ def roofline(kind, tier, prof, steps, npts):
     else:
         active = sum(s["pit"] for s in steps)
         alg = active * npts * _bytes_per_point(kind, tier)
-        name = "ax_kernel<8,double,...> pressure operator (Arnoldi step)"
+        name = "ax_kernel<8,...> pressure operator (Arnoldi step)"
     achieved = alg / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+    traffic = stored_traffic(kind, tier, workload)
     return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launches": nlaunch, "active_units": active,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "launches": nlaunch, "active_units": active,
             "kernel_ms_total": tot_ms, "avg_launch_ms": tot_ms / max(nlaunch, 1),
-            "alg_bytes_total": alg}
+            "alg_bytes_per_launch": alg / max(nlaunch, 1), "alg_bytes_total": alg}
 
 
 def cpu_baseline(nel, N, nu, dt, pres_iters_per_step, restart=30):
@@ -171,7 +233,11 @@ def main():
     ap.add_argument("--vtol", type=float, default=1e-6)
     ap.add_argument("--ptol", type=float, default=1e-4)
     ap.add_argument("--proj", type=int, default=0, help="pressure projection space (0 = off; the paper uses 20)")
-    ap.add_argument("--prof", default="ax_vel", choices=["ax_vel", "ax_pres", "gm_upd_dots", "none"])
+    ap.add_argument("--prof", default="ax_resid",
+                    choices=["ax_resid", "ax_vel", "ax_pres", "gm_upd_dots", "gm_upd_norm", "none"],
+                    help="kernel class timed with HIP events for the roofline record (default: the dominant kernel)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="finish with plain 1 GiB device copies (calibration of the PMC byte counters)")
     ap.add_argument("--tier", default="fp32b")
     ap.add_argument("--nel", type=int, default=32)
     ap.add_argument("--order", type=int, default=7)
@@ -199,8 +265,9 @@ def main():
     npts = args.nel ** 3 * (N + 1) ** 3
 
     log("bench: %s  %d^3 elements N=%d (%d pts)  dt=%g  Re=%g" % (args.tier, args.nel, N, npts, dt, args.re))
-    prof_class = {"ax_vel": sem.PROF_AX_VEL, "ax_pres": sem.PROF_AX_PRES, "gm_upd_dots": sem.PROF_GM_UPD_DOTS,
-                  "none": None}[args.prof]
+    prof_class = {"ax_resid": sem.PROF_AX_RESID, "ax_vel": sem.PROF_AX_VEL, "ax_pres": sem.PROF_AX_PRES,
+                  "gm_upd_dots": sem.PROF_GM_UPD_DOTS,
+                  "gm_upd_norm": sem.PROF_GM_UPD_NORM, "none": None}[args.prof]
     ctx, t_mx, st_mx, ser_mx, prof = run_tier(sem, torch, args.tier, nel, N, nu, dt, args.warmup, args.steps, prof_class,
                                               args.vtol, args.ptol, args.proj)
     steps_s = args.steps / t_mx
@@ -213,12 +280,15 @@ def main():
                       "global_batch": 1, "seq_len": npts, "parallelism": "single-gpu"}}
     out["iters"] = {"vel": [s["vit"] for s in st_mx], "pres": [s["pit"] for s in st_mx]}
 
-    if prof is not None:
-        out["roofline"] = roofline(args.prof, args.tier, prof, st_mx, npts)
+    if prof is not None and not (args.proj and args.prof == "ax_resid"):
+        # (the launch accounting of ax_resid covers the solver without projection)
+        out["roofline"] = roofline(args.prof, args.tier, prof, st_mx, npts, out["config"]["workload"])
 
     if not args.no_ax:
         g32, ms32 = ax_rate(sem, torch, ctx, torch.float32)
-        out["ax_gdofs"] = {"fp32": g32, "fp32_ms": ms32}
+        out["ax_gdofs"] = {"fp32": g32, "fp32_ms": ms32,
+                           "fp32_hbm_GBps": g32 * 32, "fp32_frac": g32 * 32 / HBM_PEAK_GBS,
+                           "note": "Poisson operator (u, w fp32, 6 G fp32: 32 B/point), HIP events, 20 launches"}
     if not args.no_fp64:
         ctx64, t64, st64, ser64, _ = run_tier(sem, torch, "fp64", nel, N, nu, dt, args.warmup, args.steps, None,
                                               args.vtol, args.ptol, args.proj)
@@ -237,6 +307,8 @@ def main():
             g64, ms64 = ax_rate(sem, torch, ctx64, torch.float64)
             out["ax_gdofs"]["fp64"] = g64
             out["ax_gdofs"]["fp64_ms"] = ms64
+            out["ax_gdofs"]["fp64_hbm_GBps"] = g64 * 64
+            out["ax_gdofs"]["fp64_frac"] = g64 * 64 / HBM_PEAK_GBS
         del ctx64
     del ctx
     torch.cuda.synchronize()
@@ -255,6 +327,15 @@ def main():
         log("cpu baseline: oracle sample of the same workload")
         pbar = sum(s["pit"] for s in st_mx) / len(st_mx)
         out["cpu_baseline"] = cpu_baseline(nel, N, nu, dt, pbar)
+    if args.calib_copy:
+        # plain device copies of known size: what the PMC byte counters read for
+        # exactly 1 GiB read + 1 GiB written per dispatch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b_ = torch.empty_like(a)
+        for _ in range(3):
+            b_.copy_(a)
+        torch.cuda.synchronize()
+        del a, b_
     out["time_breakdown_note"] = "value = %d timed steps / wall time of sem_fluid_step (HIP event profiling of one kernel class on)" % args.steps
     print(json.dumps(out), flush=True)
 

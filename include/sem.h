@@ -131,6 +131,7 @@ typedef struct {
     int vel_iters[3], pres_iters;
     double vel_res[3], pres_res;     /* final residual norms */
     int status;                      /* SEM_OK, SEM_ENAN or SEM_ENOTCONV */
+    int vel_cycles;                  /* velocity solve cycles (fp64 residual checks after the first) */
 } sem_step_stats;
 
 typedef struct {
@@ -258,7 +259,9 @@ enum {
     SEM_PROF_GM_UPD_DOTS = 4, /* GMRES update + second-pass dots */
     SEM_PROF_GM_UPD_NORM = 5, /* GMRES second update + norm */
     SEM_PROF_DSSUM_PRES = 6,  /* dssum of the Arnoldi operator output */
-    SEM_PROF_AX_ANY = 7       /* every standalone sem_ax call */
+    SEM_PROF_AX_ANY = 7,      /* every standalone sem_ax call */
+    SEM_PROF_AX_RESID = 8     /* fp64 operator of the true residuals: velocity checks, GMRES cycle ends,
+                                 projection update */
 };
 int sem_prof_start(int kclass);
 int sem_prof_stop(double* total_ms, int64_t* launches);

@@ -356,7 +356,9 @@ static __device__ __noinline__ void fin_body(ReqDesc* R, int ri, const FinArgs a
             o[0] = S[S_TIME]; o[1] = S[S_KE]; o[2] = S[S_ENST]; o[3] = S[S_MAXDIV];
             for (int c = 0; c < 3; ++c) { o[4 + c] = I[I_VIT + c]; o[7 + c] = S[S_RN + c]; }
             o[10] = I[I_GIT]; o[11] = S[S_GBETA]; o[12] = I[I_NAN]; o[13] = I[I_STEP];
-            o[14] = I[I_VREF] + I[I_VREF + 1] + I[I_VREF + 2]; o[15] = I[I_ORDER];
+            o[14] = I[I_VREF] > I[I_VREF + 1] ? I[I_VREF] : I[I_VREF + 1];
+            if (I[I_VREF + 2] > o[14]) o[14] = I[I_VREF + 2];
+            o[15] = I[I_ORDER];
         }
         break;
     }

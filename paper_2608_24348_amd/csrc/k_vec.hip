@@ -62,7 +62,9 @@ __device__ __forceinline__ void put_partial(const ReqDesc* R, int slot, int blk,
 }
 
 // ------------------------------------------------------------------ generic point-wise ops
-template <typename TV, typename A>
+// one instantiation per operation (OP == a.op): each kernel holds only its
+// own loop, and profiles name the operation
+template <typename TV, typename A, int OP>
 __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs a)
 {
     __shared__ double red[(SEM_VEC_THREADS / 64) * 2];
@@ -76,7 +78,7 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
     const SEM_GLOBAL double* S = gp(R->S);
     double acc[2] = {0.0, 0.0};
 
-    switch (a.op) {
+    switch (OP) {
     case V_VRESID: {
         auto rhs = fld<double>(R, F_RHS + c);
         auto w = fld<double>(R, F_W64 + c);
@@ -200,7 +202,7 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         MulWalk mw(R, pr);
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x, mw.next()) {
             const double fv = f ? f[p] : 1.0;
-            if (a.op == V_SUM_UNIQUE) acc[0] += fv * mw.im();
+            if (OP == V_SUM_UNIQUE) acc[0] += fv * mw.im();
             else acc[0] += fv * B[p];
         }
         double v2[1] = {acc[0]};
@@ -315,18 +317,15 @@ __device__ __forceinline__ void gm_body(const ReqDesc* R, const PtRange& pr, dou
     // the last pass stores the orthogonalised vector as V_{J+1}, unnormalised
     SEM_GLOBAL TB* vn = fldw<TB>(R, F_V) + (long long)NJ * np;
     MulWalk mw(R, pr);
-    for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x, mw.next()) {
-        double vr[NJ];
-#pragma unroll
-        for (int i = 0; i < NJ; ++i) vr[i] = (double)V[i * np + p];
-        const double im = mw.im();
+    // one point: every load of the point was issued before (vr, ws)
+    auto point = [&](long long p, const double (&vr)[NJ], double ws, double im) {
         if (MODE == 0) {
-            const double wv = w[p] * im;
+            const double wv = ws * im;
             accm += wv;
 #pragma unroll
             for (int i = 0; i < NJ; ++i) acc[i] += vr[i] * wv;
         } else if (MODE == 1) {
-            double wv = w[p] - mean;
+            double wv = ws - mean;
 #pragma unroll
             for (int i = 0; i < NJ; ++i) wv -= h[i] * vr[i];
             wd[p] = wv;
@@ -334,12 +333,40 @@ __device__ __forceinline__ void gm_body(const ReqDesc* R, const PtRange& pr, dou
 #pragma unroll
             for (int i = 0; i < NJ; ++i) acc[i] += vr[i] * wv;
         } else {
-            double wv = wd[p];
+            double wv = ws;
 #pragma unroll
             for (int i = 0; i < NJ; ++i) wv -= h[i] * vr[i];
             vn[p] = (TB)wv;
             acc[0] += wv * wv * im;
         }
+    };
+    const SEM_GLOBAL double* win = MODE == 2 ? (const SEM_GLOBAL double*)wd : w;
+    long long p = pr.p0 + threadIdx.x;
+    const long long bd = blockDim.x;
+#ifndef SEM_GM_PAIR_MAX
+#define SEM_GM_PAIR_MAX 12
+#endif
+    if constexpr (NJ <= SEM_GM_PAIR_MAX) {
+        // two points per iteration (p, p + blockDim): twice the loads in
+        // flight; the accumulation order (p before p + blockDim) is unchanged
+        for (; p + bd < pr.p1; p += 2 * bd) {
+            double va[NJ], vb[NJ];
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) { va[i] = (double)V[i * np + p]; vb[i] = (double)V[i * np + p + bd]; }
+            const double wa = win[p], wb = win[p + bd];
+            const double ia = mw.im();
+            mw.next();
+            const double ib = mw.im();
+            mw.next();
+            point(p, va, wa, ia);
+            point(p + bd, vb, wb, ib);
+        }
+    }
+    for (; p < pr.p1; p += bd, mw.next()) {
+        double vr[NJ];
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) vr[i] = (double)V[i * np + p];
+        point(p, vr, win[p], mw.im());
     }
 }
 
@@ -568,9 +595,25 @@ void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s)
         return;
     default: break;
     }
-    if (a.tv == P64) hipLaunchKernelGGL((vec_kernel<double, double>), grid, blk, 0, s, b, a);
-    else if (a.ta == P64) hipLaunchKernelGGL((vec_kernel<float, double>), grid, blk, 0, s, b, a);
-    else hipLaunchKernelGGL((vec_kernel<float, float>), grid, blk, 0, s, b, a);
+    // operations on the velocity solver vectors come in every storage /
+    // accumulation pair; the others are fp64
+#define VEC_T(OP)                                                                                        \
+    case OP:                                                                                             \
+        if (a.tv == P64) hipLaunchKernelGGL((vec_kernel<double, double, OP>), grid, blk, 0, s, b, a);   \
+        else if (a.ta == P64) hipLaunchKernelGGL((vec_kernel<float, double, OP>), grid, blk, 0, s, b, a);\
+        else hipLaunchKernelGGL((vec_kernel<float, float, OP>), grid, blk, 0, s, b, a);                 \
+        return;
+#define VEC_D(OP)                                                                                        \
+    case OP: hipLaunchKernelGGL((vec_kernel<double, double, OP>), grid, blk, 0, s, b, a); return;
+    switch (a.op) {
+        VEC_T(V_PCG_INIT) VEC_T(V_PCG_UPD) VEC_T(V_PCG_P) VEC_T(V_US_ADD)
+        VEC_D(V_VRESID) VEC_D(V_US_COPY) VEC_D(V_RHS) VEC_D(V_IDV) VEC_D(V_SUM_UNIQUE) VEC_D(V_SUM_MASS)
+        VEC_D(V_SUB_MEAN) VEC_D(V_COPY) VEC_D(V_ZERO) VEC_D(V_GM_RESID) VEC_D(V_CORRECT) VEC_D(V_MASS_RAW)
+        VEC_D(V_PR_V) VEC_D(V_AXPY_RAW)
+    default: break;
+    }
+#undef VEC_T
+#undef VEC_D
 }
 
 // ------------------------------------------------------------------ finalise kernel

@@ -570,7 +570,10 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
     const int tv = r.tv;
     int* hf = c0->hflags;
     // fp64 residual of the current state: R64 = RHS - dssum(H U), norms -> VACT
-    ax(b, lx, F_U, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, P64, s);
+    {
+        ProfScope ps(SEM_PROF_AX_RESID, s);
+        ax(b, lx, F_U, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, P64, s);
+    }
     launch_dssum(b, F_W64, 3, P64, -1, nullptr, s);
     vec(b, V_VRESID, 3, P64, -1, s, -1, -1, P64, P64, FIN_VINIT);
     const int maxref = c0->flow.vel_max_refine;
@@ -606,7 +609,10 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
         }
         vec(b, V_US_ADD, 3, tv, -1, s, cyc == 0 ? 1 : 0);
         if (tv == P64) break;  // fp64 recurrence residual is the solver's stop criterion
-        ax(b, lx, F_US, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, P64, s);
+        {
+            ProfScope ps(SEM_PROF_AX_RESID, s);
+            ax(b, lx, F_US, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, P64, s);
+        }
         launch_dssum(b, F_W64, 3, P64, -1, nullptr, s);
         vec(b, V_VRESID, 3, P64, -1, s, -1, -1, P64, P64, FIN_VINIT);
     }
@@ -618,14 +624,17 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
 void gmres_cycle_end(const Batch& b, int lx, const Resolved& r, hipStream_t s)
 {
     vec(b, V_GM_XUPD, 1, r.tpd, I_GEND, s, -1, -1, P64, r.tb);
-    ax(b, lx, F_GX, F_GWD, 1, -1, 1.0, 0.0, -1, -1, I_GENDAX, P64, P64, P64, s);
+    {
+        ProfScope ps(SEM_PROF_AX_RESID, s);
+        ax(b, lx, F_GX, F_GWD, 1, -1, 1.0, 0.0, -1, -1, I_GENDAX, P64, P64, P64, s);
+    }
     launch_dssum(b, F_GWD, 1, P64, I_GENDAX, nullptr, s);
     vec(b, V_GM_RESID, 1, P64, I_GEND, s, -1, -1, P64, r.tb, FIN_GM_RESTART);
 }
 
-// One Arnoldi step of GMRES(m), then the cycle end where pending; every
-// kernel is gated so converged requests idle.
-void gmres_iteration(const Batch& b, int lx, const Resolved& r, hipStream_t s)
+// One Arnoldi step of GMRES(m); every kernel is gated so requests whose
+// cycle ended (or that converged) idle until the next cycle end.
+void gmres_arnoldi(const Batch& b, int lx, const Resolved& r, hipStream_t s)
 {
     {
         // w = A M^{-1} V_J: the Jacobi scaling is applied while loading V_J
@@ -653,7 +662,6 @@ void gmres_iteration(const Batch& b, int lx, const Resolved& r, hipStream_t s)
         ProfScope ps(SEM_PROF_GM_UPD_NORM, s);
         vec(b, V_GM_UPD_NORM, 1, P64, I_GARN, s, -1, -1, P64, r.tb, FIN_GM_COL);
     }
-    gmres_cycle_end(b, lx, r, s);
 }
 
 // GMRES on F_GB -> F_GX in three pieces so a serving loop can change the
@@ -667,15 +675,29 @@ void gmres_start(const Batch& b, int lx, const Resolved& r, hipStream_t s)
     gmres_cycle_end(b, lx, r, s);
 }
 
-// returns the number of requests still iterating, or a negative status
-int gmres_advance(sem_ctx* const* ctxs, const Batch& b, hipStream_t s, int max_iters)
+// Advance by up to max_iters Arnoldi steps; returns the number of requests
+// still iterating, or a negative status.  lockstep: every request of the
+// batch started its solve together, so all active ones reach J + 1 = m at
+// the same step: the cycle-end kernels then run only where a restart is due
+// and before each read of the convergence flags (a request whose cycle ended
+// earlier idles, gated, until then).  Otherwise (requests that joined at
+// different times) the cycle end follows every Arnoldi step.
+int gmres_advance(sem_ctx* const* ctxs, const Batch& b, hipStream_t s, int max_iters, bool lockstep)
 {
     sem_ctx* c0 = ctxs[0];
+    const int m = c0->flow.gmres_restart;
     int K = first_chunk(ctxs, b.n, true);
-    int done = 0, act = 0;
+    int done = 0, act = 0, since = 0;
     while (done < max_iters) {
         const int k = std::min(K, max_iters - done);
-        for (int q = 0; q < k; ++q) gmres_iteration(b, c0->lx, c0->rs, s);
+        for (int q = 0; q < k; ++q) {
+            gmres_arnoldi(b, c0->lx, c0->rs, s);
+            ++since;
+            if (!lockstep || since == m || q == k - 1) {
+                gmres_cycle_end(b, c0->lx, c0->rs, s);
+                if (since == m) since = 0;
+            }
+        }
         done += k;
         K = poll_k();
         act = poll(b, I_GACT, 1, c0->hflags, s);
@@ -707,7 +729,10 @@ void projection_update(const Batch& b, int lx, const Resolved& r, hipStream_t s)
 {
     fin(b, FIN_PR_POST, s);
     vec(b, V_PR_V, 1, P64, -1, s);
-    ax(b, lx, F_GW, F_GWD, 1, -1, 1.0, 0.0, -1, -1, -1, P64, P64, P64, s);
+    {
+        ProfScope ps(SEM_PROF_AX_RESID, s);
+        ax(b, lx, F_GW, F_GWD, 1, -1, 1.0, 0.0, -1, -1, -1, P64, P64, P64, s);
+    }
     launch_dssum(b, F_GWD, 1, P64, -1, nullptr, s);
     vec(b, V_PR_BDOTS, 1, P64, -1, s, -1, -1, P64, r.tb, FIN_PR_BETA);
     vec(b, V_PR_ORTH, 1, P64, I_PRADD, s, -1, -1, P64, r.tb);
@@ -721,7 +746,7 @@ int pressure_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
     const int limit = c0->flow.pres_maxit + c0->flow.pres_maxit / std::max(1, m) + 4;
     const bool proj = c0->flow.mode == SEM_MODE_FLUID && c0->flow.proj_dim > 0;
     gmres_start(b, c0->lx, c0->rs, s);
-    int rc = gmres_advance(ctxs, b, s, limit);
+    int rc = gmres_advance(ctxs, b, s, limit, true);
     if (rc < 0) return rc;
     if (proj) projection_update(b, c0->lx, c0->rs, s);
     gmres_finish(b, s);
@@ -1132,6 +1157,7 @@ int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stat
                 ss.pres_iters = (int)o[10];
                 ss.pres_res = o[11];
                 ss.status = sti;
+                ss.vel_cycles = (int)o[14];
             }
             c->pred_v = std::max(1, (int)std::max(o[4], std::max(o[5], o[6])));
             c->pred_p = std::max(1, (int)o[10]);
@@ -1201,7 +1227,7 @@ int sem_poisson_advance(sem_ctx* const* ctxs, int n, int max_iters, int* active)
     if (rc) return rc;
     if (max_iters < 1) return fail(SEM_EINVAL, "max_iters must be >= 1");
     Batch b = make_batch(ctxs, n);
-    rc = gmres_advance(ctxs, b, ctxs[0]->stream, max_iters);
+    rc = gmres_advance(ctxs, b, ctxs[0]->stream, max_iters, false);
     if (rc < 0) return rc;
     if (active)
         for (int i = 0; i < n; ++i) active[i] = ctxs[0]->hflags[i] != 0;
@@ -1234,7 +1260,7 @@ int sem_poisson_finish(sem_ctx* c, void* sol, sem_solve_stats* st)
 
 int sem_prof_start(int kclass)
 {
-    if (kclass < SEM_PROF_AX_VEL || kclass > SEM_PROF_AX_ANY) return fail(SEM_EINVAL, "unknown profiling class");
+    if (kclass < SEM_PROF_AX_VEL || kclass > SEM_PROF_AX_RESID) return fail(SEM_EINVAL, "unknown profiling class");
     g_prof.kclass = kclass;
     g_prof.used = 0;
     return 0;

@@ -60,7 +60,7 @@ class FlowDesc(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("t", C.c_double), ("ke", C.c_double), ("enst", C.c_double), ("maxdiv", C.c_double),
                 ("vel_iters", C.c_int * 3), ("pres_iters", C.c_int), ("vel_res", C.c_double * 3),
-                ("pres_res", C.c_double), ("status", C.c_int)]
+                ("pres_res", C.c_double), ("status", C.c_int), ("vel_cycles", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -77,7 +77,8 @@ EXPORTS = ["sem_setup", "sem_workspace_bytes", "sem_bind", "sem_ax", "sem_dssum"
            "sem_conv", "sem_opgrad", "sem_wdiv", "sem_sizes", "sem_destroy", "sem_strerror", "sem_last_error",
            "sem_prof_start", "sem_prof_stop", "sem_poisson_begin", "sem_poisson_advance", "sem_poisson_finish",
            "sem_mass", "sem_node_field"]
-PROF_AX_VEL, PROF_AX_PRES, PROF_GM_DOTS, PROF_GM_UPD_DOTS, PROF_GM_UPD_NORM, PROF_DSSUM_PRES, PROF_AX_ANY = range(1, 8)
+PROF_AX_VEL, PROF_AX_PRES, PROF_GM_DOTS, PROF_GM_UPD_DOTS, PROF_GM_UPD_NORM, PROF_DSSUM_PRES, PROF_AX_ANY, PROF_AX_RESID = \
+    range(1, 9)
 
 _lib = None
 
@@ -358,7 +359,8 @@ class Context:
 
 def _stats_dict(s):
     return {"t": s.t, "ke": s.ke, "enst": s.enst, "maxdiv": s.maxdiv, "vit": list(s.vel_iters),
-            "pit": s.pres_iters, "vres": list(s.vel_res), "pres": s.pres_res, "status": s.status}
+            "pit": s.pres_iters, "vres": list(s.vel_res), "pres": s.pres_res, "status": s.status,
+            "vcyc": s.vel_cycles}
 
 
 def fluid_step(ctxs, nsteps=1):
