@@ -90,6 +90,10 @@ def load():
         return _lib
     if not os.path.exists(LIBPATH):
         raise RuntimeError("libsem.so is not built (run __graft_entry__.build() or paper_2608_24348_amd/build.py)")
+    # torch provides device memory and streams: its HIP runtime must be the
+    # process's only one, so it is loaded before libsem (whose HIP dependency
+    # then resolves to the same library instead of a second runtime)
+    import torch  # noqa: F401
     L = C.CDLL(LIBPATH)
     vp = C.c_void_p
     L.sem_setup.argtypes = [C.POINTER(MeshDesc), C.POINTER(FlowDesc), C.POINTER(Precision), C.POINTER(vp)]

@@ -58,6 +58,9 @@ class Server:
         self.torch = torch
         self.device = device
         if budget_bytes is None:
+            # blocks the caching allocator still holds from earlier work are
+            # returned first, so the budget is the device's real free memory
+            torch.cuda.empty_cache()
             free, _ = torch.cuda.mem_get_info(torch.device(device))
             budget_bytes = int(0.9 * free)
         self.budget = int(budget_bytes)
