@@ -122,6 +122,7 @@ PROF_KERNELS = {
 
 
 KERNEL_SOURCES = {"ax_resid": ("k_ax.hip", "k_common.h", "sem_internal.h"),
+                  "ax_presid": ("k_ax.hip", "k_common.h", "sem_internal.h"),
                   "ax_vel": ("k_ax.hip", "k_common.h", "sem_internal.h"),
                   "ax_pres": ("k_ax.hip", "k_common.h", "sem_internal.h")}
 
@@ -158,20 +159,27 @@ def roofline(kind, tier, prof, steps, npts, workload):
     tot_ms, nlaunch = prof
     bv = _basis_bytes(tier)
     if kind == "ax_resid":
-        # fp64 operator of the true residuals: per step one velocity check
-        # before the solve and one after every cycle with fp32 vectors (3
-        # components, Helmholtz: u, w, 6 G, B = 72 B/point each), and one
-        # Poisson residual (u, w, 6 G = 64 B/point) at the end of every GMRES
-        # cycle that started from a nonzero iterate; other launches are gated
-        # no-ops (converged requests)
+        # fp64 velocity residual operator R_L = RHS_L - H_L u (3 components,
+        # Helmholtz: u, RHS_L, w, 6 G, B = 80 B/point each): per step one check
+        # before the solve and, with fp32 vectors, one after every cycle
         alg = 0.0
         active = 0
         for s in steps:
             nv = 1 + (s["vcyc"] if tier != "fp64" else 0)
+            alg += nv * 3 * npts * 80
+            active += nv
+        name = "ax_kernel<8, double, double, double, 0, double, 1> -- fp64 velocity residual RHS_L - H_L u"
+    elif kind == "ax_presid":
+        # fp64 Poisson residual operator at the end of every GMRES cycle that
+        # started from a nonzero iterate (u, w, 6 G = 64 B/point); the other
+        # launches are gated no-ops of converged requests
+        alg = 0.0
+        active = 0
+        for s in steps:
             ncyc = (s["pit"] + 29) // 30 if s["pit"] > 0 else 0
-            alg += nv * 3 * npts * 72 + ncyc * npts * 64
-            active += nv + ncyc
-        name = "ax_kernel<8, double, double, double, 0, double> -- fp64 operator of the true residuals"
+            alg += ncyc * npts * 64
+            active += ncyc
+        name = "ax_kernel<8, double, double, double, 0, double, 0> -- fp64 GMRES cycle-end residual"
     elif kind in PROF_KERNELS:
         kname, what, fbytes = PROF_KERNELS[kind]
         alg = 0.0
@@ -234,7 +242,7 @@ def main():
     ap.add_argument("--ptol", type=float, default=1e-4)
     ap.add_argument("--proj", type=int, default=0, help="pressure projection space (0 = off; the paper uses 20)")
     ap.add_argument("--prof", default="ax_resid",
-                    choices=["ax_resid", "ax_vel", "ax_pres", "gm_upd_dots", "gm_upd_norm", "none"],
+                    choices=["ax_resid", "ax_presid", "ax_vel", "ax_pres", "gm_upd_dots", "gm_upd_norm", "none"],
                     help="kernel class timed with HIP events for the roofline record (default: the dominant kernel)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with plain 1 GiB device copies (calibration of the PMC byte counters)")
@@ -265,7 +273,8 @@ def main():
     npts = args.nel ** 3 * (N + 1) ** 3
 
     log("bench: %s  %d^3 elements N=%d (%d pts)  dt=%g  Re=%g" % (args.tier, args.nel, N, npts, dt, args.re))
-    prof_class = {"ax_resid": sem.PROF_AX_RESID, "ax_vel": sem.PROF_AX_VEL, "ax_pres": sem.PROF_AX_PRES,
+    prof_class = {"ax_resid": sem.PROF_AX_RESID, "ax_presid": sem.PROF_AX_PRESID, "ax_vel": sem.PROF_AX_VEL,
+                  "ax_pres": sem.PROF_AX_PRES,
                   "gm_upd_dots": sem.PROF_GM_UPD_DOTS,
                   "gm_upd_norm": sem.PROF_GM_UPD_NORM, "none": None}[args.prof]
     ctx, t_mx, st_mx, ser_mx, prof = run_tier(sem, torch, args.tier, nel, N, nu, dt, args.warmup, args.steps, prof_class,
@@ -280,8 +289,8 @@ def main():
                       "global_batch": 1, "seq_len": npts, "parallelism": "single-gpu"}}
     out["iters"] = {"vel": [s["vit"] for s in st_mx], "pres": [s["pit"] for s in st_mx]}
 
-    if prof is not None and not (args.proj and args.prof == "ax_resid"):
-        # (the launch accounting of ax_resid covers the solver without projection)
+    if prof is not None and not (args.proj and args.prof == "ax_presid"):
+        # (the launch accounting of ax_presid covers the solver without projection)
         out["roofline"] = roofline(args.prof, args.tier, prof, st_mx, npts, out["config"]["workload"])
 
     if not args.no_ax:

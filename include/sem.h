@@ -260,7 +260,8 @@ enum {
     SEM_PROF_GM_UPD_NORM = 5, /* GMRES second update + norm */
     SEM_PROF_DSSUM_PRES = 6,  /* dssum of the Arnoldi operator output */
     SEM_PROF_AX_ANY = 7,      /* every standalone sem_ax call */
-    SEM_PROF_AX_RESID = 8     /* fp64 operator of the true residuals: velocity checks, GMRES cycle ends,
+    SEM_PROF_AX_RESID = 8,    /* fp64 velocity residual operator, RHS_L - H_L u (3 components) */
+    SEM_PROF_AX_PRESID = 9    /* fp64 Poisson operator of the GMRES cycle-end residuals and the
                                  projection update */
 };
 int sem_prof_start(int kclass);

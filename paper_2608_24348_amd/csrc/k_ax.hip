@@ -48,7 +48,10 @@ template <> __device__ __forceinline__ int bfield<float>() { return F_B32; }
 
 // PC: Jacobi scaling of the input on load (0 none, 1 fp64 diagonal, 2 fp32),
 // a template parameter so the load stays unconditional
-template <int LX, typename TU, typename TG, typename C, int PC, typename TW>
+// SUB: residual form, w = r_L - (operator u) with r_L the local (unassembled)
+// right-hand side a.sub; the caller assembles w afterwards, which equals
+// dssum(r_L) - dssum(operator u) (QQ^T is linear)
+template <int LX, typename TU, typename TG, typename C, int PC, typename TW, int SUB = 0>
 __global__ void __launch_bounds__(Nthr<LX>::v)
 ax_kernel(Batch bt, AxLaunch a)
 {
@@ -112,6 +115,7 @@ ax_kernel(Batch bt, AxLaunch a)
     TG graw[6][NG];
     TG braw[LX];
     TPC praw[PC ? LX : 1];
+    TW rraw[SUB ? LX : 1];
     C ureg[LX], wacc[LX];
     const long long ebase = (long long)ee * L3;
     const long long gbase = (long long)ee * 6 * L3;
@@ -124,6 +128,11 @@ ax_kernel(Batch bt, AxLaunch a)
     if constexpr (PC != 0) {
 #pragma unroll
         for (int k = 0; k < LX; ++k) praw[k] = ldg(pcv + ebase + k * L2 + ij);
+    }
+    if constexpr (SUB != 0) {
+        const SEM_GLOBAL TW* rl = gfield<TW>(R, a.sub + comp);
+#pragma unroll
+        for (int k = 0; k < LX; ++k) rraw[k] = ldg(rl + ebase + k * L2 + ij);
     }
     if (helm) {
 #pragma unroll
@@ -200,7 +209,7 @@ ax_kernel(Batch bt, AxLaunch a)
             const int p = k * L2 + ij;
             const C bk = helm ? to<C>(braw[k]) * bsc : (C)0;
             const C wv = h1 * wacc[k] + h2 * bk * ureg[k];
-            const TW ws = to<TW>(wv);
+            const TW ws = SUB ? (TW)(rraw[k] - to<TW>(wv)) : to<TW>(wv);
             stg(w + ebase + p, ws);
             if (a.pdot >= 0) dot += (double)ureg[k] * (double)to<C>(ws);
         }
@@ -240,6 +249,12 @@ static void ax_go(const Batch& b, const AxLaunch& a, hipStream_t s)
         }
         if (a.precond >= 0) {
             hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 2, TU>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+            return;
+        }
+    }
+    if constexpr (sizeof(TU) == 8 && sizeof(TG) == 8 && sizeof(C) == 8) {
+        if (a.sub >= 0) {
+            hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0, TU, 1>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
             return;
         }
     }

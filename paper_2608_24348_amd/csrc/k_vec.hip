@@ -80,13 +80,10 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
 
     switch (OP) {
     case V_VRESID: {
-        auto rhs = fld<double>(R, F_RHS + c);
-        auto w = fld<double>(R, F_W64 + c);
-        auto r = fldw<double>(R, F_R64 + c);
+        auto r = fld<double>(R, F_R64 + c);
         MulWalk mw(R, pr);
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x, mw.next()) {
-            const double v = rhs[p] - w[p];
-            r[p] = v;
+            const double v = r[p];
             acc[0] += v * v * mw.im();
         }
         double v2[1] = {acc[0]};

@@ -518,11 +518,21 @@ void ax(const Batch& b, int lx, int src, int dst, int ncomp, int hsel, double h1
     AxLaunch a;
     a.src = src; a.src_vj = 0; a.dst = dst; a.ncomp = ncomp; a.hsel = hsel; a.h1 = h1; a.h2 = h2;
     a.precond = precond; a.tpc = P64; a.pdot = pdot; a.gate = gate; a.tu = tu; a.tg = tg; a.tc = tc; a.out64 = 0;
-    a.u_raw = nullptr; a.w_raw = nullptr;
+    a.u_raw = nullptr; a.w_raw = nullptr; a.sub = -1;
     launch_ax(b, lx, a, s);
 }
 
 // fin: FinOp launched right after (the scalar step consuming the partials), or -1
+// R64_L = RHS_L - (h1 A + h2 B) u for the three velocity components (fp64)
+void resid_ax(const Batch& b, int lx, int src, hipStream_t s)
+{
+    AxLaunch a;
+    a.src = src; a.src_vj = 0; a.dst = F_R64; a.ncomp = 3; a.hsel = S_H1; a.h1 = 0; a.h2 = 0;
+    a.precond = -1; a.tpc = P64; a.pdot = -1; a.gate = -1; a.tu = P64; a.tg = P64; a.tc = P64; a.out64 = 0;
+    a.u_raw = nullptr; a.w_raw = nullptr; a.sub = F_RHS;
+    launch_ax(b, lx, a, s);
+}
+
 void vec(const Batch& b, int op, int ncomp, int tv, int gate, hipStream_t s, int f0 = -1, int f1 = -1, int ta = P64,
          int tb = P64, int fin_op = -1)
 {
@@ -569,12 +579,13 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
     const Resolved& r = c0->rs;
     const int tv = r.tv;
     int* hf = c0->hflags;
-    // fp64 residual of the current state: R64 = RHS - dssum(H U), norms -> VACT
+    // fp64 residual of the current state: R64 = dssum(RHS_L - H_L U) (the
+    // local rhs is not assembled on its own), norms -> VACT
     {
         ProfScope ps(SEM_PROF_AX_RESID, s);
-        ax(b, lx, F_U, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, P64, s);
+        resid_ax(b, lx, F_U, s);
     }
-    launch_dssum(b, F_W64, 3, P64, -1, nullptr, s);
+    launch_dssum(b, F_R64, 3, P64, -1, nullptr, s);
     vec(b, V_VRESID, 3, P64, -1, s, -1, -1, P64, P64, FIN_VINIT);
     const int maxref = c0->flow.vel_max_refine;
     for (int cyc = 0; cyc < maxref; ++cyc) {
@@ -611,9 +622,9 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
         if (tv == P64) break;  // fp64 recurrence residual is the solver's stop criterion
         {
             ProfScope ps(SEM_PROF_AX_RESID, s);
-            ax(b, lx, F_US, F_W64, 3, S_H1, 0, 0, -1, -1, -1, P64, P64, P64, s);
+            resid_ax(b, lx, F_US, s);
         }
-        launch_dssum(b, F_W64, 3, P64, -1, nullptr, s);
+        launch_dssum(b, F_R64, 3, P64, -1, nullptr, s);
         vec(b, V_VRESID, 3, P64, -1, s, -1, -1, P64, P64, FIN_VINIT);
     }
     return check_hip_last();
@@ -625,7 +636,7 @@ void gmres_cycle_end(const Batch& b, int lx, const Resolved& r, hipStream_t s)
 {
     vec(b, V_GM_XUPD, 1, r.tpd, I_GEND, s, -1, -1, P64, r.tb);
     {
-        ProfScope ps(SEM_PROF_AX_RESID, s);
+        ProfScope ps(SEM_PROF_AX_PRESID, s);
         ax(b, lx, F_GX, F_GWD, 1, -1, 1.0, 0.0, -1, -1, I_GENDAX, P64, P64, P64, s);
     }
     launch_dssum(b, F_GWD, 1, P64, I_GENDAX, nullptr, s);
@@ -643,7 +654,7 @@ void gmres_arnoldi(const Batch& b, int lx, const Resolved& r, hipStream_t s)
         a.src = -1; a.src_vj = 1; a.dst = F_GW; a.ncomp = 1; a.hsel = -1; a.h1 = 1.0; a.h2 = 0.0;
         a.precond = r.tpd == P64 ? F_IDP64 : F_IDP32; a.tpc = r.tpd; a.pdot = -1; a.gate = I_GARN;
         a.tu = r.tb; a.tg = r.axp_g; a.tc = r.axp_c; a.u_raw = nullptr; a.w_raw = nullptr;
-        a.out64 = 1;
+        a.out64 = 1; a.sub = -1;
         launch_ax(b, lx, a, s);
     }
     {
@@ -730,7 +741,7 @@ void projection_update(const Batch& b, int lx, const Resolved& r, hipStream_t s)
     fin(b, FIN_PR_POST, s);
     vec(b, V_PR_V, 1, P64, -1, s);
     {
-        ProfScope ps(SEM_PROF_AX_RESID, s);
+        ProfScope ps(SEM_PROF_AX_PRESID, s);
         ax(b, lx, F_GW, F_GWD, 1, -1, 1.0, 0.0, -1, -1, -1, P64, P64, P64, s);
     }
     launch_dssum(b, F_GWD, 1, P64, -1, nullptr, s);
@@ -1038,7 +1049,7 @@ int sem_ax(sem_ctx* c, const void* u, void* w, double h1, double h2, int buf_pre
     AxLaunch a;
     a.src = -1; a.src_vj = 0; a.dst = -1; a.ncomp = 1; a.hsel = -1; a.h1 = h1; a.h2 = h2;
     a.precond = -1; a.tpc = P64; a.pdot = -1; a.gate = -1; a.tu = tu; a.tg = tg; a.tc = tc; a.out64 = 0;
-    a.u_raw = u; a.w_raw = w;
+    a.u_raw = u; a.w_raw = w; a.sub = -1;
     {
         ProfScope ps(SEM_PROF_AX_ANY, c->stream);
         launch_ax(b, c->lx, a, c->stream);
@@ -1109,8 +1120,7 @@ int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stat
         // (i) explicit terms: convection, old pressure gradient, BDF/EXT history
         launch_conv(b, lx, r.conv_m, r.conv_c, s);
         launch_opgrad(b, lx, r.opg_m, r.opg_c, F_P, F_GP, s);
-        vec(b, V_RHS, 3, P64, -1, s);
-        launch_dssum(b, F_RHS, 3, P64, -1, nullptr, s);
+        vec(b, V_RHS, 3, P64, -1, s);  // local rhs: assembled together with the residual
         // (ii) velocity Helmholtz solves -> u*
         rc = velocity_solve(ctxs, b, s);
         if (rc) return rc;
@@ -1260,7 +1270,7 @@ int sem_poisson_finish(sem_ctx* c, void* sol, sem_solve_stats* st)
 
 int sem_prof_start(int kclass)
 {
-    if (kclass < SEM_PROF_AX_VEL || kclass > SEM_PROF_AX_RESID) return fail(SEM_EINVAL, "unknown profiling class");
+    if (kclass < SEM_PROF_AX_VEL || kclass > SEM_PROF_AX_PRESID) return fail(SEM_EINVAL, "unknown profiling class");
     g_prof.kclass = kclass;
     g_prof.used = 0;
     return 0;

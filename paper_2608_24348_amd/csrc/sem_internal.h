@@ -235,6 +235,7 @@ struct AxLaunch {
     int gate;                   // I index checked per component (nonzero = run), or -1
     int tu, tg, tc;             // PrecId of vectors, geometry and arithmetic
     int out64;                  // nonzero: the output is fp64 whatever tu is (Arnoldi operator output)
+    int sub;                    // field id of a local rhs r_L: output r_L - (operator u) (fp64 only), or -1
     const void* u_raw;          // direct pointers (standalone sem_ax), used when src < 0
     void* w_raw;
 };
@@ -258,7 +259,7 @@ void launch_diagnostics(const Batch& b, int lx, hipStream_t s);
 
 // point-wise / reduction / scalar kernels
 enum VecOp : int {
-    V_VRESID = 0,     // R64 = RHS - W64, partial |R64|^2 -> R_A+c
+    V_VRESID = 0,     // partial |R64|^2 -> R_A+c (R64 = dssum(RHS_L - H_L u), formed by the operator)
     V_PCG_INIT,       // PX = 0, PR = R64, PZ = PR*IDV, PP = PZ, partial (r,z) -> R_B+c
     V_PCG_UPD,        // PX += a PP, PR -= a PW, PZ = PR*IDV, partials (r,r) -> R_B+c, (r,z) -> R_C+c
     V_PCG_P,          // PP = PZ + b PP
