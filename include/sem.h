@@ -235,6 +235,15 @@ int sem_node_field(sem_ctx* ctx, int what, double amp, double* out);
 /* time and step counter (for checkpoint/restart) */
 int sem_set_clock(sem_ctx* ctx, double t, int step);
 
+/* Step-level precision (the time/step level of Fig. 4): copy the fluid state
+ * of src (velocity and its two lags, the two convection lags, pressure, time
+ * and step count) into dst, a bound fluid context on the same device with
+ * the same mesh, dt and BDF/EXT order and any precision tier; dst then
+ * continues the run in its tier.  Exact (the state is fp64 in every tier);
+ * dst's projection space starts empty.  Synchronises both streams.  Returns
+ * SEM_EINVAL when the contexts do not match, SEM_ESTATE when one is not bound. */
+int sem_copy_state(sem_ctx* dst, sem_ctx* src);
+
 /* Kinetic energy, enstrophy and max |div u| of the current velocity
  * (computes them; synchronises). */
 int sem_diagnostics(sem_ctx* ctx, sem_diag* out);

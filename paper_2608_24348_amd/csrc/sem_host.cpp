@@ -1380,6 +1380,49 @@ int sem_node_field(sem_ctx* c, int what, double amp, double* out)
     return check_hip_last();
 }
 
+// The time/step level of the precision model (Fig. 4): a run may change
+// tiers between steps by carrying its state into a context of another tier.
+// Every state field is fp64 in every tier, so the copy is exact.
+int sem_copy_state(sem_ctx* dst, sem_ctx* src)
+{
+    int rc = bind_check(dst);
+    if (rc) return rc;
+    if ((rc = bind_check(src))) return rc;
+    if (dst == src) return fail(SEM_EINVAL, "source and destination are the same context");
+    if (dst->flow.mode != SEM_MODE_FLUID || src->flow.mode != SEM_MODE_FLUID)
+        return fail(SEM_EINVAL, "sem_copy_state needs two fluid-mode contexts");
+    const sem_mesh_desc& a = dst->mesh;
+    const sem_mesh_desc& b = src->mesh;
+    bool same = a.order == b.order && a.deform_amp == b.deform_amp;
+    for (int d = 0; d < 3; ++d) same = same && a.nel[d] == b.nel[d] && a.lo[d] == b.lo[d] && a.hi[d] == b.hi[d];
+    for (int q = 0; q < 9; ++q) same = same && a.deform_phase[q] == b.deform_phase[q];
+    if (!same) return fail(SEM_EINVAL, "sem_copy_state needs the same mesh");
+    if (dst->flow.dt != src->flow.dt || dst->flow.torder != src->flow.torder)
+        return fail(SEM_EINVAL, "sem_copy_state needs the same time step and BDF/EXT order (the history is at dt spacing)");
+    static const int fids[] = {F_U, F_U + 1, F_U + 2, F_UL1, F_UL1 + 1, F_UL1 + 2, F_UL2, F_UL2 + 1, F_UL2 + 2,
+                               F_BNL1, F_BNL1 + 1, F_BNL1 + 2, F_BNL2, F_BNL2 + 1, F_BNL2 + 2, F_P};
+    HIPCHK(hipStreamSynchronize(src->stream));
+    HIPCHK(hipStreamSynchronize(dst->stream));
+    for (int fid : fids) {
+        char *ps, *pd;
+        if ((rc = current_ptr(src, fid, &ps))) return rc;
+        if ((rc = current_ptr(dst, fid, &pd))) return rc;
+        HIPCHK(hipMemcpyAsync(pd, ps, 8 * (size_t)dst->np, hipMemcpyDeviceToDevice, dst->stream));
+    }
+    // clock and step (the BDF/EXT order ramp follows the step count); the
+    // projection space starts empty in the new tier
+    HIPCHK(hipMemcpyAsync(dst->hdesc.S + S_TIME, src->hdesc.S + S_TIME, sizeof(double), hipMemcpyDeviceToDevice,
+                          dst->stream));
+    HIPCHK(hipMemcpyAsync(dst->hdesc.I + I_STEP, src->hdesc.I + I_STEP, sizeof(int), hipMemcpyDeviceToDevice,
+                          dst->stream));
+    const int zero = 0;
+    HIPCHK(hipMemcpyAsync(dst->hdesc.I + I_PRL, &zero, sizeof(int), hipMemcpyHostToDevice, dst->stream));
+    HIPCHK(hipStreamSynchronize(dst->stream));
+    dst->pred_v = src->pred_v;
+    dst->pred_p = src->pred_p;
+    return 0;
+}
+
 int sem_set_clock(sem_ctx* c, double t, int step)
 {
     int rc = bind_check(c);

@@ -76,7 +76,7 @@ EXPORTS = ["sem_setup", "sem_workspace_bytes", "sem_bind", "sem_ax", "sem_dssum"
            "sem_poisson_solve", "sem_get_field", "sem_set_field", "sem_set_clock", "sem_diagnostics",
            "sem_conv", "sem_opgrad", "sem_wdiv", "sem_sizes", "sem_destroy", "sem_strerror", "sem_last_error",
            "sem_prof_start", "sem_prof_stop", "sem_poisson_begin", "sem_poisson_advance", "sem_poisson_finish",
-           "sem_mass", "sem_node_field"]
+           "sem_mass", "sem_node_field", "sem_copy_state"]
 PROF_AX_VEL, PROF_AX_PRES, PROF_GM_DOTS, PROF_GM_UPD_DOTS, PROF_GM_UPD_NORM, PROF_DSSUM_PRES, PROF_AX_ANY, PROF_AX_RESID, \
     PROF_AX_PRESID = range(1, 10)
 
@@ -121,6 +121,7 @@ def load():
     L.sem_poisson_finish.argtypes = [vp, vp, C.POINTER(SolveStats)]
     L.sem_mass.argtypes = [vp, vp, vp, C.c_int]
     L.sem_node_field.argtypes = [vp, C.c_int, C.c_double, vp]
+    L.sem_copy_state.argtypes = [vp, vp]
     L.sem_prof_start.argtypes = [C.c_int]
     L.sem_prof_stop.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     _lib = L
@@ -423,3 +424,24 @@ def poisson_solve(ctxs, rhs, sol):
     st = (SolveStats * n)()
     _check(load().sem_poisson_solve(arr, n, r, s, st))
     return [{"iters": st[i].iters, "res": st[i].res, "status": st[i].status} for i in range(n)]
+
+
+def copy_state(dst, src):
+    """Carry the fluid state of context src into dst (same mesh and dt, any tier)."""
+    _check(load().sem_copy_state(dst.h, src.h))
+
+
+def run_schedule(mesh, flow, schedule, device="cuda:0"):
+    """Run a step-level precision schedule, e.g. [("fp64", 100), ("fp32b", 100)]:
+    each phase runs its steps in a context of its tier, starting from the
+    state the previous phase ended with.  Returns the per-step statistics."""
+    stats = []
+    prev = None
+    for name, nsteps in schedule:
+        ctx = Context(mesh, flow, tier(name), device=device)
+        if prev is not None:
+            copy_state(ctx, prev)
+            prev.close()
+        stats += fluid_step([ctx], nsteps)[0]
+        prev = ctx
+    return stats, prev

@@ -257,3 +257,45 @@ def test_mixed_tier_c1_energy_and_enstrophy_error(sem, tier, proj):
     print(tier, "e_E,max %.3e %%  e_Omega,max %.3e %%" % (eE, eO), "pit", [s["pit"] for s in gst])
     lim = (1e-4, 1e-3) if tier == "fp32b" else (1e-2, 1e-1)
     assert eE <= lim[0] and eO <= lim[1]
+
+
+def test_copy_state_continues_the_run_bitwise(sem):
+    """Carrying the state to a fresh context (same tier) continues the run
+    exactly: the step-level precision control hands over an exact state."""
+    nel, N, nu, dt = (4, 4, 4), 7, 1 / 800, 1e-3
+    a = _ctx(sem, nel, N, nu=nu, dt=dt)
+    sem.fluid_step([a], 5)
+    b = _ctx(sem, nel, N, nu=nu, dt=dt)
+    sem.copy_state(b, a)
+    sa = sem.fluid_step([a], 3)[0]
+    sb = sem.fluid_step([b], 3)[0]
+    assert [s["pit"] for s in sa] == [s["pit"] for s in sb]
+    assert [s["t"] for s in sa] == [s["t"] for s in sb]
+    assert np.array_equal(a.velocity(), b.velocity()) and np.array_equal(a.pressure(), b.pressure())
+    # mismatched meshes are refused
+    c = _ctx(sem, (4, 4, 2), N, nu=nu, dt=dt)
+    with pytest.raises(sem.SemError):
+        sem.copy_state(c, a)
+
+
+def test_precision_schedule_fp64_then_fp32b_c1(sem):
+    """Time/step-level precision (Fig. 4): fp64 for the first 5 steps of C1,
+    fp32b for the next 5; the fp64 phase is bitwise the fp64 run, the whole
+    series stays within the fp32b error bounds against the oracle."""
+    from oracle import e_max
+    nel, N, nu, dt = (8, 8, 8), 7, 1 / 1600, 1e-3
+    mesh = sem.mesh_desc(nel, N)
+    flow = sem.flow_desc(nu=nu, dt=dt)
+    sched, last = sem.run_schedule(mesh, flow, [("fp64", 5), ("fp32b", 5)])
+    ref = _ctx(sem, nel, N, nu=nu, dt=dt)
+    r64 = sem.fluid_step([ref], 5)[0]
+    assert [s["ke"] for s in sched[:5]] == [s["ke"] for s in r64]
+    m = OracleMesh(nel, N)
+    f = OracleFluid(m, nu, dt, init=INIT_TGV3D)
+    ost = [f.step() for _ in range(10)]
+    assert all(s["status"] == 0 for s in sched)
+    assert abs(sched[-1]["t"] - 10 * dt) < 1e-12
+    eE = e_max([s["ke"] for s in sched], [s["ke"] for s in ost])
+    eO = e_max([s["enst"] for s in sched], [s["enst"] for s in ost])
+    print("schedule fp64 x5 + fp32b x5: e_E,max %.3e %%  e_Omega,max %.3e %%" % (eE, eO))
+    assert eE <= 1e-4 and eO <= 1e-3

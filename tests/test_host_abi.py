@@ -86,7 +86,8 @@ def test_policy_rules():
 
 def test_flow_validation():
     md = sem.mesh_desc((2, 2, 2), 4)
-    for kw in (dict(nu=0.0), dict(dt=-1.0), dict(torder=4), dict(restart=31), dict(vel_tol=0.0), dict(max_refine=0)):
+    for kw in (dict(nu=0.0), dict(dt=-1.0), dict(torder=4), dict(restart=31), dict(vel_tol=0.0), dict(max_refine=0),
+               dict(proj=-1), dict(proj=21), dict(mode=sem.MODE_POISSON, proj=5)):
         with pytest.raises(sem.SemError):
             sem.Context(md, sem.flow_desc(**kw), sem.tier("fp64"), bind=False)
 
@@ -96,3 +97,5 @@ def test_unbound_context_calls_fail_cleanly():
     L = sem.load()
     assert L.sem_dssum(c.h, C.c_void_p(1), 0) == -6
     assert L.sem_ax(c.h, C.c_void_p(1), C.c_void_p(1), 1.0, 0.0, 0, -1, 0) == -6
+    d = sem.Context(sem.mesh_desc((2, 2, 2), 3), sem.flow_desc(), sem.tier("fp32b"), bind=False)
+    assert L.sem_copy_state(d.h, c.h) == -6
