@@ -69,6 +69,14 @@ def _load():
     L.orc_opgrad.argtypes = [vp, _dp, _dp, _dp, _dp]
     L.orc_wdiv.argtypes = [vp, _dp, _dp, _dp, _dp]
     L.orc_conv.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_conv_dealias.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_gl.restype = C.c_int
+    L.orc_gl.argtypes = [C.c_int, _dp, _dp]
+    L.orc_lxd.restype = C.c_int
+    L.orc_lxd.argtypes = [C.c_int]
+    L.orc_interp.argtypes = [C.c_int, _dp, C.c_int, _dp, _dp]
+    L.orc_fluid_set_dealias.restype = C.c_int
+    L.orc_fluid_set_dealias.argtypes = [vp, C.c_int]
     L.orc_curl_div.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_diagnostics.argtypes = [vp, _dp, _dp, _dp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.POINTER(C.c_double)]
@@ -120,6 +128,28 @@ def _load():
 
 def num_threads():
     return _load().orc_num_threads()
+
+
+def gl(n):
+    """Gauss-Legendre nodes and weights (n points)."""
+    L = _load()
+    z = np.zeros(n)
+    w = np.zeros(n)
+    if L.orc_gl(n, z, w) != 0:
+        raise ValueError("unsupported point count %d" % n)
+    return z, w
+
+
+def lxd(lx):
+    """Points per direction of the 3/2-rule dealiasing grid."""
+    return _load().orc_lxd(int(lx))
+
+
+def interp_matrix(xi, z):
+    """Lagrange basis of the nodes xi evaluated at the points z: I[q, l]."""
+    I = np.zeros(len(z) * len(xi))
+    _load().orc_interp(len(xi), _c(xi), len(z), _c(z), I)
+    return I.reshape(len(z), len(xi))
 
 
 def gll(N):
@@ -262,6 +292,12 @@ class OracleMesh:
         self.L.orc_conv(self.h, _c(u[0]), _c(u[1]), _c(u[2]), *o)
         return np.stack(o)
 
+    def conv_dealias(self, u):
+        """-B (u . grad) u integrated on the 3/2-rule Gauss-Legendre grid."""
+        o = [np.zeros(self.np) for _ in range(3)]
+        self.L.orc_conv_dealias(self.h, _c(u[0]), _c(u[1]), _c(u[2]), *o)
+        return np.stack(o)
+
     def curl_div(self, u):
         o = [np.zeros(self.np) for _ in range(4)]
         self.L.orc_curl_div(self.h, _c(u[0]), _c(u[1]), _c(u[2]), *o)
@@ -358,7 +394,7 @@ class OracleFluid:
     """FP64 TGV stepper on an OracleMesh (keeps a reference to the mesh)."""
 
     def __init__(self, mesh, nu, dt, torder=3, vtol=1e-8, ptol=1e-8, vmaxit=500, pmaxit=1000,
-                 restart=30, init=INIT_TGV3D, proj=0):
+                 restart=30, init=INIT_TGV3D, proj=0, dealias=False):
         self.mesh = mesh
         self.L = mesh.L
         self.h = self.L.orc_fluid_new(mesh.h, float(nu), float(dt), int(torder), float(vtol), float(ptol),
@@ -367,6 +403,7 @@ class OracleFluid:
             raise ValueError("invalid fluid parameters")
         if self.L.orc_fluid_set_proj(self.h, int(proj)) != 0:
             raise ValueError("invalid projection dimension")
+        self.L.orc_fluid_set_dealias(self.h, 1 if dealias else 0)
 
     @property
     def proj_size(self):

@@ -655,6 +655,210 @@ void orc_conv(const orc_mesh* m, const double* ux, const double* uy, const doubl
     }
 }
 
+/* ------------------------------------------------------------------ */
+/* Dealiased convection (3/2 rule): the convective term is integrated   */
+/* on lxd = ceil(3 lx / 2) Gauss-Legendre points per direction instead  */
+/* of by collocation on the GLL points (the paper runs with dealiasing, */
+/* Sec. 3).  Velocity and its reference derivatives are interpolated to */
+/* the fine points, the geometry there comes from the interpolated      */
+/* coordinates, and the weighted integrand is tested against every GLL  */
+/* basis function (transposed interpolation):                            */
+/*   BN_f(l) = - sum_q w_q jac_q phi_l(z_q) sum_c u_c(z_q) du_f/dx_c(z_q) */
+/* ------------------------------------------------------------------ */
+#define ORC_MAXLXD 24
+
+int orc_lxd(int lx) { return (3 * lx + 1) / 2; }
+
+/* Gauss-Legendre nodes (roots of P_n) and weights 2 / ((1 - z^2) P_n'(z)^2). */
+int orc_gl(int n, double* z, double* w)
+{
+    if (n < 1 || n > ORC_MAXLXD) return -1;
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        double x = -cos(pi * (i + 0.75) / (n + 0.5));   /* Chebyshev-like start */
+        for (int it = 0; it < 100; ++it) {
+            double P, dP;
+            legendre(n, x, &P, &dP);
+            double dx = P / dP;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        double P, dP;
+        legendre(n, x, &P, &dP);
+        z[i] = x;
+        w[i] = 2.0 / ((1.0 - x * x) * dP * dP);
+    }
+    /* symmetric node set */
+    for (int i = 0; i < n / 2; ++i) {
+        double a = 0.5 * (z[n - 1 - i] - z[i]);
+        z[i] = -a; z[n - 1 - i] = a;
+        double b = 0.5 * (w[i] + w[n - 1 - i]);
+        w[i] = b; w[n - 1 - i] = b;
+    }
+    if (n % 2) z[n / 2] = 0.0;
+    return 0;
+}
+
+/* Lagrange basis of the GLL nodes xi (lx of them) at the points z (nz):
+ * I[q * lx + l] = prod_{m != l} (z_q - xi_m) / (xi_l - xi_m). */
+void orc_interp(int lx, const double* xi, int nz, const double* z, double* I)
+{
+    for (int q = 0; q < nz; ++q)
+        for (int l = 0; l < lx; ++l) {
+            double v = 1.0;
+            for (int mm = 0; mm < lx; ++mm)
+                if (mm != l) v *= (z[q] - xi[mm]) / (xi[l] - xi[mm]);
+            I[q * lx + l] = v;
+        }
+}
+
+/* out[c3][c2][c1] = sum A1[c1][a] A2[c2][b] A3[c3][c] in[c][b][a] with
+ * A_d of size (nout_d x nin): the tensor-product map of three 1D matrices
+ * (index order k slowest, i fastest on both sides). */
+static void tensor3(int nin, int n1, int n2, int n3, const double* A1, const double* A2, const double* A3,
+                    const double* in, double* out)
+{
+    double t1[ORC_MAXLXD * ORC_MAXLXD * ORC_MAXLXD], t2[ORC_MAXLXD * ORC_MAXLXD * ORC_MAXLXD];
+    /* along i */
+    for (int c = 0; c < nin; ++c)
+        for (int b = 0; b < nin; ++b)
+            for (int i = 0; i < n1; ++i) {
+                double s = 0;
+                for (int a = 0; a < nin; ++a) s += A1[i * nin + a] * in[a + nin * (b + nin * c)];
+                t1[i + n1 * (b + nin * c)] = s;
+            }
+    /* along j */
+    for (int c = 0; c < nin; ++c)
+        for (int j = 0; j < n2; ++j)
+            for (int i = 0; i < n1; ++i) {
+                double s = 0;
+                for (int b = 0; b < nin; ++b) s += A2[j * nin + b] * t1[i + n1 * (b + nin * c)];
+                t2[i + n1 * (j + n2 * c)] = s;
+            }
+    /* along k */
+    for (int k = 0; k < n3; ++k)
+        for (int j = 0; j < n2; ++j)
+            for (int i = 0; i < n1; ++i) {
+                double s = 0;
+                for (int c = 0; c < nin; ++c) s += A3[k * nin + c] * t2[i + n1 * (j + n2 * c)];
+                out[i + n1 * (j + n2 * k)] = s;
+            }
+}
+
+/* transposed map: out[c][b][a] = sum_{k,j,i} A1[i][a] A2[j][b] A3[k][c] in[k][j][i] */
+static void tensor3_t(int nout, int n1, int n2, int n3, const double* A1, const double* A2, const double* A3,
+                      const double* in, double* out)
+{
+    double t1[ORC_MAXLXD * ORC_MAXLXD * ORC_MAXLXD], t2[ORC_MAXLXD * ORC_MAXLXD * ORC_MAXLXD];
+    for (int k = 0; k < n3; ++k)
+        for (int j = 0; j < n2; ++j)
+            for (int a = 0; a < nout; ++a) {
+                double s = 0;
+                for (int i = 0; i < n1; ++i) s += A1[i * nout + a] * in[i + n1 * (j + n2 * k)];
+                t1[a + nout * (j + n2 * k)] = s;
+            }
+    for (int k = 0; k < n3; ++k)
+        for (int b = 0; b < nout; ++b)
+            for (int a = 0; a < nout; ++a) {
+                double s = 0;
+                for (int j = 0; j < n2; ++j) s += A2[j * nout + b] * t1[a + nout * (j + n2 * k)];
+                t2[a + nout * (b + nout * k)] = s;
+            }
+    for (int c = 0; c < nout; ++c)
+        for (int b = 0; b < nout; ++b)
+            for (int a = 0; a < nout; ++a) {
+                double s = 0;
+                for (int k = 0; k < n3; ++k) s += A3[k * nout + c] * t2[a + nout * (b + nout * k)];
+                out[a + nout * (b + nout * c)] = s;
+            }
+}
+
+void orc_conv_dealias(const orc_mesh* m, const double* ux, const double* uy, const double* uz,
+                      double* bx, double* by, double* bz)
+{
+    const int lx = m->lx, nd = orc_lxd(lx);
+    const long n3 = (long)lx * lx * lx, np = m->np;
+    const long nd3 = (long)nd * nd * nd;
+    double z[ORC_MAXLXD], wz[ORC_MAXLXD], I[ORC_MAXLXD * ORC_MAXLX], ID[ORC_MAXLXD * ORC_MAXLX];
+    orc_gl(nd, z, wz);
+    orc_interp(lx, m->xi, nd, z, I);
+    /* derivative values at the fine points: ID = I D (D u holds the nodal
+     * values of the derivative polynomial, which I interpolates exactly) */
+    for (int q = 0; q < nd; ++q)
+        for (int l = 0; l < lx; ++l) {
+            double s = 0;
+            for (int mm = 0; mm < lx; ++mm) s += I[q * lx + mm] * m->D[mm * lx + l];
+            ID[q * lx + l] = s;
+        }
+    const double* U[3] = { ux, uy, uz };
+    double* O[3] = { bx, by, bz };
+    #pragma omp parallel
+    {
+        double* xr = dalloc(9 * nd3);     /* xr[(c*3+a)] = d x_c / d r_a at fine points */
+        double* rx = dalloc(9 * nd3);     /* rx[(a*3+c)] = d r_a / d x_c times the fine weight W */
+        double* uf = dalloc(3 * nd3);     /* velocity at fine points */
+        double* g = dalloc(3 * nd3);      /* reference derivatives of one component */
+        double* t = dalloc(nd3);
+        double ue[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX], o[ORC_MAXLX * ORC_MAXLX * ORC_MAXLX];
+        #pragma omp for
+        for (int e = 0; e < m->E; ++e) {
+            /* geometry at the fine points from the interpolated coordinates */
+            for (int c = 0; c < 3; ++c) {
+                for (long q = 0; q < n3; ++q) ue[q] = m->xyz[(long)c * np + e * n3 + q];
+                tensor3(lx, nd, nd, nd, ID, I, I, ue, xr + (long)(c * 3 + 0) * nd3);
+                tensor3(lx, nd, nd, nd, I, ID, I, ue, xr + (long)(c * 3 + 1) * nd3);
+                tensor3(lx, nd, nd, nd, I, I, ID, ue, xr + (long)(c * 3 + 2) * nd3);
+            }
+            for (int k = 0; k < nd; ++k)
+            for (int j = 0; j < nd; ++j)
+            for (int i = 0; i < nd; ++i) {
+                long q = i + nd * (j + (long)nd * k);
+                double J[3][3];
+                for (int c = 0; c < 3; ++c)
+                    for (int a = 0; a < 3; ++a) J[c][a] = xr[(long)(c * 3 + a) * nd3 + q];
+                double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+                           - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+                           + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                double inv[3][3];
+                inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+                inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+                inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+                inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+                inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+                inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+                inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+                inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+                inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+                double W = det * wz[i] * wz[j] * wz[k];
+                for (int a = 0; a < 3; ++a)
+                    for (int c = 0; c < 3; ++c) rx[(long)(a * 3 + c) * nd3 + q] = W * inv[a][c];
+            }
+            for (int c = 0; c < 3; ++c) {
+                for (long q = 0; q < n3; ++q) ue[q] = U[c][e * n3 + q];
+                tensor3(lx, nd, nd, nd, I, I, I, ue, uf + (long)c * nd3);
+            }
+            for (int f = 0; f < 3; ++f) {
+                for (long q = 0; q < n3; ++q) ue[q] = U[f][e * n3 + q];
+                tensor3(lx, nd, nd, nd, ID, I, I, ue, g);
+                tensor3(lx, nd, nd, nd, I, ID, I, ue, g + nd3);
+                tensor3(lx, nd, nd, nd, I, I, ID, ue, g + 2 * nd3);
+                for (long q = 0; q < nd3; ++q) {
+                    double s = 0;
+                    for (int c = 0; c < 3; ++c) {
+                        double dx = 0;
+                        for (int a = 0; a < 3; ++a) dx += rx[(long)(a * 3 + c) * nd3 + q] * g[(long)a * nd3 + q];
+                        s += uf[(long)c * nd3 + q] * dx;
+                    }
+                    t[q] = s;
+                }
+                tensor3_t(lx, nd, nd, nd, I, I, I, t, o);
+                for (long q = 0; q < n3; ++q) O[f][e * n3 + q] = -o[q];
+            }
+        }
+        free(xr); free(rx); free(uf); free(g); free(t);
+    }
+}
+
 /* Element-local vorticity and divergence (no inter-element averaging). */
 void orc_curl_div(const orc_mesh* m, const double* ux, const double* uy, const double* uz,
                   double* wx, double* wy, double* wz, double* dv)
@@ -1006,6 +1210,7 @@ typedef struct {
     int vit[3], pit;
     double vres[3], pres;
     orc_proj* proj;                     /* pressure projection space, or NULL */
+    int dealias;                        /* convection on the 3/2 Gauss-Legendre grid */
 } orc_fluid;
 
 typedef struct {
@@ -1065,6 +1270,26 @@ int orc_fluid_set_proj(orc_fluid* f, int L)
 }
 
 int orc_fluid_proj_size(const orc_fluid* f) { return f->proj ? f->proj->l : 0; }
+
+static void fluid_conv(const orc_fluid* f, const double* ux, const double* uy, const double* uz,
+                       double* bx, double* by, double* bz)
+{
+    if (f->dealias) orc_conv_dealias(f->m, ux, uy, uz, bx, by, bz);
+    else orc_conv(f->m, ux, uy, uz, bx, by, bz);
+}
+
+/* dealiased (1) or collocated (0) convection; the history of a fresh run
+ * (lags = initial condition) is recomputed with the chosen form */
+int orc_fluid_set_dealias(orc_fluid* f, int on)
+{
+    f->dealias = on ? 1 : 0;
+    if (f->step == 0) {
+        long np = f->m->np;
+        fluid_conv(f, f->u[0], f->u[1], f->u[2], f->bn1[0], f->bn1[1], f->bn1[2]);
+        for (int c = 0; c < 3; ++c) memcpy(f->bn2[c], f->bn1[c], np * sizeof(double));
+    }
+    return 0;
+}
 
 void orc_fluid_free(orc_fluid* f)
 {
@@ -1128,7 +1353,7 @@ int orc_fluid_step(orc_fluid* f, orc_step_stats* st)
     double* rp = dalloc(np); double* phi = dalloc(np);
 
     /* (i) explicit RHS: extrapolated convection, BDF history, old pressure gradient */
-    orc_conv(m, f->u[0], f->u[1], f->u[2], bn[0], bn[1], bn[2]);
+    fluid_conv(f, f->u[0], f->u[1], f->u[2], bn[0], bn[1], bn[2]);
     orc_opgrad(m, f->p, gp[0], gp[1], gp[2]);
     for (int c = 0; c < 3; ++c) {
         const double* BN[3] = { bn[c], f->bn1[c], f->bn2[c] };

@@ -11,7 +11,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle import OracleMesh, OracleFluid, OracleProjection, gll, deriv_matrix, e_max, e_peak, e_series
+from oracle import OracleMesh, OracleFluid, OracleProjection, gll, gl, lxd, interp_matrix, deriv_matrix, e_max, e_peak, e_series
 from oracle.oracle import INIT_TGV2D, INIT_TGV3D
 from paper_2608_24348_amd import inputs
 
@@ -343,6 +343,111 @@ def test_element_subset_mesh_reproduces_full_mesh_elements():
     assert np.array_equal(sub.conv(v[:, pick]), full.conv(v)[:, pick])
 
 
+# ---------------------------------------------------------------- dealiased convection
+@pytest.mark.parametrize("n", list(range(1, 25)))
+def test_gauss_legendre_matches_numpy(n):
+    z, w = gl(n)
+    zr, wr = np.polynomial.legendre.leggauss(n)
+    assert np.allclose(z, zr, atol=1e-14, rtol=0) and np.allclose(w, wr, atol=1e-14, rtol=0)
+
+
+def test_dealias_grid_and_interpolation_matrix():
+    assert [lxd(lx) for lx in (4, 6, 8, 10, 12)] == [6, 9, 12, 15, 18]
+    for N in (3, 5, 7):
+        xi, _ = gll(N)
+        z, _ = gl(lxd(N + 1))
+        I = interp_matrix(xi, z)
+        P = np.polynomial.polynomial
+        for l in range(N + 1):
+            others = np.delete(xi, l)
+            c = P.polyfromroots(others) / np.prod(xi[l] - others)
+            assert np.allclose(I[:, l], P.polyval(z, c), atol=1e-13, rtol=0)
+        # interpolation reproduces polynomials of degree <= N
+        for k in range(N + 1):
+            assert np.allclose(I @ xi ** k, z ** k, atol=1e-13, rtol=0)
+
+
+def _lagrange_polys(xi):
+    P = np.polynomial.polynomial
+    out = []
+    for l in range(len(xi)):
+        others = np.delete(xi, l)
+        out.append(P.polyfromroots(others) / np.prod(xi[l] - others))
+    return out
+
+
+def _brute_dealias(m, u, nq):
+    """-sum_q W_q phi(z_q) u.grad u on an nq^3 Gauss-Legendre rule per element, by
+    numpy polynomial evaluation of the nodal fields and of the coordinates."""
+    P = np.polynomial.polynomial
+    xi, _, _ = m.tables()
+    lx = m.lx
+    z, wq = np.polynomial.legendre.leggauss(nq)
+    polys = _lagrange_polys(xi)
+    V = np.stack([P.polyval(z, c) for c in polys], axis=1)               # (nq, lx)
+    dV = np.stack([P.polyval(z, P.polyder(c)) for c in polys], axis=1)   # (nq, lx)
+    X = m.coords()
+    n3 = lx ** 3
+    out = np.zeros((3, m.np))
+    for e in range(m.E):
+        sl = slice(e * n3, (e + 1) * n3)
+        xe = X[:, sl].reshape(3, lx, lx, lx)      # [c][k][j][i]
+        ue = u[:, sl].reshape(3, lx, lx, lx)
+
+        def ev(f, A, B, Cm):  # A along i, B along j, Cm along k
+            return np.einsum("ai,bj,ck,kji->cba", A, B, Cm, f)
+        J = np.zeros((nq, nq, nq, 3, 3))
+        for c in range(3):
+            J[..., c, 0] = ev(xe[c], dV, V, V)
+            J[..., c, 1] = ev(xe[c], V, dV, V)
+            J[..., c, 2] = ev(xe[c], V, V, dV)
+        jac = np.linalg.det(J)
+        rx = np.linalg.inv(J)                       # [.., a, c] = d r_a / d x_c
+        W = jac * np.einsum("k,j,i->kji", wq, wq, wq)
+        uf = np.stack([ev(ue[c], V, V, V) for c in range(3)])
+        for f in range(3):
+            g = np.stack([ev(ue[f], dV, V, V), ev(ue[f], V, dV, V), ev(ue[f], V, V, dV)], axis=-1)
+            dx = np.einsum("...ac,...a->...c", rx, g)
+            T = W * np.einsum("c...,...c->...", uf, dx)
+            # test against every GLL basis function: sum_q phi_l(z_q) T_q
+            o = np.einsum("ai,bj,ck,cba->kji", V, V, V, T)
+            out[f, sl] = -o.ravel()
+    return out
+
+
+def test_dealiased_convection_is_exact_galerkin_on_affine_elements():
+    # affine, non-cubic elements: the integrand has degree 3N-1 per direction,
+    # integrated exactly by the 3/2 rule and by any finer rule
+    N = 4
+    m = OracleMesh((2, 2, 2), N, lo=(-1.0, -2.0, 0.5), hi=(2.0, 1.0, 3.0))
+    u = np.random.default_rng(21).standard_normal((3, m.np))
+    got = m.conv_dealias(u)
+    ref = _brute_dealias(m, u, 2 * (N + 1) + 2)
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_dealiased_convection_matches_same_rule_brute_force_on_curved_elements():
+    N = 3
+    m = OracleMesh((2, 2, 2), N, amp=0.1, phase=inputs.deform_phases())
+    u = np.random.default_rng(22).standard_normal((3, m.np))
+    got = m.conv_dealias(u)
+    ref = _brute_dealias(m, u, lxd(N + 1))
+    assert np.abs(got - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_dealiased_and_collocated_convection_agree_on_smooth_fields():
+    # both converge to the continuous B u.grad u for the smooth TGV field
+    diffs = []
+    for N in (5, 7, 9):
+        m = OracleMesh((4, 4, 4), N)
+        X = m.coords()
+        u = np.stack([np.sin(X[0]) * np.cos(X[1]) * np.cos(X[2]), -np.cos(X[0]) * np.sin(X[1]) * np.cos(X[2]),
+                      0 * X[0]])
+        a, b = m.conv_dealias(u), m.conv(u)
+        diffs.append(np.abs(a - b).max() / np.abs(b).max())
+    assert diffs[1] < diffs[0] / 10 and diffs[2] < diffs[1] / 10
+
+
 # ---------------------------------------------------------------- pressure projection
 def _unique(loc, uid, n):
     u = np.zeros(n)
@@ -448,6 +553,20 @@ def test_tgv2d_extruded_decays_exactly():
     pe = (np.cos(2 * X[0]) + np.cos(2 * X[1])) / 4 * math.exp(-4 * nu * t)
     assert np.abs(f.pressure() - pe).max() < 1e-5
     # KE0 = 1/4 decaying as exp(-2 nu t) squared
+    assert abs(st["ke"] - 0.25 * decay ** 2) < 1e-8
+
+
+def test_tgv2d_extruded_decays_exactly_with_dealiased_convection():
+    nu, dt, nsteps = 0.05, 1e-3, 50
+    m = OracleMesh((4, 4, 2), 7)
+    f = OracleFluid(m, nu, dt, init=INIT_TGV2D, dealias=True)
+    for _ in range(nsteps):
+        st = f.step()
+    X = m.coords()
+    decay = math.exp(-2 * nu * f.time)
+    ue = np.stack([np.sin(X[0]) * np.cos(X[1]) * decay, -np.cos(X[0]) * np.sin(X[1]) * decay])
+    u = f.velocity()
+    assert np.abs(u[:2] - ue).max() < 1e-6 and np.abs(u[2]).max() < 1e-10
     assert abs(st["ke"] - 0.25 * decay ** 2) < 1e-8
 
 
