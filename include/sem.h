@@ -118,6 +118,11 @@ typedef struct {
     int proj_dim;                    /* pressure projection space 0..SEM_MAX_PROJ (0 = off; fluid mode):
                                         GMRES starts from the A-norm best approximation of the new
                                         pressure increment in the span of earlier ones (Sec. 3 uses 20) */
+    int dealias;                     /* 1: the convective term is integrated on ceil(3 lx / 2) Gauss-Legendre
+                                        points per direction (the 3/2 rule; Sec. 3 runs with dealiasing)
+                                        instead of by collocation on the GLL points; fluid mode only, conv
+                                        storage fp64 or fp32.  Adds 9 E ceil(3 lx/2)^3 fp64 metric terms
+                                        (plus an fp32 copy when conv storage is fp32). */
 } sem_flow_desc;
 
 #define SEM_MAX_PROJ 20
@@ -250,7 +255,9 @@ int sem_diagnostics(sem_ctx* ctx, sem_diag* out);
 
 /* Element-local SEM operators on caller arrays (fp64, E*lx^3 each, not
  * assembled): conv -> 3 outputs, opgrad(p) -> 3 outputs, wdiv(3 inputs) ->
- * 1 output; the SEM-block precision policy of the context applies. */
+ * 1 output; the SEM-block precision policy of the context applies.  conv is
+ * -B (u . grad) u (Sec. 2), dealiased when the context's flow has dealias set;
+ * it needs a fluid-mode context. */
 int sem_conv(sem_ctx* ctx, const double* const* u3, double* const* out3);
 int sem_opgrad(sem_ctx* ctx, const double* p, double* const* out3);
 int sem_wdiv(sem_ctx* ctx, const double* const* v3, double* out);
@@ -270,8 +277,9 @@ enum {
     SEM_PROF_DSSUM_PRES = 6,  /* dssum of the Arnoldi operator output */
     SEM_PROF_AX_ANY = 7,      /* every standalone sem_ax call */
     SEM_PROF_AX_RESID = 8,    /* fp64 velocity residual operator, RHS_L - H_L u (3 components) */
-    SEM_PROF_AX_PRESID = 9    /* fp64 Poisson operator of the GMRES cycle-end residuals and the
+    SEM_PROF_AX_PRESID = 9,   /* fp64 Poisson operator of the GMRES cycle-end residuals and the
                                  projection update */
+    SEM_PROF_CONV = 10        /* convective term of the fluid step (collocated or dealiased) */
 };
 int sem_prof_start(int kclass);
 int sem_prof_stop(double* total_ms, int64_t* launches);

@@ -117,6 +117,26 @@ template <typename A, int NV> __device__ __forceinline__ void block_sum(A (&v)[N
     __syncthreads();
 }
 
+// Coordinates of local node (i,j,k) of element e: reference position in the
+// box plus the optional smooth perturbation amp*h_c*prod_q sin(pi X_q/h_q + phi).
+__device__ __forceinline__ void node_xyz(const MeshParams& mp, const double* xi, int e, int i, int j, int k, double out[3])
+{
+    const int ex = e % mp.nel[0];
+    const int ey = (e / mp.nel[0]) % mp.nel[1];
+    const int ez = e / (mp.nel[0] * mp.nel[1]);
+    double X[3] = {(ex + 0.5 * (1.0 + xi[i])) * mp.h[0], (ey + 0.5 * (1.0 + xi[j])) * mp.h[1],
+                   (ez + 0.5 * (1.0 + xi[k])) * mp.h[2]};
+    const double pi = 3.14159265358979323846;
+    for (int c = 0; c < 3; ++c) {
+        double d = 0.0;
+        if (mp.amp != 0.0) {
+            d = mp.amp * mp.h[c];
+            for (int q = 0; q < 3; ++q) d *= sin(pi * X[q] / mp.h[q] + mp.phase[3 * c + q]);
+        }
+        out[c] = mp.lo[c] + X[c] + d;
+    }
+}
+
 __device__ __forceinline__ bool gate_ok(const ReqDesc* R, int gate)
 {
     return gate < 0 || gp(R->I)[gate] != 0;

@@ -156,6 +156,15 @@ struct Resolved {
     int kind16;             // P16 or PBF
 };
 
+// member-wise (the struct has padding, so a byte comparison is not meaningful)
+bool same_policy(const Resolved& a, const Resolved& b)
+{
+    return a.tv == b.tv && a.tva == b.tva && a.axv_g == b.axv_g && a.axv_c == b.axv_c && a.tpd == b.tpd &&
+           a.tb == b.tb && a.axp_g == b.axp_g && a.axp_c == b.axp_c && a.opg_m == b.opg_m && a.opg_c == b.opg_c &&
+           a.conv_m == b.conv_m && a.conv_c == b.conv_c && a.div_m == b.div_m && a.div_c == b.div_c &&
+           a.need32 == b.need32 && a.need16 == b.need16 && a.kind16 == b.kind16;
+}
+
 // (vector, geometry, arithmetic) instantiations of the Helmholtz kernel
 bool ax_supported(int u, int g, int c)
 {
@@ -178,6 +187,53 @@ bool op_supported(int m, int c)
 struct Tuples {
     std::vector<int> idx2, idx4, idx8;
 };
+
+// Gauss-Legendre points of the dealiasing grid: the n zeros of P_n by Newton
+// from cos(pi (4i+3)/(4n+2)), weights 2 / ((1 - z^2) P_n'(z)^2); the GLL
+// Lagrange basis at those points, I[q][l] = prod_{m != l} (z_q - x_m)/(x_l - x_m),
+// and ID = I D (the derivative polynomial D u is interpolated exactly).
+static void dealias_tables(int lx, const std::vector<double>& x, const std::vector<double>& D, std::vector<double>& I,
+                    std::vector<double>& ID, std::vector<double>& wz)
+{
+    const int n = (3 * lx + 1) / 2;
+    const double pi = 3.14159265358979323846;
+    std::vector<double> z(n);
+    wz.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double t = -std::cos(pi * (4.0 * i + 3.0) / (4.0 * n + 2.0));
+        double a, b, c, da, dc;
+        for (int it = 0; it < 100; ++it) {
+            legendre_trio(n - 1, t, a, b, c, da, dc);  // c = P_n(t), dc = P_n'(t)
+            const double dt = c / dc;
+            t -= dt;
+            if (std::fabs(dt) <= 1e-16) break;
+        }
+        legendre_trio(n - 1, t, a, b, c, da, dc);
+        z[i] = t;
+        wz[i] = 2.0 / ((1.0 - t * t) * dc * dc);
+    }
+    for (int i = 0; i < n / 2; ++i) {  // exact symmetry of nodes and weights
+        const double s = 0.5 * (z[n - 1 - i] - z[i]), w = 0.5 * (wz[i] + wz[n - 1 - i]);
+        z[i] = -s; z[n - 1 - i] = s;
+        wz[i] = w; wz[n - 1 - i] = w;
+    }
+    if (n % 2) z[n / 2] = 0.0;
+    I.assign((size_t)n * lx, 0.0);
+    ID.assign((size_t)n * lx, 0.0);
+    for (int q = 0; q < n; ++q)
+        for (int l = 0; l < lx; ++l) {
+            double v = 1.0;
+            for (int m = 0; m < lx; ++m)
+                if (m != l) v *= (z[q] - x[m]) / (x[l] - x[m]);
+            I[(size_t)q * lx + l] = v;
+        }
+    for (int q = 0; q < n; ++q)
+        for (int l = 0; l < lx; ++l) {
+            double s = 0.0;
+            for (int m = 0; m < lx; ++m) s += I[(size_t)q * lx + m] * D[(size_t)m * lx + l];
+            ID[(size_t)q * lx + l] = s;
+        }
+}
 
 // ------------------------------------------------------------------ context
 struct sem_ctx {
@@ -433,6 +489,12 @@ void build_layout(sem_ctx* c)
             field(F_PRX, (size_t)c->flow.proj_dim * psize(r.tb) * (size_t)np);
             field(F_PRXB, d);
         }
+        if (c->flow.dealias) {
+            const size_t lxd = (size_t)(3 * c->lx + 1) / 2;
+            const size_t nf = 9 * (size_t)c->E * lxd * lxd * lxd;
+            field(F_MFD64, 8 * nf);
+            if (r.conv_m == P32) field(F_MFD32, 4 * nf);
+        }
     }
     c->bytes = off;
 }
@@ -512,6 +574,14 @@ struct ProfScope {
 };
 
 // ------------------------------------------------------------------ launch helpers
+// B N(u) of the current velocity into F_BN: dealiased (3/2 rule) or collocated
+void convection(const Batch& b, const sem_ctx* c, hipStream_t s)
+{
+    ProfScope ps(SEM_PROF_CONV, s);
+    if (c->flow.dealias) launch_conv_dealias(b, c->lx, c->rs.conv_m, c->rs.conv_c, s);
+    else launch_conv(b, c->lx, c->rs.conv_m, c->rs.conv_c, s);
+}
+
 void ax(const Batch& b, int lx, int src, int dst, int ncomp, int hsel, double h1, double h2, int precond, int pdot,
         int gate, int tu, int tg, int tc, hipStream_t s)
 {
@@ -821,12 +891,17 @@ int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_pr
             return fail(SEM_EINVAL, "bad velocity tolerance/limits");
         if (flow->init < SEM_INIT_ZERO || flow->init > SEM_INIT_TGV2D) return fail(SEM_EINVAL, "bad init");
         if (flow->proj_dim < 0 || flow->proj_dim > SEM_MAX_PROJ) return fail(SEM_EINVAL, "proj_dim must be 0..20");
+        if (flow->dealias != 0 && flow->dealias != 1) return fail(SEM_EINVAL, "dealias must be 0 or 1");
     } else if (flow->proj_dim != 0) {
         return fail(SEM_EINVAL, "proj_dim applies to the fluid mode only");
+    } else if (flow->dealias != 0) {
+        return fail(SEM_EINVAL, "dealias applies to the fluid mode only");
     }
     Resolved rs;
     int rc = resolve_policy(prec, rs);
     if (rc) return rc;
+    if (flow->mode == SEM_MODE_FLUID && flow->dealias && rs.conv_m != P64 && rs.conv_m != P32)
+        return fail(SEM_EINVAL, "dealiased convection needs conv storage fp64 or fp32");
 
     sem_ctx* c = new sem_ctx();
     c->mesh = *mesh;
@@ -852,11 +927,18 @@ int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_pr
     gll_tables(c->N, x, w, D);
     // fp64 table: D (lx*lx), GLL weights, GLL nodes, then 1/multiplicity of
     // every local point of a conforming box mesh (lx^3; a face coordinate
-    // doubles the number of copies); fp32 table: D, weights, nodes
+    // doubles the number of copies), then the dealiasing tables I, ID (lxd*lx
+    // each) and the Gauss-Legendre weights (lxd); fp32 table: D, weights,
+    // nodes, I, ID, Gauss-Legendre weights
+    std::vector<double> dI, dID, dwz;
+    dealias_tables((int)lx, x, D, dI, dID, dwz);
+    std::vector<double> dl(dI);
+    dl.insert(dl.end(), dID.begin(), dID.end());
+    dl.insert(dl.end(), dwz.begin(), dwz.end());
     c->D64tab.resize(lx * lx + 2 * lx + lx * lx * lx);
-    c->D32tab.resize(lx * lx + 2 * lx);
     for (int q = 0; q < lx * lx; ++q) c->D64tab[q] = D[q];
     for (int q = 0; q < lx; ++q) { c->D64tab[lx * lx + q] = w[q]; c->D64tab[lx * lx + lx + q] = x[q]; }
+    c->D32tab.resize(lx * lx + 2 * lx);
     for (size_t q = 0; q < c->D32tab.size(); ++q) c->D32tab[q] = (float)c->D64tab[q];
     for (int k = 0; k < lx; ++k)
         for (int j = 0; j < lx; ++j)
@@ -867,6 +949,8 @@ int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_pr
                 if (k == 0 || k == lx - 1) r *= 0.5;
                 c->D64tab[lx * lx + 2 * lx + i + lx * (j + lx * k)] = r;
             }
+    c->D64tab.insert(c->D64tab.end(), dl.begin(), dl.end());
+    for (double v : dl) c->D32tab.push_back((float)v);
     build_tuples(c);
     build_layout(c);
     MeshParams& mp = c->mp;
@@ -967,6 +1051,7 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     launch_dssum(b, F_IBSUM64, 1, P64, -1, nullptr, s);
     launch_geo_post(b, s);
     if (c->rs.need32 || c->rs.need16) launch_geo_cast(b, c->lx, c->rs.need32 ? 1 : 0, c->rs.need16 ? c->rs.kind16 : 0, s);
+    if (c->flow.mode == SEM_MODE_FLUID && c->flow.dealias) launch_dealias_geom(b, c->lx, c->mp, c->rs.conv_m == P32, s);
     // domain volume (sum of B)
     vec(b, V_SUM_MASS, 1, P64, -1, s, -1, -1, P64, P64, FIN_VOL);
     int rc = check_hip_last();
@@ -974,7 +1059,7 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     if (c->flow.mode == SEM_MODE_FLUID) {
         launch_init_fields(b, c->lx, c->flow.init, c->mp, s);
         // history of the convective term starts at the initial field
-        launch_conv(b, c->lx, c->rs.conv_m, c->rs.conv_c, s);
+        convection(b, c, s);
         vec(b, V_COPY, 3, P64, -1, s, F_BN, F_BNL1);
         vec(b, V_COPY, 3, P64, -1, s, F_BN, F_BNL2);
         rc = check_hip_last();
@@ -1078,13 +1163,15 @@ static int check_batch(sem_ctx* const* ctxs, int n, int min_mode)
         if (rc) return rc;
         if (ctxs[i]->flow.mode < min_mode) return fail(SEM_EINVAL, "context mode does not hold the needed workspaces");
         if (ctxs[i]->lx != ctxs[0]->lx) return fail(SEM_EINVAL, "batched contexts must share the order");
-        if (memcmp(&ctxs[i]->rs, &ctxs[0]->rs, sizeof(Resolved)) != 0)
+        if (!same_policy(ctxs[i]->rs, ctxs[0]->rs))
             return fail(SEM_EINVAL, "batched contexts must share the precision policy");
         if (ctxs[i]->stream != ctxs[0]->stream) return fail(SEM_EINVAL, "batched contexts must share the stream");
         if (ctxs[i]->flow.gmres_restart != ctxs[0]->flow.gmres_restart)
             return fail(SEM_EINVAL, "batched contexts must share the GMRES restart length");
         if (ctxs[i]->flow.proj_dim != ctxs[0]->flow.proj_dim)
             return fail(SEM_EINVAL, "batched contexts must share the projection dimension");
+        if (ctxs[i]->flow.dealias != ctxs[0]->flow.dealias)
+            return fail(SEM_EINVAL, "batched contexts must share the dealiasing setting");
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(SEM_EINVAL, "a context appears twice in a batch");
     }
@@ -1118,7 +1205,7 @@ int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stat
         fin(b, FIN_STEP_BEGIN, s);
         vec(b, V_IDV, 1, P64, I_IDVSTALE, s);
         // (i) explicit terms: convection, old pressure gradient, BDF/EXT history
-        launch_conv(b, lx, r.conv_m, r.conv_c, s);
+        convection(b, c0, s);
         launch_opgrad(b, lx, r.opg_m, r.opg_c, F_P, F_GP, s);
         vec(b, V_RHS, 3, P64, -1, s);  // local rhs: assembled together with the residual
         // (ii) velocity Helmholtz solves -> u*
@@ -1270,7 +1357,7 @@ int sem_poisson_finish(sem_ctx* c, void* sol, sem_solve_stats* st)
 
 int sem_prof_start(int kclass)
 {
-    if (kclass < SEM_PROF_AX_VEL || kclass > SEM_PROF_AX_PRESID) return fail(SEM_EINVAL, "unknown profiling class");
+    if (kclass < SEM_PROF_AX_VEL || kclass > SEM_PROF_CONV) return fail(SEM_EINVAL, "unknown profiling class");
     g_prof.kclass = kclass;
     g_prof.used = 0;
     return 0;
@@ -1477,7 +1564,7 @@ int sem_conv(sem_ctx* c, const double* const* u3, double* const* out3)
     }
     sem_ctx* one[1] = {c};
     Batch b = make_batch(one, 1);
-    launch_conv(b, c->lx, c->rs.conv_m, c->rs.conv_c, c->stream);
+    convection(b, c, c->stream);
     for (int q = 0; q < 3; ++q) {
         HIPCHK(hipMemcpyAsync(out3[q], bnp[q], nb, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(sv[q], c->hdesc.f[F_W64 + q], nb, hipMemcpyDeviceToDevice, c->stream));

@@ -73,6 +73,9 @@ enum FieldId : int {
     // pressure projection (fluid mode with proj_dim > 0)
     F_PRX,                      // proj_dim stored vectors, stride np, basis storage precision, unnormalised
     F_PRXB,                     // the projected guess of the current step (fp64)
+    // dealiased convection (flow.dealias): metric terms at the LXD^3 Gauss-Legendre points
+    F_MFD64,                    // [E][9][lxd3] W dr_a/dx_c, index a*3+c (W = jac * GL weights)
+    F_MFD32,                    // fp32 copy (conv storage fp32)
     NFIELD
 };
 
@@ -167,8 +170,9 @@ struct ReqDesc {
     double* S;                  // scalars
     int* I;                     // integer state
     double* part;               // reduction partials [NRED][pstride]
-    const double* D64;          // D[i*lx+l] (lx*lx), then w[lx], then xi[lx]
-    const float* D32;           // same layout in fp32
+    const double* D64;          // D[i*lx+l] (lx*lx), w[lx], xi[lx], 1/mult[lx^3], then the dealiasing
+                                // tables I[lxd*lx], ID[lxd*lx] (= I D), wz[lxd]
+    const float* D32;           // D, w, xi, I, ID, wz in fp32
     void* f[NFIELD];
 };
 
@@ -253,6 +257,8 @@ void launch_node_field(const Batch& b, int lx, const MeshParams& mp, int what, d
 
 // SEM operators (output fp64)
 void launch_conv(const Batch& b, int lx, int tm, int tc, hipStream_t s);
+void launch_dealias_geom(const Batch& b, int lx, const MeshParams& mp, int want32, hipStream_t s);
+void launch_conv_dealias(const Batch& b, int lx, int tm, int tc, hipStream_t s);
 void launch_opgrad(const Batch& b, int lx, int tm, int tc, int src, int dst, hipStream_t s);
 void launch_wdiv(const Batch& b, int lx, int tm, int tc, int src, int dst, hipStream_t s);
 void launch_diagnostics(const Batch& b, int lx, hipStream_t s);

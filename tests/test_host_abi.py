@@ -92,6 +92,25 @@ def test_flow_validation():
             sem.Context(md, sem.flow_desc(**kw), sem.tier("fp64"), bind=False)
 
 
+def test_dealias_validation_and_workspace():
+    md = sem.mesh_desc((2, 2, 2), 4)
+    for kw in (dict(dealias=2), dict(dealias=-1), dict(mode=sem.MODE_POISSON, dealias=1),
+               dict(mode=sem.MODE_OPERATOR, dealias=1)):
+        with pytest.raises(sem.SemError):
+            sem.Context(md, sem.flow_desc(**kw), sem.tier("fp64"), bind=False)
+    # the fine-grid metric terms exist in fp64 or fp32 only
+    p16 = sem.precision(sem.FP32, kernels={sem.K_CONV: (sem.FP32, sem.FP32, sem.FP16)})
+    sem.Context(md, sem.flow_desc(), p16, bind=False)
+    with pytest.raises(sem.SemError):
+        sem.Context(md, sem.flow_desc(dealias=1), p16, bind=False)
+    # workspace grows by the 9 metric terms per fine point (fp64, plus fp32 under fp32 conv storage)
+    E, nd = 8, (3 * 5 + 1) // 2
+    for t, per in (("fp64", 8), ("fp32b", 12)):
+        a = sem.Context(md, sem.flow_desc(), sem.tier(t), bind=False)
+        b = sem.Context(md, sem.flow_desc(dealias=1), sem.tier(t), bind=False)
+        assert 0 <= (b.bytes - a.bytes) - 9 * E * nd ** 3 * per < 512
+
+
 def test_unbound_context_calls_fail_cleanly():
     c = sem.Context(sem.mesh_desc((2, 2, 2), 3), sem.flow_desc(), sem.tier("fp64"), bind=False)
     L = sem.load()
