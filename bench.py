@@ -44,9 +44,10 @@ def gmres_j_sequence(iters, m):
     return out
 
 
-def run_tier(sem, torch, tier, nel, N, nu, dt, warmup, steps, prof_class=None, vtol=1e-6, ptol=1e-4, proj=0):
+def run_tier(sem, torch, tier, nel, N, nu, dt, warmup, steps, prof_class=None, vtol=1e-6, ptol=1e-4, proj=0,
+             dealias=0):
     ctx = sem.Context(sem.mesh_desc(nel, N), sem.flow_desc(nu=nu, dt=dt, restart=30, vel_tol=vtol, pres_tol=ptol,
-                                                           proj=proj),
+                                                           proj=proj, dealias=dealias),
                       sem.tier(tier))
     torch.cuda.synchronize()
     series = []
@@ -152,7 +153,30 @@ def stored_traffic(kind, tier, workload):
     return d["hbm_bytes_per_launch"]
 
 
-def roofline(kind, tier, prof, steps, npts, workload):
+def conv_units(N, dealias, tier):
+    """Algorithmic HBM bytes and flops of the convective term per element:
+    u (3 fp64 fields) in, B N(u) (3 fp64 fields) out, 9 metric terms per
+    point of the grid it integrates on (GLL points, or the lxd^3 Gauss-Legendre
+    points when dealiased) in the conv storage precision.  Flops of the
+    dealiased form: 12 interpolations to the fine grid (u and its three
+    reference derivatives per component, 2 lx flops per output point of each
+    of the three one-dimensional stages), 3 transposed ones back, and the
+    point-wise contravariant products."""
+    lx = N + 1
+    tm = 8 if tier == "fp64" else 4
+    if not dealias:
+        byt = lx ** 3 * (3 * 8 + 9 * tm + 3 * 8)
+        fl = lx ** 3 * 3 * (3 * 2 * lx + 3 * 6 + 2)
+        return byt, fl
+    nd = (3 * lx + 1) // 2
+    byt = lx ** 3 * 6 * 8 + 9 * tm * nd ** 3
+    interp = 2 * lx * (lx * lx * nd + lx * nd * nd + nd ** 3)
+    back = 2 * nd * (lx * nd * nd + lx * lx * nd + lx ** 3)
+    point = nd ** 3 * (3 * 3 * 2 + 3 * 3 * 2)
+    return byt, 12 * interp + 3 * back + point
+
+
+def roofline(kind, tier, prof, steps, npts, workload, N=7, dealias=0):
     """Achieved HBM bandwidth of one kernel class over the timed region:
     algorithmic bytes of its launches / summed HIP-event kernel time of all
     its launches (gated no-op launches after convergence included)."""
@@ -189,6 +213,22 @@ def roofline(kind, tier, prof, steps, npts, workload):
                 alg += fbytes(npts, J, bv)
                 active += 1
         name = (kname % ("float" if bv == 4 else "double")) + " -- " + what
+    elif kind == "conv":
+        lx = N + 1
+        E = npts // lx ** 3
+        byt, fl = conv_units(N, dealias, tier)
+        tot_ms, nlaunch = prof
+        alg = nlaunch * E * byt
+        achieved = alg / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+        flops = nlaunch * E * fl / (tot_ms * 1e-3) / 1e12 if tot_ms > 0 else 0.0
+        peak_fl = 78.6 if tier == "fp64" else 157.3
+        name = ("conv_dealias_kernel<%d, %s>" % (lx, "double, double" if tier == "fp64" else "float, float")
+                if dealias else "conv_kernel<%d, ...>" % lx) + " -- convective term B N(u)"
+        return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launches": nlaunch, "active_units": nlaunch,
+                "kernel_ms_total": tot_ms, "avg_launch_ms": tot_ms / max(nlaunch, 1),
+                "alg_bytes_per_launch": E * byt, "alg_bytes_total": alg,
+                "vector_tflops": flops, "vector_peak_tflops": peak_fl, "vector_frac": flops / peak_fl}
     elif kind == "ax_vel":
         active = sum(sum(s["vit"]) for s in steps)  # component launches that did work
         alg = active * npts * _bytes_per_point(kind, tier)
@@ -241,8 +281,11 @@ def main():
     ap.add_argument("--vtol", type=float, default=1e-6)
     ap.add_argument("--ptol", type=float, default=1e-4)
     ap.add_argument("--proj", type=int, default=0, help="pressure projection space (0 = off; the paper uses 20)")
+    ap.add_argument("--dealias", type=int, default=0, choices=[0, 1],
+                    help="1: convection on the 3/2-rule Gauss-Legendre grid (the paper's runs are dealiased)")
     ap.add_argument("--prof", default="ax_resid",
-                    choices=["ax_resid", "ax_presid", "ax_vel", "ax_pres", "gm_upd_dots", "gm_upd_norm", "none"],
+                    choices=["ax_resid", "ax_presid", "ax_vel", "ax_pres", "gm_upd_dots", "gm_upd_norm", "conv",
+                             "none"],
                     help="kernel class timed with HIP events for the roofline record (default: the dominant kernel)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with plain 1 GiB device copies (calibration of the PMC byte counters)")
@@ -276,22 +319,26 @@ def main():
     prof_class = {"ax_resid": sem.PROF_AX_RESID, "ax_presid": sem.PROF_AX_PRESID, "ax_vel": sem.PROF_AX_VEL,
                   "ax_pres": sem.PROF_AX_PRES,
                   "gm_upd_dots": sem.PROF_GM_UPD_DOTS,
-                  "gm_upd_norm": sem.PROF_GM_UPD_NORM, "none": None}[args.prof]
+                  "gm_upd_norm": sem.PROF_GM_UPD_NORM, "conv": sem.PROF_CONV, "none": None}[args.prof]
     ctx, t_mx, st_mx, ser_mx, prof = run_tier(sem, torch, args.tier, nel, N, nu, dt, args.warmup, args.steps, prof_class,
-                                              args.vtol, args.ptol, args.proj)
+                                              args.vtol, args.ptol, args.proj, args.dealias)
     steps_s = args.steps / t_mx
     out = {"metric": METRIC, "value": steps_s, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * t_mx / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if args.tier != "fp64" else "f64",
            "data": "synthetic",
            "config": {"workload": "TGV Re=%g, %d^3 elements, N=%d (%d local pts), dt=%g, tier %s (fp64 state, "
-                                  "GMRES orthogonalisation and residual checks)" % (args.re, args.nel, N, npts, dt, args.tier),
+                                  "GMRES orthogonalisation and residual checks)%s" % (args.re, args.nel, N, npts, dt,
+                                                                                     args.tier,
+                                                                                     ", dealiased convection"
+                                                                                     if args.dealias else ""),
                       "global_batch": 1, "seq_len": npts, "parallelism": "single-gpu"}}
     out["iters"] = {"vel": [s["vit"] for s in st_mx], "pres": [s["pit"] for s in st_mx]}
 
     if prof is not None and not (args.proj and args.prof == "ax_presid"):
         # (the launch accounting of ax_presid covers the solver without projection)
-        out["roofline"] = roofline(args.prof, args.tier, prof, st_mx, npts, out["config"]["workload"])
+        out["roofline"] = roofline(args.prof, args.tier, prof, st_mx, npts, out["config"]["workload"], N,
+                                   args.dealias)
 
     if not args.no_ax:
         g32, ms32 = ax_rate(sem, torch, ctx, torch.float32)
@@ -300,7 +347,7 @@ def main():
                            "note": "Poisson operator (u, w fp32, 6 G fp32: 32 B/point), HIP events, 20 launches"}
     if not args.no_fp64:
         ctx64, t64, st64, ser64, _ = run_tier(sem, torch, "fp64", nel, N, nu, dt, args.warmup, args.steps, None,
-                                              args.vtol, args.ptol, args.proj)
+                                              args.vtol, args.ptol, args.proj, args.dealias)
         out["fp64_steps_per_s"] = args.steps / t64
         out["speedup_vs_fp64"] = steps_s / (args.steps / t64)
         ke_mx = [r[1] for r in ser_mx]

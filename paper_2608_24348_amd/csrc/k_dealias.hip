@@ -269,6 +269,537 @@ __global__ void __launch_bounds__(Dl<LX>::NT) conv_dealias_kernel(Batch bt)
     }
 }
 
+// ------------------------------------------------------------------
+// Matrix-core form (LXD <= 16): every one-dimensional contraction is a small
+// dense product with the 1D matrix (I, ID or I^T) as one operand, done with
+// the 16x16x4 MFMA of the arithmetic type.  The matrix operands sit in
+// registers for the whole kernel (for these shapes the lane layout of the
+// A and B operands coincide: lane l holds row/column l % 16, k = l / 16), the
+// tensor operand is read from LDS once per stage, and the fine-grid products
+// stay in the accumulators, so LDS traffic drops from two reads per FMA to
+// about one read and one write per staged value.  Four waves share an
+// element; output tiles go round-robin over the waves.
+template <typename C> struct Mma;
+template <> struct Mma<float> {
+    typedef float V4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ V4 mma(float a, float b, V4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    // accumulator entry r of a lane in row group g holds output row:
+    static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
+};
+template <> struct Mma<double> {
+    typedef double V4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ V4 mma(double a, double b, V4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
+};
+
+template <int LX> struct Dm {
+    static constexpr int LXD = (3 * LX + 1) / 2;
+    static constexpr int NL = LX * LX, NN = LXD * LXD, N3 = LX * LX * LX, ND3 = LXD * LXD * LXD;
+    static constexpr int KSX = (LX + 3) / 4, KSD = (LXD + 3) / 4;   // k-steps over coarse / fine indices
+    static constexpr int NLT = (NL + 15) / 16, NNT = (NN + 15) / 16;  // tiles over lines / fine planes
+    static constexpr int NW = 4, NT = 64 * NW;
+    static constexpr int JW = (NNT + NW - 1) / NW;                  // fine-plane tiles per wave
+    static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+    static constexpr int R1 = cmax(2 * NL * LXD, ND3);             // Y1 (P, Q) / T / Z2
+    static constexpr int R2 = 3 * LX * NN;                          // Y2 (3 kinds) / Z1
+};
+
+template <int LX, typename TM, typename C>
+__global__ void __launch_bounds__(Dm<LX>::NT) conv_dealias_mfma_kernel(Batch bt)
+{
+    using D = Dm<LX>;
+    using M = Mma<C>;
+    typedef typename M::V4 V4;
+    constexpr int LXD = D::LXD, NL = D::NL, NN = D::NN, N3 = D::N3, ND3 = D::ND3;
+    constexpr int KSX = D::KSX, KSD = D::KSD, NLT = D::NLT, NNT = D::NNT, JW = D::JW;
+    static_assert(LXD <= 16, "one 16-row tile over the fine index");
+    __shared__ C sU[3 * N3];
+    __shared__ C R1[D::R1];
+    __shared__ C R2[D::R2];
+    const int gb = blockIdx.x;
+    const int ri = find_req(bt.eb, bt.n, gb);
+    const ReqDesc* R = bt.r[ri];
+    const int blk = gb - bt.eb[ri];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, m = lane & 15, g = lane >> 4;
+    // 1D matrices in registers: fI/fD[s] = I/ID[m][4s+g] (forward stages), bI[s] = I[4s+g][m] (transposed stages)
+    C fI[KSX], fD[KSX], bI[KSD];
+    {
+        const int o = sizeof(C) == 8 ? dl_off64<LX>() : dl_off32<LX>();
+#pragma unroll
+        for (int s = 0; s < KSX; ++s) {
+            const int k = 4 * s + g;
+            const bool ok = m < LXD && k < LX;
+            if constexpr (sizeof(C) == 8) {
+                fI[s] = ok ? gp(R->D64)[o + m * LX + k] : 0.0;
+                fD[s] = ok ? gp(R->D64)[o + LXD * LX + m * LX + k] : 0.0;
+            } else {
+                fI[s] = ok ? gp(R->D32)[o + m * LX + k] : 0.0f;
+                fD[s] = ok ? gp(R->D32)[o + LXD * LX + m * LX + k] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < KSD; ++s) {
+            const int k = 4 * s + g;
+            const bool ok = k < LXD && m < LX;
+            if constexpr (sizeof(C) == 8) bI[s] = ok ? gp(R->D64)[o + k * LX + m] : 0.0;
+            else bI[s] = ok ? gp(R->D32)[o + k * LX + m] : 0.0f;
+        }
+    }
+    const SEM_GLOBAL TM* MF = gfield<TM>(R, mfd_field<TM>());
+    const SEM_GLOBAL double* U[3];
+    SEM_GLOBAL double* O[3];
+    for (int c = 0; c < 3; ++c) { U[c] = gfield<double>(R, F_U + c); O[c] = gfieldw<double>(R, F_BN + c); }
+    C* sY1 = R1;            // [2][NL][LXD]: P = I u, Q = ID u along the first index
+    C* sT = R1;             // [LXD][NN]: weighted integrand at the fine points
+    C* sZ2 = R1;            // [NL][LXD]
+    C* sY2 = R2;            // [3][LX][NN]
+    C* sZ1 = R2;            // [LX][NN]
+
+    for (int el = 0; el < R->epb; ++el) {
+        const int e = blk * R->epb + el;
+        if (e >= R->E) break;
+        const long long eb = (long long)e * N3;
+        for (int p = t; p < 3 * N3; p += D::NT) {
+            const int c = p / N3;
+            sU[p] = (C)U[c][eb + (p - c * N3)];
+        }
+        block_sync_lds();
+        const SEM_GLOBAL TM* me = MF + (long long)e * 9 * ND3;
+
+        // ---- contravariant velocity V_a = sum_c u_c (W dr_a/dx_c) at this wave's fine points
+        V4 V[3][JW];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int j = 0; j < JW; ++j) V[a][j] = V4{0, 0, 0, 0};
+        for (int c = 0; c < 3; ++c) {
+            // first index: Y1[L][i'] = sum_a u[L][a] I[i'][a]
+            for (int lt = w; lt < NLT; lt += 4) {
+                V4 acc = {0, 0, 0, 0};
+                const int L = 16 * lt + m;
+#pragma unroll
+                for (int s = 0; s < KSX; ++s) {
+                    const int a = 4 * s + g;
+                    const C av = (L < NL && a < LX) ? sU[c * N3 + L * LX + a] : (C)0;
+                    acc = M::mma(av, fI[s], acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int Lo = 16 * lt + M::row(g, r);
+                    if (Lo < NL && m < LXD) sY1[Lo * LXD + m] = acc[r];
+                }
+            }
+            block_sync_lds();
+            // second index, per third-index plane cc: Y2[cc][j'][i'] = sum_b I[j'][b] Y1[cc LX + b][i']
+            for (int cc = w; cc < LX; cc += 4) {
+                V4 acc = {0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < KSX; ++s) {
+                    const int b = 4 * s + g;
+                    const C bv = (b < LX && m < LXD) ? sY1[(cc * LX + b) * LXD + m] : (C)0;
+                    acc = M::mma(fI[s], bv, acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int jo = M::row(g, r);
+                    if (jo < LXD && m < LXD) sY2[cc * NN + jo * LXD + m] = acc[r];
+                }
+            }
+            block_sync_lds();
+            // third index: u_c(k', n) = sum_cc I[k'][cc] Y2[cc][n], straight into V
+#pragma unroll
+            for (int j = 0; j < JW; ++j) {
+                const int tn = w + 4 * j;
+                if (tn < NNT) {
+                    const int n = 16 * tn + m;
+                    V4 acc = {0, 0, 0, 0};
+#pragma unroll
+                    for (int s = 0; s < KSX; ++s) {
+                        const int cc = 4 * s + g;
+                        const C bv = (cc < LX && n < NN) ? sY2[cc * NN + n] : (C)0;
+                        acc = M::mma(fI[s], bv, acc);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int kk = M::row(g, r);
+                        if (n < NN && kk < LXD) {
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) V[a][j][r] += acc[r] * (C)me[(long long)(a * 3 + c) * ND3 + kk * NN + n];
+                        }
+                    }
+                }
+            }
+        }
+
+        // ---- per component: T = sum_a V_a d_a u_f at the fine points, tested back on the GLL points
+        for (int f = 0; f < 3; ++f) {
+            block_sync_lds();
+            // first index: P = I u_f, Q = ID u_f
+            for (int job = w; job < 2 * NLT; job += 4) {
+                const int which = job / NLT, lt = job - which * NLT;
+                const int L = 16 * lt + m;
+                V4 acc = {0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < KSX; ++s) {
+                    const int a = 4 * s + g;
+                    const C av = (L < NL && a < LX) ? sU[f * N3 + L * LX + a] : (C)0;
+                    acc = M::mma(av, which ? fD[s] : fI[s], acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int Lo = 16 * lt + M::row(g, r);
+                    if (Lo < NL && m < LXD) sY1[which * NL * LXD + Lo * LXD + m] = acc[r];
+                }
+            }
+            block_sync_lds();
+            // second index: kind 0: I P (for d/dt), 1: ID P (d/ds), 2: I Q (d/dr)
+            for (int job = w; job < 3 * LX; job += 4) {
+                const int kind = job / LX, cc = job - kind * LX;
+                const C* src = sY1 + (kind == 2 ? NL * LXD : 0);
+                V4 acc = {0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < KSX; ++s) {
+                    const int b = 4 * s + g;
+                    const C bv = (b < LX && m < LXD) ? src[(cc * LX + b) * LXD + m] : (C)0;
+                    acc = M::mma(kind == 1 ? fD[s] : fI[s], bv, acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int jo = M::row(g, r);
+                    if (jo < LXD && m < LXD) sY2[kind * LX * NN + cc * NN + jo * LXD + m] = acc[r];
+                }
+            }
+            block_sync_lds();
+            // third index: d/dt = ID (I P), d/ds = I (ID P), d/dr = I (I Q); T accumulated in registers
+#pragma unroll
+            for (int j = 0; j < JW; ++j) {
+                const int tn = w + 4 * j;
+                if (tn < NNT) {
+                    const int n = 16 * tn + m;
+                    V4 T = {0, 0, 0, 0};
+#pragma unroll
+                    for (int kind = 0; kind < 3; ++kind) {
+                        V4 acc = {0, 0, 0, 0};
+#pragma unroll
+                        for (int s = 0; s < KSX; ++s) {
+                            const int cc = 4 * s + g;
+                            const C bv = (cc < LX && n < NN) ? sY2[kind * LX * NN + cc * NN + n] : (C)0;
+                            acc = M::mma(kind == 0 ? fD[s] : fI[s], bv, acc);
+                        }
+                        const int a = 2 - kind;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) T[r] += V[a][j][r] * acc[r];
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int kk = M::row(g, r);
+                        if (kk < LXD && n < NN) sT[kk * NN + n] = T[r];
+                    }
+                }
+            }
+            block_sync_lds();
+            // transposed third index: Z1[c][n] = sum_k' I[k'][c] T[k'][n]
+            for (int tn = w; tn < NNT; tn += 4) {
+                const int n = 16 * tn + m;
+                V4 acc = {0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < KSD; ++s) {
+                    const int kk = 4 * s + g;
+                    const C bv = (kk < LXD && n < NN) ? sT[kk * NN + n] : (C)0;
+                    acc = M::mma(bI[s], bv, acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int c = M::row(g, r);
+                    if (c < LX && n < NN) sZ1[c * NN + n] = acc[r];
+                }
+            }
+            block_sync_lds();
+            // transposed second index, per plane c: Z2[c][b][i'] = sum_j' I[j'][b] Z1[c][j'][i']
+            for (int c = w; c < LX; c += 4) {
+                V4 acc = {0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < KSD; ++s) {
+                    const int jj = 4 * s + g;
+                    const C bv = (jj < LXD && m < LXD) ? sZ1[c * NN + jj * LXD + m] : (C)0;
+                    acc = M::mma(bI[s], bv, acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int b = M::row(g, r);
+                    if (b < LX && m < LXD) sZ2[(c * LX + b) * LXD + m] = acc[r];
+                }
+            }
+            block_sync_lds();
+            // transposed first index: BN_f[L][a] = -sum_i' Z2[L][i'] I[i'][a]
+            for (int lt = w; lt < NLT; lt += 4) {
+                const int L = 16 * lt + m;
+                V4 acc = {0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < KSD; ++s) {
+                    const int ii = 4 * s + g;
+                    const C av = (L < NL && ii < LXD) ? sZ2[L * LXD + ii] : (C)0;
+                    acc = M::mma(av, bI[s], acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int Lo = 16 * lt + M::row(g, r);
+                    if (Lo < NL && m < LX) O[f][eb + Lo * LX + m] = -(double)acc[r];
+                }
+            }
+        }
+    }
+}
+
+// Single-pass matrix-core form: the three components go through every
+// stage together, so an element takes seven workgroup barriers.  About one
+// wave per 16-point tile of a fine-grid plane keeps the heaviest stage
+// (velocity, contravariant velocity and the three derivatives of each
+// component on the fine points) nearly balanced; the smaller stages
+// distribute their tiles round-robin.  Operand reads carry no bounds tests:
+// every 1D-matrix register is zero outside its index range, and every LDS
+// region is zero-filled at the start with a pad behind it, so out-of-range
+// lanes read finite values that either meet a zero matrix entry or land in
+// output rows/columns that are never stored.  Stores of partial tiles write
+// their unused lanes to a scratch slot instead of branching.
+template <int LX, typename C> struct Dv2 {
+    using D = Dm<LX>;
+    static constexpr int LXD = D::LXD, NL = D::NL, NN = D::NN, N3 = D::N3, ND3 = D::ND3;
+    // waves: one per fine tile, rounded down to a multiple of four so that
+    // two workgroups place evenly on the four SIMDs of a CU
+    static constexpr int NW = D::NNT <= 4 ? D::NNT : (D::NNT / 4) * 4, NT = 64 * NW;
+    static constexpr int PAD = 4 * NN + 64;
+    static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+    // region X: u (3 N3) + Y1 (6 NL LXD) | T (3 LXD^3) | Z2 (3 NL LXD); region Y: Y2 (9 LX NN) | Z1 (3 LX NN)
+    static constexpr int X = cmax(cmax(3 * N3 + 6 * NL * LXD, 3 * ND3), 3 * NL * LXD) + PAD;
+    static constexpr int Y = 9 * LX * NN + PAD;
+    static constexpr int DUMMY = X + Y;          // 64 scratch slots for unused lanes of partial tiles
+    static constexpr int TOTAL = X + Y + 64;
+    static constexpr bool fits = TOTAL * (int)sizeof(C) <= 160 * 1024 && LXD <= 16 && NW <= 16;
+    // workgroups per CU that the LDS allows (at most 2), and the waves per SIMD
+    // the register allocation must leave room for so that they are co-resident
+    // (a workgroup's waves go round-robin over the four SIMDs, so a SIMD may
+    // hold ceil(NW/4) waves of each)
+    static constexpr int WG = TOTAL * (int)sizeof(C) * 2 <= 160 * 1024 ? 2 : 1;
+    static constexpr int WPE = WG * ((NW + 3) / 4);
+    static constexpr int NUP = (N3 + NT - 1) / NT;   // velocity points per thread
+};
+
+template <int LX, typename TM, typename C>
+__global__ void __launch_bounds__((Dv2<LX, C>::NT), (Dv2<LX, C>::WPE)) conv_dealias_v2_kernel(Batch bt)
+{
+    using D = Dm<LX>;
+    using Q = Dv2<LX, C>;
+    using M = Mma<C>;
+    typedef typename M::V4 V4;
+    constexpr int LXD = D::LXD, NL = D::NL, NN = D::NN, N3 = D::N3, ND3 = D::ND3;
+    constexpr int KSX = D::KSX, KSD = D::KSD, NLT = D::NLT, NNT = D::NNT, NW = Q::NW;
+    static_assert(Q::fits, "LDS footprint");
+    __shared__ C lds[Q::TOTAL];
+    C* const sU = lds;                       // [3][N3]
+    C* const sY1 = lds + 3 * N3;             // [3][2][NL][LXD]: P = I u, Q = ID u along the first index
+    C* const sT = lds;                       // [3][LXD^3]
+    C* const sZ2 = lds;                      // [3][NL][LXD]
+    C* const sY2 = lds + Q::X;               // [3][3][LX][NN]: I P, ID P, I Q along the second index
+    C* const sZ1 = lds + Q::X;               // [3][LX][NN]
+    const int gb = blockIdx.x;
+    const int ri = find_req(bt.eb, bt.n, gb);
+    const ReqDesc* R = bt.r[ri];
+    const int blk = gb - bt.eb[ri];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, m = lane & 15, g = lane >> 4;
+    const int dummy = Q::DUMMY + lane;
+    for (int p = t; p < Q::TOTAL; p += Q::NT) lds[p] = (C)0;
+    C fI[KSX], fD[KSX], bI[KSD];
+    {
+        const int o = sizeof(C) == 8 ? dl_off64<LX>() : dl_off32<LX>();
+#pragma unroll
+        for (int s = 0; s < KSX; ++s) {
+            const int k = 4 * s + g;
+            const bool ok = m < LXD && k < LX;
+            if constexpr (sizeof(C) == 8) {
+                fI[s] = ok ? gp(R->D64)[o + m * LX + k] : 0.0;
+                fD[s] = ok ? gp(R->D64)[o + LXD * LX + m * LX + k] : 0.0;
+            } else {
+                fI[s] = ok ? gp(R->D32)[o + m * LX + k] : 0.0f;
+                fD[s] = ok ? gp(R->D32)[o + LXD * LX + m * LX + k] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < KSD; ++s) {
+            const int k = 4 * s + g;
+            const bool ok = k < LXD && m < LX;
+            if constexpr (sizeof(C) == 8) bI[s] = ok ? gp(R->D64)[o + k * LX + m] : 0.0;
+            else bI[s] = ok ? gp(R->D32)[o + k * LX + m] : 0.0f;
+        }
+    }
+    const SEM_GLOBAL TM* MF = gfield<TM>(R, mfd_field<TM>());
+    const SEM_GLOBAL double* U0 = gfield<double>(R, F_U);
+    const SEM_GLOBAL double* U1 = gfield<double>(R, F_U1);
+    const SEM_GLOBAL double* U2 = gfield<double>(R, F_U2);
+    SEM_GLOBAL double* O0 = gfieldw<double>(R, F_BN);
+    SEM_GLOBAL double* O1 = gfieldw<double>(R, F_BNb);
+    SEM_GLOBAL double* O2 = gfieldw<double>(R, F_BNc);
+
+    // the velocity of the next element is loaded while the current one is processed
+    constexpr int NUP = Q::NUP;
+    double un[3][NUP];
+    auto load_u = [&](int e) {
+        const long long eb = (long long)e * N3;
+#pragma unroll
+        for (int q = 0; q < NUP; ++q) {
+            const int p = t + q * Q::NT;
+            const int pc = p < N3 ? p : N3 - 1;
+            un[0][q] = U0[eb + pc];
+            un[1][q] = U1[eb + pc];
+            un[2][q] = U2[eb + pc];
+        }
+    };
+    const int e0 = blk * R->epb;
+    if (e0 < R->E) load_u(e0);
+    for (int el = 0; el < R->epb; ++el) {
+        const int e = blk * R->epb + el;
+        if (e >= R->E) break;
+        const long long eb = (long long)e * N3;
+        block_sync_lds();  // the previous element's last stage has read region X
+#pragma unroll
+        for (int q = 0; q < NUP; ++q) {
+            const int p = t + q * Q::NT;
+            if (p < N3) {
+                sU[p] = (C)un[0][q];
+                sU[N3 + p] = (C)un[1][q];
+                sU[2 * N3 + p] = (C)un[2][q];
+            }
+        }
+        if (el + 1 < R->epb && e + 1 < R->E) load_u(e + 1);
+        block_sync_lds();
+        // S1, first index: Y1[c][mat][L][i'] = sum_a u_c[L][a] mat[i'][a]
+        for (int job = w; job < 6 * NLT; job += NW) {
+            const int cm = job / NLT, lt = job - cm * NLT;
+            const int c = cm >> 1, mat = cm & 1;
+            const C* src = sU + c * N3 + (16 * lt + m) * LX + g;
+            V4 acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < KSX; ++s) acc = M::mma(src[4 * s], mat ? fD[s] : fI[s], acc);
+            C* dst = sY1 + cm * NL * LXD;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int L = 16 * lt + M::row(g, r);
+                lds[(L < NL && m < LXD) ? (int)(dst - lds) + L * LXD + m : dummy] = acc[r];
+            }
+        }
+        block_sync_lds();
+        // S2, second index per plane cc: kind 0 I P, 1 ID P, 2 I Q
+        for (int job = w; job < 9 * LX; job += NW) {
+            const int ck = job / LX, cc = job - ck * LX;
+            const int c = ck / 3, kind = ck - 3 * c;
+            const C* src = sY1 + (2 * c + (kind == 2)) * NL * LXD + (cc * LX + g) * LXD + m;
+            V4 acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < KSX; ++s) acc = M::mma(kind == 1 ? fD[s] : fI[s], src[4 * s * LXD], acc);
+            const int base = (int)(sY2 - lds) + ck * LX * NN + cc * NN;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int jo = M::row(g, r);
+                lds[(jo < LXD && m < LXD) ? base + jo * LXD + m : dummy] = acc[r];
+            }
+        }
+        block_sync_lds();
+        // S3, third index, one fine tile per wave: u_c, V_a = sum_c u_c W dr_a/dx_c,
+        // then T_f = V_r d_r u_f + V_s d_s u_f + V_t d_t u_f
+        const SEM_GLOBAL TM* me = MF + (long long)e * 9 * ND3;
+        for (int tn = w; tn < NNT; tn += NW) {
+            const int n = 16 * tn + m;
+            int qoff[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int kk = M::row(g, r);
+                qoff[r] = (kk < LXD ? kk : LXD - 1) * NN + (n < NN ? n : NN - 1);
+            }
+            C mf[9][4];
+#pragma unroll
+            for (int ac = 0; ac < 9; ++ac)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) mf[ac][r] = (C)me[ac * ND3 + qoff[r]];
+            const C* y2 = sY2 + g * NN + n;
+            V4 V[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) V[a] = V4{0, 0, 0, 0};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                V4 uc = {0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < KSX; ++s) uc = M::mma(fI[s], y2[(3 * c) * LX * NN + 4 * s * NN], uc);
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) V[a][r] += uc[r] * mf[a * 3 + c][r];
+            }
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                V4 dt = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, dr = {0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < KSX; ++s) {
+                    dt = M::mma(fD[s], y2[(3 * f + 0) * LX * NN + 4 * s * NN], dt);
+                    ds = M::mma(fI[s], y2[(3 * f + 1) * LX * NN + 4 * s * NN], ds);
+                    dr = M::mma(fI[s], y2[(3 * f + 2) * LX * NN + 4 * s * NN], dr);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int kk = M::row(g, r);
+                    const C T = V[0][r] * dr[r] + V[1][r] * ds[r] + V[2][r] * dt[r];
+                    lds[(kk < LXD && n < NN) ? (int)(sT - lds) + f * ND3 + kk * NN + n : dummy] = T;
+                }
+            }
+        }
+        block_sync_lds();
+        // B1, transposed third index: Z1[f][c][n] = sum_k' I[k'][c] T_f[k'][n]
+        for (int job = w; job < 3 * NNT; job += NW) {
+            const int f = job / NNT, tn = job - f * NNT;
+            const int n = 16 * tn + m;
+            const C* src = sT + f * ND3 + g * NN + n;
+            V4 acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < KSD; ++s) acc = M::mma(bI[s], src[4 * s * NN], acc);
+            const int base = (int)(sZ1 - lds) + f * LX * NN;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = M::row(g, r);
+                lds[(c < LX && n < NN) ? base + c * NN + n : dummy] = acc[r];
+            }
+        }
+        block_sync_lds();
+        // B2, transposed second index per plane c: Z2[f][c LX + b][i'] = sum_j' I[j'][b] Z1[f][c][j'][i']
+        for (int job = w; job < 3 * LX; job += NW) {
+            const int f = job / LX, c = job - f * LX;
+            const C* src = sZ1 + f * LX * NN + c * NN + g * LXD + m;
+            V4 acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < KSD; ++s) acc = M::mma(bI[s], src[4 * s * LXD], acc);
+            const int base = (int)(sZ2 - lds) + f * NL * LXD + c * LX * LXD;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int b = M::row(g, r);
+                lds[(b < LX && m < LXD) ? base + b * LXD + m : dummy] = acc[r];
+            }
+        }
+        block_sync_lds();
+        // B3, transposed first index: BN_f[L][a] = -sum_i' Z2[f][L][i'] I[i'][a]
+        for (int job = w; job < 3 * NLT; job += NW) {
+            const int f = job / NLT, lt = job - f * NLT;
+            const C* src = sZ2 + f * NL * LXD + (16 * lt + m) * LXD + g;
+            V4 acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < KSD; ++s) acc = M::mma(src[4 * s], bI[s], acc);
+            SEM_GLOBAL double* O = f == 0 ? O0 : f == 1 ? O1 : O2;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int L = 16 * lt + M::row(g, r);
+                if (L < NL && m < LX) O[eb + L * LX + m] = -(double)acc[r];
+            }
+        }
+    }
+}
+
 #define DL_LX_SWITCH(lx, CALL) \
     switch (lx) { \
     case 3: CALL(3); break; case 4: CALL(4); break; case 5: CALL(5); break; case 6: CALL(6); break; \
@@ -292,7 +823,16 @@ void launch_dealias_geom(const Batch& b, int lx, const MeshParams& mp, int want3
 void launch_conv_dealias(const Batch& b, int lx, int tm, int tc, hipStream_t s)
 {
     if (b.eb[b.n] == 0) return;
-#define GO3(L, TM, C) hipLaunchKernelGGL((conv_dealias_kernel<L, TM, C>), dim3(b.eb[b.n]), dim3(Dl<L>::NT), 0, s, b)
+    // matrix-core form while the fine grid fits one 16-row tile (lx <= 10)
+#define GO3(L, TM, C)                                                                                                  \
+    do {                                                                                                               \
+        if constexpr (Dv2<L, C>::fits)                                                                                 \
+            hipLaunchKernelGGL((conv_dealias_v2_kernel<L, TM, C>), dim3(b.eb[b.n]), dim3((Dv2<L, C>::NT)), 0, s, b);  \
+        else if constexpr ((3 * L + 1) / 2 <= 16)                                                                      \
+            hipLaunchKernelGGL((conv_dealias_mfma_kernel<L, TM, C>), dim3(b.eb[b.n]), dim3(Dm<L>::NT), 0, s, b);      \
+        else                                                                                                           \
+            hipLaunchKernelGGL((conv_dealias_kernel<L, TM, C>), dim3(b.eb[b.n]), dim3(Dl<L>::NT), 0, s, b);           \
+    } while (0)
     if (tm == P64) {
 #define GO(L) GO3(L, double, double)
         DL_LX_SWITCH(lx, GO)
