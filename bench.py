@@ -222,7 +222,7 @@ def roofline(kind, tier, prof, steps, npts, workload, N=7, dealias=0):
         achieved = alg / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
         flops = nlaunch * E * fl / (tot_ms * 1e-3) / 1e12 if tot_ms > 0 else 0.0
         peak_fl = 78.6 if tier == "fp64" else 157.3
-        name = ("conv_dealias_kernel<%d, %s>" % (lx, "double, double" if tier == "fp64" else "float, float")
+        name = ("conv_dealias_v2_kernel<%d, %s>" % (lx, "double, double" if tier == "fp64" else "float, float")
                 if dealias else "conv_kernel<%d, ...>" % lx) + " -- convective term B N(u)"
         return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launches": nlaunch, "active_units": nlaunch,
