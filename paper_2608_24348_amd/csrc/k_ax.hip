@@ -142,7 +142,7 @@ ax_kernel(Batch bt, AxLaunch a)
     for (int k = 0; k < NG; ++k) {
         if (GALL || k == 0) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) graw[q][k] = ldg(G + gbase + q * L3 + k * L2 + ij);
+            for (int q = 0; q < 6; ++q) graw[q][k] = ldg_stream(G + gbase + q * L3 + k * L2 + ij);
         }
     }
     block_sync_lds();  // sD ready
@@ -168,7 +168,7 @@ ax_kernel(Batch bt, AxLaunch a)
         if (!GALL && k + 1 < LX) {
             const int pn = (k + 1) * L2 + ij;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) graw[q][(k + 1) & 1] = ldg(G + gbase + q * L3 + pn);
+            for (int q = 0; q < 6; ++q) graw[q][(k + 1) & 1] = ldg_stream(G + gbase + q * L3 + pn);
         }
         if (el < EPB) su[el][ij] = ureg[k];
         block_sync_lds();

@@ -52,6 +52,19 @@ template <> __device__ __forceinline__ void stg<__hip_bfloat16>(SEM_GLOBAL __hip
     *(SEM_GLOBAL unsigned short*)p = __bfloat16_as_ushort(v);
 }
 
+// Streaming loads for data each launch reads exactly once (geometric factors,
+// metric terms): the nontemporal hint keeps them from evicting the solver
+// vectors that the next kernel reads again from the caches.
+template <typename T> __device__ __forceinline__ T ldg_stream(const SEM_GLOBAL T* p) { return __builtin_nontemporal_load(p); }
+template <> __device__ __forceinline__ __half ldg_stream<__half>(const SEM_GLOBAL __half* p)
+{
+    return __ushort_as_half(__builtin_nontemporal_load((const SEM_GLOBAL unsigned short*)p));
+}
+template <> __device__ __forceinline__ __hip_bfloat16 ldg_stream<__hip_bfloat16>(const SEM_GLOBAL __hip_bfloat16* p)
+{
+    return __ushort_as_bfloat16(__builtin_nontemporal_load((const SEM_GLOBAL unsigned short*)p));
+}
+
 template <typename T> struct TypeOf;
 template <> struct TypeOf<double> { static constexpr int id = P64; };
 template <> struct TypeOf<float> { static constexpr int id = P32; };

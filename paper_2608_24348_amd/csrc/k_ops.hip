@@ -24,8 +24,8 @@ template <> __device__ __forceinline__ int mfield<float>() { return F_M32; }
 template <typename TM, typename C>
 __device__ __forceinline__ C ldm(const SEM_GLOBAL TM* M, long long off, C sc)
 {
-    if constexpr (sizeof(TM) == 2) return to<C>(ldg(M + off)) * sc;
-    else return (C)M[off];
+    if constexpr (sizeof(TM) == 2) return to<C>(ldg_stream(M + off)) * sc;
+    else return (C)ldg_stream(M + off);
 }
 
 template <typename TM, typename C>
@@ -233,6 +233,9 @@ __global__ void __launch_bounds__(ONthr<LX>::v) diagnostics_kernel(Batch bt)
         if (live) {
             const int p = k * L2 + ij;
             const double bm = B[ebase + p];
+            double m[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) m[q] = ldg_stream(M + ((long long)ee * 9 + q) * L3 + p);
             double gr[3][3];  // gr[f][c] = d u_f / d x_c
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
@@ -245,8 +248,7 @@ __global__ void __launch_bounds__(ONthr<LX>::v) diagnostics_kernel(Batch bt)
                 }
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    gr[f][c] = (M[((long long)ee * 9 + 0 * 3 + c) * L3 + p] * dr + M[((long long)ee * 9 + 1 * 3 + c) * L3 + p] * ds
-                              + M[((long long)ee * 9 + 2 * 3 + c) * L3 + p] * dt) / bm;
+                    gr[f][c] = (m[0 * 3 + c] * dr + m[1 * 3 + c] * ds + m[2 * 3 + c] * dt) / bm;
             }
             const double wx = gr[2][1] - gr[1][2];
             const double wy = gr[0][2] - gr[2][0];

@@ -160,22 +160,28 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         break;
     }
     case V_RHS: {
+        // all three components per point (the mass is read once)
         auto B = fld<double>(R, F_B64);
-        auto bn0 = fld<double>(R, F_BN + c);
-        auto bn1 = fld<double>(R, F_BNL1 + c);
-        auto bn2 = fld<double>(R, F_BNL2 + c);
-        auto u0 = fld<double>(R, F_U + c);
-        auto u1 = fld<double>(R, F_UL1 + c);
-        auto u2 = fld<double>(R, F_UL2 + c);
-        auto gp = fld<double>(R, F_GP + c);
-        auto rhs = fldw<double>(R, F_RHS + c);
+        const SEM_GLOBAL double *bn0[3], *bn1[3], *bn2[3], *u0[3], *u1[3], *u2[3], *gpr[3];
+        SEM_GLOBAL double* rhs[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            bn0[q] = fld<double>(R, F_BN + q); bn1[q] = fld<double>(R, F_BNL1 + q); bn2[q] = fld<double>(R, F_BNL2 + q);
+            u0[q] = fld<double>(R, F_U + q); u1[q] = fld<double>(R, F_UL1 + q); u2[q] = fld<double>(R, F_UL2 + q);
+            gpr[q] = fld<double>(R, F_GP + q);
+            rhs[q] = fldw<double>(R, F_RHS + q);
+        }
         const double a1 = S[S_EXT], a2 = S[S_EXT + 1], a3 = S[S_EXT + 2];
         const double b1 = S[S_BDF], b2 = S[S_BDF + 1], b3 = S[S_BDF + 2];
         const double idt = 1.0 / S[S_DT];
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
-            const double ext = a1 * bn0[p] + a2 * bn1[p] + a3 * bn2[p];
-            const double hist = b1 * u0[p] + b2 * u1[p] + b3 * u2[p];
-            rhs[p] = ext + B[p] * idt * hist - gp[p];
+            const double bi = B[p] * idt;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const double ext = a1 * bn0[q][p] + a2 * bn1[q][p] + a3 * bn2[q][p];
+                const double hist = b1 * u0[q][p] + b2 * u1[q][p] + b3 * u2[q][p];
+                rhs[q][p] = ext + bi * hist - gpr[q][p];
+            }
         }
         break;
     }
@@ -246,16 +252,24 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         break;
     }
     case V_CORRECT: {
-        auto us = fld<double>(R, F_US + c);
-        auto gp = fld<double>(R, F_GP + c);
+        // all three components per point, and p += phi
+        const SEM_GLOBAL double *us[3], *gpr[3];
+        SEM_GLOBAL double* un[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            us[q] = fld<double>(R, F_US + q);
+            gpr[q] = fld<double>(R, F_GP + q);
+            un[q] = fldw<double>(R, F_UL2 + q);
+        }
         auto ib = fld<double>(R, F_IBSUM64);
-        auto un = fldw<double>(R, F_UL2 + c);
+        auto pres = fldw<double>(R, F_P);
+        auto phi = fld<double>(R, F_GX);
         const double f = S[S_DT] / S[S_BETA0];
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) un[p] = us[p] - f * gp[p] * ib[p];
-        if (c == 0) {
-            auto pres = fldw<double>(R, F_P);
-            auto phi = fld<double>(R, F_GX);
-            for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) pres[p] += phi[p];
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+            const double ibp = ib[p];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) un[q][p] = us[q][p] - f * gpr[q][p] * ibp;
+            pres[p] += phi[p];
         }
         break;
     }

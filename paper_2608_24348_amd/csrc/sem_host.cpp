@@ -1207,7 +1207,7 @@ int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stat
         // (i) explicit terms: convection, old pressure gradient, BDF/EXT history
         convection(b, c0, s);
         launch_opgrad(b, lx, r.opg_m, r.opg_c, F_P, F_GP, s);
-        vec(b, V_RHS, 3, P64, -1, s);  // local rhs: assembled together with the residual
+        vec(b, V_RHS, 1, P64, -1, s);  // local rhs (3 components), assembled together with the residual
         // (ii) velocity Helmholtz solves -> u*
         rc = velocity_solve(ctxs, b, s);
         if (rc) return rc;
@@ -1227,7 +1227,7 @@ int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stat
         // (iv) correction and pressure update, lag rotation, diagnostics
         launch_opgrad(b, lx, r.opg_m, r.opg_c, F_GX, F_GP, s);
         launch_dssum(b, F_GP, 3, P64, -1, nullptr, s);
-        vec(b, V_CORRECT, 3, P64, -1, s);
+        vec(b, V_CORRECT, 1, P64, -1, s);  // 3 components and p += phi
         fin(b, FIN_STEP_END, s);
         launch_diagnostics(b, lx, s);
         fin(b, FIN_DIAG, s);
