@@ -73,25 +73,45 @@ def run_tier(sem, torch, tier, nel, N, nu, dt, warmup, steps, prof_class=None, v
     return ctx, (t1 - t0), st, series, prof
 
 
-def ax_rate(sem, torch, ctx, dtype, reps=20, nvec=4):
-    """Poisson-operator GDOF/s on the context's mesh (HIP events, current
-    stream).  The launches cycle through nvec distinct input/output pairs
-    (at least 0.5 GB together) so that no launch finds its vectors in the
-    last-level cache left by the previous one: the rate is HBM-bound."""
-    us = [torch.randn(ctx.np, dtype=torch.float64, device="cuda:0").to(dtype) for _ in range(nvec)]
+def ax_rate(sem, torch, ctx, dtype, geom, reps=20, nvec=2):
+    """Poisson-operator GDOF/s (HIP events, current stream).  The launches
+    cycle through nvec distinct input/output pairs so that no launch finds
+    its vectors in the last-level cache left by the previous one."""
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(0)
+    us = [torch.randn(ctx.np, dtype=torch.float64, device="cuda:0", generator=g).to(dtype) for _ in range(nvec)]
     ws = [torch.empty_like(us[0]) for _ in range(nvec)]
     for q in range(nvec):
-        ctx.ax(us[q], ws[q], 1.0, 0.0)
+        ctx.ax(us[q], ws[q], 1.0, 0.0, geom=geom)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for r in range(reps):
-        ctx.ax(us[r % nvec], ws[r % nvec], 1.0, 0.0)
+        ctx.ax(us[r % nvec], ws[r % nvec], 1.0, 0.0, geom=geom)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     del us, ws
     return ctx.np / (ms * 1e-3) / 1e9, ms
+
+
+def ax_leg(sem, torch, inputs, nel=64, N=7):
+    """The Ax microbenchmark workload: 64^3 elements N=7 (134 M points),
+    sinusoidally deformed (amplitude 0.1 h, seeded phases), u ~ N(0,1)
+    seeded; Poisson operator in every storage tier (bytes per point: vectors
+    in and out + 6 geometric factors)."""
+    ctx = sem.Context(sem.mesh_desc((nel,) * 3, N, amp=0.1, phase=inputs.deform_phases()),
+                      sem.flow_desc(mode=sem.MODE_OPERATOR), sem.tier("fp32b+fp16all"))
+    out = {"workload": "Poisson operator, %d^3 elements N=%d (%d points), deformed amp 0.1 h, u ~ N(0,1); "
+                       "HIP events over 20 launches cycling through 2 vector pairs" % (nel, N, ctx.np)}
+    for name, dt, geom, bpp in (("fp64", torch.float64, sem.FP64, 64), ("fp32", torch.float32, sem.FP32, 32),
+                                ("fp32_fp16geom", torch.float32, sem.FP16, 20), ("fp16", torch.float16, sem.FP16, 16)):
+        gd, ms = ax_rate(sem, torch, ctx, dt, geom)
+        out[name] = {"gdof_per_s": gd, "ms": ms, "bytes_per_point": bpp, "hbm_GBps": gd * bpp,
+                     "frac": gd * bpp / HBM_PEAK_GBS}
+    del ctx
+    torch.cuda.empty_cache()
+    return out
 
 
 # algorithmic bytes per local point of one active (component) launch, by tier
@@ -344,12 +364,6 @@ def main():
         out["roofline"] = roofline(args.prof, args.tier, prof, st_mx, npts, out["config"]["workload"], N,
                                    args.dealias)
 
-    if not args.no_ax:
-        g32, ms32 = ax_rate(sem, torch, ctx, torch.float32)
-        out["ax_gdofs"] = {"fp32": g32, "fp32_ms": ms32,
-                           "fp32_hbm_GBps": g32 * 32, "fp32_frac": g32 * 32 / HBM_PEAK_GBS,
-                           "note": "Poisson operator (u, w fp32, 6 G fp32: 32 B/point; fp64: 64), HIP events, "
-                                   "20 launches cycling through 4 distinct vector pairs"}
     if not args.no_fp64:
         ctx64, t64, st64, ser64, _ = run_tier(sem, torch, "fp64", nel, N, nu, dt, args.warmup, args.steps, None,
                                               args.vtol, args.ptol, args.proj, args.dealias)
@@ -364,15 +378,14 @@ def main():
                                     "max_div_mx": max(r[3] for r in ser_mx), "max_div_fp64": max(r[3] for r in ser64),
                                     "steps_compared": len(ke64)}
         out["iters_fp64"] = {"vel": [s["vit"] for s in st64], "pres": [s["pit"] for s in st64]}
-        if not args.no_ax:
-            g64, ms64 = ax_rate(sem, torch, ctx64, torch.float64)
-            out["ax_gdofs"]["fp64"] = g64
-            out["ax_gdofs"]["fp64_ms"] = ms64
-            out["ax_gdofs"]["fp64_hbm_GBps"] = g64 * 64
-            out["ax_gdofs"]["fp64_frac"] = g64 * 64 / HBM_PEAK_GBS
         del ctx64
     del ctx
     torch.cuda.synchronize()
+    if not args.no_ax:
+        from paper_2608_24348_amd import inputs
+        torch.cuda.empty_cache()
+        log("ax: 64^3 deformed mesh, every storage tier")
+        out["ax_gdofs"] = ax_leg(sem, torch, inputs)
     if args.serve > 0:
         from paper_2608_24348_amd import serve
         log("serving: %d requests, burst then Poisson arrivals at 0.7x the burst rate" % args.serve)

@@ -120,9 +120,9 @@ typedef struct {
                                         pressure increment in the span of earlier ones (Sec. 3 uses 20) */
     int dealias;                     /* 1: the convective term is integrated on ceil(3 lx / 2) Gauss-Legendre
                                         points per direction (the 3/2 rule; Sec. 3 runs with dealiasing)
-                                        instead of by collocation on the GLL points; fluid mode only, conv
-                                        storage fp64 or fp32.  Adds 9 E ceil(3 lx/2)^3 fp64 metric terms
-                                        (plus an fp32 copy when conv storage is fp32). */
+                                        instead of by collocation on the GLL points; fluid mode only.
+                                        Adds 9 E ceil(3 lx/2)^3 fp64 metric terms, plus a copy in the conv
+                                        storage precision when that is fp32 or 16-bit (element-scaled). */
 } sem_flow_desc;
 
 #define SEM_MAX_PROJ 20

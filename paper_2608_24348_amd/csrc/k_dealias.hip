@@ -165,23 +165,56 @@ __global__ void __launch_bounds__(Dl<LX>::NT) dealias_geom_kernel(Batch bt, Mesh
     }
 }
 
-// fp32 copy of the fine-grid metric terms
-__global__ void __launch_bounds__(256) dealias_cast_kernel(Batch bt, long long per_elem)
+// fp32 and element-scaled 16-bit copies of the fine-grid metric terms, each
+// rounded once from fp64 (power-of-two scales keep the 16-bit rounding single)
+template <typename T16>
+__global__ void __launch_bounds__(256) dealias_cast_kernel(Batch bt, int per_elem, int want32, int want16)
 {
+    __shared__ double red[4];
     const int g = blockIdx.x;
     const int ri = find_req(bt.eb, bt.n, g);
     const ReqDesc* R = bt.r[ri];
     const int blk = g - bt.eb[ri];
-    const long long e0 = (long long)blk * R->epb;
-    long long e1 = e0 + R->epb;
-    if (e1 > R->E) e1 = R->E;
     const SEM_GLOBAL double* src = gfield<double>(R, F_MFD64);
-    SEM_GLOBAL float* dst = gfieldw<float>(R, F_MFD32);
-    for (long long p = e0 * per_elem + threadIdx.x; p < e1 * per_elem; p += blockDim.x) dst[p] = (float)src[p];
+    for (int el = 0; el < R->epb; ++el) {
+        const int e = blk * R->epb + el;
+        if (e >= R->E) break;
+        const SEM_GLOBAL double* me = src + (long long)e * per_elem;
+        if (want32) {
+            SEM_GLOBAL float* dst = gfieldw<float>(R, F_MFD32) + (long long)e * per_elem;
+            for (int p = threadIdx.x; p < per_elem; p += blockDim.x) dst[p] = (float)me[p];
+        }
+        if (want16) {
+            double mx = 0.0;
+            for (int p = threadIdx.x; p < per_elem; p += blockDim.x) mx = fmax(mx, fabs(me[p]));
+            mx = wave_max(mx);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+            __syncthreads();
+            mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+            __syncthreads();
+            const double sc = mx > 0 ? exp2(ceil(log2(mx))) : 1.0;
+            if (threadIdx.x == 0) gfieldw<float>(R, F_MFDSC)[e] = (float)sc;
+            SEM_GLOBAL T16* dst = gfieldw<T16>(R, F_MFD16) + (long long)e * per_elem;
+            for (int p = threadIdx.x; p < per_elem; p += blockDim.x) stg(dst + p, to<T16>(me[p] / sc));
+        }
+    }
 }
 
-template <typename TM> __device__ __forceinline__ int mfd_field() { return F_MFD32; }
+template <typename TM> __device__ __forceinline__ int mfd_field() { return F_MFD16; }
 template <> __device__ __forceinline__ int mfd_field<double>() { return F_MFD64; }
+template <> __device__ __forceinline__ int mfd_field<float>() { return F_MFD32; }
+
+// one fine-grid metric term in the arithmetic type (16-bit storage carries the element scale)
+template <typename TM, typename C> __device__ __forceinline__ C mload(const SEM_GLOBAL TM* p, C sc)
+{
+    if constexpr (sizeof(TM) == 2) return to<C>(ldg(p)) * sc;
+    else return (C)*p;
+}
+template <typename TM, typename C> __device__ __forceinline__ C mscale(const ReqDesc* R, int e)
+{
+    if constexpr (sizeof(TM) == 2) return (C)gfield<float>(R, F_MFDSC)[e];
+    else return (C)1;
+}
 
 // BN = dealiased -B (u . grad) u of the velocity field (F_U), fp64 output
 template <int LX, typename TM, typename C>
@@ -226,6 +259,7 @@ __global__ void __launch_bounds__(Dl<LX>::NT) conv_dealias_kernel(Batch bt)
         }
         __syncthreads();
         const SEM_GLOBAL TM* me = MF + (long long)e * 9 * ND3;
+        const C msc = mscale<TM, C>(R, e);
         // contravariant velocity V_a = sum_c u_c W dr_a/dx_c at this thread's fine points
         C V[3][NQ];
 #pragma unroll
@@ -240,7 +274,7 @@ __global__ void __launch_bounds__(Dl<LX>::NT) conv_dealias_kernel(Batch bt)
                 if (q < ND3) {
                     const C uf = F[q];
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) V[a][r] += uf * (C)me[(a * 3 + c) * ND3 + q];
+                    for (int a = 0; a < 3; ++a) V[a][r] += uf * mload<TM, C>(me + (a * 3 + c) * ND3 + q, msc);
                 }
             }
             __syncthreads();
@@ -365,6 +399,7 @@ __global__ void __launch_bounds__(Dm<LX>::NT) conv_dealias_mfma_kernel(Batch bt)
         }
         block_sync_lds();
         const SEM_GLOBAL TM* me = MF + (long long)e * 9 * ND3;
+        const C msc = mscale<TM, C>(R, e);
 
         // ---- contravariant velocity V_a = sum_c u_c (W dr_a/dx_c) at this wave's fine points
         V4 V[3][JW];
@@ -424,7 +459,7 @@ __global__ void __launch_bounds__(Dm<LX>::NT) conv_dealias_mfma_kernel(Batch bt)
                         const int kk = M::row(g, r);
                         if (n < NN && kk < LXD) {
 #pragma unroll
-                            for (int a = 0; a < 3; ++a) V[a][j][r] += acc[r] * (C)me[(long long)(a * 3 + c) * ND3 + kk * NN + n];
+                            for (int a = 0; a < 3; ++a) V[a][j][r] += acc[r] * mload<TM, C>(me + (a * 3 + c) * ND3 + kk * NN + n, msc);
                         }
                     }
                 }
@@ -707,6 +742,7 @@ __global__ void __launch_bounds__((Dv2<LX, C>::NT), (Dv2<LX, C>::WPE)) conv_deal
         // S3, third index, one fine tile per wave: u_c, V_a = sum_c u_c W dr_a/dx_c,
         // then T_f = V_r d_r u_f + V_s d_s u_f + V_t d_t u_f
         const SEM_GLOBAL TM* me = MF + (long long)e * 9 * ND3;
+        const C msc = mscale<TM, C>(R, e);
         for (int tn = w; tn < NNT; tn += NW) {
             const int n = 16 * tn + m;
             int qoff[4];
@@ -719,7 +755,7 @@ __global__ void __launch_bounds__((Dv2<LX, C>::NT), (Dv2<LX, C>::WPE)) conv_deal
 #pragma unroll
             for (int ac = 0; ac < 9; ++ac)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) mf[ac][r] = (C)me[ac * ND3 + qoff[r]];
+                for (int r = 0; r < 4; ++r) mf[ac][r] = mload<TM, C>(me + ac * ND3 + qoff[r], msc);
             const C* y2 = sY2 + g * NN + n;
             V4 V[3];
 #pragma unroll
@@ -806,20 +842,25 @@ __global__ void __launch_bounds__((Dv2<LX, C>::NT), (Dv2<LX, C>::WPE)) conv_deal
     case 7: CALL(7); break; case 8: CALL(8); break; case 9: CALL(9); break; case 10: CALL(10); break; \
     case 11: CALL(11); break; case 12: CALL(12); break; default: break; }
 
-void launch_dealias_geom(const Batch& b, int lx, const MeshParams& mp, int want32, hipStream_t s)
+void launch_dealias_geom(const Batch& b, int lx, const MeshParams& mp, int want32, int want16, hipStream_t s)
 {
     if (b.eb[b.n] == 0) return;
 #define GO(L) hipLaunchKernelGGL(dealias_geom_kernel<L>, dim3(b.eb[b.n]), dim3(Dl<L>::NT), 0, s, b, mp)
     DL_LX_SWITCH(lx, GO)
 #undef GO
-    if (want32) {
-        const long long per = 9LL * ((3 * lx + 1) / 2) * ((3 * lx + 1) / 2) * ((3 * lx + 1) / 2);
-        hipLaunchKernelGGL(dealias_cast_kernel, dim3(b.eb[b.n]), dim3(256), 0, s, b, per);
+    if (want32 || want16) {
+        const int nd = (3 * lx + 1) / 2;
+        const int per = 9 * nd * nd * nd;
+        if (want16 == PBF)
+            hipLaunchKernelGGL(dealias_cast_kernel<__hip_bfloat16>, dim3(b.eb[b.n]), dim3(256), 0, s, b, per, want32, 1);
+        else
+            hipLaunchKernelGGL(dealias_cast_kernel<__half>, dim3(b.eb[b.n]), dim3(256), 0, s, b, per, want32,
+                               want16 == P16 ? 1 : 0);
     }
 }
 
 // metric storage tm and arithmetic tc (tables in the arithmetic precision):
-// (fp64, fp64), (fp32, fp64) or (fp32, fp32)
+// (fp64, fp64), (fp32, fp64), (fp32, fp32) or (fp16/bf16, fp32)
 void launch_conv_dealias(const Batch& b, int lx, int tm, int tc, hipStream_t s)
 {
     if (b.eb[b.n] == 0) return;
@@ -835,6 +876,14 @@ void launch_conv_dealias(const Batch& b, int lx, int tm, int tc, hipStream_t s)
     } while (0)
     if (tm == P64) {
 #define GO(L) GO3(L, double, double)
+        DL_LX_SWITCH(lx, GO)
+#undef GO
+    } else if (tm == P16) {
+#define GO(L) GO3(L, __half, float)
+        DL_LX_SWITCH(lx, GO)
+#undef GO
+    } else if (tm == PBF) {
+#define GO(L) GO3(L, __hip_bfloat16, float)
         DL_LX_SWITCH(lx, GO)
 #undef GO
     } else if (tc == P64) {

@@ -494,6 +494,10 @@ void build_layout(sem_ctx* c)
             const size_t nf = 9 * (size_t)c->E * lxd * lxd * lxd;
             field(F_MFD64, 8 * nf);
             if (r.conv_m == P32) field(F_MFD32, 4 * nf);
+            if (r.conv_m == P16 || r.conv_m == PBF) {
+                field(F_MFD16, 2 * nf);
+                field(F_MFDSC, 4 * (size_t)c->E);
+            }
         }
     }
     c->bytes = off;
@@ -900,8 +904,6 @@ int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_pr
     Resolved rs;
     int rc = resolve_policy(prec, rs);
     if (rc) return rc;
-    if (flow->mode == SEM_MODE_FLUID && flow->dealias && rs.conv_m != P64 && rs.conv_m != P32)
-        return fail(SEM_EINVAL, "dealiased convection needs conv storage fp64 or fp32");
 
     sem_ctx* c = new sem_ctx();
     c->mesh = *mesh;
@@ -1051,7 +1053,9 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     launch_dssum(b, F_IBSUM64, 1, P64, -1, nullptr, s);
     launch_geo_post(b, s);
     if (c->rs.need32 || c->rs.need16) launch_geo_cast(b, c->lx, c->rs.need32 ? 1 : 0, c->rs.need16 ? c->rs.kind16 : 0, s);
-    if (c->flow.mode == SEM_MODE_FLUID && c->flow.dealias) launch_dealias_geom(b, c->lx, c->mp, c->rs.conv_m == P32, s);
+    if (c->flow.mode == SEM_MODE_FLUID && c->flow.dealias)
+        launch_dealias_geom(b, c->lx, c->mp, c->rs.conv_m == P32,
+                            (c->rs.conv_m == P16 || c->rs.conv_m == PBF) ? c->rs.conv_m : 0, s);
     // domain volume (sum of B)
     vec(b, V_SUM_MASS, 1, P64, -1, s, -1, -1, P64, P64, FIN_VOL);
     int rc = check_hip_last();

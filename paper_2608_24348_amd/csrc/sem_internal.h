@@ -76,6 +76,8 @@ enum FieldId : int {
     // dealiased convection (flow.dealias): metric terms at the LXD^3 Gauss-Legendre points
     F_MFD64,                    // [E][9][lxd3] W dr_a/dx_c, index a*3+c (W = jac * GL weights)
     F_MFD32,                    // fp32 copy (conv storage fp32)
+    F_MFD16,                    // 16-bit copy (conv storage fp16/bf16), element-scaled
+    F_MFDSC,                    // float[E]: scale of F_MFD16
     NFIELD
 };
 
@@ -257,7 +259,7 @@ void launch_node_field(const Batch& b, int lx, const MeshParams& mp, int what, d
 
 // SEM operators (output fp64)
 void launch_conv(const Batch& b, int lx, int tm, int tc, hipStream_t s);
-void launch_dealias_geom(const Batch& b, int lx, const MeshParams& mp, int want32, hipStream_t s);
+void launch_dealias_geom(const Batch& b, int lx, const MeshParams& mp, int want32, int want16, hipStream_t s);
 void launch_conv_dealias(const Batch& b, int lx, int tm, int tc, hipStream_t s);
 void launch_opgrad(const Batch& b, int lx, int tm, int tc, int src, int dst, hipStream_t s);
 void launch_wdiv(const Batch& b, int lx, int tm, int tc, int src, int dst, hipStream_t s);

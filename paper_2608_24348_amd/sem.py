@@ -152,7 +152,8 @@ def precision(rp=FP64, blocks=None, kernels=None, exceptions=None):
     return p
 
 
-TIERS = ("fp64", "fp32b", "fp32b-p32", "fp32b+fp16", "fp32b+bf16", "fp32b+fp16p", "fp32b+fp16all", "fp32b+bf16all")
+TIERS = ("fp64", "fp32b", "fp32b-p32", "fp32b+fp16", "fp32b+bf16", "fp32b+fp16p", "fp32b+fp16a", "fp32b+bf16a",
+         "fp32b+fp16all", "fp32b+bf16all")
 
 
 def tier(name):
@@ -171,13 +172,15 @@ def tier(name):
                   operator and opgrad (B-6 style)
     fp32b+bf16    same with bf16
     fp32b+fp16p   fp32b with fp16-stored geometry for the pressure operator (B-7)
+    fp32b+fp16a   fp32b with fp16-stored metric terms for the convective term,
+                  collocated or dealiased (B-5, adv_dealias); fp32b+bf16a with bf16
     fp32b+fp16all / fp32b+bf16all  16-bit geometry for both operators and
                   opgrad (operator microbenchmarks)
     """
     if name == "fp64":
         return precision(FP64)
     h = {"fp32b": None, "fp32b-p32": None, "fp32b+fp16": FP16, "fp32b+bf16": BF16, "fp32b+fp16p": FP16,
-         "fp32b+fp16all": FP16, "fp32b+bf16all": BF16}
+         "fp32b+fp16a": FP16, "fp32b+bf16a": BF16, "fp32b+fp16all": FP16, "fp32b+bf16all": BF16}
     if name not in h:
         raise ValueError("unknown tier %r" % name)
     blocks = {BLOCK_SEM: (FP32, FP32, FP32), BLOCK_VEL: (FP32, FP32, FP32), BLOCK_PRES: (FP64, FP64, FP32)}
@@ -189,6 +192,8 @@ def tier(name):
         ks[K_OPGRAD] = (FP32, FP32, h[name])
     if name in ("fp32b+fp16p", "fp32b+fp16all", "fp32b+bf16all"):
         ks[K_AX_PRES] = (FP64, FP64, h[name])
+    if name in ("fp32b+fp16a", "fp32b+bf16a"):
+        ks[K_CONV] = (FP32, FP32, h[name])
     return precision(FP32, blocks=blocks, kernels=ks)
 
 

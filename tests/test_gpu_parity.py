@@ -237,10 +237,13 @@ def test_dealiased_convection_fp64_matches_oracle(sem, nel, N, amp):
         assert _rel(got[q].cpu().numpy(), ref[q]) < 1e-12
 
 
-def _dealias_abs_bound(m, u):
+def _dealias_abs_bound(m, u, floor=0.0):
     """Magnitude of every term of the dealiased convection, element by element:
     the same contractions as the method with every factor replaced by its
-    absolute value (the Higham-style bound multiplies it by gamma_K)."""
+    absolute value (the Higham-style bound multiplies it by gamma_K).  With
+    floor > 0 every metric term is raised by floor * (the element's largest
+    metric term), which covers absolute (subnormal) rounding of scaled 16-bit
+    storage."""
     xi, _, D = m.tables()
     lx = m.lx
     nd = lxd(lx)
@@ -259,7 +262,9 @@ def _dealias_abs_bound(m, u):
     J = np.moveaxis(J, (1, 2), (-2, -1))                # [e][k][j][i][c][a] = dx_c/dr_a
     det = np.linalg.det(J)
     W = det * np.einsum("k,j,i->kji", wz, wz, wz)
-    rx = np.linalg.inv(J) * W[..., None, None]          # [..][a][c] = W dr_a/dx_c
+    rx = np.abs(np.linalg.inv(J) * W[..., None, None])  # [..][a][c] = |W dr_a/dx_c|
+    if floor:
+        rx = rx + floor * rx.reshape(E, -1).max(axis=1)[:, None, None, None, None, None]
     uf = np.stack([t3(aI, aI, aI, U[c]) for c in range(3)], -1)     # [e][k][j][i][c]
     V = np.abs(np.einsum("ekjiac,ekjic->ekjia", np.abs(rx), uf))
     out = np.zeros((3, E, lx, lx, lx))
@@ -268,6 +273,28 @@ def _dealias_abs_bound(m, u):
         T = (V * g).sum(-1)
         out[f] = np.einsum("ia,jb,kc,ekji->ecba", aI, aI, aI, T, optimize=True)
     return out.reshape(3, m.np)
+
+
+@pytest.mark.parametrize("tier,eps16", [("fp32b+fp16a", 2.0 ** -11), ("fp32b+bf16a", 2.0 ** -8)])
+@pytest.mark.parametrize("nel,N,amp", [((4, 4, 4), 5, 0.1), ((2, 2, 2), 11, 0.1), ((2, 4, 2), 7, 0.1)])
+def test_dealiased_convection_16bit_metric_within_rounding_bound(sem, nel, N, amp, tier, eps16):
+    """B-5 (Table 2: fp16 in adv_dealias): the fine-grid metric terms stored in
+    16 bits with a power-of-two scale per element, fp32 arithmetic.  Bound:
+    gamma_K |terms| (fp32 arithmetic as in the fp32 case) + eps16 |terms|
+    (one rounding of each metric term; the floor covers fp16 subnormals)."""
+    c = _ctx(sem, nel, N, tier=tier, amp=amp, dealias=1)
+    m = OracleMesh(nel, N, amp=amp, phase=inputs.deform_phases() if amp else None)
+    u = np.stack([inputs.local_normal(nel, N, seed=s) for s in (9, 10, 11)])
+    ref = m.conv_dealias(u)
+    got = np.stack([g.cpu().numpy() for g in c.conv([_dev(u[q]) for q in range(3)])])
+    lx = N + 1
+    K = 6 * lx + 3 * lxd(lx) + 6 + 12
+    gam = K * 2.0 ** -24 / (1 - K * 2.0 ** -24)
+    bound = gam * _dealias_abs_bound(m, u) + eps16 * _dealias_abs_bound(m, u, floor=2.0 ** -13)
+    err = np.abs(got - ref)
+    assert np.all(err <= bound), float((err / bound).max())
+    # the 16-bit storage is in effect: errors well above fp32 rounding
+    assert _rel(got, ref) > 10 * gam
 
 
 @pytest.mark.parametrize("nel,N,amp", [((4, 4, 4), 5, 0.1), ((2, 2, 2), 11, 0.1), ((2, 4, 2), 7, 0.0)])
@@ -330,7 +357,7 @@ def test_batched_step_is_bitwise_equal_to_alone(sem, proj, dealias):
 
 
 @pytest.mark.parametrize("tier,proj,dealias", [("fp32b", 0, 0), ("fp32b+fp16", 0, 0), ("fp32b+bf16", 0, 0),
-                                               ("fp32b", 20, 0), ("fp32b", 0, 1)])
+                                               ("fp32b", 20, 0), ("fp32b", 0, 1), ("fp32b+fp16a", 0, 1)])
 def test_mixed_tier_c1_energy_and_enstrophy_error(sem, tier, proj, dealias):
     """Mixed tiers against the FP64 oracle on C1 (8^3, N=7, 10 steps): the error
     metrics of the paper (Sec. 4.2 equations) stay inside the stated bounds:
