@@ -64,11 +64,17 @@ ax_kernel(Batch bt, AxLaunch a)
     __shared__ C ss[EPB][L2];
     __shared__ double red[Nthr<LX>::v / 64];
 
-    const int g = blockIdx.x;
+    // Components of one element block run as blocks x, x+8, x+16 of a 1-D
+    // grid: workgroups go round-robin over the 8 XCDs, so those land on the
+    // same XCD back to back and the geometric factors the components share
+    // are read from HBM once and from that XCD's L2 after.
+    const int bx = blockIdx.x;
+    const int comp = (bx / 8) % a.ncomp;
+    const int g = (bx / (8 * a.ncomp)) * 8 + (bx & 7);
+    if (g >= bt.eb[bt.n]) return;
     const int ri = find_req(bt.eb, bt.n, g);
     const ReqDesc* R = bt.r[ri];
     const int blk = g - bt.eb[ri];
-    const int comp = blockIdx.y;
     if (!gate_ok(R, a.gate < 0 ? -1 : a.gate + comp)) return;
 
     const int t = threadIdx.x;
@@ -227,7 +233,8 @@ ax_kernel(Batch bt, AxLaunch a)
 template <int LX, typename TU, typename TG, typename C>
 static void ax_go(const Batch& b, const AxLaunch& a, hipStream_t s)
 {
-    dim3 grid(b.eb[b.n], a.ncomp);
+    // 1-D grid: groups of 8 element blocks, each group once per component
+    dim3 grid(((b.eb[b.n] + 7) / 8) * 8 * a.ncomp);
     if constexpr (sizeof(TU) == 4) {
         // the Arnoldi operator of an fp32-stored GMRES basis: Jacobi scaling on
         // load and an fp64 output
@@ -284,8 +291,10 @@ static void ax_lx(const Batch& b, const AxLaunch& a, hipStream_t s)
     else if (u == PBF && g == PBF && c == P32) ax_go<LX, __hip_bfloat16, __hip_bfloat16, float>(b, a, s);
 }
 
-void launch_ax(const Batch& b, int lx, const AxLaunch& a, hipStream_t s)
+void launch_ax(const Batch& b, int lx, const AxLaunch& a0, hipStream_t s)
 {
+    AxLaunch a = a0;
+    if (a.ncomp < 1) a.ncomp = 1;
     switch (lx) {
     case 3: ax_lx<3>(b, a, s); break;
     case 4: ax_lx<4>(b, a, s); break;
