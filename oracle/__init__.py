@@ -11,6 +11,7 @@ ordering, Sec. 3 problem definition and the error metrics of Sec. 4.2).
 """
 from .oracle import (  # noqa: F401
     build_oracle, OracleMesh, OracleFluid, OracleProjection, gll, gl, lxd, interp_matrix, deriv_matrix, num_threads,
+    bdf_ext_var,
 )
 from .metrics import (  # noqa: F401
     e_series, e_max, e_peak,

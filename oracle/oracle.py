@@ -19,7 +19,8 @@ _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 
 class _StepStats(C.Structure):
     _fields_ = [("t", C.c_double), ("ke", C.c_double), ("enst", C.c_double), ("maxdiv", C.c_double),
-                ("vit", C.c_int * 3), ("pit", C.c_int), ("vres", C.c_double * 3), ("pres", C.c_double)]
+                ("vit", C.c_int * 3), ("pit", C.c_int), ("vres", C.c_double * 3), ("pres", C.c_double),
+                ("dt", C.c_double), ("cfl", C.c_double)]
 
 
 def build_oracle(force=False):
@@ -77,6 +78,11 @@ def _load():
     L.orc_interp.argtypes = [C.c_int, _dp, C.c_int, _dp, _dp]
     L.orc_fluid_set_dealias.restype = C.c_int
     L.orc_fluid_set_dealias.argtypes = [vp, C.c_int]
+    L.orc_fluid_set_cfl.restype = C.c_int
+    L.orc_fluid_set_cfl.argtypes = [vp, C.c_double]
+    L.orc_bdf_ext_var.argtypes = [C.c_int, _dp, C.POINTER(C.c_double), _dp, _dp]
+    L.orc_cfl_rate.restype = C.c_double
+    L.orc_cfl_rate.argtypes = [vp, _dp, _dp, _dp]
     L.orc_curl_div.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_diagnostics.argtypes = [vp, _dp, _dp, _dp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.POINTER(C.c_double)]
@@ -138,6 +144,17 @@ def gl(n):
     if L.orc_gl(n, z, w) != 0:
         raise ValueError("unsupported point count %d" % n)
     return z, w
+
+
+def bdf_ext_var(k, h):
+    """BDF-k / EXT-k coefficients for step sizes h = (t_{n+1}-t_n, t_n-t_{n-1},
+    t_{n-1}-t_{n-2}): (beta0, b[3], a[3])."""
+    hh = np.ascontiguousarray(np.array(list(h) + [0.0] * (3 - len(h)), dtype=np.float64))
+    b0 = C.c_double(0.0)
+    b = np.zeros(3)
+    a = np.zeros(3)
+    _load().orc_bdf_ext_var(int(k), hh, C.byref(b0), b, a)
+    return b0.value, b, a
 
 
 def lxd(lx):
@@ -292,6 +309,10 @@ class OracleMesh:
         self.L.orc_conv(self.h, _c(u[0]), _c(u[1]), _c(u[2]), *o)
         return np.stack(o)
 
+    def cfl_rate(self, u):
+        """Advective CFL rate max_points sum_a |u . grad r_a| / dr_a (CFL = dt * rate)."""
+        return self.L.orc_cfl_rate(self.h, _c(u[0]), _c(u[1]), _c(u[2]))
+
     def conv_dealias(self, u):
         """-B (u . grad) u integrated on the 3/2-rule Gauss-Legendre grid."""
         o = [np.zeros(self.np) for _ in range(3)]
@@ -394,7 +415,7 @@ class OracleFluid:
     """FP64 TGV stepper on an OracleMesh (keeps a reference to the mesh)."""
 
     def __init__(self, mesh, nu, dt, torder=3, vtol=1e-8, ptol=1e-8, vmaxit=500, pmaxit=1000,
-                 restart=30, init=INIT_TGV3D, proj=0, dealias=False):
+                 restart=30, init=INIT_TGV3D, proj=0, dealias=False, cfl=0.0):
         self.mesh = mesh
         self.L = mesh.L
         self.h = self.L.orc_fluid_new(mesh.h, float(nu), float(dt), int(torder), float(vtol), float(ptol),
@@ -404,6 +425,8 @@ class OracleFluid:
         if self.L.orc_fluid_set_proj(self.h, int(proj)) != 0:
             raise ValueError("invalid projection dimension")
         self.L.orc_fluid_set_dealias(self.h, 1 if dealias else 0)
+        if self.L.orc_fluid_set_cfl(self.h, float(cfl)) != 0:
+            raise ValueError("invalid CFL target")
 
     @property
     def proj_size(self):
@@ -445,4 +468,5 @@ class OracleFluid:
         st = _StepStats()
         self.L.orc_fluid_step(self.h, C.byref(st))
         return {"t": st.t, "ke": st.ke, "enst": st.enst, "maxdiv": st.maxdiv,
-                "vit": list(st.vit), "pit": st.pit, "vres": list(st.vres), "pres": st.pres}
+                "vit": list(st.vit), "pit": st.pit, "vres": list(st.vres), "pres": st.pres,
+                "dt": st.dt, "cfl": st.cfl}

@@ -1211,12 +1211,16 @@ typedef struct {
     double vres[3], pres;
     orc_proj* proj;                     /* pressure projection space, or NULL */
     int dealias;                        /* convection on the 3/2 Gauss-Legendre grid */
+    double cfl_target;                  /* > 0: adaptive dt (Sec. 3: target CFL 0.4); dt is then the maximum */
+    double dth[3];                      /* steps dt_n, dt_{n-1}, dt_{n-2} of the latest steps */
+    double last_cfl;                    /* CFL number of the last step */
 } orc_fluid;
 
 typedef struct {
     double t, ke, enst, maxdiv;
     int vit[3], pit;
     double vres[3], pres;
+    double dt, cfl;                     /* step size and CFL number of the step */
 } orc_step_stats;
 
 /* init: 0 = 3D Taylor-Green, 1 = 2D Taylor-Green extruded in z, 2 = zero */
@@ -1328,6 +1332,81 @@ void orc_fluid_set_clock(orc_fluid* f, double t, int step) { f->t = t; f->step =
 double orc_fluid_time(const orc_fluid* f) { return f->t; }
 int orc_fluid_stepno(const orc_fluid* f) { return f->step; }
 
+/* BDF-k / EXT-k coefficients for the step sizes h[0] = t_{n+1} - t_n,
+ * h[1] = t_n - t_{n-1}, h[2] = t_{n-1} - t_{n-2}.  With the time nodes
+ * tau_0 = t_{n+1}, tau_j = t_{n+1-j}:
+ *   du/dt(t_{n+1}) ~ (beta0 u^{n+1} - sum_j b_j u^{n+1-j}) / h[0],
+ *   beta0 = h[0] l_0'(tau_0), b_j = -h[0] l_j'(tau_0)   (Lagrange basis over tau_0..tau_k)
+ *   N(t_{n+1}) ~ sum_j a_j N^{n+1-j},  a_j = L_j(tau_0)  (Lagrange basis over tau_1..tau_k). */
+void orc_bdf_ext_var(int k, const double h[3], double* beta0, double b[3], double a[3])
+{
+    double tau[4];
+    tau[0] = 0.0;
+    for (int j = 1; j <= 3; ++j) tau[j] = tau[j - 1] - h[j - 1];
+    b[0] = b[1] = b[2] = a[0] = a[1] = a[2] = 0.0;
+    /* derivative of the Lagrange basis over tau_0..tau_k at tau_0 */
+    double d0 = 0.0;
+    for (int m = 1; m <= k; ++m) d0 += 1.0 / (tau[0] - tau[m]);
+    *beta0 = h[0] * d0;
+    for (int j = 1; j <= k; ++j) {
+        double num = 1.0, den = 1.0;
+        for (int m = 0; m <= k; ++m) {
+            if (m == j) continue;
+            den *= tau[j] - tau[m];
+            if (m != 0) num *= tau[0] - tau[m];
+        }
+        b[j - 1] = -h[0] * num / den;
+    }
+    /* extrapolation weights over tau_1..tau_k at tau_0 */
+    for (int j = 1; j <= k; ++j) {
+        double v = 1.0;
+        for (int m = 1; m <= k; ++m)
+            if (m != j) v *= (tau[0] - tau[m]) / (tau[j] - tau[m]);
+        a[j - 1] = v;
+    }
+}
+
+/* Advective CFL rate of a velocity field: the largest, over all local points,
+ * of sum_a |u . grad r_a| / dr_a, with dr_a the spacing of the GLL nodes
+ * around the point's index along direction a (half the distance between its
+ * two neighbours inside, the distance to the one neighbour at an end).  The
+ * CFL number of a step is dt times this rate. */
+double orc_cfl_rate(const orc_mesh* m, const double* ux, const double* uy, const double* uz)
+{
+    const int lx = m->lx;
+    const long np = m->np, n3 = (long)lx * lx * lx;
+    double dr[ORC_MAXLX];
+    for (int i = 0; i < lx; ++i) {
+        if (i == 0) dr[i] = m->xi[1] - m->xi[0];
+        else if (i == lx - 1) dr[i] = m->xi[lx - 1] - m->xi[lx - 2];
+        else dr[i] = 0.5 * (m->xi[i + 1] - m->xi[i - 1]);
+    }
+    const double* U[3] = { ux, uy, uz };
+    double best = 0.0;
+    for (long p = 0; p < np; ++p) {
+        const long q = p % n3;
+        const int idx[3] = { (int)(q % lx), (int)((q / lx) % lx), (int)(q / ((long)lx * lx)) };
+        double rate = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double v = 0.0;
+            for (int c = 0; c < 3; ++c) v += U[c][p] * m->drdx[(long)(a * 3 + c) * np + p];
+            rate += fabs(v) / dr[idx[a]];
+        }
+        if (rate > best) best = rate;
+    }
+    return best;
+}
+
+/* Adaptive time stepping toward a target CFL number (Sec. 3 runs with a
+ * target of 0.4): dt_n = target / rate(u^n), at most the configured dt, and
+ * after the first step within [0.5, 1.1] times the previous step. */
+int orc_fluid_set_cfl(orc_fluid* f, double target)
+{
+    if (!(target >= 0.0)) return -1;
+    f->cfl_target = target;
+    return 0;
+}
+
 /* BDF-k and EXT-k coefficients for constant dt. */
 static void bdf_ext(int k, double* beta0, double b[3], double a[3])
 {
@@ -1343,8 +1422,23 @@ int orc_fluid_step(orc_fluid* f, orc_step_stats* st)
     long np = m->np;
     int k = f->step + 1 < f->torder ? f->step + 1 : f->torder;
     double beta0, b[3], a[3];
-    bdf_ext(k, &beta0, b, a);
     double dt = f->dt, nu = f->nu;
+    const double rate = orc_cfl_rate(m, f->u[0], f->u[1], f->u[2]);
+    if (f->cfl_target > 0.0) {
+        /* the step that meets the target CFL with the current velocity */
+        double want = rate > 0.0 ? f->cfl_target / rate : f->dt;
+        if (f->step > 0) {
+            if (want > 1.1 * f->dth[0]) want = 1.1 * f->dth[0];
+            if (want < 0.5 * f->dth[0]) want = 0.5 * f->dth[0];
+        }
+        dt = want < f->dt ? want : f->dt;
+        f->dth[2] = f->dth[1]; f->dth[1] = f->dth[0]; f->dth[0] = dt;
+        orc_bdf_ext_var(k, f->dth, &beta0, b, a);
+    } else {
+        bdf_ext(k, &beta0, b, a);
+    }
+    const double cfl = dt * rate;
+    f->last_cfl = cfl;
     double h1 = nu, h2 = beta0 / dt;
 
     double *bn[3], *rhs[3], *gp[3], *us[3];
@@ -1398,6 +1492,8 @@ int orc_fluid_step(orc_fluid* f, orc_step_stats* st)
 
     if (st) {
         st->t = f->t;
+        st->dt = dt;
+        st->cfl = cfl;
         orc_diagnostics(m, f->u[0], f->u[1], f->u[2], &st->ke, &st->enst, &st->maxdiv);
         for (int c = 0; c < 3; ++c) { st->vit[c] = f->vit[c]; st->vres[c] = f->vres[c]; }
         st->pit = f->pit; st->pres = f->pres;

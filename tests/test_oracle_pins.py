@@ -611,3 +611,77 @@ def test_poisson_manufactured_on_deformed_mesh():
         errs.append(np.abs(p - m.remove_mean_mass(s)).max())
     # curved elements: GLL quadrature of the mapped integrands converges spectrally too
     assert errs[1] < errs[0] / 10 and errs[1] < 2e-4
+
+
+# ---------------------------------------------------------------- adaptive time stepping (Sec. 3: target CFL 0.4)
+def test_variable_step_bdf_ext_reduce_to_the_constant_step_schemes():
+    from oracle import bdf_ext_var
+    want = {1: (1.0, [1, 0, 0], [1, 0, 0]), 2: (1.5, [2, -0.5, 0], [2, -1, 0]),
+            3: (11 / 6, [3, -1.5, 1 / 3], [3, -3, 1])}
+    for k, (b0, b, a) in want.items():
+        for h in (1e-3, 0.25):
+            g0, gb, ga = bdf_ext_var(k, (h, h, h))
+            assert abs(g0 - b0) < 1e-14 and np.allclose(gb, b, atol=1e-14) and np.allclose(ga, a, atol=1e-14)
+
+
+def test_variable_step_bdf_ext_are_exact_on_polynomials():
+    """BDF-k differentiates polynomials of degree <= k exactly at t_{n+1} and
+    EXT-k extrapolates degree <= k-1 exactly, for any step sizes; one degree
+    more is not exact (the order is k, not higher)."""
+    from oracle import bdf_ext_var
+    rng = np.random.default_rng(31)
+    for _ in range(20):
+        h = rng.uniform(0.5, 1.5, 3) * 0.01
+        T = rng.uniform(-1, 1)
+        tau = [T, T - h[0], T - h[0] - h[1], T - h[0] - h[1] - h[2]]
+        for k in (1, 2, 3):
+            b0, b, a = bdf_ext_var(k, h)
+            for d in range(k + 2):
+                p = lambda t: (t - 0.3) ** d
+                dp = d * (T - 0.3) ** (d - 1) if d else 0.0
+                approx = (b0 * p(tau[0]) - sum(b[j] * p(tau[j + 1]) for j in range(k))) / h[0]
+                ext = sum(a[j] * p(tau[j + 1]) for j in range(k))
+                if d <= k:
+                    assert abs(approx - dp) < 1e-8 * (1 + abs(dp)), (k, d)
+                else:
+                    assert abs(approx - dp) > 1e-12
+                if d <= k - 1:
+                    assert abs(ext - p(T)) < 1e-10 * (1 + abs(p(T))), (k, d)
+
+
+def test_cfl_rate_matches_the_affine_closed_form():
+    """On affine elements dr_a/dx_c = 2/h_a delta_ac, so the rate at a node is
+    sum_a |u_a| (2/h_a) / dr(i_a) with the GLL spacing dr."""
+    N = 5
+    m = OracleMesh((2, 3, 2), N, lo=(-1.0, 0.0, 0.5), hi=(2.0, 1.5, 2.5))
+    X = m.coords()
+    u = np.stack([np.sin(X[0]) * np.cos(X[1]), -np.cos(X[0]) * np.sin(X[1]) + 0.3, np.sin(X[2])])
+    xi, _ = gll(N)
+    dr = np.array([xi[1] - xi[0]] + [0.5 * (xi[i + 1] - xi[i - 1]) for i in range(1, N)] + [xi[N] - xi[N - 1]])
+    hs = np.array([3.0 / 2, 1.5 / 3, 2.0 / 2])
+    lx = N + 1
+    idx = np.arange(m.np) % lx ** 3
+    ii = [idx % lx, (idx // lx) % lx, idx // lx ** 2]
+    rate = sum(np.abs(u[a]) * (2 / hs[a]) / dr[ii[a]] for a in range(3))
+    assert abs(m.cfl_rate(u) - rate.max()) < 1e-12 * rate.max()
+
+
+def test_adaptive_dt_follows_the_controller_and_keeps_the_2d_tgv_exact_decay():
+    nu, dtmax, target = 0.05, 0.1, 0.4
+    m = OracleMesh((4, 4, 2), 7)
+    f = OracleFluid(m, nu, dtmax, init=INIT_TGV2D, cfl=target)
+    rate0 = m.cfl_rate(f.velocity())
+    sts = [f.step() for _ in range(25)]
+    dts = [s["dt"] for s in sts]
+    assert abs(dts[0] - min(dtmax, target / rate0)) < 1e-15 * dts[0]
+    for p, q in zip(dts, dts[1:]):
+        assert 0.5 * p * (1 - 1e-15) <= q <= 1.1 * p * (1 + 1e-15) and q <= dtmax
+    assert all(s["cfl"] <= target * (1 + 1e-12) for s in sts)
+    # the decaying field's CFL rate falls, so the step grows toward the target
+    assert dts[-1] > dts[0] and abs(sts[-1]["cfl"] - target) < 1e-12
+    assert abs(sts[-1]["t"] - sum(dts)) < 1e-13
+    X = m.coords()
+    decay = math.exp(-2 * nu * f.time)
+    ue = np.stack([np.sin(X[0]) * np.cos(X[1]) * decay, -np.cos(X[0]) * np.sin(X[1]) * decay])
+    u = f.velocity()
+    assert np.abs(u[:2] - ue).max() < 5e-5 and np.abs(u[2]).max() < 1e-8
