@@ -123,6 +123,12 @@ typedef struct {
                                         instead of by collocation on the GLL points; fluid mode only.
                                         Adds 9 E ceil(3 lx/2)^3 fp64 metric terms, plus a copy in the conv
                                         storage precision when that is fp32 or 16-bit (element-scaled). */
+    double cfl_target;               /* > 0: adaptive time stepping toward this CFL number (Sec. 3 uses
+                                        0.4; fluid mode): each step takes dt_n = cfl_target / rate(u^n),
+                                        at most dt, and after the first step within [0.5, 1.1] dt_{n-1};
+                                        rate(u) = max over local points of sum_a |u . grad r_a| / dr_a
+                                        (dr: local GLL spacing); BDF/EXT use the variable-step
+                                        coefficients.  0: fixed dt. */
 } sem_flow_desc;
 
 #define SEM_MAX_PROJ 20
@@ -137,6 +143,7 @@ typedef struct {
     double vel_res[3], pres_res;     /* final residual norms */
     int status;                      /* SEM_OK, SEM_ENAN or SEM_ENOTCONV */
     int vel_cycles;                  /* velocity solve cycles (fp64 residual checks after the first) */
+    double dt, cfl;                  /* step size and CFL number (dt * rate(u^n)) of the step */
 } sem_step_stats;
 
 typedef struct {

@@ -284,10 +284,12 @@ static __device__ __noinline__ void fin_body(ReqDesc* R, int ri, const FinArgs a
         double ke = slot_sum(R, R_X0, red);
         double en = slot_sum(R, R_X1, red);
         double md = slot_max(R, R_X2, red);
+        double cr = slot_max(R, R_X4, red);
         if (t == 0) {
             S[S_KE] = ke / S[S_VOL];
             S[S_ENST] = en / S[S_VOL];
             S[S_MAXDIV] = md;
+            S[S_CFLR] = cr;
             if (!finite(ke) || !finite(en)) I[I_NAN] = 1;
         }
         break;
@@ -298,9 +300,50 @@ static __device__ __noinline__ void fin_body(ReqDesc* R, int ri, const FinArgs a
             const int k = I[I_STEP] + 1 < torder ? I[I_STEP] + 1 : torder;
             I[I_ORDER] = k;
             double b0, b1 = 0, b2 = 0, b3 = 0, a1 = 0, a2 = 0, a3 = 0;
-            if (k == 1) { b0 = 1.0; b1 = 1.0; a1 = 1.0; }
+            const double rate = S[S_CFLR];
+            if (S[S_CFLT] > 0.0) {
+                // adaptive step toward the target CFL, at most the configured dt,
+                // and after the first step within [0.5, 1.1] of the previous one
+                double dt = rate > 0.0 ? S[S_CFLT] / rate : S[S_DTMAX];
+                if (I[I_STEP] > 0) {
+                    const double prev = S[S_DTH];
+                    if (dt > 1.1 * prev) dt = 1.1 * prev;
+                    if (dt < 0.5 * prev) dt = 0.5 * prev;
+                }
+                if (dt > S[S_DTMAX]) dt = S[S_DTMAX];
+                S[S_DTH + 2] = S[S_DTH + 1];
+                S[S_DTH + 1] = S[S_DTH];
+                S[S_DTH] = dt;
+                S[S_DT] = dt;
+                // BDF-k: derivative at t_{n+1} of the interpolant through the
+                // last k+1 time levels; EXT-k: its value from the last k levels
+                // (nodes measured back from t_{n+1}: 0, -h0, -h0-h1, -h0-h1-h2)
+                double z[4];
+                z[0] = 0.0;
+                for (int q = 1; q < 4; ++q) z[q] = z[q - 1] - S[S_DTH + q - 1];
+                double bb[4] = {0, 0, 0, 0}, aa[4] = {0, 0, 0, 0};
+                double s0 = 0.0;
+                for (int q = 1; q <= k; ++q) s0 += 1.0 / (z[0] - z[q]);
+                bb[0] = dt * s0;
+                for (int j = 1; j <= k; ++j) {
+                    double nu_ = 1.0, de = 1.0, w = 1.0;
+                    for (int q = 0; q <= k; ++q) {
+                        if (q == j) continue;
+                        de *= z[j] - z[q];
+                        if (q != 0) {
+                            nu_ *= z[0] - z[q];
+                            w *= (z[0] - z[q]) / (z[j] - z[q]);
+                        }
+                    }
+                    bb[j] = -dt * nu_ / de;
+                    aa[j] = w;
+                }
+                b0 = bb[0]; b1 = bb[1]; b2 = bb[2]; b3 = bb[3];
+                a1 = aa[1]; a2 = aa[2]; a3 = aa[3];
+            } else if (k == 1) { b0 = 1.0; b1 = 1.0; a1 = 1.0; }
             else if (k == 2) { b0 = 1.5; b1 = 2.0; b2 = -0.5; a1 = 2.0; a2 = -1.0; }
             else { b0 = 11.0 / 6.0; b1 = 3.0; b2 = -1.5; b3 = 1.0 / 3.0; a1 = 3.0; a2 = -3.0; a3 = 1.0; }
+            S[S_CFL] = S[S_DT] * rate;
             S[S_BETA0] = b0;
             S[S_BDF] = b1; S[S_BDF + 1] = b2; S[S_BDF + 2] = b3;
             S[S_EXT] = a1; S[S_EXT + 1] = a2; S[S_EXT + 2] = a3;
@@ -359,6 +402,7 @@ static __device__ __noinline__ void fin_body(ReqDesc* R, int ri, const FinArgs a
             o[14] = I[I_VREF] > I[I_VREF + 1] ? I[I_VREF] : I[I_VREF + 1];
             if (I[I_VREF + 2] > o[14]) o[14] = I[I_VREF + 2];
             o[15] = I[I_ORDER];
+            o[16] = S[S_DT]; o[17] = S[S_CFL];
         }
         break;
     }

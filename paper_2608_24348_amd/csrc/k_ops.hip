@@ -214,6 +214,14 @@ __global__ void __launch_bounds__(ONthr<LX>::v) diagnostics_kernel(Batch bt)
     load_D<LX, double>(R, sD);
     const SEM_GLOBAL double* M = gfield<double>(R, F_M64);
     const SEM_GLOBAL double* B = gfield<double>(R, F_B64);
+    // 1 / (GLL spacing around each index): half the distance between the two
+    // neighbours inside, the distance to the one neighbour at an end
+    __shared__ double sidr[LX];
+    if (t < LX) {
+        const SEM_GLOBAL double* xi = gp(R->D64) + LX * LX + LX;
+        const double d = t == 0 ? xi[1] - xi[0] : t == LX - 1 ? xi[LX - 1] - xi[LX - 2] : 0.5 * (xi[t + 1] - xi[t - 1]);
+        sidr[t] = 1.0 / d;
+    }
     double col[3][LX];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -221,7 +229,7 @@ __global__ void __launch_bounds__(ONthr<LX>::v) diagnostics_kernel(Batch bt)
 #pragma unroll
         for (int k = 0; k < LX; ++k) col[c][k] = u[ebase + k * L2 + ij];
     }
-    double ke = 0, en = 0, md = 0;
+    double ke = 0, en = 0, md = 0, cr = 0;
     block_sync_lds();
 #pragma unroll
     for (int k = 0; k < LX; ++k) {
@@ -257,23 +265,37 @@ __global__ void __launch_bounds__(ONthr<LX>::v) diagnostics_kernel(Batch bt)
             ke += bm * 0.5 * (col[0][k] * col[0][k] + col[1][k] * col[1][k] + col[2][k] * col[2][k]);
             en += bm * 0.5 * (wx * wx + wy * wy + wz * wz);
             md = fmax(md, fabs(dv));
+            // advective CFL rate: sum_a |u . grad r_a| / dr_a, grad r_a = M_a. / B
+            const int ia[3] = {i, j, k};
+            double rate = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double ua = (col[0][k] * m[a * 3 + 0] + col[1][k] * m[a * 3 + 1] + col[2][k] * m[a * 3 + 2]) / bm;
+                rate += fabs(ua) * sidr[ia[a]];
+            }
+            cr = fmax(cr, rate);
         }
         block_sync_lds();
     }
     double v[2] = {ke, en};
     block_sum<double, 2>(v, red);
     md = wave_max(md);
-    __shared__ double mred[ONthr<LX>::v / 64];
-    if ((t & 63) == 0) mred[t >> 6] = md;
+    cr = wave_max(cr);
+    __shared__ double mred[ONthr<LX>::v / 64][2];
+    if ((t & 63) == 0) { mred[t >> 6][0] = md; mred[t >> 6][1] = cr; }
     block_sync_lds();
     if (t == 0) {
-        double m = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, mred[w]);
+        double m = 0, c = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { m = fmax(m, mred[w][0]); c = fmax(c, mred[w][1]); }
         SEM_GLOBAL double* part = gp(R->part);
         part[(long long)R_X0 * R->pstride + blk] = v[0];
         part[(long long)R_X1 * R->pstride + blk] = v[1];
         part[(long long)R_X2 * R->pstride + blk] = m;
-        if (blk == 0) { gp(R->I)[I_PCNT + R_X0] = R->nb; gp(R->I)[I_PCNT + R_X1] = R->nb; gp(R->I)[I_PCNT + R_X2] = R->nb; }
+        part[(long long)R_X4 * R->pstride + blk] = c;
+        if (blk == 0) {
+            gp(R->I)[I_PCNT + R_X0] = R->nb; gp(R->I)[I_PCNT + R_X1] = R->nb; gp(R->I)[I_PCNT + R_X2] = R->nb;
+            gp(R->I)[I_PCNT + R_X4] = R->nb;
+        }
     }
 }
 

@@ -896,10 +896,14 @@ int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_pr
         if (flow->init < SEM_INIT_ZERO || flow->init > SEM_INIT_TGV2D) return fail(SEM_EINVAL, "bad init");
         if (flow->proj_dim < 0 || flow->proj_dim > SEM_MAX_PROJ) return fail(SEM_EINVAL, "proj_dim must be 0..20");
         if (flow->dealias != 0 && flow->dealias != 1) return fail(SEM_EINVAL, "dealias must be 0 or 1");
+        if (!(flow->cfl_target >= 0.0) || !std::isfinite(flow->cfl_target))
+            return fail(SEM_EINVAL, "cfl_target must be finite and >= 0");
     } else if (flow->proj_dim != 0) {
         return fail(SEM_EINVAL, "proj_dim applies to the fluid mode only");
     } else if (flow->dealias != 0) {
         return fail(SEM_EINVAL, "dealias applies to the fluid mode only");
+    } else if (flow->cfl_target != 0.0) {
+        return fail(SEM_EINVAL, "cfl_target applies to the fluid mode only");
     }
     Resolved rs;
     int rc = resolve_policy(prec, rs);
@@ -1020,6 +1024,8 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     std::vector<int> I(NINT, 0);
     S[S_NU] = c->flow.nu;
     S[S_DT] = c->flow.dt;
+    S[S_DTMAX] = c->flow.dt;
+    S[S_CFLT] = c->flow.mode == SEM_MODE_FLUID ? c->flow.cfl_target : 0.0;
     S[S_VTOL] = c->flow.vel_tol;
     S[S_PTOL] = c->flow.pres_tol;
     S[S_H1] = 1.0;
@@ -1066,6 +1072,9 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
         convection(b, c, s);
         vec(b, V_COPY, 3, P64, -1, s, F_BN, F_BNL1);
         vec(b, V_COPY, 3, P64, -1, s, F_BN, F_BNL2);
+        // diagnostics of the initial field (also its CFL rate for the first step)
+        launch_diagnostics(b, c->lx, s);
+        fin(b, FIN_DIAG, s);
         rc = check_hip_last();
         if (rc) return rc;
     }
@@ -1176,6 +1185,8 @@ static int check_batch(sem_ctx* const* ctxs, int n, int min_mode)
             return fail(SEM_EINVAL, "batched contexts must share the projection dimension");
         if (ctxs[i]->flow.dealias != ctxs[0]->flow.dealias)
             return fail(SEM_EINVAL, "batched contexts must share the dealiasing setting");
+        if ((ctxs[i]->flow.cfl_target > 0.0) != (ctxs[0]->flow.cfl_target > 0.0))
+            return fail(SEM_EINVAL, "batched contexts must all use fixed or all adaptive dt");
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(SEM_EINVAL, "a context appears twice in a batch");
     }
@@ -1205,6 +1216,11 @@ int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stat
     double* hs = stats_buffer();
     if (!hs) return fail(SEM_EHIP, "pinned statistics buffer allocation failed");
     int status = 0;
+    if (c0->flow.cfl_target > 0.0 && nsteps > 0) {
+        // the CFL rate of the current velocity (it may have been set since the last step)
+        launch_diagnostics(b, lx, s);
+        fin(b, FIN_DIAG, s);
+    }
     for (int st = 0; st < nsteps; ++st) {
         fin(b, FIN_STEP_BEGIN, s);
         vec(b, V_IDV, 1, P64, I_IDVSTALE, s);
@@ -1259,6 +1275,8 @@ int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stat
                 ss.pres_res = o[11];
                 ss.status = sti;
                 ss.vel_cycles = (int)o[14];
+                ss.dt = o[16];
+                ss.cfl = o[17];
             }
             c->pred_v = std::max(1, (int)std::max(o[4], std::max(o[5], o[6])));
             c->pred_p = std::max(1, (int)o[10]);
@@ -1503,6 +1521,9 @@ int sem_copy_state(sem_ctx* dst, sem_ctx* src)
     // clock and step (the BDF/EXT order ramp follows the step count); the
     // projection space starts empty in the new tier
     HIPCHK(hipMemcpyAsync(dst->hdesc.S + S_TIME, src->hdesc.S + S_TIME, sizeof(double), hipMemcpyDeviceToDevice,
+                          dst->stream));
+    // step-size history (variable-step BDF/EXT under adaptive dt)
+    HIPCHK(hipMemcpyAsync(dst->hdesc.S + S_DTH, src->hdesc.S + S_DTH, 3 * sizeof(double), hipMemcpyDeviceToDevice,
                           dst->stream));
     HIPCHK(hipMemcpyAsync(dst->hdesc.I + I_STEP, src->hdesc.I + I_STEP, sizeof(int), hipMemcpyDeviceToDevice,
                           dst->stream));

@@ -111,6 +111,11 @@ enum ScalarId : int {
     S_PRS = S_PRB + SEM_MAX_PROJ,   // SEM_MAX_PROJ: 1/||X_i||_A of the stored projection vectors
     S_GVS = S_PRS + SEM_MAX_PROJ,   // m+1: 1/norm of the stored (unnormalised) basis vectors V_i
     S_GMEAN = S_GVS + SEM_MAXM + 1,  // unique-node mean of the current Arnoldi operator output
+    S_CFLT,                     // target CFL number (> 0: adaptive dt)
+    S_DTMAX,                    // largest step (the configured dt)
+    S_DTH,                      // 3: step sizes dt_n, dt_{n-1}, dt_{n-2}
+    S_CFLR = S_DTH + 3,         // CFL rate of the current velocity (from the diagnostics kernel)
+    S_CFL,                      // CFL number of the current step
     S_RED,                      // generic finalised reductions (SEM_NRED values)
     NSCALAR = S_RED + 64
 };
@@ -124,6 +129,7 @@ enum RedSlot : int {
     R_GN = R_GM + SEM_MAXM + 1, // GMRES norm
     R_GMEAN,                    // GMRES operator-output unique sum (null-space deflation)
     R_X0, R_X1, R_X2, R_X3,     // diagnostics and means
+    R_X4,                       // CFL rate (max)
     NRED
 };
 
@@ -323,7 +329,7 @@ enum FinOp : int {
     NFINOP
 };
 
-#define SEM_NSTAT 16
+#define SEM_NSTAT 18
 
 struct FinArgs {
     int op, gate, ncomp, f0;

@@ -55,13 +55,14 @@ class FlowDesc(C.Structure):
                 ("torder", C.c_int), ("vel_tol", C.c_double), ("pres_tol", C.c_double),
                 ("vel_maxit", C.c_int), ("pres_maxit", C.c_int), ("gmres_restart", C.c_int),
                 ("vel_max_refine", C.c_int), ("init", C.c_int), ("proj_dim", C.c_int),
-                ("dealias", C.c_int)]
+                ("dealias", C.c_int), ("cfl_target", C.c_double)]
 
 
 class StepStats(C.Structure):
     _fields_ = [("t", C.c_double), ("ke", C.c_double), ("enst", C.c_double), ("maxdiv", C.c_double),
                 ("vel_iters", C.c_int * 3), ("pres_iters", C.c_int), ("vel_res", C.c_double * 3),
-                ("pres_res", C.c_double), ("status", C.c_int), ("vel_cycles", C.c_int)]
+                ("pres_res", C.c_double), ("status", C.c_int), ("vel_cycles", C.c_int), ("dt", C.c_double),
+                ("cfl", C.c_double)]
 
 
 class SolveStats(C.Structure):
@@ -213,7 +214,7 @@ def mesh_desc(nel, order, lo=(-math.pi,) * 3, hi=(math.pi,) * 3, amp=0.0, phase=
 
 
 def flow_desc(mode=MODE_FLUID, nu=1.0 / 1600, dt=1e-3, torder=3, vel_tol=1e-8, pres_tol=1e-8, vel_maxit=500,
-              pres_maxit=1000, restart=30, max_refine=8, init=INIT_TGV3D, proj=0, dealias=0):
+              pres_maxit=1000, restart=30, max_refine=8, init=INIT_TGV3D, proj=0, dealias=0, cfl=0.0):
     f = FlowDesc()
     f.size = C.sizeof(FlowDesc)
     f.mode = mode
@@ -229,6 +230,7 @@ def flow_desc(mode=MODE_FLUID, nu=1.0 / 1600, dt=1e-3, torder=3, vel_tol=1e-8, p
     f.init = init
     f.proj_dim = proj
     f.dealias = int(dealias)
+    f.cfl_target = float(cfl)
     return f
 
 
@@ -372,7 +374,7 @@ class Context:
 def _stats_dict(s):
     return {"t": s.t, "ke": s.ke, "enst": s.enst, "maxdiv": s.maxdiv, "vit": list(s.vel_iters),
             "pit": s.pres_iters, "vres": list(s.vel_res), "pres": s.pres_res, "status": s.status,
-            "vcyc": s.vel_cycles}
+            "vcyc": s.vel_cycles, "dt": s.dt, "cfl": s.cfl}
 
 
 def fluid_step(ctxs, nsteps=1):

@@ -337,6 +337,51 @@ def test_fluid_dealiased_c1_matches_oracle(sem):
     assert _rel(c.velocity(), f.velocity()) < 1e-8
 
 
+def test_fluid_adaptive_cfl_c1_matches_oracle(sem):
+    """Adaptive time stepping toward CFL 0.4 (Sec. 3) on C1 (8^3, N = 7, 10
+    steps, tolerances 1e-8): every step size agrees with the oracle's to 1e-9
+    relative (a step is the target over a maximum of velocity terms, so it
+    carries the velocity's own parity, ~1e-11; the first step ~1e-14), each
+    CFL number is the target, iteration counts are equal, KE and enstrophy
+    agree to 1e-9, and the clock is the sum of the steps."""
+    nel, N = (8, 8, 8), 7
+    nu, dtmax, target = 1 / 1600, 0.05, 0.4
+    c = _ctx(sem, nel, N, nu=nu, dt=dtmax, cfl=target)
+    m = OracleMesh(nel, N)
+    f = OracleFluid(m, nu, dtmax, init=INIT_TGV3D, cfl=target)
+    gst = sem.fluid_step([c], 10)[0]
+    for k in range(10):
+        o = f.step()
+        g = gst[k]
+        print("step", k + 1, "dt", g["dt"], o["dt"], "cfl", g["cfl"], "its", g["vit"], g["pit"], o["vit"], o["pit"])
+        assert g["status"] == 0
+        assert abs(g["dt"] - o["dt"]) <= (1e-12 if k == 0 else 1e-9) * o["dt"]
+        assert abs(g["cfl"] - o["cfl"]) <= 1e-12
+        assert g["vit"] == o["vit"] and g["pit"] == o["pit"]
+        assert abs(g["ke"] - o["ke"]) <= 1e-9 * o["ke"]
+        assert abs(g["enst"] - o["enst"]) <= 1e-9 * o["enst"]
+    assert abs(gst[-1]["t"] - sum(s["dt"] for s in gst)) < 1e-13
+    assert gst[0]["dt"] < dtmax and abs(gst[0]["cfl"] - target) < 1e-12
+    assert _rel(c.velocity(), f.velocity()) < 1e-8
+
+
+def test_batched_adaptive_dt_is_bitwise_equal_to_alone(sem):
+    """Each request of a batch keeps its own step size under adaptive dt."""
+    specs = [((4, 4, 4), 7, 1 / 400), ((2, 2, 4), 7, 1 / 100)]
+    alone = []
+    for nel, N, nu in specs:
+        c = _ctx(sem, nel, N, nu=nu, dt=0.05, cfl=0.4)
+        st = sem.fluid_step([c], 4)[0]
+        alone.append((st, c.velocity()))
+    ctxs = [_ctx(sem, nel, N, nu=nu, dt=0.05, cfl=0.4) for nel, N, nu in specs]
+    mix = sem.fluid_step(ctxs, 4)
+    for i, c in enumerate(ctxs):
+        st, u = alone[i]
+        assert [s["dt"] for s in mix[i]] == [s["dt"] for s in st]
+        assert np.array_equal(c.velocity(), u)
+    assert mix[0][0]["dt"] != mix[1][0]["dt"]
+
+
 @pytest.mark.parametrize("proj,dealias", [(0, 0), (3, 0), (0, 1)])
 def test_batched_step_is_bitwise_equal_to_alone(sem, proj, dealias):
     # with a 3-vector projection space, 5 steps include a full-space restart

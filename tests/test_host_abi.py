@@ -87,7 +87,8 @@ def test_policy_rules():
 def test_flow_validation():
     md = sem.mesh_desc((2, 2, 2), 4)
     for kw in (dict(nu=0.0), dict(dt=-1.0), dict(torder=4), dict(restart=31), dict(vel_tol=0.0), dict(max_refine=0),
-               dict(proj=-1), dict(proj=21), dict(mode=sem.MODE_POISSON, proj=5)):
+               dict(proj=-1), dict(proj=21), dict(mode=sem.MODE_POISSON, proj=5), dict(cfl=-0.1),
+               dict(cfl=float("inf")), dict(cfl=float("nan")), dict(mode=sem.MODE_POISSON, cfl=0.4)):
         with pytest.raises(sem.SemError):
             sem.Context(md, sem.flow_desc(**kw), sem.tier("fp64"), bind=False)
 
