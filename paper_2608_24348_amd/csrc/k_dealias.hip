@@ -194,8 +194,22 @@ __global__ void __launch_bounds__(256) dealias_cast_kernel(Batch bt, int per_ele
             __syncthreads();
             const double sc = mx > 0 ? exp2(ceil(log2(mx))) : 1.0;
             if (threadIdx.x == 0) gfieldw<float>(R, F_MFDSC)[e] = (float)sc;
-            SEM_GLOBAL T16* dst = gfieldw<T16>(R, F_MFD16) + (long long)e * per_elem;
-            for (int p = threadIdx.x; p < per_elem; p += blockDim.x) stg(dst + p, to<T16>(me[p] / sc));
+            const int lx = R->lx;
+            const int per16 = dl16_per_elem(lx);
+            SEM_GLOBAL T16* dst = gfieldw<T16>(R, F_MFD16) + (long long)e * per16;
+            if (dl16_lane(lx)) {
+                // [tile][ac][g][m][r]: fine point (k' = 4g + r, n = 16 tile + m); zero outside
+                const int nd = (3 * lx + 1) / 2, nn = nd * nd, ng = (nd + 3) / 4;
+                for (int p = threadIdx.x; p < per16; p += blockDim.x) {
+                    const int r = p & 3, m = (p >> 2) & 15, rest = p >> 6;
+                    const int g = rest % ng, ac = (rest / ng) % 9, tile = rest / (ng * 9);
+                    const int kk = 4 * g + r, n = 16 * tile + m;
+                    const double v = (kk < nd && n < nn) ? me[(long long)ac * nd * nn + kk * nn + n] / sc : 0.0;
+                    stg(dst + p, to<T16>(v));
+                }
+            } else {
+                for (int p = threadIdx.x; p < per_elem; p += blockDim.x) stg(dst + p, to<T16>(me[p] / sc));
+            }
         }
     }
 }
@@ -752,10 +766,33 @@ __global__ void __launch_bounds__((Dv2<LX, C>::NT), (Dv2<LX, C>::WPE)) conv_deal
                 qoff[r] = (kk < LXD ? kk : LXD - 1) * NN + (n < NN ? n : NN - 1);
             }
             C mf[9][4];
+            if constexpr (sizeof(TM) == 2) {
+                // lane-ordered 16-bit terms: four rows of one term in one 8-byte load
+                static_assert(dl16_lane(LX), "lane-ordered 16-bit metric layout");
+                constexpr int NG = (LXD + 3) / 4;
+                const SEM_GLOBAL TM* m16 = MF + (long long)e * dl16_per_elem(LX) + (long long)tn * 9 * NG * 64;
+                // row groups past the fine grid (g >= NG) read the last group
+                // instead: unconditional loads, and those rows are never stored
+                const int gg = g < NG ? g : NG - 1;
+                unsigned long long raw[9];
 #pragma unroll
-            for (int ac = 0; ac < 9; ++ac)
+                for (int ac = 0; ac < 9; ++ac)
+                    raw[ac] = *(const SEM_GLOBAL unsigned long long*)(m16 + (ac * NG + gg) * 64 + m * 4);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) mf[ac][r] = mload<TM, C>(me + ac * ND3 + qoff[r], msc);
+                for (int ac = 0; ac < 9; ++ac)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const unsigned short hb = (unsigned short)((raw[ac] >> (16 * r)) & 0xffff);
+                        TM hv;
+                        __builtin_memcpy(&hv, &hb, 2);
+                        mf[ac][r] = to<C>(hv) * msc;
+                    }
+            } else {
+#pragma unroll
+                for (int ac = 0; ac < 9; ++ac)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) mf[ac][r] = mload<TM, C>(me + ac * ND3 + qoff[r], msc);
+            }
             const C* y2 = sY2 + g * NN + n;
             V4 V[3];
 #pragma unroll

@@ -495,7 +495,7 @@ void build_layout(sem_ctx* c)
             field(F_MFD64, 8 * nf);
             if (r.conv_m == P32) field(F_MFD32, 4 * nf);
             if (r.conv_m == P16 || r.conv_m == PBF) {
-                field(F_MFD16, 2 * nf);
+                field(F_MFD16, 2 * (size_t)c->E * dl16_per_elem(c->lx));
                 field(F_MFDSC, 4 * (size_t)c->E);
             }
         }

@@ -201,6 +201,16 @@ struct Batch {
     const ReqDesc* r[SEM_MAXB];
 };
 
+// 16-bit fine-grid metric terms of the dealiased convection: lane-ordered for
+// the matrix-core kernel (lx <= 10), per element [tile][ac][g][m][r] with
+// r fastest (one 8-byte load per lane and term), else natural [ac][point]
+__host__ __device__ constexpr int dl16_lane(int lx) { return lx <= 10 ? 1 : 0; }
+__host__ __device__ constexpr int dl16_per_elem(int lx)
+{
+    return dl16_lane(lx) ? (((3 * lx + 1) / 2) * ((3 * lx + 1) / 2) + 15) / 16 * 9 * (((3 * lx + 1) / 2 + 3) / 4) * 64
+                         : 9 * ((3 * lx + 1) / 2) * ((3 * lx + 1) / 2) * ((3 * lx + 1) / 2);
+}
+
 // elements per workgroup of the element kernels (shared by host and device)
 __host__ __device__ constexpr int epb_of(int lx)
 {
