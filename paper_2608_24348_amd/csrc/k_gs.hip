@@ -28,20 +28,29 @@ __device__ __forceinline__ void gs_chunk(const ReqDesc* R, int field, int gate, 
 #pragma unroll
         for (int m = 0; m < M; ++m) id[q][m] = idx[base + m];
     }
+    // every component's gathers are issued before any scatter (a store may
+    // alias a later component's loads in the compiler's view, which would
+    // otherwise serialise the components)
+    T v[NC][TPT][M];
+    bool on[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        if (!gate_ok(R, gate < 0 ? -1 : gate + c)) continue;
-        SEM_GLOBAL T* u = field >= 0 ? gfieldw<T>(R, field + c) : gp((T*)raw);
-        T v[TPT][M];
+        on[c] = gate_ok(R, gate < 0 ? -1 : gate + c);
+        const SEM_GLOBAL T* u = field >= 0 ? gfield<T>(R, field + c) : gp((const T*)raw);
 #pragma unroll
         for (int q = 0; q < TPT; ++q)
 #pragma unroll
-            for (int m = 0; m < M; ++m) v[q][m] = ldg(u + id[q][m]);
+            for (int m = 0; m < M; ++m) v[c][q][m] = ldg(u + id[q][m]);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (!on[c]) continue;
+        SEM_GLOBAL T* u = field >= 0 ? gfieldw<T>(R, field + c) : gp((T*)raw);
 #pragma unroll
         for (int q = 0; q < TPT; ++q) {
             A s = (A)0;
 #pragma unroll
-            for (int m = 0; m < M; ++m) s += to<A>(v[q][m]);
+            for (int m = 0; m < M; ++m) s += to<A>(v[c][q][m]);
             const T r = to<T>(s);
             if (own[q]) {
 #pragma unroll
