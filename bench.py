@@ -207,14 +207,17 @@ def roofline(kind, tier, prof, steps, npts, workload, N=7, dealias=0):
     tot_ms, nlaunch = prof
     bv = _basis_bytes(tier)
     if kind == "ax_resid":
-        # fp64 velocity residual operator R_L = RHS_L - H_L u (3 components,
-        # Helmholtz: u, RHS_L, w, 6 G, B = 80 B/point each): per step one check
-        # before the solve and, with fp32 vectors, one after every cycle
+        # fp64 velocity residual operator R_L = RHS_L - H_L u for the three
+        # components in one launch: the least the launch must move is u, RHS_L
+        # and w of each component plus the 6 G and B the components share,
+        # 16 values = 128 B/point (three separate applications would be
+        # 3 x 80); per step one check before the solve and, with fp32
+        # vectors, one after every cycle
         alg = 0.0
         active = 0
         for s in steps:
             nv = 1 + (s["vcyc"] if tier != "fp64" else 0)
-            alg += nv * 3 * npts * 80
+            alg += nv * npts * 128
             active += nv
         name = "ax_kernel<8, double, double, double, 0, double, 1> -- fp64 velocity residual RHS_L - H_L u"
     elif kind == "ax_presid":

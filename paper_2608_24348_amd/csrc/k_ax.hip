@@ -135,11 +135,6 @@ ax_kernel(Batch bt, AxLaunch a)
 #pragma unroll
         for (int k = 0; k < LX; ++k) praw[k] = ldg(pcv + ebase + k * L2 + ij);
     }
-    if constexpr (SUB != 0) {
-        const SEM_GLOBAL TW* rl = gfield<TW>(R, a.sub + comp);
-#pragma unroll
-        for (int k = 0; k < LX; ++k) rraw[k] = ldg(rl + ebase + k * L2 + ij);
-    }
     if (helm) {
 #pragma unroll
         for (int k = 0; k < LX; ++k) braw[k] = ldg(Bm + ebase + k * L2 + ij);
@@ -208,6 +203,14 @@ ax_kernel(Batch bt, AxLaunch a)
         }
     }
 
+    // the local rhs of the residual form is loaded only now: it is needed at
+    // the store, and holding it through the k-walk would cost the registers
+    // of a second wave per SIMD
+    if constexpr (SUB != 0) {
+        const SEM_GLOBAL TW* rl = gfield<TW>(R, a.sub + comp);
+#pragma unroll
+        for (int k = 0; k < LX; ++k) rraw[k] = ldg(rl + ebase + k * L2 + ij);
+    }
     double dot = 0.0;
     if (live) {
 #pragma unroll
