@@ -53,7 +53,7 @@ class Server:
     """Runs a list of request specs (see inputs.request_stream) to completion."""
 
     def __init__(self, budget_bytes=None, max_batch=16, gmres_chunk=30, device="cuda:0", vel_tol=1e-6,
-                 pres_tol=1e-4, poisson_tol=1e-8, keep_fields=False):
+                 pres_tol=1e-4, poisson_tol=1e-8, keep_fields=False, policy="rr", tgv_steps=1):
         import torch
         self.torch = torch
         self.device = device
@@ -70,6 +70,12 @@ class Server:
         self.pres_tol = pres_tol
         self.poisson_tol = poisson_tol  # Poisson requests
         self.keep_fields = keep_fields
+        # next batch key: "rr" round robin over keys with work, "oldest" the key
+        # holding the longest-waiting active request
+        if policy not in ("rr", "oldest"):
+            raise ValueError("policy must be 'rr' or 'oldest'")
+        self.policy = policy
+        self.tgv_steps = max(1, int(tgv_steps))  # fluid steps per round of a TGV batch
         self.used = 0
 
     # ---------------------------------------------------------------- request life cycle
@@ -151,22 +157,30 @@ class Server:
                 if pending:
                     time.sleep(max(0.0, min(0.05, pending[0].spec["arrival"] - (time.perf_counter() - t0))))
                 continue
-            # next batch key with work (round robin)
-            while not active.get(keys_rr[0]):
+            if self.policy == "oldest":
+                key = min((k for k, v in active.items() if v), key=lambda k: active[k][0].t_arrival)
+            else:
+                # next batch key with work (round robin)
+                while not active.get(keys_rr[0]):
+                    keys_rr.rotate(-1)
+                key = keys_rr[0]
                 keys_rr.rotate(-1)
-            key = keys_rr[0]
-            keys_rr.rotate(-1)
             batch = active[key][:self.max_batch]
             ctxs = [r.ctx for r in batch]
             rounds += 1
             if key[2] == "tgv":
-                st = sem.fluid_step(ctxs, 1)
+                # as many steps as the batch's requests all still need, at most tgv_steps
+                k = min([self.tgv_steps] + [r.spec["steps"] - r.steps_done for r in batch])
+                st = sem.fluid_step(ctxs, k)
                 now = time.perf_counter() - t0
-                for r, s in zip(batch, st):
-                    s = s[0]
-                    r.steps_done += 1
-                    r.stats.append(s)
-                    r.ops += sum(s["vit"]) + s["pit"] + (6 if r.spec["tier"] != "fp64" else 3) + 1
+                for r, ss in zip(batch, st):
+                    bad = 0
+                    for s in ss:
+                        r.steps_done += 1
+                        r.stats.append(s)
+                        r.ops += sum(s["vit"]) + s["pit"] + (6 if r.spec["tier"] != "fp64" else 3) + 1
+                        bad = bad or s["status"]
+                    s = {"status": bad}
                     if s["status"] != 0 or r.steps_done >= r.spec["steps"]:
                         self._retire(r, now, "ok" if s["status"] == 0 else "status%d" % s["status"])
                         active[key].remove(r)
@@ -203,20 +217,20 @@ def summarize(done, makespan):
     return out
 
 
-def measure(n_requests=256, seed=24348, loads=(0.4, 0.7, 1.0), max_batch=16, log=None):
+def measure(n_requests=256, seed=24348, loads=(0.4, 0.7, 1.0), max_batch=16, log=None, **server_kw):
     """Serving measurement: a burst of the whole stream (all requests at t = 0)
     gives the saturated request rate; the same stream is then replayed with
     Poisson arrivals at each fraction of that rate."""
     from . import inputs
     out = {"requests": n_requests, "seed": seed}
     burst = inputs.request_stream(n_requests=n_requests, qps=1e12, seed=seed)
-    done, ms = Server(max_batch=max_batch).run(burst, log=log)
+    done, ms = Server(max_batch=max_batch, **server_kw).run(burst, log=log)
     sat = summarize(done, ms)
     out["saturated"] = sat
     for f in loads:
         qps = f * sat["requests_per_s"]
         specs = inputs.request_stream(n_requests=n_requests, qps=qps, seed=seed)
-        done, ms = Server(max_batch=max_batch).run(specs, log=log)
+        done, ms = Server(max_batch=max_batch, **server_kw).run(specs, log=log)
         out["load_%.1f" % f] = dict(summarize(done, ms), qps=qps)
     return out
 
