@@ -174,12 +174,14 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         const double a1 = S[S_EXT], a2 = S[S_EXT + 1], a3 = S[S_EXT + 2];
         const double b1 = S[S_BDF], b2 = S[S_BDF + 1], b3 = S[S_BDF + 2];
         const double idt = 1.0 / S[S_DT];
+        // the lags are read once per step: streaming loads keep them from
+        // evicting the fields the following kernels read again
         for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
             const double bi = B[p] * idt;
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                const double ext = a1 * bn0[q][p] + a2 * bn1[q][p] + a3 * bn2[q][p];
-                const double hist = b1 * u0[q][p] + b2 * u1[q][p] + b3 * u2[q][p];
+                const double ext = a1 * bn0[q][p] + a2 * ldg_stream(bn1[q] + p) + a3 * ldg_stream(bn2[q] + p);
+                const double hist = b1 * u0[q][p] + b2 * ldg_stream(u1[q] + p) + b3 * ldg_stream(u2[q] + p);
                 rhs[q][p] = ext + bi * hist - gpr[q][p];
             }
         }
