@@ -365,6 +365,30 @@ def test_fluid_adaptive_cfl_c1_matches_oracle(sem):
     assert _rel(c.velocity(), f.velocity()) < 1e-8
 
 
+def test_paper_solver_settings_match_oracle(sem):
+    """The solver settings of Sec. 3 together: dealiased convection, adaptive dt
+    toward CFL 0.4, pressure projection space of dimension 20 (4^3 elements,
+    N = 7, 8 steps, tolerances 1e-8).  Velocity iteration counts equal,
+    pressure counts within 1 (the projected guess carries earlier rounding),
+    step sizes within 1e-9, KE and enstrophy within 1e-9."""
+    nel, N = (4, 4, 4), 7
+    nu, dtmax, target = 1 / 1600, 0.05, 0.4
+    c = _ctx(sem, nel, N, nu=nu, dt=dtmax, cfl=target, dealias=1, proj=20)
+    m = OracleMesh(nel, N)
+    f = OracleFluid(m, nu, dtmax, init=INIT_TGV3D, cfl=target, dealias=True, proj=20)
+    gst = sem.fluid_step([c], 8)[0]
+    for k in range(8):
+        o = f.step()
+        g = gst[k]
+        assert g["status"] == 0
+        assert g["vit"] == o["vit"] and abs(g["pit"] - o["pit"]) <= 1, (k, g, o)
+        assert abs(g["dt"] - o["dt"]) <= 1e-9 * o["dt"]
+        assert abs(g["ke"] - o["ke"]) <= 1e-9 * o["ke"]
+        assert abs(g["enst"] - o["enst"]) <= 1e-9 * o["enst"]
+    assert f.proj_size > 0
+    assert _rel(c.velocity(), f.velocity()) < 1e-8
+
+
 def test_batched_adaptive_dt_is_bitwise_equal_to_alone(sem):
     """Each request of a batch keeps its own step size under adaptive dt."""
     specs = [((4, 4, 4), 7, 1 / 400), ((2, 2, 4), 7, 1 / 100)]
