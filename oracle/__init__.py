@@ -10,7 +10,7 @@ mathematics is stated (textbook SEM on GLL points; the paper's Fig. 3 step
 ordering, Sec. 3 problem definition and the error metrics of Sec. 4.2).
 """
 from .oracle import (  # noqa: F401
-    build_oracle, OracleMesh, OracleFluid, OracleProjection, gll, gl, lxd, interp_matrix, deriv_matrix, num_threads,
+    build_oracle, OracleMesh, OracleFluid, OracleProjection, OracleHSMG, gll, gl, lxd, interp_matrix, deriv_matrix, num_threads,
     bdf_ext_var,
 )
 from .metrics import (  # noqa: F401

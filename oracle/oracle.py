@@ -128,6 +128,25 @@ def _load():
     L.orc_poisson_proj.restype = C.c_int
     L.orc_poisson_proj.argtypes = [vp, vp, _dp, _dp, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_double)]
     L.orc_num_threads.restype = C.c_int
+    L.orc_hsmg_new.restype = vp
+    L.orc_hsmg_new.argtypes = [vp]
+    L.orc_hsmg_free.argtypes = [vp]
+    L.orc_hsmg_level.restype = C.c_int
+    L.orc_hsmg_level.argtypes = [vp, C.c_int, C.c_int, _dp, _dp, _dp, _dp]
+    for f in ("orc_hsmg_local_solve", "orc_hsmg_smooth"):
+        getattr(L, f).argtypes = [vp, C.c_int, _dp, _dp]
+    for f in ("orc_hsmg_coarse_solve", "orc_hsmg_prolong_fm", "orc_hsmg_restrict_mf", "orc_hsmg_restrict_cm",
+              "orc_hsmg_prolong_mc", "orc_hsmg_apply"):
+        getattr(L, f).argtypes = [vp, _dp, _dp]
+    for f in ("orc_hsmg_nm", "orc_hsmg_nc"):
+        getattr(L, f).restype = C.c_long
+        getattr(L, f).argtypes = [vp]
+    L.orc_hsmg_lxm.restype = C.c_int
+    L.orc_hsmg_lxm.argtypes = [vp]
+    L.orc_poisson_pc.restype = C.c_int
+    L.orc_poisson_pc.argtypes = [vp, vp, _dp, _dp, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_double)]
+    L.orc_fluid_set_hsmg.restype = C.c_int
+    L.orc_fluid_set_hsmg.argtypes = [vp, C.c_int]
     _lib = L
     return L
 
@@ -407,6 +426,78 @@ class OracleProjection:
         return p, it, res.value
 
 
+class OracleHSMG:
+    """Three-level hybrid Schwarz multigrid preconditioner of the pressure
+    Poisson operator on an unperturbed periodic OracleMesh with N >= 4
+    (levels N, N/2, 1; Schwarz smoothing by fast diagonalisation on the two
+    upper levels, exact coarse solve).  Vectors: fine level as the mesh's
+    local layout, middle level [E][lxm^3], coarse level on the unique corner
+    nodes cx + nx (cy + ny cz)."""
+
+    def __init__(self, mesh):
+        self.mesh = mesh
+        self.L = mesh.L
+        self.h = self.L.orc_hsmg_new(mesh.h)
+        if not self.h:
+            raise ValueError("HSMG needs an unperturbed box mesh with N >= 4")
+        self.lxm = self.L.orc_hsmg_lxm(self.h)
+        self.nm = self.L.orc_hsmg_nm(self.h)
+        self.nc = self.L.orc_hsmg_nc(self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.L.orc_hsmg_free(self.h)
+            self.h = None
+
+    def level(self, level, c):
+        """1D tables of level 0 (fine) or 1 (middle), direction c: A, diag(B), S, lambda."""
+        lx = self.mesh.lx if level == 0 else self.lxm
+        A = np.zeros(lx * lx); Bd = np.zeros(lx); S = np.zeros(lx * lx); lam = np.zeros(lx)
+        self.L.orc_hsmg_level(self.h, int(level), int(c), A, Bd, S, lam)
+        return A.reshape(lx, lx), Bd, S.reshape(lx, lx), lam
+
+    def local_solve(self, level, r):
+        out = np.zeros(len(r))
+        self.L.orc_hsmg_local_solve(self.h, int(level), _c(r), out)
+        return out
+
+    def smooth(self, level, r):
+        out = np.zeros(len(r))
+        self.L.orc_hsmg_smooth(self.h, int(level), _c(r), out)
+        return out
+
+    def _map(self, fn, x, n):
+        out = np.zeros(n)
+        getattr(self.L, fn)(self.h, _c(x), out)
+        return out
+
+    def coarse_solve(self, rc):
+        return self._map("orc_hsmg_coarse_solve", rc, self.nc)
+
+    def prolong_fm(self, zm):
+        return self._map("orc_hsmg_prolong_fm", zm, self.mesh.np)
+
+    def restrict_mf(self, rf):
+        return self._map("orc_hsmg_restrict_mf", rf, self.nm)
+
+    def restrict_cm(self, rm):
+        return self._map("orc_hsmg_restrict_cm", rm, self.nc)
+
+    def prolong_mc(self, ec):
+        return self._map("orc_hsmg_prolong_mc", ec, self.nm)
+
+    def apply(self, r):
+        return self._map("orc_hsmg_apply", r, self.mesh.np)
+
+    def poisson(self, rhs, tol=1e-8, maxit=1000, restart=30):
+        """HSMG-preconditioned GMRES for A p = rhs, as OracleMesh.poisson."""
+        p = np.zeros(self.mesh.np)
+        res = C.c_double()
+        it = self.L.orc_poisson_pc(self.mesh.h, self.h, _c(rhs), p, float(tol), int(maxit), int(restart),
+                                   C.byref(res))
+        return p, it, res.value
+
+
 INIT_TGV3D, INIT_TGV2D, INIT_ZERO = 0, 1, 2
 FIELD_U, FIELD_P, FIELD_ULAG1, FIELD_ULAG2, FIELD_BNLAG1, FIELD_BNLAG2 = 0, 3, 4, 7, 10, 13
 
@@ -415,7 +506,7 @@ class OracleFluid:
     """FP64 TGV stepper on an OracleMesh (keeps a reference to the mesh)."""
 
     def __init__(self, mesh, nu, dt, torder=3, vtol=1e-8, ptol=1e-8, vmaxit=500, pmaxit=1000,
-                 restart=30, init=INIT_TGV3D, proj=0, dealias=False, cfl=0.0):
+                 restart=30, init=INIT_TGV3D, proj=0, dealias=False, cfl=0.0, hsmg=False):
         self.mesh = mesh
         self.L = mesh.L
         self.h = self.L.orc_fluid_new(mesh.h, float(nu), float(dt), int(torder), float(vtol), float(ptol),
@@ -427,6 +518,8 @@ class OracleFluid:
         self.L.orc_fluid_set_dealias(self.h, 1 if dealias else 0)
         if self.L.orc_fluid_set_cfl(self.h, float(cfl)) != 0:
             raise ValueError("invalid CFL target")
+        if self.L.orc_fluid_set_hsmg(self.h, 1 if hsmg else 0) != 0:
+            raise ValueError("HSMG needs an unperturbed box mesh with N >= 4")
 
     @property
     def proj_size(self):

@@ -961,8 +961,23 @@ int orc_pcg(const orc_mesh* m, double h1, double h2, const double* b, double* x,
  * removed before orthogonalisation: a no-op in exact arithmetic that keeps
  * rounding errors from feeding the constant null direction into the basis.
  * Returns the number of Arnoldi steps; *res = final true residual norm. */
+typedef struct orc_hsmg orc_hsmg;
+void orc_hsmg_apply(const orc_hsmg* H, const double* r, double* z);
+
+/* GMRES right-preconditioned by Jacobi (pc == NULL) or by the HSMG
+ * preconditioner pc (defined further down): z_j = M^{-1} v_j and, at each
+ * cycle end, x += M^{-1} (V y); M^{-1} is linear in both cases. */
+static int gmres_pc(const orc_mesh* m, double h1, double h2, const double* b, double* x,
+                    double tol, int maxit, int mrst, int deflate, const orc_hsmg* pc, double* res, double* hist);
+
 int orc_gmres_ex(const orc_mesh* m, double h1, double h2, const double* b, double* x,
                  double tol, int maxit, int mrst, int deflate, double* res, double* hist)
+{
+    return gmres_pc(m, h1, h2, b, x, tol, maxit, mrst, deflate, NULL, res, hist);
+}
+
+static int gmres_pc(const orc_mesh* m, double h1, double h2, const double* b, double* x,
+                    double tol, int maxit, int mrst, int deflate, const orc_hsmg* pc, double* res, double* hist)
 {
     long np = m->np;
     int mm = mrst;
@@ -988,7 +1003,8 @@ int orc_gmres_ex(const orc_mesh* m, double h1, double h2, const double* b, doubl
         int jend = 0;
         for (int j = 0; j < mm && it < maxit; ++j) {
             double* vj = V + (long)j * np;
-            for (long i = 0; i < np; ++i) z[i] = vj[i] / d[i];
+            if (pc) orc_hsmg_apply(pc, vj, z);
+            else for (long i = 0; i < np; ++i) z[i] = vj[i] / d[i];
             apply_assembled(m, z, w, h1, h2);
             if (deflate) orc_remove_mean_unique(m, w);
             /* classical Gram-Schmidt, twice */
@@ -1035,7 +1051,13 @@ int orc_gmres_ex(const orc_mesh* m, double h1, double h2, const double* b, doubl
         for (long q = 0; q < np; ++q) {
             double s = 0;
             for (int i = 0; i < jend; ++i) s += V[(long)i * np + q] * y[i];
-            x[q] += s / d[q];
+            z[q] = s;
+        }
+        if (pc) {
+            orc_hsmg_apply(pc, z, w);
+            for (long q = 0; q < np; ++q) x[q] += w[q];
+        } else {
+            for (long q = 0; q < np; ++q) x[q] += z[q] / d[q];
         }
     }
     if (res) *res = beta;
@@ -1072,19 +1094,431 @@ void orc_remove_mean_mass(const orc_mesh* m, double* x)
     free(a);
 }
 
+/* ------------------------------------------------------------------ */
+/* Three-level hybrid Schwarz multigrid (HSMG) preconditioner of the   */
+/* pressure Poisson operator.  Sec. 3 names GMRES preconditioned by a  */
+/* three-level HSMG with a coarse-grid solve; it fixes no more than     */
+/* that, so the operator is defined here (after Lottes & Fischer 2005, */
+/* "Hybrid multigrid/Schwarz algorithms for the spectral element       */
+/* method", with the additive form across levels):                     */
+/*                                                                      */
+/*   levels f (order N), m (order N_m = N/2), c (order 1), all on the   */
+/*   same periodic box of equal elements;                               */
+/*   M^{-1} r = S_f r + P_fm ( S_m r_m + P_mc A_c^+ R_cm r_m ),          */
+/*   r_m = R_mf r.                                                       */
+/*                                                                      */
+/* S_l (levels f, m): additive Schwarz on element subdomains: for each   */
+/* element the local problem L_e u = r_e (r_e = the element's copy of    */
+/* the assembled residual) with the separable operator                  */
+/*   L = B_z x B_y x A_x + B_z x A_y x B_x + A_z x B_y x B_x,            */
+/* whose 1D matrices are the element's GLL stiffness and mass, extended  */
+/* by one linear segment of length delta = (h/2)(xi_1 - xi_0) (the gap  */
+/* to the next node inside the neighbour) ending at a zero Dirichlet    */
+/* node on each side:                                                    */
+/*   A = (2/h) D^T W D + (E_00 + E_NN) / delta,                          */
+/*   B = (h/2) W       + (E_00 + E_NN) delta / 2;                        */
+/* solved by fast diagonalisation (A S = B S Lambda, S^T B S = I); the   */
+/* local solutions are summed over element copies (dssum) and weighted  */
+/* by 1/multiplicity.                                                   */
+/* P_fm, P_mc: tensor-product Lagrange interpolation from the coarser    */
+/* level's GLL points to the finer level's, element by element.         */
+/* R = P^T in the unique-node inner product: R r = dssum(P_e^T (r/mult)).*/
+/* A_c^+: exact solve with the assembled order-1 SEM Poisson operator on */
+/* the unique corner nodes, on the complement of the constant vector     */
+/* (periodic: the operator is singular); separable on the box, so it is */
+/* also solved by fast diagonalisation.                                  */
+/* The symmetric eigenproblems use cyclic Jacobi rotations (Golub & Van */
+/* Loan, Sec. 8.5).                                                     */
+/* ------------------------------------------------------------------ */
+
+/* Eigen-decomposition of the symmetric n x n matrix a (destroyed):
+ * a = Q diag(lam) Q^T, Q[i*n + k] = component i of eigenvector k. */
+static void jacobi_eig(int n, double* a, double* Q, double* lam)
+{
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) Q[i * n + k] = i == k ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                tot += a[i * n + k] * a[i * n + k];
+                if (i != k) off += a[i * n + k] * a[i * n + k];
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double apq = a[p * n + q];
+                if (apq == 0.0) continue;
+                double theta = (a[q * n + q] - a[p * n + p]) / (2.0 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < n; ++k) {        /* rows/cols p, q of a */
+                    double akp = a[k * n + p], akq = a[k * n + q];
+                    a[k * n + p] = c * akp - sn * akq;
+                    a[k * n + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double apk = a[p * n + k], aqk = a[q * n + k];
+                    a[p * n + k] = c * apk - sn * aqk;
+                    a[q * n + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double qkp = Q[k * n + p], qkq = Q[k * n + q];
+                    Q[k * n + p] = c * qkp - sn * qkq;
+                    Q[k * n + q] = sn * qkp + c * qkq;
+                }
+            }
+    }
+    for (int i = 0; i < n; ++i) lam[i] = a[i * n + i];
+}
+
+/* Generalised problem A s = lambda B s with B diagonal positive (bd):
+ * S = B^{-1/2} Q with Q the eigenvectors of B^{-1/2} A B^{-1/2}. */
+static void gen_eig_diag(int n, const double* A, const double* bd, double* S, double* lam)
+{
+    double* C = dalloc((long)n * n);
+    double* Q = dalloc((long)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) C[i * n + k] = A[i * n + k] / sqrt(bd[i] * bd[k]);
+    jacobi_eig(n, C, Q, lam);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) S[i * n + k] = Q[i * n + k] / sqrt(bd[i]);
+    free(C); free(Q);
+}
+
+typedef struct {
+    int N, lx;
+    double xi[ORC_MAXLX], w[ORC_MAXLX], D[ORC_MAXLX * ORC_MAXLX];
+    double A[3][ORC_MAXLX * ORC_MAXLX], Bd[3][ORC_MAXLX];   /* local 1D matrices (B diagonal) */
+    double S[3][ORC_MAXLX * ORC_MAXLX], lam[3][ORC_MAXLX];  /* their fast diagonalisation */
+} hs_level;
+
+struct orc_hsmg {
+    const orc_mesh* m;
+    int nel[3], E;
+    hs_level lv[2];                 /* 0 = fine, 1 = middle */
+    double* Jfm;                    /* lx_f x lx_m: fine GLL points from middle Lagrange basis */
+    double* Jmc;                    /* lx_m x 2 */
+    double* Sc[3]; double* lamc[3]; /* coarse 1D periodic fast diagonalisation, n_c x n_c */
+    int c0[3];                      /* index of the constant (zero-eigenvalue) mode per direction */
+    long nm;                        /* middle-level local points E * lx_m^3 */
+    long* gid_m; int* mult_m; long nglob_m;
+    long nc;                        /* unique coarse nodes */
+};
+
+static void hs_level_init(hs_level* L, int N, const double h[3])
+{
+    L->N = N; L->lx = N + 1;
+    int lx = L->lx;
+    orc_gll(N, L->xi, L->w);
+    orc_deriv(N, L->xi, L->D);
+    for (int c = 0; c < 3; ++c) {
+        double delta = 0.5 * h[c] * (L->xi[1] - L->xi[0]);
+        for (int i = 0; i < lx; ++i)
+            for (int j = 0; j < lx; ++j) {
+                double s = 0.0;     /* (D^T W D)_ij */
+                for (int q = 0; q < lx; ++q) s += L->D[q * lx + i] * L->w[q] * L->D[q * lx + j];
+                L->A[c][i * lx + j] = 2.0 / h[c] * s;
+            }
+        for (int i = 0; i < lx; ++i) L->Bd[c][i] = 0.5 * h[c] * L->w[i];
+        L->A[c][0] += 1.0 / delta; L->A[c][N * lx + N] += 1.0 / delta;
+        L->Bd[c][0] += 0.5 * delta; L->Bd[c][N] += 0.5 * delta;
+        gen_eig_diag(lx, L->A[c], L->Bd[c], L->S[c], L->lam[c]);
+    }
+}
+
+orc_hsmg* orc_hsmg_new(const orc_mesh* m)
+{
+    if (m->amp != 0.0 || m->N < 4) return NULL;
+    orc_hsmg* H = (orc_hsmg*)calloc(1, sizeof(orc_hsmg));
+    H->m = m; H->E = m->E;
+    for (int c = 0; c < 3; ++c) H->nel[c] = m->nel[c];
+    hs_level_init(&H->lv[0], m->N, m->h);
+    hs_level_init(&H->lv[1], m->N / 2, m->h);
+    const int lxf = H->lv[0].lx, lxm = H->lv[1].lx;
+    H->Jfm = dalloc((long)lxf * lxm);
+    orc_interp(lxm, H->lv[1].xi, lxf, H->lv[0].xi, H->Jfm);
+    double xc[2] = {-1.0, 1.0};
+    H->Jmc = dalloc((long)lxm * 2);
+    orc_interp(2, xc, lxm, H->lv[1].xi, H->Jmc);
+    /* middle-level periodic numbering */
+    const int Nm = H->lv[1].N;
+    H->nm = (long)m->E * lxm * lxm * lxm;
+    long ngx = (long)m->nel[0] * Nm, ngy = (long)m->nel[1] * Nm, ngz = (long)m->nel[2] * Nm;
+    H->nglob_m = ngx * ngy * ngz;
+    H->gid_m = (long*)calloc((size_t)H->nm, sizeof(long));
+    H->mult_m = (int*)calloc((size_t)H->nm, sizeof(int));
+    for (int ez = 0; ez < m->nel[2]; ++ez)
+    for (int ey = 0; ey < m->nel[1]; ++ey)
+    for (int ex = 0; ex < m->nel[0]; ++ex) {
+        int e = ex + m->nel[0] * (ey + m->nel[1] * ez);
+        for (int k = 0; k < lxm; ++k)
+        for (int j = 0; j < lxm; ++j)
+        for (int i = 0; i < lxm; ++i) {
+            long p = (long)e * lxm * lxm * lxm + i + lxm * (j + lxm * k);
+            long gx = ((long)ex * Nm + i) % ngx, gy = ((long)ey * Nm + j) % ngy, gz = ((long)ez * Nm + k) % ngz;
+            H->gid_m[p] = gx + ngx * (gy + ngy * gz);
+        }
+    }
+    int* cnt = (int*)calloc((size_t)H->nglob_m, sizeof(int));
+    for (long p = 0; p < H->nm; ++p) cnt[H->gid_m[p]]++;
+    for (long p = 0; p < H->nm; ++p) H->mult_m[p] = cnt[H->gid_m[p]];
+    free(cnt);
+    /* coarse 1D periodic operators: element k joins nodes k and k+1 (mod n) */
+    H->nc = (long)m->nel[0] * m->nel[1] * m->nel[2];
+    for (int c = 0; c < 3; ++c) {
+        int n = m->nel[c];
+        double h = m->h[c];
+        double* A = dalloc((long)n * n);
+        double* bd = dalloc(n);
+        for (int k = 0; k < n; ++k) {
+            int a = k, b = (k + 1) % n;
+            A[a * n + a] += 1.0 / h; A[b * n + b] += 1.0 / h;
+            A[a * n + b] -= 1.0 / h; A[b * n + a] -= 1.0 / h;
+            bd[a] += 0.5 * h; bd[b] += 0.5 * h;
+        }
+        H->Sc[c] = dalloc((long)n * n); H->lamc[c] = dalloc(n);
+        gen_eig_diag(n, A, bd, H->Sc[c], H->lamc[c]);
+        int i0 = 0;
+        for (int i = 1; i < n; ++i) if (H->lamc[c][i] < H->lamc[c][i0]) i0 = i;
+        H->c0[c] = i0;
+        free(A); free(bd);
+    }
+    return H;
+}
+
+void orc_hsmg_free(orc_hsmg* H)
+{
+    if (!H) return;
+    free(H->Jfm); free(H->Jmc); free(H->gid_m); free(H->mult_m);
+    for (int c = 0; c < 3; ++c) { free(H->Sc[c]); free(H->lamc[c]); }
+    free(H);
+}
+
+/* 1D tables of one level (0 fine, 1 middle), direction c: A (lx*lx), the
+ * diagonal of B (lx), S (lx*lx), lambda (lx).  Returns lx. */
+int orc_hsmg_level(const orc_hsmg* H, int level, int c, double* A, double* Bd, double* S, double* lam)
+{
+    const hs_level* L = &H->lv[level];
+    int lx = L->lx;
+    if (A) memcpy(A, L->A[c], sizeof(double) * lx * lx);
+    if (Bd) memcpy(Bd, L->Bd[c], sizeof(double) * lx);
+    if (S) memcpy(S, L->S[c], sizeof(double) * lx * lx);
+    if (lam) memcpy(lam, L->lam[c], sizeof(double) * lx);
+    return lx;
+}
+
+/* Local solve u = L^{-1} r of one element at level L (lx^3 values):
+ * u = (S_z x S_y x S_x) diag(1 / (lam_x + lam_y + lam_z)) (S_z x S_y x S_x)^T r. */
+static void hs_local_solve(const hs_level* L, const double* r, double* u)
+{
+    int lx = L->lx;
+    long n3 = (long)lx * lx * lx;
+    double St[3][ORC_MAXLX * ORC_MAXLX];
+    for (int c = 0; c < 3; ++c)
+        for (int i = 0; i < lx; ++i)
+            for (int k = 0; k < lx; ++k) St[c][k * lx + i] = L->S[c][i * lx + k];
+    double* t = dalloc(n3);
+    tensor3(lx, lx, lx, lx, St[0], St[1], St[2], r, t);
+    for (int k = 0; k < lx; ++k)
+        for (int j = 0; j < lx; ++j)
+            for (int i = 0; i < lx; ++i)
+                t[i + lx * (j + lx * k)] /= L->lam[0][i] + L->lam[1][j] + L->lam[2][k];
+    tensor3(lx, lx, lx, lx, L->S[0], L->S[1], L->S[2], t, u);
+    free(t);
+}
+
+void orc_hsmg_local_solve(const orc_hsmg* H, int level, const double* r, double* u)
+{
+    hs_local_solve(&H->lv[level], r, u);
+}
+
+/* Exact coarse solve: rc, ec on the unique corner nodes (cx + nx (cy + ny cz));
+ * the constant mode is dropped. */
+void orc_hsmg_coarse_solve(const orc_hsmg* H, const double* rc, double* ec)
+{
+    const int nx = H->nel[0], ny = H->nel[1], nz = H->nel[2];
+    double* St[3];
+    for (int c = 0; c < 3; ++c) {
+        int n = H->nel[c];
+        St[c] = dalloc((long)n * n);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) St[c][k * n + i] = H->Sc[c][i * n + k];
+    }
+    double* t = dalloc(H->nc);
+    /* tensor3 takes equal input extents; apply the three directions one by one */
+    double* u = dalloc(H->nc);
+    memcpy(u, rc, sizeof(double) * H->nc);
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int dir = 0; dir < 3; ++dir) {
+            const double* Mt = pass == 0 ? St[dir] : H->Sc[dir];
+            int n = H->nel[dir];
+            for (int cz = 0; cz < nz; ++cz)
+            for (int cy = 0; cy < ny; ++cy)
+            for (int cx = 0; cx < nx; ++cx) {
+                int o[3] = {cx, cy, cz};
+                double s = 0.0;
+                for (int a = 0; a < n; ++a) {
+                    int q[3] = {cx, cy, cz};
+                    q[dir] = a;
+                    s += Mt[o[dir] * n + a] * u[q[0] + (long)nx * (q[1] + (long)ny * q[2])];
+                }
+                t[cx + (long)nx * (cy + (long)ny * cz)] = s;
+            }
+            memcpy(u, t, sizeof(double) * H->nc);
+        }
+        if (pass == 0)
+            for (int cz = 0; cz < nz; ++cz)
+            for (int cy = 0; cy < ny; ++cy)
+            for (int cx = 0; cx < nx; ++cx) {
+                long q = cx + (long)nx * (cy + (long)ny * cz);
+                if (cx == H->c0[0] && cy == H->c0[1] && cz == H->c0[2]) u[q] = 0.0;
+                else u[q] /= H->lamc[0][cx] + H->lamc[1][cy] + H->lamc[2][cz];
+            }
+    }
+    memcpy(ec, u, sizeof(double) * H->nc);
+    free(t); free(u);
+    for (int c = 0; c < 3; ++c) free(St[c]);
+}
+
+/* element e's middle-level local block of a middle-level vector */
+#define HSM(H, e) ((long)(e) * (H)->lv[1].lx * (H)->lv[1].lx * (H)->lv[1].lx)
+
+static void dssum_m(const orc_hsmg* H, double* u)
+{
+    double* g = dalloc(H->nglob_m);
+    for (long p = 0; p < H->nm; ++p) g[H->gid_m[p]] += u[p];
+    for (long p = 0; p < H->nm; ++p) u[p] = g[H->gid_m[p]];
+    free(g);
+}
+
+/* prolongation fine <- middle of a continuous middle vector (element by element) */
+void orc_hsmg_prolong_fm(const orc_hsmg* H, const double* zm, double* zf)
+{
+    const int lxf = H->lv[0].lx, lxm = H->lv[1].lx;
+    long nf3 = (long)lxf * lxf * lxf;
+    for (int e = 0; e < H->E; ++e) tensor3(lxm, lxf, lxf, lxf, H->Jfm, H->Jfm, H->Jfm, zm + HSM(H, e), zf + e * nf3);
+}
+
+/* restriction middle <- fine of an assembled fine vector: dssum_m(J^T (r / mult)) */
+void orc_hsmg_restrict_mf(const orc_hsmg* H, const double* rf, double* rm)
+{
+    const orc_mesh* m = H->m;
+    const int lxf = H->lv[0].lx, lxm = H->lv[1].lx;
+    long nf3 = (long)lxf * lxf * lxf;
+    double* Jt = dalloc((long)lxm * lxf);
+    for (int i = 0; i < lxf; ++i)
+        for (int a = 0; a < lxm; ++a) Jt[a * lxf + i] = H->Jfm[i * lxm + a];
+    double* t = dalloc(nf3);
+    for (int e = 0; e < H->E; ++e) {
+        for (long q = 0; q < nf3; ++q) t[q] = rf[e * nf3 + q] / m->mult[e * nf3 + q];
+        tensor3(lxf, lxm, lxm, lxm, Jt, Jt, Jt, t, rm + HSM(H, e));
+    }
+    dssum_m(H, rm);
+    free(Jt); free(t);
+}
+
+/* coarse corner node of element e, corner (a, b, c) in {0,1}^3 */
+static long hs_corner(const orc_hsmg* H, int e, int a, int b, int c)
+{
+    const int nx = H->nel[0], ny = H->nel[1], nz = H->nel[2];
+    int ex = e % nx, ey = (e / nx) % ny, ez = e / (nx * ny);
+    return (ex + a) % nx + (long)nx * ((ey + b) % ny + (long)ny * ((ez + c) % nz));
+}
+
+/* restriction coarse <- middle: rc (unique corner nodes) = sum over elements of J^T (rm / mult_m) */
+void orc_hsmg_restrict_cm(const orc_hsmg* H, const double* rm, double* rc)
+{
+    const int lxm = H->lv[1].lx;
+    long nm3 = (long)lxm * lxm * lxm;
+    double Jt[2 * ORC_MAXLX];
+    for (int i = 0; i < lxm; ++i)
+        for (int a = 0; a < 2; ++a) Jt[a * lxm + i] = H->Jmc[i * 2 + a];
+    double* t = dalloc(nm3);
+    double c8[8];
+    for (long q = 0; q < H->nc; ++q) rc[q] = 0.0;
+    for (int e = 0; e < H->E; ++e) {
+        for (long q = 0; q < nm3; ++q) t[q] = rm[HSM(H, e) + q] / H->mult_m[HSM(H, e) + q];
+        tensor3(lxm, 2, 2, 2, Jt, Jt, Jt, t, c8);
+        for (int c = 0; c < 2; ++c)
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a) rc[hs_corner(H, e, a, b, c)] += c8[a + 2 * (b + 2 * c)];
+    }
+    free(t);
+}
+
+/* prolongation middle <- coarse: trilinear interpolation of the corner values */
+void orc_hsmg_prolong_mc(const orc_hsmg* H, const double* ec, double* zm)
+{
+    for (int e = 0; e < H->E; ++e) {
+        double c8[8];
+        for (int c = 0; c < 2; ++c)
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a) c8[a + 2 * (b + 2 * c)] = ec[hs_corner(H, e, a, b, c)];
+        tensor3(2, H->lv[1].lx, H->lv[1].lx, H->lv[1].lx, H->Jmc, H->Jmc, H->Jmc, c8, zm + HSM(H, e));
+    }
+}
+
+/* Schwarz smoother of one level: W (dssum (local solves of the element copies of r)) */
+static void hs_smooth(const orc_hsmg* H, int level, const double* r, double* z)
+{
+    const hs_level* L = &H->lv[level];
+    long n3 = (long)L->lx * L->lx * L->lx;
+    #pragma omp parallel for
+    for (int e = 0; e < H->E; ++e) hs_local_solve(L, r + e * n3, z + e * n3);
+    if (level == 0) {
+        orc_dssum(H->m, z);
+        for (long p = 0; p < H->m->np; ++p) z[p] /= H->m->mult[p];
+    } else {
+        dssum_m(H, z);
+        for (long p = 0; p < H->nm; ++p) z[p] /= H->mult_m[p];
+    }
+}
+
+void orc_hsmg_smooth(const orc_hsmg* H, int level, const double* r, double* z) { hs_smooth(H, level, r, z); }
+
+/* z = M^{-1} r (r assembled, z continuous) */
+void orc_hsmg_apply(const orc_hsmg* H, const double* r, double* z)
+{
+    const long np = H->m->np, nm = H->nm;
+    double* rm = dalloc(nm); double* zm = dalloc(nm); double* em = dalloc(nm);
+    double* rc = dalloc(H->nc); double* ec = dalloc(H->nc);
+    double* zf = dalloc(np);
+    orc_hsmg_restrict_mf(H, r, rm);
+    orc_hsmg_restrict_cm(H, rm, rc);
+    orc_hsmg_coarse_solve(H, rc, ec);
+    hs_smooth(H, 1, rm, zm);
+    orc_hsmg_prolong_mc(H, ec, em);
+    for (long p = 0; p < nm; ++p) zm[p] += em[p];
+    hs_smooth(H, 0, r, z);
+    orc_hsmg_prolong_fm(H, zm, zf);
+    for (long p = 0; p < np; ++p) z[p] += zf[p];
+    free(rm); free(zm); free(em); free(rc); free(ec); free(zf);
+}
+
+long orc_hsmg_nm(const orc_hsmg* H) { return H->nm; }
+long orc_hsmg_nc(const orc_hsmg* H) { return H->nc; }
+int orc_hsmg_lxm(const orc_hsmg* H) { return H->lv[1].lx; }
+
 /* Periodic Poisson solve A p = rhs (rhs assembled): unique-node mean of the
  * rhs removed, GMRES from zero, mass-weighted mean of p removed. */
-int orc_poisson(const orc_mesh* m, const double* rhs, double* p, double tol, int maxit, int mrst, double* res)
+int orc_poisson_pc(const orc_mesh* m, const orc_hsmg* H, const double* rhs, double* p, double tol, int maxit,
+                   int mrst, double* res)
 {
     long np = m->np;
     double* b = dalloc(np);
     memcpy(b, rhs, np * sizeof(double));
     orc_remove_mean_unique(m, b);
     for (long i = 0; i < np; ++i) p[i] = 0.0;
-    int it = orc_gmres_ex(m, 1.0, 0.0, b, p, tol, maxit, mrst, 1, res, NULL);
+    int it = gmres_pc(m, 1.0, 0.0, b, p, tol, maxit, mrst, 1, H, res, NULL);
     orc_remove_mean_mass(m, p);
     free(b);
     return it;
+}
+
+int orc_poisson(const orc_mesh* m, const double* rhs, double* p, double tol, int maxit, int mrst, double* res)
+{
+    return orc_poisson_pc(m, NULL, rhs, p, tol, maxit, mrst, res);
 }
 
 /* ------------------------------------------------------------------ */
@@ -1177,8 +1611,8 @@ int orc_proj_update(orc_proj* P, const double* x, const double* xbar)
 /* Periodic Poisson solve with projection: unique-node mean of the rhs
  * removed, GMRES from the projected guess, space updated, mass-weighted
  * mean of p removed. */
-int orc_poisson_proj(const orc_mesh* m, orc_proj* P, const double* rhs, double* p, double tol, int maxit,
-                     int mrst, double* res)
+static int poisson_proj(const orc_mesh* m, orc_proj* P, const orc_hsmg* H, const double* rhs, double* p,
+                        double tol, int maxit, int mrst, double* res)
 {
     long np = m->np;
     double* b = dalloc(np); double* xbar = dalloc(np);
@@ -1186,11 +1620,17 @@ int orc_poisson_proj(const orc_mesh* m, orc_proj* P, const double* rhs, double* 
     orc_remove_mean_unique(m, b);
     orc_proj_guess(P, b, xbar);
     memcpy(p, xbar, np * sizeof(double));
-    int it = orc_gmres_ex(m, 1.0, 0.0, b, p, tol, maxit, mrst, 1, res, NULL);
+    int it = gmres_pc(m, 1.0, 0.0, b, p, tol, maxit, mrst, 1, H, res, NULL);
     orc_proj_update(P, p, xbar);
     orc_remove_mean_mass(m, p);
     free(b); free(xbar);
     return it;
+}
+
+int orc_poisson_proj(const orc_mesh* m, orc_proj* P, const double* rhs, double* p, double tol, int maxit,
+                     int mrst, double* res)
+{
+    return poisson_proj(m, P, NULL, rhs, p, tol, maxit, mrst, res);
 }
 
 /* ------------------------------------------------------------------ */
@@ -1214,6 +1654,7 @@ typedef struct {
     double cfl_target;                  /* > 0: adaptive dt (Sec. 3: target CFL 0.4); dt is then the maximum */
     double dth[3];                      /* steps dt_n, dt_{n-1}, dt_{n-2} of the latest steps */
     double last_cfl;                    /* CFL number of the last step */
+    orc_hsmg* hsmg;                     /* pressure preconditioner: HSMG, or NULL for Jacobi */
 } orc_fluid;
 
 typedef struct {
@@ -1275,6 +1716,16 @@ int orc_fluid_set_proj(orc_fluid* f, int L)
 
 int orc_fluid_proj_size(const orc_fluid* f) { return f->proj ? f->proj->l : 0; }
 
+/* pressure preconditioner: 1 = HSMG (needs an unperturbed box and N >= 4), 0 = Jacobi */
+int orc_fluid_set_hsmg(orc_fluid* f, int on)
+{
+    orc_hsmg_free(f->hsmg);
+    f->hsmg = NULL;
+    if (!on) return 0;
+    f->hsmg = orc_hsmg_new(f->m);
+    return f->hsmg ? 0 : -1;
+}
+
 static void fluid_conv(const orc_fluid* f, const double* ux, const double* uy, const double* uz,
                        double* bx, double* by, double* bz)
 {
@@ -1299,6 +1750,7 @@ void orc_fluid_free(orc_fluid* f)
 {
     if (!f) return;
     orc_proj_free(f->proj);
+    orc_hsmg_free(f->hsmg);
     for (int c = 0; c < 3; ++c) { free(f->u[c]); free(f->ul1[c]); free(f->ul2[c]); free(f->bn1[c]); free(f->bn2[c]); }
     free(f->p); free(f);
 }
@@ -1470,8 +1922,8 @@ int orc_fluid_step(orc_fluid* f, orc_step_stats* st)
     orc_wdiv(m, us[0], us[1], us[2], rp);
     orc_dssum(m, rp);
     for (long q = 0; q < np; ++q) rp[q] *= beta0 / dt;
-    if (f->proj) f->pit = orc_poisson_proj(m, f->proj, rp, phi, f->ptol, f->pmaxit, f->mrst, &f->pres);
-    else f->pit = orc_poisson(m, rp, phi, f->ptol, f->pmaxit, f->mrst, &f->pres);
+    if (f->proj) f->pit = poisson_proj(m, f->proj, f->hsmg, rp, phi, f->ptol, f->pmaxit, f->mrst, &f->pres);
+    else f->pit = orc_poisson_pc(m, f->hsmg, rp, phi, f->ptol, f->pmaxit, f->mrst, &f->pres);
     /* (iv) correction u^{n+1} = u* - (dt/beta0) dssum(B grad phi) / Bsum, p += phi */
     orc_opgrad(m, phi, gp[0], gp[1], gp[2]);
     for (int c = 0; c < 3; ++c) orc_dssum(m, gp[c]);
