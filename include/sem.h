@@ -129,6 +129,19 @@ typedef struct {
                                         rate(u) = max over local points of sum_a |u . grad r_a| / dr_a
                                         (dr: local GLL spacing); BDF/EXT use the variable-step
                                         coefficients.  0: fixed dt. */
+    int hsmg;                        /* pressure GMRES preconditioner (Poisson and fluid modes):
+                                        0 = Jacobi (the assembled diagonal);
+                                        1 = three-level hybrid Schwarz multigrid (Sec. 3 names HSMG
+                                        for the pressure): levels of order N, N/2 and 1; additive
+                                        Schwarz on element subdomains (fast diagonalisation of the
+                                        separable element stiffness extended by one segment to a
+                                        zero Dirichlet node) on the two upper levels, Lagrange
+                                        interpolation between levels and its unique-node transpose,
+                                        an exact order-1 coarse solve off the constant mode, the
+                                        levels added (a linear preconditioner).  fp64 arithmetic in
+                                        every tier.  Needs an unperturbed mesh, order 4..11, at
+                                        least 2 elements per direction and an fp64 or fp32 pressure
+                                        basis.  Adds about 3 E lx^3 + 4 E (lx/2)^3 doubles. */
 } sem_flow_desc;
 
 #define SEM_MAX_PROJ 20
@@ -286,7 +299,8 @@ enum {
     SEM_PROF_AX_RESID = 8,    /* fp64 velocity residual operator, RHS_L - H_L u (3 components) */
     SEM_PROF_AX_PRESID = 9,   /* fp64 Poisson operator of the GMRES cycle-end residuals and the
                                  projection update */
-    SEM_PROF_CONV = 10        /* convective term of the fluid step (collocated or dealiased) */
+    SEM_PROF_CONV = 10,       /* convective term of the fluid step (collocated or dealiased) */
+    SEM_PROF_HSMG = 11        /* HSMG preconditioner applications of the Arnoldi steps */
 };
 int sem_prof_start(int kclass);
 int sem_prof_stop(double* total_ms, int64_t* launches);

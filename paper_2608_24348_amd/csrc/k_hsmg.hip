@@ -1,0 +1,474 @@
+// Three-level hybrid Schwarz multigrid (HSMG) preconditioner of the pressure
+// Poisson operator (Sec. 3: the pressure GMRES is preconditioned by a
+// three-level HSMG with a coarse-grid solve).  Periodic box of equal
+// elements; levels of order N (fine), N/2 (middle) and 1 (coarse):
+//
+//   M^{-1} r = S_f r + P_fm ( S_m r_m + P_mc A_c^+ R_cm r_m ),  r_m = R_mf r
+//
+// S_l: additive Schwarz over element subdomains; the local problem is the
+// element's separable stiffness, extended by one linear segment to a zero
+// Dirichlet node on each side, solved by fast diagonalisation
+// (u = S3 diag(1/(lx_i + ly_j + lz_k)) S3^T r); the local solutions of all
+// copies of a node are summed and divided by their number.
+// P: tensor-product Lagrange interpolation between the levels' GLL points;
+// R = P^T in the unique-node inner product (R r = dssum(P_e^T (r / mult))).
+// A_c^+: exact solve of the order-1 operator off the constant mode, by fast
+// diagonalisation on the nx ny nz corner nodes.
+//
+// One apply = 11 launches, every one gated per request:
+//   hs_down   (fine FDM solve -> F_HSF; fine->middle restriction -> F_HRM)
+//   hs_mid    (sum copies of F_HRM; middle FDM -> F_HSM; middle->coarse -> F_HC8)
+//   hs_cgath  (coarse rhs on unique corner nodes -> F_HCA)
+//   hs_cpass  x6 (coarse S^T along x, y, z with the eigenvalue scaling, then S)
+//   hs_midup  (z_m = summed F_HSM / count + trilinear coarse correction -> F_HZM)
+//   hs_up     (z = summed F_HSF / count + J3 z_m -> F_HZ, or added to F_GX)
+// The copy sums use index arithmetic on the periodic box in an order shared
+// by all copies of a node, so every copy receives the identical value.
+#include "k_common.h"
+
+namespace semk {
+
+// the copies of 1D index i of element column ex (n elements, order N):
+// (element, index) pairs, left element first
+struct Cand {
+    int e[2], i[2], n;
+};
+__device__ __forceinline__ Cand cand(int i, int ex, int n, int N)
+{
+    Cand c;
+    if (i == 0) { c.e[0] = ex == 0 ? n - 1 : ex - 1; c.i[0] = N; c.e[1] = ex; c.i[1] = 0; c.n = 2; }
+    else if (i == N) { c.e[0] = ex; c.i[0] = N; c.e[1] = ex + 1 == n ? 0 : ex + 1; c.i[1] = 0; c.n = 2; }
+    else { c.e[0] = ex; c.i[0] = i; c.e[1] = ex; c.i[1] = i; c.n = 1; }
+    return c;
+}
+
+// sum of the copies of node (i,j,k) of element (ex,ey,ez) in the [E][L^3]
+// field f (AVG: divided by their number)
+template <int L, bool AVG = false>
+__device__ __forceinline__ double box_sum(const SEM_GLOBAL double* f, const int* nel, int ex, int ey, int ez,
+                                          int i, int j, int k)
+{
+    constexpr int N = L - 1, L3 = L * L * L;
+    const Cand cx = cand(i, ex, nel[0], N), cy = cand(j, ey, nel[1], N), cz = cand(k, ez, nel[2], N);
+    double s = 0.0;
+    for (int c = 0; c < cz.n; ++c)
+        for (int b = 0; b < cy.n; ++b)
+            for (int a = 0; a < cx.n; ++a) {
+                const long long e = cx.e[a] + (long long)nel[0] * (cy.e[b] + (long long)nel[1] * cz.e[c]);
+                s += f[e * L3 + cx.i[a] + L * (cy.i[b] + L * cz.i[c])];
+            }
+    return AVG ? s / (double)(cx.n * cy.n * cz.n) : s;
+}
+
+__device__ __forceinline__ double inv_mult(int i, int j, int k, int N)
+{
+    const int m = (i == 0 || i == N ? 2 : 1) * (j == 0 || j == N ? 2 : 1) * (k == 0 || k == N ? 2 : 1);
+    return 1.0 / (double)m;
+}
+
+// Fast-diagonalisation solve of one element at order L - 1.  Thread (i, j)
+// of L*L holds column v[k] of the input and receives the column of the
+// solution.  S[c][i*L+k] = component i of eigenvector k, lam[c][k].
+// sA, sB: L^3 LDS scratch; one barrier before the first write.
+template <int L>
+__device__ __forceinline__ void fdm_solve(double (&v)[L], const double* sS, const double* sLam, double* sA,
+                                          double* sB, int i, int j)
+{
+    constexpr int L2 = L * L;
+    const double* Sx = sS;
+    const double* Sy = sS + L2;
+    const double* Sz = sS + 2 * L2;
+    double w[L];
+    // forward, x: w[k] = sum_a Sx[a][i] v(a, j, k)
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < L; ++k) sA[k * L2 + j * L + i] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < L; ++a) s += Sx[a * L + i] * sA[k * L2 + j * L + a];
+        w[k] = s;
+    }
+    // forward, y
+#pragma unroll
+    for (int k = 0; k < L; ++k) sB[k * L2 + j * L + i] = w[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < L; ++b) s += Sy[b * L + j] * sB[k * L2 + b * L + i];
+        v[k] = s;
+    }
+    // forward z, scaling, inverse z (in registers)
+    const double lij = sLam[i] + sLam[L + j];
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < L; ++c) s += Sz[c * L + k] * v[c];
+        w[k] = s / (lij + sLam[2 * L + k]);
+    }
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < L; ++c) s += Sz[k * L + c] * w[c];
+        v[k] = s;
+    }
+    // inverse y (sA was last read before the barrier above)
+#pragma unroll
+    for (int k = 0; k < L; ++k) sA[k * L2 + j * L + i] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < L; ++b) s += Sy[j * L + b] * sA[k * L2 + b * L + i];
+        w[k] = s;
+    }
+    // inverse x
+#pragma unroll
+    for (int k = 0; k < L; ++k) sB[k * L2 + j * L + i] = w[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < L; ++a) s += Sx[i * L + a] * sB[k * L2 + j * L + a];
+        v[k] = s;
+    }
+}
+
+__device__ __forceinline__ void elem_xyz(int e, const int* nel, int& ex, int& ey, int& ez)
+{
+    ex = e % nel[0];
+    const int r = e / nel[0];
+    ey = r % nel[1];
+    ez = r / nel[1];
+}
+
+// ---------------------------------------------------------------- fine level, down
+// MODE 0: r = s_J V_J (basis storage TB); MODE 1: r = F_HT (fp64)
+template <int LX, typename TB, int MODE>
+__global__ void __launch_bounds__(LX * LX) hs_down_kernel(Batch bt, int gate)
+{
+    constexpr int LM = hs_lxm(LX), L2 = LX * LX, L3 = L2 * LX, N = LX - 1;
+    __shared__ double sA[L3], sB[L3];
+    __shared__ double sS[3 * L2], sLam[3 * LX], sJ[LX * LM];
+    const int g = blockIdx.x;
+    const int ri = find_req(bt.el, bt.n, g);
+    const ReqDesc* R = bt.r[ri];
+    const int e = g - bt.el[ri];
+    if (!gate_ok(R, gate)) return;
+    const int t = threadIdx.x, i = t % LX, j = t / LX;
+    const HsOff o = hs_off(LX, R->nel);
+    const SEM_GLOBAL double* tb = gfield<double>(R, F_HST);
+    for (int q = t; q < 3 * L2; q += L2) sS[q] = tb[o.Sf + q];
+    for (int q = t; q < 3 * LX; q += L2) sLam[q] = tb[o.Lf + q];
+    for (int q = t; q < LX * LM; q += L2) sJ[q] = tb[o.J + q];
+
+    const long long base = (long long)e * L3;
+    double v[LX];
+    if constexpr (MODE == 0) {
+        const int J = gp(R->I)[I_GJ];
+        const double sc = gp(R->S)[S_GVS + J];
+        const SEM_GLOBAL TB* V = gfield<TB>(R, F_V) + (long long)J * R->np;
+#pragma unroll
+        for (int k = 0; k < LX; ++k) v[k] = sc * (double)V[base + i + LX * (j + LX * k)];
+    } else {
+        const SEM_GLOBAL double* T = gfield<double>(R, F_HT);
+#pragma unroll
+        for (int k = 0; k < LX; ++k) v[k] = T[base + i + LX * (j + LX * k)];
+    }
+
+    // restriction to the middle level: t = J^T J^T J^T (r / mult)
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < LX; ++k) sA[k * L2 + j * LX + i] = v[k] * inv_mult(i, j, k, N);
+    __syncthreads();
+    if (i < LM) {
+        // x: sB[k][j][a] = sum_q J[q][a] sA[k][j][q], a = i
+#pragma unroll
+        for (int k = 0; k < LX; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < LX; ++q) s += sJ[q * LM + i] * sA[k * L2 + j * LX + q];
+            sB[k * L2 + j * LX + i] = s;
+        }
+    }
+    __syncthreads();
+    if (i < LM && j < LM) {
+        // y then z for output column (a, b) = (i, j)
+        double col[LX];
+#pragma unroll
+        for (int k = 0; k < LX; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < LX; ++q) s += sJ[q * LM + j] * sB[k * L2 + q * LX + i];
+            col[k] = s;
+        }
+        SEM_GLOBAL double* out = gfieldw<double>(R, F_HRM) + (long long)e * LM * LM * LM;
+#pragma unroll
+        for (int c = 0; c < LM; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < LX; ++k) s += sJ[k * LM + c] * col[k];
+            out[i + LM * (j + LM * c)] = s;
+        }
+    }
+    // fine local solve
+    fdm_solve<LX>(v, sS, sLam, sA, sB, i, j);
+    SEM_GLOBAL double* u = gfieldw<double>(R, F_HSF);
+#pragma unroll
+    for (int k = 0; k < LX; ++k) u[base + i + LX * (j + LX * k)] = v[k];
+}
+
+// ---------------------------------------------------------------- middle level, down
+template <int LM>
+__global__ void __launch_bounds__(LM * LM) hs_mid_kernel(Batch bt, int lx, int gate)
+{
+    constexpr int L2 = LM * LM, L3 = L2 * LM, N = LM - 1;
+    __shared__ double sA[L3], sB[L3];
+    __shared__ double sS[3 * L2], sLam[3 * LM], sJc[2 * LM], sC[2 * L2];
+    const int g = blockIdx.x;
+    const int ri = find_req(bt.el, bt.n, g);
+    const ReqDesc* R = bt.r[ri];
+    const int e = g - bt.el[ri];
+    if (!gate_ok(R, gate)) return;
+    const int t = threadIdx.x, i = t % LM, j = t / LM;
+    const HsOff o = hs_off(lx, R->nel);
+    const SEM_GLOBAL double* tb = gfield<double>(R, F_HST);
+    for (int q = t; q < 3 * L2; q += L2) sS[q] = tb[o.Sm + q];
+    for (int q = t; q < 3 * LM; q += L2) sLam[q] = tb[o.Lm + q];
+    for (int q = t; q < 2 * LM; q += L2) sJc[q] = tb[o.Jc + q];
+    __syncthreads();
+    int ex, ey, ez;
+    elem_xyz(e, R->nel, ex, ey, ez);
+    const SEM_GLOBAL double* rm = gfield<double>(R, F_HRM);
+    double v[LM];
+    // the assembled middle residual: sum of the element contributions
+#pragma unroll
+    for (int k = 0; k < LM; ++k) v[k] = box_sum<LM>(rm, R->nel, ex, ey, ez, i, j, k);
+    // coarse restriction of this element: c8 = Jc^T Jc^T Jc^T (r_m / mult)
+    {
+        double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < LM; ++k) {
+            const double x = v[k] * inv_mult(i, j, k, N);
+            c0 += sJc[k * 2 + 0] * x;
+            c1 += sJc[k * 2 + 1] * x;
+        }
+        __syncthreads();
+        sC[0 * L2 + j * LM + i] = c0;
+        sC[1 * L2 + j * LM + i] = c1;
+        __syncthreads();
+        if (t < 8) {
+            const int ca = t & 1, cb = (t >> 1) & 1, cc = t >> 2;
+            double s = 0.0;
+            for (int b = 0; b < LM; ++b)
+                for (int a = 0; a < LM; ++a) s += sJc[a * 2 + ca] * sJc[b * 2 + cb] * sC[cc * L2 + b * LM + a];
+            gfieldw<double>(R, F_HC8)[(long long)e * 8 + t] = s;
+        }
+    }
+    fdm_solve<LM>(v, sS, sLam, sA, sB, i, j);
+    SEM_GLOBAL double* u = gfieldw<double>(R, F_HSM) + (long long)e * L3;
+#pragma unroll
+    for (int k = 0; k < LM; ++k) u[i + LM * (j + LM * k)] = v[k];
+}
+
+// ---------------------------------------------------------------- coarse level
+// unique corner node q = cx + nx (cy + ny cz) gathers the corner
+// contributions of its 8 elements
+__global__ void __launch_bounds__(256) hs_cgath_kernel(Batch bt, int gate)
+{
+    const int ri = blockIdx.y;
+    const ReqDesc* R = bt.r[ri];
+    if (!gate_ok(R, gate)) return;
+    const int nx = R->nel[0], ny = R->nel[1], nz = R->nel[2];
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nx * ny * nz) return;
+    const int cx = q % nx, cy = (q / nx) % ny, cz = q / (nx * ny);
+    const SEM_GLOBAL double* c8 = gfield<double>(R, F_HC8);
+    double s = 0.0;
+    for (int c = 0; c < 2; ++c)
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) {
+                const int ex = (cx - a + nx) % nx, ey = (cy - b + ny) % ny, ez = (cz - c + nz) % nz;
+                s += c8[(long long)(ex + nx * (ey + ny * ez)) * 8 + a + 2 * (b + 2 * c)];
+            }
+    gfieldw<double>(R, F_HCA)[q] = s;
+}
+
+// one direction of the coarse fast diagonalisation: out = S^T in (fwd) or
+// S in along direction dir; fwd with scale also divides by the eigenvalue
+// sum (the constant mode is set to zero)
+__global__ void __launch_bounds__(256) hs_cpass_kernel(Batch bt, int lx, int dir, int fwd, int scale, int src, int dst,
+                                                      int gate)
+{
+    const int ri = blockIdx.y;
+    const ReqDesc* R = bt.r[ri];
+    if (!gate_ok(R, gate)) return;
+    const int nx = R->nel[0], ny = R->nel[1], nz = R->nel[2];
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nx * ny * nz) return;
+    const int c3[3] = {q % nx, (q / nx) % ny, q / (nx * ny)};
+    const HsOff o = hs_off(lx, R->nel);
+    const SEM_GLOBAL double* tb = gfield<double>(R, F_HST);
+    const SEM_GLOBAL double* S = tb + o.Sc[dir];
+    const SEM_GLOBAL double* in = gfield<double>(R, src);
+    const int n = R->nel[dir];
+    const int stride = dir == 0 ? 1 : dir == 1 ? nx : nx * ny;
+    const int me = c3[dir];
+    const long long q0 = q - (long long)me * stride;
+    double s = 0.0;
+    for (int a = 0; a < n; ++a) s += (fwd ? S[a * n + me] : S[me * n + a]) * in[q0 + (long long)a * stride];
+    if (scale) {
+        if (c3[0] == R->hs_c0[0] && c3[1] == R->hs_c0[1] && c3[2] == R->hs_c0[2]) s = 0.0;
+        else s /= tb[o.Lc[0] + c3[0]] + tb[o.Lc[1] + c3[1]] + tb[o.Lc[2] + c3[2]];
+    }
+    gfieldw<double>(R, dst)[q] = s;
+}
+
+// ---------------------------------------------------------------- middle level, up
+template <int LM>
+__global__ void __launch_bounds__(LM * LM) hs_midup_kernel(Batch bt, int lx, int gate)
+{
+    constexpr int L3 = LM * LM * LM;
+    __shared__ double sJc[2 * LM];
+    __shared__ double sE[8];
+    const int g = blockIdx.x;
+    const int ri = find_req(bt.el, bt.n, g);
+    const ReqDesc* R = bt.r[ri];
+    const int e = g - bt.el[ri];
+    if (!gate_ok(R, gate)) return;
+    const int t = threadIdx.x, i = t % LM, j = t / LM;
+    const HsOff o = hs_off(lx, R->nel);
+    const SEM_GLOBAL double* tb = gfield<double>(R, F_HST);
+    for (int q = t; q < 2 * LM; q += LM * LM) sJc[q] = tb[o.Jc + q];
+    int ex, ey, ez;
+    elem_xyz(e, R->nel, ex, ey, ez);
+    const int nx = R->nel[0], ny = R->nel[1], nz = R->nel[2];
+    if (t < 8) {
+        const int a = t & 1, b = (t >> 1) & 1, c = t >> 2;
+        const int cx = (ex + a) % nx, cy = (ey + b) % ny, cz = (ez + c) % nz;
+        sE[t] = gfield<double>(R, F_HCA)[cx + nx * (cy + ny * cz)];
+    }
+    __syncthreads();
+    const SEM_GLOBAL double* sm = gfield<double>(R, F_HSM);
+    SEM_GLOBAL double* zm = gfieldw<double>(R, F_HZM) + (long long)e * L3;
+#pragma unroll
+    for (int k = 0; k < LM; ++k) {
+        double p = 0.0;
+        for (int c = 0; c < 2; ++c)
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a)
+                    p += sE[a + 2 * (b + 2 * c)] * sJc[i * 2 + a] * sJc[j * 2 + b] * sJc[k * 2 + c];
+        zm[i + LM * (j + LM * k)] = box_sum<LM, true>(sm, R->nel, ex, ey, ez, i, j, k) + p;
+    }
+}
+
+// ---------------------------------------------------------------- fine level, up
+// MODE 0: z -> F_HZ (type TZ); MODE 1: F_GX += z
+template <int LX, typename TZ, int MODE>
+__global__ void __launch_bounds__(LX * LX) hs_up_kernel(Batch bt, int gate)
+{
+    constexpr int LM = hs_lxm(LX), L2 = LX * LX, L3 = L2 * LX;
+    __shared__ double sA[LM * LM * LM], sB[LM * LM * LX];
+    __shared__ double sJ[LX * LM];
+    const int g = blockIdx.x;
+    const int ri = find_req(bt.el, bt.n, g);
+    const ReqDesc* R = bt.r[ri];
+    const int e = g - bt.el[ri];
+    if (!gate_ok(R, gate)) return;
+    const int t = threadIdx.x, i = t % LX, j = t / LX;
+    const HsOff o = hs_off(LX, R->nel);
+    const SEM_GLOBAL double* tb = gfield<double>(R, F_HST);
+    for (int q = t; q < LX * LM; q += L2) sJ[q] = tb[o.J + q];
+    const SEM_GLOBAL double* zm = gfield<double>(R, F_HZM) + (long long)e * LM * LM * LM;
+    for (int q = t; q < LM * LM * LM; q += L2) sA[q] = zm[q];
+    __syncthreads();
+    // x: sB[c][b][i] = sum_a J[i][a] zm[c][b][a]
+    if (j < LM) {
+#pragma unroll
+        for (int c = 0; c < LM; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < LM; ++a) s += sJ[i * LM + a] * sA[c * LM * LM + j * LM + a];
+            sB[c * LM * LX + j * LX + i] = s;
+        }
+    }
+    __syncthreads();
+    double col[LM];
+#pragma unroll
+    for (int c = 0; c < LM; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < LM; ++b) s += sJ[j * LM + b] * sB[c * LM * LX + b * LX + i];
+        col[c] = s;
+    }
+    int ex, ey, ez;
+    elem_xyz(e, R->nel, ex, ey, ez);
+    const SEM_GLOBAL double* sf = gfield<double>(R, F_HSF);
+    const long long base = (long long)e * L3;
+#pragma unroll
+    for (int k = 0; k < LX; ++k) {
+        double p = 0.0;
+#pragma unroll
+        for (int c = 0; c < LM; ++c) p += sJ[k * LM + c] * col[c];
+        const double z = box_sum<LX, true>(sf, R->nel, ex, ey, ez, i, j, k) + p;
+        const long long pt = base + i + LX * (j + LX * k);
+        if constexpr (MODE == 0) gfieldw<TZ>(R, F_HZ)[pt] = (TZ)z;
+        else gfieldw<double>(R, F_GX)[pt] += z;
+    }
+}
+
+template <int LX>
+static void hsmg_go(const Batch& b, int src_vj, int tb, int tz, int gate, hipStream_t s)
+{
+    constexpr int LM = hs_lxm(LX);
+    const int ne = b.el[b.n];
+    if (ne == 0) return;
+    if (src_vj) {
+        if (tb == P64) hipLaunchKernelGGL((hs_down_kernel<LX, double, 0>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
+        else hipLaunchKernelGGL((hs_down_kernel<LX, float, 0>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
+    } else {
+        hipLaunchKernelGGL((hs_down_kernel<LX, double, 1>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
+    }
+    hipLaunchKernelGGL((hs_mid_kernel<LM>), dim3(ne), dim3(LM * LM), 0, s, b, LX, gate);
+    const dim3 cg((b.ncmax + 255) / 256, b.n);
+    hipLaunchKernelGGL(hs_cgath_kernel, cg, dim3(256), 0, s, b, gate);
+    // S^T along x, y, z (scaled), then S along z, y, x: F_HCA -> F_HCB -> ... -> F_HCA
+    const int dirs[6] = {0, 1, 2, 2, 1, 0};
+    for (int p = 0; p < 6; ++p) {
+        const int src = (p & 1) ? F_HCB : F_HCA, dst = (p & 1) ? F_HCA : F_HCB;
+        hipLaunchKernelGGL(hs_cpass_kernel, cg, dim3(256), 0, s, b, LX, dirs[p], p < 3 ? 1 : 0, p == 2 ? 1 : 0,
+                           src, dst, gate);
+    }
+    hipLaunchKernelGGL((hs_midup_kernel<LM>), dim3(ne), dim3(LM * LM), 0, s, b, LX, gate);
+    if (src_vj) {
+        if (tz == P64) hipLaunchKernelGGL((hs_up_kernel<LX, double, 0>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
+        else hipLaunchKernelGGL((hs_up_kernel<LX, float, 0>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
+    } else {
+        hipLaunchKernelGGL((hs_up_kernel<LX, double, 1>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
+    }
+}
+
+void launch_hsmg(const Batch& b, int lx, int src_vj, int tb, int tz, int gate, hipStream_t s)
+{
+    switch (lx) {
+    case 5: hsmg_go<5>(b, src_vj, tb, tz, gate, s); break;
+    case 6: hsmg_go<6>(b, src_vj, tb, tz, gate, s); break;
+    case 7: hsmg_go<7>(b, src_vj, tb, tz, gate, s); break;
+    case 8: hsmg_go<8>(b, src_vj, tb, tz, gate, s); break;
+    case 9: hsmg_go<9>(b, src_vj, tb, tz, gate, s); break;
+    case 10: hsmg_go<10>(b, src_vj, tb, tz, gate, s); break;
+    case 11: hsmg_go<11>(b, src_vj, tb, tz, gate, s); break;
+    case 12: hsmg_go<12>(b, src_vj, tb, tz, gate, s); break;
+    default: break;
+    }
+}
+
+}  // namespace semk

@@ -532,7 +532,7 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) pr_pass_kernel(Batch bt, int 
 
 // x += IDP * sum_{i < jend} y_i V_i  (right preconditioning applied once per
 // cycle, with the same stored diagonal the Arnoldi operator used)
-template <int NJ, typename TD, typename TB>
+template <int NJ, typename TD, typename TB, bool VY = false>
 __device__ __forceinline__ void xupd_body(const ReqDesc* R, const PtRange& pr)
 {
     const SEM_GLOBAL TB* V = fld<TB>(R, F_V);
@@ -549,11 +549,12 @@ __device__ __forceinline__ void xupd_body(const ReqDesc* R, const PtRange& pr)
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < NJ; ++i) s += y[i] * vr[i];
-        x[p] += s * (double)idp[p];
+        if constexpr (VY) gfieldw<double>(R, F_HT)[p] = s;
+        else x[p] += s * (double)idp[p];
     }
 }
 
-template <typename TD, typename TB>
+template <typename TD, typename TB, bool VY = false>
 __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_xupd_kernel(Batch bt, int gate)
 {
     const int g = blockIdx.x;
@@ -562,8 +563,13 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_xupd_kernel(Batch bt, int 
     const int blk = g - bt.vb[ri];
     if (!gate_ok(R, gate)) return;
     const PtRange pr = pt_range(R, blk);
+    if (VY && gp(R->I)[I_GJEND] == 0) {
+        // no Arnoldi step yet (the start of a solve): V y = 0
+        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) gfieldw<double>(R, F_HT)[p] = 0.0;
+        return;
+    }
     switch (gp(R->I)[I_GJEND]) {
-#define XU_CASE(n) case n: xupd_body<n, TD, TB>(R, pr); break;
+#define XU_CASE(n) case n: xupd_body<n, TD, TB, VY>(R, pr); break;
         SEM_NJ_CASES(XU_CASE)
 #undef XU_CASE
     default: break;
@@ -600,6 +606,10 @@ void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s)
 #undef PR_GO
         return;
     }
+    case V_GM_VY:
+        if (a.tb == P64) hipLaunchKernelGGL((gm_xupd_kernel<double, double, true>), grid, blk, 0, s, b, a.gate);
+        else hipLaunchKernelGGL((gm_xupd_kernel<double, float, true>), grid, blk, 0, s, b, a.gate);
+        return;
     case V_GM_XUPD:
         if (a.tv == P64 && a.tb == P64) hipLaunchKernelGGL((gm_xupd_kernel<double, double>), grid, blk, 0, s, b, a.gate);
         else if (a.tv == P64) hipLaunchKernelGGL((gm_xupd_kernel<double, float>), grid, blk, 0, s, b, a.gate);

@@ -110,6 +110,127 @@ void gll_tables(int N, std::vector<double>& x, std::vector<double>& w, std::vect
     }
 }
 
+// Symmetric eigenproblem a = V diag(lam) V^T (a: n x n row-major, destroyed;
+// V[r*n + k] = component r of eigenvector k) by cyclic two-sided Jacobi
+// rotations, each zeroing one off-diagonal pair (Rutishauser's formulas).
+static void sym_eig_jacobi(int n, std::vector<double>& a, std::vector<double>& V, std::vector<double>& lam)
+{
+    V.assign((size_t)n * n, 0.0);
+    for (int r = 0; r < n; ++r) V[(size_t)r * n + r] = 1.0;
+    auto A = [&](int r, int q) -> double& { return a[(size_t)r * n + q]; };
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int r = 0; r < n; ++r)
+            for (int q = 0; q < n; ++q) (r == q ? diag : off) += A(r, q) * A(r, q);
+        if (off <= 1e-30 * (diag + off)) break;
+        for (int p = 0; p + 1 < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A(p, q);
+                if (apq == 0.0) continue;
+                const double th = (A(q, q) - A(p, p)) / (2.0 * apq);
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                A(p, p) -= t * apq;
+                A(q, q) += t * apq;
+                A(p, q) = A(q, p) = 0.0;
+                for (int r = 0; r < n; ++r) {
+                    if (r != p && r != q) {
+                        const double arp = A(r, p), arq = A(r, q);
+                        A(r, p) = A(p, r) = cs * arp - sn * arq;
+                        A(r, q) = A(q, r) = sn * arp + cs * arq;
+                    }
+                    const double vp = V[(size_t)r * n + p], vq = V[(size_t)r * n + q];
+                    V[(size_t)r * n + p] = cs * vp - sn * vq;
+                    V[(size_t)r * n + q] = sn * vp + cs * vq;
+                }
+            }
+    }
+    lam.resize(n);
+    for (int r = 0; r < n; ++r) lam[r] = A(r, r);
+}
+
+// A s = lambda B s with B = diag(bd) > 0: S = B^{-1/2} V, V the eigenvectors
+// of B^{-1/2} A B^{-1/2}; then S^T B S = I and S^T A S = diag(lambda)
+static void fdm_pair(int n, const std::vector<double>& A, const std::vector<double>& bd, double* S, double* lam)
+{
+    std::vector<double> C((size_t)n * n), V, l;
+    for (int r = 0; r < n; ++r)
+        for (int q = 0; q < n; ++q) C[(size_t)r * n + q] = A[(size_t)r * n + q] / std::sqrt(bd[r] * bd[q]);
+    sym_eig_jacobi(n, C, V, l);
+    for (int r = 0; r < n; ++r)
+        for (int q = 0; q < n; ++q) S[(size_t)r * n + q] = V[(size_t)r * n + q] / std::sqrt(bd[r]);
+    for (int q = 0; q < n; ++q) lam[q] = l[q];
+}
+
+// HSMG tables (layout HsOff) of a periodic box of equal elements, order N:
+// per level (N and N/2) and direction the element's 1D stiffness
+// (2/h) D^T W D and mass (h/2) W, each end extended by a linear segment of
+// length delta = (h/2)(x_1 - x_0) to a zero Dirichlet node (stiffness
+// 1/delta and lumped mass delta/2 added at that end), in fast-diagonalised
+// form; the interpolation matrices between the levels; the coarse (order 1)
+// periodic 1D stiffness (2/h on the diagonal, -1/h to each neighbour) and
+// mass (h) per direction, fast-diagonalised.  c0: index of the zero
+// (constant) coarse mode per direction.
+static void hsmg_tables(int N, const int* nel, const double* h, std::vector<double>& T, int* c0)
+{
+    const int lx = N + 1, lm = hs_lxm(lx);
+    const HsOff o = hs_off(lx, nel);
+    T.assign(o.total, 0.0);
+    auto level = [&](int Nl, int oS, int oL) {
+        const int n = Nl + 1;
+        std::vector<double> x, w, D;
+        gll_tables(Nl, x, w, D);
+        for (int c = 0; c < 3; ++c) {
+            const double delta = 0.5 * h[c] * (x[1] - x[0]);
+            std::vector<double> A((size_t)n * n, 0.0), bd(n);
+            for (int r = 0; r < n; ++r)
+                for (int q = 0; q < n; ++q) {
+                    double sum = 0.0;
+                    for (int m = 0; m < n; ++m) sum += D[(size_t)m * n + r] * w[m] * D[(size_t)m * n + q];
+                    A[(size_t)r * n + q] = 2.0 / h[c] * sum;
+                }
+            for (int r = 0; r < n; ++r) bd[r] = 0.5 * h[c] * w[r];
+            A[0] += 1.0 / delta;
+            A[(size_t)Nl * n + Nl] += 1.0 / delta;
+            bd[0] += 0.5 * delta;
+            bd[Nl] += 0.5 * delta;
+            fdm_pair(n, A, bd, &T[oS + c * n * n], &T[oL + c * n]);
+        }
+        return x;
+    };
+    const std::vector<double> xf = level(N, o.Sf, o.Lf);
+    const std::vector<double> xm = level(lm - 1, o.Sm, o.Lm);
+    for (int i = 0; i < lx; ++i)
+        for (int a = 0; a < lm; ++a) {
+            double v = 1.0;
+            for (int q = 0; q < lm; ++q)
+                if (q != a) v *= (xf[i] - xm[q]) / (xm[a] - xm[q]);
+            T[o.J + i * lm + a] = v;
+        }
+    for (int a = 0; a < lm; ++a) {
+        T[o.Jc + 2 * a + 0] = 0.5 * (1.0 - xm[a]);
+        T[o.Jc + 2 * a + 1] = 0.5 * (1.0 + xm[a]);
+    }
+    for (int c = 0; c < 3; ++c) {
+        const int n = nel[c];
+        std::vector<double> A((size_t)n * n, 0.0), bd(n, 0.0);
+        for (int k = 0; k < n; ++k) {      // element k joins nodes k and k+1 (periodic)
+            const int p = k, q = (k + 1) % n;
+            A[(size_t)p * n + p] += 1.0 / h[c];
+            A[(size_t)q * n + q] += 1.0 / h[c];
+            A[(size_t)p * n + q] -= 1.0 / h[c];
+            A[(size_t)q * n + p] -= 1.0 / h[c];
+            bd[p] += 0.5 * h[c];
+            bd[q] += 0.5 * h[c];
+        }
+        fdm_pair(n, A, bd, &T[o.Sc[c]], &T[o.Lc[c]]);
+        int i0 = 0;
+        for (int q = 1; q < n; ++q)
+            if (T[o.Lc[c] + q] < T[o.Lc[c] + i0]) i0 = q;
+        c0[c] = i0;
+    }
+}
+
 int prec_rank(int p)
 {
     // FP64 > FP32 > FP16 = BF16
@@ -246,6 +367,8 @@ struct sem_ctx {
     int n2, n4, n8;
     std::vector<double> D64tab;
     std::vector<float> D32tab;
+    std::vector<double> hsT;    // HSMG tables (flow.hsmg)
+    int hs_c0[3];
     std::shared_ptr<const struct Tuples> tup;  // shared-node lists (cached per mesh shape)
     double vol;
     // layout
@@ -474,6 +597,21 @@ void build_layout(sem_ctx* c)
         field(F_GWD, d);
         field(F_GB, d);
         field(F_GX, d);
+        if (c->flow.hsmg) {
+            const int lm = hs_lxm(c->lx);
+            const size_t dm = 8 * (size_t)c->E * lm * lm * lm;
+            const size_t nc = (size_t)c->mesh.nel[0] * c->mesh.nel[1] * c->mesh.nel[2];
+            field(F_HST, 8 * (size_t)hs_off(c->lx, c->mesh.nel).total);
+            field(F_HSF, d);
+            field(F_HRM, dm);
+            field(F_HSM, dm);
+            field(F_HZM, dm);
+            field(F_HC8, 8 * 8 * (size_t)c->E);
+            field(F_HCA, 8 * nc);
+            field(F_HCB, 8 * nc);
+            field(F_HZ, psize(r.tb) * (size_t)np);
+            field(F_HT, d);
+        }
     }
     if (mode >= SEM_MODE_FLUID) {
         // the pressure solve's rhs is the pressure residual itself
@@ -511,11 +649,15 @@ semk::Batch make_batch(sem_ctx* const* ctxs, int n)
     b.eb[0] = 0;
     b.vb[0] = 0;
     b.gs[0] = 0;
+    b.el[0] = 0;
+    b.ncmax = 0;
     for (int i = 0; i < n; ++i) {
         sem_ctx* c = ctxs[i];
         b.eb[i + 1] = b.eb[i] + c->nb;
         b.vb[i + 1] = b.vb[i] + c->nvb;
         b.gs[i + 1] = b.gs[i] + c->hdesc.c2 + c->hdesc.c4 + c->hdesc.c8;
+        b.el[i + 1] = b.el[i] + c->E;
+        b.ncmax = std::max(b.ncmax, c->mesh.nel[0] * c->mesh.nel[1] * c->mesh.nel[2]);
         b.r[i] = c->ddesc;
     }
     return b;
@@ -706,9 +848,15 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
 
 // Cycle end of GMRES(m), gated on requests whose cycle ended: x update, fp64
 // true residual (no operator while x is still zero), then restart or finish.
-void gmres_cycle_end(const Batch& b, int lx, const Resolved& r, hipStream_t s)
+void gmres_cycle_end(const Batch& b, int lx, const Resolved& r, bool hsmg, hipStream_t s)
 {
-    vec(b, V_GM_XUPD, 1, r.tpd, I_GEND, s, -1, -1, P64, r.tb);
+    if (hsmg) {
+        // x += M^{-1} (V y): V y into HT, then the preconditioner adds into x
+        vec(b, V_GM_VY, 1, P64, I_GEND, s, -1, -1, P64, r.tb);
+        launch_hsmg(b, lx, 0, r.tb, P64, I_GEND, s);
+    } else {
+        vec(b, V_GM_XUPD, 1, r.tpd, I_GEND, s, -1, -1, P64, r.tb);
+    }
     {
         ProfScope ps(SEM_PROF_AX_PRESID, s);
         ax(b, lx, F_GX, F_GWD, 1, -1, 1.0, 0.0, -1, -1, I_GENDAX, P64, P64, P64, s);
@@ -719,9 +867,22 @@ void gmres_cycle_end(const Batch& b, int lx, const Resolved& r, hipStream_t s)
 
 // One Arnoldi step of GMRES(m); every kernel is gated so requests whose
 // cycle ended (or that converged) idle until the next cycle end.
-void gmres_arnoldi(const Batch& b, int lx, const Resolved& r, hipStream_t s)
+void gmres_arnoldi(const Batch& b, int lx, const Resolved& r, bool hsmg, hipStream_t s)
 {
-    {
+    if (hsmg) {
+        // w = A M^{-1} V_J with z = M^{-1} V_J in HZ (basis storage precision)
+        {
+            ProfScope ps(SEM_PROF_HSMG, s);
+            launch_hsmg(b, lx, 1, r.tb, r.tb, I_GARN, s);
+        }
+        ProfScope ps(SEM_PROF_AX_PRES, s);
+        AxLaunch a;
+        a.src = F_HZ; a.src_vj = 0; a.dst = F_GW; a.ncomp = 1; a.hsel = -1; a.h1 = 1.0; a.h2 = 0.0;
+        a.precond = -1; a.tpc = P64; a.pdot = -1; a.gate = I_GARN;
+        a.tu = r.tb; a.tg = r.axp_g; a.tc = r.axp_c; a.u_raw = nullptr; a.w_raw = nullptr;
+        a.out64 = 1; a.sub = -1;
+        launch_ax(b, lx, a, s);
+    } else {
         // w = A M^{-1} V_J: the Jacobi scaling is applied while loading V_J
         ProfScope ps(SEM_PROF_AX_PRES, s);
         AxLaunch a;
@@ -754,10 +915,10 @@ void gmres_arnoldi(const Batch& b, int lx, const Resolved& r, hipStream_t s)
 // device): start (GX zeroed by the caller), advance by up to max_iters Arnoldi
 // steps, finish (mass-mean removal of GX).
 // Start: the first cycle end runs at once (r = b, beta, V_0 = r / beta).
-void gmres_start(const Batch& b, int lx, const Resolved& r, hipStream_t s)
+void gmres_start(const Batch& b, int lx, const Resolved& r, bool hsmg, hipStream_t s)
 {
     fin(b, FIN_GM_START, s);
-    gmres_cycle_end(b, lx, r, s);
+    gmres_cycle_end(b, lx, r, hsmg, s);
 }
 
 // Advance by up to max_iters Arnoldi steps; returns the number of requests
@@ -776,10 +937,10 @@ int gmres_advance(sem_ctx* const* ctxs, const Batch& b, hipStream_t s, int max_i
     while (done < max_iters) {
         const int k = std::min(K, max_iters - done);
         for (int q = 0; q < k; ++q) {
-            gmres_arnoldi(b, c0->lx, c0->rs, s);
+            gmres_arnoldi(b, c0->lx, c0->rs, c0->flow.hsmg != 0, s);
             ++since;
             if (!lockstep || since == m || q == k - 1) {
-                gmres_cycle_end(b, c0->lx, c0->rs, s);
+                gmres_cycle_end(b, c0->lx, c0->rs, c0->flow.hsmg != 0, s);
                 if (since == m) since = 0;
             }
         }
@@ -830,7 +991,7 @@ int pressure_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
     const int m = c0->flow.gmres_restart;
     const int limit = c0->flow.pres_maxit + c0->flow.pres_maxit / std::max(1, m) + 4;
     const bool proj = c0->flow.mode == SEM_MODE_FLUID && c0->flow.proj_dim > 0;
-    gmres_start(b, c0->lx, c0->rs, s);
+    gmres_start(b, c0->lx, c0->rs, c0->flow.hsmg != 0, s);
     int rc = gmres_advance(ctxs, b, s, limit, true);
     if (rc < 0) return rc;
     if (proj) projection_update(b, c0->lx, c0->rs, s);
@@ -908,6 +1069,15 @@ int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_pr
     Resolved rs;
     int rc = resolve_policy(prec, rs);
     if (rc) return rc;
+    if (flow->hsmg != 0 && flow->hsmg != 1) return fail(SEM_EINVAL, "hsmg must be 0 or 1");
+    if (flow->hsmg) {
+        if (flow->mode < SEM_MODE_POISSON) return fail(SEM_EINVAL, "hsmg applies to the Poisson and fluid modes");
+        if (mesh->deform_amp != 0.0) return fail(SEM_EINVAL, "hsmg needs an unperturbed box mesh");
+        if (mesh->order < 4) return fail(SEM_EINVAL, "hsmg needs order >= 4");
+        for (int d = 0; d < 3; ++d)
+            if (mesh->nel[d] < 2) return fail(SEM_EINVAL, "hsmg needs at least 2 elements per direction");
+        if (rs.tb != P64 && rs.tb != P32) return fail(SEM_EINVAL, "hsmg needs an fp64 or fp32 pressure basis");
+    }
 
     sem_ctx* c = new sem_ctx();
     c->mesh = *mesh;
@@ -968,6 +1138,7 @@ int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_pr
     mp.N = c->N;
     mp.amp = mesh->deform_amp;
     for (int q = 0; q < 9; ++q) mp.phase[q] = mesh->deform_phase[q];
+    if (flow->hsmg) hsmg_tables(c->N, mesh->nel, mp.h, c->hsT, c->hs_c0);
     *out = c;
     return 0;
 }
@@ -1007,6 +1178,9 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     d.prec16 = c->rs.need16 ? c->rs.kind16 : 0;
     d.gm_m = c->flow.gmres_restart;
     d.proj_L = c->flow.mode == SEM_MODE_FLUID ? c->flow.proj_dim : 0;
+    for (int q = 0; q < 3; ++q) d.nel[q] = c->mesh.nel[q];
+    d.hs = c->flow.hsmg;
+    for (int q = 0; q < 3; ++q) d.hs_c0[q] = c->flow.hsmg ? c->hs_c0[q] : 0;
     d.np = c->np; d.nglob = c->nglob;
     d.idx2 = (const int*)(c->dev + c->off_i2);
     d.idx4 = (const int*)(c->dev + c->off_i4);
@@ -1042,6 +1216,8 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     HIPCHK(hipMemcpyAsync(d.I, I.data(), sizeof(int) * NINT, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync((void*)d.D64, c->D64tab.data(), sizeof(double) * c->D64tab.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync((void*)d.D32, c->D32tab.data(), sizeof(float) * c->D32tab.size(), hipMemcpyHostToDevice, s));
+    if (c->flow.hsmg)
+        HIPCHK(hipMemcpyAsync(d.f[F_HST], c->hsT.data(), sizeof(double) * c->hsT.size(), hipMemcpyHostToDevice, s));
     const Tuples& T = *c->tup;
     if (!T.idx2.empty()) HIPCHK(hipMemcpyAsync((void*)d.idx2, T.idx2.data(), sizeof(int) * T.idx2.size(), hipMemcpyHostToDevice, s));
     if (!T.idx4.empty()) HIPCHK(hipMemcpyAsync((void*)d.idx4, T.idx4.data(), sizeof(int) * T.idx4.size(), hipMemcpyHostToDevice, s));
@@ -1187,6 +1363,8 @@ static int check_batch(sem_ctx* const* ctxs, int n, int min_mode)
             return fail(SEM_EINVAL, "batched contexts must share the dealiasing setting");
         if ((ctxs[i]->flow.cfl_target > 0.0) != (ctxs[0]->flow.cfl_target > 0.0))
             return fail(SEM_EINVAL, "batched contexts must all use fixed or all adaptive dt");
+        if (ctxs[i]->flow.hsmg != ctxs[0]->flow.hsmg)
+            return fail(SEM_EINVAL, "batched contexts must use the same pressure preconditioner");
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(SEM_EINVAL, "a context appears twice in a batch");
     }
@@ -1336,7 +1514,7 @@ int sem_poisson_begin(sem_ctx* const* ctxs, int n, const void* const* rhs)
     vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_GB, -1, P64, P64, FIN_MEAN_UNIQUE);
     vec(b, V_SUB_MEAN, 1, P64, -1, s, F_GB, -1);
     vec(b, V_ZERO, 1, P64, -1, s, F_GX);
-    gmres_start(b, c0->lx, c0->rs, s);
+    gmres_start(b, c0->lx, c0->rs, c0->flow.hsmg != 0, s);
     return check_hip_last();
 }
 
@@ -1379,7 +1557,7 @@ int sem_poisson_finish(sem_ctx* c, void* sol, sem_solve_stats* st)
 
 int sem_prof_start(int kclass)
 {
-    if (kclass < SEM_PROF_AX_VEL || kclass > SEM_PROF_CONV) return fail(SEM_EINVAL, "unknown profiling class");
+    if (kclass < SEM_PROF_AX_VEL || kclass > SEM_PROF_HSMG) return fail(SEM_EINVAL, "unknown profiling class");
     g_prof.kclass = kclass;
     g_prof.used = 0;
     return 0;

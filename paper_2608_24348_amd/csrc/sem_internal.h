@@ -78,6 +78,16 @@ enum FieldId : int {
     F_MFD32,                    // fp32 copy (conv storage fp32)
     F_MFD16,                    // 16-bit copy (conv storage fp16/bf16), element-scaled
     F_MFDSC,                    // float[E]: scale of F_MFD16
+    // HSMG pressure preconditioner (flow.hsmg): levels lx, hs_lxm(lx), 2
+    F_HST,                      // double tables, layout HsOff
+    F_HSF,                      // [E][lx3]   fine-level local Schwarz solutions (element copies, unsummed)
+    F_HRM,                      // [E][lxm3]  restricted residual, element contributions (unsummed)
+    F_HSM,                      // [E][lxm3]  middle-level local Schwarz solutions (unsummed)
+    F_HZM,                      // [E][lxm3]  middle-level correction (continuous)
+    F_HC8,                      // [E][8]     coarse-corner contributions of each element
+    F_HCA, F_HCB,               // [nx ny nz] coarse vectors (unique corner nodes), ping-pong
+    F_HZ,                       // [E][lx3]   M^{-1} V_J in the basis storage precision (Arnoldi operator input)
+    F_HT,                       // [E][lx3]   sum_i y_i V_i (fp64) at a cycle end
     NFIELD
 };
 
@@ -171,6 +181,9 @@ struct ReqDesc {
     int prec16;                 // 0 none, 2 fp16, 3 bf16
     int gm_m;                   // GMRES restart
     int proj_L;                 // pressure projection space dimension (0 = off)
+    int nel[3];                 // elements per direction of the periodic box
+    int hs;                     // HSMG pressure preconditioner on
+    int hs_c0[3];               // index of the constant coarse mode per direction
     long long np, nglob;
     const int* idx2;            // [n2][2]
     const int* idx4;            // [n4][4]
@@ -198,6 +211,8 @@ struct Batch {
     int eb[SEM_MAXB + 1];       // prefix over element blocks
     int vb[SEM_MAXB + 1];       // prefix over point-wise blocks
     int gs[SEM_MAXB + 1];       // prefix over shared-node chunks
+    int el[SEM_MAXB + 1];       // prefix over elements (one-element-per-workgroup kernels)
+    int ncmax;                  // largest coarse HSMG grid (nx ny nz) of the batch
     const ReqDesc* r[SEM_MAXB];
 };
 
@@ -209,6 +224,33 @@ __host__ __device__ constexpr int dl16_per_elem(int lx)
 {
     return dl16_lane(lx) ? (((3 * lx + 1) / 2) * ((3 * lx + 1) / 2) + 15) / 16 * 9 * (((3 * lx + 1) / 2 + 3) / 4) * 64
                          : 9 * ((3 * lx + 1) / 2) * ((3 * lx + 1) / 2) * ((3 * lx + 1) / 2);
+}
+
+// HSMG middle level: order N/2
+__host__ __device__ constexpr int hs_lxm(int lx) { return (lx - 1) / 2 + 1; }
+
+// offsets (doubles) of the HSMG tables in F_HST: fine S (3 lx^2, S[c][i*lx+k] =
+// component i of eigenvector k), fine lambda (3 lx), middle S, middle lambda,
+// J fine<-middle (lx*lxm, J[i*lxm+a]), J middle<-coarse (lxm*2), coarse S per
+// direction (n_c^2 each), coarse lambda per direction (n_c each)
+struct HsOff {
+    int Sf, Lf, Sm, Lm, J, Jc, Sc[3], Lc[3], total;
+};
+__host__ __device__ inline HsOff hs_off(int lx, const int* nel)
+{
+    const int lm = hs_lxm(lx);
+    HsOff o;
+    o.Sf = 0;
+    o.Lf = o.Sf + 3 * lx * lx;
+    o.Sm = o.Lf + 3 * lx;
+    o.Lm = o.Sm + 3 * lm * lm;
+    o.J = o.Lm + 3 * lm;
+    o.Jc = o.J + lx * lm;
+    int q = o.Jc + 2 * lm;
+    for (int c = 0; c < 3; ++c) { o.Sc[c] = q; q += nel[c] * nel[c]; }
+    for (int c = 0; c < 3; ++c) { o.Lc[c] = q; q += nel[c]; }
+    o.total = q;
+    return o;
 }
 
 // elements per workgroup of the element kernels (shared by host and device)
@@ -281,6 +323,10 @@ void launch_opgrad(const Batch& b, int lx, int tm, int tc, int src, int dst, hip
 void launch_wdiv(const Batch& b, int lx, int tm, int tc, int src, int dst, hipStream_t s);
 void launch_diagnostics(const Batch& b, int lx, hipStream_t s);
 
+// HSMG: z = M^{-1} r with r = s_J V_J (src_vj, the Arnoldi step; z -> F_HZ in
+// precision tz) or r = F_HT (z added to F_GX, the cycle end); gated per request
+void launch_hsmg(const Batch& b, int lx, int src_vj, int tb, int tz, int gate, hipStream_t s);
+
 // point-wise / reduction / scalar kernels
 enum VecOp : int {
     V_VRESID = 0,     // partial |R64|^2 -> R_A+c (R64 = dssum(RHS_L - H_L u), formed by the operator)
@@ -309,6 +355,7 @@ enum VecOp : int {
     V_PR_V,           // GW = GX - PRXB (GX alone when the space restarts): the candidate direction
     V_PR_BDOTS,       // partials (X_i, GWD) -> R_GM+i, i < l, and (GW, GWD) -> R_GM+l
     V_PR_ORTH,        // X_l = GW - sum_i beta_i s_i X_i
+    V_GM_VY,          // HT = sum_{i<jend} y_i V_i  (the HSMG cycle end applies M^{-1} to it)
     NVECOP
 };
 

@@ -55,7 +55,7 @@ class FlowDesc(C.Structure):
                 ("torder", C.c_int), ("vel_tol", C.c_double), ("pres_tol", C.c_double),
                 ("vel_maxit", C.c_int), ("pres_maxit", C.c_int), ("gmres_restart", C.c_int),
                 ("vel_max_refine", C.c_int), ("init", C.c_int), ("proj_dim", C.c_int),
-                ("dealias", C.c_int), ("cfl_target", C.c_double)]
+                ("dealias", C.c_int), ("cfl_target", C.c_double), ("hsmg", C.c_int)]
 
 
 class StepStats(C.Structure):
@@ -80,7 +80,7 @@ EXPORTS = ["sem_setup", "sem_workspace_bytes", "sem_bind", "sem_ax", "sem_dssum"
            "sem_prof_start", "sem_prof_stop", "sem_poisson_begin", "sem_poisson_advance", "sem_poisson_finish",
            "sem_mass", "sem_node_field", "sem_copy_state"]
 PROF_AX_VEL, PROF_AX_PRES, PROF_GM_DOTS, PROF_GM_UPD_DOTS, PROF_GM_UPD_NORM, PROF_DSSUM_PRES, PROF_AX_ANY, PROF_AX_RESID, \
-    PROF_AX_PRESID, PROF_CONV = range(1, 11)
+    PROF_AX_PRESID, PROF_CONV, PROF_HSMG = range(1, 12)
 
 _lib = None
 
@@ -214,7 +214,7 @@ def mesh_desc(nel, order, lo=(-math.pi,) * 3, hi=(math.pi,) * 3, amp=0.0, phase=
 
 
 def flow_desc(mode=MODE_FLUID, nu=1.0 / 1600, dt=1e-3, torder=3, vel_tol=1e-8, pres_tol=1e-8, vel_maxit=500,
-              pres_maxit=1000, restart=30, max_refine=8, init=INIT_TGV3D, proj=0, dealias=0, cfl=0.0):
+              pres_maxit=1000, restart=30, max_refine=8, init=INIT_TGV3D, proj=0, dealias=0, cfl=0.0, hsmg=0):
     f = FlowDesc()
     f.size = C.sizeof(FlowDesc)
     f.mode = mode
@@ -231,6 +231,7 @@ def flow_desc(mode=MODE_FLUID, nu=1.0 / 1600, dt=1e-3, torder=3, vel_tol=1e-8, p
     f.proj_dim = proj
     f.dealias = int(dealias)
     f.cfl_target = float(cfl)
+    f.hsmg = int(hsmg)
     return f
 
 

@@ -1,0 +1,126 @@
+"""GPU parity of the HSMG pressure preconditioner (flow.hsmg = 1), called
+through the C ABI, against the oracle's HSMG (oracle/sem_oracle.c): GMRES
+iteration counts and solutions of Poisson solves, fluid steps with the
+paper's solver settings, fp32 basis storage, and batched runs."""
+import numpy as np
+import pytest
+
+from oracle import OracleMesh, OracleFluid, OracleHSMG
+from oracle.oracle import INIT_TGV3D
+from paper_2608_24348_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sem():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2608_24348_amd import sem as s
+    s.load()
+    return s
+
+
+def _ctx(sem, nel, N, tier="fp64", mode=None, **kw):
+    mode = sem.MODE_FLUID if mode is None else mode
+    return sem.Context(sem.mesh_desc(nel, N), sem.flow_desc(mode=mode, hsmg=1, **kw), sem.tier(tier))
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _rhs(m, nel, N, seed):
+    X = m.coords()
+    f = 3 * np.sin(X[0]) * np.sin(2 * X[1]) * np.cos(X[2]) + 0.1 * m.from_lattice(inputs.lattice_normal(nel, N, seed))
+    return m.dssum(m.mass() * f)
+
+
+# (elements, order): middle orders 3, 2, 5, 2 (lx 8, 6, 12, 5); a ragged element grid
+@pytest.mark.parametrize("nel,N", [((4, 4, 4), 7), ((3, 4, 2), 5), ((2, 2, 2), 11), ((4, 2, 3), 4)])
+def test_hsmg_poisson_solve_matches_oracle(sem, nel, N):
+    c = _ctx(sem, nel, N, mode=sem.MODE_POISSON, pres_tol=1e-10, pres_maxit=2000)
+    m = OracleMesh(nel, N)
+    H = OracleHSMG(m)
+    rhs = _rhs(m, nel, N, 3)
+    pref, itref, resref = H.poisson(rhs, tol=1e-10, maxit=2000)
+    _, itjac, _ = m.poisson(rhs, tol=1e-10, maxit=4000)
+    sol = torch.empty(c.np, dtype=torch.float64, device="cuda:0")
+    st = sem.poisson_solve([c], [torch.from_numpy(rhs).to("cuda:0")], [sol])[0]
+    print(nel, N, "iters gpu", st["iters"], "oracle", itref, "jacobi", itjac)
+    assert st["status"] == 0
+    assert abs(st["iters"] - itref) <= 1, (st["iters"], itref)
+    assert st["iters"] * 3 <= itjac
+    assert _rel(sol.cpu().numpy(), pref) < 1e-8
+
+
+def test_hsmg_poisson_fp32_basis(sem):
+    """fp32b tier: the basis is stored in fp32 and the pressure operator runs in
+    fp32; the HSMG arithmetic stays fp64.  The solution is the oracle's within
+    the solver tolerance's reach (tolerance 1e-6 relative, as the pressure
+    tolerance of the paper's runs)."""
+    nel, N = (4, 4, 4), 7
+    m = OracleMesh(nel, N)
+    H = OracleHSMG(m)
+    rhs = _rhs(m, nel, N, 5)
+    tol = 1e-6 * float(np.sqrt(m.glsc(rhs, rhs)))
+    c = _ctx(sem, nel, N, tier="fp32b", mode=sem.MODE_POISSON, pres_tol=tol, pres_maxit=500)
+    pref, itref, _ = H.poisson(rhs, tol=tol, maxit=500)
+    sol = torch.empty(c.np, dtype=torch.float64, device="cuda:0")
+    st = sem.poisson_solve([c], [torch.from_numpy(rhs).to("cuda:0")], [sol])[0]
+    print("fp32b iters", st["iters"], "oracle", itref)
+    assert st["status"] == 0
+    assert abs(st["iters"] - itref) <= 2
+    assert _rel(sol.cpu().numpy(), pref) < 2e-5
+
+
+@pytest.mark.parametrize("proj,dealias,cfl", [(0, 0, 0.0), (20, 1, 0.4)])
+def test_hsmg_fluid_matches_oracle(sem, proj, dealias, cfl):
+    """4^3 elements, N = 7, 6 steps, tolerances 1e-8: velocity counts equal,
+    pressure counts within 1, KE and enstrophy within 1e-9; the second case
+    is the paper's solver settings (Sec. 3: dealiased, adaptive dt at CFL
+    0.4, projection 20) with HSMG."""
+    nel, N = (4, 4, 4), 7
+    nu, dt = 1 / 1600, (0.05 if cfl else 2e-3)
+    c = _ctx(sem, nel, N, nu=nu, dt=dt, proj=proj, dealias=dealias, cfl=cfl)
+    m = OracleMesh(nel, N)
+    f = OracleFluid(m, nu, dt, init=INIT_TGV3D, proj=proj, dealias=bool(dealias), cfl=cfl, hsmg=True)
+    gst = sem.fluid_step([c], 6)[0]
+    for k in range(6):
+        o = f.step()
+        g = gst[k]
+        assert g["status"] == 0
+        assert g["vit"] == o["vit"] and abs(g["pit"] - o["pit"]) <= 1, (k, g, o)
+        assert abs(g["dt"] - o["dt"]) <= 1e-9 * o["dt"]
+        assert abs(g["ke"] - o["ke"]) <= 1e-9 * o["ke"]
+        assert abs(g["enst"] - o["enst"]) <= 1e-9 * o["enst"]
+    print("pit", [s["pit"] for s in gst])
+    assert _rel(c.velocity(), f.velocity()) < 1e-8
+
+
+def test_hsmg_lowers_pressure_iterations_in_the_fluid_step(sem):
+    nel, N = (4, 4, 4), 7
+    a = sem.Context(sem.mesh_desc(nel, N), sem.flow_desc(nu=1 / 1600, dt=5e-3), sem.tier("fp64"))
+    b = _ctx(sem, nel, N, nu=1 / 1600, dt=5e-3)
+    sa = sem.fluid_step([a], 4)[0]
+    sb = sem.fluid_step([b], 4)[0]
+    print("jacobi", [s["pit"] for s in sa], "hsmg", [s["pit"] for s in sb])
+    assert sum(s["pit"] for s in sb) * 3 <= sum(s["pit"] for s in sa)
+    assert _rel(b.velocity(), a.velocity()) < 1e-7
+
+
+def test_hsmg_batched_is_bitwise_equal_to_alone(sem):
+    specs = [((4, 4, 4), 7, 1 / 400), ((6, 4, 2), 7, 1 / 1000), ((2, 2, 4), 7, 1 / 100)]
+    alone = []
+    for nel, N, nu in specs:
+        c = _ctx(sem, nel, N, nu=nu, dt=1e-3, proj=3)
+        st = sem.fluid_step([c], 4)[0]
+        alone.append((st, c.velocity(), c.pressure()))
+    ctxs = [_ctx(sem, nel, N, nu=nu, dt=1e-3, proj=3) for nel, N, nu in specs]
+    mix = sem.fluid_step(ctxs, 4)
+    for i, c in enumerate(ctxs):
+        st, u, p = alone[i]
+        assert [s["pit"] for s in mix[i]] == [s["pit"] for s in st]
+        assert np.array_equal(c.velocity(), u)
+        assert np.array_equal(c.pressure(), p)

@@ -112,6 +112,33 @@ def test_dealias_validation_and_workspace():
         assert 0 <= (b.bytes - a.bytes) - 9 * E * nd ** 3 * per - extra < 768, t
 
 
+def test_hsmg_validation_and_workspace():
+    fd = sem.flow_desc(hsmg=1)
+    for md, fdd in ((sem.mesh_desc((2, 2, 2), 3), fd),                       # order below 4
+                    (sem.mesh_desc((2, 2, 2), 6, amp=0.05), fd),             # perturbed mesh
+                    (sem.mesh_desc((1, 2, 2), 6), fd),                       # one element in x
+                    (sem.mesh_desc((2, 2, 2), 6), sem.flow_desc(mode=sem.MODE_OPERATOR, hsmg=1)),
+                    (sem.mesh_desc((2, 2, 2), 6), sem.flow_desc(hsmg=2))):
+        with pytest.raises(sem.SemError):
+            sem.Context(md, fdd, sem.tier("fp64"), bind=False)
+    # 16-bit pressure basis storage is refused (the preconditioner output is stored in it)
+    md = sem.mesh_desc((3, 2, 2), 7)
+    with pytest.raises(sem.SemError):
+        sem.Context(md, fd, sem.precision(sem.FP32, blocks={sem.BLOCK_PRES: (sem.FP32, sem.FP32, sem.FP16)}), bind=False)
+    # workspace: tables, 3 fine fp64 vectors plus one in the basis precision,
+    # 3 middle vectors, 8 corner values per element, 2 coarse vectors
+    E, lx, lm, nc = 12, 8, 4, 12
+    for t, pb in (("fp64", 8), ("fp32b", 4)):
+        a = sem.Context(md, sem.flow_desc(), sem.tier(t), bind=False)
+        b = sem.Context(md, fd, sem.tier(t), bind=False)
+        tables = 8 * (3 * lx * lx + 3 * lx + 3 * lm * lm + 3 * lm + lx * lm + 2 * lm + 9 + 2 * 4 + 3 + 2 * 2)
+        want = tables + E * lx ** 3 * (2 * 8 + pb) + 3 * 8 * E * lm ** 3 + 64 * E + 2 * 8 * nc
+        assert 0 <= (b.bytes - a.bytes) - want < 11 * 256, t
+    for t in ("fp64", "fp32b", "fp32b+fp16", "fp32b+fp16a"):
+        sem.Context(md, fd, sem.tier(t), bind=False)
+    sem.Context(md, sem.flow_desc(mode=sem.MODE_POISSON, hsmg=1), sem.tier("fp64"), bind=False)
+
+
 def test_unbound_context_calls_fail_cleanly():
     c = sem.Context(sem.mesh_desc((2, 2, 2), 3), sem.flow_desc(), sem.tier("fp64"), bind=False)
     L = sem.load()
