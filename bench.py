@@ -45,9 +45,9 @@ def gmres_j_sequence(iters, m):
 
 
 def run_tier(sem, torch, tier, nel, N, nu, dt, warmup, steps, prof_class=None, vtol=1e-6, ptol=1e-4, proj=0,
-             dealias=0, cfl=0.0):
+             dealias=0, cfl=0.0, hsmg=0):
     ctx = sem.Context(sem.mesh_desc(nel, N), sem.flow_desc(nu=nu, dt=dt, restart=30, vel_tol=vtol, pres_tol=ptol,
-                                                           proj=proj, dealias=dealias, cfl=cfl),
+                                                           proj=proj, dealias=dealias, cfl=cfl, hsmg=hsmg),
                       sem.tier(tier))
     torch.cuda.synchronize()
     series = []
@@ -310,11 +310,15 @@ def main():
     ap.add_argument("--proj", type=int, default=0, help="pressure projection space (0 = off; the paper uses 20)")
     ap.add_argument("--cfl", type=float, default=0.0,
                     help="> 0: adaptive dt toward this CFL number, --dt the largest step (the paper uses 0.4)")
+    ap.add_argument("--hsmg", type=int, default=0, choices=[0, 1],
+                    help="1: HSMG pressure preconditioner (the paper's runs use HSMG), 0: Jacobi")
+    ap.add_argument("--hsmg-leg", type=int, default=1, choices=[0, 1],
+                    help="with --hsmg 0: also run the workload with HSMG in both tiers (the hsmg_leg record)")
     ap.add_argument("--dealias", type=int, default=0, choices=[0, 1],
                     help="1: convection on the 3/2-rule Gauss-Legendre grid (the paper's runs are dealiased)")
     ap.add_argument("--prof", default="ax_resid",
                     choices=["ax_resid", "ax_presid", "ax_vel", "ax_pres", "gm_upd_dots", "gm_upd_norm", "conv",
-                             "none"],
+                             "hsmg", "none"],
                     help="kernel class timed with HIP events for the roofline record (default: the dominant kernel)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with plain 1 GiB device copies (calibration of the PMC byte counters)")
@@ -348,9 +352,10 @@ def main():
     prof_class = {"ax_resid": sem.PROF_AX_RESID, "ax_presid": sem.PROF_AX_PRESID, "ax_vel": sem.PROF_AX_VEL,
                   "ax_pres": sem.PROF_AX_PRES,
                   "gm_upd_dots": sem.PROF_GM_UPD_DOTS,
-                  "gm_upd_norm": sem.PROF_GM_UPD_NORM, "conv": sem.PROF_CONV, "none": None}[args.prof]
+                  "gm_upd_norm": sem.PROF_GM_UPD_NORM, "conv": sem.PROF_CONV, "hsmg": sem.PROF_HSMG,
+                  "none": None}[args.prof]
     ctx, t_mx, st_mx, ser_mx, prof = run_tier(sem, torch, args.tier, nel, N, nu, dt, args.warmup, args.steps, prof_class,
-                                              args.vtol, args.ptol, args.proj, args.dealias, args.cfl)
+                                              args.vtol, args.ptol, args.proj, args.dealias, args.cfl, args.hsmg)
     steps_s = args.steps / t_mx
     out = {"metric": METRIC, "value": steps_s, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * t_mx / args.steps, "higher_is_better": True,
@@ -362,7 +367,9 @@ def main():
                                                                                      (", dealiased convection"
                                                                                       if args.dealias else "")
                                                                                      + (", adaptive dt CFL %g" % args.cfl
-                                                                                        if args.cfl > 0 else "")),
+                                                                                        if args.cfl > 0 else "")
+                                                                                     + (", HSMG pressure preconditioner"
+                                                                                        if args.hsmg else "")),
                       "global_batch": 1, "seq_len": npts, "parallelism": "single-gpu"}}
     out["iters"] = {"vel": [s["vit"] for s in st_mx], "pres": [s["pit"] for s in st_mx]}
     if args.cfl > 0:
@@ -370,14 +377,17 @@ def main():
         out["adaptive_dt"] = {"cfl_target": args.cfl, "dt_min": min(dts), "dt_max": max(dts),
                               "simulated_time": sum(dts), "simulated_time_per_s": sum(dts) / t_mx}
 
-    if prof is not None and not (args.proj and args.prof == "ax_presid"):
+    if prof is not None and args.prof == "hsmg":
+        # one record per preconditioner application of an Arnoldi step (11 launches)
+        out["hsmg"] = {"applies": prof[1], "ms_per_apply": prof[0] / max(prof[1], 1)}
+    elif prof is not None and not (args.proj and args.prof == "ax_presid"):
         # (the launch accounting of ax_presid covers the solver without projection)
         out["roofline"] = roofline(args.prof, args.tier, prof, st_mx, npts, out["config"]["workload"], N,
                                    args.dealias)
 
     if not args.no_fp64:
         ctx64, t64, st64, ser64, _ = run_tier(sem, torch, "fp64", nel, N, nu, dt, args.warmup, args.steps, None,
-                                              args.vtol, args.ptol, args.proj, args.dealias, args.cfl)
+                                              args.vtol, args.ptol, args.proj, args.dealias, args.cfl, args.hsmg)
         out["fp64_steps_per_s"] = args.steps / t64
         out["speedup_vs_fp64"] = steps_s / (args.steps / t64)
         ke_mx = [r[1] for r in ser_mx]
@@ -392,6 +402,25 @@ def main():
         del ctx64
     del ctx
     torch.cuda.synchronize()
+    if not args.hsmg and not args.no_fp64 and args.hsmg_leg:
+        # the same workload with the HSMG pressure preconditioner (both tiers)
+        log("hsmg leg: the same workload, HSMG pressure preconditioner")
+        leg = {}
+        sers = {}
+        for t in (args.tier, "fp64"):
+            c_h, t_h, st_h, ser_h, _ = run_tier(sem, torch, t, nel, N, nu, dt, args.warmup, args.steps, None,
+                                                args.vtol, args.ptol, args.proj, args.dealias, args.cfl, 1)
+            leg[t] = {"steps_per_s": args.steps / t_h,
+                      "pres_iters_mean": sum(s["pit"] for s in st_h) / len(st_h)}
+            sers[t] = ser_h
+            del c_h
+        hm, h64 = sers[args.tier], sers["fp64"]
+        out["hsmg_leg"] = {"tier": leg[args.tier], "fp64": leg["fp64"],
+                           "speedup_vs_fp64": leg[args.tier]["steps_per_s"] / leg["fp64"]["steps_per_s"],
+                           "jacobi_pres_iters_mean": sum(s["pit"] for s in st_mx) / len(st_mx),
+                           "e_E_max_pct": e_max([r[1] for r in hm], [r[1] for r in h64]),
+                           "e_Omega_max_pct": e_max([r[2] for r in hm], [r[2] for r in h64])}
+        torch.cuda.synchronize()
     if not args.no_ax:
         from paper_2608_24348_amd import inputs
         torch.cuda.empty_cache()

@@ -139,8 +139,8 @@ typedef struct {
                                         interpolation between levels and its unique-node transpose,
                                         an exact order-1 coarse solve off the constant mode, the
                                         levels added (a linear preconditioner).  fp64 arithmetic in
-                                        every tier.  Needs an unperturbed mesh, order 4..11, at
-                                        least 2 elements per direction and an fp64 or fp32 pressure
+                                        every tier.  Needs an unperturbed mesh, order 4..11, 2..64
+                                        elements per direction and an fp64 or fp32 pressure
                                         basis.  Adds about 3 E lx^3 + 4 E (lx/2)^3 doubles. */
 } sem_flow_desc;
 

@@ -15,11 +15,12 @@
 // A_c^+: exact solve of the order-1 operator off the constant mode, by fast
 // diagonalisation on the nx ny nz corner nodes.
 //
-// One apply = 11 launches, every one gated per request:
+// One apply = 8 launches, every one gated per request:
 //   hs_down   (fine FDM solve -> F_HSF; fine->middle restriction -> F_HRM)
 //   hs_mid    (sum copies of F_HRM; middle FDM -> F_HSM; middle->coarse -> F_HC8)
 //   hs_cgath  (coarse rhs on unique corner nodes -> F_HCA)
-//   hs_cpass  x6 (coarse S^T along x, y, z with the eigenvalue scaling, then S)
+//   hs_cxy, hs_cz, hs_cxy (coarse S^T along x and y, then z with the
+//             eigenvalue scaling and S along z, then S along y and x)
 //   hs_midup  (z_m = summed F_HSM / count + trilinear coarse correction -> F_HZM)
 //   hs_up     (z = summed F_HSF / count + J3 z_m -> F_HZ, or added to F_GX)
 // The copy sums use index arithmetic on the periodic box in an order shared
@@ -51,12 +52,21 @@ __device__ __forceinline__ double box_sum(const SEM_GLOBAL double* f, const int*
     constexpr int N = L - 1, L3 = L * L * L;
     const Cand cx = cand(i, ex, nel[0], N), cy = cand(j, ey, nel[1], N), cz = cand(k, ez, nel[2], N);
     double s = 0.0;
-    for (int c = 0; c < cz.n; ++c)
-        for (int b = 0; b < cy.n; ++b)
-            for (int a = 0; a < cx.n; ++a) {
+    // fixed trip counts keep the candidate arrays in registers
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        if (c >= cz.n) break;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            if (b >= cy.n) break;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                if (a >= cx.n) break;
                 const long long e = cx.e[a] + (long long)nel[0] * (cy.e[b] + (long long)nel[1] * cz.e[c]);
                 s += f[e * L3 + cx.i[a] + L * (cy.i[b] + L * cz.i[c])];
             }
+        }
+    }
     return AVG ? s / (double)(cx.n * cy.n * cz.n) : s;
 }
 
@@ -227,26 +237,29 @@ __global__ void __launch_bounds__(LX * LX) hs_down_kernel(Batch bt, int gate)
 }
 
 // ---------------------------------------------------------------- middle level, down
+// hs_mepb(LM) elements per workgroup (one request per workgroup)
 template <int LM>
-__global__ void __launch_bounds__(LM * LM) hs_mid_kernel(Batch bt, int lx, int gate)
+__global__ void __launch_bounds__(hs_mepb(LM) * LM * LM) hs_mid_kernel(Batch bt, int lx, int gate)
 {
-    constexpr int L2 = LM * LM, L3 = L2 * LM, N = LM - 1;
-    __shared__ double sA[L3], sB[L3];
-    __shared__ double sS[3 * L2], sLam[3 * LM], sJc[2 * LM], sC[2 * L2];
+    constexpr int L2 = LM * LM, L3 = L2 * LM, N = LM - 1, EP = hs_mepb(LM);
+    __shared__ double sA[EP * L3], sB[EP * L3];
+    __shared__ double sS[3 * L2], sLam[3 * LM], sJc[2 * LM], sC[EP * 2 * L2];
     const int g = blockIdx.x;
-    const int ri = find_req(bt.el, bt.n, g);
+    const int ri = find_req(bt.hm, bt.n, g);
     const ReqDesc* R = bt.r[ri];
-    const int e = g - bt.el[ri];
     if (!gate_ok(R, gate)) return;
-    const int t = threadIdx.x, i = t % LM, j = t / LM;
+    const int t = threadIdx.x, el = t / L2, ij = t - el * L2, i = ij % LM, j = ij / LM;
+    const int e = (g - bt.hm[ri]) * EP + el;
+    const bool live = e < R->E;
+    const int ee = live ? e : 0;        // lanes past the last element work on element 0 and store nothing
     const HsOff o = hs_off(lx, R->nel);
     const SEM_GLOBAL double* tb = gfield<double>(R, F_HST);
-    for (int q = t; q < 3 * L2; q += L2) sS[q] = tb[o.Sm + q];
-    for (int q = t; q < 3 * LM; q += L2) sLam[q] = tb[o.Lm + q];
-    for (int q = t; q < 2 * LM; q += L2) sJc[q] = tb[o.Jc + q];
+    for (int q = t; q < 3 * L2; q += EP * L2) sS[q] = tb[o.Sm + q];
+    for (int q = t; q < 3 * LM; q += EP * L2) sLam[q] = tb[o.Lm + q];
+    for (int q = t; q < 2 * LM; q += EP * L2) sJc[q] = tb[o.Jc + q];
     __syncthreads();
     int ex, ey, ez;
-    elem_xyz(e, R->nel, ex, ey, ez);
+    elem_xyz(ee, R->nel, ex, ey, ez);
     const SEM_GLOBAL double* rm = gfield<double>(R, F_HRM);
     double v[LM];
     // the assembled middle residual: sum of the element contributions
@@ -261,22 +274,24 @@ __global__ void __launch_bounds__(LM * LM) hs_mid_kernel(Batch bt, int lx, int g
             c0 += sJc[k * 2 + 0] * x;
             c1 += sJc[k * 2 + 1] * x;
         }
+        double* C = sC + el * 2 * L2;
+        C[0 * L2 + j * LM + i] = c0;
+        C[1 * L2 + j * LM + i] = c1;
         __syncthreads();
-        sC[0 * L2 + j * LM + i] = c0;
-        sC[1 * L2 + j * LM + i] = c1;
-        __syncthreads();
-        if (t < 8) {
-            const int ca = t & 1, cb = (t >> 1) & 1, cc = t >> 2;
+        if (ij < 8 && live) {
+            const int ca = ij & 1, cb = (ij >> 1) & 1, cc = ij >> 2;
             double s = 0.0;
             for (int b = 0; b < LM; ++b)
-                for (int a = 0; a < LM; ++a) s += sJc[a * 2 + ca] * sJc[b * 2 + cb] * sC[cc * L2 + b * LM + a];
-            gfieldw<double>(R, F_HC8)[(long long)e * 8 + t] = s;
+                for (int a = 0; a < LM; ++a) s += sJc[a * 2 + ca] * sJc[b * 2 + cb] * C[cc * L2 + b * LM + a];
+            gfieldw<double>(R, F_HC8)[(long long)e * 8 + ij] = s;
         }
     }
-    fdm_solve<LM>(v, sS, sLam, sA, sB, i, j);
-    SEM_GLOBAL double* u = gfieldw<double>(R, F_HSM) + (long long)e * L3;
+    fdm_solve<LM>(v, sS, sLam, sA + el * L3, sB + el * L3, i, j);
+    if (live) {
+        SEM_GLOBAL double* u = gfieldw<double>(R, F_HSM) + (long long)e * L3;
 #pragma unroll
-    for (int k = 0; k < LM; ++k) u[i + LM * (j + LM * k)] = v[k];
+        for (int k = 0; k < LM; ++k) u[i + LM * (j + LM * k)] = v[k];
+    }
 }
 
 // ---------------------------------------------------------------- coarse level
@@ -302,61 +317,110 @@ __global__ void __launch_bounds__(256) hs_cgath_kernel(Batch bt, int gate)
     gfieldw<double>(R, F_HCA)[q] = s;
 }
 
-// one direction of the coarse fast diagonalisation: out = S^T in (fwd) or
-// S in along direction dir; fwd with scale also divides by the eigenvalue
-// sum (the constant mode is set to zero)
-__global__ void __launch_bounds__(256) hs_cpass_kernel(Batch bt, int lx, int dir, int fwd, int scale, int src, int dst,
-                                                      int gate)
+// coarse fast diagonalisation, x and y directions of one z-plane per
+// workgroup (grid.x = z index): fwd: out = (S_y^T x S_x^T) in, else
+// out = (S_y x S_x) in
+__global__ void __launch_bounds__(256) hs_cxy_kernel(Batch bt, int lx, int fwd, int src, int dst, int gate)
 {
-    const int ri = blockIdx.y;
-    const ReqDesc* R = bt.r[ri];
+    __shared__ double sP[HS_CPLANE], sQ[HS_CPLANE];
+    const ReqDesc* R = bt.r[blockIdx.y];
     if (!gate_ok(R, gate)) return;
     const int nx = R->nel[0], ny = R->nel[1], nz = R->nel[2];
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nx * ny * nz) return;
-    const int c3[3] = {q % nx, (q / nx) % ny, q / (nx * ny)};
+    const int cz = blockIdx.x;
+    if (cz >= nz) return;
     const HsOff o = hs_off(lx, R->nel);
     const SEM_GLOBAL double* tb = gfield<double>(R, F_HST);
-    const SEM_GLOBAL double* S = tb + o.Sc[dir];
-    const SEM_GLOBAL double* in = gfield<double>(R, src);
-    const int n = R->nel[dir];
-    const int stride = dir == 0 ? 1 : dir == 1 ? nx : nx * ny;
-    const int me = c3[dir];
-    const long long q0 = q - (long long)me * stride;
-    double s = 0.0;
-    for (int a = 0; a < n; ++a) s += (fwd ? S[a * n + me] : S[me * n + a]) * in[q0 + (long long)a * stride];
-    if (scale) {
-        if (c3[0] == R->hs_c0[0] && c3[1] == R->hs_c0[1] && c3[2] == R->hs_c0[2]) s = 0.0;
-        else s /= tb[o.Lc[0] + c3[0]] + tb[o.Lc[1] + c3[1]] + tb[o.Lc[2] + c3[2]];
+    const SEM_GLOBAL double* Sx = tb + o.Sc[0];
+    const SEM_GLOBAL double* Sy = tb + o.Sc[1];
+    const SEM_GLOBAL double* in = gfield<double>(R, src) + (long long)cz * nx * ny;
+    const int np = nx * ny;
+    for (int q = threadIdx.x; q < np; q += blockDim.x) sP[q] = in[q];
+    __syncthreads();
+    for (int q = threadIdx.x; q < np; q += blockDim.x) {
+        const int x = q % nx, y = q / nx;
+        double s = 0.0;
+        for (int a = 0; a < nx; ++a) s += (fwd ? Sx[a * nx + x] : Sx[x * nx + a]) * sP[y * nx + a];
+        sQ[q] = s;
     }
-    gfieldw<double>(R, dst)[q] = s;
+    __syncthreads();
+    SEM_GLOBAL double* out = gfieldw<double>(R, dst) + (long long)cz * nx * ny;
+    for (int q = threadIdx.x; q < np; q += blockDim.x) {
+        const int x = q % nx, y = q / nx;
+        double s = 0.0;
+        for (int b = 0; b < ny; ++b) s += (fwd ? Sy[b * ny + y] : Sy[y * ny + b]) * sQ[b * nx + x];
+        out[q] = s;
+    }
+}
+
+// coarse fast diagonalisation, z direction of one y-row per workgroup
+// (grid.x = y index): S_z^T, division by the eigenvalue sums (the constant
+// mode is dropped), S_z
+__global__ void __launch_bounds__(256) hs_cz_kernel(Batch bt, int lx, int src, int dst, int gate)
+{
+    __shared__ double sP[HS_CPLANE], sQ[HS_CPLANE];
+    const ReqDesc* R = bt.r[blockIdx.y];
+    if (!gate_ok(R, gate)) return;
+    const int nx = R->nel[0], ny = R->nel[1], nz = R->nel[2];
+    const int cy = blockIdx.x;
+    if (cy >= ny) return;
+    const HsOff o = hs_off(lx, R->nel);
+    const SEM_GLOBAL double* tb = gfield<double>(R, F_HST);
+    const SEM_GLOBAL double* Sz = tb + o.Sc[2];
+    const SEM_GLOBAL double* in = gfield<double>(R, src);
+    const int np = nx * nz;                 // (x, z) of row cy, x fastest
+    for (int q = threadIdx.x; q < np; q += blockDim.x) {
+        const int x = q % nx, z = q / nx;
+        sP[q] = in[x + (long long)nx * (cy + (long long)ny * z)];
+    }
+    __syncthreads();
+    const double ly = tb[o.Lc[1] + cy];
+    for (int q = threadIdx.x; q < np; q += blockDim.x) {
+        const int x = q % nx, z = q / nx;
+        double s = 0.0;
+        for (int c = 0; c < nz; ++c) s += Sz[c * nz + z] * sP[c * nx + x];
+        if (x == R->hs_c0[0] && cy == R->hs_c0[1] && z == R->hs_c0[2]) s = 0.0;
+        else s /= tb[o.Lc[0] + x] + ly + tb[o.Lc[2] + z];
+        sQ[q] = s;
+    }
+    __syncthreads();
+    SEM_GLOBAL double* out = gfieldw<double>(R, dst);
+    for (int q = threadIdx.x; q < np; q += blockDim.x) {
+        const int x = q % nx, z = q / nx;
+        double s = 0.0;
+        for (int c = 0; c < nz; ++c) s += Sz[z * nz + c] * sQ[c * nx + x];
+        out[x + (long long)nx * (cy + (long long)ny * z)] = s;
+    }
 }
 
 // ---------------------------------------------------------------- middle level, up
 template <int LM>
-__global__ void __launch_bounds__(LM * LM) hs_midup_kernel(Batch bt, int lx, int gate)
+__global__ void __launch_bounds__(hs_mepb(LM) * LM * LM) hs_midup_kernel(Batch bt, int lx, int gate)
 {
-    constexpr int L3 = LM * LM * LM;
+    constexpr int L2 = LM * LM, L3 = L2 * LM, EP = hs_mepb(LM);
     __shared__ double sJc[2 * LM];
-    __shared__ double sE[8];
+    __shared__ double sE[EP * 8];
     const int g = blockIdx.x;
-    const int ri = find_req(bt.el, bt.n, g);
+    const int ri = find_req(bt.hm, bt.n, g);
     const ReqDesc* R = bt.r[ri];
-    const int e = g - bt.el[ri];
     if (!gate_ok(R, gate)) return;
-    const int t = threadIdx.x, i = t % LM, j = t / LM;
+    const int t = threadIdx.x, el = t / L2, ij = t - el * L2, i = ij % LM, j = ij / LM;
+    const int e = (g - bt.hm[ri]) * EP + el;
+    const bool live = e < R->E;
+    const int ee = live ? e : 0;
     const HsOff o = hs_off(lx, R->nel);
     const SEM_GLOBAL double* tb = gfield<double>(R, F_HST);
-    for (int q = t; q < 2 * LM; q += LM * LM) sJc[q] = tb[o.Jc + q];
+    for (int q = t; q < 2 * LM; q += EP * L2) sJc[q] = tb[o.Jc + q];
     int ex, ey, ez;
-    elem_xyz(e, R->nel, ex, ey, ez);
+    elem_xyz(ee, R->nel, ex, ey, ez);
     const int nx = R->nel[0], ny = R->nel[1], nz = R->nel[2];
-    if (t < 8) {
-        const int a = t & 1, b = (t >> 1) & 1, c = t >> 2;
+    if (ij < 8) {
+        const int a = ij & 1, b = (ij >> 1) & 1, c = ij >> 2;
         const int cx = (ex + a) % nx, cy = (ey + b) % ny, cz = (ez + c) % nz;
-        sE[t] = gfield<double>(R, F_HCA)[cx + nx * (cy + ny * cz)];
+        sE[el * 8 + ij] = gfield<double>(R, F_HCB)[cx + nx * (cy + ny * cz)];
     }
     __syncthreads();
+    if (!live) return;
+    const double* E8 = sE + el * 8;
     const SEM_GLOBAL double* sm = gfield<double>(R, F_HSM);
     SEM_GLOBAL double* zm = gfieldw<double>(R, F_HZM) + (long long)e * L3;
 #pragma unroll
@@ -365,7 +429,7 @@ __global__ void __launch_bounds__(LM * LM) hs_midup_kernel(Batch bt, int lx, int
         for (int c = 0; c < 2; ++c)
             for (int b = 0; b < 2; ++b)
                 for (int a = 0; a < 2; ++a)
-                    p += sE[a + 2 * (b + 2 * c)] * sJc[i * 2 + a] * sJc[j * 2 + b] * sJc[k * 2 + c];
+                    p += E8[a + 2 * (b + 2 * c)] * sJc[i * 2 + a] * sJc[j * 2 + b] * sJc[k * 2 + c];
         zm[i + LM * (j + LM * k)] = box_sum<LM, true>(sm, R->nel, ex, ey, ez, i, j, k) + p;
     }
 }
@@ -412,16 +476,15 @@ __global__ void __launch_bounds__(LX * LX) hs_up_kernel(Batch bt, int gate)
     int ex, ey, ez;
     elem_xyz(e, R->nel, ex, ey, ez);
     const SEM_GLOBAL double* sf = gfield<double>(R, F_HSF);
-    const long long base = (long long)e * L3;
+    const long long base = (long long)e * L3 + i + LX * j;
 #pragma unroll
     for (int k = 0; k < LX; ++k) {
         double p = 0.0;
 #pragma unroll
         for (int c = 0; c < LM; ++c) p += sJ[k * LM + c] * col[c];
         const double z = box_sum<LX, true>(sf, R->nel, ex, ey, ez, i, j, k) + p;
-        const long long pt = base + i + LX * (j + LX * k);
-        if constexpr (MODE == 0) gfieldw<TZ>(R, F_HZ)[pt] = (TZ)z;
-        else gfieldw<double>(R, F_GX)[pt] += z;
+        if constexpr (MODE == 0) gfieldw<TZ>(R, F_HZ)[base + L2 * k] = (TZ)z;
+        else gfieldw<double>(R, F_GX)[base + L2 * k] += z;
     }
 }
 
@@ -437,17 +500,17 @@ static void hsmg_go(const Batch& b, int src_vj, int tb, int tz, int gate, hipStr
     } else {
         hipLaunchKernelGGL((hs_down_kernel<LX, double, 1>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
     }
-    hipLaunchKernelGGL((hs_mid_kernel<LM>), dim3(ne), dim3(LM * LM), 0, s, b, LX, gate);
+    constexpr int EP = hs_mepb(LM);
+    const int nmb = b.hm[b.n];
+    hipLaunchKernelGGL((hs_mid_kernel<LM>), dim3(nmb), dim3(EP * LM * LM), 0, s, b, LX, gate);
     const dim3 cg((b.ncmax + 255) / 256, b.n);
     hipLaunchKernelGGL(hs_cgath_kernel, cg, dim3(256), 0, s, b, gate);
-    // S^T along x, y, z (scaled), then S along z, y, x: F_HCA -> F_HCB -> ... -> F_HCA
-    const int dirs[6] = {0, 1, 2, 2, 1, 0};
-    for (int p = 0; p < 6; ++p) {
-        const int src = (p & 1) ? F_HCB : F_HCA, dst = (p & 1) ? F_HCA : F_HCB;
-        hipLaunchKernelGGL(hs_cpass_kernel, cg, dim3(256), 0, s, b, LX, dirs[p], p < 3 ? 1 : 0, p == 2 ? 1 : 0,
-                           src, dst, gate);
-    }
-    hipLaunchKernelGGL((hs_midup_kernel<LM>), dim3(ne), dim3(LM * LM), 0, s, b, LX, gate);
+    // coarse fast diagonalisation: F_HCA -> (x, y fwd) F_HCB -> (z) F_HCA -> (x, y inv) F_HCB
+    const dim3 cp(b.cnmax, b.n);
+    hipLaunchKernelGGL(hs_cxy_kernel, cp, dim3(256), 0, s, b, LX, 1, (int)F_HCA, (int)F_HCB, gate);
+    hipLaunchKernelGGL(hs_cz_kernel, cp, dim3(256), 0, s, b, LX, (int)F_HCB, (int)F_HCA, gate);
+    hipLaunchKernelGGL(hs_cxy_kernel, cp, dim3(256), 0, s, b, LX, 0, (int)F_HCA, (int)F_HCB, gate);
+    hipLaunchKernelGGL((hs_midup_kernel<LM>), dim3(nmb), dim3(EP * LM * LM), 0, s, b, LX, gate);
     if (src_vj) {
         if (tz == P64) hipLaunchKernelGGL((hs_up_kernel<LX, double, 0>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
         else hipLaunchKernelGGL((hs_up_kernel<LX, float, 0>), dim3(ne), dim3(LX * LX), 0, s, b, gate);

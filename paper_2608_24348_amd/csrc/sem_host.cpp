@@ -650,14 +650,21 @@ semk::Batch make_batch(sem_ctx* const* ctxs, int n)
     b.vb[0] = 0;
     b.gs[0] = 0;
     b.el[0] = 0;
+    b.hm[0] = 0;
     b.ncmax = 0;
+    b.cnmax = 0;
     for (int i = 0; i < n; ++i) {
         sem_ctx* c = ctxs[i];
         b.eb[i + 1] = b.eb[i] + c->nb;
         b.vb[i + 1] = b.vb[i] + c->nvb;
         b.gs[i + 1] = b.gs[i] + c->hdesc.c2 + c->hdesc.c4 + c->hdesc.c8;
         b.el[i + 1] = b.el[i] + c->E;
+        {
+            const int mp = hs_mepb(hs_lxm(c->lx));
+            b.hm[i + 1] = b.hm[i] + (c->E + mp - 1) / mp;
+        }
         b.ncmax = std::max(b.ncmax, c->mesh.nel[0] * c->mesh.nel[1] * c->mesh.nel[2]);
+        b.cnmax = std::max(b.cnmax, std::max(c->mesh.nel[1], c->mesh.nel[2]));
         b.r[i] = c->ddesc;
     }
     return b;
@@ -1075,7 +1082,8 @@ int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_pr
         if (mesh->deform_amp != 0.0) return fail(SEM_EINVAL, "hsmg needs an unperturbed box mesh");
         if (mesh->order < 4) return fail(SEM_EINVAL, "hsmg needs order >= 4");
         for (int d = 0; d < 3; ++d)
-            if (mesh->nel[d] < 2) return fail(SEM_EINVAL, "hsmg needs at least 2 elements per direction");
+            if (mesh->nel[d] < 2 || mesh->nel[d] > HS_NELMAX)
+                return fail(SEM_EINVAL, "hsmg needs 2..64 elements per direction");
         if (rs.tb != P64 && rs.tb != P32) return fail(SEM_EINVAL, "hsmg needs an fp64 or fp32 pressure basis");
     }
 

@@ -23,6 +23,8 @@
 #define SEM_GS_TPT4 2        // quads per thread
 #define SEM_GS_TPT8 1        // octets per thread
 #define SEM_VEC_THREADS 256  // threads of point-wise kernels
+#define HS_NELMAX 64         // HSMG: elements per direction at most (a coarse plane fits in LDS)
+#define HS_CPLANE (HS_NELMAX * HS_NELMAX)
 
 namespace semk {
 
@@ -212,7 +214,9 @@ struct Batch {
     int vb[SEM_MAXB + 1];       // prefix over point-wise blocks
     int gs[SEM_MAXB + 1];       // prefix over shared-node chunks
     int el[SEM_MAXB + 1];       // prefix over elements (one-element-per-workgroup kernels)
+    int hm[SEM_MAXB + 1];       // prefix over HSMG middle-level blocks (hs_mepb elements each)
     int ncmax;                  // largest coarse HSMG grid (nx ny nz) of the batch
+    int cnmax;                  // largest ny or nz of the batch (coarse-pass workgroups)
     const ReqDesc* r[SEM_MAXB];
 };
 
@@ -226,8 +230,9 @@ __host__ __device__ constexpr int dl16_per_elem(int lx)
                          : 9 * ((3 * lx + 1) / 2) * ((3 * lx + 1) / 2) * ((3 * lx + 1) / 2);
 }
 
-// HSMG middle level: order N/2
+// HSMG middle level: order N/2; its kernels take hs_mepb elements per workgroup
 __host__ __device__ constexpr int hs_lxm(int lx) { return (lx - 1) / 2 + 1; }
+__host__ __device__ constexpr int hs_mepb(int lm) { return 64 / (lm * lm) > 0 ? 64 / (lm * lm) : 1; }
 
 // offsets (doubles) of the HSMG tables in F_HST: fine S (3 lx^2, S[c][i*lx+k] =
 // component i of eigenvector k), fine lambda (3 lx), middle S, middle lambda,

@@ -117,6 +117,7 @@ def test_hsmg_validation_and_workspace():
     for md, fdd in ((sem.mesh_desc((2, 2, 2), 3), fd),                       # order below 4
                     (sem.mesh_desc((2, 2, 2), 6, amp=0.05), fd),             # perturbed mesh
                     (sem.mesh_desc((1, 2, 2), 6), fd),                       # one element in x
+                    (sem.mesh_desc((2, 65, 2), 4), fd),                      # coarse plane beyond 64 x 64
                     (sem.mesh_desc((2, 2, 2), 6), sem.flow_desc(mode=sem.MODE_OPERATOR, hsmg=1)),
                     (sem.mesh_desc((2, 2, 2), 6), sem.flow_desc(hsmg=2))):
         with pytest.raises(sem.SemError):
