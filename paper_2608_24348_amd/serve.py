@@ -5,7 +5,8 @@ Poisson solve) arrive over time.  Each arrival is set up on the host
 (``sem_setup``; workspace size known before any device memory is touched)
 and waits in a FIFO until its workspace fits the HBM budget; admission binds
 it (device geometry, initial condition or right-hand side).  Admitted
-requests are grouped by batch key (polynomial order, precision tier, kind);
+requests are grouped by batch key (polynomial order, precision tier, kind,
+pressure preconditioner: HSMG where the request allows it, else Jacobi);
 every round the loop takes the next key with work, forms a batch of up to
 ``max_batch`` requests and runs one unit of work for all of them in single
 batched launches: one fluid time step for TGV requests, or one chunk of
@@ -28,15 +29,20 @@ import numpy as np
 from . import sem
 
 
-def _key(spec):
-    return (spec["N"] + 1, spec["tier"], spec["kind"])
+def _hsmg_ok(spec):
+    """the HSMG pressure preconditioner needs order >= 4 and 2..64 elements per direction"""
+    return spec["N"] >= 4 and all(2 <= n <= 64 for n in spec["nel"])
+
+
+def _key(spec, hsmg=0):
+    return (spec["N"] + 1, spec["tier"], spec["kind"], 1 if hsmg and _hsmg_ok(spec) else 0)
 
 
 class Request:
-    def __init__(self, spec):
+    def __init__(self, spec, hsmg=0):
         self.spec = spec
         self.kind = spec["kind"]
-        self.key = _key(spec)
+        self.key = _key(spec, hsmg)
         self.ctx = None
         self.steps_done = 0
         self.t_arrival = None
@@ -53,7 +59,7 @@ class Server:
     """Runs a list of request specs (see inputs.request_stream) to completion."""
 
     def __init__(self, budget_bytes=None, max_batch=16, gmres_chunk=30, device="cuda:0", vel_tol=1e-6,
-                 pres_tol=1e-4, poisson_tol=1e-8, keep_fields=False, policy="rr", tgv_steps=1):
+                 pres_tol=1e-4, poisson_tol=1e-8, keep_fields=False, policy="rr", tgv_steps=1, hsmg=1):
         import torch
         self.torch = torch
         self.device = device
@@ -76,6 +82,7 @@ class Server:
             raise ValueError("policy must be 'rr' or 'oldest'")
         self.policy = policy
         self.tgv_steps = max(1, int(tgv_steps))  # fluid steps per round of a TGV batch
+        self.hsmg = 1 if hsmg else 0                # HSMG pressure preconditioner where a request allows it
         self.used = 0
 
     # ---------------------------------------------------------------- request life cycle
@@ -84,7 +91,7 @@ class Server:
         mode = sem.MODE_FLUID if r.kind == "tgv" else sem.MODE_POISSON
         ptol = self.pres_tol if r.kind == "tgv" else self.poisson_tol
         flow = sem.flow_desc(mode=mode, nu=1.0 / s["Re"], dt=s["dt"], vel_tol=self.vel_tol, pres_tol=ptol,
-                             pres_maxit=3000)
+                             pres_maxit=3000, hsmg=r.key[3])
         r.ctx = sem.Context(sem.mesh_desc(s["nel"], s["N"]), flow, sem.tier(s["tier"]), device=self.device,
                             bind=False)
         r.bytes = r.ctx.bytes + 256
@@ -123,7 +130,7 @@ class Server:
 
     # ---------------------------------------------------------------- main loop
     def run(self, specs, log=None):
-        reqs = [Request(s) for s in sorted(specs, key=lambda s: s["arrival"])]
+        reqs = [Request(s, self.hsmg) for s in sorted(specs, key=lambda s: s["arrival"])]
         pending = collections.deque(reqs)
         waiting = collections.deque()
         active = collections.OrderedDict()
@@ -244,10 +251,12 @@ def main():
     ap.add_argument("--seed", type=int, default=24348)
     ap.add_argument("--loads", default="0.4,0.7,1.0", help="fractions of the saturated request rate")
     ap.add_argument("--max-batch", type=int, default=16)
+    ap.add_argument("--hsmg", type=int, default=1, choices=[0, 1],
+                    help="HSMG pressure preconditioner where a request allows it (1), Jacobi everywhere (0)")
     args = ap.parse_args()
     sem.load()
     res = measure(args.requests, args.seed, tuple(float(x) for x in args.loads.split(",")), args.max_batch,
-                  log=lambda m: print(m, file=sys.stderr, flush=True))
+                  log=lambda m: print(m, file=sys.stderr, flush=True), hsmg=args.hsmg)
     print(json.dumps(res), flush=True)
 
 

@@ -51,7 +51,7 @@ def test_admission_queues_under_small_budget_and_rejects_oversize(serve):
     probe = serve.Server()
     sizes = []
     for s in specs:
-        r = serve.Request(s)
+        r = serve.Request(s, probe.hsmg)
         probe._setup(r)
         sizes.append(r.bytes)
         r.ctx.close()
