@@ -154,15 +154,17 @@ def test_c3_dssum_sampled_copy_sets_and_multiplicity(sem):
     torch.cuda.empty_cache()
 
 
-def test_c2_bench_configuration_five_steps_match_oracle(sem):
+@pytest.mark.parametrize("hsmg", [0, 1])
+def test_c2_bench_configuration_five_steps_match_oracle(sem, hsmg):
     """The benchmark's workload and launch path (32^3, N = 7, Re 1600, dt 5e-4,
-    tolerances 1e-6 / 1e-4), fp64 tier, against the full oracle; the fifth
-    step is the first with pressure iterations."""
+    tolerances 1e-6 / 1e-4), fp64 tier, against the full oracle, with the
+    Jacobi (the fifth step is the first with pressure iterations) and the
+    HSMG pressure preconditioner (the bench default)."""
     nel, N, nu, dt = (32, 32, 32), 7, 1 / 1600, 5e-4
-    c = _ctx(sem, nel, N, "fp64", sem.MODE_FLUID, nu=nu, dt=dt, vel_tol=1e-6, pres_tol=1e-4)
+    c = _ctx(sem, nel, N, "fp64", sem.MODE_FLUID, nu=nu, dt=dt, vel_tol=1e-6, pres_tol=1e-4, hsmg=hsmg)
     gst = sem.fluid_step([c], 5)[0]
     m = OracleMesh(nel, N)
-    f = OracleFluid(m, nu, dt, vtol=1e-6, ptol=1e-4, init=INIT_TGV3D)
+    f = OracleFluid(m, nu, dt, vtol=1e-6, ptol=1e-4, init=INIT_TGV3D, hsmg=bool(hsmg))
     for k in range(5):
         o = f.step()
         g = gst[k]
