@@ -141,7 +141,11 @@ typedef struct {
                                         levels added (a linear preconditioner).  fp64 arithmetic in
                                         every tier.  Needs an unperturbed mesh, order 4..11, 2..64
                                         elements per direction and an fp64 or fp32 pressure
-                                        basis.  Adds about 3 E lx^3 + 4 E (lx/2)^3 doubles. */
+                                        basis.  GMRES keeps Z_j = M^{-1} V_j of each Arnoldi step
+                                        (flexible-GMRES storage), so a cycle end adds sum_j y_j Z_j
+                                        instead of applying M once more.  Adds E lx^3 doubles,
+                                        (restart + 2) E lx^3 values in the pressure basis precision
+                                        and 3 E (N/2 + 1)^3 doubles. */
 } sem_flow_desc;
 
 #define SEM_MAX_PROJ 20

@@ -22,7 +22,9 @@
 //   hs_cxy, hs_cz, hs_cxy (coarse S^T along x and y, then z with the
 //             eigenvalue scaling and S along z, then S along y and x)
 //   hs_midup  (z_m = summed F_HSM / count + trilinear coarse correction -> F_HZM)
-//   hs_up     (z = summed F_HSF / count + J3 z_m -> F_HZ, or added to F_GX)
+//   hs_up     (z = summed F_HSF / count + J3 z_m -> F_HZ and Z_J of F_HZS)
+// It runs in the Arnoldi steps only: the cycle end forms x += sum_j y_j Z_j
+// from the kept Z_j (M is linear, so this is x += M^{-1} V y).
 // The copy sums use index arithmetic on the periodic box in an order shared
 // by all copies of a node, so every copy receives the identical value.
 #include "k_common.h"
@@ -161,8 +163,8 @@ __device__ __forceinline__ void elem_xyz(int e, const int* nel, int& ex, int& ey
 }
 
 // ---------------------------------------------------------------- fine level, down
-// MODE 0: r = s_J V_J (basis storage TB); MODE 1: r = F_HT (fp64)
-template <int LX, typename TB, int MODE>
+// r = s_J V_J (basis storage TB)
+template <int LX, typename TB>
 __global__ void __launch_bounds__(LX * LX) hs_down_kernel(Batch bt, int gate)
 {
     constexpr int LM = hs_lxm(LX), L2 = LX * LX, L3 = L2 * LX, N = LX - 1;
@@ -182,16 +184,12 @@ __global__ void __launch_bounds__(LX * LX) hs_down_kernel(Batch bt, int gate)
 
     const long long base = (long long)e * L3;
     double v[LX];
-    if constexpr (MODE == 0) {
+    {
         const int J = gp(R->I)[I_GJ];
         const double sc = gp(R->S)[S_GVS + J];
         const SEM_GLOBAL TB* V = gfield<TB>(R, F_V) + (long long)J * R->np;
 #pragma unroll
         for (int k = 0; k < LX; ++k) v[k] = sc * (double)V[base + i + LX * (j + LX * k)];
-    } else {
-        const SEM_GLOBAL double* T = gfield<double>(R, F_HT);
-#pragma unroll
-        for (int k = 0; k < LX; ++k) v[k] = T[base + i + LX * (j + LX * k)];
     }
 
     // restriction to the middle level: t = J^T J^T J^T (r / mult)
@@ -435,8 +433,8 @@ __global__ void __launch_bounds__(hs_mepb(LM) * LM * LM) hs_midup_kernel(Batch b
 }
 
 // ---------------------------------------------------------------- fine level, up
-// MODE 0: z -> F_HZ (type TZ); MODE 1: F_GX += z
-template <int LX, typename TZ, int MODE>
+// z -> F_HZ (the operator's input) and Z_J of F_HZS (the cycle end's x update), type TZ
+template <int LX, typename TZ>
 __global__ void __launch_bounds__(LX * LX) hs_up_kernel(Batch bt, int gate)
 {
     constexpr int LM = hs_lxm(LX), L2 = LX * LX, L3 = L2 * LX;
@@ -477,29 +475,27 @@ __global__ void __launch_bounds__(LX * LX) hs_up_kernel(Batch bt, int gate)
     elem_xyz(e, R->nel, ex, ey, ez);
     const SEM_GLOBAL double* sf = gfield<double>(R, F_HSF);
     const long long base = (long long)e * L3 + i + LX * j;
+    SEM_GLOBAL TZ* hz = gfieldw<TZ>(R, F_HZ) + base;
+    SEM_GLOBAL TZ* zj = gfieldw<TZ>(R, F_HZS) + (long long)gp(R->I)[I_GJ] * R->np + base;
 #pragma unroll
     for (int k = 0; k < LX; ++k) {
         double p = 0.0;
 #pragma unroll
         for (int c = 0; c < LM; ++c) p += sJ[k * LM + c] * col[c];
-        const double z = box_sum<LX, true>(sf, R->nel, ex, ey, ez, i, j, k) + p;
-        if constexpr (MODE == 0) gfieldw<TZ>(R, F_HZ)[base + L2 * k] = (TZ)z;
-        else gfieldw<double>(R, F_GX)[base + L2 * k] += z;
+        const TZ z = (TZ)(box_sum<LX, true>(sf, R->nel, ex, ey, ez, i, j, k) + p);
+        hz[L2 * k] = z;
+        zj[L2 * k] = z;
     }
 }
 
 template <int LX>
-static void hsmg_go(const Batch& b, int src_vj, int tb, int tz, int gate, hipStream_t s)
+static void hsmg_go(const Batch& b, int tb, int gate, hipStream_t s)
 {
     constexpr int LM = hs_lxm(LX);
     const int ne = b.el[b.n];
     if (ne == 0) return;
-    if (src_vj) {
-        if (tb == P64) hipLaunchKernelGGL((hs_down_kernel<LX, double, 0>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
-        else hipLaunchKernelGGL((hs_down_kernel<LX, float, 0>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
-    } else {
-        hipLaunchKernelGGL((hs_down_kernel<LX, double, 1>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
-    }
+    if (tb == P64) hipLaunchKernelGGL((hs_down_kernel<LX, double>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
+    else hipLaunchKernelGGL((hs_down_kernel<LX, float>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
     constexpr int EP = hs_mepb(LM);
     const int nmb = b.hm[b.n];
     hipLaunchKernelGGL((hs_mid_kernel<LM>), dim3(nmb), dim3(EP * LM * LM), 0, s, b, LX, gate);
@@ -511,25 +507,21 @@ static void hsmg_go(const Batch& b, int src_vj, int tb, int tz, int gate, hipStr
     hipLaunchKernelGGL(hs_cz_kernel, cp, dim3(256), 0, s, b, LX, (int)F_HCB, (int)F_HCA, gate);
     hipLaunchKernelGGL(hs_cxy_kernel, cp, dim3(256), 0, s, b, LX, 0, (int)F_HCA, (int)F_HCB, gate);
     hipLaunchKernelGGL((hs_midup_kernel<LM>), dim3(nmb), dim3(EP * LM * LM), 0, s, b, LX, gate);
-    if (src_vj) {
-        if (tz == P64) hipLaunchKernelGGL((hs_up_kernel<LX, double, 0>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
-        else hipLaunchKernelGGL((hs_up_kernel<LX, float, 0>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
-    } else {
-        hipLaunchKernelGGL((hs_up_kernel<LX, double, 1>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
-    }
+    if (tb == P64) hipLaunchKernelGGL((hs_up_kernel<LX, double>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
+    else hipLaunchKernelGGL((hs_up_kernel<LX, float>), dim3(ne), dim3(LX * LX), 0, s, b, gate);
 }
 
-void launch_hsmg(const Batch& b, int lx, int src_vj, int tb, int tz, int gate, hipStream_t s)
+void launch_hsmg(const Batch& b, int lx, int tb, int gate, hipStream_t s)
 {
     switch (lx) {
-    case 5: hsmg_go<5>(b, src_vj, tb, tz, gate, s); break;
-    case 6: hsmg_go<6>(b, src_vj, tb, tz, gate, s); break;
-    case 7: hsmg_go<7>(b, src_vj, tb, tz, gate, s); break;
-    case 8: hsmg_go<8>(b, src_vj, tb, tz, gate, s); break;
-    case 9: hsmg_go<9>(b, src_vj, tb, tz, gate, s); break;
-    case 10: hsmg_go<10>(b, src_vj, tb, tz, gate, s); break;
-    case 11: hsmg_go<11>(b, src_vj, tb, tz, gate, s); break;
-    case 12: hsmg_go<12>(b, src_vj, tb, tz, gate, s); break;
+    case 5: hsmg_go<5>(b, tb, gate, s); break;
+    case 6: hsmg_go<6>(b, tb, gate, s); break;
+    case 7: hsmg_go<7>(b, tb, gate, s); break;
+    case 8: hsmg_go<8>(b, tb, gate, s); break;
+    case 9: hsmg_go<9>(b, tb, gate, s); break;
+    case 10: hsmg_go<10>(b, tb, gate, s); break;
+    case 11: hsmg_go<11>(b, tb, gate, s); break;
+    case 12: hsmg_go<12>(b, tb, gate, s); break;
     default: break;
     }
 }

@@ -532,16 +532,19 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) pr_pass_kernel(Batch bt, int 
 
 // x += IDP * sum_{i < jend} y_i V_i  (right preconditioning applied once per
 // cycle, with the same stored diagonal the Arnoldi operator used)
-template <int NJ, typename TD, typename TB, bool VY = false>
+// XZ = false: x += D^{-1} sum_i y_i s_i V_i (Jacobi);
+// XZ = true:  x += sum_i y_i Z_i with Z_i = M^{-1} s_i V_i kept from the
+// Arnoldi steps (HSMG; the same vector as M^{-1} V y for a linear M)
+template <int NJ, typename TD, typename TB, bool XZ = false>
 __device__ __forceinline__ void xupd_body(const ReqDesc* R, const PtRange& pr)
 {
-    const SEM_GLOBAL TB* V = fld<TB>(R, F_V);
+    const SEM_GLOBAL TB* V = fld<TB>(R, XZ ? F_HZS : F_V);
     auto idp = fld<TD>(R, sizeof(TD) == 8 ? F_IDP64 : F_IDP32);
     auto x = fldw<double>(R, F_GX);
     const long long np = R->np;
     double y[NJ];
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) y[i] = gp(R->S)[S_GY + i] * gp(R->S)[S_GVS + i];
+    for (int i = 0; i < NJ; ++i) y[i] = gp(R->S)[S_GY + i] * (XZ ? 1.0 : gp(R->S)[S_GVS + i]);
     for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
         double vr[NJ];
 #pragma unroll
@@ -549,12 +552,12 @@ __device__ __forceinline__ void xupd_body(const ReqDesc* R, const PtRange& pr)
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < NJ; ++i) s += y[i] * vr[i];
-        if constexpr (VY) gfieldw<double>(R, F_HT)[p] = s;
+        if constexpr (XZ) x[p] += s;
         else x[p] += s * (double)idp[p];
     }
 }
 
-template <typename TD, typename TB, bool VY = false>
+template <typename TD, typename TB, bool XZ = false>
 __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_xupd_kernel(Batch bt, int gate)
 {
     const int g = blockIdx.x;
@@ -563,13 +566,8 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) gm_xupd_kernel(Batch bt, int 
     const int blk = g - bt.vb[ri];
     if (!gate_ok(R, gate)) return;
     const PtRange pr = pt_range(R, blk);
-    if (VY && gp(R->I)[I_GJEND] == 0) {
-        // no Arnoldi step yet (the start of a solve): V y = 0
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) gfieldw<double>(R, F_HT)[p] = 0.0;
-        return;
-    }
     switch (gp(R->I)[I_GJEND]) {
-#define XU_CASE(n) case n: xupd_body<n, TD, TB, VY>(R, pr); break;
+#define XU_CASE(n) case n: xupd_body<n, TD, TB, XZ>(R, pr); break;
         SEM_NJ_CASES(XU_CASE)
 #undef XU_CASE
     default: break;
@@ -606,7 +604,7 @@ void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s)
 #undef PR_GO
         return;
     }
-    case V_GM_VY:
+    case V_GM_XZ:
         if (a.tb == P64) hipLaunchKernelGGL((gm_xupd_kernel<double, double, true>), grid, blk, 0, s, b, a.gate);
         else hipLaunchKernelGGL((gm_xupd_kernel<double, float, true>), grid, blk, 0, s, b, a.gate);
         return;

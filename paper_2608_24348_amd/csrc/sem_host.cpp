@@ -610,7 +610,7 @@ void build_layout(sem_ctx* c)
             field(F_HCA, 8 * nc);
             field(F_HCB, 8 * nc);
             field(F_HZ, psize(r.tb) * (size_t)np);
-            field(F_HT, d);
+            field(F_HZS, (size_t)(c->flow.gmres_restart + 1) * psize(r.tb) * (size_t)np);
         }
     }
     if (mode >= SEM_MODE_FLUID) {
@@ -858,9 +858,8 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
 void gmres_cycle_end(const Batch& b, int lx, const Resolved& r, bool hsmg, hipStream_t s)
 {
     if (hsmg) {
-        // x += M^{-1} (V y): V y into HT, then the preconditioner adds into x
-        vec(b, V_GM_VY, 1, P64, I_GEND, s, -1, -1, P64, r.tb);
-        launch_hsmg(b, lx, 0, r.tb, P64, I_GEND, s);
+        // x += M^{-1} V y = sum_j y_j Z_j with the Z_j = M^{-1} s_j V_j of the Arnoldi steps
+        vec(b, V_GM_XZ, 1, P64, I_GEND, s, -1, -1, P64, r.tb);
     } else {
         vec(b, V_GM_XUPD, 1, r.tpd, I_GEND, s, -1, -1, P64, r.tb);
     }
@@ -880,7 +879,7 @@ void gmres_arnoldi(const Batch& b, int lx, const Resolved& r, bool hsmg, hipStre
         // w = A M^{-1} V_J with z = M^{-1} V_J in HZ (basis storage precision)
         {
             ProfScope ps(SEM_PROF_HSMG, s);
-            launch_hsmg(b, lx, 1, r.tb, r.tb, I_GARN, s);
+            launch_hsmg(b, lx, r.tb, I_GARN, s);
         }
         ProfScope ps(SEM_PROF_AX_PRES, s);
         AxLaunch a;

@@ -89,7 +89,7 @@ enum FieldId : int {
     F_HC8,                      // [E][8]     coarse-corner contributions of each element
     F_HCA, F_HCB,               // [nx ny nz] coarse vectors (unique corner nodes), ping-pong
     F_HZ,                       // [E][lx3]   M^{-1} V_J in the basis storage precision (Arnoldi operator input)
-    F_HT,                       // [E][lx3]   sum_i y_i V_i (fp64) at a cycle end
+    F_HZS,                      // (m+1) x [E][lx3] Z_j = M^{-1} s_j V_j of every Arnoldi step, basis precision
     NFIELD
 };
 
@@ -328,9 +328,10 @@ void launch_opgrad(const Batch& b, int lx, int tm, int tc, int src, int dst, hip
 void launch_wdiv(const Batch& b, int lx, int tm, int tc, int src, int dst, hipStream_t s);
 void launch_diagnostics(const Batch& b, int lx, hipStream_t s);
 
-// HSMG: z = M^{-1} r with r = s_J V_J (src_vj, the Arnoldi step; z -> F_HZ in
-// precision tz) or r = F_HT (z added to F_GX, the cycle end); gated per request
-void launch_hsmg(const Batch& b, int lx, int src_vj, int tb, int tz, int gate, hipStream_t s);
+// HSMG in the Arnoldi step: z = M^{-1} s_J V_J into F_HZ (the operator's
+// input) and into Z_J of F_HZS (the cycle end's x update), both in the basis
+// precision tb; gated per request
+void launch_hsmg(const Batch& b, int lx, int tb, int gate, hipStream_t s);
 
 // point-wise / reduction / scalar kernels
 enum VecOp : int {
@@ -360,7 +361,7 @@ enum VecOp : int {
     V_PR_V,           // GW = GX - PRXB (GX alone when the space restarts): the candidate direction
     V_PR_BDOTS,       // partials (X_i, GWD) -> R_GM+i, i < l, and (GW, GWD) -> R_GM+l
     V_PR_ORTH,        // X_l = GW - sum_i beta_i s_i X_i
-    V_GM_VY,          // HT = sum_{i<jend} y_i V_i  (the HSMG cycle end applies M^{-1} to it)
+    V_GM_XZ,          // GX += sum_{i<jend} y_i Z_i  (HSMG cycle end: Z_i = M^{-1} s_i V_i kept from the Arnoldi steps)
     NVECOP
 };
 

@@ -126,14 +126,15 @@ def test_hsmg_validation_and_workspace():
     md = sem.mesh_desc((3, 2, 2), 7)
     with pytest.raises(sem.SemError):
         sem.Context(md, fd, sem.precision(sem.FP32, blocks={sem.BLOCK_PRES: (sem.FP32, sem.FP32, sem.FP16)}), bind=False)
-    # workspace: tables, 3 fine fp64 vectors plus one in the basis precision,
-    # 3 middle vectors, 8 corner values per element, 2 coarse vectors
-    E, lx, lm, nc = 12, 8, 4, 12
+    # workspace: tables, the fine local solutions (fp64), M^{-1} V_J and the
+    # kept Z_0..Z_m (basis precision), 3 middle vectors, 8 corner values per
+    # element, 2 coarse vectors
+    E, lx, lm, nc, m = 12, 8, 4, 12, 30
     for t, pb in (("fp64", 8), ("fp32b", 4)):
         a = sem.Context(md, sem.flow_desc(), sem.tier(t), bind=False)
         b = sem.Context(md, fd, sem.tier(t), bind=False)
         tables = 8 * (3 * lx * lx + 3 * lx + 3 * lm * lm + 3 * lm + lx * lm + 2 * lm + 9 + 2 * 4 + 3 + 2 * 2)
-        want = tables + E * lx ** 3 * (2 * 8 + pb) + 3 * 8 * E * lm ** 3 + 64 * E + 2 * 8 * nc
+        want = tables + E * lx ** 3 * (8 + (m + 2) * pb) + 3 * 8 * E * lm ** 3 + 64 * E + 2 * 8 * nc
         assert 0 <= (b.bytes - a.bytes) - want < 11 * 256, t
     for t in ("fp64", "fp32b", "fp32b+fp16", "fp32b+fp16a"):
         sem.Context(md, fd, sem.tier(t), bind=False)
