@@ -55,6 +55,31 @@ def test_hsmg_poisson_solve_matches_oracle(sem, nel, N):
     assert _rel(sol.cpu().numpy(), pref) < 1e-8
 
 
+@pytest.mark.parametrize("nel", [(64, 64, 2), (64, 2, 64)])
+def test_hsmg_poisson_largest_coarse_planes(sem, nel):
+    """64 elements in two directions: the coarse x-y plane (first case) or
+    x-z row set (second case) fills the 64 x 64 LDS tile of the coarse
+    passes exactly.  Cubic elements of edge 2 pi / 64 (the box is cut to
+    fit), order 4, tolerance 1e-10: counts within 1, solution within 1e-8
+    of the oracle's HSMG solve."""
+    N = 4
+    h = 2 * np.pi / 64
+    lo = tuple(-0.5 * h * n for n in nel)
+    hi = tuple(0.5 * h * n for n in nel)
+    c = sem.Context(sem.mesh_desc(nel, N, lo=lo, hi=hi),
+                    sem.flow_desc(mode=sem.MODE_POISSON, hsmg=1, pres_tol=1e-10, pres_maxit=2000), sem.tier("fp64"))
+    m = OracleMesh(nel, N, lo=lo, hi=hi)
+    H = OracleHSMG(m)
+    rhs = _rhs(m, nel, N, 9)
+    pref, itref, _ = H.poisson(rhs, tol=1e-10, maxit=2000)
+    sol = torch.empty(c.np, dtype=torch.float64, device="cuda:0")
+    st = sem.poisson_solve([c], [torch.from_numpy(rhs).to("cuda:0")], [sol])[0]
+    print(nel, "iters gpu", st["iters"], "oracle", itref)
+    assert st["status"] == 0
+    assert abs(st["iters"] - itref) <= 1
+    assert _rel(sol.cpu().numpy(), pref) < 1e-8
+
+
 def test_hsmg_poisson_fp32_basis(sem):
     """fp32b tier: the basis is stored in fp32 and the pressure operator runs in
     fp32; the HSMG arithmetic stays fp64.  The solution is the oracle's within
