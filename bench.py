@@ -347,7 +347,7 @@ def main():
                     help="requests of the serving leg (seeded TGV/Poisson stream; 0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the element-sharded "
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the element-sharded "
               "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

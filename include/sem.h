@@ -178,7 +178,7 @@ typedef struct {
  * weights, derivative matrix, shared-node lists).  Host only: no device
  * allocation and no HIP call.  Errors: SEM_EINVAL (invalid mesh, order,
  * flow parameters, or a precision above rp outside the SEM_X exceptions, or
- * a combination this build has no kernel for). */
+ * a combination the library has no kernel for). */
 int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_precision* prec, sem_ctx** out);
 
 /* Exact device bytes sem_bind needs for this context (geometry in every
