@@ -121,7 +121,34 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         auto w = fld<TV>(R, F_PW + c);
         A rr = 0, rz = 0;
         MulWalk mw(R, pr);
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x, mw.next()) {
+        // four of the thread's points per pass, every load before the first
+        // store (the stores could alias the loads in the compiler's view,
+        // which would serialise the points); same per-thread order of the sums
+        constexpr int U = 4;
+        const long long st = blockDim.x;
+        long long p = pr.p0 + threadIdx.x;
+        for (; p + (U - 1) * st < pr.p1; p += U * st) {
+            TV xv[U], pv[U], r0[U], wv[U], dv[U];
+            A im[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const long long q = p + u * st;
+                xv[u] = x[q]; pv[u] = pp[q]; r0[u] = r[q]; wv[u] = w[q]; dv[u] = idv[q];
+                im[u] = (A)mw.im();
+                mw.next();
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const long long q = p + u * st;
+                x[q] = xv[u] + alpha * pv[u];
+                const TV rv = r0[u] - alpha * wv[u];
+                const TV zv = rv * dv[u];
+                r[q] = rv; z[q] = zv;
+                rr += (A)(rv * rv) * im[u];
+                rz += (A)(rv * zv) * im[u];
+            }
+        }
+        for (; p < pr.p1; p += st, mw.next()) {
             x[p] += alpha * pp[p];
             const TV rv = r[p] - alpha * w[p];
             const TV zv = rv * idv[p];
