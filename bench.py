@@ -45,7 +45,7 @@ def gmres_j_sequence(iters, m):
 
 
 def run_tier(sem, torch, tier, nel, N, nu, dt, warmup, steps, prof_class=None, vtol=1e-6, ptol=1e-4, proj=0,
-             dealias=0, cfl=0.0, hsmg=0):
+             dealias=0, cfl=0.0, hsmg=0, graph=0):
     ctx = sem.Context(sem.mesh_desc(nel, N), sem.flow_desc(nu=nu, dt=dt, restart=30, vel_tol=vtol, pres_tol=ptol,
                                                            proj=proj, dealias=dealias, cfl=cfl, hsmg=hsmg),
                       sem.tier(tier))
@@ -54,16 +54,19 @@ def run_tier(sem, torch, tier, nel, N, nu, dt, warmup, steps, prof_class=None, v
     d0 = ctx.diagnostics()
     series.append((0.0, d0["ke"], d0["enst"], d0["maxdiv"]))
     if warmup:
-        for s in sem.fluid_step([ctx], warmup)[0]:
+        for s in sem.fluid_step([ctx], warmup, graph=bool(graph))[0]:
             series.append((s["t"], s["ke"], s["enst"], s["maxdiv"]))
             log("  %s warmup step t=%.4f its v=%s p=%d" % (tier, s["t"], s["vit"], s["pit"]))
     torch.cuda.synchronize()
     if prof_class:
         sem.prof_start(prof_class)
+    g0 = sem.graph_counters()
     t0 = time.perf_counter()
-    st = sem.fluid_step([ctx], steps)[0]
+    st = sem.fluid_step([ctx], steps, graph=bool(graph))[0]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    g1 = sem.graph_counters()
+    ctx.graph_counts = {"replays": g1[0] - g0[0], "reruns": g1[1] - g0[1], "captures": g1[2] - g0[2]}
     prof = sem.prof_stop() if prof_class else None
     for s in st:
         series.append((s["t"], s["ke"], s["enst"], s["maxdiv"]))
@@ -73,21 +76,21 @@ def run_tier(sem, torch, tier, nel, N, nu, dt, warmup, steps, prof_class=None, v
     return ctx, (t1 - t0), st, series, prof
 
 
-def ax_rate(sem, torch, ctx, dtype, geom, reps=20, nvec=2):
-    """Poisson-operator GDOF/s (HIP events, current stream).  The launches
-    cycle through nvec distinct input/output pairs so that no launch finds
-    its vectors in the last-level cache left by the previous one."""
+def ax_rate(sem, torch, ctx, dtype, geom, reps=20, nvec=2, h1=1.0, h2=0.0):
+    """Operator GDOF/s (HIP events, current stream).  The launches cycle
+    through nvec distinct input/output pairs so that no launch finds its
+    vectors in the last-level cache left by the previous one."""
     g = torch.Generator(device="cuda:0")
     g.manual_seed(0)
     us = [torch.randn(ctx.np, dtype=torch.float64, device="cuda:0", generator=g).to(dtype) for _ in range(nvec)]
     ws = [torch.empty_like(us[0]) for _ in range(nvec)]
     for q in range(nvec):
-        ctx.ax(us[q], ws[q], 1.0, 0.0, geom=geom)
+        ctx.ax(us[q], ws[q], h1, h2, geom=geom)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for r in range(reps):
-        ctx.ax(us[r % nvec], ws[r % nvec], 1.0, 0.0, geom=geom)
+        ctx.ax(us[r % nvec], ws[r % nvec], h1, h2, geom=geom)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -95,22 +98,79 @@ def ax_rate(sem, torch, ctx, dtype, geom, reps=20, nvec=2):
     return ctx.np / (ms * 1e-3) / 1e9, ms
 
 
+def dssum_rate(sem, torch, ctx, dtype, reps=20, nvec=2):
+    """Gather-scatter (dssum) time per launch, HIP events, nvec distinct vectors."""
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(1)
+    us = [torch.randn(ctx.np, dtype=torch.float64, device="cuda:0", generator=g).to(dtype) for _ in range(nvec)]
+    for q in range(nvec):
+        ctx.dssum(us[q])
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in range(reps):
+        ctx.dssum(us[r % nvec])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del us
+    return ms
+
+
 def ax_leg(sem, torch, inputs, nel=64, N=7):
     """The Ax microbenchmark workload: 64^3 elements N=7 (134 M points),
     sinusoidally deformed (amplitude 0.1 h, seeded phases), u ~ N(0,1)
-    seeded; Poisson operator in every storage tier (bytes per point: vectors
-    in and out + 6 geometric factors)."""
-    ctx = sem.Context(sem.mesh_desc((nel,) * 3, N, amp=0.1, phase=inputs.deform_phases()),
-                      sem.flow_desc(mode=sem.MODE_OPERATOR), sem.tier("fp32b+fp16all"))
-    out = {"workload": "Poisson operator, %d^3 elements N=%d (%d points), deformed amp 0.1 h, u ~ N(0,1); "
-                       "HIP events over 20 launches cycling through 2 vector pairs" % (nel, N, ctx.np)}
-    for name, dt, geom, bpp in (("fp64", torch.float64, sem.FP64, 64), ("fp32", torch.float32, sem.FP32, 32),
-                                ("fp32_fp16geom", torch.float32, sem.FP16, 20), ("fp16", torch.float16, sem.FP16, 16)):
-        gd, ms = ax_rate(sem, torch, ctx, dt, geom)
-        out[name] = {"gdof_per_s": gd, "ms": ms, "bytes_per_point": bpp, "hbm_GBps": gd * bpp,
-                     "frac": gd * bpp / HBM_PEAK_GBS}
-    del ctx
-    torch.cuda.empty_cache()
+    seeded; the operator in Poisson form in every storage tier and in
+    Helmholtz form (h1 = 1/1600, h2 = 11/6 / 5e-4) in fp64 and fp32 (bytes per
+    point: vectors in and out + 6 geometric factors, + B for Helmholtz), then
+    dssum of a vector in fp64 and fp32 (bytes per point: the shared fraction
+    of points read and written once, plus a 4-byte index each)."""
+    out = {"workload": "%d^3 elements N=%d (%d points), deformed amp 0.1 h, u ~ N(0,1); HIP events over 20 launches "
+                       "cycling through 2 vector pairs" % (nel, N, nel ** 3 * (N + 1) ** 3)}
+    for tier16, legs in (("fp32b+fp16all", (("fp64", torch.float64, sem.FP64, 64, 0),
+                                             ("fp32", torch.float32, sem.FP32, 32, 0),
+                                             ("fp32_fp16geom", torch.float32, sem.FP16, 20, 0),
+                                             ("fp16", torch.float16, sem.FP16, 16, 0),
+                                             ("fp64_helmholtz", torch.float64, sem.FP64, 72, 1),
+                                             ("fp32_helmholtz", torch.float32, sem.FP32, 36, 1))),
+                         ("fp32b+bf16all", (("bf16", torch.bfloat16, sem.BF16, 16, 0),
+                                            ("fp32_bf16geom", torch.float32, sem.BF16, 20, 0)))):
+        ctx = sem.Context(sem.mesh_desc((nel,) * 3, N, amp=0.1, phase=inputs.deform_phases()),
+                          sem.flow_desc(mode=sem.MODE_OPERATOR), sem.tier(tier16))
+        for name, dt, geom, bpp, helm in legs:
+            h1, h2 = (1.0 / 1600, 11.0 / 6.0 / 5e-4) if helm else (1.0, 0.0)
+            gd, ms = ax_rate(sem, torch, ctx, dt, geom, h1=h1, h2=h2)
+            out[name] = {"gdof_per_s": gd, "ms": ms, "bytes_per_point": bpp, "hbm_GBps": gd * bpp,
+                         "frac": gd * bpp / HBM_PEAK_GBS}
+        if tier16 == "fp32b+fp16all":
+            lx = N + 1
+            shared = 1.0 - ((lx - 2) / lx) ** 3
+            for name, dt, b in (("dssum_fp64", torch.float64, 8), ("dssum_fp32", torch.float32, 4)):
+                ms = dssum_rate(sem, torch, ctx, dt)
+                alg = ctx.np * shared * (2 * b + 4)
+                out[name] = {"ms": ms, "alg_bytes": alg, "hbm_GBps": alg / (ms * 1e-3) / 1e9,
+                             "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del ctx
+        torch.cuda.empty_cache()
+    return out
+
+
+def c4_leg(sem, torch, steps, tiers=("fp64", "fp32b", "fp32b+fp16"), graph=0):
+    """The higher-order workload: 16^3 elements, N = 11 (7.1 M points), Re 1600,
+    dt 2.5e-4, tolerances 1e-6 / 1e-4, HSMG; steps/s per tier, and each tier's
+    error metrics and max|div| against the oracle's stored series."""
+    nel, N, dt = 16, 11, 2.5e-4
+    ref = oracle_series(nel, N, dt, 1600.0, 1e-6, 1e-4, 1, 0, 0.0, 0)
+    out = {"workload": "TGV Re=1600, 16^3 elements, N=11 (7077888 local pts), dt=2.5e-4, HSMG, %d steps" % steps}
+    for t in tiers:
+        c, secs, st, ser, _ = run_tier(sem, torch, t, (nel,) * 3, N, 1.0 / 1600, dt, 0, steps, None, 1e-6, 1e-4,
+                                       0, 0, 0.0, 1, graph)
+        out[t] = {"steps_per_s": steps / secs, "max_div": max(r[3] for r in ser)}
+        if ref is not None:
+            out[t]["error_vs_oracle"] = error_vs_oracle(ser, ref)
+        del c
+        torch.cuda.synchronize()
+    out["speedup_vs_fp64"] = {t: out[t]["steps_per_s"] / out["fp64"]["steps_per_s"] for t in tiers if t != "fp64"}
     return out
 
 
@@ -272,6 +332,54 @@ def roofline(kind, tier, prof, steps, npts, workload, N=7, dealias=0):
             "alg_bytes_per_launch": alg / max(nlaunch, 1), "alg_bytes_total": alg}
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+# which operators of a step compute in which precision, by tier (the config string)
+TIER_NOTE = {
+    "fp64": "everything fp64",
+    "fp32b": "fp32: SEM operators (convection, opgrad), velocity operator and PCG vectors, GMRES basis and "
+             "projection storage; fp64: pressure-operator arithmetic (fp32-stored geometry), HSMG, weak divergence "
+             "of u*, GMRES orthogonalisation/dots/H, BDF/EXT state, residual checks, global reductions",
+    "fp32b-p32": "fp32: SEM operators, velocity operator and PCG vectors, pressure operator (arithmetic and "
+                 "storage), GMRES basis storage; fp64: HSMG, weak divergence of u*, GMRES orthogonalisation/dots/H, "
+                 "BDF/EXT state, residual checks, global reductions",
+    "fp32b+fp16": "fp32b with fp16-stored geometry in the velocity operator and opgrad (fp32 arithmetic)",
+}
+
+
+def oracle_series(nel, N, dt, re, vtol, ptol, hsmg, dealias, cfl, proj):
+    """The FP64 oracle's stored series of the same workload (written by
+    tests/golden/make_tgv_series.py, which runs only the CPU oracle), or None
+    when no stored series matches the workload."""
+    if dealias or cfl > 0 or proj or not hsmg:
+        return None
+    for name in ("tgv32_n7", "tgv16_n11"):
+        path = os.path.join(GOLDEN, "oracle_series_%s.json" % name)
+        if not os.path.exists(path):
+            continue
+        with open(path) as fh:
+            d = json.load(fh)
+        if (d["nel"], d["N"], d["dt"], d["re"], d["vel_tol"], d["pres_tol"]) == (nel, N, dt, re, vtol, ptol):
+            return d
+    return None
+
+
+def error_vs_oracle(series, ref):
+    """Sec. 4.2 error metrics of a GPU series (t, KE, enstrophy, max|div|) against
+    the oracle's series over the steps both hold (the denominators are the
+    maxima of the oracle series over those steps)."""
+    from oracle.metrics import e_max, e_peak
+    rows = ref["series"]
+    n = min(len(series), len(rows))
+    assert all(abs(series[k][0] - rows[k]["t"]) <= 1e-12 for k in range(n)), "time levels differ"
+    ke, ke_o = [series[k][1] for k in range(n)], [rows[k]["ke"] for k in range(n)]
+    en, en_o = [series[k][2] for k in range(n)], [rows[k]["enst"] for k in range(n)]
+    return {"e_E_max_pct": e_max(ke, ke_o), "e_Omega_max_pct": e_max(en, en_o),
+            "e_Omega_peak_pct": e_peak(en, en_o),
+            "max_div_diff": max(abs(series[k][3] - rows[k]["maxdiv"]) for k in range(n)),
+            "max_div_oracle": max(rows[k]["maxdiv"] for k in range(n)), "steps_compared": n - 1}
+
+
 def cpu_baseline(nel, N, nu, dt, pres_iters_per_step, restart=30, hsmg=0):
     """FP64 oracle on the host cores, on a bounded sample of the same workload.
 
@@ -312,6 +420,17 @@ def cpu_baseline(nel, N, nu, dt, pres_iters_per_step, restart=30, hsmg=0):
                          "first step is the estimate" % pres_iters_per_step)}
 
 
+def calib_copies(torch):
+    """Plain device copies of known size: what the PMC byte counters read for
+    exactly 1 GiB read + 1 GiB written per dispatch."""
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    b_ = torch.empty_like(a)
+    for _ in range(3):
+        b_.copy_(a)
+    torch.cuda.synchronize()
+    del a, b_
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,6 +454,8 @@ def main():
                     help="kernel class timed with HIP events for the roofline record (default: the dominant kernel)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with plain 1 GiB device copies (calibration of the PMC byte counters)")
+    ap.add_argument("--graph", type=int, default=0, choices=[0, 1],
+                    help="1: every step replayed as a HIP graph (sem_fluid_step_graph), in every tier")
     ap.add_argument("--tier", default="fp32b")
     ap.add_argument("--nel", type=int, default=32)
     ap.add_argument("--order", type=int, default=7)
@@ -343,8 +464,18 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ax", action="store_true")
-    ap.add_argument("--serve", type=int, default=64,
+    ap.add_argument("--ax-only", action="store_true",
+                    help="run only the operator/dssum leg on the 64^3 deformed mesh (for kernel profiling)")
+    ap.add_argument("--serve", type=int, default=256,
                     help="requests of the serving leg (seeded TGV/Poisson stream; 0 = skip)")
+    ap.add_argument("--serve-loads", default="0.4,0.7,1.0", help="serving: fractions of the saturated rate")
+    ap.add_argument("--serve-streams", type=int, default=4, help="serving: worker streams (host threads), 1..4")
+    ap.add_argument("--serve-graph", type=int, default=1, choices=[0, 1],
+                    help="serving: TGV steps replayed as HIP graphs")
+    ap.add_argument("--p32-leg", type=int, default=1, choices=[0, 1],
+                    help="also run the fp32b-p32 tier (fp32 pressure operator) on the headline workload")
+    ap.add_argument("--c4-steps", type=int, default=400,
+                    help="steps of the 16^3, N = 11 leg in fp64, fp32b and fp32b+fp16 (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the element-sharded "
@@ -355,6 +486,13 @@ def main():
     from paper_2608_24348_amd import sem
     from oracle.metrics import e_max, e_peak
     sem.load()
+    if args.ax_only:
+        from paper_2608_24348_amd import inputs
+        res = {"ax_gdofs": ax_leg(sem, torch, inputs)}
+        if args.calib_copy:
+            calib_copies(torch)
+        print(json.dumps(res), flush=True)
+        return
     nel = (args.nel,) * 3
     N = args.order
     nu = 1.0 / args.re
@@ -368,15 +506,16 @@ def main():
                   "gm_upd_norm": sem.PROF_GM_UPD_NORM, "conv": sem.PROF_CONV, "hsmg": sem.PROF_HSMG,
                   "none": None}[args.prof]
     ctx, t_mx, st_mx, ser_mx, prof = run_tier(sem, torch, args.tier, nel, N, nu, dt, args.warmup, args.steps, prof_class,
-                                              args.vtol, args.ptol, args.proj, args.dealias, args.cfl, args.hsmg)
+                                              args.vtol, args.ptol, args.proj, args.dealias, args.cfl, args.hsmg,
+                                              args.graph)
     steps_s = args.steps / t_mx
     out = {"metric": METRIC, "value": steps_s, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * t_mx / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if args.tier != "fp64" else "f64",
            "data": "synthetic",
-           "config": {"workload": "TGV Re=%g, %d^3 elements, N=%d (%d local pts), dt=%g, tier %s (fp64 state, "
-                                  "GMRES orthogonalisation and residual checks)%s" % (args.re, args.nel, N, npts, dt,
-                                                                                     args.tier,
+           "config": {"workload": "TGV Re=%g, %d^3 elements, N=%d (%d local pts), dt=%g, tier %s (%s)%s"
+                                  % (args.re, args.nel, N, npts, dt, args.tier,
+                                     TIER_NOTE.get(args.tier, "see sem.tier"),
                                                                                      (", dealiased convection"
                                                                                       if args.dealias else "")
                                                                                      + (", adaptive dt CFL %g" % args.cfl
@@ -386,6 +525,9 @@ def main():
                                                                                         ", Jacobi pressure preconditioner")),
                       "global_batch": 1, "seq_len": npts, "parallelism": "single-gpu"}}
     out["iters"] = {"vel": [s["vit"] for s in st_mx], "pres": [s["pit"] for s in st_mx]}
+    out["step_launch"] = "hip graph per step (sem_fluid_step_graph)" if args.graph else "host-driven (sem_fluid_step)"
+    if args.graph:
+        out["graph_counts"] = ctx.graph_counts
     if args.cfl > 0:
         dts = [s["dt"] for s in st_mx]
         out["adaptive_dt"] = {"cfl_target": args.cfl, "dt_min": min(dts), "dt_max": max(dts),
@@ -401,7 +543,8 @@ def main():
 
     if not args.no_fp64:
         ctx64, t64, st64, ser64, _ = run_tier(sem, torch, "fp64", nel, N, nu, dt, args.warmup, args.steps, None,
-                                              args.vtol, args.ptol, args.proj, args.dealias, args.cfl, args.hsmg)
+                                              args.vtol, args.ptol, args.proj, args.dealias, args.cfl, args.hsmg,
+                                              args.graph)
         out["fp64_steps_per_s"] = args.steps / t64
         out["speedup_vs_fp64"] = steps_s / (args.steps / t64)
         ke_mx = [r[1] for r in ser_mx]
@@ -414,6 +557,25 @@ def main():
                                     "steps_compared": len(ke64)}
         out["iters_fp64"] = {"vel": [s["vit"] for s in st64], "pres": [s["pit"] for s in st64]}
         del ctx64
+    ref = oracle_series(args.nel, N, dt, args.re, args.vtol, args.ptol, args.hsmg, args.dealias, args.cfl, args.proj)
+    if args.p32_leg and args.tier == "fp32b" and not args.no_fp64:
+        # the tier as the workload names it: fp32 pressure operator as well
+        c32, t32, st32, ser32, _ = run_tier(sem, torch, "fp32b-p32", nel, N, nu, dt, args.warmup, args.steps, None,
+                                            args.vtol, args.ptol, args.proj, args.dealias, args.cfl, args.hsmg,
+                                            args.graph)
+        leg = {"tier": "fp32b-p32", "note": TIER_NOTE["fp32b-p32"], "steps_per_s": args.steps / t32,
+               "speedup_vs_fp64": (args.steps / t32) / out["fp64_steps_per_s"],
+               "pres_iters_mean": sum(s["pit"] for s in st32) / len(st32)}
+        if ref is not None:
+            leg["error_vs_oracle"] = error_vs_oracle(ser32, ref)
+        out["p32_leg"] = leg
+        del c32
+    if ref is not None:
+        ev = {"reference": "FP64 CPU oracle series, tests/golden/oracle_series_%s.json" % ref["workload"],
+              args.tier: error_vs_oracle(ser_mx, ref)}
+        if not args.no_fp64:
+            ev["fp64"] = error_vs_oracle(ser64, ref)
+        out["error_vs_oracle"] = ev
     del ctx
     torch.cuda.synchronize()
     if not args.no_fp64 and args.other_pc:
@@ -425,7 +587,8 @@ def main():
         sers = {}
         for t in (args.tier, "fp64"):
             c_h, t_h, st_h, ser_h, _ = run_tier(sem, torch, t, nel, N, nu, dt, args.warmup, args.steps, None,
-                                                args.vtol, args.ptol, args.proj, args.dealias, args.cfl, other)
+                                                args.vtol, args.ptol, args.proj, args.dealias, args.cfl, other,
+                                                args.graph)
             leg[t] = {"steps_per_s": args.steps / t_h,
                       "pres_iters_mean": sum(s["pit"] for s in st_h) / len(st_h)}
             sers[t] = ser_h
@@ -442,32 +605,35 @@ def main():
         torch.cuda.empty_cache()
         log("ax: 64^3 deformed mesh, every storage tier")
         out["ax_gdofs"] = ax_leg(sem, torch, inputs)
+    if args.c4_steps > 0:
+        log("c4: 16^3 elements N=11, %d steps per tier" % args.c4_steps)
+        out["c4"] = c4_leg(sem, torch, args.c4_steps, graph=args.graph)
     if args.serve > 0:
         from paper_2608_24348_amd import serve
-        log("serving: %d requests, burst then Poisson arrivals at 0.7x the burst rate" % args.serve)
-        sv = serve.measure(args.serve, loads=(0.7,), log=log)
-        sat, mid = sv["saturated"], sv["load_0.7"]
+        loads = tuple(float(x) for x in args.serve_loads.split(","))
+        log("serving: %d requests, burst then Poisson arrivals at %s x the burst rate" % (args.serve, loads))
+        sv = serve.measure(args.serve, loads=loads, log=log, streams=args.serve_streams, graph=bool(args.serve_graph))
+        sat = sv["saturated"]
         out["serving"] = {"requests": args.serve, "stream_seed": sv["seed"],
                           "workload": "TGV (20 steps) and Poisson (tol 1e-8) requests, n 4-24, N 5/7/9, "
                                       "Re 100-1600, tiers fp64/fp32b, HSMG where the order allows (>= 4), "
                                       "batched by (order, tier, kind, preconditioner)",
+                          "streams": args.serve_streams, "graph_steps": bool(args.serve_graph),
                           "saturated_requests_per_s": sat["requests_per_s"], "saturated_gdof_per_s": sat["gdof_per_s"],
-                          "qps": mid["qps"], "p50_s": mid.get("p50_s"), "p99_s": mid.get("p99_s"),
-                          "gdof_per_s": mid["gdof_per_s"], "ok": mid["ok"]}
+                          "saturated_ok": sat["ok"]}
+        for f in loads:
+            r = sv["load_%.1f" % f]
+            out["serving"]["load_%.1f" % f] = {"qps": r["qps"], "p50_s": r.get("p50_s"), "p99_s": r.get("p99_s"),
+                                               "requests_per_s": r["requests_per_s"], "gdof_per_s": r["gdof_per_s"],
+                                               "ok": r["ok"]}
     if not args.no_cpu:
         log("cpu baseline: oracle sample of the same workload")
         pbar = sum(s["pit"] for s in st_mx) / len(st_mx)
         out["cpu_baseline"] = cpu_baseline(nel, N, nu, dt, pbar, hsmg=args.hsmg)
     if args.calib_copy:
-        # plain device copies of known size: what the PMC byte counters read for
-        # exactly 1 GiB read + 1 GiB written per dispatch
-        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
-        b_ = torch.empty_like(a)
-        for _ in range(3):
-            b_.copy_(a)
-        torch.cuda.synchronize()
-        del a, b_
-    out["time_breakdown_note"] = "value = %d timed steps / wall time of sem_fluid_step (HIP event profiling of one kernel class on)" % args.steps
+        calib_copies(torch)
+    out["time_breakdown_note"] = ("value = %d timed steps / wall time of %s (HIP event profiling of one kernel class on)"
+                                  % (args.steps, "sem_fluid_step_graph" if args.graph else "sem_fluid_step"))
     print(json.dumps(out), flush=True)
 
 

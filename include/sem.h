@@ -214,6 +214,34 @@ int sem_dssum(sem_ctx* ctx, void* u, int buf_prec);
  * reported in its stats and keeps no influence on the others. */
 int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stats);
 
+/* The same steps with each step replayed as a HIP graph (the step of Fig. 3
+ * captured once per batch and iteration budget, then launched with one call
+ * and one synchronisation).  The budgets (PCG iterations per refinement cycle,
+ * refinement cycles, Arnoldi steps) are the largest counts of the batch's
+ * previous step (pressure: of its last four steps); every solver kernel is
+ * gated on the device as in sem_fluid_step, so a request whose solves stop
+ * within the budgets gets bitwise the results of sem_fluid_step.  A request
+ * still iterating at the end of a budget has its correction, lag rotation and
+ * diagnostics gated off on the device and its step run again by
+ * sem_fluid_step's host-driven path, so results never depend on the budgets.
+ * A request's first step, and batches with adaptive dt (whose step history
+ * changes at the step's start), always take the host-driven path.  Graphs are
+ * cached per batch (up to 32) and dropped by sem_destroy of any member. */
+int sem_fluid_step_graph(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stats);
+
+/* Process-wide counts since load: graph replays, requests whose replayed step
+ * ran again on the host-driven path, graph captures (all nullable). */
+int sem_graph_counters(int64_t* replays, int64_t* reruns, int64_t* captures);
+
+/* The library's host lock (recursive; acquire = 1 locks, 0 unlocks, on the
+ * calling thread).  A step capture in one thread fails if another thread makes
+ * a device-synchronising HIP call meanwhile (allocating or freeing device or
+ * pinned memory, a copy on the legacy stream).  sem_fluid_step_graph captures
+ * under this lock, and sem_bind, sem_destroy and the library's own pinned
+ * allocations take it; a caller that makes such calls itself from another
+ * thread while graph steps run takes it around them. */
+int sem_host_lock(int acquire);
+
 /* Periodic Poisson solves A p = rhs for n POISSON- or FLUID-mode contexts of
  * the same order and policy: rhs[i] (device, fp64, assembled) has its
  * unique-node mean removed, GMRES runs from zero, and sol[i] (device, fp64)
@@ -231,7 +259,6 @@ int sem_poisson_solve(sem_ctx* const* ctxs, int n, const void* const* rhs, void*
 int sem_poisson_begin(sem_ctx* const* ctxs, int n, const void* const* rhs);
 int sem_poisson_advance(sem_ctx* const* ctxs, int n, int max_iters, int* active);
 int sem_poisson_finish(sem_ctx* ctx, void* sol, sem_solve_stats* st);
-
 /* Field access for checkpoints and tests.  which: SEM_F_*; component fields
  * use which + c.  src/dst are fp64 arrays of E*lx^3 values, on the host when
  * is_host != 0 (the call then synchronises), else device pointers. */

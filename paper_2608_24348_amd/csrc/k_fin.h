@@ -91,6 +91,7 @@ static __device__ __noinline__ void fin_body(ReqDesc* R, int ri, const FinArgs a
     SEM_GLOBAL double* S = gp(R->S);
     SEM_GLOBAL int* I = gp(R->I);
     const int t = threadIdx.x;
+    if (a.gate2 >= 0 && !I[a.gate2]) return;  // uniform per workgroup
     switch (a.op) {
     case FIN_VINIT: {
         for (int c = 0; c < 3; ++c) {
@@ -280,6 +281,18 @@ static __device__ __noinline__ void fin_body(ReqDesc* R, int ri, const FinArgs a
         if (t == 0 && I[I_PRADD]) I[I_PRL] += 1;
         break;
     }
+    case FIN_COMMIT_CHECK: {
+        // a captured step runs a fixed number of iterations: its correction,
+        // lag rotation and projection update run only where every solve
+        // stopped by itself within them (converged, hit its limit or met a
+        // non-finite value); elsewhere the host re-runs the step
+        if (t == 0) {
+            const int done = !(I[I_VACT] | I[I_VACT + 1] | I[I_VACT + 2] | I[I_GACT]);
+            I[I_COMMIT] = I[I_COMMIT + 1] = I[I_COMMIT + 2] = done;
+            if (!done) I[I_PRADD] = 0;
+        }
+        break;
+    }
     case FIN_DIAG: {
         double ke = slot_sum(R, R_X0, red);
         double en = slot_sum(R, R_X1, red);
@@ -403,6 +416,7 @@ static __device__ __noinline__ void fin_body(ReqDesc* R, int ri, const FinArgs a
             if (I[I_VREF + 2] > o[14]) o[14] = I[I_VREF + 2];
             o[15] = I[I_ORDER];
             o[16] = S[S_DT]; o[17] = S[S_CFL];
+            o[18] = I[I_COMMIT];
         }
         break;
     }

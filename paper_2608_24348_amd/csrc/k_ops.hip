@@ -42,6 +42,7 @@ __device__ __forceinline__ C melem_scale(const ReqDesc* R, int e)
     const int g = blockIdx.x;                             \
     const int ri = find_req(bt.eb, bt.n, g);              \
     const ReqDesc* R = bt.r[ri];                          \
+    if (!gate_ok(R, bt.gate)) return;                     \
     const int blk = g - bt.eb[ri];                        \
     const int t = threadIdx.x;                            \
     const int el = t / L2;                                \

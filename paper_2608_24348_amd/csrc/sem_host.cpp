@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <memory>
@@ -31,6 +32,13 @@ int fail(int code, const std::string& msg)
     g_err = msg;
     return code;
 }
+
+// Stream capture in one host thread is invalidated by device-synchronising
+// HIP calls in another (allocations and frees of device or pinned memory,
+// copies on the legacy stream).  The library makes such calls only under this
+// lock, which a capture holds throughout (with the graph cache), and exports
+// it (sem_host_lock) to callers that make such calls from other threads.
+std::recursive_mutex g_host_mu;
 
 #define HIPCHK(call)                                                                          \
     do {                                                                                      \
@@ -383,10 +391,15 @@ struct sem_ctx {
     ReqDesc* ddesc = nullptr;
     ReqDesc hdesc;
     int* hflags = nullptr;  // pinned host flags for polls
+    int device = 0;         // HIP device current at sem_bind
     MeshParams mp;
     // iteration counts of the previous step: where the host first reads the
     // convergence flags (launches past convergence are gated no-ops)
     int pred_v = 4, pred_p = 4;
+    // the last steps' counts, for the iteration budgets of a captured step:
+    // PCG iterations (largest component), refinement cycles, and the pressure
+    // iterations of the last four steps (hist_n of them valid)
+    int hist_v = 0, hist_c = 0, hist_p[4] = {0, 0, 0, 0}, hist_n = 0;
 };
 
 namespace {
@@ -651,6 +664,7 @@ semk::Batch make_batch(sem_ctx* const* ctxs, int n)
     b.gs[0] = 0;
     b.el[0] = 0;
     b.hm[0] = 0;
+    b.gate = -1;
     b.ncmax = 0;
     b.cnmax = 0;
     for (int i = 0; i < n; ++i) {
@@ -690,6 +704,16 @@ int poll_k()
     return k;
 }
 
+// Largest iteration limit over a batch: the host loops run until every
+// request has stopped by itself (each request's own limit is applied on the
+// device), so a small limit of one request never truncates another's solve.
+int batch_maxit(sem_ctx* const* ctxs, int n, bool pressure)
+{
+    int k = 0;
+    for (int i = 0; i < n; ++i) k = std::max(k, pressure ? ctxs[i]->flow.pres_maxit : ctxs[i]->flow.vel_maxit);
+    return k;
+}
+
 int first_chunk(sem_ctx* const* ctxs, int n, bool pressure)
 {
     int k = 1;
@@ -703,12 +727,24 @@ struct Prof {
     std::vector<hipEvent_t> ev;  // pairs
     size_t used = 0;             // events used (2 per launch)
     std::vector<hipStream_t> st;
+    // A captured step cannot hold event records, so while a step is captured
+    // each mark of the armed class ends the current graph segment and starts
+    // the next (split_hook): the profiled launches become segments of their
+    // own, and a replay records an event pair around each of them (acc).
+    void (*split_hook)(void*) = nullptr;
+    void* split_arg = nullptr;
+    double acc_ms = 0.0;
+    int64_t acc_n = 0;
 };
 Prof g_prof;
 
 void prof_mark(int kclass, hipStream_t s)
 {
     if (g_prof.kclass != kclass) return;
+    if (g_prof.split_hook) {
+        g_prof.split_hook(g_prof.split_arg);
+        return;
+    }
     if (g_prof.used == g_prof.ev.size()) {
         for (int q = 0; q < 256; ++q) {
             hipEvent_t e;
@@ -766,14 +802,17 @@ void vec(const Batch& b, int op, int ncomp, int tv, int gate, hipStream_t s, int
     if (fin_op >= 0) {
         FinArgs f;
         f.op = fin_op; f.gate = -1; f.ncomp = 1; f.f0 = 0; f.host_flags = nullptr; f.host_stats = nullptr;
+        f.gate2 = -1;
         launch_fin(b, f, s);
     }
 }
 
-void fin(const Batch& b, int op, hipStream_t s, int gate = -1, int ncomp = 1, int* flags = nullptr, int f0 = 0)
+void fin(const Batch& b, int op, hipStream_t s, int gate = -1, int ncomp = 1, int* flags = nullptr, int f0 = 0,
+         int gate2 = -1)
 {
     FinArgs a;
-    a.op = op; a.gate = gate; a.ncomp = ncomp; a.f0 = f0; a.host_flags = flags;
+    a.op = op; a.gate = gate; a.ncomp = ncomp; a.f0 = f0; a.host_flags = flags; a.host_stats = nullptr;
+    a.gate2 = gate2;
     launch_fin(b, a, s);
 }
 
@@ -788,6 +827,22 @@ int poll(const Batch& b, int gate, int ncomp, int* hflags, hipStream_t s)
     int cnt = 0;
     for (int i = 0; i < b.n; ++i) cnt += hflags[i] != 0;
     return cnt;
+}
+
+// One Jacobi-PCG iteration of the three velocity components of every request
+// (gated per component on I_VACT: converged components idle)
+void pcg_iteration(const Batch& b, int lx, const Resolved& r, int tv, hipStream_t s)
+{
+    {
+        ProfScope ps(SEM_PROF_AX_VEL, s);
+        // alpha = rho / (p, w): the dot of a continuous p with dssum(w_L)
+        // equals the plain local sum of p w_L, formed before the dssum
+        ax(b, lx, F_PP, F_PW, 3, S_H1, 0, 0, -1, R_A, I_VACT, tv, r.axv_g, r.axv_c, s);
+    }
+    launch_dssum(b, F_PW, 3, tv, I_VACT, nullptr, s);
+    fin(b, FIN_PCG_ALPHA, s);
+    vec(b, V_PCG_UPD, 3, tv, I_VACT, s, -1, -1, r.tva, P64, FIN_PCG_BETA);
+    vec(b, V_PCG_P, 3, tv, I_VACT, s);
 }
 
 // Jacobi-PCG on the assembled velocity Helmholtz operator for the three
@@ -810,7 +865,9 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
     }
     launch_dssum(b, F_R64, 3, P64, -1, nullptr, s);
     vec(b, V_VRESID, 3, P64, -1, s, -1, -1, P64, P64, FIN_VINIT);
-    const int maxref = c0->flow.vel_max_refine;
+    const int vmax = batch_maxit(ctxs, b.n, false);
+    int maxref = 0;
+    for (int i = 0; i < b.n; ++i) maxref = std::max(maxref, ctxs[i]->flow.vel_max_refine);
     for (int cyc = 0; cyc < maxref; ++cyc) {
         if (cyc > 0) {
             // the first cycle runs without a read: if the initial residual
@@ -823,23 +880,12 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
         int K = first_chunk(ctxs, b.n, false);
         int guard = 0;
         for (;;) {
-            for (int q = 0; q < K; ++q) {
-                {
-                    ProfScope ps(SEM_PROF_AX_VEL, s);
-                    // alpha = rho / (p, w): the dot of a continuous p with dssum(w_L)
-                    // equals the plain local sum of p w_L, formed before the dssum
-                    ax(b, lx, F_PP, F_PW, 3, S_H1, 0, 0, -1, R_A, I_VACT, tv, r.axv_g, r.axv_c, s);
-                }
-                launch_dssum(b, F_PW, 3, tv, I_VACT, nullptr, s);
-                fin(b, FIN_PCG_ALPHA, s);
-                vec(b, V_PCG_UPD, 3, tv, I_VACT, s, -1, -1, r.tva, P64, FIN_PCG_BETA);
-                vec(b, V_PCG_P, 3, tv, I_VACT, s);
-            }
+            for (int q = 0; q < K; ++q) pcg_iteration(b, lx, r, tv, s);
             guard += K;
             K = poll_k();
             int a2 = poll(b, I_VACT, 3, hf, s);
             if (a2 < 0) return a2;
-            if (a2 == 0 || guard > c0->flow.vel_maxit + K) break;
+            if (a2 == 0 || guard > vmax + K) break;
         }
         vec(b, V_US_ADD, 3, tv, -1, s, cyc == 0 ? 1 : 0);
         if (tv == P64) break;  // fp64 recurrence residual is the solver's stop criterion
@@ -976,27 +1022,33 @@ void projection_guess(const Batch& b, const Resolved& r, hipStream_t s)
 
 // After the solve: the correction GX - guess (the whole GX when the space is
 // full and restarts) is A-orthogonalised against the space with the fp64
-// operator and appended unless dependent.
-void projection_update(const Batch& b, int lx, const Resolved& r, hipStream_t s)
+// operator and appended unless dependent.  gate: I index that must be nonzero
+// for a request to update its space (the commit flag of a captured step), or -1.
+void projection_update(const Batch& b, int lx, const Resolved& r, hipStream_t s, int gate = -1)
 {
-    fin(b, FIN_PR_POST, s);
-    vec(b, V_PR_V, 1, P64, -1, s);
+    fin(b, FIN_PR_POST, s, -1, 1, nullptr, 0, gate);
+    vec(b, V_PR_V, 1, P64, gate, s);
     {
         ProfScope ps(SEM_PROF_AX_PRESID, s);
-        ax(b, lx, F_GW, F_GWD, 1, -1, 1.0, 0.0, -1, -1, -1, P64, P64, P64, s);
+        ax(b, lx, F_GW, F_GWD, 1, -1, 1.0, 0.0, -1, -1, gate, P64, P64, P64, s);
     }
-    launch_dssum(b, F_GWD, 1, P64, -1, nullptr, s);
-    vec(b, V_PR_BDOTS, 1, P64, -1, s, -1, -1, P64, r.tb, FIN_PR_BETA);
+    launch_dssum(b, F_GWD, 1, P64, gate, nullptr, s);
+    vec(b, V_PR_BDOTS, 1, P64, gate, s, -1, -1, P64, r.tb);
+    fin(b, FIN_PR_BETA, s, -1, 1, nullptr, 0, gate);
+    // (FIN_COMMIT_CHECK cleared I_PRADD where the step is not committed)
     vec(b, V_PR_ORTH, 1, P64, I_PRADD, s, -1, -1, P64, r.tb);
-    fin(b, FIN_PR_COMMIT, s);
+    fin(b, FIN_PR_COMMIT, s, -1, 1, nullptr, 0, gate);
 }
 
-int pressure_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
+// use_proj: the fluid step's pressure solve updates the projection space of
+// its contexts; stand-alone Poisson solves leave it alone
+int pressure_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s, bool use_proj)
 {
     sem_ctx* c0 = ctxs[0];
     const int m = c0->flow.gmres_restart;
-    const int limit = c0->flow.pres_maxit + c0->flow.pres_maxit / std::max(1, m) + 4;
-    const bool proj = c0->flow.mode == SEM_MODE_FLUID && c0->flow.proj_dim > 0;
+    const int pmax = batch_maxit(ctxs, b.n, true);
+    const int limit = pmax + pmax / std::max(1, m) + 4;
+    const bool proj = use_proj && c0->flow.mode == SEM_MODE_FLUID && c0->flow.proj_dim > 0;
     gmres_start(b, c0->lx, c0->rs, c0->flow.hsmg != 0, s);
     int rc = gmres_advance(ctxs, b, s, limit, true);
     if (rc < 0) return rc;
@@ -1004,6 +1056,8 @@ int pressure_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
     gmres_finish(b, s);
     return check_hip_last();
 }
+
+void graph_forget(const sem_ctx* c);  // cached step graphs of c (defined with them below)
 
 int bind_check(sem_ctx* c)
 {
@@ -1164,12 +1218,14 @@ int sem_sizes(const sem_ctx* c, int64_t* np, int64_t* nglob, int* lx, int* nelem
 
 int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
 {
+    std::lock_guard<std::recursive_mutex> lk(g_host_mu);
     if (!c || !dev_buf) return fail(SEM_EINVAL, "null argument");
     if (c->bound) return fail(SEM_ESTATE, "context already bound");
     if (bytes < c->bytes) return fail(SEM_ENOMEM, "workspace smaller than sem_workspace_bytes");
     if (((uintptr_t)dev_buf) & 255) return fail(SEM_EINVAL, "workspace must be 256-byte aligned");
     c->dev = (char*)dev_buf;
     c->stream = (hipStream_t)hip_stream;
+    HIPCHK(hipGetDevice(&c->device));
     hipStream_t s = c->stream;
     ReqDesc& d = c->hdesc;
     memset(&d, 0, sizeof(d));
@@ -1263,7 +1319,8 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     }
     HIPCHK(hipStreamSynchronize(s));
     int nanflag = 0;
-    HIPCHK(hipMemcpy(&nanflag, d.I + I_NAN, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(&nanflag, d.I + I_NAN, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
     if (nanflag) return fail(SEM_EINVAL, "non-positive Jacobian in the mesh");
     return 0;
 }
@@ -1271,6 +1328,8 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
 void sem_destroy(sem_ctx* c)
 {
     if (!c) return;
+    std::lock_guard<std::recursive_mutex> lk(g_host_mu);
+    graph_forget(c);
     if (c->hflags) (void)hipHostFree(c->hflags);
     delete c;
 }
@@ -1301,7 +1360,8 @@ int field_of(const sem_ctx* c, int which, int& fid)
 int current_ptr(sem_ctx* c, int fid, char** out)
 {
     void* p = nullptr;
-    HIPCHK(hipMemcpy(&p, &c->ddesc->f[fid], sizeof(void*), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(&p, &c->ddesc->f[fid], sizeof(void*), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     *out = (char*)p;
     return 0;
 }
@@ -1378,96 +1438,441 @@ static int check_batch(sem_ctx* const* ctxs, int n, int min_mode)
     return 0;
 }
 
-static double* stats_buffer()
+}  // extern "C"
+
+namespace {
+
+// pinned host buffer the statistics kernel writes (one per host thread, so
+// batches on different streams can step from different threads)
+double* stats_buffer()
 {
-    static double* buf = nullptr;
+    thread_local double* buf = nullptr;
     if (!buf) {
+        std::lock_guard<std::recursive_mutex> lk(g_host_mu);
         if (hipHostMalloc((void**)&buf, sizeof(double) * SEM_MAXB * SEM_NSTAT, hipHostMallocDefault) != hipSuccess)
             buf = nullptr;
     }
     return buf;
 }
 
-int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stats)
+void launch_stats(const Batch& b, double* hs, hipStream_t s)
+{
+    FinArgs fa;
+    fa.op = FIN_STATS; fa.gate = -1; fa.ncomp = 1; fa.f0 = 0; fa.host_flags = nullptr; fa.host_stats = hs;
+    fa.gate2 = -1;
+    launch_fin(b, fa, s);
+}
+
+// explicit terms of a step and the residual of its velocity solve (both paths)
+void step_head(const Batch& b, const sem_ctx* c0, hipStream_t s)
+{
+    const int lx = c0->lx;
+    const Resolved& r = c0->rs;
+    fin(b, FIN_STEP_BEGIN, s);
+    vec(b, V_IDV, 1, P64, I_IDVSTALE, s);
+    // (i) explicit terms: convection, old pressure gradient, BDF/EXT history
+    convection(b, c0, s);
+    launch_opgrad(b, lx, r.opg_m, r.opg_c, F_P, F_GP, s);
+    vec(b, V_RHS, 1, P64, -1, s);  // local rhs (3 components), assembled together with the residual
+}
+
+// (iii) pressure increment: A phi = (beta0/dt) dssum(wdiv(u*)), zero-mean rhs.
+// This rhs is the initial residual of the pressure solve (phi = 0): it is
+// formed in fp64 like every residual check, because the weak divergence of a
+// nearly divergence-free u* is a small difference of large element terms
+// whose fp32 rounding would dominate it.
+void pressure_rhs(const Batch& b, const sem_ctx* c0, hipStream_t s)
+{
+    const int lx = c0->lx;
+    launch_wdiv(b, lx, P64, P64, F_US, F_RP, s);
+    launch_dssum(b, F_RP, 1, P64, -1, nullptr, s);
+    vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_RP, -1, P64, P64, FIN_MEAN_UNIQUE);
+    vec(b, V_SUB_MEAN, 1, P64, -1, s, F_RP, S_H2);  // F_GB aliases F_RP
+    if (c0->flow.proj_dim > 0) projection_guess(b, c0->rs, s);
+    else vec(b, V_ZERO, 1, P64, -1, s, F_GX);
+}
+
+// (iv) correction and pressure update, lag rotation, diagnostics; gate: the
+// commit flag of a captured step, or -1
+void step_tail(const Batch& b, const sem_ctx* c0, hipStream_t s, int gate)
+{
+    const int lx = c0->lx;
+    const Resolved& r = c0->rs;
+    Batch bg = b;
+    bg.gate = gate;
+    launch_opgrad(bg, lx, r.opg_m, r.opg_c, F_GX, F_GP, s);
+    launch_dssum(b, F_GP, 3, P64, gate, nullptr, s);
+    vec(b, V_CORRECT, 1, P64, gate, s);  // 3 components and p += phi
+    fin(b, FIN_STEP_END, s, -1, 1, nullptr, 0, gate);
+    launch_diagnostics(bg, lx, s);
+    fin(b, FIN_DIAG, s, -1, 1, nullptr, 0, gate);
+}
+
+// One step of a batch driven from the host: the solver loops read the device
+// convergence flags between iteration chunks.  Writes the statistics into hs.
+int eager_step(sem_ctx* const* ctxs, const Batch& b, double* hs, hipStream_t s)
+{
+    sem_ctx* c0 = ctxs[0];
+    step_head(b, c0, s);
+    // (ii) velocity Helmholtz solves -> u*
+    int rc = velocity_solve(ctxs, b, s);
+    if (rc) return rc;
+    pressure_rhs(b, c0, s);
+    rc = pressure_solve(ctxs, b, s, true);
+    if (rc) return rc;
+    step_tail(b, c0, s, -1);
+    launch_stats(b, hs, s);
+    return check_hip_last();
+}
+
+// Iteration budgets of a captured step: PCG iterations per refinement cycle,
+// refinement cycles, Arnoldi steps.
+struct Budget {
+    int kv, cyc, kp;
+    bool operator<(const Budget& o) const { return std::tie(kv, cyc, kp) < std::tie(o.kv, o.cyc, o.kp); }
+};
+
+// One step with fixed iteration budgets and no host reads, in the order of
+// eager_step.  Every solver kernel is gated on the device as in the host-driven
+// path (a converged request idles), so a request whose solves stop by
+// themselves within the budgets gets bitwise the results of eager_step; its
+// commit flag is set.  Where a solve is still iterating at the end of its
+// budget the flag stays clear and the correction, the lag rotation, the
+// projection update and the diagnostics are gated off: the state is that of
+// the step's start and the host runs the step again with eager_step.
+void fixed_step(sem_ctx* const* ctxs, const Batch& b, const Budget& g, double* hs, hipStream_t s)
+{
+    sem_ctx* c0 = ctxs[0];
+    const int lx = c0->lx;
+    const Resolved& r = c0->rs;
+    const int tv = r.tv;
+    const bool hsmg = c0->flow.hsmg != 0;
+    step_head(b, c0, s);
+    {
+        ProfScope ps(SEM_PROF_AX_RESID, s);
+        resid_ax(b, lx, F_U, s);
+    }
+    launch_dssum(b, F_R64, 3, P64, -1, nullptr, s);
+    vec(b, V_VRESID, 3, P64, -1, s, -1, -1, P64, P64, FIN_VINIT);
+    const int ncyc = tv == P64 ? 1 : std::max(1, g.cyc);
+    for (int cyc = 0; cyc < ncyc; ++cyc) {
+        vec(b, V_PCG_INIT, 3, tv, -1, s, -1, -1, r.tva, P64, FIN_PCG_RHO);
+        for (int q = 0; q < g.kv; ++q) pcg_iteration(b, lx, r, tv, s);
+        vec(b, V_US_ADD, 3, tv, -1, s, cyc == 0 ? 1 : 0);
+        if (tv == P64) break;
+        {
+            ProfScope ps(SEM_PROF_AX_RESID, s);
+            resid_ax(b, lx, F_US, s);
+        }
+        launch_dssum(b, F_R64, 3, P64, -1, nullptr, s);
+        vec(b, V_VRESID, 3, P64, -1, s, -1, -1, P64, P64, FIN_VINIT);
+    }
+    pressure_rhs(b, c0, s);
+    gmres_start(b, lx, r, hsmg, s);
+    const int m = c0->flow.gmres_restart;
+    for (int q = 0; q < g.kp; ++q) {
+        gmres_arnoldi(b, lx, r, hsmg, s);
+        if ((q + 1) % m == 0 || q == g.kp - 1) gmres_cycle_end(b, lx, r, hsmg, s);
+    }
+    fin(b, FIN_COMMIT_CHECK, s);
+    if (c0->flow.mode == SEM_MODE_FLUID && c0->flow.proj_dim > 0) projection_update(b, lx, r, s, I_COMMIT);
+    gmres_finish(b, s);
+    step_tail(b, c0, s, I_COMMIT);
+    launch_stats(b, hs, s);
+}
+
+// A captured step of one batch and budget: the instantiated graph, its pinned
+// statistics buffer and the profiling events recorded in it.
+struct StepGraph {
+    // the step as one graph, or, while a kernel class is profiled, as segments
+    // split at that class's launches (timed[q]: segment q is one such launch)
+    std::vector<hipGraph_t> graph;
+    std::vector<hipGraphExec_t> exec;
+    std::vector<char> timed;
+    std::vector<hipEvent_t> ev;   // an event pair per timed segment
+    double* hs = nullptr;
+    uint64_t last_use = 0;
+    // capture state
+    hipStream_t cs = nullptr;
+    bool in_timed = false;
+    hipError_t err = hipSuccess;
+    StepGraph() = default;
+    StepGraph(const StepGraph&) = delete;
+    StepGraph& operator=(const StepGraph&) = delete;
+    ~StepGraph()
+    {
+        for (hipGraphExec_t x : exec) (void)hipGraphExecDestroy(x);
+        for (hipGraph_t g : graph) (void)hipGraphDestroy(g);
+        if (hs) (void)hipHostFree(hs);
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    // close the segment being captured (kept if it holds any node)
+    void close_segment()
+    {
+        hipGraph_t g = nullptr;
+        const hipError_t le = hipGetLastError();
+        const hipError_t e = hipStreamEndCapture(cs, &g);
+        if (err == hipSuccess) err = le != hipSuccess ? le : e;
+        if (e != hipSuccess || !g) return;
+        size_t nn = 0;
+        (void)hipGraphGetNodes(g, nullptr, &nn);
+        if (nn == 0) { (void)hipGraphDestroy(g); return; }
+        graph.push_back(g);
+        timed.push_back(in_timed ? 1 : 0);
+    }
+    void open_segment()
+    {
+        const hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (err == hipSuccess) err = e;
+    }
+    static void split(void* self)
+    {
+        StepGraph* G = (StepGraph*)self;
+        G->close_segment();
+        G->in_timed = !G->in_timed;
+        G->open_segment();
+    }
+};
+struct GraphKey {
+    std::vector<const sem_ctx*> ctxs;
+    Budget g;
+    int prof;
+    bool operator<(const GraphKey& o) const { return std::tie(ctxs, g, prof) < std::tie(o.ctxs, o.g, o.prof); }
+};
+// shared ownership: a graph evicted or forgotten while another thread replays
+// it lives until that replay's reference is dropped
+std::map<GraphKey, std::shared_ptr<StepGraph>> g_graphs;
+uint64_t g_graph_clock = 0;
+// process-wide counts: graph replays, requests whose replayed step ran again
+// eagerly, captures
+std::atomic<int64_t> g_n_replay{0}, g_n_rerun{0}, g_n_capture{0};
+#define SEM_GRAPH_CACHE 32
+
+// drop every cached graph that launches work of context c
+void graph_forget(const sem_ctx* c)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_host_mu);
+    for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+        if (std::find(it->first.ctxs.begin(), it->first.ctxs.end(), c) != it->first.ctxs.end()) {
+            it = g_graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+// capture stream of the calling thread on the current device (default priority)
+int capture_stream(int dev, hipStream_t* out)
+{
+    thread_local std::map<int, hipStream_t> streams;
+    auto it = streams.find(dev);
+    if (it != streams.end()) { *out = it->second; return 0; }
+    hipStream_t st;
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    streams[dev] = st;
+    *out = st;
+    return 0;
+}
+
+// the cached graph of this batch and budget, captured on first use
+int get_graph(sem_ctx* const* ctxs, int n, const Batch& b, const Budget& g, std::shared_ptr<StepGraph>* out)
+{
+    GraphKey key;
+    key.ctxs.assign(ctxs, ctxs + n);
+    key.g = g;
+    key.prof = g_prof.kclass;
+    std::lock_guard<std::recursive_mutex> lk(g_host_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) {
+        it->second->last_use = ++g_graph_clock;
+        *out = it->second;
+        return 0;
+    }
+    if (g_graphs.size() >= SEM_GRAPH_CACHE) {
+        auto lru = g_graphs.begin();
+        for (auto jt = g_graphs.begin(); jt != g_graphs.end(); ++jt)
+            if (jt->second->last_use < lru->second->last_use) lru = jt;
+        g_graphs.erase(lru);
+    }
+    auto Gp = std::make_shared<StepGraph>();
+    StepGraph& G = *Gp;
+    HIPCHK(hipHostMalloc((void**)&G.hs, sizeof(double) * SEM_MAXB * SEM_NSTAT, hipHostMallocDefault));
+    int rc = capture_stream(ctxs[0]->device, &G.cs);
+    if (rc) return rc;
+    G.open_segment();
+    if (G.err != hipSuccess) return fail(SEM_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(G.err));
+    if (g_prof.kclass) {
+        g_prof.split_hook = &StepGraph::split;
+        g_prof.split_arg = &G;
+    }
+    fixed_step(ctxs, b, g, G.hs, G.cs);
+    g_prof.split_hook = nullptr;
+    g_prof.split_arg = nullptr;
+    G.close_segment();
+    if (G.err != hipSuccess) return fail(SEM_EHIP, std::string("step capture failed: ") + hipGetErrorString(G.err));
+    for (size_t q = 0; q < G.graph.size(); ++q) {
+        hipGraphExec_t x = nullptr;
+        hipError_t e = hipGraphInstantiate(&x, G.graph[q], nullptr, nullptr, 0);
+        if (e != hipSuccess) return fail(SEM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        G.exec.push_back(x);
+        if (G.timed[q]) {
+            for (int k = 0; k < 2; ++k) {
+                hipEvent_t ev;
+                HIPCHK(hipEventCreate(&ev));
+                G.ev.push_back(ev);
+            }
+        }
+    }
+    G.last_use = ++g_graph_clock;
+    g_n_capture++;
+    g_graphs.emplace(key, Gp);
+    *out = Gp;
+    return 0;
+}
+
+// statistics of request c from its row o of the statistics buffer
+int take_stats(sem_ctx* c, const double* o, sem_step_stats* ss)
+{
+    int sti = SEM_OK;
+    if (o[12] != 0.0) sti = SEM_ENAN;
+    else if (o[11] > c->flow.pres_tol) sti = SEM_ENOTCONV;
+    else
+        for (int q = 0; q < 3; ++q)
+            if (o[7 + q] > c->flow.vel_tol) sti = SEM_ENOTCONV;
+    if (ss) {
+        ss->t = o[0]; ss->ke = o[1]; ss->enst = o[2]; ss->maxdiv = o[3];
+        for (int q = 0; q < 3; ++q) { ss->vel_iters[q] = (int)o[4 + q]; ss->vel_res[q] = o[7 + q]; }
+        ss->pres_iters = (int)o[10];
+        ss->pres_res = o[11];
+        ss->status = sti;
+        ss->vel_cycles = (int)o[14];
+        ss->dt = o[16];
+        ss->cfl = o[17];
+    }
+    const int vmax = (int)std::max(o[4], std::max(o[5], o[6]));
+    c->pred_v = std::max(1, vmax);
+    c->pred_p = std::max(1, (int)o[10]);
+    c->hist_v = vmax;
+    c->hist_c = (int)o[14];
+    for (int q = 3; q > 0; --q) c->hist_p[q] = c->hist_p[q - 1];
+    c->hist_p[0] = (int)o[10];
+    c->hist_n = std::min(c->hist_n + 1, 4);
+    return sti;
+}
+
+// budgets of a captured step from the batch's history (largest counts of the
+// last step, and of the last four steps for the pressure); false while a
+// request has no history yet
+bool graph_budget(sem_ctx* const* ctxs, int n, Budget* g)
+{
+    Budget b{0, 1, 0};
+    for (int i = 0; i < n; ++i) {
+        const sem_ctx* c = ctxs[i];
+        if (c->hist_n == 0) return false;
+        b.kv = std::max(b.kv, c->hist_v);
+        b.cyc = std::max(b.cyc, c->hist_c);
+        for (int q = 0; q < c->hist_n; ++q) b.kp = std::max(b.kp, c->hist_p[q]);
+    }
+    b.kv = std::max(b.kv, 1);
+    *g = b;
+    return true;
+}
+
+int fluid_steps(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stats, bool graph)
 {
     int rc = check_batch(ctxs, n, SEM_MODE_FLUID);
     if (rc) return rc;
     if (nsteps < 0) return fail(SEM_EINVAL, "nsteps must be >= 0");
     sem_ctx* c0 = ctxs[0];
-    const int lx = c0->lx;
-    const Resolved& r = c0->rs;
     hipStream_t s = c0->stream;
     Batch b = make_batch(ctxs, n);
     double* hs = stats_buffer();
     if (!hs) return fail(SEM_EHIP, "pinned statistics buffer allocation failed");
-    int status = 0;
+    // adaptive dt changes the step's history at its start: such batches step eagerly
+    if (c0->flow.cfl_target > 0.0) graph = false;
     if (c0->flow.cfl_target > 0.0 && nsteps > 0) {
         // the CFL rate of the current velocity (it may have been set since the last step)
-        launch_diagnostics(b, lx, s);
+        launch_diagnostics(b, c0->lx, s);
         fin(b, FIN_DIAG, s);
     }
     for (int st = 0; st < nsteps; ++st) {
-        fin(b, FIN_STEP_BEGIN, s);
-        vec(b, V_IDV, 1, P64, I_IDVSTALE, s);
-        // (i) explicit terms: convection, old pressure gradient, BDF/EXT history
-        convection(b, c0, s);
-        launch_opgrad(b, lx, r.opg_m, r.opg_c, F_P, F_GP, s);
-        vec(b, V_RHS, 1, P64, -1, s);  // local rhs (3 components), assembled together with the residual
-        // (ii) velocity Helmholtz solves -> u*
-        rc = velocity_solve(ctxs, b, s);
-        if (rc) return rc;
-        // (iii) pressure increment: A phi = (beta0/dt) dssum(wdiv(u*)), zero-mean rhs.
-        // This rhs is the initial residual of the pressure solve (phi = 0): it
-        // is formed in fp64 like every residual check, because the weak
-        // divergence of a nearly divergence-free u* is a small difference of
-        // large element terms whose fp32 rounding would dominate it.
-        launch_wdiv(b, lx, P64, P64, F_US, F_RP, s);
-        launch_dssum(b, F_RP, 1, P64, -1, nullptr, s);
-        vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_RP, -1, P64, P64, FIN_MEAN_UNIQUE);
-        vec(b, V_SUB_MEAN, 1, P64, -1, s, F_RP, S_H2);  // F_GB aliases F_RP
-        if (c0->flow.proj_dim > 0) projection_guess(b, r, s);
-        else vec(b, V_ZERO, 1, P64, -1, s, F_GX);
-        rc = pressure_solve(ctxs, b, s);
-        if (rc) return rc;
-        // (iv) correction and pressure update, lag rotation, diagnostics
-        launch_opgrad(b, lx, r.opg_m, r.opg_c, F_GX, F_GP, s);
-        launch_dssum(b, F_GP, 3, P64, -1, nullptr, s);
-        vec(b, V_CORRECT, 1, P64, -1, s);  // 3 components and p += phi
-        fin(b, FIN_STEP_END, s);
-        launch_diagnostics(b, lx, s);
-        fin(b, FIN_DIAG, s);
-        FinArgs fa;
-        fa.op = FIN_STATS; fa.gate = -1; fa.ncomp = 1; fa.f0 = 0; fa.host_flags = nullptr; fa.host_stats = hs;
-        launch_fin(b, fa, s);
-        rc = check_hip_last();
-        if (rc) return rc;
+        Budget g;
+        std::shared_ptr<StepGraph> G;
+        if (graph && graph_budget(ctxs, n, &g)) {
+            rc = get_graph(ctxs, n, b, g, &G);
+            if (rc) return rc;
+        }
+        if (!G) {
+            if ((rc = eager_step(ctxs, b, hs, s))) return rc;
+            HIPCHK(hipStreamSynchronize(s));
+            for (int i = 0; i < n; ++i)
+                take_stats(ctxs[i], hs + (size_t)i * SEM_NSTAT, stats ? &stats[(size_t)i * nsteps + st] : nullptr);
+            continue;
+        }
+        size_t te = 0;
+        for (size_t q = 0; q < G->exec.size(); ++q) {
+            if (G->timed[q]) HIPCHK(hipEventRecord(G->ev[te], s));
+            HIPCHK(hipGraphLaunch(G->exec[q], s));
+            if (G->timed[q]) HIPCHK(hipEventRecord(G->ev[te + 1], s));
+            if (G->timed[q]) te += 2;
+        }
         HIPCHK(hipStreamSynchronize(s));
-        for (int i = 0; i < n; ++i) {
-            const double* o = hs + (size_t)i * SEM_NSTAT;
-            sem_ctx* c = ctxs[i];
-            int sti = SEM_OK;
-            if (o[12] != 0.0) sti = SEM_ENAN;
-            else if (o[11] > c->flow.pres_tol) sti = SEM_ENOTCONV;
-            else
-                for (int q = 0; q < 3; ++q)
-                    if (o[7 + q] > c->flow.vel_tol) sti = SEM_ENOTCONV;
-            if (sti && !status) status = sti;
-            if (stats) {
-                sem_step_stats& ss = stats[(size_t)i * nsteps + st];
-                ss.t = o[0]; ss.ke = o[1]; ss.enst = o[2]; ss.maxdiv = o[3];
-                for (int q = 0; q < 3; ++q) { ss.vel_iters[q] = (int)o[4 + q]; ss.vel_res[q] = o[7 + q]; }
-                ss.pres_iters = (int)o[10];
-                ss.pres_res = o[11];
-                ss.status = sti;
-                ss.vel_cycles = (int)o[14];
-                ss.dt = o[16];
-                ss.cfl = o[17];
+        g_n_replay++;
+        for (size_t q = 0; q + 1 < te; q += 2) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, G->ev[q], G->ev[q + 1]) == hipSuccess) {
+                g_prof.acc_ms += ms;
+                g_prof.acc_n += 1;
             }
-            c->pred_v = std::max(1, (int)std::max(o[4], std::max(o[5], o[6])));
-            c->pred_p = std::max(1, (int)o[10]);
+        }
+        // requests whose solves did not finish within the budgets run the step again
+        sem_ctx* redo[SEM_MAXB];
+        int where[SEM_MAXB];
+        int nr = 0;
+        for (int i = 0; i < n; ++i) {
+            const double* o = G->hs + (size_t)i * SEM_NSTAT;
+            if (o[18] == 0.0) { redo[nr] = ctxs[i]; where[nr++] = i; continue; }
+            take_stats(ctxs[i], o, stats ? &stats[(size_t)i * nsteps + st] : nullptr);
+        }
+        if (nr) {
+            g_n_rerun += nr;
+            Batch br = make_batch(redo, nr);
+            if ((rc = eager_step(redo, br, hs, s))) return rc;
+            HIPCHK(hipStreamSynchronize(s));
+            for (int q = 0; q < nr; ++q)
+                take_stats(redo[q], hs + (size_t)q * SEM_NSTAT,
+                           stats ? &stats[(size_t)where[q] * nsteps + st] : nullptr);
         }
     }
-    (void)status;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sem_fluid_step(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stats)
+{
+    return fluid_steps(ctxs, n, nsteps, stats, false);
+}
+
+int sem_fluid_step_graph(sem_ctx* const* ctxs, int n, int nsteps, sem_step_stats* stats)
+{
+    return fluid_steps(ctxs, n, nsteps, stats, true);
+}
+
+int sem_host_lock(int acquire)
+{
+    if (acquire) g_host_mu.lock();
+    else g_host_mu.unlock();
+    return 0;
+}
+
+int sem_graph_counters(int64_t* replays, int64_t* reruns, int64_t* captures)
+{
+    if (replays) *replays = g_n_replay.load();
+    if (reruns) *reruns = g_n_rerun.load();
+    if (captures) *captures = g_n_capture.load();
     return 0;
 }
 
@@ -1486,7 +1891,7 @@ int sem_poisson_solve(sem_ctx* const* ctxs, int n, const void* const* rhs, void*
     vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_GB, -1, P64, P64, FIN_MEAN_UNIQUE);
     vec(b, V_SUB_MEAN, 1, P64, -1, s, F_GB, -1);
     vec(b, V_ZERO, 1, P64, -1, s, F_GX);
-    rc = pressure_solve(ctxs, b, s);
+    rc = pressure_solve(ctxs, b, s, false);
     if (rc) return rc;
     for (int i = 0; i < n; ++i)
         HIPCHK(hipMemcpyAsync(sol[i], ctxs[i]->hdesc.f[F_GX], 8 * (size_t)ctxs[i]->np, hipMemcpyDeviceToDevice, s));
@@ -1567,6 +1972,8 @@ int sem_prof_start(int kclass)
     if (kclass < SEM_PROF_AX_VEL || kclass > SEM_PROF_HSMG) return fail(SEM_EINVAL, "unknown profiling class");
     g_prof.kclass = kclass;
     g_prof.used = 0;
+    g_prof.acc_ms = 0.0;
+    g_prof.acc_n = 0;
     return 0;
 }
 
@@ -1580,10 +1987,15 @@ int sem_prof_stop(double* total_ms, int64_t* launches)
         HIPCHK(hipEventElapsedTime(&ms, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]));
         tot += ms;
     }
+    // plus the launches recorded inside replayed step graphs
+    tot += g_prof.acc_ms;
+    const int64_t ng = g_prof.acc_n;
     g_prof.kclass = 0;
     g_prof.used = 0;
+    g_prof.acc_ms = 0.0;
+    g_prof.acc_n = 0;
     if (total_ms) *total_ms = tot;
-    if (launches) *launches = (int64_t)n;
+    if (launches) *launches = (int64_t)n + ng;
     return 0;
 }
 
@@ -1605,22 +2017,30 @@ int sem_get_field(sem_ctx* c, int which, void* dst, int is_host)
         const int nc = fid == F_G64 ? 6 : 9;
         std::vector<double> tmp((size_t)c->np * nc);
         HIPCHK(hipStreamSynchronize(c->stream));
-        HIPCHK(hipMemcpy(tmp.data(), p, 8 * tmp.size(), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpyAsync(tmp.data(), p, 8 * tmp.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
         std::vector<double> out((size_t)c->np);
         for (long long e = 0; e < c->E; ++e)
             memcpy(out.data() + e * L3, tmp.data() + (e * nc + (long long)off) * L3, 8 * L3);
         if (is_host) memcpy(dst, out.data(), 8 * out.size());
-        else HIPCHK(hipMemcpy(dst, out.data(), 8 * out.size(), hipMemcpyHostToDevice));
+        else {
+            HIPCHK(hipMemcpyAsync(dst, out.data(), 8 * out.size(), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+        }
         return 0;
     }
     if (fid == F_IBSUM64) {
         // stored as 1/Bsum
         std::vector<double> out((size_t)c->np);
         HIPCHK(hipStreamSynchronize(c->stream));
-        HIPCHK(hipMemcpy(out.data(), p, 8 * out.size(), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpyAsync(out.data(), p, 8 * out.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
         for (auto& v : out) v = 1.0 / v;
         if (is_host) memcpy(dst, out.data(), 8 * out.size());
-        else HIPCHK(hipMemcpy(dst, out.data(), 8 * out.size(), hipMemcpyHostToDevice));
+        else {
+            HIPCHK(hipMemcpyAsync(dst, out.data(), 8 * out.size(), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+        }
         return 0;
     }
     if (is_host) {

@@ -170,7 +170,8 @@ enum IntId : int {
     I_PRL,                      // projection: vectors in the space
     I_PRFULL,                   // projection: the space was full and restarts from the whole solution
     I_PRADD,                    // projection: the new vector is independent and will be appended
-    I_PCNT,                     // NRED: number of partials the last producer of each slot wrote
+    I_COMMIT,                   // 3 (equal): the step's solves finished, its results may be committed
+    I_PCNT = I_COMMIT + 3,      // NRED: number of partials the last producer of each slot wrote
     NINT = I_PCNT + NRED + 8
 };
 
@@ -215,6 +216,8 @@ struct Batch {
     int gs[SEM_MAXB + 1];       // prefix over shared-node chunks
     int el[SEM_MAXB + 1];       // prefix over elements (one-element-per-workgroup kernels)
     int hm[SEM_MAXB + 1];       // prefix over HSMG middle-level blocks (hs_mepb elements each)
+    int gate;                   // element operators (conv, opgrad, wdiv, diagnostics): I index that must
+                                // be nonzero for a request's blocks to run, or -1
     int ncmax;                  // largest coarse HSMG grid (nx ny nz) of the batch
     int cnmax;                  // largest ny or nz of the batch (coarse-pass workgroups)
     const ReqDesc* r[SEM_MAXB];
@@ -389,15 +392,17 @@ enum FinOp : int {
     FIN_PR_POST,      // a full space restarts (l = 0, I_PRFULL)
     FIN_PR_BETA,      // beta_i = s_i (X_i, A v); ||v_orth||_A^2 = (v, A v) - sum beta_i^2; I_PRADD, s_l
     FIN_PR_COMMIT,    // l += I_PRADD
+    FIN_COMMIT_CHECK, // I_COMMIT = no velocity component and no GMRES solve still iterating
     NFINOP
 };
 
-#define SEM_NSTAT 18
+#define SEM_NSTAT 19
 
 struct FinArgs {
     int op, gate, ncomp, f0;
     int* host_flags;
     double* host_stats;
+    int gate2;        // I index that must be nonzero for the op to run on a request, or -1
 };
 
 void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s);

@@ -78,7 +78,7 @@ EXPORTS = ["sem_setup", "sem_workspace_bytes", "sem_bind", "sem_ax", "sem_dssum"
            "sem_poisson_solve", "sem_get_field", "sem_set_field", "sem_set_clock", "sem_diagnostics",
            "sem_conv", "sem_opgrad", "sem_wdiv", "sem_sizes", "sem_destroy", "sem_strerror", "sem_last_error",
            "sem_prof_start", "sem_prof_stop", "sem_poisson_begin", "sem_poisson_advance", "sem_poisson_finish",
-           "sem_mass", "sem_node_field", "sem_copy_state"]
+           "sem_mass", "sem_node_field", "sem_copy_state", "sem_fluid_step_graph", "sem_graph_counters", "sem_host_lock"]
 PROF_AX_VEL, PROF_AX_PRES, PROF_GM_DOTS, PROF_GM_UPD_DOTS, PROF_GM_UPD_NORM, PROF_DSSUM_PRES, PROF_AX_ANY, PROF_AX_RESID, \
     PROF_AX_PRESID, PROF_CONV, PROF_HSMG = range(1, 12)
 
@@ -105,6 +105,9 @@ def load():
     L.sem_ax.argtypes = [vp, vp, vp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int]
     L.sem_dssum.argtypes = [vp, vp, C.c_int]
     L.sem_fluid_step.argtypes = [C.POINTER(vp), C.c_int, C.c_int, C.POINTER(StepStats)]
+    L.sem_fluid_step_graph.argtypes = [C.POINTER(vp), C.c_int, C.c_int, C.POINTER(StepStats)]
+    L.sem_graph_counters.argtypes = [C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.sem_host_lock.argtypes = [C.c_int]
     L.sem_poisson_solve.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveStats)]
     L.sem_get_field.argtypes = [vp, C.c_int, vp, C.c_int]
     L.sem_set_field.argtypes = [vp, C.c_int, vp, C.c_int]
@@ -378,15 +381,38 @@ def _stats_dict(s):
             "vcyc": s.vel_cycles, "dt": s.dt, "cfl": s.cfl}
 
 
-def fluid_step(ctxs, nsteps=1):
-    """Advance a batch of fluid contexts by nsteps; returns per-context lists of step stats."""
+def fluid_step(ctxs, nsteps=1, graph=False):
+    """Advance a batch of fluid contexts by nsteps (graph: each step replayed as
+    a HIP graph, sem_fluid_step_graph); returns per-context lists of step stats."""
     if isinstance(ctxs, Context):
         ctxs = [ctxs]
     n = len(ctxs)
     arr = (C.c_void_p * n)(*[c.h for c in ctxs])
     st = (StepStats * (n * max(nsteps, 1)))()
-    _check(load().sem_fluid_step(arr, n, int(nsteps), st))
+    fn = load().sem_fluid_step_graph if graph else load().sem_fluid_step
+    _check(fn(arr, n, int(nsteps), st))
     return [[_stats_dict(st[i * nsteps + k]) for k in range(nsteps)] for i in range(n)]
+
+
+class host_lock:
+    """Context manager holding the library's host lock (sem_host_lock): wrap
+    device allocations, frees and legacy-stream work made from one thread while
+    another may be running graph steps."""
+
+    def __enter__(self):
+        _check(load().sem_host_lock(1))
+        return self
+
+    def __exit__(self, *exc):
+        load().sem_host_lock(0)
+        return False
+
+
+def graph_counters():
+    """(graph replays, requests re-run on the host-driven path, captures) since load."""
+    a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(load().sem_graph_counters(C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
 
 
 def prof_start(kclass):

@@ -52,14 +52,28 @@ class Request:
         self.result = None
         self.ops = 0          # operator applications performed
         self.bytes = 0
+        self.ctx_points = 0
         self.stats = []
+
+
+class _Worker:
+    """One host thread and one HIP stream (default priority).  It owns the batch
+    keys assigned to it and runs their rounds one after another; the workers
+    run concurrently, so batches of different keys overlap on the device."""
+
+    def __init__(self, idx, stream):
+        self.idx = idx
+        self.stream = stream
+        self.keys = collections.deque()   # keys owned, round-robin order
+        self.load = 0                     # local points of its active requests
 
 
 class Server:
     """Runs a list of request specs (see inputs.request_stream) to completion."""
 
     def __init__(self, budget_bytes=None, max_batch=16, gmres_chunk=30, device="cuda:0", vel_tol=1e-6,
-                 pres_tol=1e-4, poisson_tol=1e-8, keep_fields=False, policy="rr", tgv_steps=1, hsmg=1):
+                 pres_tol=1e-4, poisson_tol=1e-8, keep_fields=False, policy="rr", tgv_steps=1, hsmg=1,
+                 streams=4, graph=True):
         import torch
         self.torch = torch
         self.device = device
@@ -76,13 +90,15 @@ class Server:
         self.pres_tol = pres_tol
         self.poisson_tol = poisson_tol  # Poisson requests
         self.keep_fields = keep_fields
-        # next batch key: "rr" round robin over keys with work, "oldest" the key
-        # holding the longest-waiting active request
+        # next batch key of a worker: "rr" round robin over its keys with work,
+        # "oldest" the key holding its longest-waiting active request
         if policy not in ("rr", "oldest"):
             raise ValueError("policy must be 'rr' or 'oldest'")
         self.policy = policy
         self.tgv_steps = max(1, int(tgv_steps))  # fluid steps per round of a TGV batch
         self.hsmg = 1 if hsmg else 0                # HSMG pressure preconditioner where a request allows it
+        self.nstreams = max(1, min(int(streams), 4))
+        self.graph = bool(graph)                    # TGV steps replayed as HIP graphs
         self.used = 0
 
     # ---------------------------------------------------------------- request life cycle
@@ -96,23 +112,31 @@ class Server:
                             bind=False)
         r.bytes = r.ctx.bytes + 256
 
-    def _admit(self, r, now):
+    def _admit(self, r, now, w):
         torch = self.torch
-        r.ctx.bind(self.device)
-        self.used += r.bytes
-        r.t_admit = now
-        if r.kind == "poisson":
-            # manufactured rhs: f = 3 sin x sin y sin z + noise (seeded N(0,1) per local point)
-            f = r.ctx.node_field(3, 3.0)
-            g = torch.Generator(device=self.device)
-            g.manual_seed(int(r.spec["noise_seed"]))
-            f.add_(torch.randn(r.ctx.np, dtype=torch.float64, device=self.device, generator=g),
-                   alpha=float(r.spec["noise"]))
-            rhs = r.ctx.mass(f, assemble=True)
-            sem.poisson_begin([r.ctx], [rhs])
-            del f, rhs
+        # workspace, geometry and rhs are made on the stream of the worker that
+        # owns the request's key, ahead of that worker's use of them, under the
+        # library's host lock (no worker captures a step graph meanwhile)
+        with sem.host_lock(), torch.cuda.stream(w.stream):
+            r.ctx.bind(self.device, stream=w.stream)
+            r.t_admit = now
+            if r.kind == "poisson":
+                # manufactured rhs: f = 3 sin x sin y sin z + noise (seeded N(0,1) per local point)
+                f = r.ctx.node_field(3, 3.0)
+                g = torch.Generator(device=self.device)
+                g.manual_seed(int(r.spec["noise_seed"]))
+                f.add_(torch.randn(r.ctx.np, dtype=torch.float64, device=self.device, generator=g),
+                       alpha=float(r.spec["noise"]))
+                rhs = r.ctx.mass(f, assemble=True)
+                sem.poisson_begin([r.ctx], [rhs])
+                w.stream.synchronize()
+                del f, rhs
 
     def _retire(self, r, now, status):
+        with sem.host_lock():
+            self._retire_locked(r, now, status)
+
+    def _retire_locked(self, r, now, status):
         r.t_done = now
         r.status = status
         if self.keep_fields:
@@ -124,90 +148,168 @@ class Server:
                 r.result = {"p": sol.cpu().numpy(), "stats": st}
         elif r.kind == "poisson":
             r.result = {"stats": sem.poisson_finish(r.ctx, None)}
-        self.used -= r.bytes
         r.ctx.close()
         r.ctx = None
 
+    # ---------------------------------------------------------------- one round of a worker
+    def _round(self, key, batch):
+        """One unit of work for a batch (runs without the lock); returns the
+        requests that finished, each with its status."""
+        ctxs = [r.ctx for r in batch]
+        out = []
+        if key[2] == "tgv":
+            # as many steps as the batch's requests all still need, at most tgv_steps
+            k = min([self.tgv_steps] + [r.spec["steps"] - r.steps_done for r in batch])
+            st = sem.fluid_step(ctxs, k, graph=self.graph)
+            for r, ss in zip(batch, st):
+                bad = 0
+                for s in ss:
+                    r.steps_done += 1
+                    r.stats.append(s)
+                    r.ops += sum(s["vit"]) + s["pit"] + (6 if r.spec["tier"] != "fp64" else 3) + 1
+                    bad = bad or s["status"]
+                if bad != 0 or r.steps_done >= r.spec["steps"]:
+                    out.append((r, "ok" if bad == 0 else "status%d" % bad))
+        else:
+            flags = sem.poisson_advance(ctxs, self.gmres_chunk)
+            for r, a in zip(batch, flags):
+                if not a:
+                    out.append((r, "ok"))
+        return out
+
     # ---------------------------------------------------------------- main loop
     def run(self, specs, log=None):
+        import threading
+        torch = self.torch
         reqs = [Request(s, self.hsmg) for s in sorted(specs, key=lambda s: s["arrival"])]
         pending = collections.deque(reqs)
         waiting = collections.deque()
-        active = collections.OrderedDict()
-        keys_rr = collections.deque()
-        t0 = time.perf_counter()
+        active = collections.OrderedDict()   # key -> admitted requests
+        owner = {}                           # key -> worker
+        workers = [_Worker(i, torch.cuda.Stream(device=self.device)) for i in range(self.nstreams)]
+        cv = threading.Condition()
         done = []
-        rounds = 0
-        while pending or waiting or any(active.values()):
-            now = time.perf_counter() - t0
-            while pending and pending[0].spec["arrival"] <= now:
-                r = pending.popleft()
-                r.t_arrival = r.spec["arrival"]
-                self._setup(r)
-                waiting.append(r)
-            # FIFO admission under the HBM budget
-            while waiting and self.used + waiting[0].bytes <= self.budget:
-                r = waiting.popleft()
-                self._admit(r, time.perf_counter() - t0)
-                active.setdefault(r.key, []).append(r)
-                if r.key not in keys_rr:
-                    keys_rr.append(r.key)
-            if not any(active.values()):
-                if waiting and self.used == 0:
-                    # larger than the whole budget: reject instead of deadlocking
-                    r = waiting.popleft()
-                    r.t_done = time.perf_counter() - t0
-                    r.status = "rejected"
-                    r.ctx.close()
-                    done.append(r)
+        state = {"rounds": 0, "error": None, "stop": False}
+        t0 = time.perf_counter()
+
+        def clock():
+            return time.perf_counter() - t0
+
+        def worker_loop(w):
+            try:
+                while True:
+                    with cv:
+                        while not state["stop"] and not any(active.get(k) for k in w.keys):
+                            cv.wait()
+                        if state["stop"]:
+                            return
+                        keys = [k for k in w.keys if active.get(k)]
+                        if self.policy == "oldest":
+                            key = min(keys, key=lambda k: active[k][0].t_arrival)
+                        else:
+                            while not active.get(w.keys[0]):
+                                w.keys.rotate(-1)
+                            key = w.keys[0]
+                            w.keys.rotate(-1)
+                        batch = active[key][:self.max_batch]
+                        state["rounds"] += 1
+                        rnd = state["rounds"]
+                    finished = self._round(key, batch)
+                    now = clock()
+                    for r, status in finished:
+                        self._retire(r, now, status)
+                        if r.kind == "poisson":
+                            st = r.result["stats"]
+                            r.ops += st["iters"] + 2
+                            if st["status"] != 0:
+                                r.status = "status%d" % st["status"]
+                    with cv:
+                        for r, _ in finished:
+                            active[key].remove(r)
+                            self.used -= r.bytes
+                            w.load -= r.ctx_points
+                            done.append(r)
+                        cv.notify_all()
+                    if log and rnd % 50 == 0:
+                        log("round %d t=%.2fs active=%d waiting=%d done=%d used=%.1f GB"
+                            % (rnd, now, sum(len(v) for v in active.values()), len(waiting), len(done),
+                               self.used / 1e9))
+            except BaseException as e:  # surface worker failures in the main thread
+                with cv:
+                    state["error"] = e
+                    state["stop"] = True
+                    cv.notify_all()
+
+        threads = [threading.Thread(target=worker_loop, args=(w,), daemon=True) for w in workers]
+        for th in threads:
+            th.start()
+        try:
+            while True:
+                with cv:
+                    if state["error"] is not None:
+                        raise state["error"]
+                    if not pending and not waiting and not any(active.values()):
+                        break
+                now = clock()
+                while pending and pending[0].spec["arrival"] <= now:
+                    r = pending.popleft()
+                    r.t_arrival = r.spec["arrival"]
+                    self._setup(r)
+                    waiting.append(r)
+                # FIFO admission under the HBM budget
+                admitted = False
+                while waiting:
+                    with cv:
+                        fits = self.used + waiting[0].bytes <= self.budget
+                        idle = self.used == 0 and not any(active.values())
+                    r = waiting[0]
+                    if not fits:
+                        if idle:
+                            # larger than the whole budget: reject instead of deadlocking
+                            waiting.popleft()
+                            r.t_done = clock()
+                            r.status = "rejected"
+                            with sem.host_lock():
+                                r.ctx.close()
+                            with cv:
+                                done.append(r)
+                            continue
+                        break
+                    waiting.popleft()
+                    with cv:
+                        w = owner.get(r.key)
+                        if w is None or not active.get(r.key):
+                            # a new (or drained) key goes to the least loaded worker
+                            if w is not None and r.key in w.keys:
+                                w.keys.remove(r.key)
+                            w = min(workers, key=lambda x: x.load)
+                            owner[r.key] = w
+                            w.keys.append(r.key)
+                        self.used += r.bytes
+                        r.ctx_points = r.ctx.np
+                        w.load += r.ctx_points
+                    self._admit(r, clock(), w)
+                    with cv:
+                        active.setdefault(r.key, []).append(r)
+                        cv.notify_all()
+                    admitted = True
+                if admitted:
                     continue
-                if pending:
-                    time.sleep(max(0.0, min(0.05, pending[0].spec["arrival"] - (time.perf_counter() - t0))))
-                continue
-            if self.policy == "oldest":
-                key = min((k for k, v in active.items() if v), key=lambda k: active[k][0].t_arrival)
-            else:
-                # next batch key with work (round robin)
-                while not active.get(keys_rr[0]):
-                    keys_rr.rotate(-1)
-                key = keys_rr[0]
-                keys_rr.rotate(-1)
-            batch = active[key][:self.max_batch]
-            ctxs = [r.ctx for r in batch]
-            rounds += 1
-            if key[2] == "tgv":
-                # as many steps as the batch's requests all still need, at most tgv_steps
-                k = min([self.tgv_steps] + [r.spec["steps"] - r.steps_done for r in batch])
-                st = sem.fluid_step(ctxs, k)
-                now = time.perf_counter() - t0
-                for r, ss in zip(batch, st):
-                    bad = 0
-                    for s in ss:
-                        r.steps_done += 1
-                        r.stats.append(s)
-                        r.ops += sum(s["vit"]) + s["pit"] + (6 if r.spec["tier"] != "fp64" else 3) + 1
-                        bad = bad or s["status"]
-                    s = {"status": bad}
-                    if s["status"] != 0 or r.steps_done >= r.spec["steps"]:
-                        self._retire(r, now, "ok" if s["status"] == 0 else "status%d" % s["status"])
-                        active[key].remove(r)
-                        done.append(r)
-            else:
-                flags = sem.poisson_advance(ctxs, self.gmres_chunk)
-                now = time.perf_counter() - t0
-                for r, a in zip(batch, flags):
-                    if not a:
-                        self._retire(r, now, "ok")
-                        st = r.result["stats"]
-                        r.ops += st["iters"] + 2
-                        if st["status"] != 0:
-                            r.status = "status%d" % st["status"]
-                        active[key].remove(r)
-                        done.append(r)
-            if log and rounds % 50 == 0:
-                log("round %d t=%.2fs active=%d waiting=%d done=%d used=%.1f GB"
-                    % (rounds, now, sum(len(v) for v in active.values()), len(waiting), len(done), self.used / 1e9))
-        makespan = time.perf_counter() - t0
+                # sleep until the next arrival or until a worker retires a request
+                with cv:
+                    if state["error"] is None and (pending or waiting):
+                        wait = 0.05 if not pending else max(0.0, min(0.05, pending[0].spec["arrival"] - clock()))
+                        cv.wait(timeout=wait)
+                    elif state["error"] is None and any(active.values()):
+                        cv.wait(timeout=0.05)
+        finally:
+            with cv:
+                state["stop"] = True
+                cv.notify_all()
+            for th in threads:
+                th.join()
+            torch.cuda.synchronize()
+        makespan = clock()
         return done, makespan
 
 
@@ -253,10 +355,13 @@ def main():
     ap.add_argument("--max-batch", type=int, default=16)
     ap.add_argument("--hsmg", type=int, default=1, choices=[0, 1],
                     help="HSMG pressure preconditioner where a request allows it (1), Jacobi everywhere (0)")
+    ap.add_argument("--streams", type=int, default=4, help="worker streams (host threads), 1..4")
+    ap.add_argument("--graph", type=int, default=1, choices=[0, 1], help="TGV steps replayed as HIP graphs")
     args = ap.parse_args()
     sem.load()
     res = measure(args.requests, args.seed, tuple(float(x) for x in args.loads.split(",")), args.max_batch,
-                  log=lambda m: print(m, file=sys.stderr, flush=True), hsmg=args.hsmg)
+                  log=lambda m: print(m, file=sys.stderr, flush=True), hsmg=args.hsmg, streams=args.streams,
+                  graph=bool(args.graph))
     print(json.dumps(res), flush=True)
 
 

@@ -16,6 +16,7 @@ import pytest
 from oracle import OracleMesh, OracleFluid, e_max, e_peak
 from oracle.oracle import INIT_TGV3D
 from paper_2608_24348_amd import inputs
+import opbounds
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -47,14 +48,6 @@ def _gather(t, els, n3):
     return t.index_select(0, idx).double().cpu().numpy()
 
 
-def _op_bound(m, u, h1, h2):
-    """Conservative per-point bound of (|A| |u|): max|D|-row-sum^2 * 3 * max sum|G| * max|u| + h2 B |u|."""
-    _, _, D = m.tables()
-    gsum = np.abs(m.G()).sum(axis=0)
-    dn = np.abs(D).sum(axis=1).max()
-    return h1 * dn * dn * 3 * gsum.max() * np.abs(u).max() * np.ones(m.np) + h2 * m.mass() * np.abs(u)
-
-
 @pytest.mark.parametrize("tier16", ["fp32b+fp16all", "fp32b+bf16all"])
 def test_c3_ax_sampled_elements_every_tier(sem, tier16):
     N = 7
@@ -84,12 +77,10 @@ def test_c3_ax_sampled_elements_every_tier(sem, tier16):
             if geom == sem.FP64:
                 assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
                 continue
-            lx = N + 1
-            kk = 2 * lx + 8
             ua = 2 ** -24 if dt != torch.float64 else 2 ** -53
-            gam = kk * ua / (1 - kk * ua)
-            bound = (gam + 2 * eps_geo + eps_vec) * _op_bound(m, ul, h1, h2)
+            bound = opbounds.ax_bound(m, ul, h1, h2, ua, eps_geo, eps_vec)
             err = np.abs(got - ref)
+            print(tier16, str(dt), geom, (h1, h2), "max err/bound %.3f" % (err / bound).max())
             assert np.all(err <= bound), (str(dt), geom, (err / bound).max())
         del u, w
     del c
@@ -162,17 +153,20 @@ def test_c2_bench_configuration_five_steps_match_oracle(sem, hsmg):
     HSMG pressure preconditioner (the bench default)."""
     nel, N, nu, dt = (32, 32, 32), 7, 1 / 1600, 5e-4
     c = _ctx(sem, nel, N, "fp64", sem.MODE_FLUID, nu=nu, dt=dt, vel_tol=1e-6, pres_tol=1e-4, hsmg=hsmg)
-    gst = sem.fluid_step([c], 5)[0]
     m = OracleMesh(nel, N)
     f = OracleFluid(m, nu, dt, vtol=1e-6, ptol=1e-4, init=INIT_TGV3D, hsmg=bool(hsmg))
+    L = opbounds.div_lipschitz(m)
+    gst = []
     for k in range(5):
+        g = sem.fluid_step([c], 1)[0][0]
+        gst.append(g)
         o = f.step()
-        g = gst[k]
         print("step", k + 1, "gpu", g["vit"], g["pit"], "oracle", o["vit"], o["pit"])
         assert g["status"] == 0
         assert g["vit"] == o["vit"] and g["pit"] == o["pit"]
         assert abs(g["ke"] - o["ke"]) <= 1e-9 * o["ke"]
         assert abs(g["enst"] - o["enst"]) <= 1e-9 * o["enst"]
+        opbounds.check_maxdiv(m, L, g["maxdiv"], o["maxdiv"], c.velocity(), f.velocity(), k + 1)
     assert sum(s["pit"] for s in gst) > 0
     ug = c.velocity()
     uo = f.velocity()
@@ -183,14 +177,16 @@ def test_c4_order11_first_steps_match_oracle_and_fp16_tier_400_steps(sem):
     nel, N, nu, dt = (16, 16, 16), 11, 1 / 1600, 2.5e-4
     kw = dict(nu=nu, dt=dt, vel_tol=1e-6, pres_tol=1e-4)
     c64 = _ctx(sem, nel, N, "fp64", sem.MODE_FLUID, **kw)
-    g3 = sem.fluid_step([c64], 3)[0]
     m = OracleMesh(nel, N)
     f = OracleFluid(m, nu, dt, vtol=1e-6, ptol=1e-4, init=INIT_TGV3D)
+    L = opbounds.div_lipschitz(m)
     for k in range(3):
+        g = sem.fluid_step([c64], 1)[0][0]
         o = f.step()
-        assert g3[k]["vit"] == o["vit"] and g3[k]["pit"] == o["pit"]
-        assert abs(g3[k]["ke"] - o["ke"]) <= 1e-9 * o["ke"]
-        assert abs(g3[k]["enst"] - o["enst"]) <= 1e-9 * o["enst"]
+        assert g["vit"] == o["vit"] and g["pit"] == o["pit"]
+        assert abs(g["ke"] - o["ke"]) <= 1e-9 * o["ke"]
+        assert abs(g["enst"] - o["enst"]) <= 1e-9 * o["enst"]
+        opbounds.check_maxdiv(m, L, g["maxdiv"], o["maxdiv"], c64.velocity(), f.velocity(), k + 1)
     del f, m
     series = {}
     for tier in ("fp64", "fp32b+fp16", "fp32b+fp16p"):
@@ -209,3 +205,8 @@ def test_c4_order11_first_steps_match_oracle_and_fp16_tier_400_steps(sem):
         print(tier, "e_E,max %.3e %%  e_Omega,max %.3e %%  e_Omega,peak %.3e %%  max|div| diff %.3e (fp64 max %.3e)"
               % (eE, eO, eP, ddiv, max(dv64)))
         assert eE <= 1e-2 and eO <= 1e-1
+        # 16-bit geometry in the velocity operator and the gradient perturbs
+        # each derivative by a few fp16 unit roundoffs relative to the
+        # velocity gradient scale (at most 1 for this flow): the divergence
+        # left after the projection may grow by that much
+        assert ddiv <= 8 * 2 ** -11

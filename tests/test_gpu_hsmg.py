@@ -50,7 +50,7 @@ def test_hsmg_poisson_solve_matches_oracle(sem, nel, N):
     st = sem.poisson_solve([c], [torch.from_numpy(rhs).to("cuda:0")], [sol])[0]
     print(nel, N, "iters gpu", st["iters"], "oracle", itref, "jacobi", itjac)
     assert st["status"] == 0
-    assert abs(st["iters"] - itref) <= 1, (st["iters"], itref)
+    assert st["iters"] == itref, (st["iters"], itref)
     assert st["iters"] * 3 <= itjac
     assert _rel(sol.cpu().numpy(), pref) < 1e-8
 
@@ -60,7 +60,7 @@ def test_hsmg_poisson_largest_coarse_planes(sem, nel):
     """64 elements in two directions: the coarse x-y plane (first case) or
     x-z row set (second case) fills the 64 x 64 LDS tile of the coarse
     passes exactly.  Cubic elements of edge 2 pi / 64 (the box is cut to
-    fit), order 4, tolerance 1e-10: counts within 1, solution within 1e-8
+    fit), order 4, tolerance 1e-10: counts equal, solution within 1e-8
     of the oracle's HSMG solve."""
     N = 4
     h = 2 * np.pi / 64
@@ -76,7 +76,7 @@ def test_hsmg_poisson_largest_coarse_planes(sem, nel):
     st = sem.poisson_solve([c], [torch.from_numpy(rhs).to("cuda:0")], [sol])[0]
     print(nel, "iters gpu", st["iters"], "oracle", itref)
     assert st["status"] == 0
-    assert abs(st["iters"] - itref) <= 1
+    assert st["iters"] == itref
     assert _rel(sol.cpu().numpy(), pref) < 1e-8
 
 
@@ -103,7 +103,8 @@ def test_hsmg_poisson_fp32_basis(sem):
 @pytest.mark.parametrize("proj,dealias,cfl", [(0, 0, 0.0), (20, 1, 0.4)])
 def test_hsmg_fluid_matches_oracle(sem, proj, dealias, cfl):
     """4^3 elements, N = 7, 6 steps, tolerances 1e-8: velocity counts equal,
-    pressure counts within 1, KE and enstrophy within 1e-9; the second case
+    pressure counts within 1 (the fresh Poisson solves above have equal
+    counts), KE and enstrophy within 1e-9; the second case
     is the paper's solver settings (Sec. 3: dealiased, adaptive dt at CFL
     0.4, projection 20) with HSMG."""
     nel, N = (4, 4, 4), 7
@@ -116,6 +117,10 @@ def test_hsmg_fluid_matches_oracle(sem, proj, dealias, cfl):
         o = f.step()
         g = gst[k]
         assert g["status"] == 0
+        # the GPU applies the preconditioner in another summation order (node
+        # copies summed in tuple order, Z_j = M^{-1} s_j V_j kept and summed at
+        # the cycle end) and the step's rhs carries the previous steps'
+        # rounding: a solve may stop one iteration apart at the tolerance edge
         assert g["vit"] == o["vit"] and abs(g["pit"] - o["pit"]) <= 1, (k, g, o)
         assert abs(g["dt"] - o["dt"]) <= 1e-9 * o["dt"]
         assert abs(g["ke"] - o["ke"]) <= 1e-9 * o["ke"]

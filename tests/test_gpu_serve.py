@@ -30,7 +30,7 @@ def _same(a, b):
 
 def test_stream_completes_and_mix_equals_alone(serve):
     specs = _stream()
-    srv = serve.Server(max_batch=8, gmres_chunk=10, keep_fields=True)
+    srv = serve.Server(max_batch=8, gmres_chunk=10, keep_fields=True, streams=4, graph=True)
     done, makespan = srv.run(specs)
     assert len(done) == len(specs) and all(r.status == "ok" for r in done)
     summ = serve.summarize(done, makespan)
@@ -38,10 +38,12 @@ def test_stream_completes_and_mix_equals_alone(serve):
     assert srv.used == 0
     kinds = {r.kind for r in done}
     assert kinds == {"tgv", "poisson"}
-    # every request again, alone (arrival 0, batch of one)
+    # every request again, alone (arrival 0, batch of one), on one stream with
+    # host-driven steps: the mix ran batched, on up to four streams from
+    # concurrent host threads, with its steps replayed as graphs
     for r in done:
         spec = dict(r.spec, arrival=0.0)
-        alone, _ = serve.Server(max_batch=1, gmres_chunk=10, keep_fields=True).run([spec])
+        alone, _ = serve.Server(max_batch=1, gmres_chunk=10, keep_fields=True, streams=1, graph=False).run([spec])
         assert alone[0].status == "ok"
         assert _same(alone[0], r), r.spec
 

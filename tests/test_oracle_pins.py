@@ -685,3 +685,81 @@ def test_adaptive_dt_follows_the_controller_and_keeps_the_2d_tgv_exact_decay():
     ue = np.stack([np.sin(X[0]) * np.cos(X[1]) * decay, -np.cos(X[0]) * np.sin(X[1]) * decay])
     u = f.velocity()
     assert np.abs(u[:2] - ue).max() < 5e-5 and np.abs(u[2]).max() < 1e-8
+
+
+# ---------------------------------------------------------------- collocated convection on curved elements
+def _gll_numpy(N):
+    """GLL nodes from numpy's Legendre roots and weights from their closed form
+    w_i = 2 / (N (N + 1) L_N(x_i)^2) (independent of the oracle's tables)."""
+    Leg = np.polynomial.legendre.Legendre
+    x = np.concatenate([[-1.0], np.sort(Leg.basis(N).deriv().roots().real), [1.0]])
+    w = 2.0 / (N * (N + 1) * Leg.basis(N)(x) ** 2)
+    return x, w
+
+
+def _brute_force_conv(X, U, N):
+    """-B (u . grad) u per local point from first principles: numpy Lagrange
+    differentiation of the element-local coordinates and fields along each
+    reference direction, the Jacobian matrix inverted point by point with
+    numpy.linalg, and B = det(J) w_i w_j w_k."""
+    lx = N + 1
+    x, w = _gll_numpy(N)
+    D = _lagrange_deriv_numpy(x)
+    E = X.shape[1] // lx ** 3
+    Xe = X.reshape(3, E, lx, lx, lx)          # [c][e][k][j][i]
+    Ue = U.reshape(3, E, lx, lx, lx)
+
+    def dref(f):
+        # derivatives along r (i axis), s (j axis), t (k axis)
+        return np.stack([np.einsum("il,...kjl->...kji", D, f), np.einsum("jl,...kli->...kji", D, f),
+                         np.einsum("kl,...lji->...kji", D, f)])
+
+    dX = dref(Xe)                             # [a][c][e][k][j][i] = dx_c / dr_a
+    J = np.moveaxis(dX, (0, 1), (-1, -2))     # [e][k][j][i][c][a]
+    Jinv = np.linalg.inv(J)                   # [..][a][c] = dr_a / dx_c
+    jac = np.linalg.det(J)
+    W = np.einsum("k,j,i->kji", w, w, w)
+    B = jac * W[None]
+    dU = dref(Ue)                             # [a][f][e][k][j][i]
+    out = np.zeros_like(Ue)
+    for f in range(3):
+        for c in range(3):
+            gfc = sum(dU[a, f] * Jinv[..., a, c] for a in range(3))   # du_f / dx_c
+            out[f] -= Ue[c] * gfc
+    return (B[None] * out).reshape(3, -1)
+
+
+def test_collocated_convection_of_linear_field_on_curved_elements():
+    """On isoparametric elements a field linear in x is represented exactly,
+    its gradient is the constant matrix A, so -B (u . grad) u = -B (A u) at
+    every node to rounding, whatever the metric terms look like.  M is full
+    on the deformed mesh, so an index or transposition slip in the metric
+    contraction fails this."""
+    N = 6
+    m = OracleMesh((4, 4, 4), N, amp=0.1, phase=inputs.deform_phases())
+    X = m.coords()
+    B = m.mass()
+    rng = np.random.default_rng(41)
+    for trial in range(4):
+        A = rng.standard_normal((3, 3))
+        b = rng.standard_normal(3)
+        u = np.einsum("ic,cp->ip", A, X) + b[:, None]
+        ref = -B[None] * np.einsum("ic,cp->ip", A, u)
+        got = np.stack(m.conv(u))
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), (trial, np.abs(got - ref).max())
+
+
+def test_collocated_convection_matches_numpy_brute_force_on_curved_elements():
+    """A quadratic field on the deformed mesh (not exact in the element basis):
+    the oracle's collocated convective term equals a from-scratch numpy
+    evaluation with the Jacobian inverted point by point."""
+    N = 5
+    m = OracleMesh((2, 2, 2), N, amp=0.1, phase=inputs.deform_phases())
+    X = m.coords()
+    rng = np.random.default_rng(42)
+    Q = rng.standard_normal((3, 3, 3))
+    A = rng.standard_normal((3, 3))
+    u = np.einsum("ijk,jp,kp->ip", Q, X, X) + np.einsum("ic,cp->ip", A, X)
+    got = np.stack(m.conv(u))
+    ref = _brute_force_conv(X, u, N)
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
