@@ -36,16 +36,23 @@ def gamma(k, unit):
     return k * unit / (1 - k * unit)
 
 
-def ax_bound(m, u, h1, h2, unit_arith, eps_geo, eps_out):
+# half the spacing of the subnormal numbers of each storage format: a result
+# rounded into the subnormal range carries this absolute error instead of a
+# relative one (gradual underflow; the relative model holds for normal results)
+TINY = {"float64": 2.0 ** -1075, "float32": 2.0 ** -150, "float16": 2.0 ** -25, "bfloat16": 2.0 ** -134}
+
+
+def ax_bound(m, u, h1, h2, unit_arith, eps_geo, eps_out, tiny_out=0.0):
     """Per-point bound on |w_computed - w_exact| for the operator on the
     stored (already rounded) input u: chain length k = 2 lx + 8 (two
     lx-term contractions, the three-term metric sum, the sum over a, the
     Helmholtz term), geometry rounded once to storage (twice its unit
     roundoff: the per-element power-of-two scale is exact but the scaled
     value is rounded from fp64 through the kernel's load), output rounded
-    once to storage."""
+    once to storage (relative eps_out, or the absolute tiny_out where the
+    output is subnormal in its format)."""
     k = 2 * m.lx + 8
-    return (gamma(k, unit_arith) + 2 * eps_geo + eps_out) * abs_ax(m, u, h1, h2)
+    return (gamma(k, unit_arith) + 2 * eps_geo + eps_out) * abs_ax(m, u, h1, h2) + tiny_out
 
 
 def div_lipschitz(m):

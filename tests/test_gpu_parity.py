@@ -126,7 +126,7 @@ def test_ax_reduced_precision_within_rounding_bound(sem, tier, buf, eps_geo, eps
     c.ax(ut, w, h1, h2, geom=geom)
     got = w.double().cpu().numpy()
     u_arith = 2 ** -24 if buf != "float64" else 2 ** -53  # fp64 vectors run fp64 arithmetic
-    bound = opbounds.ax_bound(m, u_rounded, h1, h2, u_arith, eps_geo, eps_vec)
+    bound = opbounds.ax_bound(m, u_rounded, h1, h2, u_arith, eps_geo, eps_vec, opbounds.TINY[buf])
     err = np.abs(got - ref)
     assert np.all(err <= bound), (err / bound).max()
     # normwise: rounding errors of independent terms do not align, so the
