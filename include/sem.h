@@ -259,6 +259,26 @@ int sem_poisson_solve(sem_ctx* const* ctxs, int n, const void* const* rhs, void*
 int sem_poisson_begin(sem_ctx* const* ctxs, int n, const void* const* rhs);
 int sem_poisson_advance(sem_ctx* const* ctxs, int n, int max_iters, int* active);
 int sem_poisson_finish(sem_ctx* ctx, void* sol, sem_solve_stats* st);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as sem_poisson_solve for one context, bound in any mode, with the
+ * Jacobi preconditioner (flow.hsmg must be 0).  The GMRES workspace (the
+ * m + 1 basis vectors in the context's basis storage precision and four fp64
+ * vectors of E*lx^3 values, each rounded up to 256 bytes) is taken from a
+ * static device array of sem_noalloc_max_bytes() bytes that the library
+ * holds on every device it runs on until the process ends; nothing is
+ * allocated and no memset is recorded.  rhs and sol: device fp64 arrays of
+ * E*lx^3 values (rhs assembled; sol receives p with its mass-weighted mean
+ * removed).  Synchronises the context's stream.  Every call on a device
+ * shares that device's array: calls that overlap on one device (on any
+ * stream, from any thread) race and must be serialised by the caller; the
+ * context's own projection space is not touched.  Errors: SEM_ENOMEM when
+ * the workspace exceeds the array (no kernel runs), SEM_EINVAL, SEM_ESTATE,
+ * SEM_EHIP; solver status in stats as for sem_poisson_solve. */
+size_t sem_noalloc_max_bytes(void);
+int sem_poisson_solve_noalloc(sem_ctx* ctx, const void* rhs, void* sol, sem_solve_stats* stats);
+
 /* Field access for checkpoints and tests.  which: SEM_F_*; component fields
  * use which + c.  src/dst are fp64 arrays of E*lx^3 values, on the host when
  * is_host != 0 (the call then synchronises), else device pointers. */

@@ -2233,3 +2233,105 @@ int sem_wdiv(sem_ctx* c, const double* const* v3, double* out)
 }
 
 }  // extern "C"
+
+
+// ------------------------------------------------------------------ Poisson solve on an external workspace
+// The Krylov vectors of a stand-alone Jacobi-GMRES solve (the basis V_0..V_m
+// in the basis storage precision; the operator output, the working vector,
+// the rhs and the iterate in fp64) taken from memory the caller provides
+// instead of the context's bound workspace, so that a context bound in any
+// mode can solve.  The kernels reach their fields through the device copy of
+// the request descriptor: for the duration of the solve it points the Krylov
+// fields into ws, and it is restored afterwards.  Both descriptor writes are
+// kernels that take the descriptor as an argument (no host staging buffer,
+// no memset), on the context's stream.
+
+namespace {
+
+__global__ void desc_store_kernel(ReqDesc* dst, ReqDesc src)
+{
+    const unsigned long long* a = (const unsigned long long*)&src;
+    unsigned long long* b = (unsigned long long*)dst;
+    for (unsigned i = threadIdx.x; i < sizeof(ReqDesc) / 8; i += blockDim.x) b[i] = a[i];
+}
+static_assert(sizeof(ReqDesc) % 8 == 0, "descriptor copied in 8-byte words");
+
+int desc_store(ReqDesc* dst, const ReqDesc& src, hipStream_t s)
+{
+    hipLaunchKernelGGL(desc_store_kernel, dim3(1), dim3(64), 0, s, dst, src);
+    return check_hip_last();
+}
+
+}  // namespace
+
+namespace semk {
+
+int poisson_external_bytes(const sem_ctx* c, size_t* bytes, int* device)
+{
+    int rc = bind_check(const_cast<sem_ctx*>(c));
+    if (rc) return rc;
+    const size_t np = (size_t)c->np;
+    *bytes = align256((size_t)(c->flow.gmres_restart + 1) * psize(c->rs.tb) * np) + 4 * align256(8 * np);
+    *device = c->device;
+    return 0;
+}
+
+int poisson_solve_external(sem_ctx* c, char* ws, size_t ws_bytes, const void* rhs, void* sol, sem_solve_stats* st)
+{
+    size_t need = 0;
+    int dev = 0;
+    int rc = poisson_external_bytes(c, &need, &dev);
+    if (rc) return rc;
+    if (!ws || ws_bytes < need || (((uintptr_t)ws) & 255)) return fail(SEM_EINVAL, "external Krylov workspace too small or misaligned");
+    if (!rhs || !sol) return fail(SEM_EINVAL, "null rhs/sol");
+    if (c->flow.hsmg) return fail(SEM_EINVAL, "a solve on an external workspace runs the Jacobi preconditioner (flow.hsmg must be 0)");
+    const size_t np = (size_t)c->np;
+    const size_t vbytes = align256((size_t)(c->flow.gmres_restart + 1) * psize(c->rs.tb) * np);
+    const size_t dbytes = align256(8 * np);
+    hipStream_t s = c->stream;
+    ReqDesc d = c->hdesc;
+    d.f[F_V] = ws;
+    d.f[F_GW] = ws + vbytes;
+    d.f[F_GWD] = ws + vbytes + dbytes;
+    d.f[F_GB] = ws + vbytes + 2 * dbytes;
+    d.f[F_GX] = ws + vbytes + 3 * dbytes;
+    if ((rc = desc_store(c->ddesc, d, s))) return rc;
+    // event profiling would create events: it is paused for this solve
+    const int prof_saved = g_prof.kclass;
+    g_prof.kclass = 0;
+    sem_ctx* one[1] = {c};
+    Batch b = make_batch(one, 1);
+    hipError_t e = hipMemcpyAsync(d.f[F_GB], rhs, 8 * np, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) rc = fail(SEM_EHIP, std::string("hipMemcpyAsync(rhs): ") + hipGetErrorString(e));
+    if (!rc) {
+        vec(b, V_SUM_UNIQUE, 1, P64, -1, s, F_GB, -1, P64, P64, FIN_MEAN_UNIQUE);
+        vec(b, V_SUB_MEAN, 1, P64, -1, s, F_GB, -1);
+        vec(b, V_ZERO, 1, P64, -1, s, F_GX);  // ws may hold an earlier solve's values
+        rc = pressure_solve(one, b, s, false);
+    }
+    g_prof.kclass = prof_saved;
+    if (!rc) {
+        e = hipMemcpyAsync(sol, d.f[F_GX], 8 * np, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) rc = fail(SEM_EHIP, std::string("hipMemcpyAsync(sol): ") + hipGetErrorString(e));
+    }
+    // the bound descriptor comes back also after a failed solve
+    const int rc2 = desc_store(c->ddesc, c->hdesc, s);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    int it = 0, nan = 0;
+    double res = 0;
+    HIPCHK(hipMemcpyAsync(&it, c->hdesc.I + I_GIT, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&nan, c->hdesc.I + I_NAN, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&res, c->hdesc.S + S_GBETA, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st) {
+        st->iters = it;
+        st->res = res;
+        st->status = nan ? SEM_ENAN : (res > c->flow.pres_tol ? SEM_ENOTCONV : SEM_OK);
+    }
+    return check_hip_last();
+}
+
+int set_error(int code, const char* msg) { return fail(code, msg); }
+
+}  // namespace semk

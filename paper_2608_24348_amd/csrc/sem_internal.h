@@ -408,4 +408,13 @@ struct FinArgs {
 void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s);
 void launch_fin(const Batch& b, const FinArgs& a, hipStream_t s);
 
+// Stand-alone Jacobi-GMRES Poisson solve of one bound context (any mode) on a
+// caller-provided Krylov workspace ws (256-byte aligned, at least the bytes
+// poisson_external_bytes reports; device is the context's HIP device).  Same
+// arithmetic and launches as sem_poisson_solve; synchronises the stream.
+int poisson_external_bytes(const sem_ctx* c, size_t* bytes, int* device);
+int poisson_solve_external(sem_ctx* c, char* ws, size_t ws_bytes, const void* rhs, void* sol, sem_solve_stats* st);
+// records msg as the library's last error and returns code
+int set_error(int code, const char* msg);
+
 }  // namespace semk

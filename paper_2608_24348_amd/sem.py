@@ -78,7 +78,8 @@ EXPORTS = ["sem_setup", "sem_workspace_bytes", "sem_bind", "sem_ax", "sem_dssum"
            "sem_poisson_solve", "sem_get_field", "sem_set_field", "sem_set_clock", "sem_diagnostics",
            "sem_conv", "sem_opgrad", "sem_wdiv", "sem_sizes", "sem_destroy", "sem_strerror", "sem_last_error",
            "sem_prof_start", "sem_prof_stop", "sem_poisson_begin", "sem_poisson_advance", "sem_poisson_finish",
-           "sem_mass", "sem_node_field", "sem_copy_state", "sem_fluid_step_graph", "sem_graph_counters", "sem_host_lock"]
+           "sem_mass", "sem_node_field", "sem_copy_state", "sem_fluid_step_graph", "sem_graph_counters", "sem_host_lock",
+           "sem_noalloc_max_bytes", "sem_poisson_solve_noalloc"]
 PROF_AX_VEL, PROF_AX_PRES, PROF_GM_DOTS, PROF_GM_UPD_DOTS, PROF_GM_UPD_NORM, PROF_DSSUM_PRES, PROF_AX_ANY, PROF_AX_RESID, \
     PROF_AX_PRESID, PROF_CONV, PROF_HSMG = range(1, 12)
 
@@ -129,6 +130,9 @@ def load():
     L.sem_copy_state.argtypes = [vp, vp]
     L.sem_prof_start.argtypes = [C.c_int]
     L.sem_prof_stop.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.sem_noalloc_max_bytes.restype = C.c_size_t
+    L.sem_noalloc_max_bytes.argtypes = []
+    L.sem_poisson_solve_noalloc.argtypes = [vp, vp, vp, C.POINTER(SolveStats)]
     _lib = L
     return L
 
@@ -460,6 +464,21 @@ def poisson_solve(ctxs, rhs, sol):
     st = (SolveStats * n)()
     _check(load().sem_poisson_solve(arr, n, r, s, st))
     return [{"iters": st[i].iters, "res": st[i].res, "status": st[i].status} for i in range(n)]
+
+
+def poisson_solve_noalloc(ctx, rhs, sol):
+    """Poisson solve of one context (any mode, Jacobi preconditioner) whose
+    Krylov workspace is the library's static device array (no allocation);
+    rhs/sol are fp64 device tensors.  Returns the solve stats."""
+    st = SolveStats()
+    _check(load().sem_poisson_solve_noalloc(ctx.h, C.c_void_p(rhs.data_ptr()), C.c_void_p(sol.data_ptr()),
+                                            C.byref(st)))
+    return {"iters": st.iters, "res": st.res, "status": st.status}
+
+
+def noalloc_max_bytes():
+    """Size of the static device array of the allocation-free entry points."""
+    return load().sem_noalloc_max_bytes()
 
 
 def copy_state(dst, src):
