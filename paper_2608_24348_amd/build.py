@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsem.so")
-SOURCES = ["sem_host.cpp", "k_ax.hip", "k_gs.hip", "k_geom.hip", "k_ops.hip", "k_dealias.hip", "k_vec.hip", "k_hsmg.hip",
+SOURCES = ["sem_host.cpp", "k_ax.hip", "k_axm.hip", "k_gs.hip", "k_geom.hip", "k_ops.hip", "k_dealias.hip", "k_vec.hip", "k_hsmg.hip",
            "sem_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

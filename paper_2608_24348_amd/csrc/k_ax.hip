@@ -298,6 +298,7 @@ void launch_ax(const Batch& b, int lx, const AxLaunch& a0, hipStream_t s)
 {
     AxLaunch a = a0;
     if (a.ncomp < 1) a.ncomp = 1;
+    if (launch_ax_mfma(b, lx, a, s)) return;
     switch (lx) {
     case 3: ax_lx<3>(b, a, s); break;
     case 4: ax_lx<4>(b, a, s); break;

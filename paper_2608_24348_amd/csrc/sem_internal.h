@@ -313,6 +313,9 @@ struct AxLaunch {
 };
 
 void launch_ax(const Batch& b, int lx, const AxLaunch& a, hipStream_t s);
+// the matrix-core operator (lx = 8, fp32 arithmetic, 16-bit geometry, no Jacobi
+// scaling, residual form or fp64 output); false when it does not apply
+bool launch_ax_mfma(const Batch& b, int lx, const AxLaunch& a, hipStream_t s);
 void launch_dssum(const Batch& b, int field, int ncomp, int tprec, int gate, void* raw, hipStream_t s);
 
 // geometry and setup
