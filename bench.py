@@ -76,21 +76,22 @@ def run_tier(sem, torch, tier, nel, N, nu, dt, warmup, steps, prof_class=None, v
     return ctx, (t1 - t0), st, series, prof
 
 
-def ax_rate(sem, torch, ctx, dtype, geom, reps=20, nvec=2, h1=1.0, h2=0.0):
+def ax_rate(sem, torch, ctx, dtype, geom, reps=20, nvec=2, h1=1.0, h2=0.0, half=False):
     """Operator GDOF/s (HIP events, current stream).  The launches cycle
     through nvec distinct input/output pairs so that no launch finds its
-    vectors in the last-level cache left by the previous one."""
+    vectors in the last-level cache left by the previous one.  half: 16-bit
+    arithmetic (Table 2's fp16-compute overrides)."""
     g = torch.Generator(device="cuda:0")
     g.manual_seed(0)
     us = [torch.randn(ctx.np, dtype=torch.float64, device="cuda:0", generator=g).to(dtype) for _ in range(nvec)]
     ws = [torch.empty_like(us[0]) for _ in range(nvec)]
     for q in range(nvec):
-        ctx.ax(us[q], ws[q], h1, h2, geom=geom)
+        ctx.ax(us[q], ws[q], h1, h2, geom=geom, half_compute=half)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for r in range(reps):
-        ctx.ax(us[r % nvec], ws[r % nvec], h1, h2, geom=geom)
+        ctx.ax(us[r % nvec], ws[r % nvec], h1, h2, geom=geom, half_compute=half)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -124,22 +125,29 @@ def ax_leg(sem, torch, inputs, nel=64, N=7):
     Helmholtz form (h1 = 1/1600, h2 = 11/6 / 5e-4) in fp64 and fp32 (bytes per
     point: vectors in and out + 6 geometric factors, + B for Helmholtz), then
     dssum of a vector in fp64 and fp32 (bytes per point: the shared fraction
-    of points read and written once, plus a 4-byte index each)."""
+    of points read and written once, plus a 4-byte index each).  Legs named
+    *_c16 run 16-bit arithmetic (16-bit operands, fp32 sums)."""
     out = {"workload": "%d^3 elements N=%d (%d points), deformed amp 0.1 h, u ~ N(0,1); HIP events over 20 launches "
                        "cycling through 2 vector pairs" % (nel, N, nel ** 3 * (N + 1) ** 3)}
     for tier16, legs in (("fp32b+fp16all", (("fp64", torch.float64, sem.FP64, 64, 0),
                                              ("fp32", torch.float32, sem.FP32, 32, 0),
                                              ("fp32_fp16geom", torch.float32, sem.FP16, 20, 0),
                                              ("fp16", torch.float16, sem.FP16, 16, 0),
+                                             ("fp32_fp16geom_c16", torch.float32, sem.FP16, 20, 2),
+                                             ("fp16_c16", torch.float16, sem.FP16, 16, 2),
+                                             ("fp32_fp16geom_c16_helmholtz", torch.float32, sem.FP16, 22, 3),
                                              ("fp64_helmholtz", torch.float64, sem.FP64, 72, 1),
                                              ("fp32_helmholtz", torch.float32, sem.FP32, 36, 1))),
                          ("fp32b+bf16all", (("bf16", torch.bfloat16, sem.BF16, 16, 0),
-                                            ("fp32_bf16geom", torch.float32, sem.BF16, 20, 0)))):
+                                            ("fp32_bf16geom", torch.float32, sem.BF16, 20, 0),
+                                            ("bf16_c16", torch.bfloat16, sem.BF16, 16, 2),
+                                            ("fp32_bf16geom_c16", torch.float32, sem.BF16, 20, 2)))):
         ctx = sem.Context(sem.mesh_desc((nel,) * 3, N, amp=0.1, phase=inputs.deform_phases()),
                           sem.flow_desc(mode=sem.MODE_OPERATOR), sem.tier(tier16))
-        for name, dt, geom, bpp, helm in legs:
-            h1, h2 = (1.0 / 1600, 11.0 / 6.0 / 5e-4) if helm else (1.0, 0.0)
-            gd, ms = ax_rate(sem, torch, ctx, dt, geom, h1=h1, h2=h2)
+        for name, dt, geom, bpp, kind in legs:
+            # kind: 0 Poisson, 1 Helmholtz, 2 Poisson in 16-bit arithmetic, 3 Helmholtz in 16-bit arithmetic
+            h1, h2 = (1.0 / 1600, 11.0 / 6.0 / 5e-4) if kind in (1, 3) else (1.0, 0.0)
+            gd, ms = ax_rate(sem, torch, ctx, dt, geom, h1=h1, h2=h2, half=kind >= 2)
             out[name] = {"gdof_per_s": gd, "ms": ms, "bytes_per_point": bpp, "hbm_GBps": gd * bpp,
                          "frac": gd * bpp / HBM_PEAK_GBS}
         if tier16 == "fp32b+fp16all":
@@ -155,7 +163,7 @@ def ax_leg(sem, torch, inputs, nel=64, N=7):
     return out
 
 
-def c4_leg(sem, torch, steps, tiers=("fp64", "fp32b-p32", "fp32b", "fp32b+fp16"), graph=0):
+def c4_leg(sem, torch, steps, tiers=("fp64", "fp32b-p32", "fp32b", "fp32b+fp16", "fp32b+fp16c"), graph=0):
     """The higher-order workload: 16^3 elements, N = 11 (7.1 M points), Re 1600,
     dt 2.5e-4, tolerances 1e-6 / 1e-4, HSMG; steps/s per tier, and each tier's
     error metrics and max|div| against the oracle's stored series."""
@@ -279,7 +287,7 @@ def roofline(kind, tier, prof, steps, npts, workload, N=7, dealias=0):
             nv = 1 + (s["vcyc"] if tier != "fp64" else 0)
             alg += nv * npts * 128
             active += nv
-        name = "ax_kernel<8, double, double, double, 0, double, 1> -- fp64 velocity residual RHS_L - H_L u"
+        name = "ax_kernel<8, double, double, double, 0, double, 1, 0> -- fp64 velocity residual RHS_L - H_L u"
     elif kind == "ax_presid":
         # fp64 Poisson residual operator at the end of every GMRES cycle that
         # started from a nonzero iterate (u, w, 6 G = 64 B/point); the other
@@ -344,6 +352,10 @@ TIER_NOTE = {
                  "storage), GMRES basis storage; fp64: HSMG, weak divergence of u*, GMRES orthogonalisation/dots/H, "
                  "BDF/EXT state, residual checks, global reductions",
     "fp32b+fp16": "fp32b with fp16-stored geometry in the velocity operator and opgrad (fp32 arithmetic)",
+    "fp32b+fp16c": "fp32b with the velocity operator in 16-bit arithmetic (fp16 operands, fp32 sums) on fp16 "
+                   "geometry",
+    "fp32b+fp16pc": "fp32b with the pressure operator in 16-bit arithmetic (fp16 operands, fp32 sums) on fp16 "
+                    "geometry",
 }
 
 

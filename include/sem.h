@@ -85,7 +85,11 @@ typedef struct {
     int size;                        /* sizeof(sem_precision) */
     int rp;                          /* global cap: SEM_FP64 or SEM_FP32 */
     sem_role block[SEM_NBLOCK];
-    sem_role kernel[SEM_K_COUNT];    /* SEM_INHERIT fields take the block value */
+    sem_role kernel[SEM_K_COUNT];    /* SEM_INHERIT fields take the block value.  Compute
+                                        SEM_FP16/SEM_BF16 (Table 2's fp16-compute overrides)
+                                        is accepted for AX_VEL and AX_PRES only, with storage
+                                        of the same format and accumulate SEM_FP32 (see
+                                        SEM_AX_16BIT_COMPUTE at sem_ax); SEM_EINVAL otherwise. */
     unsigned fp64_exceptions;        /* SEM_X_* bits */
 } sem_precision;
 
@@ -197,10 +201,16 @@ int sem_bind(sem_ctx* ctx, void* dev_buf, size_t bytes, void* hip_stream);
  * buf_prec (FP64, FP32, FP16 or BF16 storage), geometry in geom_prec (must
  * be one the context holds; SEM_INHERIT = the AX_PRES policy when h2 == 0,
  * else AX_VEL).  Arithmetic is fp64 for fp64 vectors (fp32 with
- * SEM_AX_FP32_COMPUTE) and fp32 otherwise.  flags & SEM_ASSEMBLE
- * additionally applies dssum to w. */
+ * SEM_AX_FP32_COMPUTE) and fp32 otherwise; SEM_AX_16BIT_COMPUTE selects the
+ * 16-bit arithmetic of Table 2's fp16-compute overrides (B-6, B-7) in the
+ * geometry's format: per element, u scaled by the power of two s that puts
+ * max|u| in [0.5, 1), D, and the metric-weighted derivatives are rounded to
+ * 16 bits (nearest even), products summed in fp32, h1 gsc / s and the mass
+ * term applied in fp32 (needs 16-bit geometry and fp32 or same-format
+ * vectors).  flags & SEM_ASSEMBLE additionally applies dssum to w. */
 #define SEM_ASSEMBLE 1
-#define SEM_AX_FP32_COMPUTE 2  /* fp64 vectors, fp32 arithmetic (needs fp32 or 16-bit geometry) */
+#define SEM_AX_FP32_COMPUTE 2   /* fp64 vectors, fp32 arithmetic (needs fp32 or 16-bit geometry) */
+#define SEM_AX_16BIT_COMPUTE 4  /* 16-bit operands, fp32 sums (needs 16-bit geometry) */
 int sem_ax(sem_ctx* ctx, const void* u, void* w, double h1, double h2, int buf_prec, int geom_prec, int flags);
 
 /* Direct stiffness summation in place: every local copy of a shared node

@@ -8,6 +8,13 @@
 // layers.  Every global access is a contiguous lx*lx layer, so G, u and w
 // stream coalesced.  Storage types (vectors TU, geometry TG) and compute
 // type C are template parameters; 16-bit geometry carries a per-element scale.
+// H16 (1 fp16, 2 bf16) selects 16-bit arithmetic with fp32 accumulation: the
+// operands of every contraction are 16-bit values -- u scaled per element by
+// the power of two s that puts max|u| in [0.5, 1), D, and the weighted
+// derivatives entering the transposed contractions, each rounded to nearest
+// even -- multiplied exactly and summed in fp32, with the stored normalised G
+// in the point-wise stage and h1 gsc / s applied at the end (the matrix-core
+// kernel computes the same).
 #include "k_common.h"
 
 #include <type_traits>
@@ -46,23 +53,33 @@ template <typename TG> __device__ __forceinline__ int bfield() { return F_B16; }
 template <> __device__ __forceinline__ int bfield<double>() { return F_B64; }
 template <> __device__ __forceinline__ int bfield<float>() { return F_B32; }
 
+// an fp32 value rounded to the 16-bit format H16 names (1 fp16, 2 bf16) and back
+template <int H16> __device__ __forceinline__ float r16(float x)
+{
+    if constexpr (H16 == 1) return (float)(_Float16)x;
+    else if constexpr (H16 == 2) return (float)(__bf16)x;
+    else return x;
+}
+
 // PC: Jacobi scaling of the input on load (0 none, 1 fp64 diagonal, 2 fp32),
 // a template parameter so the load stays unconditional
 // SUB: residual form, w = r_L - (operator u) with r_L the local (unassembled)
 // right-hand side a.sub; the caller assembles w afterwards, which equals
 // dssum(r_L) - dssum(operator u) (QQ^T is linear)
-template <int LX, typename TU, typename TG, typename C, int PC, typename TW, int SUB = 0>
+template <int LX, typename TU, typename TG, typename C, int PC, typename TW, int SUB = 0, int H16 = 0>
 __global__ void __launch_bounds__(Nthr<LX>::v)
 ax_kernel(Batch bt, AxLaunch a)
 {
     constexpr int EPB = Epb<LX>::v;
     constexpr int L2 = LX * LX;
     constexpr int L3 = LX * LX * LX;
+    static_assert(H16 == 0 || (sizeof(C) == 4 && sizeof(TG) == 2 && SUB == 0), "16-bit arithmetic: fp32 sums, 16-bit G");
     __shared__ C sD[L2];
     __shared__ C su[EPB][L2];
     __shared__ C sr[EPB][L2];
     __shared__ C ss[EPB][L2];
     __shared__ double red[Nthr<LX>::v / 64];
+    __shared__ float smax[H16 ? EPB : 1];
 
     // Components of one element block run as blocks x, x+8, x+16 of a 1-D
     // grid: workgroups go round-robin over the 8 XCDs, so those land on the
@@ -86,7 +103,11 @@ ax_kernel(Batch bt, AxLaunch a)
 
     for (int q = t; q < L2; q += blockDim.x) {
         if constexpr (sizeof(C) == 8) sD[q] = (C)gp(R->D64)[q];
-        else sD[q] = (C)gp(R->D32)[q];
+        else sD[q] = r16<H16>(gp(R->D32)[q]);
+    }
+    if constexpr (H16 != 0) {
+        if (t < EPB) smax[t] = 0.0f;
+        block_sync_lds();
     }
 
     const SEM_GLOBAL TU* u = a.src_vj ? gfield<TU>(R, F_V) + (long long)gp(R->I)[I_GJ] * R->np
@@ -109,6 +130,8 @@ ax_kernel(Batch bt, AxLaunch a)
         gsc = (C)sc[ee];
         bsc = (C)sc[R->E + ee];
     }
+    // 16-bit arithmetic takes the stored normalised G; gsc goes to the end
+    const C gmul = H16 ? (C)1 : gsc;
 
     // The column's global loads are issued ahead of the k-walk and kept in
     // their storage type (converted only where they are used): u first, then
@@ -146,7 +169,24 @@ ax_kernel(Batch bt, AxLaunch a)
             for (int q = 0; q < 6; ++q) graw[q][k] = ldg_stream(G + gbase + q * L3 + k * L2 + ij);
         }
     }
-    block_sync_lds();  // sD ready
+    // uin: the operator's input as stored (Jacobi-scaled); ureg: what the
+    // contractions read (uin, or its scaled 16-bit rounding)
+    C uin[H16 ? LX : 1];
+#pragma unroll
+    for (int k = 0; k < LX; ++k) {
+        C v = to<C>(uraw[k]);
+        if constexpr (PC != 0) v *= (C)praw[k];
+        ureg[k] = v;
+        wacc[k] = (C)0;
+    }
+    if constexpr (H16 != 0) {
+        float mx = 0.0f;
+#pragma unroll
+        for (int k = 0; k < LX; ++k) mx = fmaxf(mx, fabsf((float)ureg[k]));
+        // the element's max over its columns (non-negative floats order as their bits)
+        if (el < EPB) atomicMax((int*)&smax[el], __float_as_int(mx));
+    }
+    block_sync_lds();  // sD ready (and the element maxima)
     C Di[LX], Dj[LX], DTi[LX], DTj[LX];
 #pragma unroll
     for (int l = 0; l < LX; ++l) {
@@ -155,12 +195,21 @@ ax_kernel(Batch bt, AxLaunch a)
         DTi[l] = sD[l * LX + i];
         DTj[l] = sD[l * LX + j];
     }
+    C hscale = (C)1;  // 1/s
+    if constexpr (H16 != 0) {
+        const float m = smax[el < EPB ? el : 0];
+        float sc = 1.0f;
+        if (m > 0.0f && m < INFINITY) {
+            int ex;
+            (void)frexpf(m, &ex);
+            sc = ldexpf(1.0f, -ex);
+        }
+        hscale = (C)(1.0f / sc);
 #pragma unroll
-    for (int k = 0; k < LX; ++k) {
-        C v = to<C>(uraw[k]);
-        if constexpr (PC != 0) v *= (C)praw[k];
-        ureg[k] = v;
-        wacc[k] = (C)0;
+        for (int k = 0; k < LX; ++k) {
+            uin[k] = ureg[k];
+            ureg[k] = r16<H16>(ureg[k] * sc);
+        }
     }
 
 #pragma unroll
@@ -184,10 +233,10 @@ ax_kernel(Batch bt, AxLaunch a)
         }
         C g6[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) g6[q] = to<C>(graw[q][kc]) * gsc;
-        const C wr = g6[0] * ur + g6[1] * us + g6[2] * ut;
-        const C ws = g6[1] * ur + g6[3] * us + g6[4] * ut;
-        const C wt = g6[2] * ur + g6[4] * us + g6[5] * ut;
+        for (int q = 0; q < 6; ++q) g6[q] = to<C>(graw[q][kc]) * gmul;
+        const C wr = r16<H16>(g6[0] * ur + g6[1] * us + g6[2] * ut);
+        const C ws = r16<H16>(g6[1] * ur + g6[3] * us + g6[4] * ut);
+        const C wt = r16<H16>(g6[2] * ur + g6[4] * us + g6[5] * ut);
         if (el < EPB) { sr[el][ij] = wr; ss[el][ij] = ws; }
 #pragma unroll
         for (int l = 0; l < LX; ++l) wacc[l] += sD[k * LX + l] * wt;
@@ -213,14 +262,16 @@ ax_kernel(Batch bt, AxLaunch a)
     }
     double dot = 0.0;
     if (live) {
+        const C hs = H16 ? h1 * (gsc * hscale) : h1;
 #pragma unroll
         for (int k = 0; k < LX; ++k) {
             const int p = k * L2 + ij;
+            const C uk = H16 ? uin[H16 ? k : 0] : ureg[k];
             const C bk = helm ? to<C>(braw[k]) * bsc : (C)0;
-            const C wv = h1 * wacc[k] + h2 * bk * ureg[k];
+            const C wv = hs * wacc[k] + h2 * bk * uk;
             const TW ws = SUB ? (TW)(rraw[k] - to<TW>(wv)) : to<TW>(wv);
             stg(w + ebase + p, ws);
-            if (a.pdot >= 0) dot += (double)ureg[k] * (double)to<C>(ws);
+            if (a.pdot >= 0) dot += (double)uk * (double)to<C>(ws);
         }
     }
     if (a.pdot >= 0) {
@@ -233,7 +284,7 @@ ax_kernel(Batch bt, AxLaunch a)
     }
 }
 
-template <int LX, typename TU, typename TG, typename C>
+template <int LX, typename TU, typename TG, typename C, int H16 = 0>
 static void ax_go(const Batch& b, const AxLaunch& a, hipStream_t s)
 {
     // 1-D grid: groups of 8 element blocks, each group once per component
@@ -243,32 +294,32 @@ static void ax_go(const Batch& b, const AxLaunch& a, hipStream_t s)
         // load and an fp64 output
         if (a.out64) {
             if (a.precond >= 0 && a.tpc == P64)
-                hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 1, double>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+                hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 1, double, 0, H16>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
             else if (a.precond >= 0)
-                hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 2, double>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+                hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 2, double, 0, H16>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
             else
-                hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0, double>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+                hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0, double, 0, H16>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
             return;
         }
     }
     if constexpr (sizeof(TU) == 8) {
         // the Arnoldi operator of an fp64 GMRES basis (Jacobi scaling on load)
         if (a.precond >= 0 && a.tpc == P64) {
-            hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 1, TU>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+            hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 1, TU, 0, H16>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
             return;
         }
         if (a.precond >= 0) {
-            hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 2, TU>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+            hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 2, TU, 0, H16>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
             return;
         }
     }
-    if constexpr (sizeof(TU) == 8 && sizeof(TG) == 8 && sizeof(C) == 8) {
+    if constexpr (sizeof(TU) == 8 && sizeof(TG) == 8 && sizeof(C) == 8 && H16 == 0) {
         if (a.sub >= 0) {
             hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0, TU, 1>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
             return;
         }
     }
-    hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0, TU>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+    hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0, TU, 0, H16>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
 }
 
 // supported (vector, geometry, arithmetic) instantiations; ax_supported()
@@ -292,6 +343,11 @@ static void ax_lx(const Batch& b, const AxLaunch& a, hipStream_t s)
     else if (u == P32 && g == PBF && c == P32) ax_go<LX, float, __hip_bfloat16, float>(b, a, s);
     else if (u == P16 && g == P16 && c == P32) ax_go<LX, __half, __half, float>(b, a, s);
     else if (u == PBF && g == PBF && c == P32) ax_go<LX, __hip_bfloat16, __hip_bfloat16, float>(b, a, s);
+    // 16-bit arithmetic (fp32 sums)
+    else if (u == P32 && g == P16 && c == P16) ax_go<LX, float, __half, float, 1>(b, a, s);
+    else if (u == P16 && g == P16 && c == P16) ax_go<LX, __half, __half, float, 1>(b, a, s);
+    else if (u == P32 && g == PBF && c == PBF) ax_go<LX, float, __hip_bfloat16, float, 2>(b, a, s);
+    else if (u == PBF && g == PBF && c == PBF) ax_go<LX, __hip_bfloat16, __hip_bfloat16, float, 2>(b, a, s);
 }
 
 void launch_ax(const Batch& b, int lx, const AxLaunch& a0, hipStream_t s)

@@ -297,6 +297,9 @@ bool same_policy(const Resolved& a, const Resolved& b)
 // (vector, geometry, arithmetic) instantiations of the Helmholtz kernel
 bool ax_supported(int u, int g, int c)
 {
+    // 16-bit arithmetic: geometry of that format, fp32 or same-format vectors
+    if (c == P16) return g == P16 && (u == P32 || u == P16);
+    if (c == PBF) return g == PBF && (u == P32 || u == PBF);
     if (u == P64) return (c == P64) || (c == P32 && g != P64);
     if (u == P32) return g != P64;
     if (u == P16) return c == P32 && g == P16;
@@ -440,9 +443,19 @@ int resolve_policy(const sem_precision* p, Resolved& r)
         for (int q = 0; q < 3; ++q)
             if (prec_rank(v[q]) < 0) return fail(SEM_EINVAL, std::string(kname[k]) + ": unknown precision");
         if (prec_rank(kr[k].storage) > rp) return fail(SEM_EINVAL, std::string(kname[k]) + ": storage above rp");
-        if (kr[k].compute != SEM_FP64 && kr[k].compute != SEM_FP32)
-            return fail(SEM_EINVAL, std::string(kname[k]) + ": arithmetic must be fp64 or fp32 (16-bit work is "
-                                    "expressed as 16-bit storage)");
+        if (kr[k].compute == SEM_FP16 || kr[k].compute == SEM_BF16) {
+            // Table 2's fp16-compute overrides (B-6, B-7): 16-bit operands, fp32 sums
+            if (k != SEM_K_AX_VEL && k != SEM_K_AX_PRES)
+                return fail(SEM_EINVAL, std::string(kname[k]) + ": 16-bit arithmetic is available for ax_vel and "
+                                        "ax_pres only (elsewhere 16-bit work is 16-bit storage)");
+            if (kr[k].storage != kr[k].compute)
+                return fail(SEM_EINVAL, std::string(kname[k]) + ": 16-bit arithmetic reads geometry stored in the "
+                                        "same 16-bit format");
+            if (kr[k].accumulate != SEM_FP32)
+                return fail(SEM_EINVAL, std::string(kname[k]) + ": 16-bit arithmetic accumulates in fp32");
+        } else if (kr[k].compute != SEM_FP64 && kr[k].compute != SEM_FP32) {
+            return fail(SEM_EINVAL, std::string(kname[k]) + ": unknown arithmetic");
+        }
         if (prec_rank(kr[k].accumulate) < prec_rank(kr[k].compute))
             return fail(SEM_EINVAL, std::string(kname[k]) + ": accumulate below compute");
     }
@@ -1383,7 +1396,11 @@ int sem_ax(sem_ctx* c, const void* u, void* w, double h1, double h2, int buf_pre
     const int tu = to_pid(buf_prec);
     bool held = tg == P64 || (tg == P32 && c->rs.need32) || ((tg == P16 || tg == PBF) && c->rs.need16 && c->rs.kind16 == tg);
     if (!held) return fail(SEM_EINVAL, "the requested geometry precision is not held by this context");
-    const int tc = (tu == P64 && !(flags & SEM_AX_FP32_COMPUTE)) ? P64 : P32;
+    int tc = (tu == P64 && !(flags & SEM_AX_FP32_COMPUTE)) ? P64 : P32;
+    if (flags & SEM_AX_16BIT_COMPUTE) {
+        if (tg != P16 && tg != PBF) return fail(SEM_EINVAL, "SEM_AX_16BIT_COMPUTE needs 16-bit geometry");
+        tc = tg;
+    }
     if (!ax_supported(tu, tg, tc)) return fail(SEM_EINVAL, "unsupported (vector, geometry, arithmetic) combination for Ax");
     sem_ctx* one[1] = {c};
     Batch b = make_batch(one, 1);

@@ -23,6 +23,7 @@ INIT_ZERO, INIT_TGV3D, INIT_TGV2D = 0, 1, 2
 MODE_OPERATOR, MODE_POISSON, MODE_FLUID = 0, 1, 2
 ASSEMBLE = 1
 AX_FP32_COMPUTE = 2
+AX_16BIT_COMPUTE = 4
 F_U, F_P, F_ULAG1, F_ULAG2, F_BNLAG1, F_BNLAG2 = 0, 3, 4, 7, 10, 13
 F_MASS, F_BSUM, F_G, F_M, F_DIAG_A = 16, 17, 18, 24, 33
 
@@ -184,11 +185,16 @@ def tier(name):
                   collocated or dealiased (B-5, adv_dealias); fp32b+bf16a with bf16
     fp32b+fp16all / fp32b+bf16all  16-bit geometry for both operators and
                   opgrad (operator microbenchmarks)
+    fp32b+fp16c   B-6 as Table 2 states it: the velocity Helmholtz operator in
+                  16-bit arithmetic (16-bit operands, fp32 sums) on fp16
+                  geometry; fp32b+bf16c with bf16
+    fp32b+fp16pc  B-7 likewise: the pressure operator in 16-bit arithmetic
     """
     if name == "fp64":
         return precision(FP64)
     h = {"fp32b": None, "fp32b-p32": None, "fp32b+fp16": FP16, "fp32b+bf16": BF16, "fp32b+fp16p": FP16,
-         "fp32b+fp16a": FP16, "fp32b+bf16a": BF16, "fp32b+fp16all": FP16, "fp32b+bf16all": BF16}
+         "fp32b+fp16a": FP16, "fp32b+bf16a": BF16, "fp32b+fp16all": FP16, "fp32b+bf16all": BF16,
+         "fp32b+fp16c": FP16, "fp32b+bf16c": BF16, "fp32b+fp16pc": FP16}
     if name not in h:
         raise ValueError("unknown tier %r" % name)
     blocks = {BLOCK_SEM: (FP32, FP32, FP32), BLOCK_VEL: (FP32, FP32, FP32), BLOCK_PRES: (FP64, FP64, FP32)}
@@ -202,6 +208,10 @@ def tier(name):
         ks[K_AX_PRES] = (FP64, FP64, h[name])
     if name in ("fp32b+fp16a", "fp32b+bf16a"):
         ks[K_CONV] = (FP32, FP32, h[name])
+    if name in ("fp32b+fp16c", "fp32b+bf16c"):
+        ks[K_AX_VEL] = (h[name], FP32, h[name])
+    if name == "fp32b+fp16pc":
+        ks[K_AX_PRES] = (h[name], FP32, h[name])
     return precision(FP32, blocks=blocks, kernels=ks)
 
 
@@ -305,10 +315,11 @@ class Context:
             pass
 
     # ---- operators on torch device tensors
-    def ax(self, u, w, h1=1.0, h2=0.0, geom=INHERIT, assemble=False, fp32_compute=False):
+    def ax(self, u, w, h1=1.0, h2=0.0, geom=INHERIT, assemble=False, fp32_compute=False, half_compute=False):
         assert u.is_cuda and w.is_cuda and u.numel() == self.np and w.numel() == self.np and u.dtype == w.dtype
         assert u.is_contiguous() and w.is_contiguous()
-        flags = (ASSEMBLE if assemble else 0) | (AX_FP32_COMPUTE if fp32_compute else 0)
+        flags = ((ASSEMBLE if assemble else 0) | (AX_FP32_COMPUTE if fp32_compute else 0) |
+                 (AX_16BIT_COMPUTE if half_compute else 0))
         _check(self.L.sem_ax(self.h, C.c_void_p(u.data_ptr()), C.c_void_p(w.data_ptr()), float(h1), float(h2),
                              prec_of(u), int(geom), flags))
         return w

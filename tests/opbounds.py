@@ -55,6 +55,30 @@ def ax_bound(m, u, h1, h2, unit_arith, eps_geo, eps_out, tiny_out=0.0):
     return (gamma(k, unit_arith) + 2 * eps_geo + eps_out) * abs_ax(m, u, h1, h2) + tiny_out
 
 
+def ax16_bound(m, u, h1, h2, eps_op, tiny_op, eps_geo, eps_out, tiny_out=0.0):
+    """Per-point bound for 16-bit arithmetic with fp32 sums (Table 2's
+    fp16-compute overrides as the kernels define them): on top of ax_bound's
+    fp32 terms, four operand roundings in the 16-bit format -- the input
+    (after the element's power-of-two scale s with max|u_e| s in [0.5, 1)),
+    D, the metric-weighted derivatives, D^T -- each relative eps_op, so
+    gamma_4(eps_op) (|A| |u|).  Operands that fall below the 16-bit normal
+    range carry an absolute error tiny_op in scaled units instead: 2^E_e
+    tiny_op on an input of element e (1/s = 2^E_e) propagates through |A|,
+    and on a weighted derivative (scaled by gsc_e/s, gsc_e < 2 max|G_e|)
+    through h1 |D^T| in each of the three directions."""
+    lx = m.lx
+    E = u.size // lx ** 3
+    ue = np.abs(u).reshape(E, -1).max(axis=1)
+    c = np.where(ue > 0, 2.0 ** (np.floor(np.log2(np.where(ue > 0, ue, 1.0))) + 1), 1.0)
+    _, _, D = m.tables()
+    gmax = np.abs(m.G()).reshape(6, E, -1).max(axis=(0, 2))
+    ones = np.repeat(c, lx ** 3)
+    t_in = abs_ax(m, ones, h1, 0.0)
+    t_mid = np.repeat(abs(h1) * 3 * np.abs(D).sum(axis=0).max() * 2 * gmax * c, lx ** 3)
+    return (ax_bound(m, u, h1, h2, 2.0 ** -24, eps_geo, eps_out, tiny_out) + gamma(4, eps_op) * abs_ax(m, u, h1, h2)
+            + tiny_op * (t_in + t_mid))
+
+
 def div_lipschitz(m):
     """L with |div u - div v| <= L max|u - v| at every node: the strong
     divergence sum_c sum_a (dr_a/dx_c) D_a u_c is linear in u with row sums

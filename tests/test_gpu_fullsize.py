@@ -210,7 +210,8 @@ def _errors(ser, ref):
 
 # bounds stated before the runs (fp32b: the C2 bounds; fp64: the GPU's fp64 tier
 # differs from the oracle only by solver stopping points and summation order)
-@pytest.mark.parametrize("tier,eE,eO", [("fp64", 1e-6, 1e-6), ("fp32b", 1e-4, 1e-3), ("fp32b-p32", 1e-4, 1e-3)])
+@pytest.mark.parametrize("tier,eE,eO", [("fp64", 1e-6, 1e-6), ("fp32b", 1e-4, 1e-3), ("fp32b-p32", 1e-4, 1e-3),
+                                        ("fp32b+fp16c", 1e-2, 1e-1)])
 def test_c2_series_against_stored_oracle_series(sem, tier, eE, eO):
     """C2 (32^3, N = 7, Re 1600, dt 5e-4, HSMG, tolerances 1e-6 / 1e-4), the
     bench's 205 steps, against the FP64 oracle's stored series: the error
@@ -223,7 +224,8 @@ def test_c2_series_against_stored_oracle_series(sem, tier, eE, eO):
 
 
 @pytest.mark.parametrize("tier,eE,eO", [("fp64", 1e-6, 1e-6), ("fp32b", 1e-4, 1e-3), ("fp32b+fp16", 1e-2, 1e-1),
-                                        ("fp32b+fp16p", 1e-2, 1e-1)])
+                                        ("fp32b+fp16p", 1e-2, 1e-1), ("fp32b+fp16c", 1e-2, 1e-1),
+                                        ("fp32b+fp16pc", 1e-2, 1e-1)])
 def test_c4_series_against_stored_oracle_series(sem, tier, eE, eO):
     """C4 (16^3, N = 11, dt 2.5e-4, HSMG, tolerances 1e-6 / 1e-4), 400 steps,
     against the FP64 oracle's stored series; the 16-bit tiers also bound the

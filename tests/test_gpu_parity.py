@@ -108,7 +108,8 @@ def test_dssum_matches_oracle(sem, nel, N, amp):
     ("fp32b+bf16all", "bfloat16", 2 ** -8, 2 ** -8),
 ])
 # (3, 1, 3): nine elements, so the last block of four holds a single element
-@pytest.mark.parametrize("nel,N,amp", [((4, 4, 4), 7, 0.1), ((3, 1, 3), 7, 0.1), ((2, 2, 2), 11, 0.1)])
+# (undeformed: the deformation map needs even element counts)
+@pytest.mark.parametrize("nel,N,amp", [((4, 4, 4), 7, 0.1), ((3, 1, 3), 7, 0.0), ((2, 2, 2), 11, 0.1)])
 @pytest.mark.parametrize("h1,h2", [(1.0, 0.0), (1 / 1600, 11 / 6 / 5e-4)])
 def test_ax_reduced_precision_within_rounding_bound(sem, tier, buf, eps_geo, eps_vec, nel, N, amp, h1, h2):
     """Per point: |w_gpu - w| <= (gamma_k(u_arith) + 2 eps_geo + eps_out) (|A| |u|)_i,
@@ -139,6 +140,69 @@ def test_ax_reduced_precision_within_rounding_bound(sem, tier, buf, eps_geo, eps
     print(tier, buf, nel, N, (h1, h2), "max err/bound %.3f" % (err / bound).max(),
           "normwise %.3e = %.3f unit x ratio %.2f" % (rel, rel / unit / ratio, ratio))
     assert rel <= 2 * unit * ratio
+
+
+@pytest.mark.parametrize("tier,buf,eps16,tiny16", [
+    ("fp32b+fp16all", "float32", 2 ** -11, 2 ** -25),
+    ("fp32b+fp16all", "float16", 2 ** -11, 2 ** -25),
+    ("fp32b+bf16all", "float32", 2 ** -8, 2 ** -134),
+    ("fp32b+bf16all", "bfloat16", 2 ** -8, 2 ** -134),
+])
+# N = 7 runs the matrix-core kernel (the undeformed (3, 1, 3) mesh leaves the
+# last block of four with one element); N = 5 and N = 11 the vector kernel's
+# 16-bit mode
+@pytest.mark.parametrize("nel,N,amp", [((4, 4, 4), 7, 0.1), ((3, 1, 3), 7, 0.0), ((4, 2, 2), 5, 0.1),
+                                       ((2, 2, 2), 11, 0.1)])
+@pytest.mark.parametrize("h1,h2", [(1.0, 0.0), (1 / 1600, 11 / 6 / 5e-4)])
+def test_ax_16bit_arithmetic_within_rounding_bound(sem, tier, buf, eps16, tiny16, nel, N, amp, h1, h2):
+    """Table 2's fp16-compute overrides (16-bit operands, fp32 sums): per point
+    within ax_bound's fp32 terms plus gamma_4(eps16) (|A||u|) for the four
+    16-bit operand roundings (tests/opbounds.py ax16_bound).  The rounding
+    must really happen: in Poisson form the result differs from the
+    fp32-arithmetic one by at least a hundredth of the 16-bit unit roundoff,
+    normwise (in Helmholtz form the fp32 mass term dominates the norm)."""
+    c = _ctx(sem, nel, N, tier=tier, mode=sem.MODE_OPERATOR, amp=amp)
+    m = OracleMesh(nel, N, amp=amp, phase=inputs.deform_phases() if amp else None)
+    u = inputs.local_normal(nel, N, seed=0)
+    dt = getattr(torch, buf)
+    ut = _dev(u, dt)
+    u_rounded = ut.double().cpu().numpy()
+    ref = m.ax(u_rounded, h1, h2)
+    geom = sem.FP16 if "fp16" in tier else sem.BF16
+    w = torch.empty(c.np, dtype=dt, device="cuda:0")
+    c.ax(ut, w, h1, h2, geom=geom, half_compute=True)
+    got = w.double().cpu().numpy()
+    eps_out = 2 ** -24 if buf == "float32" else eps16
+    bound = opbounds.ax16_bound(m, u_rounded, h1, h2, eps16, tiny16, eps16, eps_out, opbounds.TINY[buf])
+    err = np.abs(got - ref)
+    w32 = torch.empty_like(w)
+    c.ax(ut, w32, h1, h2, geom=geom)
+    d32 = np.linalg.norm(got - w32.double().cpu().numpy()) / np.linalg.norm(ref)
+    print(tier, buf, nel, N, (h1, h2), "max err/bound %.3f" % (err / bound).max(),
+          "normwise err %.2e, vs fp32 arithmetic %.2e" % (np.linalg.norm(got - ref) / np.linalg.norm(ref), d32))
+    assert np.all(err <= bound), (err / bound).max()
+    if h2 == 0.0:
+        assert d32 >= 0.01 * eps16
+
+
+@pytest.mark.parametrize("geom,tier", [("FP16", "fp32b+fp16all"), ("BF16", "fp32b+bf16all")])
+@pytest.mark.parametrize("N", [7, 5])
+def test_ax_16bit_arithmetic_is_scale_invariant(sem, geom, tier, N):
+    """The per-element power-of-two scale makes the 16-bit roundings relative
+    to each element's own magnitude: with fp32 vectors, w(2^-20 u) equals
+    2^-20 w(u) bit for bit (a PCG correction of size 1e-6 loses nothing to
+    the 16-bit format's subnormal range)."""
+    nel = (4, 2, 2)
+    c = _ctx(sem, nel, N, tier=tier, mode=sem.MODE_OPERATOR, amp=0.1)
+    u = inputs.local_normal(nel, N, seed=3)
+    g = getattr(sem, geom)
+    for h1, h2 in [(1.0, 0.0), (1 / 1600, 11 / 6 / 5e-4)]:
+        ut = _dev(u, torch.float32)
+        w1 = torch.empty_like(ut)
+        w2 = torch.empty_like(ut)
+        c.ax(ut, w1, h1, h2, geom=g, half_compute=True)
+        c.ax(ut * 2.0 ** -20, w2, h1, h2, geom=g, half_compute=True)
+        assert torch.equal(w2, w1 * 2.0 ** -20)
 
 
 def test_poisson_solve_matches_oracle(sem):
@@ -428,7 +492,8 @@ def test_batched_adaptive_dt_is_bitwise_equal_to_alone(sem):
     assert mix[0][0]["dt"] != mix[1][0]["dt"]
 
 
-@pytest.mark.parametrize("proj,dealias,tier", [(0, 0, "fp64"), (3, 0, "fp64"), (0, 1, "fp64"), (0, 0, "fp32b+fp16")])
+@pytest.mark.parametrize("proj,dealias,tier", [(0, 0, "fp64"), (3, 0, "fp64"), (0, 1, "fp64"), (0, 0, "fp32b+fp16"),
+                                               (0, 0, "fp32b+fp16c")])
 def test_batched_step_is_bitwise_equal_to_alone(sem, proj, dealias, tier):
     # with a 3-vector projection space, 5 steps include a full-space restart;
     # the 16-bit-geometry tier runs element counts that leave the last block
@@ -452,7 +517,8 @@ def test_batched_step_is_bitwise_equal_to_alone(sem, proj, dealias, tier):
 
 
 @pytest.mark.parametrize("tier,proj,dealias", [("fp32b", 0, 0), ("fp32b+fp16", 0, 0), ("fp32b+bf16", 0, 0),
-                                               ("fp32b", 20, 0), ("fp32b", 0, 1), ("fp32b+fp16a", 0, 1)])
+                                               ("fp32b", 20, 0), ("fp32b", 0, 1), ("fp32b+fp16a", 0, 1),
+                                               ("fp32b+fp16c", 0, 0), ("fp32b+bf16c", 0, 0), ("fp32b+fp16pc", 0, 0)])
 def test_mixed_tier_c1_energy_and_enstrophy_error(sem, tier, proj, dealias):
     """Mixed tiers against the FP64 oracle on C1 (8^3, N=7, 10 steps): the error
     metrics of the paper (Sec. 4.2 equations) stay inside the stated bounds:

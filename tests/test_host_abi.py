@@ -69,10 +69,25 @@ def test_policy_rules():
         sem.Context(md, fd, sem.precision(sem.FP32, blocks={sem.BLOCK_VEL: (sem.FP64, sem.FP64, sem.FP64)}), bind=False)
     # fp64 compute on fp32 storage is the paper's Group B pattern and is accepted for the pressure block
     sem.Context(md, fd, sem.precision(sem.FP32, blocks={sem.BLOCK_PRES: (sem.FP64, sem.FP64, sem.FP32)}), bind=False)
-    # 16-bit arithmetic is not a kernel; 16-bit storage is
-    with pytest.raises(sem.SemError):
-        sem.Context(md, fd, sem.precision(sem.FP32, kernels={sem.K_AX_VEL: (sem.FP16, sem.FP32, sem.FP16)}), bind=False)
+    # 16-bit storage with fp32 arithmetic, and Table 2's 16-bit arithmetic (fp32
+    # sums) on the Helmholtz/Poisson operators, are accepted
     sem.Context(md, fd, sem.precision(sem.FP32, kernels={sem.K_AX_VEL: (sem.FP32, sem.FP32, sem.FP16)}), bind=False)
+    for k in (sem.K_AX_VEL, sem.K_AX_PRES):
+        for h in (sem.FP16, sem.BF16):
+            sem.Context(md, fd, sem.precision(sem.FP32, kernels={k: (h, sem.FP32, h)}), bind=False)
+    for t in ("fp32b+fp16c", "fp32b+bf16c", "fp32b+fp16pc"):
+        sem.Context(md, fd, sem.tier(t), bind=False)
+    # ... but not elsewhere, not on geometry of another format, and not with
+    # 16-bit or fp64 sums
+    bad16 = [{sem.K_OPGRAD: (sem.FP16, sem.FP32, sem.FP16)}, {sem.K_CONV: (sem.BF16, sem.FP32, sem.BF16)},
+             {sem.K_AX_VEL: (sem.FP16, sem.FP32, sem.FP32)}, {sem.K_AX_VEL: (sem.FP16, sem.FP32, sem.BF16)},
+             {sem.K_AX_VEL: (sem.FP16, sem.FP16, sem.FP16)}, {sem.K_AX_PRES: (sem.BF16, sem.FP64, sem.BF16)}]
+    for ks in bad16:
+        with pytest.raises(sem.SemError):
+            sem.Context(md, fd, sem.precision(sem.FP32, kernels=ks), bind=False)
+    # fp64 velocity vectors have no 16-bit-arithmetic kernel
+    with pytest.raises(sem.SemError):
+        sem.Context(md, fd, sem.precision(sem.FP64, kernels={sem.K_AX_VEL: (sem.FP16, sem.FP32, sem.FP16)}), bind=False)
     # two 16-bit formats in one context are rejected
     with pytest.raises(sem.SemError):
         sem.Context(md, fd, sem.precision(sem.FP32, kernels={sem.K_AX_VEL: (sem.FP32, sem.FP32, sem.FP16),
