@@ -53,11 +53,12 @@ template <typename TG> __device__ __forceinline__ int bfield() { return F_B16; }
 template <> __device__ __forceinline__ int bfield<double>() { return F_B64; }
 template <> __device__ __forceinline__ int bfield<float>() { return F_B32; }
 
-// an fp32 value rounded to the 16-bit format H16 names (1 fp16, 2 bf16) and back
-template <int H16> __device__ __forceinline__ float r16(float x)
+// a value rounded to the 16-bit format H16 names (1 fp16, 2 bf16) and back;
+// H16 == 0 returns it unchanged in its own type (fp64 arithmetic stays fp64)
+template <int H16, typename C> __device__ __forceinline__ C r16(C x)
 {
-    if constexpr (H16 == 1) return (float)(_Float16)x;
-    else if constexpr (H16 == 2) return (float)(__bf16)x;
+    if constexpr (H16 == 1) return (C)(float)(_Float16)(float)x;
+    else if constexpr (H16 == 2) return (C)(float)(__bf16)(float)x;
     else return x;
 }
 
