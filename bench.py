@@ -125,7 +125,7 @@ def ax_leg(sem, torch, inputs, nel=64, N=7):
     Helmholtz form (h1 = 1/1600, h2 = 11/6 / 5e-4) in fp64 and fp32 (bytes per
     point: vectors in and out + 6 geometric factors, + B for Helmholtz), then
     dssum of a vector in fp64 and fp32 (bytes per point: the shared fraction
-    of points read and written once, plus a 4-byte index each).  Legs named
+    of points read and written once).  Legs named
     *_c16 run 16-bit arithmetic (16-bit operands, fp32 sums)."""
     out = {"workload": "%d^3 elements N=%d (%d points), deformed amp 0.1 h, u ~ N(0,1); HIP events over 20 launches "
                        "cycling through 2 vector pairs" % (nel, N, nel ** 3 * (N + 1) ** 3)}
@@ -155,7 +155,7 @@ def ax_leg(sem, torch, inputs, nel=64, N=7):
             shared = 1.0 - ((lx - 2) / lx) ** 3
             for name, dt, b in (("dssum_fp64", torch.float64, 8), ("dssum_fp32", torch.float32, 4)):
                 ms = dssum_rate(sem, torch, ctx, dt)
-                alg = ctx.np * shared * (2 * b + 4)
+                alg = ctx.np * shared * 2 * b
                 out[name] = {"ms": ms, "alg_bytes": alg, "hbm_GBps": alg / (ms * 1e-3) / 1e9,
                              "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del ctx
@@ -173,7 +173,10 @@ def c4_leg(sem, torch, steps, tiers=("fp64", "fp32b-p32", "fp32b", "fp32b+fp16",
     for t in tiers:
         c, secs, st, ser, _ = run_tier(sem, torch, t, (nel,) * 3, N, 1.0 / 1600, dt, 0, steps, None, 1e-6, 1e-4,
                                        0, 0, 0.0, 1, graph)
-        out[t] = {"steps_per_s": steps / secs, "max_div": max(r[3] for r in ser)}
+        out[t] = {"steps_per_s": steps / secs, "max_div": max(r[3] for r in ser),
+                  "vel_iters_mean": sum(max(x["vit"]) for x in st) / len(st),
+                  "vel_cycles_mean": sum(x["vcyc"] for x in st) / len(st),
+                  "pres_iters_mean": sum(x["pit"] for x in st) / len(st)}
         if ref is not None:
             out[t]["error_vs_oracle"] = error_vs_oracle(ser, ref)
         del c

@@ -1,106 +1,124 @@
-// Direct stiffness summation (gather-scatter Q Q^T) without atomics.
+// Direct stiffness summation (gather-scatter Q Q^T) on the periodic box,
+// without atomics or index lists.
 //
-// The shared nodes of a request are listed once, grouped by multiplicity:
-// pairs (face interiors), quads (edge interiors), octets (vertices), each
-// tuple holding the local indices of all copies of one unique node.  A thread
-// owns TPT tuples (strided by the workgroup size, so a wave's accesses follow
-// the list order): it loads all their indices, then for every component all
-// copies, adds the copies in list order and writes the sum back to every
-// copy -- deterministic and race free, with several gathers in flight per
-// thread.  Nodes with a single copy are untouched.
+// Every shared node has one owner copy: the one whose local coordinates are
+// all in [1, N] (a node on the face i = 0 is the i = N node of the element
+// before it in x, and so on).  Element e owns N^3 - (N-1)^3 nodes -- its faces
+// k = N, j = N (k < N) and i = N (j, k < N) -- and for each one a thread reads
+// all 2, 4 or 8 copies, adds them in a fixed order (copy s takes the +d
+// neighbour's side in direction d when bit d of s is set, directions x, y, z
+// in that order among the boundary ones) and writes the sum to every copy.
+// Each node's copies are touched by its owner thread only, so the in-place
+// update is race free and every copy gets the same bits.  Workgroup p runs
+// element block (p % 8) * per + p / 8: workgroups go round-robin over the 8
+// XCDs, so each XCD walks one contiguous range of blocks and the x and y
+// neighbours' lines an owner touches were brought into that XCD's L2 by the
+// blocks just before it.
 #include "k_common.h"
 
 namespace semk {
 
-template <typename T, typename A, int M, int TPT, int NC>
-__device__ __forceinline__ void gs_chunk(const ReqDesc* R, int field, int gate, void* raw,
-                                         const SEM_GLOBAL int* idx, int ntup, int chunk)
+template <typename T, typename A, int NC>
+__global__ void __launch_bounds__(SEM_GS_THREADS)
+dssum_box_kernel(Batch bt, int field, int gate, void* raw, int per)
 {
-    const int t = threadIdx.x;
-    int id[TPT][M];
-    bool own[TPT];
-#pragma unroll
-    for (int q = 0; q < TPT; ++q) {
-        const int tup = (chunk * TPT + q) * SEM_GS_THREADS + t;
-        own[q] = tup < ntup;
-        // threads past the end repeat the last tuple and never store
-        const long long base = (long long)M * (own[q] ? tup : ntup - 1);
-#pragma unroll
-        for (int m = 0; m < M; ++m) id[q][m] = idx[base + m];
-    }
-    // every component's gathers are issued before any scatter (a store may
-    // alias a later component's loads in the compiler's view, which would
-    // otherwise serialise the components)
-    T v[NC][TPT][M];
+    const int p = blockIdx.x;
+    const int g = (p & 7) * per + (p >> 3);
+    if (g >= bt.eb[bt.n]) return;
+    const int ri = find_req(bt.eb, bt.n, g);
+    const ReqDesc* R = bt.r[ri];
+    const int blk = g - bt.eb[ri];
+    const int lx = R->lx, N = lx - 1, nx = R->nel[0], ny = R->nel[1], nz = R->nel[2];
+    const long long L3 = (long long)lx * lx * lx;
+    const int nown = N * N + N * (N - 1) + (N - 1) * (N - 1);
+    const int e0 = blk * R->epb;
+    const int ne = min(R->epb, R->E - e0);
+
     bool on[NC];
+    const SEM_GLOBAL T* ur[NC];
+    SEM_GLOBAL T* uw[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         on[c] = gate_ok(R, gate < 0 ? -1 : gate + c);
-        const SEM_GLOBAL T* u = field >= 0 ? gfield<T>(R, field + c) : gp((const T*)raw);
-#pragma unroll
-        for (int q = 0; q < TPT; ++q)
-#pragma unroll
-            for (int m = 0; m < M; ++m) v[c][q][m] = ldg(u + id[q][m]);
+        ur[c] = field >= 0 ? gfield<T>(R, field + c) : gp((const T*)raw);
+        uw[c] = field >= 0 ? gfieldw<T>(R, field + c) : gp((T*)raw);
     }
+    bool any = false;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        if (!on[c]) continue;
-        SEM_GLOBAL T* u = field >= 0 ? gfieldw<T>(R, field + c) : gp((T*)raw);
+    for (int c = 0; c < NC; ++c) any = any || on[c];
+    if (!any) return;
+
+    for (int q = threadIdx.x; q < ne * nown; q += SEM_GS_THREADS) {
+        const int el = q / nown;
+        int r = q - el * nown;
+        int i, j, k;
+        if (r < N * N) { k = N; i = 1 + r % N; j = 1 + r / N; }
+        else if ((r -= N * N) < N * (N - 1)) { j = N; i = 1 + r % N; k = 1 + r / N; }
+        else { r -= N * (N - 1); i = N; j = 1 + r % (N - 1); k = 1 + r / (N - 1); }
+        const int e = e0 + el;
+        const int ex = e % nx, ey = (e / nx) % ny, ez = e / (nx * ny);
+        // per direction: the two (element coordinate, local coordinate) sides
+        const int cx[2] = {ex, ex + 1 == nx ? 0 : ex + 1}, lxi[2] = {i, 0};
+        const int cy[2] = {ey, ey + 1 == ny ? 0 : ey + 1}, lyj[2] = {j, 0};
+        const int cz[2] = {ez, ez + 1 == nz ? 0 : ez + 1}, lzk[2] = {k, 0};
+        const int bx = i == N, by = j == N, bz = k == N;
+        const int nb = bx + by + bz;
+        long long idx[8];
 #pragma unroll
-        for (int q = 0; q < TPT; ++q) {
-            A s = (A)0;
+        for (int s = 0; s < 8; ++s) {
+            if (s >> nb) break;
+            // bit b of s goes to the b-th boundary direction (x, y, z order)
+            int b = 0, sx = 0, sy = 0, sz = 0;
+            if (bx) sx = (s >> b++) & 1;
+            if (by) sy = (s >> b++) & 1;
+            if (bz) sz = (s >> b++) & 1;
+            const long long ee = cx[sx] + (long long)nx * (cy[sy] + (long long)ny * cz[sz]);
+            idx[s] = ee * L3 + lxi[sx] + lx * (lyj[sy] + lx * lzk[sz]);
+        }
+        const int ncopy = 1 << nb;
+        T v[NC][8];
 #pragma unroll
-            for (int m = 0; m < M; ++m) s += to<A>(v[c][q][m]);
-            const T r = to<T>(s);
-            if (own[q]) {
+        for (int c = 0; c < NC; ++c)
 #pragma unroll
-                for (int m = 0; m < M; ++m) stg(u + id[q][m], r);
-            }
+            for (int s = 0; s < 8; ++s)
+                if (s < ncopy) v[c][s] = ldg(ur[c] + idx[s]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (!on[c]) continue;
+            A sum = (A)0;
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+                if (s < ncopy) sum += to<A>(v[c][s]);
+            const T w = to<T>(sum);
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+                if (s < ncopy) stg(uw[c] + idx[s], w);
         }
     }
 }
 
-template <typename T, typename A, int NC>
-__global__ void __launch_bounds__(SEM_GS_THREADS)
-dssum_kernel(Batch bt, int field, int gate, void* raw)
-{
-    const int g = blockIdx.x;
-    const int ri = find_req(bt.gs, bt.n, g);
-    const ReqDesc* R = bt.r[ri];
-    int c = g - bt.gs[ri];
-    if (c < R->c2) {
-        gs_chunk<T, A, 2, SEM_GS_TPT2, NC>(R, field, gate, raw, gp(R->idx2), R->n2, c);
-        return;
-    }
-    c -= R->c2;
-    if (c < R->c4) {
-        gs_chunk<T, A, 4, SEM_GS_TPT4, NC>(R, field, gate, raw, gp(R->idx4), R->n4, c);
-        return;
-    }
-    c -= R->c4;
-    gs_chunk<T, A, 8, SEM_GS_TPT8, NC>(R, field, gate, raw, gp(R->idx8), R->n8, c);
-}
-
 template <typename T, typename A>
-static void dssum_go(const Batch& b, int field, int ncomp, int gate, void* raw, hipStream_t s)
+static void dssum_box_go(const Batch& b, int field, int ncomp, int gate, void* raw, hipStream_t s)
 {
-    dim3 grid(b.gs[b.n]);
+    const int nblk = b.eb[b.n];
+    const int per = (nblk + 7) / 8;
+    dim3 grid(8 * per);
     if (ncomp == 3)
-        hipLaunchKernelGGL((dssum_kernel<T, A, 3>), grid, dim3(SEM_GS_THREADS), 0, s, b, field, gate, raw);
+        hipLaunchKernelGGL((dssum_box_kernel<T, A, 3>), grid, dim3(SEM_GS_THREADS), 0, s, b, field, gate, raw, per);
     else
         for (int c = 0; c < ncomp; ++c)
-            hipLaunchKernelGGL((dssum_kernel<T, A, 1>), grid, dim3(SEM_GS_THREADS), 0, s, b,
-                               field >= 0 ? field + c : field, gate < 0 ? gate : gate + c, raw);
+            hipLaunchKernelGGL((dssum_box_kernel<T, A, 1>), grid, dim3(SEM_GS_THREADS), 0, s, b,
+                               field >= 0 ? field + c : field, gate < 0 ? gate : gate + c, raw, per);
 }
 
 void launch_dssum(const Batch& b, int field, int ncomp, int tprec, int gate, void* raw, hipStream_t s)
 {
-    if (b.gs[b.n] == 0) return;
+    if (b.eb[b.n] == 0) return;
     switch (tprec) {
-    case P64: dssum_go<double, double>(b, field, ncomp, gate, raw, s); break;
-    case P32: dssum_go<float, float>(b, field, ncomp, gate, raw, s); break;
-    case P16: dssum_go<__half, float>(b, field, ncomp, gate, raw, s); break;
-    case PBF: dssum_go<__hip_bfloat16, float>(b, field, ncomp, gate, raw, s); break;
+    case P64: dssum_box_go<double, double>(b, field, ncomp, gate, raw, s); break;
+    case P32: dssum_box_go<float, float>(b, field, ncomp, gate, raw, s); break;
+    case P16: dssum_box_go<__half, float>(b, field, ncomp, gate, raw, s); break;
+    case PBF: dssum_box_go<__hip_bfloat16, float>(b, field, ncomp, gate, raw, s); break;
     default: break;
     }
 }

@@ -315,11 +315,6 @@ bool op_supported(int m, int c)
 
 }  // namespace
 
-// shared-node lists of one periodic box shape (nel, order)
-struct Tuples {
-    std::vector<int> idx2, idx4, idx8;
-};
-
 // Gauss-Legendre points of the dealiasing grid: the n zeros of P_n by Newton
 // from cos(pi (4i+3)/(4n+2)), weights 2 / ((1 - z^2) P_n'(z)^2); the GLL
 // Lagrange basis at those points, I[q][l] = prod_{m != l} (z_q - x_m)/(x_l - x_m),
@@ -375,15 +370,13 @@ struct sem_ctx {
     Resolved rs;
     int N, lx, E, epb, nb, vepb, nvb, pstride;
     long long np, nglob;
-    int n2, n4, n8;
     std::vector<double> D64tab;
     std::vector<float> D32tab;
     std::vector<double> hsT;    // HSMG tables (flow.hsmg)
     int hs_c0[3];
-    std::shared_ptr<const struct Tuples> tup;  // shared-node lists (cached per mesh shape)
     double vol;
     // layout
-    size_t off_desc, off_S, off_I, off_part, off_D64, off_D32, off_i2, off_i4, off_i8;
+    size_t off_desc, off_S, off_I, off_part, off_D64, off_D32;
     size_t foff[NFIELD];
     size_t fbytes[NFIELD];
     size_t bytes;
@@ -504,79 +497,6 @@ int resolve_policy(const sem_precision* p, Resolved& r)
     return 0;
 }
 
-// shared-node tuples of the periodic box, grouped by multiplicity, each
-// tuple sorted by local index and emitted once (by its smallest copy)
-void build_tuples_into(const sem_ctx* c, Tuples* T)
-{
-    const int nx = c->mesh.nel[0], ny = c->mesh.nel[1], nz = c->mesh.nel[2];
-    const int N = c->N, lx = c->lx;
-    const long long L3 = (long long)lx * lx * lx;
-    for (int e = 0; e < c->E; ++e) {
-        const int ex = e % nx, ey = (e / nx) % ny, ez = e / (nx * ny);
-        for (int k = 0; k < lx; ++k)
-            for (int j = 0; j < lx; ++j)
-                for (int i = 0; i < lx; ++i) {
-                    const bool bi = (i == 0 || i == N), bj = (j == 0 || j == N), bk = (k == 0 || k == N);
-                    const int nb = (int)bi + (int)bj + (int)bk;
-                    if (nb == 0) continue;
-                    // candidate (element coordinate, local index) pairs per direction
-                    int ce[3][2], cl[3][2], cn[3];
-                    const int ecoord[3] = {ex, ey, ez}, lcoord[3] = {i, j, k}, nel[3] = {nx, ny, nz};
-                    for (int d = 0; d < 3; ++d) {
-                        const int l = lcoord[d], ec = ecoord[d];
-                        if (l == 0) {
-                            ce[d][0] = ec; cl[d][0] = 0;
-                            ce[d][1] = (ec - 1 + nel[d]) % nel[d]; cl[d][1] = N;
-                            cn[d] = 2;
-                        } else if (l == N) {
-                            ce[d][0] = ec; cl[d][0] = N;
-                            ce[d][1] = (ec + 1) % nel[d]; cl[d][1] = 0;
-                            cn[d] = 2;
-                        } else {
-                            ce[d][0] = ec; cl[d][0] = l; cn[d] = 1;
-                        }
-                    }
-                    int ids[8], m = 0;
-                    for (int a = 0; a < cn[0]; ++a)
-                        for (int b = 0; b < cn[1]; ++b)
-                            for (int q = 0; q < cn[2]; ++q) {
-                                const long long ee = ce[0][a] + (long long)nx * (ce[1][b] + (long long)ny * ce[2][q]);
-                                ids[m++] = (int)(ee * L3 + cl[0][a] + lx * (cl[1][b] + lx * cl[2][q]));
-                            }
-                    std::sort(ids, ids + m);
-                    const int self = (int)(e * L3 + i + lx * (j + lx * k));
-                    if (ids[0] != self) continue;
-                    std::vector<int>& dst = m == 2 ? T->idx2 : m == 4 ? T->idx4 : T->idx8;
-                    dst.insert(dst.end(), ids, ids + m);
-                }
-    }
-}
-
-// The lists depend only on (nel, order): contexts of the same shape share one
-// immutable copy (serving creates many requests of few shapes).
-void build_tuples(sem_ctx* c)
-{
-    static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int>, std::shared_ptr<const Tuples>> cache;
-    const auto key = std::make_tuple(c->mesh.nel[0], c->mesh.nel[1], c->mesh.nel[2], c->N);
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        auto it = cache.find(key);
-        if (it != cache.end()) c->tup = it->second;
-    }
-    if (!c->tup) {
-        auto T = std::make_shared<Tuples>();
-        build_tuples_into(c, T.get());
-        std::lock_guard<std::mutex> lk(mu);
-        auto it = cache.find(key);
-        if (it == cache.end()) it = cache.emplace(key, std::shared_ptr<const Tuples>(T)).first;
-        c->tup = it->second;
-    }
-    c->n2 = (int)(c->tup->idx2.size() / 2);
-    c->n4 = (int)(c->tup->idx4.size() / 4);
-    c->n8 = (int)(c->tup->idx8.size() / 8);
-}
-
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 void build_layout(sem_ctx* c)
@@ -590,9 +510,6 @@ void build_layout(sem_ctx* c)
     c->off_part = take(sizeof(double) * (size_t)NRED * c->pstride);
     c->off_D64 = take(sizeof(double) * c->D64tab.size());
     c->off_D32 = take(sizeof(float) * c->D32tab.size());
-    c->off_i2 = take(sizeof(int) * c->tup->idx2.size());
-    c->off_i4 = take(sizeof(int) * c->tup->idx4.size());
-    c->off_i8 = take(sizeof(int) * c->tup->idx8.size());
     for (int f = 0; f < NFIELD; ++f) { c->foff[f] = 0; c->fbytes[f] = 0; }
     auto field = [&](int f, size_t bytes) { c->fbytes[f] = bytes; c->foff[f] = take(bytes); };
     const size_t d = 8 * (size_t)np;
@@ -674,7 +591,6 @@ semk::Batch make_batch(sem_ctx* const* ctxs, int n)
     b.n = n;
     b.eb[0] = 0;
     b.vb[0] = 0;
-    b.gs[0] = 0;
     b.el[0] = 0;
     b.hm[0] = 0;
     b.gate = -1;
@@ -684,7 +600,6 @@ semk::Batch make_batch(sem_ctx* const* ctxs, int n)
         sem_ctx* c = ctxs[i];
         b.eb[i + 1] = b.eb[i] + c->nb;
         b.vb[i + 1] = b.vb[i] + c->nvb;
-        b.gs[i + 1] = b.gs[i] + c->hdesc.c2 + c->hdesc.c4 + c->hdesc.c8;
         b.el[i + 1] = b.el[i] + c->E;
         {
             const int mp = hs_mepb(hs_lxm(c->lx));
@@ -1201,7 +1116,6 @@ int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_pr
             }
     c->D64tab.insert(c->D64tab.end(), dl.begin(), dl.end());
     for (double v : dl) c->D32tab.push_back((float)v);
-    build_tuples(c);
     build_layout(c);
     MeshParams& mp = c->mp;
     for (int d = 0; d < 3; ++d) {
@@ -1246,11 +1160,6 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     d.pstride = c->pstride;
     if (c->nb > c->pstride || c->nvb > c->pstride || (long long)c->nb * c->epb < c->E || (long long)c->nvb * c->vepb < c->E)
         return fail(SEM_EINVAL, "internal block layout inconsistent");
-    d.n2 = c->n2; d.n4 = c->n4; d.n8 = c->n8;
-    const int ch2 = SEM_GS_THREADS * SEM_GS_TPT2, ch4 = SEM_GS_THREADS * SEM_GS_TPT4, ch8 = SEM_GS_THREADS * SEM_GS_TPT8;
-    d.c2 = (c->n2 + ch2 - 1) / ch2;
-    d.c4 = (c->n4 + ch4 - 1) / ch4;
-    d.c8 = (c->n8 + ch8 - 1) / ch8;
     d.prec16 = c->rs.need16 ? c->rs.kind16 : 0;
     d.gm_m = c->flow.gmres_restart;
     d.proj_L = c->flow.mode == SEM_MODE_FLUID ? c->flow.proj_dim : 0;
@@ -1258,9 +1167,6 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     d.hs = c->flow.hsmg;
     for (int q = 0; q < 3; ++q) d.hs_c0[q] = c->flow.hsmg ? c->hs_c0[q] : 0;
     d.np = c->np; d.nglob = c->nglob;
-    d.idx2 = (const int*)(c->dev + c->off_i2);
-    d.idx4 = (const int*)(c->dev + c->off_i4);
-    d.idx8 = (const int*)(c->dev + c->off_i8);
     d.S = (double*)(c->dev + c->off_S);
     d.I = (int*)(c->dev + c->off_I);
     d.part = (double*)(c->dev + c->off_part);
@@ -1294,11 +1200,7 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     HIPCHK(hipMemcpyAsync((void*)d.D32, c->D32tab.data(), sizeof(float) * c->D32tab.size(), hipMemcpyHostToDevice, s));
     if (c->flow.hsmg)
         HIPCHK(hipMemcpyAsync(d.f[F_HST], c->hsT.data(), sizeof(double) * c->hsT.size(), hipMemcpyHostToDevice, s));
-    const Tuples& T = *c->tup;
-    if (!T.idx2.empty()) HIPCHK(hipMemcpyAsync((void*)d.idx2, T.idx2.data(), sizeof(int) * T.idx2.size(), hipMemcpyHostToDevice, s));
-    if (!T.idx4.empty()) HIPCHK(hipMemcpyAsync((void*)d.idx4, T.idx4.data(), sizeof(int) * T.idx4.size(), hipMemcpyHostToDevice, s));
-    if (!T.idx8.empty()) HIPCHK(hipMemcpyAsync((void*)d.idx8, T.idx8.data(), sizeof(int) * T.idx8.size(), hipMemcpyHostToDevice, s));
-    // the copies read pageable host memory owned by the cache: finish them before returning
+    // the copies read pageable host memory: finish them before returning
     HIPCHK(hipStreamSynchronize(s));
     c->bound = true;
 

@@ -19,9 +19,6 @@
 #define SEM_MAXB 48          // requests per batched launch
 #define SEM_MAXM 30          // largest GMRES restart length
 #define SEM_GS_THREADS 256   // threads of the gather-scatter kernel
-#define SEM_GS_TPT2 4        // pairs per thread
-#define SEM_GS_TPT4 2        // quads per thread
-#define SEM_GS_TPT8 1        // octets per thread
 #define SEM_VEC_THREADS 256  // threads of point-wise kernels
 #define HS_NELMAX 64         // HSMG: elements per direction at most (a coarse plane fits in LDS)
 #define HS_CPLANE (HS_NELMAX * HS_NELMAX)
@@ -179,8 +176,6 @@ struct ReqDesc {
     int E, lx, epb, nb;         // elements, points per direction, elements per block, blocks
     int vepb, nvb;              // elements per point-wise block, point-wise blocks
     int pstride;                // row stride of the partials: max(nb, nvb)
-    int n2, n4, n8;             // shared-node tuple counts (pairs, quads, octets)
-    int c2, c4, c8;             // tuple chunk counts
     int prec16;                 // 0 none, 2 fp16, 3 bf16
     int gm_m;                   // GMRES restart
     int proj_L;                 // pressure projection space dimension (0 = off)
@@ -188,9 +183,6 @@ struct ReqDesc {
     int hs;                     // HSMG pressure preconditioner on
     int hs_c0[3];               // index of the constant coarse mode per direction
     long long np, nglob;
-    const int* idx2;            // [n2][2]
-    const int* idx4;            // [n4][4]
-    const int* idx8;            // [n8][8]
     double* S;                  // scalars
     int* I;                     // integer state
     double* part;               // reduction partials [NRED][pstride]
@@ -213,7 +205,6 @@ struct Batch {
     int n;                      // requests
     int eb[SEM_MAXB + 1];       // prefix over element blocks
     int vb[SEM_MAXB + 1];       // prefix over point-wise blocks
-    int gs[SEM_MAXB + 1];       // prefix over shared-node chunks
     int el[SEM_MAXB + 1];       // prefix over elements (one-element-per-workgroup kernels)
     int hm[SEM_MAXB + 1];       // prefix over HSMG middle-level blocks (hs_mepb elements each)
     int gate;                   // element operators (conv, opgrad, wdiv, diagnostics): I index that must

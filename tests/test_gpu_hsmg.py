@@ -118,7 +118,7 @@ def test_hsmg_fluid_matches_oracle(sem, proj, dealias, cfl):
         g = gst[k]
         assert g["status"] == 0
         # the GPU applies the preconditioner in another summation order (node
-        # copies summed in tuple order, Z_j = M^{-1} s_j V_j kept and summed at
+        # copies summed in the owner's fixed order, Z_j = M^{-1} s_j V_j kept and summed at
         # the cycle end) and the step's rhs carries the previous steps'
         # rounding: a solve may stop one iteration apart at the tolerance edge
         assert g["vit"] == o["vit"] and abs(g["pit"] - o["pit"]) <= 1, (k, g, o)
