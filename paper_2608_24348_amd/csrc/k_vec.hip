@@ -294,7 +294,28 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         auto pres = fldw<double>(R, F_P);
         auto phi = fld<double>(R, F_GX);
         const double f = S[S_DT] / S[S_BETA0];
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
+        // four of the thread's points per pass, every load before the first store
+        constexpr int U = 4;
+        const long long st = blockDim.x;
+        long long p = pr.p0 + threadIdx.x;
+        for (; p + (U - 1) * st < pr.p1; p += U * st) {
+            double ibv[U], uv[U][3], gv[U][3], pv[U], fv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const long long x = p + u * st;
+                ibv[u] = ib[x]; pv[u] = pres[x]; fv[u] = phi[x];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) { uv[u][q] = us[q][x]; gv[u][q] = gpr[q][x]; }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const long long x = p + u * st;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) un[q][x] = uv[u][q] - f * gv[u][q] * ibv[u];
+                pres[x] = pv[u] + fv[u];
+            }
+        }
+        for (; p < pr.p1; p += st) {
             const double ibp = ib[p];
 #pragma unroll
             for (int q = 0; q < 3; ++q) un[q][p] = us[q][p] - f * gpr[q][p] * ibp;
