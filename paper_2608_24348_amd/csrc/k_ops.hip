@@ -111,7 +111,11 @@ __global__ void __launch_bounds__(ONthr<LX>::v) conv_kernel(Batch bt)
     }
 }
 
-template <int LX, typename TM, typename C>
+// RHS: the step head's form.  Instead of storing grad p it forms the local
+// velocity rhs of the BDF/EXT step point by point,
+//   rhs_c = sum_q a_q BN_c^{n-q} + (B / dt) sum_q b_q u_c^{n-q} - (grad p)_c,
+// so grad p is never written and read back (48 bytes per point)
+template <int LX, typename TM, typename C, bool RHS = false>
 __global__ void __launch_bounds__(ONthr<LX>::v) opgrad_kernel(Batch bt, int src, int dst)
 {
     OPS_PROLOGUE(LX)
@@ -121,16 +125,35 @@ __global__ void __launch_bounds__(ONthr<LX>::v) opgrad_kernel(Batch bt, int src,
     const SEM_GLOBAL TM* M = gfield<TM>(R, mfield<TM>());
     const C msc = melem_scale<TM, C>(R, ee);
     const SEM_GLOBAL double* u = gfield<double>(R, src);
+    double a1 = 0, a2 = 0, a3 = 0, b1 = 0, b2 = 0, b3 = 0, idt = 0;
+    if constexpr (RHS) {
+        const SEM_GLOBAL double* S = gp(R->S);
+        a1 = S[S_EXT]; a2 = S[S_EXT + 1]; a3 = S[S_EXT + 2];
+        b1 = S[S_BDF]; b2 = S[S_BDF + 1]; b3 = S[S_BDF + 2];
+        idt = 1.0 / S[S_DT];
+    }
     C col[LX];
 #pragma unroll
     for (int k = 0; k < LX; ++k) col[k] = (C)u[ebase + k * L2 + ij];
     block_sync_lds();
 #pragma unroll
     for (int k = 0; k < LX; ++k) {
+        const int p = k * L2 + ij;
+        // the rhs inputs of this layer are loaded ahead of the contraction
+        double bv = 0, hv[3] = {0, 0, 0}, ev[3] = {0, 0, 0};
+        if constexpr (RHS) {
+            bv = gfield<double>(R, F_B64)[ebase + p];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                ev[c] = a1 * gfield<double>(R, F_BN + c)[ebase + p] + a2 * ldg_stream(gfield<double>(R, F_BNL1 + c) + ebase + p) +
+                        a3 * ldg_stream(gfield<double>(R, F_BNL2 + c) + ebase + p);
+                hv[c] = b1 * gfield<double>(R, F_U + c)[ebase + p] + b2 * ldg_stream(gfield<double>(R, F_UL1 + c) + ebase + p) +
+                        b3 * ldg_stream(gfield<double>(R, F_UL2 + c) + ebase + p);
+            }
+        }
         if (el < EPB) su[el][ij] = col[k];
         block_sync_lds();
         if (live) {
-            const int p = k * L2 + ij;
             C dr = 0, ds = 0, dt = 0;
 #pragma unroll
             for (int l = 0; l < LX; ++l) {
@@ -143,7 +166,8 @@ __global__ void __launch_bounds__(ONthr<LX>::v) opgrad_kernel(Batch bt, int src,
                 C gc = ldm<TM, C>(M, ((long long)ee * 9 + 0 * 3 + c) * L3 + p, msc) * dr
                      + ldm<TM, C>(M, ((long long)ee * 9 + 1 * 3 + c) * L3 + p, msc) * ds
                      + ldm<TM, C>(M, ((long long)ee * 9 + 2 * 3 + c) * L3 + p, msc) * dt;
-                gfieldw<double>(R, dst + c)[ebase + p] = (double)gc;
+                if constexpr (RHS) gfieldw<double>(R, F_RHS + c)[ebase + p] = ev[c] + (bv * idt) * hv[c] - (double)gc;
+                else gfieldw<double>(R, dst + c)[ebase + p] = (double)gc;
             }
         }
         block_sync_lds();
@@ -327,6 +351,20 @@ void launch_opgrad(const Batch& b, int lx, int tm, int tc, int src, int dst, hip
 {
     dim3 grid(b.eb[b.n]);
 #define GO(L) OPS_DISPATCH(opgrad_kernel, L, grid, dim3(ONthr<L>::v), s, b, src, dst)
+    OPS_LX_SWITCH(lx, GO)
+#undef GO
+}
+
+void launch_opgrad_rhs(const Batch& b, int lx, int tm, int tc, int src, hipStream_t s)
+{
+    dim3 grid(b.eb[b.n]);
+#define GO(L)                                                                                                          \
+    if (tm == P64) hipLaunchKernelGGL((opgrad_kernel<L, double, double, true>), grid, dim3(ONthr<L>::v), 0, s, b, src, -1); \
+    else if (tm == P32 && tc == P64)                                                                                   \
+        hipLaunchKernelGGL((opgrad_kernel<L, float, double, true>), grid, dim3(ONthr<L>::v), 0, s, b, src, -1);       \
+    else if (tm == P32) hipLaunchKernelGGL((opgrad_kernel<L, float, float, true>), grid, dim3(ONthr<L>::v), 0, s, b, src, -1); \
+    else if (tm == P16) hipLaunchKernelGGL((opgrad_kernel<L, __half, float, true>), grid, dim3(ONthr<L>::v), 0, s, b, src, -1); \
+    else hipLaunchKernelGGL((opgrad_kernel<L, __hip_bfloat16, float, true>), grid, dim3(ONthr<L>::v), 0, s, b, src, -1);
     OPS_LX_SWITCH(lx, GO)
 #undef GO
 }

@@ -186,34 +186,6 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
         }
         break;
     }
-    case V_RHS: {
-        // all three components per point (the mass is read once)
-        auto B = fld<double>(R, F_B64);
-        const SEM_GLOBAL double *bn0[3], *bn1[3], *bn2[3], *u0[3], *u1[3], *u2[3], *gpr[3];
-        SEM_GLOBAL double* rhs[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            bn0[q] = fld<double>(R, F_BN + q); bn1[q] = fld<double>(R, F_BNL1 + q); bn2[q] = fld<double>(R, F_BNL2 + q);
-            u0[q] = fld<double>(R, F_U + q); u1[q] = fld<double>(R, F_UL1 + q); u2[q] = fld<double>(R, F_UL2 + q);
-            gpr[q] = fld<double>(R, F_GP + q);
-            rhs[q] = fldw<double>(R, F_RHS + q);
-        }
-        const double a1 = S[S_EXT], a2 = S[S_EXT + 1], a3 = S[S_EXT + 2];
-        const double b1 = S[S_BDF], b2 = S[S_BDF + 1], b3 = S[S_BDF + 2];
-        const double idt = 1.0 / S[S_DT];
-        // the lags are read once per step: streaming loads keep them from
-        // evicting the fields the following kernels read again
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) {
-            const double bi = B[p] * idt;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const double ext = a1 * bn0[q][p] + a2 * ldg_stream(bn1[q] + p) + a3 * ldg_stream(bn2[q] + p);
-                const double hist = b1 * u0[q][p] + b2 * ldg_stream(u1[q] + p) + b3 * ldg_stream(u2[q] + p);
-                rhs[q][p] = ext + bi * hist - gpr[q][p];
-            }
-        }
-        break;
-    }
     case V_IDV: {
         const double h1 = S[S_H1], h2 = S[S_H2];
         auto da = fld<double>(R, F_DA64);
@@ -676,7 +648,7 @@ void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s)
     case OP: hipLaunchKernelGGL((vec_kernel<double, double, OP>), grid, blk, 0, s, b, a); return;
     switch (a.op) {
         VEC_T(V_PCG_INIT) VEC_T(V_PCG_UPD) VEC_T(V_PCG_P) VEC_T(V_US_ADD)
-        VEC_D(V_VRESID) VEC_D(V_US_COPY) VEC_D(V_RHS) VEC_D(V_IDV) VEC_D(V_SUM_UNIQUE) VEC_D(V_SUM_MASS)
+        VEC_D(V_VRESID) VEC_D(V_US_COPY) VEC_D(V_IDV) VEC_D(V_SUM_UNIQUE) VEC_D(V_SUM_MASS)
         VEC_D(V_SUB_MEAN) VEC_D(V_COPY) VEC_D(V_ZERO) VEC_D(V_GM_RESID) VEC_D(V_CORRECT) VEC_D(V_MASS_RAW)
         VEC_D(V_PR_V) VEC_D(V_AXPY_RAW)
     default: break;

@@ -1391,8 +1391,9 @@ void step_head(const Batch& b, const sem_ctx* c0, hipStream_t s)
     vec(b, V_IDV, 1, P64, I_IDVSTALE, s);
     // (i) explicit terms: convection, old pressure gradient, BDF/EXT history
     convection(b, c0, s);
-    launch_opgrad(b, lx, r.opg_m, r.opg_c, F_P, F_GP, s);
-    vec(b, V_RHS, 1, P64, -1, s);  // local rhs (3 components), assembled together with the residual
+    // local rhs (3 components) with the old pressure gradient folded in;
+    // assembled together with the residual
+    launch_opgrad_rhs(b, lx, r.opg_m, r.opg_c, F_P, s);
 }
 
 // (iii) pressure increment: A phi = (beta0/dt) dssum(wdiv(u*)), zero-mean rhs.

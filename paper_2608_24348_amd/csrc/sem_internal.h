@@ -322,6 +322,8 @@ void launch_conv(const Batch& b, int lx, int tm, int tc, hipStream_t s);
 void launch_dealias_geom(const Batch& b, int lx, const MeshParams& mp, int want32, int want16, hipStream_t s);
 void launch_conv_dealias(const Batch& b, int lx, int tm, int tc, hipStream_t s);
 void launch_opgrad(const Batch& b, int lx, int tm, int tc, int src, int dst, hipStream_t s);
+// grad p folded into the step's local velocity rhs (F_RHS), without storing grad p
+void launch_opgrad_rhs(const Batch& b, int lx, int tm, int tc, int src, hipStream_t s);
 void launch_wdiv(const Batch& b, int lx, int tm, int tc, int src, int dst, hipStream_t s);
 void launch_diagnostics(const Batch& b, int lx, hipStream_t s);
 
@@ -338,7 +340,6 @@ enum VecOp : int {
     V_PCG_P,          // PP = PZ + b PP
     V_US_COPY,        // US = U
     V_US_ADD,         // US += PX  (f0 == 1: US = U + PX)
-    V_RHS,            // velocity rhs from the BDF/EXT history
     V_IDV,            // velocity Jacobi inverse diagonal for the current (h1,h2)
     V_SUM_UNIQUE,     // partial sum(f/mult) of field f0 -> R_X3
     V_SUM_MASS,       // partial sum(B f) of field f0 -> R_X3
