@@ -140,7 +140,7 @@ template <typename T> __device__ __forceinline__ void cvt4t(typename Raw4<T>::ty
 }
 
 template <typename TU, typename TG>
-__global__ void __launch_bounds__(128, 3) axm_kernel(Batch bt, AxLaunch a)
+__global__ void __launch_bounds__(128, sizeof(TG) == 4 ? 2 : 3) axm_kernel(Batch bt, AxLaunch a)
 {
     constexpr int LX = 8, L3 = 512;
     __shared__ float sbuf[2][3 * AXM_WS];
@@ -169,13 +169,18 @@ __global__ void __launch_bounds__(128, 3) axm_kernel(Batch bt, AxLaunch a)
 
     const SEM_GLOBAL TU* u = a.src >= 0 ? gfield<TU>(R, a.src + comp) : gp((const TU*)a.u_raw);
     SEM_GLOBAL TU* wo = a.dst >= 0 ? gfieldw<TU>(R, a.dst + comp) : gp((TU*)a.w_raw);
-    const SEM_GLOBAL TG* G = gfield<TG>(R, F_G16);
-    const SEM_GLOBAL TG* Bm = gfield<TG>(R, F_B16);
+    constexpr bool G32 = sizeof(TG) == 4;  // fp32 geometry: no element scale
+    const SEM_GLOBAL TG* G = gfield<TG>(R, G32 ? F_G32 : F_G16);
+    const SEM_GLOBAL TG* Bm = gfield<TG>(R, G32 ? F_B32 : F_B16);
     float h1, h2;
     if (a.hsel >= 0) { h1 = (float)gp(R->S)[a.hsel]; h2 = (float)gp(R->S)[a.hsel + 1]; }
     else { h1 = (float)a.h1; h2 = (float)a.h2; }
-    const SEM_GLOBAL float* scl = gfield<float>(R, F_GSC);
-    const float gsc = scl[ee], bsc = scl[R->E + ee];
+    float gsc = 1.0f, bsc = 1.0f;
+    if constexpr (!G32) {
+        const SEM_GLOBAL float* scl = gfield<float>(R, F_GSC);
+        gsc = scl[ee];
+        bsc = scl[R->E + ee];
+    }
 
     // D (and D^T) operands of the four k-steps: step s covers l = 4(s%2) + g of
     // the half kk' (or e', ii') = s/2 of the K index; zero off the block
@@ -194,7 +199,7 @@ __global__ void __launch_bounds__(128, 3) axm_kernel(Batch bt, AxLaunch a)
     const long long gb = (long long)ee * 6 * L3;
     const bool helm = h2 != 0.0f;
     typename Raw4<TU>::type uraw[4];
-    u2v graw[4][6], braw[4];
+    typename Raw4<TG>::type graw[4][6], braw[4];
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) uraw[tt] = ld_raw(u + eb + (2 * tt + gh) * 64 + mj * 8 + 4 * gl);
 #pragma unroll
@@ -242,7 +247,7 @@ __global__ void __launch_bounds__(128, 3) axm_kernel(Batch bt, AxLaunch a)
         const f4v dt = *(const f4v*)(sT + me * AXM_ES + o);
         float gv[6][4];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) Q4<TG>::unpack(graw[tt][q], gv[q]);
+        for (int q = 0; q < 6; ++q) cvt4t<TG>(graw[tt][q], gv[q]);
         float wr[4], ws[4], wt[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -298,7 +303,7 @@ __global__ void __launch_bounds__(128, 3) axm_kernel(Batch bt, AxLaunch a)
         const int o = (2 * tt + gh) * 64 + mj * 8 + 4 * gl;
         const f4v kt = *(const f4v*)(sT + me * AXM_ES + o);
         float bv[4] = {0.f, 0.f, 0.f, 0.f};
-        if (helm) Q4<TG>::unpack(braw[tt], bv);
+        if (helm) cvt4t<TG>(braw[tt], bv);
         float wv[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) wv[r] = h1 * (acc[tt][r] + kt[r]) + h2 * (bv[r] * bsc) * ur[tt][r];
@@ -563,7 +568,8 @@ __global__ void __launch_bounds__(128, 3) axmh_kernel(Batch bt, AxLaunch a)
 
 bool launch_ax_mfma(const Batch& b, int lx, const AxLaunch& a, hipStream_t s)
 {
-    if (lx != 8 || (a.tg != P16 && a.tg != PBF) || a.precond >= 0 || a.sub >= 0 || a.out64 || a.src_vj) return false;
+    if (lx != 8 || (a.tg != P16 && a.tg != PBF && a.tg != P32) || a.precond >= 0 || a.sub >= 0 || a.out64 || a.src_vj)
+        return false;
     const int ncomp = a.ncomp < 1 ? 1 : a.ncomp;
     AxLaunch q = a;
     q.ncomp = ncomp;
@@ -583,6 +589,11 @@ bool launch_ax_mfma(const Batch& b, int lx, const AxLaunch& a, hipStream_t s)
         return true;
     }
     if (a.tc != P32) return false;
+    if (a.tg == P32) {
+        if (a.tu != P32) return false;
+        hipLaunchKernelGGL((axm_kernel<float, float>), grid, dim3(128), 0, s, b, q);
+        return true;
+    }
     if (a.tu == P32 && a.tg == P16) hipLaunchKernelGGL((axm_kernel<float, __half>), grid, dim3(128), 0, s, b, q);
     else if (a.tu == P32 && a.tg == PBF) hipLaunchKernelGGL((axm_kernel<float, __hip_bfloat16>), grid, dim3(128), 0, s, b, q);
     else if (a.tu == P16 && a.tg == P16) hipLaunchKernelGGL((axm_kernel<__half, __half>), grid, dim3(128), 0, s, b, q);

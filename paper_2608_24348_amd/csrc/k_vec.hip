@@ -82,7 +82,23 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
     case V_VRESID: {
         auto r = fld<double>(R, F_R64 + c);
         MulWalk mw(R, pr);
-        for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x, mw.next()) {
+        // four of the thread's points per pass (loads first), summed in the
+        // same per-thread order as one at a time
+        constexpr int U = 4;
+        const long long st = blockDim.x;
+        long long p = pr.p0 + threadIdx.x;
+        for (; p + (U - 1) * st < pr.p1; p += U * st) {
+            double v[U], im[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                v[u] = r[p + u * st];
+                im[u] = mw.im();
+                mw.next();
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc[0] += v[u] * v[u] * im[u];
+        }
+        for (; p < pr.p1; p += st, mw.next()) {
             const double v = r[p];
             acc[0] += v * v * mw.im();
         }
@@ -178,12 +194,20 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
     case V_US_ADD: {
         auto x = fld<TV>(R, F_PX + c);
         auto us = fldw<double>(R, F_US + c);
-        if (a.f0 == 1) {
-            auto u = fld<double>(R, F_U + c);
-            for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) us[p] = u[p] + (double)x[p];
-        } else {
-            for (long long p = pr.p0 + threadIdx.x; p < pr.p1; p += blockDim.x) us[p] += (double)x[p];
+        // four of the thread's points per pass, every load before the first store
+        constexpr int U = 4;
+        const long long st = blockDim.x;
+        const SEM_GLOBAL double* base = a.f0 == 1 ? fld<double>(R, F_U + c) : us;
+        long long p = pr.p0 + threadIdx.x;
+        for (; p + (U - 1) * st < pr.p1; p += U * st) {
+            double bv[U];
+            TV xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) { bv[u] = base[p + u * st]; xv[u] = x[p + u * st]; }
+#pragma unroll
+            for (int u = 0; u < U; ++u) us[p + u * st] = bv[u] + (double)xv[u];
         }
+        for (; p < pr.p1; p += st) us[p] = base[p] + (double)x[p];
         break;
     }
     case V_IDV: {
