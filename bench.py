@@ -491,11 +491,12 @@ def main():
     ap.add_argument("--alt-tier", default="fp32b",
                     help="another tier run on the headline workload beside --tier ('' = skip)")
     ap.add_argument("--c4-steps", type=int, default=400,
-                    help="steps of the 16^3, N = 11 leg in fp64, fp32b-p32, fp32b and fp32b+fp16 (0 = skip)")
+                    help="steps of the 16^3, N = 11 leg in fp64, fp32b-p32, fp32b, fp32b+fp16 and fp32b+fp16c (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the library has no multi-GPU path (the element-sharded "
-              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (a request's elements would be "
+              "sharded by slabs of the box, with face exchanges around each dssum); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
