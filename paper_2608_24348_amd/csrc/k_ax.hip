@@ -62,6 +62,11 @@ template <int H16, typename C> __device__ __forceinline__ C r16(C x)
     else return x;
 }
 
+// one element per wave at lx = 8 (64 columns): the k-walk's layers are wave-private
+template <int LX> struct AxWave {
+    static constexpr bool v = LX * LX == 64 && Nthr<LX>::v == Epb<LX>::v * 64;
+};
+
 // PC: Jacobi scaling of the input on load (0 none, 1 fp64 diagonal, 2 fp32),
 // a template parameter so the load stays unconditional
 // SUB: residual form, w = r_L - (operator u) with r_L the local (unassembled)
@@ -222,7 +227,7 @@ ax_kernel(Batch bt, AxLaunch a)
             for (int q = 0; q < 6; ++q) graw[q][(k + 1) & 1] = ldg_stream(G + gbase + q * L3 + pn);
         }
         if (el < EPB) su[el][ij] = ureg[k];
-        block_sync_lds();
+        lds_handoff<AxWave<LX>::v>();
         C ur = 0, us = 0, ut = 0;
         if (el < EPB) {
 #pragma unroll
@@ -241,7 +246,7 @@ ax_kernel(Batch bt, AxLaunch a)
         if (el < EPB) { sr[el][ij] = wr; ss[el][ij] = ws; }
 #pragma unroll
         for (int l = 0; l < LX; ++l) wacc[l] += sD[k * LX + l] * wt;
-        block_sync_lds();
+        lds_handoff<AxWave<LX>::v>();
         if (el < EPB) {
             C acc = 0;
 #pragma unroll

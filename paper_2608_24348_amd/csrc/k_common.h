@@ -32,6 +32,17 @@ __device__ __forceinline__ void block_sync_lds()
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Hand-off between per-element LDS layers.  WAVE: each element is exactly one
+// wave, so its layers are private to that wave and a wave's LDS operations
+// complete in order -- waiting for its own LDS traffic is enough and the waves
+// of a workgroup never wait for each other.  Otherwise elements span waves and
+// the workgroup barrier is needed.
+template <bool WAVE> __device__ __forceinline__ void lds_handoff()
+{
+    if constexpr (WAVE) asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    else block_sync_lds();
+}
+
 // loads and stores through global pointers (16-bit types move as raw bits)
 template <typename T> __device__ __forceinline__ T ldg(const SEM_GLOBAL T* p) { return *p; }
 template <> __device__ __forceinline__ __half ldg<__half>(const SEM_GLOBAL __half* p)

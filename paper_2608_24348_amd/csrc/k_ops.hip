@@ -16,6 +16,10 @@ template <int LX> struct OEpb {
 template <int LX> struct ONthr {
     static constexpr int v = (LX * LX * OEpb<LX>::v + 63) / 64 * 64;
 };
+// one element per wave at lx = 8: the k-loops' LDS layers are wave-private
+template <int LX> struct OWave {
+    static constexpr bool v = LX * LX == 64 && ONthr<LX>::v == OEpb<LX>::v * 64;
+};
 
 template <typename TM> __device__ __forceinline__ int mfield() { return F_M16; }
 template <> __device__ __forceinline__ int mfield<double>() { return F_M64; }
@@ -86,7 +90,7 @@ __global__ void __launch_bounds__(ONthr<LX>::v) conv_kernel(Batch bt)
 #pragma unroll
             for (int c = 0; c < 3; ++c) su[c][el][ij] = col[c][k];
         }
-        block_sync_lds();
+        lds_handoff<OWave<LX>::v>();
         if (live) {
             const int p = k * L2 + ij;
             C m[9];
@@ -107,7 +111,7 @@ __global__ void __launch_bounds__(ONthr<LX>::v) conv_kernel(Batch bt)
                 gfieldw<double>(R, F_BN + f)[ebase + p] = -(double)s;
             }
         }
-        block_sync_lds();
+        lds_handoff<OWave<LX>::v>();
     }
 }
 
@@ -152,7 +156,7 @@ __global__ void __launch_bounds__(ONthr<LX>::v) opgrad_kernel(Batch bt, int src,
             }
         }
         if (el < EPB) su[el][ij] = col[k];
-        block_sync_lds();
+        lds_handoff<OWave<LX>::v>();
         if (live) {
             C dr = 0, ds = 0, dt = 0;
 #pragma unroll
@@ -170,7 +174,7 @@ __global__ void __launch_bounds__(ONthr<LX>::v) opgrad_kernel(Batch bt, int src,
                 else gfieldw<double>(R, dst + c)[ebase + p] = (double)gc;
             }
         }
-        block_sync_lds();
+        lds_handoff<OWave<LX>::v>();
     }
 }
 
@@ -204,7 +208,7 @@ __global__ void __launch_bounds__(ONthr<LX>::v) wdiv_kernel(Batch bt, int src, i
         if (el < EPB) { sr[el][ij] = f[0]; ss[el][ij] = f[1]; }
 #pragma unroll
         for (int l = 0; l < LX; ++l) wacc[l] += sD[k * LX + l] * f[2];
-        block_sync_lds();
+        lds_handoff<OWave<LX>::v>();
         if (el < EPB) {
             C acc = 0;
 #pragma unroll
@@ -214,7 +218,7 @@ __global__ void __launch_bounds__(ONthr<LX>::v) wdiv_kernel(Batch bt, int src, i
             }
             wacc[k] += acc;
         }
-        block_sync_lds();
+        lds_handoff<OWave<LX>::v>();
     }
     if (live) {
         SEM_GLOBAL double* out = gfieldw<double>(R, dst);
@@ -262,7 +266,7 @@ __global__ void __launch_bounds__(ONthr<LX>::v) diagnostics_kernel(Batch bt)
 #pragma unroll
             for (int c = 0; c < 3; ++c) su[c][el][ij] = col[c][k];
         }
-        block_sync_lds();
+        lds_handoff<OWave<LX>::v>();
         if (live) {
             const int p = k * L2 + ij;
             const double bm = B[ebase + p];
@@ -300,7 +304,7 @@ __global__ void __launch_bounds__(ONthr<LX>::v) diagnostics_kernel(Batch bt)
             }
             cr = fmax(cr, rate);
         }
-        block_sync_lds();
+        lds_handoff<OWave<LX>::v>();
     }
     double v[2] = {ke, en};
     block_sum<double, 2>(v, red);
