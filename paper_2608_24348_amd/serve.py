@@ -323,6 +323,12 @@ def summarize(done, makespan):
     if len(lat):
         out.update({"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                     "mean_s": float(lat.mean()), "max_s": float(lat.max())})
+        # the tail: the three slowest requests, with their wait for admission
+        # and their time from admission to completion
+        ok = sorted((r for r in done if r.status == "ok"), key=lambda r: r.t_done - r.t_arrival)[-3:]
+        out["slowest"] = [{"kind": r.spec["kind"], "nel": list(r.spec["nel"]), "N": r.spec["N"], "tier": r.spec["tier"],
+                           "latency_s": r.t_done - r.t_arrival, "admit_wait_s": r.t_admit - r.t_arrival,
+                           "service_s": r.t_done - r.t_admit} for r in reversed(ok)]
     return out
 
 
