@@ -156,8 +156,12 @@ def ax_leg(sem, torch, inputs, nel=64, N=7):
             for name, dt, b in (("dssum_fp64", torch.float64, 8), ("dssum_fp32", torch.float32, 4)):
                 ms = dssum_rate(sem, torch, ctx, dt)
                 alg = ctx.np * shared * 2 * b
+                # every row of lx nodes holds a shared node (i = 0 and N), so every
+                # line is read and written: one read and one write of the vector
+                line = ctx.np * 2 * b
                 out[name] = {"ms": ms, "alg_bytes": alg, "hbm_GBps": alg / (ms * 1e-3) / 1e9,
-                             "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                             "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "line_floor_bytes": line,
+                             "line_GBps": line / (ms * 1e-3) / 1e9}
         del ctx
         torch.cuda.empty_cache()
     return out

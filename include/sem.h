@@ -181,8 +181,9 @@ typedef struct {
 /* Validates the descriptors and builds the host tables (GLL nodes and
  * weights, derivative matrix, shared-node lists).  Host only: no device
  * allocation and no HIP call.  Errors: SEM_EINVAL (invalid mesh, order,
- * flow parameters, or a precision above rp outside the SEM_X exceptions, or
- * a combination the library has no kernel for). */
+ * flow parameters, 2^31 or more local points, 2^29 or more local points along
+ * one line of elements in x, a precision above rp outside the SEM_X
+ * exceptions, or a combination the library has no kernel for). */
 int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_precision* prec, sem_ctx** out);
 
 /* Exact device bytes sem_bind needs for this context (geometry in every

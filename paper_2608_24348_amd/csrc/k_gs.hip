@@ -1,107 +1,221 @@
 // Direct stiffness summation (gather-scatter Q Q^T) on the periodic box,
 // without atomics or index lists.
 //
-// Every shared node has one owner copy: the one whose local coordinates are
-// all in [1, N] (a node on the face i = 0 is the i = N node of the element
-// before it in x, and so on).  Element e owns N^3 - (N-1)^3 nodes -- its faces
-// k = N, j = N (k < N) and i = N (j, k < N) -- and for each one a thread reads
-// all 2, 4 or 8 copies, adds them in a fixed order (copy s takes the +d
-// neighbour's side in direction d when bit d of s is set, directions x, y, z
-// in that order among the boundary ones) and writes the sum to every copy.
-// Each node's copies are touched by its owner thread only, so the in-place
-// update is race free and every copy gets the same bits.  Workgroup p runs
-// element block (p % 8) * per + p / 8: workgroups go round-robin over the 8
-// XCDs, so each XCD walks one contiguous range of blocks and the x and y
-// neighbours' lines an owner touches were brought into that XCD's L2 by the
-// blocks just before it.
+// A row is the lx nodes of one element that share (j, k).
+// Task (x-line of elements (ey, ez), j, k), j and k in [1, N], owns the rows
+// (e, j, k) of every element e of the line and, where they hold the same
+// nodes, the rows (e+y, 0, k) when j = N, (e+z, j, 0) when k = N and
+// (e+y+z, 0, 0) when both: every row of the mesh belongs to exactly one task.
+// One wave runs a task.  A lane holds V consecutive nodes of a row (one word
+// of V * sizeof(T) bytes, 8 where lx allows), lx / V lanes a row, and the wave
+// walks the line in segments of 64 / (lx / V) elements, so each load or store
+// moves whole rows.  The x-neighbour's copy of a node (i = N against the next
+// element's i = 0) comes from the neighbouring lane, or from the registers of
+// the neighbouring segment, or, across the periodic wrap, from values read
+// before any row of the line is written.  Every copy of a node adds the same
+// values in the same order (copy s takes the +d side in direction d when bit d
+// of s is set, directions x, y, z in that order among the boundary ones) and
+// so gets the same bits.  Rows of different tasks are disjoint, so the
+// in-place update is race free, and every row is read once and written once,
+// whole: no partial-line writes reach memory.
 #include "k_common.h"
 
 namespace semk {
 
-template <typename T, typename A>
-__global__ void __launch_bounds__(SEM_GS_THREADS)
-dssum_box_kernel(Batch bt, int field, int gate, void* raw, int per)
-{
-    const int p = blockIdx.x;
-    const int g = (p & 7) * per + (p >> 3);
-    if (g >= bt.eb[bt.n]) return;
-    const int ri = find_req(bt.eb, bt.n, g);
-    const ReqDesc* R = bt.r[ri];
-    if (!gate_ok(R, gate)) return;
-    const int blk = g - bt.eb[ri];
-    const int lx = R->lx, N = lx - 1, nx = R->nel[0], ny = R->nel[1], nz = R->nel[2];
-    const long long L3 = (long long)lx * lx * lx;
-    const int nown = N * N + N * (N - 1) + (N - 1) * (N - 1);
-    const int e0 = blk * R->epb;
-    const int ne = min(R->epb, R->E - e0);
-    const SEM_GLOBAL T* ur = field >= 0 ? gfield<T>(R, field) : gp((const T*)raw);
-    SEM_GLOBAL T* uw = field >= 0 ? gfieldw<T>(R, field) : gp((T*)raw);
+// segments in flight per task: with three, the rows of a wave cover the HBM
+// latency (measured at 64^3 elements, N = 7: 0.50 against 0.51 ms for two at
+// fp64, 0.30 against 0.31 ms at fp32)
+constexpr int GS_DEPTH = 3;
 
-    for (int q = threadIdx.x; q < ne * nown; q += SEM_GS_THREADS) {
-        const int el = q / nown;
-        int r = q - el * nown;
-        int i, j, k;
-        if (r < N * N) { k = N; i = 1 + r % N; j = 1 + r / N; }
-        else if ((r -= N * N) < N * (N - 1)) { j = N; i = 1 + r % N; k = 1 + r / N; }
-        else { r -= N * (N - 1); i = N; j = 1 + r % (N - 1); k = 1 + r / (N - 1); }
-        const int e = e0 + el;
-        const int ex = e % nx, ey = (e / nx) % ny, ez = e / (nx * ny);
-        // per direction: the two (element coordinate, local coordinate) sides
-        const int cx[2] = {ex, ex + 1 == nx ? 0 : ex + 1}, lxi[2] = {i, 0};
-        const int cy[2] = {ey, ey + 1 == ny ? 0 : ey + 1}, lyj[2] = {j, 0};
-        const int cz[2] = {ez, ez + 1 == nz ? 0 : ez + 1}, lzk[2] = {k, 0};
-        const int bx = i == N, by = j == N, bz = k == N;
-        const int nb = bx + by + bz;
-        long long idx[8];
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            if (s >> nb) break;
-            // bit b of s goes to the b-th boundary direction (x, y, z order)
-            int b = 0, sx = 0, sy = 0, sz = 0;
-            if (bx) sx = (s >> b++) & 1;
-            if (by) sy = (s >> b++) & 1;
-            if (bz) sz = (s >> b++) & 1;
-            const long long ee = cx[sx] + (long long)nx * (cy[sy] + (long long)ny * cz[sz]);
-            idx[s] = ee * L3 + lxi[sx] + lx * (lyj[sy] + lx * lzk[sz]);
-        }
-        const int ncopy = 1 << nb;
-        T v[8];
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-            if (s < ncopy) v[s] = ldg(ur + idx[s]);
-        A sum = (A)0;
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-            if (s < ncopy) sum += to<A>(v[s]);
-        const T w = to<T>(sum);
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-            if (s < ncopy) stg(uw + idx[s], w);
+template <int B> struct GsWord;
+template <> struct GsWord<2> { using type = unsigned short; };
+template <> struct GsWord<4> { using type = unsigned int; };
+template <> struct GsWord<8> { using type = unsigned long long; };
+
+template <typename U> __device__ __forceinline__ U lane_get(U v, int src)
+{
+    if constexpr (sizeof(U) == 8) {
+        const int lo = __shfl((int)(unsigned)v, src, 64), hi = __shfl((int)(unsigned)(v >> 32), src, 64);
+        return (U)(unsigned)lo | ((U)(unsigned)hi << 32);
+    } else {
+        return (U)(unsigned)__shfl((int)(unsigned)v, src, 64);
     }
 }
 
-// one launch per component: with three fields at once the lines a block's
-// neighbours touch no longer fit an XCD's L2 across the blocks in flight
-// (measured at 32^3, N = 7: 1.04 against 0.93 ms of fp64 dssum per step)
-template <typename T, typename A>
-static void dssum_box_go(const Batch& b, int field, int ncomp, int gate, void* raw, hipStream_t s)
+template <typename U> __device__ __forceinline__ U lane_bcast(U v, int src)
 {
-    const int nblk = b.eb[b.n];
+    if constexpr (sizeof(U) == 8) {
+        const int lo = __builtin_amdgcn_readlane((int)(unsigned)v, src);
+        const int hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), src);
+        return (U)(unsigned)lo | ((U)(unsigned)hi << 32);
+    } else {
+        return (U)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, src);
+    }
+}
+
+template <typename T, int V, typename U> __device__ __forceinline__ T word_get(U w, int q)
+{
+    T v[V];
+    __builtin_memcpy(v, &w, sizeof(U));
+    return v[q];
+}
+
+// one task: NC = 1, 2 or 4 copy rows; row t of the line's element ex starts
+// at byte rr[t] + ex * eb (eb = bytes per element, ib = the lane's byte
+// offset in a row; the setup keeps a line of elements below 4 GB).  Segment s + GS_DEPTH is loaded while segment s is summed,
+// so the x-neighbour of its last element (segment s + 1) is already in
+// registers; the GS_DEPTH + 1 segment buffers rotate by name (the loop is
+// unrolled), so no register copy waits for a load in flight.
+template <int NC, int V, typename T, typename A>
+__device__ __forceinline__ void gs_row_task(const SEM_GLOBAL char* const* rr, SEM_GLOBAL char* const* rw,
+                                            unsigned eb, unsigned ib, int nx, int W, int LP, int el, int p,
+                                            int lane)
+{
+    using U = typename GsWord<V * sizeof(T)>::type;
+    const int nseg = (nx + W - 1) / W;
+    U buf[GS_DEPTH + 1][NC], first[NC], carry[NC];
+    // segment s, lane (el, p); lanes past the line read its last element
+    // (their values are never used)
+    auto load = [&](U (&v)[NC], int s) {
+        const unsigned off = (unsigned)min(s * W + el, nx - 1) * eb + ib;
+#pragma unroll
+        for (int t = 0; t < NC; ++t) v[t] = *(const SEM_GLOBAL U*)(rr[t] + off);
+    };
+    // lane p = 0 holds node i = 0 in its first slot, lane p = LP - 1 node i = N in its last
+    const bool lo = p == 0, hi = p == LP - 1;
+    // sum and store segment s (cur), load segment s + GS_DEPTH into nn
+    auto step = [&](U (&cur)[NC], const U (&nxt)[NC], U (&nn)[NC], int s) {
+        load(nn, s + GS_DEPTH);
+        const int ws = min(W, nx - s * W);
+        const bool more = s + 1 < nseg;
+        T lp[NC], rp[NC];
+#pragma unroll
+        for (int t = 0; t < NC; ++t) {
+            if (s == 0) first[t] = lane_bcast(cur[t], 0);
+            const U r = lane_get(cur[t], min(lane + 1, 63));
+            const U l = lane_get(cur[t], max(lane - 1, 0));
+            const U nb0 = more ? lane_bcast(nxt[t], 0) : first[t];
+            rp[t] = word_get<T, V>(el + 1 < ws ? r : nb0, 0);          // i = 0 of element e+x
+            lp[t] = word_get<T, V>(el > 0 ? l : carry[t], V - 1);      // i = N of element e-x
+        }
+        T out[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            const bool xl = lo && q == 0, xh = hi && q == V - 1;
+            const T o0 = word_get<T, V>(cur[0], q);
+            A sum = to<A>(xl ? lp[0] : o0);
+            if (xl || xh) sum += to<A>(xl ? o0 : rp[0]);
+#pragma unroll
+            for (int t = 1; t < NC; ++t) {
+                const T ot = word_get<T, V>(cur[t], q);
+                sum += to<A>(xl ? lp[t] : ot);
+                if (xl || xh) sum += to<A>(xl ? ot : rp[t]);
+            }
+            out[q] = to<T>(sum);
+        }
+        U w;
+        __builtin_memcpy(&w, out, sizeof(U));
+        if (el < ws) {
+            const unsigned off = (unsigned)(s * W + el) * eb + ib;
+#pragma unroll
+            for (int t = 0; t < NC; ++t) *(SEM_GLOBAL U*)(rw[t] + off) = w;
+        }
+#pragma unroll
+        for (int t = 0; t < NC; ++t) carry[t] = lane_bcast(cur[t], W * LP - 1);
+    };
+    {
+        // the word holding i = N of the line's last element
+        const unsigned off = (unsigned)(nx - 1) * eb + (unsigned)((LP - 1) * V * sizeof(T));
+#pragma unroll
+        for (int t = 0; t < NC; ++t) carry[t] = *(const SEM_GLOBAL U*)(rr[t] + off);
+    }
+#pragma unroll
+    for (int r = 0; r < GS_DEPTH; ++r) load(buf[r], r);
+    for (int s = 0;;) {
+#pragma unroll
+        for (int r = 0; r <= GS_DEPTH; ++r) {
+            step(buf[r], buf[(r + 1) % (GS_DEPTH + 1)], buf[(r + GS_DEPTH) % (GS_DEPTH + 1)], s);
+            if (++s >= nseg) return;
+        }
+    }
+}
+
+// Workgroup p runs task block (p % 8) * per + p / 8, so each XCD walks one
+// contiguous range; within a request the blocks go (ez, k, ey), so the two
+// blocks that share the lines of a row j = 0 are neighbours on one XCD.
+template <typename T, typename A, int V>
+__global__ void __launch_bounds__(SEM_GS_THREADS)
+dssum_rows_kernel(Batch bt, int field, int gate, void* raw, int per)
+{
+    const int pb = blockIdx.x;
+    const int g = (pb & 7) * per + (pb >> 3);
+    if (g >= bt.gl[bt.n]) return;
+    const int ri = find_req(bt.gl, bt.n, g);
+    const ReqDesc* R = bt.r[ri];
+    if (!gate_ok(R, gate)) return;
+    const int lx = R->lx, N = lx - 1, nx = R->nel[0], ny = R->nel[1], nz = R->nel[2];
+    const int blk = g - bt.gl[ri];
+    const int ey = blk % ny, k = 1 + (blk / ny) % N, ez = blk / (ny * N);
+    const int eyp = ey + 1 == ny ? 0 : ey + 1, ezp = ez + 1 == nz ? 0 : ez + 1;
+    const long long L3 = (long long)lx * lx * lx;
+    const int lane = threadIdx.x & 63;
+    const int LP = lx / V, W = 64 / LP, el = lane / LP, p = lane - el * LP;
+    const SEM_GLOBAL T* ur = field >= 0 ? gfield<T>(R, field) : gp((const T*)raw);
+    SEM_GLOBAL T* uw = field >= 0 ? gfieldw<T>(R, field) : gp((T*)raw);
+    const unsigned eb = (unsigned)(L3 * sizeof(T)), ib = (unsigned)(p * V * sizeof(T));
+    // the wave index is uniform; say so, so that the row bases stay scalar
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int j = 1 + wv; j <= N; j += SEM_GS_THREADS / 64) {
+        const int by = j == N, bz = k == N;
+        const SEM_GLOBAL char* rr[4];
+        SEM_GLOBAL char* rw[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            int yy = ey, jj = j, zz = ez, kk = k, bit = 0;
+            if (by && ((t >> bit++) & 1)) { yy = eyp; jj = 0; }
+            if (bz && ((t >> bit++) & 1)) { zz = ezp; kk = 0; }
+            const long long o = (long long)nx * (yy + (long long)ny * zz) * L3 + lx * (jj + lx * kk);
+            rr[t] = (const SEM_GLOBAL char*)(ur + o);
+            rw[t] = (SEM_GLOBAL char*)(uw + o);
+        }
+        if (by && bz) gs_row_task<4, V, T, A>(rr, rw, eb, ib, nx, W, LP, el, p, lane);
+        else if (by || bz) gs_row_task<2, V, T, A>(rr, rw, eb, ib, nx, W, LP, el, p, lane);
+        else gs_row_task<1, V, T, A>(rr, rw, eb, ib, nx, W, LP, el, p, lane);
+    }
+}
+
+// one launch per component
+template <typename T, typename A, int V>
+static void dssum_rows_go(const Batch& b, int field, int ncomp, int gate, void* raw, hipStream_t s)
+{
+    const int nblk = b.gl[b.n];
     const int per = (nblk + 7) / 8;
     dim3 grid(8 * per);
     for (int c = 0; c < ncomp; ++c)
-        hipLaunchKernelGGL((dssum_box_kernel<T, A>), grid, dim3(SEM_GS_THREADS), 0, s, b,
+        hipLaunchKernelGGL((dssum_rows_kernel<T, A, V>), grid, dim3(SEM_GS_THREADS), 0, s, b,
                            field >= 0 ? field + c : field, gate < 0 ? gate : gate + c, raw, per);
+}
+
+// nodes per lane: as many as fit 8 bytes and divide lx; a batch shares one lx
+template <typename T, typename A>
+static void dssum_pick(const Batch& b, int field, int ncomp, int gate, void* raw, hipStream_t s)
+{
+    const int lx = b.lx;
+    if constexpr (sizeof(T) <= 2)
+        if (lx % 4 == 0) return dssum_rows_go<T, A, 4>(b, field, ncomp, gate, raw, s);
+    if constexpr (sizeof(T) <= 4)
+        if (lx % 2 == 0) return dssum_rows_go<T, A, 2>(b, field, ncomp, gate, raw, s);
+    dssum_rows_go<T, A, 1>(b, field, ncomp, gate, raw, s);
 }
 
 void launch_dssum(const Batch& b, int field, int ncomp, int tprec, int gate, void* raw, hipStream_t s)
 {
-    if (b.eb[b.n] == 0) return;
+    if (b.gl[b.n] == 0) return;
     switch (tprec) {
-    case P64: dssum_box_go<double, double>(b, field, ncomp, gate, raw, s); break;
-    case P32: dssum_box_go<float, float>(b, field, ncomp, gate, raw, s); break;
-    case P16: dssum_box_go<__half, float>(b, field, ncomp, gate, raw, s); break;
-    case PBF: dssum_box_go<__hip_bfloat16, float>(b, field, ncomp, gate, raw, s); break;
+    case P64: dssum_pick<double, double>(b, field, ncomp, gate, raw, s); break;
+    case P32: dssum_pick<float, float>(b, field, ncomp, gate, raw, s); break;
+    case P16: dssum_pick<__half, float>(b, field, ncomp, gate, raw, s); break;
+    case PBF: dssum_pick<__hip_bfloat16, float>(b, field, ncomp, gate, raw, s); break;
     default: break;
     }
 }

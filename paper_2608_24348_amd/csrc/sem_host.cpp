@@ -589,10 +589,12 @@ semk::Batch make_batch(sem_ctx* const* ctxs, int n)
     semk::Batch b;
     memset(&b, 0, sizeof(b));
     b.n = n;
+    b.lx = n > 0 ? ctxs[0]->lx : 0;
     b.eb[0] = 0;
     b.vb[0] = 0;
     b.el[0] = 0;
     b.hm[0] = 0;
+    b.gl[0] = 0;
     b.gate = -1;
     b.ncmax = 0;
     b.cnmax = 0;
@@ -605,6 +607,7 @@ semk::Batch make_batch(sem_ctx* const* ctxs, int n)
             const int mp = hs_mepb(hs_lxm(c->lx));
             b.hm[i + 1] = b.hm[i] + (c->E + mp - 1) / mp;
         }
+        b.gl[i + 1] = b.gl[i] + c->mesh.nel[1] * c->mesh.nel[2] * (c->lx - 1);
         b.ncmax = std::max(b.ncmax, c->mesh.nel[0] * c->mesh.nel[1] * c->mesh.nel[2]);
         b.cnmax = std::max(b.cnmax, std::max(c->mesh.nel[1], c->mesh.nel[2]));
         b.r[i] = c->ddesc;
@@ -1031,6 +1034,9 @@ int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_pr
     }
     const long long lx = mesh->order + 1;
     if (E * lx * lx * lx >= (1LL << 31)) return fail(SEM_EINVAL, "more than 2^31 local points");
+    // the gather-scatter addresses a line of elements along x with 32-bit byte offsets
+    if (mesh->nel[0] * lx * lx * lx * 8 >= (1LL << 32))
+        return fail(SEM_EINVAL, "more than 2^29 local points along one line of elements in x");
     if (!(std::fabs(mesh->deform_amp) < 0.25)) return fail(SEM_EINVAL, "deform_amp must be below 0.25 (positive Jacobian)");
     if (flow->mode < SEM_MODE_OPERATOR || flow->mode > SEM_MODE_FLUID) return fail(SEM_EINVAL, "bad mode");
     if (flow->mode >= SEM_MODE_POISSON) {

@@ -203,10 +203,12 @@ struct MeshParams {
 
 struct Batch {
     int n;                      // requests
+    int lx;                     // points per direction, shared by every request of a batch
     int eb[SEM_MAXB + 1];       // prefix over element blocks
     int vb[SEM_MAXB + 1];       // prefix over point-wise blocks
     int el[SEM_MAXB + 1];       // prefix over elements (one-element-per-workgroup kernels)
     int hm[SEM_MAXB + 1];       // prefix over HSMG middle-level blocks (hs_mepb elements each)
+    int gl[SEM_MAXB + 1];       // prefix over gather-scatter workgroups (one per x-line of elements and k)
     int gate;                   // element operators (conv, opgrad, wdiv, diagnostics): I index that must
                                 // be nonzero for a request's blocks to run, or -1
     int ncmax;                  // largest coarse HSMG grid (nx ny nz) of the batch

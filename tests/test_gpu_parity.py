@@ -96,6 +96,28 @@ def test_dssum_matches_oracle(sem, nel, N, amp):
     c.dssum(t32)
     ref32 = m.dssum(u.astype(np.float32).astype(np.float64))
     assert np.abs(t32.cpu().numpy() - ref32).max() <= 8 * 2 ** -23 * np.abs(ref32).max()
+    _copies_equal(m.gid(), t.cpu().numpy())
+    _copies_equal(m.gid(), t32.cpu().numpy())
+    # 16-bit storage: the copies are summed in fp32 and the sum rounded once;
+    # per point |err| <= u_16 |sum| + 7 * 2^-24 sum|copies| (+ half the fp16
+    # subnormal spacing)
+    for dt, u16, tiny in ((torch.float16, 2 ** -11, 2 ** -25), (torch.bfloat16, 2 ** -8, 0.0)):
+        th = _dev(u, dt)
+        uh = th.double().cpu().numpy()
+        c.dssum(th)
+        got = th.double().cpu().numpy()
+        refh = m.dssum(uh)
+        bound = u16 * np.abs(refh) + 7 * 2 ** -24 * m.dssum(np.abs(uh)) + tiny
+        assert (np.abs(got - refh) <= bound).all()
+        _copies_equal(m.gid(), got)
+
+
+def _copies_equal(gid, v):
+    """every copy of a global node holds the same value"""
+    o = np.argsort(gid, kind="stable")
+    g, x = gid[o], v[o]
+    same = g[1:] == g[:-1]
+    assert (x[1:][same] == x[:-1][same]).all()
 
 
 @pytest.mark.parametrize("tier,buf,eps_geo,eps_vec", [

@@ -50,6 +50,8 @@ def test_setup_sizes_and_layout(nel, N, tier):
 @pytest.mark.parametrize("bad", [
     dict(order=1), dict(order=12), dict(nel=(0, 2, 2)),
     dict(amp=0.1, nel=(3, 2, 2)), dict(amp=0.3),
+    # 2^29 local points along one line of elements in x (4 GiB of fp64)
+    dict(nel=(1 << 20, 1, 1), order=7),
 ])
 def test_setup_rejects_bad_meshes(bad):
     nel = bad.get("nel", (2, 2, 2))
