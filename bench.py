@@ -124,8 +124,9 @@ def ax_leg(sem, torch, inputs, nel=64, N=7):
     seeded; the operator in Poisson form in every storage tier and in
     Helmholtz form (h1 = 1/1600, h2 = 11/6 / 5e-4) in fp64 and fp32 (bytes per
     point: vectors in and out + 6 geometric factors, + B for Helmholtz), then
-    dssum of a vector in fp64 and fp32 (bytes per point: the shared fraction
-    of points read and written once).  Legs named
+    dssum of a vector in fp64, fp32 and fp16 (bytes per point: the shared
+    fraction of points read and written once; also the line floor, every point
+    read and written once).  Legs named
     *_c16 run 16-bit arithmetic (16-bit operands, fp32 sums)."""
     out = {"workload": "%d^3 elements N=%d (%d points), deformed amp 0.1 h, u ~ N(0,1); HIP events over 20 launches "
                        "cycling through 2 vector pairs" % (nel, N, nel ** 3 * (N + 1) ** 3)}
@@ -153,7 +154,8 @@ def ax_leg(sem, torch, inputs, nel=64, N=7):
         if tier16 == "fp32b+fp16all":
             lx = N + 1
             shared = 1.0 - ((lx - 2) / lx) ** 3
-            for name, dt, b in (("dssum_fp64", torch.float64, 8), ("dssum_fp32", torch.float32, 4)):
+            for name, dt, b in (("dssum_fp64", torch.float64, 8), ("dssum_fp32", torch.float32, 4),
+                                ("dssum_fp16", torch.float16, 2)):
                 ms = dssum_rate(sem, torch, ctx, dt)
                 alg = ctx.np * shared * 2 * b
                 # every row of lx nodes holds a shared node (i = 0 and N), so every

@@ -62,10 +62,11 @@ template <typename T, int V, typename U> __device__ __forceinline__ T word_get(U
 
 // one task: NC = 1, 2 or 4 copy rows; row t of the line's element ex starts
 // at byte rr[t] + ex * eb (eb = bytes per element, ib = the lane's byte
-// offset in a row; the setup keeps a line of elements below 4 GB).  Segment s + GS_DEPTH is loaded while segment s is summed,
-// so the x-neighbour of its last element (segment s + 1) is already in
-// registers; the GS_DEPTH + 1 segment buffers rotate by name (the loop is
-// unrolled), so no register copy waits for a load in flight.
+// offset in a row; the setup keeps a line of elements below 4 GB).  Segment
+// s + GS_DEPTH is loaded while segment s is summed, so the x-neighbour of its
+// last element (segment s + 1) is already in registers; the GS_DEPTH + 1
+// segment buffers rotate by name (the loop is unrolled), so no register copy
+// waits for a load in flight.
 template <int NC, int V, typename T, typename A>
 __device__ __forceinline__ void gs_row_task(const SEM_GLOBAL char* const* rr, SEM_GLOBAL char* const* rw,
                                             unsigned eb, unsigned ib, int nx, int W, int LP, int el, int p,
@@ -184,16 +185,189 @@ dssum_rows_kernel(Batch bt, int field, int gate, void* raw, int per)
     }
 }
 
+// Plane form, where an element's plane fits a wave (lx * lx / V <= 64 lanes).
+// Task (x-line of elements, k), k in [1, N], owns for every element e of the
+// line the rows (e, j, k), j in [1, N], and the row (e+y, 0, k), which holds
+// the other copies of the plane's j = N nodes; when k = N it also owns the
+// same rows of the planes k = 0 of e+z and e+y+z.  Every row of the mesh
+// belongs to exactly one task.  Lane el * SL + r * LP + p (SL = lx * LP lanes
+// an element) holds V nodes of slot r: slot 0 the row (e+y, 0, k), slots
+// 1..N the rows (e, r, k); a load thus moves rows 1..N of an element's plane,
+// which are contiguous, and the neighbour's row 0.  The y copy of a node sits
+// N slots away in the same register, the z copy in the z-plane register of the
+// same lane, and the x copies come from the next or previous element's lanes,
+// as in the row form.  Every copy of a node adds the same values in the same
+// order, so all copies get the same bits.
+template <typename U> struct GsSeg {
+    U m[2];   // [0] plane k, [1] plane 0 of e+z
+};
+
+template <int ZC, int V, typename T, typename A>
+__device__ __forceinline__ void gs_plane_task(SEM_GLOBAL char* const* lp, unsigned eb, int nx, int EW, int SL,
+                                              int LP, int N, int el, int r, int p, int lane)
+{
+    using U = typename GsWord<V * sizeof(T)>::type;
+    constexpr int NZ = ZC + 1;
+    const int nseg = (nx + EW - 1) / EW;
+    // source lanes: the same slot of the next and previous element (in this
+    // segment, or element 0 of the next and the last of the previous one), and
+    // for each the y copy, dy lanes away (lanes past the last element of a
+    // segment clamp; their values are never used)
+    const int dy = r == 0 ? N * LP : r == N ? -N * LP : 0;
+    auto cl = [](int l) { return min(max(l, 0), 63); };
+    const int rsrc = cl(lane + SL - LP + 1), lsrc = cl(lane - SL + LP - 1);
+    const int rnext = r * LP, lprev = (EW - 1) * SL + r * LP + LP - 1;
+    const int ysrc = cl(lane + dy), rsrc_y = cl(rsrc + dy), lsrc_y = cl(lsrc + dy);
+    const int rnext_y = cl(rnext + dy), lprev_y = cl(lprev + dy);
+    GsSeg<U> buf[GS_DEPTH + 1], first, prev;
+    auto load = [&](GsSeg<U>& b, int s) {
+        const unsigned off = (unsigned)min(s * EW + el, nx - 1) * eb;
+#pragma unroll
+        for (int z = 0; z < NZ; ++z) b.m[z] = *(const SEM_GLOBAL U*)(lp[z] + off);
+    };
+    const bool own_y = r == 0, yb = r == 0 || r == N;
+    // sum and store segment s (cur), load segment s + GS_DEPTH into nn
+    auto step = [&](GsSeg<U>& cur, GsSeg<U>& nxt, GsSeg<U>& nn, int s) {
+        load(nn, s + GS_DEPTH);
+        const int ws = min(EW, nx - s * EW);
+        const bool more = s + 1 < nseg;
+        if (s == 0) first = cur;
+        // per z plane, the words of this lane's node and of its x neighbours on
+        // the -y side (..m) and the +y side (..p) of the node: own element (c),
+        // previous element (l), next element (r)
+        U cm[2], cp[2], lm[2], lpl[2], rm[2], rp[2];
+#pragma unroll
+        for (int z = 0; z < NZ; ++z) {
+            const U an = more ? nxt.m[z] : first.m[z];
+            const U cy = lane_get(cur.m[z], ysrc);
+            U rw0 = lane_get(an, rnext), rw1 = lane_get(an, rnext_y);
+            U lw0 = lane_get(prev.m[z], lprev), lw1 = lane_get(prev.m[z], lprev_y);
+            if (EW > 1) {
+                const U c0 = lane_get(cur.m[z], rsrc), c1 = lane_get(cur.m[z], rsrc_y);
+                const U d0 = lane_get(cur.m[z], lsrc), d1 = lane_get(cur.m[z], lsrc_y);
+                if (el + 1 < ws) { rw0 = c0; rw1 = c1; }
+                if (el > 0) { lw0 = d0; lw1 = d1; }
+            }
+            cm[z] = own_y ? cy : cur.m[z];
+            cp[z] = own_y ? cur.m[z] : cy;
+            lm[z] = own_y ? lw1 : lw0;
+            lpl[z] = own_y ? lw0 : lw1;
+            rm[z] = own_y ? rw1 : rw0;
+            rp[z] = own_y ? rw0 : rw1;
+        }
+        T out[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            // lo: node i = 0, the +x copy (its -x copy is the previous element's
+            // i = N); hi: node i = N, the -x copy
+            const bool lo = p == 0 && q == 0, hi = p == LP - 1 && q == V - 1, xb = lo || hi;
+            // copy (xs, ys, zs) of the node, xs / ys = 1 on the +x / +y side
+            auto term = [&](int zs, int ys, int xs) -> A {
+                const T own = word_get<T, V>(ys ? cp[zs] : cm[zs], q);
+                const T left = word_get<T, V>(ys ? lpl[zs] : lm[zs], V - 1);
+                const T right = word_get<T, V>(ys ? rp[zs] : rm[zs], 0);
+                return to<A>(xs ? (lo ? own : right) : (lo ? left : own));
+            };
+            A sum = term(0, 0, 0);
+            if (xb) sum += term(0, 0, 1);
+            if (yb) {
+                sum += term(0, 1, 0);
+                if (xb) sum += term(0, 1, 1);
+            }
+            if constexpr (ZC) {
+                sum += term(1, 0, 0);
+                if (xb) sum += term(1, 0, 1);
+                if (yb) {
+                    sum += term(1, 1, 0);
+                    if (xb) sum += term(1, 1, 1);
+                }
+            }
+            out[q] = to<T>(sum);
+        }
+        U w;
+        __builtin_memcpy(&w, out, sizeof(U));
+        if (el < ws) {
+            const unsigned off = (unsigned)(s * EW + el) * eb;
+#pragma unroll
+            for (int z = 0; z < NZ; ++z) *(SEM_GLOBAL U*)(lp[z] + off) = w;
+        }
+        prev = cur;
+    };
+    {
+        // the line's last element, for the left neighbour of the first
+        const unsigned off = (unsigned)(nx - 1) * eb;
+#pragma unroll
+        for (int z = 0; z < NZ; ++z) prev.m[z] = *(const SEM_GLOBAL U*)(lp[z] + off);
+    }
+#pragma unroll
+    for (int b = 0; b < GS_DEPTH; ++b) load(buf[b], b);
+    for (int s = 0;;) {
+#pragma unroll
+        for (int b = 0; b <= GS_DEPTH; ++b) {
+            step(buf[b], buf[(b + 1) % (GS_DEPTH + 1)], buf[(b + GS_DEPTH) % (GS_DEPTH + 1)], s);
+            if (++s >= nseg) return;
+        }
+    }
+}
+
+// Workgroup p runs task block (p % 8) * per + p / 8 (one x-line and four
+// planes k, a wave each); within a request the blocks go (ez, k / 4, ey).
+template <typename T, typename A, int V>
+__global__ void __launch_bounds__(SEM_GS_THREADS)
+dssum_planes_kernel(Batch bt, int field, int gate, void* raw, int per)
+{
+    const int pb = blockIdx.x;
+    const int g = (pb & 7) * per + (pb >> 3);
+    if (g >= bt.gq[bt.n]) return;
+    const int ri = find_req(bt.gq, bt.n, g);
+    const ReqDesc* R = bt.r[ri];
+    if (!gate_ok(R, gate)) return;
+    const int lx = R->lx, N = lx - 1, nx = R->nel[0], ny = R->nel[1], nz = R->nel[2];
+    const int nkq = (N + 3) / 4;
+    const int blk = g - bt.gq[ri];
+    const int ey = blk % ny, kq = (blk / ny) % nkq, ez = blk / (ny * nkq);
+    // the wave index is uniform; say so, so that k and its branches stay scalar
+    const int k = 4 * kq + 1 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (k > N) return;
+    const int eyp = ey + 1 == ny ? 0 : ey + 1, ezp = ez + 1 == nz ? 0 : ez + 1;
+    const long long L3 = (long long)lx * lx * lx;
+    const int lane = threadIdx.x & 63;
+    const int LP = lx / V, SL = lx * LP, EW = 64 / SL;
+    const int el = lane / SL, r = (lane - el * SL) / LP, p = lane - el * SL - r * LP;
+    SEM_GLOBAL T* u = field >= 0 ? gfieldw<T>(R, field) : gp((T*)raw);
+    // this lane's word in element 0 of the line: slot 0 from the +y line
+    const long long lin = (long long)nx * (ey + (long long)ny * ez), liny = (long long)nx * (eyp + (long long)ny * ez);
+    const long long linz = (long long)nx * (ey + (long long)ny * ezp), linyz = (long long)nx * (eyp + (long long)ny * ezp);
+    SEM_GLOBAL char* lp[2];
+    lp[0] = (SEM_GLOBAL char*)(u + (r == 0 ? liny : lin) * L3 + lx * (r + lx * k) + p * V);
+    lp[1] = (SEM_GLOBAL char*)(u + (r == 0 ? linyz : linz) * L3 + lx * r + p * V);
+    const unsigned eb = (unsigned)(L3 * sizeof(T));
+    if (k == N) gs_plane_task<1, V, T, A>(lp, eb, nx, EW, SL, LP, N, el, r, p, lane);
+    else gs_plane_task<0, V, T, A>(lp, eb, nx, EW, SL, LP, N, el, r, p, lane);
+}
+
+// The plane form asks for LDS it does not use, so that at most five of its
+// workgroups share a CU (160 KB): fewer line walks at once run faster (64^3
+// elements, N = 7: fp64 0.461 against 0.487 ms at seven waves per SIMD, fp32
+// 0.237 against 0.242 ms; three workgroups: 0.658 ms).
+constexpr unsigned GS_PLANES_LDS = 32000;
+
 // one launch per component
 template <typename T, typename A, int V>
-static void dssum_rows_go(const Batch& b, int field, int ncomp, int gate, void* raw, hipStream_t s)
+static void dssum_go(const Batch& b, int field, int ncomp, int gate, void* raw, hipStream_t s)
 {
-    const int nblk = b.gl[b.n];
+    const bool planes = gs_planes(b.lx, V);
+    const int nblk = planes ? b.gq[b.n] : b.gl[b.n];
     const int per = (nblk + 7) / 8;
     dim3 grid(8 * per);
-    for (int c = 0; c < ncomp; ++c)
-        hipLaunchKernelGGL((dssum_rows_kernel<T, A, V>), grid, dim3(SEM_GS_THREADS), 0, s, b,
-                           field >= 0 ? field + c : field, gate < 0 ? gate : gate + c, raw, per);
+    for (int c = 0; c < ncomp; ++c) {
+        const int f = field >= 0 ? field + c : field, gt = gate < 0 ? gate : gate + c;
+        if (planes)
+            hipLaunchKernelGGL((dssum_planes_kernel<T, A, V>), grid, dim3(SEM_GS_THREADS), GS_PLANES_LDS, s, b, f, gt,
+                               raw, per);
+        else
+            hipLaunchKernelGGL((dssum_rows_kernel<T, A, V>), grid, dim3(SEM_GS_THREADS), 0, s, b, f, gt, raw, per);
+    }
 }
 
 // nodes per lane: as many as fit 8 bytes and divide lx; a batch shares one lx
@@ -202,10 +376,10 @@ static void dssum_pick(const Batch& b, int field, int ncomp, int gate, void* raw
 {
     const int lx = b.lx;
     if constexpr (sizeof(T) <= 2)
-        if (lx % 4 == 0) return dssum_rows_go<T, A, 4>(b, field, ncomp, gate, raw, s);
+        if (lx % 4 == 0) return dssum_go<T, A, 4>(b, field, ncomp, gate, raw, s);
     if constexpr (sizeof(T) <= 4)
-        if (lx % 2 == 0) return dssum_rows_go<T, A, 2>(b, field, ncomp, gate, raw, s);
-    dssum_rows_go<T, A, 1>(b, field, ncomp, gate, raw, s);
+        if (lx % 2 == 0) return dssum_go<T, A, 2>(b, field, ncomp, gate, raw, s);
+    dssum_go<T, A, 1>(b, field, ncomp, gate, raw, s);
 }
 
 void launch_dssum(const Batch& b, int field, int ncomp, int tprec, int gate, void* raw, hipStream_t s)

@@ -595,6 +595,7 @@ semk::Batch make_batch(sem_ctx* const* ctxs, int n)
     b.el[0] = 0;
     b.hm[0] = 0;
     b.gl[0] = 0;
+    b.gq[0] = 0;
     b.gate = -1;
     b.ncmax = 0;
     b.cnmax = 0;
@@ -608,6 +609,7 @@ semk::Batch make_batch(sem_ctx* const* ctxs, int n)
             b.hm[i + 1] = b.hm[i] + (c->E + mp - 1) / mp;
         }
         b.gl[i + 1] = b.gl[i] + c->mesh.nel[1] * c->mesh.nel[2] * (c->lx - 1);
+        b.gq[i + 1] = b.gq[i] + c->mesh.nel[1] * c->mesh.nel[2] * ((c->lx - 1 + 3) / 4);
         b.ncmax = std::max(b.ncmax, c->mesh.nel[0] * c->mesh.nel[1] * c->mesh.nel[2]);
         b.cnmax = std::max(b.cnmax, std::max(c->mesh.nel[1], c->mesh.nel[2]));
         b.r[i] = c->ddesc;

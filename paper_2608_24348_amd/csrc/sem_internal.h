@@ -208,7 +208,8 @@ struct Batch {
     int vb[SEM_MAXB + 1];       // prefix over point-wise blocks
     int el[SEM_MAXB + 1];       // prefix over elements (one-element-per-workgroup kernels)
     int hm[SEM_MAXB + 1];       // prefix over HSMG middle-level blocks (hs_mepb elements each)
-    int gl[SEM_MAXB + 1];       // prefix over gather-scatter workgroups (one per x-line of elements and k)
+    int gl[SEM_MAXB + 1];       // prefix over row-form gather-scatter workgroups (one per x-line of elements and k)
+    int gq[SEM_MAXB + 1];       // prefix over plane-form gather-scatter workgroups (one per x-line and 4 planes k)
     int gate;                   // element operators (conv, opgrad, wdiv, diagnostics): I index that must
                                 // be nonzero for a request's blocks to run, or -1
     int ncmax;                  // largest coarse HSMG grid (nx ny nz) of the batch
@@ -253,6 +254,10 @@ __host__ __device__ inline HsOff hs_off(int lx, const int* nel)
     o.total = q;
     return o;
 }
+
+// gather-scatter: the plane form runs where an element's plane fits a wave
+// with V nodes a lane (lx * lx / V <= 64), else the row form
+__host__ __device__ constexpr bool gs_planes(int lx, int V) { return lx * (lx / V) <= 64; }
 
 // elements per workgroup of the element kernels (shared by host and device)
 __host__ __device__ constexpr int epb_of(int lx)
