@@ -70,7 +70,7 @@ template <typename T, int V, typename U> __device__ __forceinline__ T word_get(U
 template <int NC, int V, typename T, typename A>
 __device__ __forceinline__ void gs_row_task(const SEM_GLOBAL char* const* rr, SEM_GLOBAL char* const* rw,
                                             unsigned eb, unsigned ib, int nx, int W, int LP, int el, int p,
-                                            int lane)
+                                            int lane, bool nrm, double& acc)
 {
     using U = typename GsWord<V * sizeof(T)>::type;
     const int nseg = (nx + W - 1) / W;
@@ -120,6 +120,15 @@ __device__ __forceinline__ void gs_row_task(const SEM_GLOBAL char* const* rr, SE
             const unsigned off = (unsigned)(s * W + el) * eb + ib;
 #pragma unroll
             for (int t = 0; t < NC; ++t) *(SEM_GLOBAL U*)(rw[t] + off) = w;
+            // NC copies of each node written here, each 1 / (NC * 2^x) of it
+            if (nrm) {
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    const double v = to<double>(out[q]);
+                    const bool xb = (lo && q == 0) || (hi && q == V - 1);
+                    acc += xb ? 0.5 * v * v : v * v;
+                }
+            }
         }
 #pragma unroll
         for (int t = 0; t < NC; ++t) carry[t] = lane_bcast(cur[t], W * LP - 1);
@@ -141,12 +150,28 @@ __device__ __forceinline__ void gs_row_task(const SEM_GLOBAL char* const* rr, SE
     }
 }
 
+// Squared norm over unique nodes, fused into the sum: every local point is
+// written by exactly one lane, which adds w^2 / (its node's copy count), so a
+// workgroup's lanes add up to sum_nodes w^2 over the nodes they wrote.  The
+// workgroup's fixed-order sum is its partial (slot pslot, one per workgroup of
+// the request; workgroup 0 records their number).
+__device__ __forceinline__ void gs_put_norm(const ReqDesc* R, int pslot, int blk, double acc, int nblk)
+{
+    __shared__ double red[SEM_GS_THREADS / 64];
+    double v[1] = {acc};
+    block_sum<double, 1>(v, red);
+    if (threadIdx.x == 0) {
+        gp(R->part)[(long long)pslot * R->pstride + blk] = v[0];
+        if (blk == 0) gp(R->I)[I_PCNT + pslot] = nblk;
+    }
+}
+
 // Workgroup p runs task block (p % 8) * per + p / 8, so each XCD walks one
 // contiguous range; within a request the blocks go (ez, k, ey), so the two
 // blocks that share the lines of a row j = 0 are neighbours on one XCD.
 template <typename T, typename A, int V>
 __global__ void __launch_bounds__(SEM_GS_THREADS)
-dssum_rows_kernel(Batch bt, int field, int gate, void* raw, int per)
+dssum_rows_kernel(Batch bt, int field, int gate, void* raw, int per, int pslot)
 {
     const int pb = blockIdx.x;
     const int g = (pb & 7) * per + (pb >> 3);
@@ -166,6 +191,7 @@ dssum_rows_kernel(Batch bt, int field, int gate, void* raw, int per)
     const unsigned eb = (unsigned)(L3 * sizeof(T)), ib = (unsigned)(p * V * sizeof(T));
     // the wave index is uniform; say so, so that the row bases stay scalar
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double acc = 0.0;
     for (int j = 1 + wv; j <= N; j += SEM_GS_THREADS / 64) {
         const int by = j == N, bz = k == N;
         const SEM_GLOBAL char* rr[4];
@@ -179,10 +205,11 @@ dssum_rows_kernel(Batch bt, int field, int gate, void* raw, int per)
             rr[t] = (const SEM_GLOBAL char*)(ur + o);
             rw[t] = (SEM_GLOBAL char*)(uw + o);
         }
-        if (by && bz) gs_row_task<4, V, T, A>(rr, rw, eb, ib, nx, W, LP, el, p, lane);
-        else if (by || bz) gs_row_task<2, V, T, A>(rr, rw, eb, ib, nx, W, LP, el, p, lane);
-        else gs_row_task<1, V, T, A>(rr, rw, eb, ib, nx, W, LP, el, p, lane);
+        if (by && bz) gs_row_task<4, V, T, A>(rr, rw, eb, ib, nx, W, LP, el, p, lane, pslot >= 0, acc);
+        else if (by || bz) gs_row_task<2, V, T, A>(rr, rw, eb, ib, nx, W, LP, el, p, lane, pslot >= 0, acc);
+        else gs_row_task<1, V, T, A>(rr, rw, eb, ib, nx, W, LP, el, p, lane, pslot >= 0, acc);
     }
+    if (pslot >= 0) gs_put_norm(R, pslot, blk, acc, bt.gl[ri + 1] - bt.gl[ri]);
 }
 
 // Plane form, where an element's plane fits a wave (lx * lx / V <= 64 lanes).
@@ -204,7 +231,7 @@ template <typename U> struct GsSeg {
 
 template <int ZC, int V, typename T, typename A>
 __device__ __forceinline__ void gs_plane_task(SEM_GLOBAL char* const* lp, unsigned eb, int nx, int EW, int SL,
-                                              int LP, int N, int el, int r, int p, int lane)
+                                              int LP, int N, int el, int r, int p, int lane, bool nrm, double& acc)
 {
     using U = typename GsWord<V * sizeof(T)>::type;
     constexpr int NZ = ZC + 1;
@@ -290,6 +317,16 @@ __device__ __forceinline__ void gs_plane_task(SEM_GLOBAL char* const* lp, unsign
             const unsigned off = (unsigned)(s * EW + el) * eb;
 #pragma unroll
             for (int z = 0; z < NZ; ++z) *(SEM_GLOBAL U*)(lp[z] + off) = w;
+            // NZ copies of each node written here, each 1 / (NZ * 2^(x + y)) of it
+            if (nrm) {
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    const double v = to<double>(out[q]);
+                    const bool xb = (p == 0 && q == 0) || (p == LP - 1 && q == V - 1);
+                    const double f = (xb ? 0.5 : 1.0) * (yb ? 0.5 : 1.0);
+                    acc += f * v * v;
+                }
+            }
         }
         prev = cur;
     };
@@ -314,7 +351,7 @@ __device__ __forceinline__ void gs_plane_task(SEM_GLOBAL char* const* lp, unsign
 // planes k, a wave each); within a request the blocks go (ez, k / 4, ey).
 template <typename T, typename A, int V>
 __global__ void __launch_bounds__(SEM_GS_THREADS)
-dssum_planes_kernel(Batch bt, int field, int gate, void* raw, int per)
+dssum_planes_kernel(Batch bt, int field, int gate, void* raw, int per, int pslot)
 {
     const int pb = blockIdx.x;
     const int g = (pb & 7) * per + (pb >> 3);
@@ -328,7 +365,6 @@ dssum_planes_kernel(Batch bt, int field, int gate, void* raw, int per)
     const int ey = blk % ny, kq = (blk / ny) % nkq, ez = blk / (ny * nkq);
     // the wave index is uniform; say so, so that k and its branches stay scalar
     const int k = 4 * kq + 1 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (k > N) return;
     const int eyp = ey + 1 == ny ? 0 : ey + 1, ezp = ez + 1 == nz ? 0 : ez + 1;
     const long long L3 = (long long)lx * lx * lx;
     const int lane = threadIdx.x & 63;
@@ -342,8 +378,10 @@ dssum_planes_kernel(Batch bt, int field, int gate, void* raw, int per)
     lp[0] = (SEM_GLOBAL char*)(u + (r == 0 ? liny : lin) * L3 + lx * (r + lx * k) + p * V);
     lp[1] = (SEM_GLOBAL char*)(u + (r == 0 ? linyz : linz) * L3 + lx * r + p * V);
     const unsigned eb = (unsigned)(L3 * sizeof(T));
-    if (k == N) gs_plane_task<1, V, T, A>(lp, eb, nx, EW, SL, LP, N, el, r, p, lane);
-    else gs_plane_task<0, V, T, A>(lp, eb, nx, EW, SL, LP, N, el, r, p, lane);
+    double acc = 0.0;
+    if (k == N) gs_plane_task<1, V, T, A>(lp, eb, nx, EW, SL, LP, N, el, r, p, lane, pslot >= 0, acc);
+    else if (k < N) gs_plane_task<0, V, T, A>(lp, eb, nx, EW, SL, LP, N, el, r, p, lane, pslot >= 0, acc);
+    if (pslot >= 0) gs_put_norm(R, pslot, blk, acc, bt.gq[ri + 1] - bt.gq[ri]);
 }
 
 // The plane form asks for LDS it does not use, so that at most five of its
@@ -354,7 +392,7 @@ constexpr unsigned GS_PLANES_LDS = 32000;
 
 // one launch per component
 template <typename T, typename A, int V>
-static void dssum_go(const Batch& b, int field, int ncomp, int gate, void* raw, hipStream_t s)
+static void dssum_go(const Batch& b, int field, int ncomp, int gate, void* raw, hipStream_t s, int pslot)
 {
     const bool planes = gs_planes(b.lx, V);
     const int nblk = planes ? b.gq[b.n] : b.gl[b.n];
@@ -362,34 +400,35 @@ static void dssum_go(const Batch& b, int field, int ncomp, int gate, void* raw, 
     dim3 grid(8 * per);
     for (int c = 0; c < ncomp; ++c) {
         const int f = field >= 0 ? field + c : field, gt = gate < 0 ? gate : gate + c;
+        const int ps = pslot >= 0 ? pslot + c : -1;
         if (planes)
             hipLaunchKernelGGL((dssum_planes_kernel<T, A, V>), grid, dim3(SEM_GS_THREADS), GS_PLANES_LDS, s, b, f, gt,
-                               raw, per);
+                               raw, per, ps);
         else
-            hipLaunchKernelGGL((dssum_rows_kernel<T, A, V>), grid, dim3(SEM_GS_THREADS), 0, s, b, f, gt, raw, per);
+            hipLaunchKernelGGL((dssum_rows_kernel<T, A, V>), grid, dim3(SEM_GS_THREADS), 0, s, b, f, gt, raw, per, ps);
     }
 }
 
 // nodes per lane: as many as fit 8 bytes and divide lx; a batch shares one lx
 template <typename T, typename A>
-static void dssum_pick(const Batch& b, int field, int ncomp, int gate, void* raw, hipStream_t s)
+static void dssum_pick(const Batch& b, int field, int ncomp, int gate, void* raw, hipStream_t s, int pslot)
 {
     const int lx = b.lx;
     if constexpr (sizeof(T) <= 2)
-        if (lx % 4 == 0) return dssum_go<T, A, 4>(b, field, ncomp, gate, raw, s);
+        if (lx % 4 == 0) return dssum_go<T, A, 4>(b, field, ncomp, gate, raw, s, pslot);
     if constexpr (sizeof(T) <= 4)
-        if (lx % 2 == 0) return dssum_go<T, A, 2>(b, field, ncomp, gate, raw, s);
-    dssum_go<T, A, 1>(b, field, ncomp, gate, raw, s);
+        if (lx % 2 == 0) return dssum_go<T, A, 2>(b, field, ncomp, gate, raw, s, pslot);
+    dssum_go<T, A, 1>(b, field, ncomp, gate, raw, s, pslot);
 }
 
-void launch_dssum(const Batch& b, int field, int ncomp, int tprec, int gate, void* raw, hipStream_t s)
+void launch_dssum(const Batch& b, int field, int ncomp, int tprec, int gate, void* raw, hipStream_t s, int pslot)
 {
     if (b.gl[b.n] == 0) return;
     switch (tprec) {
-    case P64: dssum_pick<double, double>(b, field, ncomp, gate, raw, s); break;
-    case P32: dssum_pick<float, float>(b, field, ncomp, gate, raw, s); break;
-    case P16: dssum_pick<__half, float>(b, field, ncomp, gate, raw, s); break;
-    case PBF: dssum_pick<__hip_bfloat16, float>(b, field, ncomp, gate, raw, s); break;
+    case P64: dssum_pick<double, double>(b, field, ncomp, gate, raw, s, pslot); break;
+    case P32: dssum_pick<float, float>(b, field, ncomp, gate, raw, s, pslot); break;
+    case P16: dssum_pick<__half, float>(b, field, ncomp, gate, raw, s, pslot); break;
+    case PBF: dssum_pick<__hip_bfloat16, float>(b, field, ncomp, gate, raw, s, pslot); break;
     default: break;
     }
 }

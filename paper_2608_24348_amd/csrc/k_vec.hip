@@ -79,34 +79,6 @@ __global__ void __launch_bounds__(SEM_VEC_THREADS) vec_kernel(Batch bt, VecArgs 
     double acc[2] = {0.0, 0.0};
 
     switch (OP) {
-    case V_VRESID: {
-        auto r = fld<double>(R, F_R64 + c);
-        MulWalk mw(R, pr);
-        // four of the thread's points per pass (loads first), summed in the
-        // same per-thread order as one at a time
-        constexpr int U = 4;
-        const long long st = blockDim.x;
-        long long p = pr.p0 + threadIdx.x;
-        for (; p + (U - 1) * st < pr.p1; p += U * st) {
-            double v[U], im[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                v[u] = r[p + u * st];
-                im[u] = mw.im();
-                mw.next();
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) acc[0] += v[u] * v[u] * im[u];
-        }
-        for (; p < pr.p1; p += st, mw.next()) {
-            const double v = r[p];
-            acc[0] += v * v * mw.im();
-        }
-        double v2[1] = {acc[0]};
-        block_sum<double, 1>(v2, red);
-        if (threadIdx.x == 0) put_partial(R, R_A + c, blk, v2[0]);
-        break;
-    }
     case V_PCG_INIT: {
         auto r64 = fld<double>(R, F_R64 + c);
         auto idv = fld<TV>(R, idv_field<TV>());
@@ -672,7 +644,7 @@ void launch_vec(const Batch& b, const VecArgs& a, hipStream_t s)
     case OP: hipLaunchKernelGGL((vec_kernel<double, double, OP>), grid, blk, 0, s, b, a); return;
     switch (a.op) {
         VEC_T(V_PCG_INIT) VEC_T(V_PCG_UPD) VEC_T(V_PCG_P) VEC_T(V_US_ADD)
-        VEC_D(V_VRESID) VEC_D(V_US_COPY) VEC_D(V_IDV) VEC_D(V_SUM_UNIQUE) VEC_D(V_SUM_MASS)
+        VEC_D(V_US_COPY) VEC_D(V_IDV) VEC_D(V_SUM_UNIQUE) VEC_D(V_SUM_MASS)
         VEC_D(V_SUB_MEAN) VEC_D(V_COPY) VEC_D(V_ZERO) VEC_D(V_GM_RESID) VEC_D(V_CORRECT) VEC_D(V_MASS_RAW)
         VEC_D(V_PR_V) VEC_D(V_AXPY_RAW)
     default: break;

@@ -791,13 +791,14 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
     const int tv = r.tv;
     int* hf = c0->hflags;
     // fp64 residual of the current state: R64 = dssum(RHS_L - H_L U) (the
-    // local rhs is not assembled on its own), norms -> VACT
+    // local rhs is not assembled on its own); the gather-scatter also forms
+    // the norms over unique nodes, and the finaliser sets VACT
     {
         ProfScope ps(SEM_PROF_AX_RESID, s);
         resid_ax(b, lx, F_U, s);
     }
-    launch_dssum(b, F_R64, 3, P64, -1, nullptr, s);
-    vec(b, V_VRESID, 3, P64, -1, s, -1, -1, P64, P64, FIN_VINIT);
+    launch_dssum(b, F_R64, 3, P64, -1, nullptr, s, R_A);
+    fin(b, FIN_VINIT, s);
     const int vmax = batch_maxit(ctxs, b.n, false);
     int maxref = 0;
     for (int i = 0; i < b.n; ++i) maxref = std::max(maxref, ctxs[i]->flow.vel_max_refine);
@@ -826,8 +827,8 @@ int velocity_solve(sem_ctx* const* ctxs, const Batch& b, hipStream_t s)
             ProfScope ps(SEM_PROF_AX_RESID, s);
             resid_ax(b, lx, F_US, s);
         }
-        launch_dssum(b, F_R64, 3, P64, -1, nullptr, s);
-        vec(b, V_VRESID, 3, P64, -1, s, -1, -1, P64, P64, FIN_VINIT);
+        launch_dssum(b, F_R64, 3, P64, -1, nullptr, s, R_A);
+        fin(b, FIN_VINIT, s);
     }
     return check_hip_last();
 }
@@ -1090,7 +1091,8 @@ int sem_setup(const sem_mesh_desc* mesh, const sem_flow_desc* flow, const sem_pr
     c->nb = (int)((E + c->epb - 1) / c->epb);
     c->vepb = vepb_of(c->lx, c->E);
     c->nvb = (c->E + c->vepb - 1) / c->vepb;
-    c->pstride = std::max(c->nb, c->nvb);
+    // partials come from element blocks, point-wise blocks and gather-scatter workgroups
+    c->pstride = std::max(std::max(c->nb, c->nvb), gs_blocks(c->lx, mesh->nel[1], mesh->nel[2]));
     if (c->nb > c->pstride || c->nvb > c->pstride || (long long)c->nb * c->epb < c->E ||
         (long long)c->nvb * c->vepb < c->E) {
         delete c;
@@ -1480,8 +1482,8 @@ void fixed_step(sem_ctx* const* ctxs, const Batch& b, const Budget& g, double* h
         ProfScope ps(SEM_PROF_AX_RESID, s);
         resid_ax(b, lx, F_U, s);
     }
-    launch_dssum(b, F_R64, 3, P64, -1, nullptr, s);
-    vec(b, V_VRESID, 3, P64, -1, s, -1, -1, P64, P64, FIN_VINIT);
+    launch_dssum(b, F_R64, 3, P64, -1, nullptr, s, R_A);
+    fin(b, FIN_VINIT, s);
     const int ncyc = tv == P64 ? 1 : std::max(1, g.cyc);
     for (int cyc = 0; cyc < ncyc; ++cyc) {
         vec(b, V_PCG_INIT, 3, tv, -1, s, -1, -1, r.tva, P64, FIN_PCG_RHO);
@@ -1492,8 +1494,8 @@ void fixed_step(sem_ctx* const* ctxs, const Batch& b, const Budget& g, double* h
             ProfScope ps(SEM_PROF_AX_RESID, s);
             resid_ax(b, lx, F_US, s);
         }
-        launch_dssum(b, F_R64, 3, P64, -1, nullptr, s);
-        vec(b, V_VRESID, 3, P64, -1, s, -1, -1, P64, P64, FIN_VINIT);
+        launch_dssum(b, F_R64, 3, P64, -1, nullptr, s, R_A);
+        fin(b, FIN_VINIT, s);
     }
     pressure_rhs(b, c0, s);
     gmres_start(b, lx, r, hsmg, s);

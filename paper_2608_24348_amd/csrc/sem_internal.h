@@ -258,6 +258,8 @@ __host__ __device__ inline HsOff hs_off(int lx, const int* nel)
 // gather-scatter: the plane form runs where an element's plane fits a wave
 // with V nodes a lane (lx * lx / V <= 64), else the row form
 __host__ __device__ constexpr bool gs_planes(int lx, int V) { return lx * (lx / V) <= 64; }
+// most gather-scatter workgroups of one request, over both forms
+__host__ __device__ constexpr int gs_blocks(int lx, int ny, int nz) { return ny * nz * (lx - 1); }
 
 // elements per workgroup of the element kernels (shared by host and device)
 __host__ __device__ constexpr int epb_of(int lx)
@@ -314,7 +316,10 @@ void launch_ax(const Batch& b, int lx, const AxLaunch& a, hipStream_t s);
 // the matrix-core operator (lx = 8, fp32 arithmetic, 16-bit geometry, no Jacobi
 // scaling, residual form or fp64 output); false when it does not apply
 bool launch_ax_mfma(const Batch& b, int lx, const AxLaunch& a, hipStream_t s);
-void launch_dssum(const Batch& b, int field, int ncomp, int tprec, int gate, void* raw, hipStream_t s);
+// pslot >= 0: also the squared norm over unique nodes of each component c,
+// as per-workgroup partials in slot pslot + c (see gs_blocks for their count)
+void launch_dssum(const Batch& b, int field, int ncomp, int tprec, int gate, void* raw, hipStream_t s,
+                  int pslot = -1);
 
 // geometry and setup
 void launch_geometry(const Batch& b, int lx, const MeshParams& mp, hipStream_t s);
@@ -341,8 +346,7 @@ void launch_hsmg(const Batch& b, int lx, int tb, int gate, hipStream_t s);
 
 // point-wise / reduction / scalar kernels
 enum VecOp : int {
-    V_VRESID = 0,     // partial |R64|^2 -> R_A+c (R64 = dssum(RHS_L - H_L u), formed by the operator)
-    V_PCG_INIT,       // PX = 0, PR = R64, PZ = PR*IDV, PP = PZ, partial (r,z) -> R_B+c
+    V_PCG_INIT = 0,   // PX = 0, PR = R64, PZ = PR*IDV, PP = PZ, partial (r,z) -> R_B+c
     V_PCG_UPD,        // PX += a PP, PR -= a PW, PZ = PR*IDV, partials (r,r) -> R_B+c, (r,z) -> R_C+c
     V_PCG_P,          // PP = PZ + b PP
     V_US_COPY,        // US = U
