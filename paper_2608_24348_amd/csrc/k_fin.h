@@ -11,23 +11,47 @@
 namespace semk {
 
 // ------------------------------------------------------------------ finalise kernels
-// fixed-order sum of the partials of one slot (valid in thread 0): thread t
-// adds partials t, t+bd, t+2bd, ... in that order (four loads in flight),
-// then the per-thread sums are added in a fixed tree.
+// fixed-order sums of the partials of NS slots (valid in thread 0): for each
+// slot, thread t adds partials t, t+bd, t+2bd, ... in that order, then the
+// per-thread sums are added in a fixed tree.  The slots are read together,
+// eight loads of each in flight, so a finaliser waits for one round of loads
+// where it waited for NS.  red must hold (blockDim.x / 64) * NS values.
+template <int NS>
+static __device__ void slot_sums(const ReqDesc* R, const int (&slot)[NS], double (&out)[NS], double* red)
+{
+    constexpr int U = 8;
+    const SEM_GLOBAL double* p[NS];
+    int cnt[NS], most = 0;
+    double s[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        p[k] = gp(R->part) + (long long)slot[k] * R->pstride;
+        cnt[k] = gp(R->I)[I_PCNT + slot[k]];
+        most = max(most, cnt[k]);
+        s[k] = 0.0;
+    }
+    const int bd = blockDim.x;
+    for (int q = threadIdx.x; q < most; q += U * bd) {
+        double a[NS][U];
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[k][u] = q + u * bd < cnt[k] ? p[k][q + u * bd] : 0.0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (q + u * bd < cnt[k]) s[k] += a[k][u];
+    }
+    block_sum<double, NS>(s, red);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) out[k] = s[k];
+}
 static __device__ double slot_sum(const ReqDesc* R, int slot, double* red)
 {
-    double s = 0.0;
-    const SEM_GLOBAL double* p = gp(R->part) + (long long)slot * R->pstride;
-    const int cnt = gp(R->I)[I_PCNT + slot];
-    const int bd = blockDim.x;
-    int q = threadIdx.x;
-    for (; q + 3 * bd < cnt; q += 4 * bd) {
-        const double a0 = p[q], a1 = p[q + bd], a2 = p[q + 2 * bd], a3 = p[q + 3 * bd];
-        s += a0; s += a1; s += a2; s += a3;
-    }
-    for (; q < cnt; q += bd) s += p[q];
-    double v[1] = {s};
-    block_sum<double, 1>(v, red);
+    const int sl[1] = {slot};
+    double v[1];
+    slot_sums<1>(R, sl, v, red);
     return v[0];
 }
 static __device__ double slot_max(const ReqDesc* R, int slot, double* red)
@@ -80,9 +104,10 @@ static __device__ void multi_slot_sum(const ReqDesc* R, int slot0, int nslots, d
 
 static __device__ __forceinline__ bool finite(double v) { return isfinite(v); }
 
-// The scalar logic of one request, run by one workgroup of any size up to
-// 1024 threads (the slot sums use every thread; the multi-slot sum uses the
-// first 256).  ri is the request's position in its batch (host arrays).
+// The scalar logic of one request, run by one workgroup of 256 threads (the
+// slot sums use every thread and red holds 4 waves x 8 slots; the multi-slot
+// sum uses the first 256).  ri is the request's position in its batch (host
+// arrays).
 static __device__ __noinline__ void fin_body(ReqDesc* R, int ri, const FinArgs a)
 {
     __shared__ double red[32];
@@ -94,8 +119,11 @@ static __device__ __noinline__ void fin_body(ReqDesc* R, int ri, const FinArgs a
     if (a.gate2 >= 0 && !I[a.gate2]) return;  // uniform per workgroup
     switch (a.op) {
     case FIN_VINIT: {
+        const int sl[3] = {R_A, R_A + 1, R_A + 2};
+        double v[3];
+        slot_sums<3>(R, sl, v, red);
         for (int c = 0; c < 3; ++c) {
-            double s = slot_sum(R, R_A + c, red);
+            const double s = v[c];
             if (t == 0) {
                 double rn = sqrt(s);
                 S[S_R0 + c] = rn;
@@ -109,25 +137,29 @@ static __device__ __noinline__ void fin_body(ReqDesc* R, int ri, const FinArgs a
         break;
     }
     case FIN_PCG_RHO: {
-        for (int c = 0; c < 3; ++c) {
-            double s = slot_sum(R, R_B + c, red);
-            if (t == 0 && I[I_VACT + c]) S[S_RHO + c] = s;
-        }
+        const int sl[3] = {R_B, R_B + 1, R_B + 2};
+        double v[3];
+        slot_sums<3>(R, sl, v, red);
+        for (int c = 0; c < 3; ++c)
+            if (t == 0 && I[I_VACT + c]) S[S_RHO + c] = v[c];
         break;
     }
     case FIN_PCG_ALPHA: {
-        for (int c = 0; c < 3; ++c) {
-            if (!I[I_VACT + c]) continue;  // uniform per block
-            double s = slot_sum(R, R_A + c, red);
-            if (t == 0) S[S_ALPHA + c] = S[S_RHO + c] / s;
-        }
+        // (an idle component's slot is summed too; its result is not used)
+        const int sl[3] = {R_A, R_A + 1, R_A + 2};
+        double v[3];
+        slot_sums<3>(R, sl, v, red);
+        for (int c = 0; c < 3; ++c)
+            if (t == 0 && I[I_VACT + c]) S[S_ALPHA + c] = S[S_RHO + c] / v[c];
         break;
     }
     case FIN_PCG_BETA: {
+        const int sl[6] = {R_B, R_C, R_B + 1, R_C + 1, R_B + 2, R_C + 2};
+        double v[6];
+        slot_sums<6>(R, sl, v, red);
         for (int c = 0; c < 3; ++c) {
             if (!I[I_VACT + c]) continue;
-            double rr = slot_sum(R, R_B + c, red);
-            double rz = slot_sum(R, R_C + c, red);
+            const double rr = v[2 * c], rz = v[2 * c + 1];
             if (t == 0) {
                 double rn = sqrt(rr);
                 S[S_RN + c] = rn;
@@ -294,8 +326,10 @@ static __device__ __noinline__ void fin_body(ReqDesc* R, int ri, const FinArgs a
         break;
     }
     case FIN_DIAG: {
-        double ke = slot_sum(R, R_X0, red);
-        double en = slot_sum(R, R_X1, red);
+        const int sl[2] = {R_X0, R_X1};
+        double v[2];
+        slot_sums<2>(R, sl, v, red);
+        const double ke = v[0], en = v[1];
         double md = slot_max(R, R_X2, red);
         double cr = slot_max(R, R_X4, red);
         if (t == 0) {
