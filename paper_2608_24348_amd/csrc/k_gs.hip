@@ -1,23 +1,25 @@
 // Direct stiffness summation (gather-scatter Q Q^T) on the periodic box,
 // without atomics or index lists.
 //
-// A row is the lx nodes of one element that share (j, k).
-// Task (x-line of elements (ey, ez), j, k), j and k in [1, N], owns the rows
-// (e, j, k) of every element e of the line and, where they hold the same
-// nodes, the rows (e+y, 0, k) when j = N, (e+z, j, 0) when k = N and
-// (e+y+z, 0, 0) when both: every row of the mesh belongs to exactly one task.
-// One wave runs a task.  A lane holds V consecutive nodes of a row (one word
-// of V * sizeof(T) bytes, 8 where lx allows), lx / V lanes a row, and the wave
-// walks the line in segments of 64 / (lx / V) elements, so each load or store
-// moves whole rows.  The x-neighbour's copy of a node (i = N against the next
-// element's i = 0) comes from the neighbouring lane, or from the registers of
-// the neighbouring segment, or, across the periodic wrap, from values read
-// before any row of the line is written.  Every copy of a node adds the same
-// values in the same order (copy s takes the +d side in direction d when bit d
-// of s is set, directions x, y, z in that order among the boundary ones) and
-// so gets the same bits.  Rows of different tasks are disjoint, so the
-// in-place update is race free, and every row is read once and written once,
-// whole: no partial-line writes reach memory.
+// A row is the lx nodes of one element that share (j, k).  The rows are split
+// into tasks, one wave each, such that every row of the mesh belongs to
+// exactly one task and a task holds every copy of the nodes in its rows: rows
+// of different tasks are disjoint, so the in-place update is race free, and
+// every row is read once and written once, whole (no partial-line writes reach
+// memory).  Every copy of a node adds the same values in the same order (copy
+// s takes the +d side in direction d when bit d of s is set, directions x, y,
+// z in that order among the boundary ones) and so gets the same bits.
+//
+// A task walks one x-line of elements in segments; a lane holds V consecutive
+// nodes of a row in one word of V * sizeof(T) bytes (8 where lx allows).  The
+// x copy of a node (i = N against the next element's i = 0) comes from the
+// next element's lanes, or from the next segment's registers, or, across the
+// periodic wrap, from values read before any row of the line is written.
+// Two forms share this:
+// - the plane form (dssum_planes_kernel), where an element's plane fits a
+//   wave: one load moves rows 1..N of a plane of an element;
+// - the row form (dssum_rows_kernel) for the other orders: one load moves one
+//   row from each of 64 / (lx / V) elements.
 #include "k_common.h"
 
 namespace semk {
@@ -60,6 +62,12 @@ template <typename T, int V, typename U> __device__ __forceinline__ T word_get(U
     return v[q];
 }
 
+// Row form.  Task (x-line of elements (ey, ez), j, k), j and k in [1, N],
+// owns the rows (e, j, k) of every element e of the line and, where they hold
+// the same nodes, the rows (e+y, 0, k) when j = N, (e+z, j, 0) when k = N and
+// (e+y+z, 0, 0) when both.  Lane el * (lx / V) + p holds word p of the rows of
+// element el of the segment.
+//
 // one task: NC = 1, 2 or 4 copy rows; row t of the line's element ex starts
 // at byte rr[t] + ex * eb (eb = bytes per element, ib = the lane's byte
 // offset in a row; the setup keeps a line of elements below 4 GB).  Segment
@@ -216,15 +224,13 @@ dssum_rows_kernel(Batch bt, int field, int gate, void* raw, int per, int pslot)
 // Task (x-line of elements, k), k in [1, N], owns for every element e of the
 // line the rows (e, j, k), j in [1, N], and the row (e+y, 0, k), which holds
 // the other copies of the plane's j = N nodes; when k = N it also owns the
-// same rows of the planes k = 0 of e+z and e+y+z.  Every row of the mesh
-// belongs to exactly one task.  Lane el * SL + r * LP + p (SL = lx * LP lanes
-// an element) holds V nodes of slot r: slot 0 the row (e+y, 0, k), slots
-// 1..N the rows (e, r, k); a load thus moves rows 1..N of an element's plane,
-// which are contiguous, and the neighbour's row 0.  The y copy of a node sits
-// N slots away in the same register, the z copy in the z-plane register of the
-// same lane, and the x copies come from the next or previous element's lanes,
-// as in the row form.  Every copy of a node adds the same values in the same
-// order, so all copies get the same bits.
+// same rows of the planes k = 0 of e+z and e+y+z.  Lane el * SL + r * LP + p
+// (SL = lx * LP lanes an element) holds word p of slot r: slot 0 the row
+// (e+y, 0, k), slots 1..N the rows (e, r, k); a load thus moves rows 1..N of
+// an element's plane, which are contiguous, and the neighbour's row 0.  The y
+// copy of a node sits N slots away in the same register, the z copy in the
+// z-plane register of the same lane, and the x copies come from the next or
+// previous element's lanes.
 template <typename U> struct GsSeg {
     U m[2];   // [0] plane k, [1] plane 0 of e+z
 };
