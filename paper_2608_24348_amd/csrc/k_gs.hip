@@ -11,7 +11,8 @@
 // z in that order among the boundary ones) and so gets the same bits.
 //
 // A task walks one x-line of elements in segments; a lane holds V consecutive
-// nodes of a row in one word of V * sizeof(T) bytes (8 where lx allows).  The
+// nodes of a row in one word of V * sizeof(T) bytes (16 where lx allows in the
+// plane form, up to 8 in the row form).  The
 // x copy of a node (i = N against the next element's i = 0) comes from the
 // next element's lanes, or from the next segment's registers, or, across the
 // periodic wrap, from values read before any row of the line is written.
@@ -33,10 +34,17 @@ template <int B> struct GsWord;
 template <> struct GsWord<2> { using type = unsigned short; };
 template <> struct GsWord<4> { using type = unsigned int; };
 template <> struct GsWord<8> { using type = unsigned long long; };
+typedef unsigned long long GsW16 __attribute__((ext_vector_type(2)));
+template <> struct GsWord<16> { using type = GsW16; };
 
 template <typename U> __device__ __forceinline__ U lane_get(U v, int src)
 {
-    if constexpr (sizeof(U) == 8) {
+    if constexpr (sizeof(U) == 16) {
+        U r;
+        r.x = lane_get(v.x, src);
+        r.y = lane_get(v.y, src);
+        return r;
+    } else if constexpr (sizeof(U) == 8) {
         const int lo = __shfl((int)(unsigned)v, src, 64), hi = __shfl((int)(unsigned)(v >> 32), src, 64);
         return (U)(unsigned)lo | ((U)(unsigned)hi << 32);
     } else {
@@ -46,7 +54,12 @@ template <typename U> __device__ __forceinline__ U lane_get(U v, int src)
 
 template <typename U> __device__ __forceinline__ U lane_bcast(U v, int src)
 {
-    if constexpr (sizeof(U) == 8) {
+    if constexpr (sizeof(U) == 16) {
+        U r;
+        r.x = lane_bcast(v.x, src);
+        r.y = lane_bcast(v.y, src);
+        return r;
+    } else if constexpr (sizeof(U) == 8) {
         const int lo = __builtin_amdgcn_readlane((int)(unsigned)v, src);
         const int hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), src);
         return (U)(unsigned)lo | ((U)(unsigned)hi << 32);
@@ -415,11 +428,15 @@ static void dssum_go(const Batch& b, int field, int ncomp, int gate, void* raw, 
     }
 }
 
-// nodes per lane: as many as fit 8 bytes and divide lx; a batch shares one lx
+// nodes per lane: 16 bytes of them where lx allows and the plane form fits
+// (64^3 elements, N = 7: fp64 0.442 against 0.467 ms with 8-byte words), else
+// as many as fit 8 bytes and divide lx; a batch shares one lx
 template <typename T, typename A>
 static void dssum_pick(const Batch& b, int field, int ncomp, int gate, void* raw, hipStream_t s, int pslot)
 {
     const int lx = b.lx;
+    constexpr int V16 = 16 / (int)sizeof(T);
+    if (lx % V16 == 0 && gs_planes(lx, V16)) return dssum_go<T, A, V16>(b, field, ncomp, gate, raw, s, pslot);
     if constexpr (sizeof(T) <= 2)
         if (lx % 4 == 0) return dssum_go<T, A, 4>(b, field, ncomp, gate, raw, s, pslot);
     if constexpr (sizeof(T) <= 4)
