@@ -197,6 +197,15 @@ size_t sem_workspace_bytes(const sem_ctx* ctx);
  * SEM_ESTATE (already bound). */
 int sem_bind(sem_ctx* ctx, void* dev_buf, size_t bytes, void* hip_stream);
 
+/* Moves a bound context to another stream (a hipStream_t, 0 = null stream):
+ * its later calls, and batches whose first context it is, run there.  Work
+ * already queued on the old stream is not waited for: the caller orders the
+ * two streams (for instance by synchronising the old one first).  Lets a
+ * server bind requests on a stream of their own and then hand them to the
+ * stream that runs their batches.  Host only.  Errors: SEM_EINVAL (null
+ * context), SEM_ESTATE (not bound). */
+int sem_set_stream(sem_ctx* ctx, void* hip_stream);
+
 /* Helmholtz operator w = h1 * sum_ab D_a^T G_ab D_b u + h2 * B u on every
  * element (the paper's ax_helm), u and w device arrays of E*lx^3 values in
  * buf_prec (FP64, FP32, FP16 or BF16 storage), geometry in geom_prec (must

@@ -1250,6 +1250,15 @@ int sem_bind(sem_ctx* c, void* dev_buf, size_t bytes, void* hip_stream)
     return 0;
 }
 
+int sem_set_stream(sem_ctx* c, void* hip_stream)
+{
+    std::lock_guard<std::recursive_mutex> lk(g_host_mu);
+    if (!c) return fail(SEM_EINVAL, "null argument");
+    if (!c->bound) return fail(SEM_ESTATE, "context not bound");
+    c->stream = (hipStream_t)hip_stream;
+    return 0;
+}
+
 void sem_destroy(sem_ctx* c)
 {
     if (!c) return;

@@ -80,7 +80,7 @@ EXPORTS = ["sem_setup", "sem_workspace_bytes", "sem_bind", "sem_ax", "sem_dssum"
            "sem_conv", "sem_opgrad", "sem_wdiv", "sem_sizes", "sem_destroy", "sem_strerror", "sem_last_error",
            "sem_prof_start", "sem_prof_stop", "sem_poisson_begin", "sem_poisson_advance", "sem_poisson_finish",
            "sem_mass", "sem_node_field", "sem_copy_state", "sem_fluid_step_graph", "sem_graph_counters", "sem_host_lock",
-           "sem_noalloc_max_bytes", "sem_poisson_solve_noalloc"]
+           "sem_noalloc_max_bytes", "sem_poisson_solve_noalloc", "sem_set_stream"]
 PROF_AX_VEL, PROF_AX_PRES, PROF_GM_DOTS, PROF_GM_UPD_DOTS, PROF_GM_UPD_NORM, PROF_DSSUM_PRES, PROF_AX_ANY, PROF_AX_RESID, \
     PROF_AX_PRESID, PROF_CONV, PROF_HSMG = range(1, 12)
 
@@ -104,6 +104,7 @@ def load():
     L.sem_workspace_bytes.restype = C.c_size_t
     L.sem_workspace_bytes.argtypes = [vp]
     L.sem_bind.argtypes = [vp, vp, C.c_size_t, vp]
+    L.sem_set_stream.argtypes = [vp, vp]
     L.sem_ax.argtypes = [vp, vp, vp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int]
     L.sem_dssum.argtypes = [vp, vp, C.c_int]
     L.sem_fluid_step.argtypes = [C.POINTER(vp), C.c_int, C.c_int, C.POINTER(StepStats)]
@@ -293,14 +294,28 @@ class Context:
         if bind:
             self.bind(device)
 
-    def bind(self, device="cuda:0", stream=None):
+    def bind(self, device="cuda:0", stream=None, workspace=None):
+        """workspace: a uint8 device tensor of at least ``bytes`` bytes, 256-byte
+        aligned (for instance a slice of a server's arena); else one is allocated."""
         torch = _torch()
-        self.ws = torch.empty(self.bytes + 256, dtype=torch.uint8, device=device)
-        base = self.ws.data_ptr()
-        aligned = (base + 255) // 256 * 256
+        if workspace is None:
+            self.ws = torch.empty(self.bytes + 256, dtype=torch.uint8, device=device)
+            base = self.ws.data_ptr()
+            aligned = (base + 255) // 256 * 256
+        else:
+            assert workspace.dtype == torch.uint8 and workspace.numel() >= self.bytes
+            assert workspace.data_ptr() % 256 == 0
+            self.ws = workspace
+            aligned = workspace.data_ptr()
         s = stream if stream is not None else torch.cuda.current_stream(device)
         self.stream = s
         _check(self.L.sem_bind(self.h, C.c_void_p(aligned), C.c_size_t(self.bytes), C.c_void_p(s.cuda_stream)))
+
+    def set_stream(self, stream):
+        """later calls (and batches led by this context) run on ``stream``; the
+        caller orders it after the old stream's work"""
+        _check(self.L.sem_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+        self.stream = stream
 
     def close(self):
         if getattr(self, "h", None):

@@ -3,8 +3,10 @@
 Requests (a TGV run of a fixed number of steps, or a manufactured periodic
 Poisson solve) arrive over time.  Each arrival is set up on the host
 (``sem_setup``; workspace size known before any device memory is touched)
-and waits in a FIFO until its workspace fits the HBM budget; admission binds
-it (device geometry, initial condition or right-hand side).  Admitted
+and waits in a FIFO until its workspace fits in the server's arena (the HBM
+budget, one device allocation, first fit); admission binds it there
+(device geometry, initial condition or right-hand side) on an admission
+stream, then hands it to the stream of the worker that owns its key.  Admitted
 requests are grouped by batch key (polynomial order, precision tier, kind,
 pressure preconditioner: HSMG where the request allows it, else Jacobi);
 every round the loop takes the next key with work, forms a batch of up to
@@ -50,10 +52,57 @@ class Request:
         self.t_done = None
         self.status = None
         self.result = None
+        self.slot = None      # (offset, bytes) of its workspace in the arena
         self.ops = 0          # operator applications performed
         self.bytes = 0
         self.ctx_points = 0
         self.stats = []
+
+
+class _Arena:
+    """Request workspaces carved out of one device buffer: first fit over a
+    sorted free list, 256-byte granules, freed ranges merged with their
+    neighbours.  One allocation per server run instead of one per request."""
+
+    G = 256
+
+    def __init__(self, torch, nbytes, device, buf=None):
+        self.size = max(self.G, nbytes // self.G * self.G)
+        if buf is None:
+            buf = torch.empty(self.size + self.G, dtype=torch.uint8, device=device)
+        assert buf.numel() >= self.size + self.G
+        self.buf = buf
+        self.base = (-self.buf.data_ptr()) % self.G   # first 256-byte aligned offset
+        self.free = [[0, self.size]]                   # [offset, bytes], sorted, disjoint
+
+    def alloc(self, nbytes):
+        n = -(-nbytes // self.G) * self.G
+        for i, (o, sz) in enumerate(self.free):
+            if sz >= n:
+                if sz == n:
+                    del self.free[i]
+                else:
+                    self.free[i] = [o + n, sz - n]
+                return o, n
+        return None
+
+    def view(self, off, n):
+        return self.buf[self.base + off:self.base + off + n]
+
+    def release(self, off, n):
+        i = 0
+        while i < len(self.free) and self.free[i][0] < off:
+            i += 1
+        self.free.insert(i, [off, n])
+        if i + 1 < len(self.free) and off + n == self.free[i + 1][0]:
+            self.free[i][1] += self.free[i + 1][1]
+            del self.free[i + 1]
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == off:
+            self.free[i - 1][1] += self.free[i][1]
+            del self.free[i]
+
+    def empty(self):
+        return self.free == [[0, self.size]]
 
 
 class _Worker:
@@ -80,9 +129,10 @@ class Server:
         if budget_bytes is None:
             # blocks the caching allocator still holds from earlier work are
             # returned first, so the budget is the device's real free memory
+            # (plus the arena an earlier server of this process left)
             torch.cuda.empty_cache()
             free, _ = torch.cuda.mem_get_info(torch.device(device))
-            budget_bytes = int(0.9 * free)
+            budget_bytes = int(0.9 * (free + _arena_held(device)))
         self.budget = int(budget_bytes)
         self.max_batch = min(int(max_batch), 48)
         self.gmres_chunk = int(gmres_chunk)
@@ -114,11 +164,14 @@ class Server:
 
     def _admit(self, r, now, w):
         torch = self.torch
-        # workspace, geometry and rhs are made on the stream of the worker that
-        # owns the request's key, ahead of that worker's use of them, under the
-        # library's host lock (no worker captures a step graph meanwhile)
-        with sem.host_lock(), torch.cuda.stream(w.stream):
-            r.ctx.bind(self.device, stream=w.stream)
+        # geometry and rhs are made on the admission stream, in the request's
+        # slice of the arena, under the library's host lock (no worker captures
+        # a step graph meanwhile); once that stream is done the request moves
+        # to the stream of the worker that owns its key, so admission never
+        # waits for a worker's queued steps
+        adm = self.adm_stream
+        with sem.host_lock(), torch.cuda.stream(adm):
+            r.ctx.bind(self.device, stream=adm, workspace=self.arena.view(*r.slot))
             r.t_admit = now
             if r.kind == "poisson":
                 # manufactured rhs: f = 3 sin x sin y sin z + noise (seeded N(0,1) per local point)
@@ -129,8 +182,10 @@ class Server:
                        alpha=float(r.spec["noise"]))
                 rhs = r.ctx.mass(f, assemble=True)
                 sem.poisson_begin([r.ctx], [rhs])
-                w.stream.synchronize()
+            adm.synchronize()
+            if r.kind == "poisson":
                 del f, rhs
+            r.ctx.set_stream(w.stream)
 
     def _retire(self, r, now, status):
         with sem.host_lock():
@@ -186,7 +241,9 @@ class Server:
         waiting = collections.deque()
         active = collections.OrderedDict()   # key -> admitted requests
         owner = {}                           # key -> worker
-        workers = [_Worker(i, torch.cuda.Stream(device=self.device)) for i in range(self.nstreams)]
+        workers = [_Worker(i, _stream(torch, self.device, i)) for i in range(self.nstreams)]
+        self.adm_stream = _stream(torch, self.device, "admission")
+        self.arena = _Arena(torch, self.budget, self.device, _arena_buffer(torch, self.device, self.budget))
         cv = threading.Condition()
         done = []
         state = {"rounds": 0, "error": None, "stop": False}
@@ -226,6 +283,9 @@ class Server:
                     with cv:
                         for r, _ in finished:
                             active[key].remove(r)
+                            # the request's work is complete and its context closed
+                            self.arena.release(*r.slot)
+                            r.slot = None
                             self.used -= r.bytes
                             w.load -= r.ctx_points
                             done.append(r)
@@ -260,10 +320,10 @@ class Server:
                 admitted = False
                 while waiting:
                     with cv:
-                        fits = self.used + waiting[0].bytes <= self.budget
-                        idle = self.used == 0 and not any(active.values())
+                        slot = self.arena.alloc(waiting[0].bytes)
+                        idle = self.arena.empty() and not any(active.values())
                     r = waiting[0]
-                    if not fits:
+                    if slot is None:
                         if idle:
                             # larger than the whole budget: reject instead of deadlocking
                             waiting.popleft()
@@ -276,6 +336,7 @@ class Server:
                             continue
                         break
                     waiting.popleft()
+                    r.slot = slot
                     with cv:
                         w = owner.get(r.key)
                         if w is None or not active.get(r.key):
@@ -309,8 +370,48 @@ class Server:
             for th in threads:
                 th.join()
             torch.cuda.synchronize()
+            self.arena = None
         makespan = clock()
         return done, makespan
+
+
+# streams are kept for the process: a server made per measurement reuses them
+# instead of creating (and leaking) hardware-queue slots every time
+_STREAMS = {}
+# the workspace arena is kept for the process too (one device allocation of
+# the budget, reused by later servers; release_arena gives it back)
+_ARENAS = {}
+
+
+def _arena_held(device):
+    buf = _ARENAS.get(str(device))
+    return 0 if buf is None else buf.numel()
+
+
+def _arena_buffer(torch, device, nbytes):
+    need = nbytes + _Arena.G
+    buf = _ARENAS.get(str(device))
+    if buf is None or buf.numel() < need:
+        _ARENAS.pop(str(device), None)
+        buf = None
+        torch.cuda.empty_cache()
+        buf = torch.empty(need, dtype=torch.uint8, device=device)
+        _ARENAS[str(device)] = buf
+    return buf
+
+
+def release_arena(device="cuda:0"):
+    """Give the servers' workspace arena of this process back to the device."""
+    import torch
+    if _ARENAS.pop(str(device), None) is not None:
+        torch.cuda.empty_cache()
+
+
+def _stream(torch, device, tag):
+    key = (str(device), tag)
+    if key not in _STREAMS:
+        _STREAMS[key] = torch.cuda.Stream(device=device)
+    return _STREAMS[key]
 
 
 def summarize(done, makespan):
@@ -347,6 +448,7 @@ def measure(n_requests=256, seed=24348, loads=(0.4, 0.7, 1.0), max_batch=16, log
         specs = inputs.request_stream(n_requests=n_requests, qps=qps, seed=seed)
         done, ms = Server(max_batch=max_batch, **server_kw).run(specs, log=log)
         out["load_%.1f" % f] = dict(summarize(done, ms), qps=qps)
+    release_arena(server_kw.get("device", "cuda:0"))
     return out
 
 

@@ -15,7 +15,9 @@ def serve():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2608_24348_amd import serve as s
-    return s
+    yield s
+    # the servers' workspace arena outlives them; give it back to later tests
+    s.release_arena()
 
 
 def _stream(n=12, qps=200.0, seed=7):

@@ -165,3 +165,6 @@ def test_unbound_context_calls_fail_cleanly():
     assert L.sem_ax(c.h, C.c_void_p(1), C.c_void_p(1), 1.0, 0.0, 0, -1, 0) == -6
     d = sem.Context(sem.mesh_desc((2, 2, 2), 3), sem.flow_desc(), sem.tier("fp32b"), bind=False)
     assert L.sem_copy_state(d.h, c.h) == -6
+    # moving an unbound context to a stream, or a null context
+    assert L.sem_set_stream(c.h, None) == -6
+    assert L.sem_set_stream(None, None) == -1
