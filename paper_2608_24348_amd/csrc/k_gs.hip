@@ -411,9 +411,9 @@ constexpr unsigned GS_PLANES_LDS = 32000;
 
 // one launch per component
 template <typename T, typename A, int V>
-static void dssum_go(const Batch& b, int field, int ncomp, int gate, void* raw, hipStream_t s, int pslot)
+static void dssum_go(const Batch& b, int field, int ncomp, int gate, void* raw, hipStream_t s, int pslot,
+                     bool planes)
 {
-    const bool planes = gs_planes(b.lx, V);
     const int nblk = planes ? b.gq[b.n] : b.gl[b.n];
     const int per = (nblk + 7) / 8;
     dim3 grid(8 * per);
@@ -428,20 +428,30 @@ static void dssum_go(const Batch& b, int field, int ncomp, int gate, void* raw, 
     }
 }
 
-// nodes per lane: 16 bytes of them where lx allows and the plane form fits
-// (64^3 elements, N = 7: fp64 0.442 against 0.467 ms with 8-byte words), else
-// as many as fit 8 bytes and divide lx; a batch shares one lx
+// Word size and form, as measured (a batch shares one lx):
+// - 16-byte words where they divide a row: the plane form when its segments
+//   fill at least 48 of the 64 lanes, else the row form (64^3 elements, N = 7:
+//   fp64 planes 0.442 ms against 0.467 with 8-byte words; 16^3, N = 11: fp64
+//   rows 24.5 against 27.7 us with 8-byte rows, fp32 rows 19.5 against 22.5 us
+//   in planes of 36 lanes);
+// - else as many nodes as fit 8 bytes and divide lx, in the plane form where
+//   the plane fits a wave (16^3, N = 11, fp16: 13.8 us against 18.2 in rows).
+static int gs_plane_lanes(int lx, int V) { return (64 / (lx * (lx / V))) * lx * (lx / V); }
+
 template <typename T, typename A>
 static void dssum_pick(const Batch& b, int field, int ncomp, int gate, void* raw, hipStream_t s, int pslot)
 {
     const int lx = b.lx;
     constexpr int V16 = 16 / (int)sizeof(T);
-    if (lx % V16 == 0 && gs_planes(lx, V16)) return dssum_go<T, A, V16>(b, field, ncomp, gate, raw, s, pslot);
+    if (lx % V16 == 0) {
+        const bool planes = gs_planes(lx, V16) && gs_plane_lanes(lx, V16) >= 48;
+        return dssum_go<T, A, V16>(b, field, ncomp, gate, raw, s, pslot, planes);
+    }
     if constexpr (sizeof(T) <= 2)
-        if (lx % 4 == 0) return dssum_go<T, A, 4>(b, field, ncomp, gate, raw, s, pslot);
+        if (lx % 4 == 0) return dssum_go<T, A, 4>(b, field, ncomp, gate, raw, s, pslot, gs_planes(lx, 4));
     if constexpr (sizeof(T) <= 4)
-        if (lx % 2 == 0) return dssum_go<T, A, 2>(b, field, ncomp, gate, raw, s, pslot);
-    dssum_go<T, A, 1>(b, field, ncomp, gate, raw, s, pslot);
+        if (lx % 2 == 0) return dssum_go<T, A, 2>(b, field, ncomp, gate, raw, s, pslot, gs_planes(lx, 2));
+    dssum_go<T, A, 1>(b, field, ncomp, gate, raw, s, pslot, gs_planes(lx, 1));
 }
 
 void launch_dssum(const Batch& b, int field, int ncomp, int tprec, int gate, void* raw, hipStream_t s, int pslot)
