@@ -72,7 +72,7 @@ template <int LX> struct AxWave {
 // SUB: residual form, w = r_L - (operator u) with r_L the local (unassembled)
 // right-hand side a.sub; the caller assembles w afterwards, which equals
 // dssum(r_L) - dssum(operator u) (QQ^T is linear)
-template <int LX, typename TU, typename TG, typename C, int PC, typename TW, int SUB = 0, int H16 = 0>
+template <int LX, typename TU, typename TG, typename C, int PC, typename TW, int SUB = 0, int H16 = 0, int SHG = 0>
 __global__ void __launch_bounds__(Nthr<LX>::v)
 ax_kernel(Batch bt, AxLaunch a)
 {
@@ -158,11 +158,12 @@ ax_kernel(Batch bt, AxLaunch a)
     // past the last element) address element 0 (ee == 0), which always
     // exists, and never store.  Guarding the loads would turn each into a
     // divergent branch whose join waits for it.
-    // the geometric factors bypass L2 retention when one component reads them;
-    // the components of a multi-component launch share them through L2
-    // (the three-component fp64 velocity residual at 32^3, N = 7: 0.459 ms
-    // against 0.472 ms with the bypass)
-    const bool shared_g = a.ncomp > 1;
+    // SHG: the geometric factors bypass L2 retention when one component reads
+    // them; the components of a multi-component launch (SHG = 1) share them
+    // through L2 (the three-component fp64 velocity residual at 32^3, N = 7:
+    // 0.459 ms against 0.472 ms with the bypass).  A compile-time choice: a
+    // run-time one cost the single-component forms 8%.
+    auto gload = [](const SEM_GLOBAL TG* p) { if constexpr (SHG != 0) return ldg(p); else return ldg_stream(p); };
 #pragma unroll
     for (int k = 0; k < LX; ++k) uraw[k] = ldg(u + ebase + k * L2 + ij);
     if constexpr (PC != 0) {
@@ -178,7 +179,7 @@ ax_kernel(Batch bt, AxLaunch a)
         if (GALL || k == 0) {
 #pragma unroll
             for (int q = 0; q < 6; ++q)
-                graw[q][k] = shared_g ? ldg(G + gbase + q * L3 + k * L2 + ij) : ldg_stream(G + gbase + q * L3 + k * L2 + ij);
+                graw[q][k] = gload(G + gbase + q * L3 + k * L2 + ij);
         }
     }
     // uin: the operator's input as stored (Jacobi-scaled); ureg: what the
@@ -231,7 +232,7 @@ ax_kernel(Batch bt, AxLaunch a)
             const int pn = (k + 1) * L2 + ij;
 #pragma unroll
             for (int q = 0; q < 6; ++q)
-                graw[q][(k + 1) & 1] = shared_g ? ldg(G + gbase + q * L3 + pn) : ldg_stream(G + gbase + q * L3 + pn);
+                graw[q][(k + 1) & 1] = gload(G + gbase + q * L3 + pn);
         }
         if (el < EPB) su[el][ij] = ureg[k];
         lds_handoff<AxWave<LX>::v>();
@@ -328,11 +329,13 @@ static void ax_go(const Batch& b, const AxLaunch& a, hipStream_t s)
     }
     if constexpr (sizeof(TU) == 8 && sizeof(TG) == 8 && sizeof(C) == 8 && H16 == 0) {
         if (a.sub >= 0) {
-            hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0, TU, 1>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+            if (a.ncomp > 1) hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0, TU, 1, 0, 1>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+            else hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0, TU, 1>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
             return;
         }
     }
-    hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0, TU, 0, H16>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+    if (a.ncomp > 1) hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0, TU, 0, H16, 1>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
+    else hipLaunchKernelGGL((ax_kernel<LX, TU, TG, C, 0, TU, 0, H16>), grid, dim3(Nthr<LX>::v), 0, s, b, a);
 }
 
 // supported (vector, geometry, arithmetic) instantiations; ax_supported()

@@ -139,7 +139,7 @@ template <typename T> __device__ __forceinline__ void cvt4t(typename Raw4<T>::ty
     else cvt4<T>(v, o);
 }
 
-template <typename TU, typename TG>
+template <typename TU, typename TG, int SHG>
 __global__ void __launch_bounds__(128, sizeof(TG) == 4 ? 2 : 3) axm_kernel(Batch bt, AxLaunch a)
 {
     constexpr int LX = 8, L3 = 512;
@@ -198,11 +198,11 @@ __global__ void __launch_bounds__(128, sizeof(TG) == 4 ? 2 : 3) axm_kernel(Batch
     const long long eb = (long long)ee * L3;
     const long long gb = (long long)ee * 6 * L3;
     const bool helm = h2 != 0.0f;
-    // the geometric factors bypass L2 retention when one component reads
-    // them; the components of a multi-component launch share them through L2
-    // (three velocity components at 32^3, N = 7: 66.5 B/point of traffic
-    // with the bypass against 52 B/point read once)
-    const bool shared_g = a.ncomp > 1;
+    // SHG: the geometric factors bypass L2 retention when one component reads
+    // them; the components of a multi-component launch (SHG = 1) share them
+    // through L2 (three velocity components at 32^3, N = 7: 66.5 B/point of
+    // traffic with the bypass against 52 B/point read once)
+    constexpr bool shared_g = SHG != 0;
     typename Raw4<TU>::type uraw[4];
     typename Raw4<TG>::type graw[4][6], braw[4];
 #pragma unroll
@@ -402,7 +402,7 @@ __device__ __forceinline__ float pow2_scale(float m)
 constexpr int AXH_ES = 520;
 constexpr int AXH_WS = 2 * AXH_ES;
 
-template <typename TU, typename TH>
+template <typename TU, typename TH, int SHG>
 __global__ void __launch_bounds__(128, 3) axmh_kernel(Batch bt, AxLaunch a)
 {
     constexpr int LX = 8, L3 = 512;
@@ -456,9 +456,8 @@ __global__ void __launch_bounds__(128, 3) axmh_kernel(Batch bt, AxLaunch a)
     const long long eb = (long long)ee * L3;
     const long long gb = (long long)ee * 6 * L3;
     const bool helm = h2 != 0.0f;
-    // the geometric factors bypass L2 retention when one component reads
-    // them; the components of a multi-component launch share them through L2
-    const bool shared_g = a.ncomp > 1;
+    // SHG as in axm_kernel
+    constexpr bool shared_g = SHG != 0;
     typename Raw4<TU>::type uraw[4];
     u2v graw[4][6], braw[4];
 #pragma unroll
@@ -587,32 +586,33 @@ bool launch_ax_mfma(const Batch& b, int lx, const AxLaunch& a, hipStream_t s)
     q.ncomp = ncomp;
     dim3 grid(((b.eb[b.n] + 7) / 8) * 8 * ncomp);
     static_assert(epb_of(8) == 4, "a workgroup of two waves covers one block of four elements");
+    // components of one launch share the geometric factors through L2
+#define AXM_GO(KER, TU_, TG_)                                                                \
+    do {                                                                                     \
+        if (ncomp > 1) hipLaunchKernelGGL((KER<TU_, TG_, 1>), grid, dim3(128), 0, s, b, q); \
+        else hipLaunchKernelGGL((KER<TU_, TG_, 0>), grid, dim3(128), 0, s, b, q);           \
+    } while (0)
+    bool ok = true;
     if (a.tc == P16 && a.tg == P16) {
-        if (a.tu == P32) hipLaunchKernelGGL((axmh_kernel<float, __half>), grid, dim3(128), 0, s, b, q);
-        else if (a.tu == P16) hipLaunchKernelGGL((axmh_kernel<__half, __half>), grid, dim3(128), 0, s, b, q);
-        else return false;
-        return true;
-    }
-    if (a.tc == PBF && a.tg == PBF) {
-        if (a.tu == P32) hipLaunchKernelGGL((axmh_kernel<float, __hip_bfloat16>), grid, dim3(128), 0, s, b, q);
-        else if (a.tu == PBF)
-            hipLaunchKernelGGL((axmh_kernel<__hip_bfloat16, __hip_bfloat16>), grid, dim3(128), 0, s, b, q);
-        else return false;
-        return true;
-    }
-    if (a.tc != P32) return false;
-    if (a.tg == P32) {
-        if (a.tu != P32) return false;
-        hipLaunchKernelGGL((axm_kernel<float, float>), grid, dim3(128), 0, s, b, q);
-        return true;
-    }
-    if (a.tu == P32 && a.tg == P16) hipLaunchKernelGGL((axm_kernel<float, __half>), grid, dim3(128), 0, s, b, q);
-    else if (a.tu == P32 && a.tg == PBF) hipLaunchKernelGGL((axm_kernel<float, __hip_bfloat16>), grid, dim3(128), 0, s, b, q);
-    else if (a.tu == P16 && a.tg == P16) hipLaunchKernelGGL((axm_kernel<__half, __half>), grid, dim3(128), 0, s, b, q);
-    else if (a.tu == PBF && a.tg == PBF)
-        hipLaunchKernelGGL((axm_kernel<__hip_bfloat16, __hip_bfloat16>), grid, dim3(128), 0, s, b, q);
-    else return false;
-    return true;
+        if (a.tu == P32) AXM_GO(axmh_kernel, float, __half);
+        else if (a.tu == P16) AXM_GO(axmh_kernel, __half, __half);
+        else ok = false;
+    } else if (a.tc == PBF && a.tg == PBF) {
+        if (a.tu == P32) AXM_GO(axmh_kernel, float, __hip_bfloat16);
+        else if (a.tu == PBF) AXM_GO(axmh_kernel, __hip_bfloat16, __hip_bfloat16);
+        else ok = false;
+    } else if (a.tc != P32) {
+        ok = false;
+    } else if (a.tg == P32) {
+        if (a.tu == P32) AXM_GO(axm_kernel, float, float);
+        else ok = false;
+    } else if (a.tu == P32 && a.tg == P16) AXM_GO(axm_kernel, float, __half);
+    else if (a.tu == P32 && a.tg == PBF) AXM_GO(axm_kernel, float, __hip_bfloat16);
+    else if (a.tu == P16 && a.tg == P16) AXM_GO(axm_kernel, __half, __half);
+    else if (a.tu == PBF && a.tg == PBF) AXM_GO(axm_kernel, __hip_bfloat16, __hip_bfloat16);
+    else ok = false;
+#undef AXM_GO
+    return ok;
 }
 
 }  // namespace semk
