@@ -296,7 +296,7 @@ def roofline(kind, tier, prof, steps, npts, workload, N=7, dealias=0):
             nv = 1 + (s["vcyc"] if tier != "fp64" else 0)
             alg += nv * npts * 128
             active += nv
-        name = "ax_kernel<8, double, double, double, 0, double, 1, 0> -- fp64 velocity residual RHS_L - H_L u"
+        name = "ax_kernel<8, double, double, double, 0, double, 1, 0, 1> -- fp64 velocity residual RHS_L - H_L u"
     elif kind == "ax_presid":
         # fp64 Poisson residual operator at the end of every GMRES cycle that
         # started from a nonzero iterate (u, w, 6 G = 64 B/point); the other
@@ -307,7 +307,7 @@ def roofline(kind, tier, prof, steps, npts, workload, N=7, dealias=0):
             ncyc = (s["pit"] + 29) // 30 if s["pit"] > 0 else 0
             alg += ncyc * npts * 64
             active += ncyc
-        name = "ax_kernel<8, double, double, double, 0, double, 0> -- fp64 GMRES cycle-end residual"
+        name = "ax_kernel<8, double, double, double, 0, double, 0, 0, 0> -- fp64 GMRES cycle-end residual"
     elif kind in PROF_KERNELS:
         kname, what, fbytes = PROF_KERNELS[kind]
         alg = 0.0
