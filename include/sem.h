@@ -379,7 +379,14 @@ int sem_prof_stop(double* total_ms, int64_t* launches);
 /* Sizes of a bound or unbound context. */
 int sem_sizes(const sem_ctx* ctx, int64_t* np, int64_t* nglob, int* lx, int* nelem);
 
+/* Frees the context's host state: its tables, its pinned status words and the step
+ * graphs cached for any batch it belongs to.  NULL is a no-op.  It neither waits for
+ * nor frees device memory: the workspace belongs to the caller, and kernels of this
+ * context still queued on its stream may use it, so synchronise that stream before
+ * the workspace is reused or freed.  Takes the library's host lock. */
 void sem_destroy(sem_ctx* ctx);
+/* Static text naming a status code (SEM_OK, SEM_E*); never NULL, unknown codes
+ * included.  The caller does not free it. */
 const char* sem_strerror(int status);
 /* Text of the last error recorded by any call on this thread. */
 const char* sem_last_error(void);
