@@ -303,8 +303,14 @@ class Context:
             base = self.ws.data_ptr()
             aligned = (base + 255) // 256 * 256
         else:
-            assert workspace.dtype == torch.uint8 and workspace.numel() >= self.bytes
-            assert workspace.data_ptr() % 256 == 0
+            if workspace.dtype != torch.uint8:
+                raise ValueError("workspace must be a uint8 tensor, got %s" % workspace.dtype)
+            if workspace.numel() < self.bytes:
+                raise ValueError("workspace holds %d bytes, the context needs %d" % (workspace.numel(), self.bytes))
+            if workspace.data_ptr() % 256:
+                raise ValueError("workspace must start on a 256-byte boundary")
+            if not workspace.is_cuda or not workspace.is_contiguous():
+                raise ValueError("workspace must be a contiguous device tensor")
             self.ws = workspace
             aligned = workspace.data_ptr()
         s = stream if stream is not None else torch.cuda.current_stream(device)

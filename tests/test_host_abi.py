@@ -168,3 +168,22 @@ def test_unbound_context_calls_fail_cleanly():
     # moving an unbound context to a stream, or a null context
     assert L.sem_set_stream(c.h, None) == -6
     assert L.sem_set_stream(None, None) == -1
+
+
+def test_bind_rejects_unfit_workspaces():
+    """A caller-provided workspace is checked before anything reaches the
+    device: element type, size, 256-byte alignment, device residence."""
+    import torch
+    c = sem.Context(sem.mesh_desc((2, 2, 2), 3), sem.flow_desc(), sem.tier("fp64"), bind=False)
+    raw = torch.empty(c.bytes + 512, dtype=torch.uint8)
+    off = (-raw.data_ptr()) % 256
+    fit = raw[off:off + c.bytes]
+    with pytest.raises(ValueError, match="uint8"):
+        c.bind("cpu", workspace=torch.empty(c.bytes, dtype=torch.float32))
+    with pytest.raises(ValueError, match="needs"):
+        c.bind("cpu", workspace=fit[:c.bytes - 256])
+    with pytest.raises(ValueError, match="256-byte"):
+        c.bind("cpu", workspace=raw[off + 1:off + 1 + c.bytes])
+    with pytest.raises(ValueError, match="device tensor"):
+        c.bind("cpu", workspace=fit)
+    assert c.ws is None
