@@ -296,7 +296,7 @@ def roofline(kind, tier, prof, steps, npts, workload, N=7, dealias=0):
             nv = 1 + (s["vcyc"] if tier != "fp64" else 0)
             alg += nv * npts * 128
             active += nv
-        name = "ax_kernel<8, double, double, double, 0, double, 1, 0, 1> -- fp64 velocity residual RHS_L - H_L u"
+        name = "ax_kernel<%d, double, double, double, 0, double, 1, 0, 1> -- fp64 velocity residual RHS_L - H_L u" % (N + 1)
     elif kind == "ax_presid":
         # fp64 Poisson residual operator at the end of every GMRES cycle that
         # started from a nonzero iterate (u, w, 6 G = 64 B/point); the other
@@ -307,7 +307,7 @@ def roofline(kind, tier, prof, steps, npts, workload, N=7, dealias=0):
             ncyc = (s["pit"] + 29) // 30 if s["pit"] > 0 else 0
             alg += ncyc * npts * 64
             active += ncyc
-        name = "ax_kernel<8, double, double, double, 0, double, 0, 0, 0> -- fp64 GMRES cycle-end residual"
+        name = "ax_kernel<%d, double, double, double, 0, double, 0, 0, 0> -- fp64 GMRES cycle-end residual" % (N + 1)
     elif kind in PROF_KERNELS:
         kname, what, fbytes = PROF_KERNELS[kind]
         alg = 0.0
@@ -336,11 +336,11 @@ def roofline(kind, tier, prof, steps, npts, workload, N=7, dealias=0):
     elif kind == "ax_vel":
         active = sum(sum(s["vit"]) for s in steps)  # component launches that did work
         alg = active * npts * _bytes_per_point(kind, tier)
-        name = "ax_kernel<8,...> velocity Helmholtz operator (PCG)"
+        name = "ax_kernel<%d,...> velocity Helmholtz operator (PCG)" % (N + 1)
     else:
         active = sum(s["pit"] for s in steps)
         alg = active * npts * _bytes_per_point(kind, tier)
-        name = "ax_kernel<8,...> pressure operator (Arnoldi step)"
+        name = "ax_kernel<%d,...> pressure operator (Arnoldi step)" % (N + 1)
     achieved = alg / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
     traffic = stored_traffic(kind, tier, workload)
     return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
