@@ -20,9 +20,11 @@
 #include <type_traits>
 
 // register budget (bytes per thread) under which all six geometric factors of
-// a column are loaded before the k-walk instead of one layer ahead
+// a column are loaded before the k-walk instead of one layer ahead: lx <= 8 in
+// fp32.  At lx = 12 the whole column's G (72 VGPRs) held the fp32 operators
+// at one five-wave workgroup per CU; loaded a layer ahead, two fit.
 #ifndef SEM_AX_GALL_BYTES
-#define SEM_AX_GALL_BYTES 384
+#define SEM_AX_GALL_BYTES 192
 #endif
 
 namespace semk {
